@@ -1,0 +1,337 @@
+"""Plain FP64 reference of the EPIC imaging path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the GPU library imports or calls this
+module; only the tests, the smoke check and the benchmark's CPU-baseline leg
+do.  It is deliberately slow and literal: every step is the definition
+written out in float64/complex128 with NumPy, with no blocking, fusion or
+reordering beyond what the definition states.
+
+What it computes (paper: Sec. 2, Eq. 1 and Eq. 2):
+
+* Eq. 1, inner sum: each calibrated voltage E_e^p is spread onto a regular
+  aperture grid r_j with the conjugate of its element's gridding kernel,
+  G^p[j] = sum_e W_e*(r_j - r_e) E_e^p.  The kernel here is diagonal in
+  polarisation (the same kernel for both feeds).
+* Eq. 1, outer sum: a 2D Fourier sum with the positive exponent,
+  E^p[k] = sum_j dA_j exp(+2 pi i s_k . r_j / lambda) G^p[j], written on
+  centred integer indices as exp(+2 pi i (k - N/2).(j - N/2) / N), with the
+  cell area dA_j taken as 1.
+* Eq. 2: pixelwise outer product of polarisations, E^a conj(E^b), summed
+  over the integration; XX, YY and XY = Ex conj(Ey) are kept.
+* Autocorrelation removal: the e = e' terms of the squared sum.  They are
+  sum_a S_a^{pq} |B_a[k]|^2 with S_a^{pq} = sum_t E_a^p conj(E_a^q) and
+  B_a the image of element a's kernel footprint alone.
+* The FX route: form every pairwise visibility V_ab = sum_t E_a conj(E_b)
+  explicitly, grid it at the footprint displacements with the correlated
+  kernel conj(W_a(j)) W_b(j'), and Fourier transform.  Expanding |sum|^2 in
+  Eq. 1/2 shows it equals the EPIC image exactly (all pairs), and the
+  autocorrelation-removed EPIC image equals FX over a != b.
+
+Readings where the paper is silent (grid geometry, kernel shape, voltage
+packing) are the ones listed in the design notes: cell = cell_lambda *
+lambda, grid index of an element x = pos / cell + N/2, support start
+j0 = floor(x - K/2 + 1), a Gaussian kernel of width sigma cells truncated to
+K x K and normalised to unit sum, 4+4-bit two's-complement voltages with the
+real part in the high nibble.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+
+__all__ = [
+    "C_LIGHT", "decode_int4", "grid_geometry", "gaussian_kernel",
+    "support_inside", "grid", "centred_dft_matrix", "sky", "n_products",
+    "accumulate", "antenna_autos", "antenna_beams", "auto_term", "readout",
+    "fx_image", "channel_reference", "epic_reference",
+]
+
+
+# --------------------------------------------------------------------------
+# Voltages
+# --------------------------------------------------------------------------
+def decode_int4(b) -> np.ndarray:
+    """4+4-bit packed byte -> complex integer (Sec. 4 digitised voltages).
+
+    High nibble = real, low nibble = imaginary, two's complement (so 0x8
+    decodes to -8).
+    """
+    b = np.asarray(b, dtype=np.uint8).astype(np.int16)
+    hi = b >> 4
+    lo = b & 0xF
+    hi = np.where(hi >= 8, hi - 16, hi)
+    lo = np.where(lo >= 8, lo - 16, lo)
+    return hi.astype(np.float64) + 1j * lo.astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# Grid geometry and kernel (Eq. 1 inner sum; Sec. 4 grid spacing)
+# --------------------------------------------------------------------------
+def grid_geometry(pos, freq_hz, n, cell_lambda=0.5, k=3):
+    """Element positions in grid units and the first cell of each support.
+
+    The grid point j sits at (j - N/2) * cell metres, with
+    cell = cell_lambda * lambda.  Returns ``x`` (float64 [A][2], (east,
+    north) in cells) and ``j0`` (int64 [A][2]) such that the K x K support
+    of element a covers cells j0 .. j0+K-1 on each axis.
+    """
+    pos = np.asarray(pos, dtype=np.float64)
+    lam = C_LIGHT / float(freq_hz)
+    cell = cell_lambda * lam
+    x = pos / cell + n / 2.0
+    j0 = np.floor(x - k / 2.0 + 1.0).astype(np.int64)
+    return x, j0
+
+
+def gaussian_kernel(x, j0, k=3, sigma=0.5):
+    """Real, unit-sum Gaussian kernel sampled on each element's support.
+
+    Returns ``w`` float64 [A][K][K] indexed [a][dy][dx], the weight on cell
+    (j0y + dy, j0x + dx).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    A = x.shape[0]
+    w = np.zeros((A, k, k))
+    for a in range(A):
+        for dy in range(k):
+            for dx in range(k):
+                ex = j0[a, 0] + dx - x[a, 0]
+                ey = j0[a, 1] + dy - x[a, 1]
+                w[a, dy, dx] = np.exp(-(ex * ex + ey * ey) / (2.0 * sigma * sigma))
+        w[a] /= w[a].sum()
+    return w
+
+
+def support_inside(j0, k, n, aperture_n=0) -> bool:
+    """True when every support lies inside the gridded region.
+
+    The gridded region is the central ``aperture_n`` cells of the N-grid
+    (all of it when ``aperture_n`` is 0).
+    """
+    m = n if aperture_n in (0, None) else aperture_n
+    lo = (n - m) // 2
+    hi = lo + m - 1
+    return bool(np.all(j0 >= lo) and np.all(j0 + k - 1 <= hi))
+
+
+def grid(E, j0, w, n) -> np.ndarray:
+    """Eq. 1 inner sum: G[jy][jx] = sum_a conj(w_a(j)) E_a.
+
+    ``E`` is complex [..., A]; returns complex128 [..., N, N].
+    """
+    E = np.asarray(E, dtype=np.complex128)
+    A = E.shape[-1]
+    k = w.shape[-1]
+    G = np.zeros(E.shape[:-1] + (n, n), dtype=np.complex128)
+    wc = np.conj(w)
+    for a in range(A):
+        for dy in range(k):
+            for dx in range(k):
+                G[..., j0[a, 1] + dy, j0[a, 0] + dx] += wc[a, dy, dx] * E[..., a]
+    return G
+
+
+def centred_dft_matrix(n) -> np.ndarray:
+    """F[k][j] = exp(+2 pi i (k - N/2)(j - N/2) / N) (Eq. 1 outer sum).
+
+    The exponent is reduced modulo N in integer arithmetic before the
+    exponential so every entry is accurate to float64 rounding.
+    """
+    idx = np.arange(n, dtype=np.int64) - n // 2
+    p = np.mod(np.outer(idx, idx), n).astype(np.float64)
+    return np.exp(2j * np.pi * p / n)
+
+
+def sky(G) -> np.ndarray:
+    """Eq. 1 outer sum on a grid G[..., jy, jx]: returns E[..., ky, kx].
+
+    Separable direct DFT: E = F G F^T with F from ``centred_dft_matrix``.
+    """
+    G = np.asarray(G, dtype=np.complex128)
+    F = centred_dft_matrix(G.shape[-1])
+    return F @ G @ F.T
+
+
+# --------------------------------------------------------------------------
+# Eq. 2: polarisation products and the time sum
+# --------------------------------------------------------------------------
+def n_products(n_pol: int) -> int:
+    """XX only for one feed; XX, YY, Re XY, Im XY for two."""
+    return 1 if n_pol == 1 else 4
+
+
+def accumulate(Esky) -> np.ndarray:
+    """Eq. 2 summed over time from sky images ``Esky`` [T][P][N][N].
+
+    Returns float64 [n_prod][N][N]: XX = sum |Ex|^2, YY = sum |Ey|^2 and
+    XY = sum Ex conj(Ey) split into real and imaginary planes.
+    """
+    Esky = np.asarray(Esky)
+    P = Esky.shape[1]
+    ex = Esky[:, 0]
+    xx = np.sum(np.abs(ex) ** 2, axis=0)
+    if P == 1:
+        return xx[None]
+    ey = Esky[:, 1]
+    yy = np.sum(np.abs(ey) ** 2, axis=0)
+    xy = np.sum(ex * np.conj(ey), axis=0)
+    return np.stack([xx, yy, xy.real, xy.imag])
+
+
+def antenna_autos(E) -> np.ndarray:
+    """Per-element time sums S_a^{pq} = sum_t E_a^p conj(E_a^q).
+
+    ``E`` is complex [T][P][A]; returns float64 [A][n_prod] in the same
+    product order as ``accumulate`` (values are exact integers for int4
+    inputs).
+    """
+    E = np.asarray(E)
+    P = E.shape[1]
+    xx = np.sum(np.abs(E[:, 0]) ** 2, axis=0)
+    if P == 1:
+        return xx[:, None]
+    yy = np.sum(np.abs(E[:, 1]) ** 2, axis=0)
+    xy = np.sum(E[:, 0] * np.conj(E[:, 1]), axis=0)
+    return np.stack([xx, yy, xy.real, xy.imag], axis=1)
+
+
+def antenna_beams(j0, w, n) -> np.ndarray:
+    """B_a[k]: the Eq. 1 image of element a's kernel footprint alone.
+
+    B_a[ky][kx] = sum_{dy,dx} conj(w_a[dy][dx]) F[ky][j0y+dy] F[kx][j0x+dx].
+    Returns complex128 [A][N][N].
+    """
+    F = centred_dft_matrix(n)
+    A, k = w.shape[0], w.shape[-1]
+    B = np.zeros((A, n, n), dtype=np.complex128)
+    wc = np.conj(w)
+    for a in range(A):
+        Fy = F[:, j0[a, 1]:j0[a, 1] + k]          # [N][K]
+        Fx = F[:, j0[a, 0]:j0[a, 0] + k]
+        B[a] = Fy @ wc[a] @ Fx.T
+    return B
+
+
+def auto_term(S, B) -> np.ndarray:
+    """sum_a S_a^{pq} |B_a[k]|^2 for each stored product.
+
+    The same kernel serves both feeds, so every product's self term is the
+    element's power pattern weighted by its own auto sum.
+    """
+    P2 = np.abs(B) ** 2                              # [A][N][N]
+    return np.einsum("ap,ayx->pyx", np.asarray(S, dtype=np.float64), P2)
+
+
+def readout(acc, auto=None, count=1, normalise=True) -> np.ndarray:
+    """(acc - auto) / count: Eq. 2's average with the self terms removed."""
+    out = np.array(acc, dtype=np.float64, copy=True)
+    if auto is not None:
+        out -= auto
+    if normalise:
+        out /= float(count)
+    return out
+
+
+# --------------------------------------------------------------------------
+# FX route (pairwise visibilities) -- the brute-force equivalence check
+# --------------------------------------------------------------------------
+def fx_image(E, j0, w, n, include_auto=True) -> np.ndarray:
+    """Image from explicit visibilities gridded with the correlated kernel.
+
+    V_ab^{pq} = sum_t E_a^p conj(E_b^q) is placed at displacement
+    d = ja - jb with weight conj(w_a(ja)) w_b(jb) for every pair of support
+    cells, on a (2N-1)^2 displacement grid, then
+    I[k] = sum_d D[d] exp(+2 pi i (k - N/2).d / N).
+    Returns float64 [n_prod][N][N] like ``accumulate``.
+    """
+    E = np.asarray(E, dtype=np.complex128)
+    T, P, A = E.shape
+    k = w.shape[-1]
+    wc = np.conj(w)
+    m = 2 * n - 1
+    # displacement transform Q[k][d], d index = displacement + (n - 1)
+    kk = np.arange(n) - n // 2
+    dd = np.arange(m) - (n - 1)
+    Q = np.exp(2j * np.pi * np.mod(np.outer(kk, dd), n) / n)
+
+    def one(p, q):
+        V = E[:, p, :].T @ np.conj(E[:, q, :])        # [A][A], V[a][b]
+        D = np.zeros((m, m), dtype=np.complex128)
+        for a in range(A):
+            for b in range(A):
+                if a == b and not include_auto:
+                    continue
+                for ay in range(k):
+                    for ax in range(k):
+                        ca = wc[a, ay, ax] * V[a, b]
+                        for by in range(k):
+                            for bx in range(k):
+                                dy = (j0[a, 1] + ay) - (j0[b, 1] + by) + n - 1
+                                dx = (j0[a, 0] + ax) - (j0[b, 0] + bx) + n - 1
+                                D[dy, dx] += ca * w[b, by, bx]
+        return Q @ D @ Q.T
+
+    xx = one(0, 0)
+    if P == 1:
+        return np.stack([xx.real])
+    yy = one(1, 1)
+    xy = one(0, 1)
+    return np.stack([xx.real, yy.real, xy.real, xy.imag])
+
+
+# --------------------------------------------------------------------------
+# Whole path for one channel / a whole block
+# --------------------------------------------------------------------------
+def channel_reference(volt_c, pos, freq_hz, n, *, cell_lambda=0.5, k=3,
+                      sigma=0.5, kernel=None, aperture_n=0,
+                      want_images=False):
+    """Reference for one channel of packed voltages ``uint8 [T][P][A]``.
+
+    ``kernel`` optionally replaces the Gaussian with explicit complex weights
+    [A][K][K] (the weight W_a on each support cell).  Returns a dict with
+    ``acc`` (float64 [n_prod][N][N]), ``autos`` ([A][n_prod]), ``auto``
+    (the self term, same shape as acc), ``j0``, ``w`` and, on request, the
+    per-sample grids and sky images.
+    """
+    E = decode_int4(volt_c)                          # [T][P][A]
+    x, j0 = grid_geometry(pos, freq_hz, n, cell_lambda, k)
+    if not support_inside(j0, k, n, aperture_n):
+        raise ValueError("an element's kernel support leaves the gridded region")
+    if kernel is None:
+        w = gaussian_kernel(x, j0, k, sigma)
+    else:
+        w = np.asarray(kernel, dtype=np.complex128)
+    G = grid(E, j0, w, n)                            # [T][P][N][N]
+    Es = sky(G)
+    acc = accumulate(Es)
+    S = antenna_autos(E)
+    B = antenna_beams(j0, w, n)
+    out = dict(acc=acc, autos=S, auto=auto_term(S, B), j0=j0, w=w, x=x,
+               count=E.shape[0])
+    if want_images:
+        out["grid"] = G
+        out["sky"] = Es
+    return out
+
+
+def epic_reference(volt, pos, freq_hz, grid_n, *, cell_lambda=0.5, k=3,
+                   sigma=0.5, kernels=None, aperture_n=0, chans=None,
+                   remove_autos=True, normalise=True):
+    """Read-out images for a block ``uint8 [T][C][P][A]``.
+
+    Returns a list over the requested channels of float64 [n_prod][N_c][N_c]
+    images, (acc - auto) / T with the optional steps as flagged.
+    """
+    volt = np.asarray(volt)
+    C = volt.shape[1]
+    chans = range(C) if chans is None else chans
+    out = []
+    for c in chans:
+        r = channel_reference(
+            volt[:, c], pos, freq_hz[c], int(grid_n[c]), cell_lambda=cell_lambda,
+            k=k, sigma=sigma, kernel=None if kernels is None else kernels[c],
+            aperture_n=aperture_n)
+        out.append(readout(r["acc"], r["auto"] if remove_autos else None,
+                           r["count"], normalise))
+    return out
