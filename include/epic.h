@@ -1,0 +1,166 @@
+/*
+ * epic.h -- C ABI of the MI355X (gfx950) EPIC imaging library, libepic.so.
+ *
+ * EPIC (E-field Parallel Imaging "Correlator"), paper Sec. 2:
+ *   Eq. 1  E^a(s_k) = sum_j dA_j exp(+2 pi i s_k.r_j / lambda)
+ *                      ( sum_e sum_p W_e^{ap*}(r_j - r_e) E_e^p )
+ *   Eq. 2  I^{ab}(s_k) = < E^a(s_k) E^{b*}(s_k) >   over t_acc
+ * The inner sum of Eq. 1 is the gridding step (epic_grid), the outer sum
+ * the spatial Fourier transform (epic_image), Eq. 2 the polarisation outer
+ * product and time average (epic_accumulate, epic_readout).  Sec. 4: the
+ * grid is finer than half a wavelength and power-of-two friendly.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an epic_status; no C++ exception crosses the ABI.
+ *   On failure a thread-local message is available from epic_last_error().
+ * - "d_" pointers are device pointers (HIP global memory) owned by the
+ *   caller; host pointers are only read during the call.  Data calls are
+ *   asynchronous on the given HIP stream (NULL = the default stream); launch
+ *   errors are returned, faults surface on a later call as EPIC_ERR_DEVICE.
+ * - Voltages: uint8 volt[t][c][p][a], one byte per complex sample, real
+ *   part in the high nibble, imaginary part in the low nibble, both two's
+ *   complement (0x8 decodes to -8).
+ * - Grid geometry (the reading of Eq. 1 the library implements): channel c
+ *   has wavelength lambda_c = 299792458 / f_c, cell = cell_lambda * lambda_c,
+ *   grid side N_c (even).  Element a sits at x_a = pos_a / cell + N_c / 2
+ *   grid units; its K x K kernel support starts at j0 = floor(x_a - K/2 + 1).
+ *   The default kernel is a real Gaussian of width kernel_sigma_cells,
+ *   normalised to unit sum over the support.  The cell area dA_j is 1.
+ * - Sky index: E[ky][kx] = sum_j G[jy][jx] exp(+2 pi i ((kx - N/2)(jx - N/2)
+ *   + (ky - N/2)(jy - N/2)) / N); pixel (N/2, N/2) is the phase centre.
+ * - Per-channel packed layouts (channel c starts after all earlier channels):
+ *     grid / sky : complex64 [t][c][p][N_c][N_c]     (P * N_c^2 per c)
+ *     images     : float32   [c][n_prod][N_c][N_c]   (n_prod = 1 if P = 1,
+ *                  else 4: XX, YY, Re XY, Im XY with XY = Ex conj(Ey))
+ *     autos      : int32     [c][a][n_prod]  sum_t E_a^p conj(E_a^q)
+ * - A plan is immutable after creation and may be used from several threads
+ *   and streams.  An accumulator must not be used on two streams at once.
+ */
+#ifndef EPIC_H
+#define EPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EPIC_OK = 0,
+    EPIC_ERR_NULL = 1,         /* a required pointer is NULL */
+    EPIC_ERR_ARG = 2,          /* a size or enum is out of range */
+    EPIC_ERR_GRID = 3,         /* support leaves the gridded region, N odd or unsupported */
+    EPIC_ERR_UNSUPPORTED = 4,  /* precision / transform / size combination not built */
+    EPIC_ERR_OOM = 5,          /* device or host allocation failed */
+    EPIC_ERR_DEVICE = 6,       /* HIP runtime error (see epic_last_error) */
+    EPIC_ERR_MISMATCH = 7,     /* accumulator belongs to another plan */
+    EPIC_ERR_BUDGET = 8        /* request exceeds a stated memory budget */
+} epic_status;
+
+/* Arithmetic of the transform step (the time accumulation is always FP32). */
+typedef enum {
+    EPIC_F32 = 0,           /* FP32 gridding + FFT on the vector units */
+    EPIC_F16_MFMA = 1,      /* direct DFT-as-GEMM on MFMA, FP16 operands, FP32 accumulate */
+    EPIC_F8E4M3_MFMA = 2,   /* same with FP8 e4m3 operands, per-channel power-of-two scale */
+    EPIC_BF16X2_MFMA = 3    /* same with the beam matrix split into BF16 hi + lo */
+} epic_precision;
+
+/* plan flags */
+#define EPIC_PLAN_DEFAULT 0u
+
+/* readout flags */
+#define EPIC_REMOVE_AUTOS 1u   /* subtract the per-element self terms */
+#define EPIC_NORMALISE 2u      /* divide by the number of accumulated samples */
+
+typedef struct {
+    int32_t n_ant;               /* A >= 1 */
+    int32_t n_pol;               /* P: 1 or 2 feeds per element */
+    int32_t n_chan;              /* C >= 1 */
+    const double *ant_pos_m;     /* host [A][2] (east, north) metres; copied */
+    const double *chan_freq_hz;  /* host [C] channel centre frequencies; copied */
+    const int32_t *grid_n;       /* host [C] FFT side per channel (even) */
+    int32_t aperture_n;          /* 0: gridded region = whole grid; else the side of the
+                                    central region every support must fit in */
+    double cell_lambda;          /* grid cell in wavelengths (0 -> 0.5) */
+    int32_t kernel_k;            /* support side K, 1..3 */
+    double kernel_sigma_cells;   /* Gaussian width in cells (0 -> 0.5) */
+    const float *kernel_table;   /* optional host [C][A][K][K][2]: complex W_a on its
+                                    support cells [dy][dx] (replaces the Gaussian); copied */
+    int32_t precision;           /* epic_precision */
+    uint32_t flags;              /* EPIC_PLAN_DEFAULT */
+} epic_plan_desc;
+
+typedef struct epic_plan_s *epic_plan;  /* opaque; owns device tables */
+typedef struct epic_acc_s *epic_acc;    /* opaque; float acc + int32 autos + count */
+
+typedef struct {
+    int64_t image_floats;       /* sum_c n_prod N_c^2: floats in one image set */
+    int64_t grid_elems_per_t;   /* sum_c P N_c^2: complex elements per time sample */
+    int64_t autos_ints;         /* C * A * n_prod */
+    int64_t bytes_plan;         /* device bytes the plan holds */
+    int64_t bytes_acc;          /* device bytes one accumulator holds */
+    int32_t n_prod;             /* 1 or 4 */
+    int32_t max_grid_n;
+} epic_plan_info;
+
+/* Plan setup (Eq. 1 gridding geometry; Sec. 4 grid spacing).  Copies the
+ * descriptor, computes every element's grid coordinate and K x K kernel
+ * weights in FP64 on the device, checks that each support lies inside the
+ * gridded region (EPIC_ERR_GRID otherwise) and builds the per-channel
+ * gather tables.  Synchronises hip_stream once.  *out is NULL on failure. */
+epic_status epic_plan_create(const epic_plan_desc *desc, void *hip_stream, epic_plan *out);
+epic_status epic_plan_destroy(epic_plan plan);
+epic_status epic_plan_get_info(epic_plan plan, epic_plan_info *info);
+
+/* Accumulators for Eq. 2: zeroed FP32 image sums, int32 self-term sums and
+ * the sample count, all device resident and owned by the handle. */
+epic_status epic_acc_create(epic_plan plan, epic_acc *out);
+epic_status epic_acc_reset(epic_acc acc, void *hip_stream);
+epic_status epic_acc_destroy(epic_acc acc);
+/* Samples accumulated so far (host value, no synchronisation). */
+epic_status epic_acc_count(epic_acc acc, int64_t *count);
+/* Raw state copy out / in (checkpoint and resume).  d_acc: float[image_floats],
+ * d_autos: int32[autos_ints]; either may be NULL to skip it. */
+epic_status epic_acc_export(epic_acc acc, float *d_acc, int32_t *d_autos, int64_t *count,
+                            void *hip_stream);
+epic_status epic_acc_import(epic_acc acc, const float *d_acc, const int32_t *d_autos,
+                            int64_t count, void *hip_stream);
+
+/* Eq. 1 inner sum for n_time samples: d_grid[t][c][p][jy][jx] =
+ * sum_a conj(W_a(j)) E_a^p (complex64).  Writes every grid element. */
+epic_status epic_grid(epic_plan plan, const uint8_t *d_volt, int32_t n_time, void *d_grid,
+                      void *hip_stream);
+
+/* Eq. 1 outer sum: the centred 2D transform of every grid (complex64 in and
+ * out, same layout; d_sky may equal d_grid for an in-place transform). */
+epic_status epic_image(epic_plan plan, const void *d_grid, int32_t n_time, void *d_sky,
+                       void *hip_stream);
+
+/* Eq. 1 + Eq. 2 accumulated over n_time samples.
+ *   d_sky == NULL: the fused path -- grid, transform and polarisation products
+ *     of every sample stay on chip; only the sums reach HBM.  Also adds the
+ *     per-element self-term sums.
+ *   d_sky != NULL: products of given sky images (layout of epic_image); the
+ *     self-term sums are added too when d_volt is also given.
+ * Sums are added in increasing time order; results do not depend on what
+ * else runs on the device. */
+epic_status epic_accumulate(epic_plan plan, epic_acc acc, const uint8_t *d_volt,
+                            const void *d_sky, int32_t n_time, void *hip_stream);
+
+/* Read-out of Eq. 2: d_img = (acc - [REMOVE_AUTOS] self terms) / [NORMALISE] count.
+ * The self term of element a is S_a^{pq} |B_a(k)|^2 with B_a the image of its
+ * kernel footprint, evaluated exactly as sum_d H[d] exp(+2 pi i (k - N/2).d / N)
+ * over footprint displacements d. */
+epic_status epic_readout(epic_plan plan, epic_acc acc, float *d_img, uint32_t flags,
+                         void *hip_stream);
+
+const char *epic_status_str(epic_status s);
+const char *epic_last_error(void);
+/* Library version string. */
+const char *epic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EPIC_H */

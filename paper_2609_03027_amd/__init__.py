@@ -1,0 +1,9 @@
+"""MI355X-native EPIC (E-field Parallel Imaging Correlator) imaging path.
+
+The compute lives in ``libepic.so`` (hand-written HIP for gfx950, C ABI in
+``include/epic.h``); this package is its thin Python binding.
+"""
+from ._lib import (  # noqa: F401
+    EPIC_BF16X2_MFMA, EPIC_F8E4M3_MFMA, EPIC_F16_MFMA, EPIC_F32, EXPORTS, NORMALISE,
+    REMOVE_AUTOS, Accumulator, EpicError, Plan, accumulate, grid, image, load, readout,
+)

@@ -1,0 +1,255 @@
+"""ctypes binding of libepic.so (include/epic.h).
+
+Argument marshalling only: device buffers are torch tensors (their
+``data_ptr()``), streams are ``torch.cuda.Stream`` objects (their raw HIP
+handle).  Every computation runs in the library's kernels; there is no
+fallback when the library is missing -- loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libepic.so")
+
+EPIC_F32, EPIC_F16_MFMA, EPIC_F8E4M3_MFMA, EPIC_BF16X2_MFMA = 0, 1, 2, 3
+REMOVE_AUTOS = 1
+NORMALISE = 2
+
+STATUS = {0: "EPIC_OK", 1: "EPIC_ERR_NULL", 2: "EPIC_ERR_ARG", 3: "EPIC_ERR_GRID",
+          4: "EPIC_ERR_UNSUPPORTED", 5: "EPIC_ERR_OOM", 6: "EPIC_ERR_DEVICE",
+          7: "EPIC_ERR_MISMATCH", 8: "EPIC_ERR_BUDGET"}
+
+# every symbol include/epic.h declares
+EXPORTS = [
+    "epic_plan_create", "epic_plan_destroy", "epic_plan_get_info",
+    "epic_acc_create", "epic_acc_reset", "epic_acc_destroy", "epic_acc_count",
+    "epic_acc_export", "epic_acc_import", "epic_grid", "epic_image",
+    "epic_accumulate", "epic_readout", "epic_status_str", "epic_last_error",
+    "epic_version",
+]
+
+
+class EpicError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [
+        ("n_ant", C.c_int32), ("n_pol", C.c_int32), ("n_chan", C.c_int32),
+        ("ant_pos_m", C.POINTER(C.c_double)),
+        ("chan_freq_hz", C.POINTER(C.c_double)),
+        ("grid_n", C.POINTER(C.c_int32)),
+        ("aperture_n", C.c_int32),
+        ("cell_lambda", C.c_double),
+        ("kernel_k", C.c_int32),
+        ("kernel_sigma_cells", C.c_double),
+        ("kernel_table", C.POINTER(C.c_float)),
+        ("precision", C.c_int32),
+        ("flags", C.c_uint32),
+    ]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [
+        ("image_floats", C.c_int64), ("grid_elems_per_t", C.c_int64),
+        ("autos_ints", C.c_int64), ("bytes_plan", C.c_int64),
+        ("bytes_acc", C.c_int64), ("n_prod", C.c_int32), ("max_grid_n", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libepic.so (built in-tree); raise if it is not there."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2609_03027_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+    sig = {
+        "epic_plan_create": [C.POINTER(PlanDesc), vp, C.POINTER(vp)],
+        "epic_plan_destroy": [vp],
+        "epic_plan_get_info": [vp, C.POINTER(PlanInfo)],
+        "epic_acc_create": [vp, C.POINTER(vp)],
+        "epic_acc_reset": [vp, vp],
+        "epic_acc_destroy": [vp],
+        "epic_acc_count": [vp, C.POINTER(i64)],
+        "epic_acc_export": [vp, vp, vp, C.POINTER(i64), vp],
+        "epic_acc_import": [vp, vp, vp, i64, vp],
+        "epic_grid": [vp, vp, i32, vp, vp],
+        "epic_image": [vp, vp, i32, vp, vp],
+        "epic_accumulate": [vp, vp, vp, vp, i32, vp],
+        "epic_readout": [vp, vp, vp, u32, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    for name in ("epic_status_str",):
+        getattr(lib, name).argtypes = [C.c_int]
+        getattr(lib, name).restype = C.c_char_p
+    for name in ("epic_last_error", "epic_version"):
+        getattr(lib, name).argtypes = []
+        getattr(lib, name).restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != 0:
+        raise EpicError(status, load().epic_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """An immutable imaging plan: array geometry, channels, grids, kernel."""
+
+    def __init__(self, pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5,
+                 kernel_k=3, kernel_sigma=0.5, kernel_table=None, precision=EPIC_F32,
+                 stream=None):
+        lib = load()
+        self._pos = np.ascontiguousarray(pos, dtype=np.float64)
+        self._freq = np.ascontiguousarray(freq_hz, dtype=np.float64)
+        self._gn = np.ascontiguousarray(grid_n, dtype=np.int32)
+        self._table = None if kernel_table is None else np.ascontiguousarray(
+            kernel_table, dtype=np.float32)
+        d = PlanDesc()
+        d.n_ant = self._pos.shape[0]
+        d.n_pol = int(n_pol)
+        d.n_chan = self._freq.shape[0]
+        d.ant_pos_m = self._pos.ctypes.data_as(C.POINTER(C.c_double))
+        d.chan_freq_hz = self._freq.ctypes.data_as(C.POINTER(C.c_double))
+        d.grid_n = self._gn.ctypes.data_as(C.POINTER(C.c_int32))
+        d.aperture_n = int(aperture_n)
+        d.cell_lambda = float(cell_lambda)
+        d.kernel_k = int(kernel_k)
+        d.kernel_sigma_cells = float(kernel_sigma)
+        d.kernel_table = (None if self._table is None else
+                          self._table.ctypes.data_as(C.POINTER(C.c_float)))
+        d.precision = int(precision)
+        d.flags = 0
+        h = C.c_void_p()
+        check(lib.epic_plan_create(C.byref(d), _stream(stream), C.byref(h)))
+        self.handle = h
+        info = PlanInfo()
+        check(lib.epic_plan_get_info(h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in PlanInfo._fields_}
+        self.n_ant, self.n_pol, self.n_chan = d.n_ant, d.n_pol, d.n_chan
+        self.n_prod = info.n_prod
+        self.grid_n = self._gn.copy()
+        n2 = self.grid_n.astype(np.int64) ** 2
+        self.img_off = np.concatenate([[0], np.cumsum(self.n_prod * n2)[:-1]])
+        self.grid_off = np.concatenate([[0], np.cumsum(self.n_pol * n2)[:-1]])
+        self.precision = precision
+
+    @classmethod
+    def from_workload(cls, wl, pos, **kw):
+        return cls(pos, wl.chan_freq_hz, wl.grid_n, wl.n_pol, aperture_n=wl.aperture_n,
+                   cell_lambda=wl.cell_lambda, kernel_k=wl.kernel_k,
+                   kernel_sigma=wl.kernel_sigma_cells, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(load().epic_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # helpers to view packed outputs per channel
+    def channel_image(self, img, c):
+        n = int(self.grid_n[c])
+        o = int(self.img_off[c])
+        return img[o:o + self.n_prod * n * n].view(self.n_prod, n, n)
+
+    def channel_grid(self, g, t, c):
+        """grid / sky tensor viewed as complex [t][elems] -> [P][N][N] of (t, c)."""
+        n = int(self.grid_n[c])
+        o = int(self.grid_off[c])
+        return g[t, o:o + self.n_pol * n * n].view(self.n_pol, n, n)
+
+
+class Accumulator:
+    """Device-resident Eq. 2 sums (FP32 images, int32 self terms, count)."""
+
+    def __init__(self, plan: Plan):
+        h = C.c_void_p()
+        check(load().epic_acc_create(plan.handle, C.byref(h)))
+        self.handle = h
+        self.plan = plan
+
+    @property
+    def count(self) -> int:
+        v = C.c_int64()
+        check(load().epic_acc_count(self.handle, C.byref(v)))
+        return v.value
+
+    def reset(self, stream=None):
+        check(load().epic_acc_reset(self.handle, _stream(stream)))
+
+    def export(self, acc=None, autos=None, stream=None) -> int:
+        n = C.c_int64()
+        check(load().epic_acc_export(self.handle, _ptr(acc), _ptr(autos), C.byref(n),
+                                     _stream(stream)))
+        return n.value
+
+    def import_(self, acc=None, autos=None, count=0, stream=None):
+        check(load().epic_acc_import(self.handle, _ptr(acc), _ptr(autos), int(count),
+                                     _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(load().epic_acc_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def grid(plan: Plan, volt, n_time: int, out, stream=None):
+    check(load().epic_grid(plan.handle, _ptr(volt), int(n_time), _ptr(out), _stream(stream)))
+
+
+def image(plan: Plan, grid_t, n_time: int, out, stream=None):
+    check(load().epic_image(plan.handle, _ptr(grid_t), int(n_time), _ptr(out), _stream(stream)))
+
+
+def accumulate(plan: Plan, acc: Accumulator, volt=None, sky=None, n_time=None, stream=None):
+    if n_time is None:
+        n_time = (volt if volt is not None else sky).shape[0]
+    check(load().epic_accumulate(plan.handle, acc.handle, _ptr(volt), _ptr(sky), int(n_time),
+                                 _stream(stream)))
+
+
+def readout(plan: Plan, acc: Accumulator, out, flags=REMOVE_AUTOS | NORMALISE, stream=None):
+    check(load().epic_readout(plan.handle, acc.handle, _ptr(out), int(flags), _stream(stream)))

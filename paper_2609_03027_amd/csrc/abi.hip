@@ -1,0 +1,274 @@
+// extern "C" entry points of libepic.so (declared in include/epic.h).
+// Argument checks happen here, before any device work; no C++ exception
+// crosses the boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace epic {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+epic_status fail(epic_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+epic_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return EPIC_ERR_DEVICE;
+}
+
+}  // namespace epic
+
+using namespace epic;
+
+#define EPIC_GUARD_BEGIN try {
+#define EPIC_GUARD_END                                                       \
+    }                                                                        \
+    catch (const std::bad_alloc &) {                                         \
+        return fail(EPIC_ERR_OOM, "host allocation failed");                 \
+    }                                                                        \
+    catch (...) {                                                            \
+        return fail(EPIC_ERR_DEVICE, "unexpected internal error");           \
+    }
+
+extern "C" {
+
+const char *epic_version(void) { return "epic-mi355x 0.1 (gfx950)"; }
+
+const char *epic_status_str(epic_status s) {
+    switch (s) {
+        case EPIC_OK: return "ok";
+        case EPIC_ERR_NULL: return "null pointer";
+        case EPIC_ERR_ARG: return "bad argument";
+        case EPIC_ERR_GRID: return "grid geometry";
+        case EPIC_ERR_UNSUPPORTED: return "unsupported";
+        case EPIC_ERR_OOM: return "out of memory";
+        case EPIC_ERR_DEVICE: return "device error";
+        case EPIC_ERR_MISMATCH: return "plan/accumulator mismatch";
+        case EPIC_ERR_BUDGET: return "over budget";
+    }
+    return "unknown status";
+}
+
+const char *epic_last_error(void) { return g_err.c_str(); }
+
+epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_plan *out) {
+    EPIC_GUARD_BEGIN
+    if (!out) return fail(EPIC_ERR_NULL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(EPIC_ERR_NULL, "descriptor is NULL");
+    if (!d->ant_pos_m || !d->chan_freq_hz || !d->grid_n)
+        return fail(EPIC_ERR_NULL, "positions, frequencies and grid sizes are required");
+    if (d->n_ant < 1 || d->n_ant > 65535) return fail(EPIC_ERR_ARG, "n_ant must be in [1, 65535]");
+    if (d->n_pol != 1 && d->n_pol != 2) return fail(EPIC_ERR_ARG, "n_pol must be 1 or 2");
+    if (d->n_chan < 1) return fail(EPIC_ERR_ARG, "n_chan must be >= 1");
+    const int K = d->kernel_k;
+    if (K < 1 || K > 3) return fail(EPIC_ERR_ARG, "kernel_k must be 1, 2 or 3");
+    const double cl = d->cell_lambda == 0.0 ? 0.5 : d->cell_lambda;
+    const double sg = d->kernel_sigma_cells == 0.0 ? 0.5 : d->kernel_sigma_cells;
+    if (!(cl > 0.0) || !std::isfinite(cl)) return fail(EPIC_ERR_ARG, "cell_lambda must be > 0");
+    if (!(sg > 0.0) || !std::isfinite(sg)) return fail(EPIC_ERR_ARG, "kernel_sigma_cells must be > 0");
+    if (d->precision < EPIC_F32 || d->precision > EPIC_BF16X2_MFMA)
+        return fail(EPIC_ERR_ARG, "unknown precision");
+    if (d->precision != EPIC_F32)
+        return fail(EPIC_ERR_UNSUPPORTED, "this precision is not built into the library");
+    if (d->aperture_n < 0 || (d->aperture_n & 1))
+        return fail(EPIC_ERR_ARG, "aperture_n must be 0 or a positive even number");
+    for (int c = 0; c < d->n_chan; ++c)
+        if (!(d->chan_freq_hz[c] > 0.0) || !std::isfinite(d->chan_freq_hz[c]))
+            return fail(EPIC_ERR_ARG, "channel frequencies must be finite and > 0");
+    for (int i = 0; i < 2 * d->n_ant; ++i)
+        if (!std::isfinite(d->ant_pos_m[i])) return fail(EPIC_ERR_ARG, "positions must be finite");
+    for (int c = 0; c < d->n_chan; ++c)
+        if (d->grid_n[c] < 8 || (d->grid_n[c] & 1))
+            return fail(EPIC_ERR_GRID, "grid sides must be even and >= 8");
+
+    auto *p = new epic_plan_s();
+    p->A = d->n_ant;
+    p->P = d->n_pol;
+    p->C = d->n_chan;
+    p->K = K;
+    p->aperture_n = d->aperture_n;
+    p->cell_lambda = cl;
+    p->sigma = sg;
+    p->precision = d->precision;
+    p->flags = d->flags;
+    p->n_prod = p->P == 2 ? 4 : 1;
+    p->pos.assign(d->ant_pos_m, d->ant_pos_m + 2 * p->A);
+    p->freq.assign(d->chan_freq_hz, d->chan_freq_hz + p->C);
+    p->grid_n.assign(d->grid_n, d->grid_n + p->C);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    epic_status st = EPIC_OK;
+    if (d->kernel_table) {
+        p->has_table = true;
+        const size_t n = (size_t)p->C * p->A * K * K * 2;
+        st = p->d_table.alloc(sizeof(float) * n);
+        if (!st) {
+            hipError_t e = hipMemcpyAsync(p->d_table.p, d->kernel_table, sizeof(float) * n,
+                                          hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = hip_fail(e, "kernel table upload");
+        }
+    }
+    if (!st) st = plan_build(p, s);
+    if (st) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return EPIC_OK;
+    EPIC_GUARD_END
+}
+
+epic_status epic_plan_destroy(epic_plan plan) {
+    EPIC_GUARD_BEGIN
+    if (!plan) return fail(EPIC_ERR_NULL, "plan is NULL");
+    delete plan;
+    return EPIC_OK;
+    EPIC_GUARD_END
+}
+
+epic_status epic_plan_get_info(epic_plan p, epic_plan_info *info) {
+    if (!p || !info) return fail(EPIC_ERR_NULL, "plan or info is NULL");
+    info->image_floats = p->image_floats;
+    info->grid_elems_per_t = p->grid_elems_per_t;
+    info->autos_ints = (int64_t)p->C * p->A * p->n_prod;
+    info->bytes_plan = p->bytes_plan;
+    const int D = 2 * p->K - 1;
+    info->bytes_acc = (int64_t)sizeof(float) * p->image_floats +
+                      (int64_t)sizeof(int32_t) * info->autos_ints +
+                      (int64_t)sizeof(double2) * p->C * (p->P == 2 ? 3 : 1) * D * D;
+    info->n_prod = p->n_prod;
+    info->max_grid_n = p->max_n;
+    return EPIC_OK;
+}
+
+epic_status epic_acc_create(epic_plan p, epic_acc *out) {
+    EPIC_GUARD_BEGIN
+    if (!out) return fail(EPIC_ERR_NULL, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(EPIC_ERR_NULL, "plan is NULL");
+    auto *a = new epic_acc_s();
+    a->plan = p;
+    const int D = 2 * p->K - 1;
+    epic_status st = a->d_acc.alloc(sizeof(float) * p->image_floats);
+    if (!st) st = a->d_autos.alloc(sizeof(int32_t) * (size_t)p->C * p->A * p->n_prod);
+    if (!st) st = a->d_h.alloc(sizeof(double2) * (size_t)p->C * (p->P == 2 ? 3 : 1) * D * D);
+    if (!st) {
+        hipError_t e = hipMemset(a->d_acc.p, 0, a->d_acc.bytes);
+        if (e == hipSuccess) e = hipMemset(a->d_autos.p, 0, a->d_autos.bytes);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) st = hip_fail(e, "accumulator zeroing");
+    }
+    if (st) {
+        delete a;
+        return st;
+    }
+    *out = a;
+    return EPIC_OK;
+    EPIC_GUARD_END
+}
+
+epic_status epic_acc_reset(epic_acc a, void *hip_stream) {
+    if (!a) return fail(EPIC_ERR_NULL, "acc is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    EPIC_HIP(hipMemsetAsync(a->d_acc.p, 0, a->d_acc.bytes, s));
+    EPIC_HIP(hipMemsetAsync(a->d_autos.p, 0, a->d_autos.bytes, s));
+    a->count = 0;
+    return EPIC_OK;
+}
+
+epic_status epic_acc_destroy(epic_acc a) {
+    EPIC_GUARD_BEGIN
+    if (!a) return fail(EPIC_ERR_NULL, "acc is NULL");
+    delete a;
+    return EPIC_OK;
+    EPIC_GUARD_END
+}
+
+epic_status epic_acc_count(epic_acc a, int64_t *count) {
+    if (!a || !count) return fail(EPIC_ERR_NULL, "acc or count is NULL");
+    *count = a->count;
+    return EPIC_OK;
+}
+
+epic_status epic_acc_export(epic_acc a, float *d_acc, int32_t *d_autos, int64_t *count,
+                            void *hip_stream) {
+    if (!a) return fail(EPIC_ERR_NULL, "acc is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (d_acc) EPIC_HIP(hipMemcpyAsync(d_acc, a->d_acc.p, a->d_acc.bytes, hipMemcpyDeviceToDevice, s));
+    if (d_autos)
+        EPIC_HIP(hipMemcpyAsync(d_autos, a->d_autos.p, a->d_autos.bytes, hipMemcpyDeviceToDevice, s));
+    if (count) *count = a->count;
+    return EPIC_OK;
+}
+
+epic_status epic_acc_import(epic_acc a, const float *d_acc, const int32_t *d_autos, int64_t count,
+                            void *hip_stream) {
+    if (!a) return fail(EPIC_ERR_NULL, "acc is NULL");
+    if (count < 0) return fail(EPIC_ERR_ARG, "count must be >= 0");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (d_acc) EPIC_HIP(hipMemcpyAsync(a->d_acc.p, d_acc, a->d_acc.bytes, hipMemcpyDeviceToDevice, s));
+    if (d_autos)
+        EPIC_HIP(hipMemcpyAsync(a->d_autos.p, d_autos, a->d_autos.bytes, hipMemcpyDeviceToDevice, s));
+    a->count = count;
+    return EPIC_OK;
+}
+
+epic_status epic_grid(epic_plan p, const uint8_t *d_volt, int32_t n_time, void *d_grid,
+                      void *hip_stream) {
+    EPIC_GUARD_BEGIN
+    if (!p || !d_volt || !d_grid) return fail(EPIC_ERR_NULL, "plan, volt and grid are required");
+    if (n_time < 0) return fail(EPIC_ERR_ARG, "n_time must be >= 0");
+    if (n_time == 0) return EPIC_OK;
+    return staged_grid(p, d_volt, n_time, d_grid, static_cast<hipStream_t>(hip_stream));
+    EPIC_GUARD_END
+}
+
+epic_status epic_image(epic_plan p, const void *d_grid, int32_t n_time, void *d_sky,
+                       void *hip_stream) {
+    EPIC_GUARD_BEGIN
+    if (!p || !d_grid || !d_sky) return fail(EPIC_ERR_NULL, "plan, grid and sky are required");
+    if (n_time < 0) return fail(EPIC_ERR_ARG, "n_time must be >= 0");
+    if (n_time == 0) return EPIC_OK;
+    return staged_image(p, d_grid, n_time, d_sky, static_cast<hipStream_t>(hip_stream));
+    EPIC_GUARD_END
+}
+
+epic_status epic_accumulate(epic_plan p, epic_acc a, const uint8_t *d_volt, const void *d_sky,
+                            int32_t n_time, void *hip_stream) {
+    EPIC_GUARD_BEGIN
+    if (!p || !a) return fail(EPIC_ERR_NULL, "plan and acc are required");
+    if (a->plan != p) return fail(EPIC_ERR_MISMATCH, "accumulator belongs to another plan");
+    if (!d_volt && !d_sky) return fail(EPIC_ERR_NULL, "volt or sky is required");
+    if (n_time < 0) return fail(EPIC_ERR_ARG, "n_time must be >= 0");
+    if (n_time == 0) return EPIC_OK;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    epic_status st;
+    if (d_sky) {
+        st = staged_accumulate(p, a, d_sky, n_time, s);
+        if (!st && d_volt) st = autos_accumulate(p, a, d_volt, n_time, s);
+    } else {
+        st = fused_accumulate(p, a, d_volt, n_time, s);
+    }
+    if (!st) a->count += n_time;
+    return st;
+    EPIC_GUARD_END
+}
+
+epic_status epic_readout(epic_plan p, epic_acc a, float *d_img, uint32_t flags, void *hip_stream) {
+    EPIC_GUARD_BEGIN
+    if (!p || !a || !d_img) return fail(EPIC_ERR_NULL, "plan, acc and img are required");
+    if (a->plan != p) return fail(EPIC_ERR_MISMATCH, "accumulator belongs to another plan");
+    if (flags & ~(EPIC_REMOVE_AUTOS | EPIC_NORMALISE)) return fail(EPIC_ERR_ARG, "unknown flags");
+    return readout(p, a, d_img, flags, static_cast<hipStream_t>(hip_stream));
+    EPIC_GUARD_END
+}
+
+}  // extern "C"

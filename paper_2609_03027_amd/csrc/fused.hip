@@ -1,0 +1,475 @@
+// Fused EPIC path: per time sample, gridding (Eq. 1 inner sum), the spatial
+// transform (Eq. 1 outer sum) and the polarisation products (Eq. 2) stay in
+// LDS and registers; only the time sums leave the chip.
+//
+// Decomposition.  With the centred transform of Eq. 1 written on integer
+// indices,
+//   E[k] = sum_j G[j] exp(+2 pi i (k - N/2)(j - N/2) / N)
+//        = (-1)^k c_N sum_j (-1)^j G[j] exp(+2 pi i k j / N)     (per axis)
+// and the factor (-1)^k c_N has modulus one and is the same for both feeds,
+// so it cancels in |E|^2 and Ex conj(Ey).  Splitting k = R k' + o with
+// N = R M,
+//   sum_j (-1)^j G[j] e^{2 pi i (R k' + o) j / N}
+//     = sum_{m<M} e^{2 pi i k' m / M} sum_{j = m mod M} (-1)^j e^{2 pi i o j / N} G[j],
+// i.e. each output class o in [0, R)^2 is an M x M transform of a grid folded
+// modulo M whose weights carry (-1)^(jx+jy) exp(+2 pi i (o . j) / N).  The
+// plan folds those factors into the gather weights, so the kernel only ever
+// runs M x M transforms (M = 16, 32, 64) with no index shifts.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <queue>
+
+#include "internal.h"
+
+namespace epic {
+
+template <int M> struct FCfg;
+template <> struct FCfg<64> { static constexpr int T = 512, RA = 8, RB = 8, ROW = 65; };
+template <> struct FCfg<32> { static constexpr int T = 128, RA = 8, RB = 4, ROW = 33; };
+template <> struct FCfg<16> { static constexpr int T = 64, RA = 4, RB = 4, ROW = 17; };
+
+// ---------------------------------------------------------------- complex
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 mul_i(float2 a) { return make_float2(-a.y, a.x); }
+
+// Length-R DFT with the positive exponent, natural order in and out:
+// v[p] <- sum_q v[q] exp(+2 pi i p q / R).
+template <int R> __device__ __forceinline__ void dft(float2 *v);
+
+template <> __device__ __forceinline__ void dft<4>(float2 *v) {
+    const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const float2 t2 = cadd(v[1], v[3]), t3 = mul_i(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+}
+
+template <> __device__ __forceinline__ void dft<8>(float2 *v) {
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft<4>(e);
+    dft<4>(o);
+    const float h = 0.70710678118654752440f;
+    // o1 *= (1+i)/sqrt2, o2 *= i, o3 *= (-1+i)/sqrt2
+    o[1] = make_float2((o[1].x - o[1].y) * h, (o[1].x + o[1].y) * h);
+    o[2] = mul_i(o[2]);
+    o[3] = make_float2(-(o[3].x + o[3].y) * h, (o[3].x - o[3].y) * h);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        v[p] = cadd(e[p], o[p]);
+        v[p + 4] = csub(e[p], o[p]);
+    }
+}
+
+// ------------------------------------------------------------ DIF passes
+// In-place decimation-in-frequency over one axis of an M x M grid stored
+// with row pitch ROW.  Pass A (radix RA, stride M/RA) multiplies output p by
+// exp(+2 pi i p j / M); pass B (radix RB, stride 1) has unit twiddles.  After
+// both passes position n of the axis holds frequency n / RB + RA (n % RB).
+template <int M, int NG, bool ALONG_X>
+__device__ __forceinline__ void pass_a(float2 *g0, float2 *g1, int tid, const float2 *tw) {
+    constexpr int RA = FCfg<M>::RA, ROW = FCfg<M>::ROW, S = M / RA;
+    const int line = tid % M, j = tid / M;
+    const int base = ALONG_X ? line * ROW + j : j * ROW + line;
+    constexpr int step = ALONG_X ? S : S * ROW;
+    float2 v0[RA], v1[RA];
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+        v0[q] = g0[base + q * step];
+        if (NG == 2) v1[q] = g1[base + q * step];
+    }
+    dft<RA>(v0);
+    if (NG == 2) dft<RA>(v1);
+#pragma unroll
+    for (int p = 1; p < RA; ++p) {
+        v0[p] = cmul(v0[p], tw[p]);
+        if (NG == 2) v1[p] = cmul(v1[p], tw[p]);
+    }
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+        g0[base + q * step] = v0[q];
+        if (NG == 2) g1[base + q * step] = v1[q];
+    }
+}
+
+template <int M, int NG, bool ALONG_X>
+__device__ __forceinline__ void pass_b(float2 *g0, float2 *g1, int tid) {
+    constexpr int T = FCfg<M>::T, RB = FCfg<M>::RB, ROW = FCfg<M>::ROW;
+    constexpr int NB = M * M / (RB * T);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int u = tid + k * T;
+        const int line = u % M, blk = u / M;
+        const int base = ALONG_X ? line * ROW + blk * RB : blk * RB * ROW + line;
+        constexpr int step = ALONG_X ? 1 : ROW;
+        float2 v0[RB], v1[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            v0[q] = g0[base + q * step];
+            if (NG == 2) v1[q] = g1[base + q * step];
+        }
+        dft<RB>(v0);
+        if (NG == 2) dft<RB>(v1);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            g0[base + q * step] = v0[q];
+            if (NG == 2) g1[base + q * step] = v1[q];
+        }
+    }
+}
+
+template <int M> __device__ __forceinline__ int unscramble(int n) {
+    return n / FCfg<M>::RB + FCfg<M>::RA * (n % FCfg<M>::RB);
+}
+
+// ------------------------------------------------------------------ kernel
+// One workgroup per item (channel c, class o), looping over all n_time
+// samples.  Gather entry (uint4): x = element | last-tap-of-cell << 31,
+// y = LDS index of the folded cell, z/w = folded complex weight (float bits).
+template <int M, int P>
+__global__ __launch_bounds__(FCfg<M>::T) void k_fused(const FusedItem *__restrict__ items,
+                                                      const uint4 *__restrict__ entries,
+                                                      const uint8_t *__restrict__ volt,
+                                                      int64_t volt_t_stride, int A, int n_time,
+                                                      float *__restrict__ acc) {
+    constexpr int T = FCfg<M>::T, RA = FCfg<M>::RA, ROW = FCfg<M>::ROW;
+    constexpr int NPIX = M * M / T;
+    constexpr int NPROD = P == 2 ? 4 : 1;
+    constexpr int GSZ = M * ROW;
+    extern __shared__ float4 smem[];
+    float2 *gx = reinterpret_cast<float2 *>(smem);
+    float2 *gy = gx + GSZ;
+    float4 *stage = reinterpret_cast<float4 *>(gx + P * GSZ);
+
+    const FusedItem it = items[blockIdx.x];
+    const int tid = threadIdx.x;
+
+    float2 tw[RA];
+    {
+        const int j = tid / M;
+#pragma unroll
+        for (int p = 0; p < RA; ++p) {
+            double sn, cs;
+            sincospi(2.0 * (double)(p * j) / (double)M, &sn, &cs);
+            tw[p] = make_float2((float)cs, (float)sn);
+        }
+    }
+    for (int i = tid; i < P * GSZ; i += T) gx[i] = make_float2(0.f, 0.f);
+
+    float av[NPIX][NPROD];
+#pragma unroll
+    for (int k = 0; k < NPIX; ++k)
+#pragma unroll
+        for (int q = 0; q < NPROD; ++q) av[k][q] = 0.f;
+
+    const uint8_t *vbase = volt + (int64_t)it.c * P * A;
+    const uint4 *ent = entries + it.entry_off + tid;
+    const int n_iter = it.n_iter;
+
+    for (int t = 0; t < n_time; ++t) {
+        const uint8_t *vt = vbase + (int64_t)t * volt_t_stride;
+        for (int a = tid; a < A; a += T) {
+            const uint32_t bx = vt[a];
+            const uint32_t by = P == 2 ? (uint32_t)vt[A + a] : 0u;
+            stage[a] = make_float4((float)dec_re(bx), (float)dec_im(bx), (float)dec_re(by),
+                                   (float)dec_im(by));
+        }
+        __syncthreads();
+
+        // gather: this lane owns whole cells, so every cell is written once
+        float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
+        for (int k = 0; k < n_iter; ++k) {
+            const uint4 e = ent[(int64_t)k * T];
+            const float4 v = stage[e.x & 0xFFFFu];
+            const float wr = __uint_as_float(e.z), wi = __uint_as_float(e.w);
+            sx.x += wr * v.x - wi * v.y;
+            sx.y += wr * v.y + wi * v.x;
+            if (P == 2) {
+                sy.x += wr * v.z - wi * v.w;
+                sy.y += wr * v.w + wi * v.z;
+            }
+            if (e.x >> 31) {
+                gx[e.y] = sx;
+                if (P == 2) gy[e.y] = sy;
+                sx = make_float2(0.f, 0.f);
+                sy = make_float2(0.f, 0.f);
+            }
+        }
+        __syncthreads();
+
+        pass_a<M, P, true>(gx, gy, tid, tw);
+        __syncthreads();
+        pass_b<M, P, true>(gx, gy, tid);
+        __syncthreads();
+        pass_a<M, P, false>(gx, gy, tid, tw);
+        __syncthreads();
+        pass_b<M, P, false>(gx, gy, tid);
+        __syncthreads();
+
+        // Eq. 2 products into this thread's pixels; leave the grid zeroed
+#pragma unroll
+        for (int k = 0; k < NPIX; ++k) {
+            const int i = tid + k * T;
+            const int idx = (i / M) * ROW + (i % M);
+            const float2 ex = gx[idx];
+            gx[idx] = make_float2(0.f, 0.f);
+            av[k][0] += ex.x * ex.x + ex.y * ex.y;
+            if (P == 2) {
+                const float2 ey = gy[idx];
+                gy[idx] = make_float2(0.f, 0.f);
+                av[k][1] += ey.x * ey.x + ey.y * ey.y;
+                av[k][2] += ex.x * ey.x + ex.y * ey.y;
+                av[k][3] += ex.y * ey.x - ex.x * ey.y;
+            }
+        }
+        // the stage barrier of the next sample orders these LDS writes
+    }
+
+    const int N = it.N, R = it.R;
+    const int64_t plane = (int64_t)N * N;
+#pragma unroll
+    for (int k = 0; k < NPIX; ++k) {
+        const int i = tid + k * T;
+        const int ky = R * unscramble<M>(i / M) + it.oy;
+        const int kx = R * unscramble<M>(i % M) + it.ox;
+        float *dst = acc + it.img_off + (int64_t)ky * N + kx;
+#pragma unroll
+        for (int q = 0; q < NPROD; ++q) dst[q * plane] += av[k][q];
+    }
+}
+
+// Per-element self-term sums S_a^{pq} = sum_t E_a^p conj(E_a^q), exact in
+// int32 (|E|^2 <= 128 per sample).  Grid: (elements, channels, time chunks).
+template <int P>
+__global__ void k_autos(const uint8_t *__restrict__ volt, int64_t volt_t_stride, int A,
+                        int n_time, int t_chunk, int32_t *__restrict__ autos) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (a >= A) return;
+    const int t0 = blockIdx.z * t_chunk;
+    const int t1 = min(n_time, t0 + t_chunk);
+    int sxx = 0, syy = 0, sre = 0, sim = 0;
+    const uint8_t *v = volt + (int64_t)c * P * A + a;
+    for (int t = t0; t < t1; ++t) {
+        const uint32_t bx = v[(int64_t)t * volt_t_stride];
+        const int xr = dec_re(bx), xi = dec_im(bx);
+        sxx += xr * xr + xi * xi;
+        if (P == 2) {
+            const uint32_t by = v[(int64_t)t * volt_t_stride + A];
+            const int yr = dec_re(by), yi = dec_im(by);
+            syy += yr * yr + yi * yi;
+            sre += xr * yr + xi * yi;
+            sim += xi * yr - xr * yi;
+        }
+    }
+    constexpr int NPROD = P == 2 ? 4 : 1;
+    int32_t *dst = autos + ((int64_t)c * A + a) * NPROD;
+    atomicAdd(dst, sxx);
+    if (P == 2) {
+        atomicAdd(dst + 1, syy);
+        atomicAdd(dst + 2, sre);
+        atomicAdd(dst + 3, sim);
+    }
+}
+
+// ------------------------------------------------------------ host build
+template <int M> static constexpr int threads_for() { return FCfg<M>::T; }
+
+static int threads_of(int M) {
+    return M == 64 ? FCfg<64>::T : M == 32 ? FCfg<32>::T : FCfg<16>::T;
+}
+static int row_of(int M) {
+    return M == 64 ? FCfg<64>::ROW : M == 32 ? FCfg<32>::ROW : FCfg<16>::ROW;
+}
+
+epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
+                        hipStream_t s) {
+    const int A = p->A, K = p->K;
+    for (int M : {64, 32, 16}) {
+        std::vector<int> chans;
+        for (int c = 0; c < p->C; ++c)
+            if (p->ch[c].M == M) chans.push_back(c);
+        if (chans.empty()) continue;
+        const int T = threads_of(M), ROW = row_of(M);
+        auto *g = new FusedGroup();
+        g->M = M;
+        p->groups.push_back(g);
+
+        struct Tap {
+            int cell, ant;
+            float wr, wi;
+        };
+        std::vector<uint4> all;
+        std::vector<FusedItem> items;
+        std::vector<Tap> taps((size_t)A * K * K);
+        std::vector<int> order;
+        for (int c : chans) {
+            const int N = p->ch[c].N, R = p->ch[c].R;
+            for (int oy = 0; oy < R; ++oy)
+                for (int ox = 0; ox < R; ++ox) {
+                    // folded taps of this class
+                    size_t n = 0;
+                    for (int a = 0; a < A; ++a) {
+                        const int jx0 = j0[((size_t)c * A + a) * 2];
+                        const int jy0 = j0[((size_t)c * A + a) * 2 + 1];
+                        for (int dy = 0; dy < K; ++dy)
+                            for (int dx = 0; dx < K; ++dx) {
+                                const int jx = jx0 + dx, jy = jy0 + dy;
+                                const size_t wi = (((size_t)c * A + a) * K * K + dy * K + dx) * 2;
+                                // conj(W) * (-1)^(jx+jy) * exp(+2 pi i (ox jx + oy jy) / N)
+                                const double wr0 = w[wi], wi0 = -w[wi + 1];
+                                const long ph = ((long)ox * jx + (long)oy * jy) % N;
+                                const double ang = 2.0 * M_PI * (double)ph / (double)N;
+                                const double sg = ((jx + jy) & 1) ? -1.0 : 1.0;
+                                const double cr = std::cos(ang) * sg, ci = std::sin(ang) * sg;
+                                Tap tp;
+                                tp.cell = (jy % M) * ROW + (jx % M);
+                                tp.ant = a;
+                                tp.wr = (float)(wr0 * cr - wi0 * ci);
+                                tp.wi = (float)(wr0 * ci + wi0 * cr);
+                                taps[n++] = tp;
+                            }
+                    }
+                    std::stable_sort(taps.begin(), taps.end(),
+                                     [](const Tap &x, const Tap &y) { return x.cell < y.cell; });
+                    // cells as runs of the sorted taps
+                    std::vector<std::pair<int, int>> runs;  // (start, count)
+                    for (size_t i = 0; i < n;) {
+                        size_t k = i;
+                        while (k < n && taps[k].cell == taps[i].cell) ++k;
+                        runs.push_back({(int)i, (int)(k - i)});
+                        i = k;
+                    }
+                    // longest-first onto the least-loaded lane
+                    order.resize(runs.size());
+                    std::iota(order.begin(), order.end(), 0);
+                    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+                        return runs[x].second > runs[y].second;
+                    });
+                    std::vector<std::vector<int>> lane_runs(T);
+                    std::vector<int> load(T, 0);
+                    using LP = std::pair<int, int>;
+                    std::priority_queue<LP, std::vector<LP>, std::greater<LP>> heap;
+                    for (int l = 0; l < T; ++l) heap.push({0, l});
+                    for (int r : order) {
+                        LP top = heap.top();
+                        heap.pop();
+                        lane_runs[top.second].push_back(r);
+                        load[top.second] += runs[r].second;
+                        heap.push({load[top.second], top.second});
+                    }
+                    const int n_iter = *std::max_element(load.begin(), load.end());
+                    const size_t off = all.size();
+                    all.resize(off + (size_t)n_iter * T, make_uint4(0u, 0u, 0u, 0u));
+                    for (int l = 0; l < T; ++l) {
+                        int k = 0;
+                        for (int r : lane_runs[l]) {
+                            for (int i = 0; i < runs[r].second; ++i, ++k) {
+                                const Tap &tp = taps[runs[r].first + i];
+                                const bool last = (i == runs[r].second - 1);
+                                uint4 e;
+                                e.x = (uint32_t)tp.ant | (last ? 0x80000000u : 0u);
+                                e.y = (uint32_t)tp.cell;
+                                e.z = __builtin_bit_cast(uint32_t, tp.wr);
+                                e.w = __builtin_bit_cast(uint32_t, tp.wi);
+                                all[off + (size_t)k * T + l] = e;
+                            }
+                        }
+                    }
+                    FusedItem fi;
+                    fi.c = c;
+                    fi.N = N;
+                    fi.R = R;
+                    fi.ox = ox;
+                    fi.oy = oy;
+                    fi.n_iter = n_iter;
+                    fi.entry_off = (int64_t)off;
+                    fi.img_off = p->ch[c].img_off;
+                    items.push_back(fi);
+                }
+        }
+        // heaviest items first so the tail of the launch is short
+        std::stable_sort(items.begin(), items.end(), [](const FusedItem &x, const FusedItem &y) {
+            return x.n_iter > y.n_iter;
+        });
+        g->n_items = (int)items.size();
+        g->host_items = items;
+        epic_status st;
+        if ((st = g->items.alloc(sizeof(FusedItem) * items.size()))) return st;
+        if ((st = g->entries.alloc(sizeof(uint4) * all.size()))) return st;
+        EPIC_HIP(hipMemcpyAsync(g->items.p, items.data(), sizeof(FusedItem) * items.size(),
+                                hipMemcpyHostToDevice, s));
+        EPIC_HIP(hipMemcpyAsync(g->entries.p, all.data(), sizeof(uint4) * all.size(),
+                                hipMemcpyHostToDevice, s));
+        EPIC_HIP(hipStreamSynchronize(s));
+    }
+    return EPIC_OK;
+}
+
+template <int M, int P>
+static epic_status launch_fused(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
+                                int A, int n_time, float *acc, hipStream_t s) {
+    constexpr int T = FCfg<M>::T, GSZ = M * FCfg<M>::ROW;
+    const size_t lds = sizeof(float2) * P * GSZ + sizeof(float4) * (size_t)A;
+    auto kern = k_fused<M, P>;
+    static int lds_max = -1;
+    if (lds_max < 0) {
+        int dev = 0, v = 0;
+        EPIC_HIP(hipGetDevice(&dev));
+        EPIC_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        EPIC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, v));
+        lds_max = v;
+    }
+    if ((int64_t)lds > lds_max)
+        return fail(EPIC_ERR_UNSUPPORTED, "fused path: LDS need " + std::to_string(lds) +
+                                              " B above the device limit");
+    hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(T), lds, s, g->items.as<FusedItem>(),
+                       g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc);
+    EPIC_HIP(hipGetLastError());
+    return EPIC_OK;
+}
+
+epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                             hipStream_t s) {
+    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    float *a = acc->d_acc.as<float>();
+    for (const FusedGroup *g : p->groups) {
+        epic_status st = EPIC_OK;
+        if (p->P == 2) {
+            if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, p->A, n_time, a, s);
+            if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, p->A, n_time, a, s);
+            if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, p->A, n_time, a, s);
+        } else {
+            if (g->M == 64) st = launch_fused<64, 1>(g, d_volt, vstride, p->A, n_time, a, s);
+            if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, p->A, n_time, a, s);
+            if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, p->A, n_time, a, s);
+        }
+        if (st) return st;
+    }
+    return autos_accumulate(p, acc, d_volt, n_time, s);
+}
+
+epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                             hipStream_t s) {
+    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    const int t_chunk = 64;
+    dim3 grid((p->A + 255) / 256, p->C, (n_time + t_chunk - 1) / t_chunk);
+    if (grid.z > 65535) return fail(EPIC_ERR_ARG, "n_time too large for one call");
+    if (p->P == 2)
+        hipLaunchKernelGGL(k_autos<2>, grid, dim3(256), 0, s, d_volt, vstride, p->A, n_time,
+                           t_chunk, acc->d_autos.as<int32_t>());
+    else
+        hipLaunchKernelGGL(k_autos<1>, grid, dim3(256), 0, s, d_volt, vstride, p->A, n_time,
+                           t_chunk, acc->d_autos.as<int32_t>());
+    EPIC_HIP(hipGetLastError());
+    return EPIC_OK;
+}
+
+}  // namespace epic

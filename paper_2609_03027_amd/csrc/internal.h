@@ -1,0 +1,168 @@
+// Internal declarations shared by the libepic translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/epic.h"
+
+namespace epic {
+
+constexpr double kCLight = 299792458.0;
+
+// Thread-local error text for epic_last_error().
+void set_error(const std::string &msg);
+epic_status fail(epic_status s, const std::string &msg);
+epic_status hip_fail(hipError_t e, const char *what);
+
+#define EPIC_HIP(call)                                              \
+    do {                                                            \
+        hipError_t _e = (call);                                     \
+        if (_e != hipSuccess) return ::epic::hip_fail(_e, #call);   \
+    } while (0)
+
+// Device buffer that frees itself.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    epic_status alloc(size_t n) {
+        release();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(EPIC_ERR_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+        }
+        bytes = n;
+        return EPIC_OK;
+    }
+    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// Per-channel geometry derived at plan time.
+struct Chan {
+    int N;            // FFT side
+    int M;            // sub-transform side used by the fused path
+    int R;            // N / M (classes per axis)
+    int64_t img_off;  // float offset of this channel's images
+    int64_t grid_off; // complex offset of this channel in one time sample of grids
+};
+
+// One work item of the fused path: a channel and one output class (ox, oy).
+// The class's grid is the aperture grid folded modulo M with the weights
+// multiplied by (-1)^(jx+jy) exp(+2 pi i (ox jx + oy jy) / N); its M x M
+// transform gives the pixels (R ky' + oy, R kx' + ox).
+struct FusedItem {
+    int32_t c;
+    int32_t N;
+    int32_t R;
+    int32_t ox, oy;
+    int32_t n_iter;      // gather iterations (entries per lane)
+    int64_t entry_off;   // first entry (uint4) of this item
+    int64_t img_off;     // float offset of channel c in the image set
+};
+
+// A group of fused items that share one sub-transform size M.
+struct FusedGroup {
+    int M = 0;
+    int n_items = 0;
+    DevBuf items;     // FusedItem[n_items]
+    DevBuf entries;   // uint4 gather entries
+    std::vector<FusedItem> host_items;
+};
+
+}  // namespace epic
+
+struct epic_plan_s {
+    int A = 0, P = 0, C = 0, K = 0;
+    int aperture_n = 0;
+    double cell_lambda = 0.5, sigma = 0.5;
+    int precision = 0;
+    uint32_t flags = 0;
+    int n_prod = 1;
+    int max_n = 0;
+    int64_t image_floats = 0;
+    int64_t grid_elems_per_t = 0;
+    std::vector<double> pos, freq;
+    std::vector<int> grid_n;
+    std::vector<epic::Chan> ch;
+    bool has_table = false;
+
+    // device tables
+    epic::DevBuf d_pos;      // double [A][2]
+    epic::DevBuf d_freq;     // double [C]
+    epic::DevBuf d_table;    // float  [C][A][K][K][2] (optional)
+    epic::DevBuf d_j0;       // int2   [C][A]
+    epic::DevBuf d_w;        // double2 [C][A][K][K]  kernel weights W (not conjugated)
+    epic::DevBuf d_chan;     // int4   [C] {N, M, R, 0}
+    epic::DevBuf d_img_off;  // int64  [C]
+    epic::DevBuf d_grid_off; // int64  [C]
+
+    // staged gather tables: per channel CSR from cell to taps
+    epic::DevBuf d_csr_off;  // int32 [sum_c N_c^2 + C]  (per channel N_c^2 + 1 offsets)
+    epic::DevBuf d_csr_base; // int64 [C] start of channel c in d_csr_off
+    epic::DevBuf d_csr_ant;  // int32 [total taps]
+    epic::DevBuf d_csr_w;    // float2 [total taps] conj(W)
+    epic::DevBuf d_twid;     // float2 per distinct N: exp(+2 pi i n / N), n < N
+    std::vector<int64_t> twid_off;  // indexed by N (-1 if unused)
+    // channels grouped by grid side (staged transform launches)
+    std::vector<int> sz_n, sz_count;
+    std::vector<int64_t> sz_off;
+    epic::DevBuf d_sz_chans; // int32 channel ids, grouped by size
+
+    // fused path
+    std::vector<epic::FusedGroup *> groups;
+
+    int64_t bytes_plan = 0;
+    ~epic_plan_s();
+};
+
+struct epic_acc_s {
+    epic_plan plan = nullptr;
+    epic::DevBuf d_acc;    // float [image_floats]
+    epic::DevBuf d_autos;  // int32 [C][A][n_prod]
+    epic::DevBuf d_h;      // double2 [C][NH][(2K-1)^2] read-out scratch (self-term sums)
+    int64_t count = 0;
+};
+
+namespace epic {
+
+// plan.hip
+epic_status plan_build(epic_plan p, hipStream_t s);
+
+// fused.hip
+epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
+                        hipStream_t s);
+epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                             hipStream_t s);
+epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                             hipStream_t s);
+
+// staged.hip
+epic_status staged_grid(epic_plan p, const uint8_t *d_volt, int n_time, void *d_grid,
+                        hipStream_t s);
+epic_status staged_image(epic_plan p, const void *d_grid, int n_time, void *d_sky,
+                         hipStream_t s);
+epic_status staged_accumulate(epic_plan p, epic_acc acc, const void *d_sky, int n_time,
+                              hipStream_t s);
+
+// readout.hip
+epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hipStream_t s);
+
+// Decode one 4+4-bit sample (real in the high nibble).
+__device__ __forceinline__ int dec_re(uint32_t b) { return ((int32_t)(b << 24)) >> 28; }
+__device__ __forceinline__ int dec_im(uint32_t b) { return ((int32_t)(b << 28)) >> 28; }
+
+}  // namespace epic

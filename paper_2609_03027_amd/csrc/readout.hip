@@ -1,0 +1,152 @@
+// Read-out of Eq. 2 (time average) with the per-element self terms removed.
+//
+// The image of element a's kernel footprint is
+//   B_a[k] = sum_j conj(W_a(j)) exp(+2 pi i (k - N/2).(j - N/2) / N),
+// and its power pattern expands over footprint displacements d = j - j':
+//   |B_a[k]|^2 = sum_d R_a[d] exp(+2 pi i (k - N/2).d / N),
+//   R_a[d]     = sum_j conj(W_a(j)) W_a(j - d),
+// with d in [-(K-1), K-1]^2.  The self term of product pq is
+// sum_a S_a^{pq} |B_a[k]|^2 = sum_d H^{pq}[d] exp(...), H^{pq}[d] =
+// sum_a S_a^{pq} R_a[d], so a (2K-1)^2-term sum per pixel evaluates it
+// exactly.  H and the per-pixel sum are formed in FP64 from the exact int32
+// self-term sums.
+#include "internal.h"
+
+namespace epic {
+
+// One thread per (channel, displacement).  H layout: double2 [C][NH][D*D]
+// with NH = 1 (XX) or 3 (XX, YY, XY).
+template <int P>
+__global__ void k_auto_h(const double2 *__restrict__ w, const int32_t *__restrict__ autos, int A,
+                         int C, int K, double2 *__restrict__ H) {
+    const int D = 2 * K - 1;
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (d >= D * D) return;
+    const int dx = d % D - (K - 1), dy = d / D - (K - 1);
+    constexpr int NPROD = P == 2 ? 4 : 1;
+    double2 hxx = make_double2(0, 0), hyy = make_double2(0, 0), hxy = make_double2(0, 0);
+    for (int a = 0; a < A; ++a) {
+        const double2 *wa = w + ((size_t)c * A + a) * K * K;
+        double rr = 0, ri = 0;
+        for (int ty = 0; ty < K; ++ty) {
+            const int uy = ty - dy;
+            if (uy < 0 || uy >= K) continue;
+            for (int tx = 0; tx < K; ++tx) {
+                const int ux = tx - dx;
+                if (ux < 0 || ux >= K) continue;
+                const double2 p = wa[ty * K + tx], q = wa[uy * K + ux];
+                // conj(p) * q
+                rr += p.x * q.x + p.y * q.y;
+                ri += p.x * q.y - p.y * q.x;
+            }
+        }
+        const int32_t *s = autos + ((size_t)c * A + a) * NPROD;
+        const double sxx = (double)s[0];
+        hxx.x += sxx * rr;
+        hxx.y += sxx * ri;
+        if (P == 2) {
+            const double syy = (double)s[1], sre = (double)s[2], sim = (double)s[3];
+            hyy.x += syy * rr;
+            hyy.y += syy * ri;
+            hxy.x += sre * rr - sim * ri;
+            hxy.y += sre * ri + sim * rr;
+        }
+    }
+    constexpr int NH = P == 2 ? 3 : 1;
+    double2 *h = H + (size_t)c * NH * D * D;
+    h[d] = hxx;
+    if (P == 2) {
+        h[D * D + d] = hyy;
+        h[2 * D * D + d] = hxy;
+    }
+}
+
+// One thread per (channel, pixel): img = (acc - remove * self) * scale.
+template <int P>
+__global__ void k_readout(const float *__restrict__ acc, const double2 *__restrict__ H,
+                          const int4 *__restrict__ chan, const int64_t *__restrict__ img_off, int K,
+                          int remove, float scale, float *__restrict__ img) {
+    const int c = blockIdx.y;
+    const int N = chan[c].x;
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= N * N) return;
+    const int ky = pix / N, kx = pix % N;
+    const int64_t plane = (int64_t)N * N;
+    constexpr int NPROD = P == 2 ? 4 : 1;
+    const float *a = acc + img_off[c] + pix;
+    float *o = img + img_off[c] + pix;
+    if (!remove) {
+#pragma unroll
+        for (int q = 0; q < NPROD; ++q) o[q * plane] = a[q * plane] * scale;
+        return;
+    }
+    const int D = 2 * K - 1;
+    constexpr int NH = P == 2 ? 3 : 1;
+    const double2 *h = H + (size_t)c * NH * D * D;
+    // exp(+2 pi i m d / N) for each axis, argument reduced exactly mod N
+    double2 px[5], py[5];
+    for (int i = 0; i < D; ++i) {
+        const int dd = i - (K - 1);
+        const long mx = (((long)(kx - N / 2) * dd) % N + N) % N;
+        const long my = (((long)(ky - N / 2) * dd) % N + N) % N;
+        double s, cs;
+        sincospi(2.0 * (double)mx / (double)N, &s, &cs);
+        px[i] = make_double2(cs, s);
+        sincospi(2.0 * (double)my / (double)N, &s, &cs);
+        py[i] = make_double2(cs, s);
+    }
+    double sxx = 0, syy = 0, sxr = 0, sxi = 0;
+    for (int iy = 0; iy < D; ++iy)
+        for (int ix = 0; ix < D; ++ix) {
+            const double er = px[ix].x * py[iy].x - px[ix].y * py[iy].y;
+            const double ei = px[ix].x * py[iy].y + px[ix].y * py[iy].x;
+            const int d = iy * D + ix;
+            const double2 hx = h[d];
+            sxx += hx.x * er - hx.y * ei;
+            if (P == 2) {
+                const double2 hy = h[D * D + d], hc = h[2 * D * D + d];
+                syy += hy.x * er - hy.y * ei;
+                sxr += hc.x * er - hc.y * ei;
+                sxi += hc.x * ei + hc.y * er;
+            }
+        }
+    o[0] = (float)(((double)a[0] - sxx) * scale);
+    if (P == 2) {
+        o[plane] = (float)(((double)a[plane] - syy) * scale);
+        o[2 * plane] = (float)(((double)a[2 * plane] - sxr) * scale);
+        o[3 * plane] = (float)(((double)a[3 * plane] - sxi) * scale);
+    }
+}
+
+epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hipStream_t s) {
+    const bool remove = (flags & EPIC_REMOVE_AUTOS) != 0;
+    const bool norm = (flags & EPIC_NORMALISE) != 0;
+    if (norm && acc->count <= 0) return fail(EPIC_ERR_ARG, "normalise requested with no samples");
+    const float scale = norm ? (float)(1.0 / (double)acc->count) : 1.0f;
+    const int D = 2 * p->K - 1;
+    DevBuf &H = acc->d_h;
+    if (remove) {
+        dim3 g((D * D + 63) / 64, p->C);
+        if (p->P == 2)
+            hipLaunchKernelGGL(k_auto_h<2>, g, dim3(64), 0, s, p->d_w.as<double2>(),
+                               acc->d_autos.as<int32_t>(), p->A, p->C, p->K, H.as<double2>());
+        else
+            hipLaunchKernelGGL(k_auto_h<1>, g, dim3(64), 0, s, p->d_w.as<double2>(),
+                               acc->d_autos.as<int32_t>(), p->A, p->C, p->K, H.as<double2>());
+        EPIC_HIP(hipGetLastError());
+    }
+    dim3 g((p->max_n * p->max_n + 255) / 256, p->C);
+    if (p->P == 2)
+        hipLaunchKernelGGL(k_readout<2>, g, dim3(256), 0, s, acc->d_acc.as<float>(),
+                           H.as<double2>(), p->d_chan.as<int4>(), p->d_img_off.as<int64_t>(), p->K,
+                           remove ? 1 : 0, scale, d_img);
+    else
+        hipLaunchKernelGGL(k_readout<1>, g, dim3(256), 0, s, acc->d_acc.as<float>(),
+                           H.as<double2>(), p->d_chan.as<int4>(), p->d_img_off.as<int64_t>(), p->K,
+                           remove ? 1 : 0, scale, d_img);
+    EPIC_HIP(hipGetLastError());
+    return EPIC_OK;
+}
+
+}  // namespace epic

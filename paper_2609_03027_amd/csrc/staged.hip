@@ -1,0 +1,276 @@
+// Staged FP32 path: gridding, transform and accumulation as separate
+// launches with the grids and sky images in HBM.  It backs epic_grid and
+// epic_image (Eq. 1 inner and outer sums) and epic_accumulate on given sky
+// images (Eq. 2), and is the plain FP32 gridding + FFT form that the fused
+// path is compared against.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace epic {
+
+// Gather gridding: one thread per output cell, summing conj(W) E over the
+// cell's taps from the plan's CSR table.  Every cell is written.
+// Grid: (cell blocks, channels, n_time * P).
+__global__ void k_grid_csr(const uint8_t *__restrict__ volt, int64_t volt_t_stride,
+                           const int4 *__restrict__ chan, const int64_t *__restrict__ grid_off,
+                           const int64_t *__restrict__ csr_base, const int32_t *__restrict__ csr_off,
+                           const int32_t *__restrict__ csr_ant, const float2 *__restrict__ csr_w,
+                           int A, int P, int64_t grid_t_stride, float2 *__restrict__ grid) {
+    const int c = blockIdx.y;
+    const int N = chan[c].x;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= N * N) return;
+    const int t = blockIdx.z / P, p = blockIdx.z % P;
+    const int32_t *off = csr_off + csr_base[c];
+    const int e0 = off[cell], e1 = off[cell + 1];
+    const uint8_t *v = volt + (int64_t)t * volt_t_stride + ((int64_t)c * P + p) * A;
+    float2 s = make_float2(0.f, 0.f);
+    for (int e = e0; e < e1; ++e) {
+        const uint32_t b = v[csr_ant[e]];
+        const float er = (float)dec_re(b), ei = (float)dec_im(b);
+        const float2 w = csr_w[e];
+        s.x += w.x * er - w.y * ei;
+        s.y += w.x * ei + w.y * er;
+    }
+    grid[(int64_t)t * grid_t_stride + grid_off[c] + (int64_t)p * N * N + cell] = s;
+}
+
+// --------------------------------------------------------------- FFT
+__device__ __forceinline__ float2 s_cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 s_csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 s_cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+struct Radices {
+    int n;
+    int r[8];
+};
+
+// Batched 1D transforms along one axis of N x N images, Stockham passes in
+// LDS with the positive exponent.  Inputs are multiplied by (-1)^j and
+// outputs by (-1)^k, which turns the plain transform into the centred one
+// of Eq. 1 (the two per-axis constants exp(i pi N/2) multiply to one over
+// the two axes).  Grid: (line blocks, images); images are (t, channel of
+// this size, p) in that order.
+__global__ __launch_bounds__(256) void k_fft_lines(const float2 *in, float2 *out,
+                                                   const int32_t *__restrict__ chans, int n_chans,
+                                                   const int64_t *__restrict__ grid_off, int P,
+                                                   int64_t grid_t_stride, int N, int LPB,
+                                                   Radices rad, const float2 *__restrict__ tw,
+                                                   int along_x) {
+    extern __shared__ float2 sbuf[];
+    float2 *b0 = sbuf, *b1 = sbuf + LPB * N;
+    const int img = blockIdx.y;
+    const int p = img % P;
+    const int ci = (img / P) % n_chans;
+    const int t = img / (P * n_chans);
+    const int c = chans[ci];
+    const int64_t base = (int64_t)t * grid_t_stride + grid_off[c] + (int64_t)p * N * N;
+    const int l0 = blockIdx.x * LPB;
+    const int tot = LPB * N;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        int l, j;
+        int64_t addr;
+        if (along_x) {
+            l = i / N;
+            j = i % N;
+            addr = base + (int64_t)(l0 + l) * N + j;
+        } else {
+            j = i / LPB;
+            l = i % LPB;
+            addr = base + (int64_t)j * N + l0 + l;
+        }
+        float2 v = in[addr];
+        if (j & 1) v = make_float2(-v.x, -v.y);
+        b0[l * N + j] = v;
+    }
+    __syncthreads();
+    int Ns = 1;
+    float2 *src = b0, *dst = b1;
+    for (int ps = 0; ps < rad.n; ++ps) {
+        const int r = rad.r[ps];
+        const int nb = N / r;
+        const int tstep = N / (Ns * r);
+        for (int u = threadIdx.x; u < LPB * nb; u += blockDim.x) {
+            const int l = u / nb, j = u % nb;
+            const int k = j % Ns;
+            const float2 *s_in = src + l * N;
+            float2 *s_out = dst + l * N;
+            float2 v[4];
+            for (int q = 0; q < r; ++q) {
+                float2 x = s_in[j + q * nb];
+                if (q) x = s_cmul(x, tw[(q * k * tstep) % N]);
+                v[q] = x;
+            }
+            if (r == 2) {
+                const float2 a = v[0], b = v[1];
+                v[0] = s_cadd(a, b);
+                v[1] = s_csub(a, b);
+            } else if (r == 3) {
+                const float h = 0.86602540378443864676f;
+                const float2 sm = s_cadd(v[1], v[2]), df = s_csub(v[1], v[2]);
+                const float2 a = v[0];
+                v[0] = s_cadd(a, sm);
+                const float2 tt = make_float2(a.x - 0.5f * sm.x, a.y - 0.5f * sm.y);
+                const float2 uu = make_float2(-h * df.y, h * df.x);
+                v[1] = s_cadd(tt, uu);
+                v[2] = s_csub(tt, uu);
+            } else {
+                const float2 t0 = s_cadd(v[0], v[2]), t1 = s_csub(v[0], v[2]);
+                const float2 t2 = s_cadd(v[1], v[3]);
+                const float2 d = s_csub(v[1], v[3]);
+                const float2 t3 = make_float2(-d.y, d.x);
+                v[0] = s_cadd(t0, t2);
+                v[2] = s_csub(t0, t2);
+                v[1] = s_cadd(t1, t3);
+                v[3] = s_csub(t1, t3);
+            }
+            const int idxD = (j / Ns) * Ns * r + k;
+            for (int q = 0; q < r; ++q) s_out[idxD + q * Ns] = v[q];
+        }
+        Ns *= r;
+        __syncthreads();
+        float2 *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        int l, k;
+        int64_t addr;
+        if (along_x) {
+            l = i / N;
+            k = i % N;
+            addr = base + (int64_t)(l0 + l) * N + k;
+        } else {
+            k = i / LPB;
+            l = i % LPB;
+            addr = base + (int64_t)k * N + l0 + l;
+        }
+        float2 v = src[l * N + k];
+        if (k & 1) v = make_float2(-v.x, -v.y);
+        out[addr] = v;
+    }
+}
+
+// Eq. 2 from sky images: one thread per (channel, pixel), time in order.
+template <int P>
+__global__ void k_accum_sky(const float2 *__restrict__ sky, const int4 *__restrict__ chan,
+                            const int64_t *__restrict__ grid_off, const int64_t *__restrict__ img_off,
+                            int64_t grid_t_stride, int n_time, float *__restrict__ acc) {
+    const int c = blockIdx.y;
+    const int N = chan[c].x;
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= N * N) return;
+    const int64_t plane = (int64_t)N * N;
+    const float2 *s = sky + grid_off[c] + pix;
+    float xx = 0.f, yy = 0.f, re = 0.f, im = 0.f;
+    for (int t = 0; t < n_time; ++t) {
+        const float2 ex = s[(int64_t)t * grid_t_stride];
+        xx += ex.x * ex.x + ex.y * ex.y;
+        if (P == 2) {
+            const float2 ey = s[(int64_t)t * grid_t_stride + plane];
+            yy += ey.x * ey.x + ey.y * ey.y;
+            re += ex.x * ey.x + ex.y * ey.y;
+            im += ex.y * ey.x - ex.x * ey.y;
+        }
+    }
+    float *a = acc + img_off[c] + pix;
+    a[0] += xx;
+    if (P == 2) {
+        a[plane] += yy;
+        a[2 * plane] += re;
+        a[3 * plane] += im;
+    }
+}
+
+static Radices radices_of(int N) {
+    Radices r{};
+    int n = N;
+    while (n % 4 == 0) {
+        r.r[r.n++] = 4;
+        n /= 4;
+    }
+    while (n % 2 == 0) {
+        r.r[r.n++] = 2;
+        n /= 2;
+    }
+    while (n % 3 == 0) {
+        r.r[r.n++] = 3;
+        n /= 3;
+    }
+    if (n != 1) r.n = -1;
+    return r;
+}
+
+epic_status staged_grid(epic_plan p, const uint8_t *d_volt, int n_time, void *d_grid,
+                        hipStream_t s) {
+    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    const int max_cells = p->max_n * p->max_n;
+    const int tp_max = 65535 / p->P;
+    for (int t0 = 0; t0 < n_time; t0 += tp_max) {
+        const int nt = std::min(tp_max, n_time - t0);
+        dim3 grid((max_cells + 255) / 256, p->C, nt * p->P);
+        hipLaunchKernelGGL(k_grid_csr, grid, dim3(256), 0, s, d_volt + (int64_t)t0 * vstride,
+                           vstride, p->d_chan.as<int4>(), p->d_grid_off.as<int64_t>(),
+                           p->d_csr_base.as<int64_t>(), p->d_csr_off.as<int32_t>(),
+                           p->d_csr_ant.as<int32_t>(), p->d_csr_w.as<float2>(), p->A, p->P,
+                           p->grid_elems_per_t,
+                           static_cast<float2 *>(d_grid) + (int64_t)t0 * p->grid_elems_per_t);
+        EPIC_HIP(hipGetLastError());
+    }
+    return EPIC_OK;
+}
+
+epic_status staged_image(epic_plan p, const void *d_grid, int n_time, void *d_sky, hipStream_t s) {
+    for (size_t gi = 0; gi < p->sz_n.size(); ++gi) {
+        const int N = p->sz_n[gi];
+        const int n_chans = p->sz_count[gi];
+        Radices rad = radices_of(N);
+        if (rad.n < 0) return fail(EPIC_ERR_UNSUPPORTED, "grid side has a prime factor above 3");
+        // lines per block: the largest divisor of N keeping a block <= 2048 elements
+        int LPB = 1;
+        for (int d = 1; d <= N && d * N <= 2048; ++d)
+            if (N % d == 0) LPB = d;
+        const int32_t *chans = p->d_sz_chans.as<int32_t>() + p->sz_off[gi];
+        const int64_t imgs_per_t = (int64_t)n_chans * p->P;
+        const int t_max = (int)std::max<int64_t>(1, 65535 / imgs_per_t);
+        const size_t lds = sizeof(float2) * 2 * LPB * N;
+        const float2 *tw = p->d_twid.as<float2>() + p->twid_off[N];
+        for (int t0 = 0; t0 < n_time; t0 += t_max) {
+            const int nt = std::min(t_max, n_time - t0);
+            const float2 *gin = static_cast<const float2 *>(d_grid) + (int64_t)t0 * p->grid_elems_per_t;
+            float2 *gout = static_cast<float2 *>(d_sky) + (int64_t)t0 * p->grid_elems_per_t;
+            dim3 grid(N / LPB, (unsigned)(imgs_per_t * nt));
+            hipLaunchKernelGGL(k_fft_lines, grid, dim3(256), lds, s, gin, gout, chans, n_chans,
+                               p->d_grid_off.as<int64_t>(), p->P, p->grid_elems_per_t, N, LPB, rad,
+                               tw, 1);
+            EPIC_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_fft_lines, grid, dim3(256), lds, s, gout, gout, chans, n_chans,
+                               p->d_grid_off.as<int64_t>(), p->P, p->grid_elems_per_t, N, LPB, rad,
+                               tw, 0);
+            EPIC_HIP(hipGetLastError());
+        }
+    }
+    return EPIC_OK;
+}
+
+epic_status staged_accumulate(epic_plan p, epic_acc acc, const void *d_sky, int n_time,
+                              hipStream_t s) {
+    dim3 grid((p->max_n * p->max_n + 255) / 256, p->C);
+    if (p->P == 2)
+        hipLaunchKernelGGL(k_accum_sky<2>, grid, dim3(256), 0, s, static_cast<const float2 *>(d_sky),
+                           p->d_chan.as<int4>(), p->d_grid_off.as<int64_t>(),
+                           p->d_img_off.as<int64_t>(), p->grid_elems_per_t, n_time,
+                           acc->d_acc.as<float>());
+    else
+        hipLaunchKernelGGL(k_accum_sky<1>, grid, dim3(256), 0, s, static_cast<const float2 *>(d_sky),
+                           p->d_chan.as<int4>(), p->d_grid_off.as<int64_t>(),
+                           p->d_img_off.as<int64_t>(), p->grid_elems_per_t, n_time,
+                           acc->d_acc.as<float>());
+    EPIC_HIP(hipGetLastError());
+    return EPIC_OK;
+}
+
+}  // namespace epic

@@ -1,0 +1,98 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol include/epic.h declares, and rejects bad arguments on the host."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2609_03027_amd", "libepic.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libepic.so not built")
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "epic.h")).read()
+    return sorted(set(re.findall(r"\b(epic_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(E.EXPORTS) == names
+
+
+def test_status_strings_and_version():
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    assert lib.epic_status_str(0) == b"ok"
+    assert lib.epic_status_str(3) == b"grid geometry"
+    assert b"gfx950" in lib.epic_version()
+
+
+def _desc(**over):
+    from paper_2609_03027_amd._lib import PlanDesc
+    pos = np.zeros((4, 2))
+    freq = np.array([60e6])
+    gn = np.array([32], dtype=np.int32)
+    d = PlanDesc()
+    d.n_ant, d.n_pol, d.n_chan = 4, 1, 1
+    d.ant_pos_m = pos.ctypes.data_as(C.POINTER(C.c_double))
+    d.chan_freq_hz = freq.ctypes.data_as(C.POINTER(C.c_double))
+    d.grid_n = gn.ctypes.data_as(C.POINTER(C.c_int32))
+    d.kernel_k = 3
+    for k, v in over.items():
+        setattr(d, k, v)
+    return d, (pos, freq, gn)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n_ant", 0, 2), ("n_pol", 3, 2), ("n_chan", 0, 2), ("kernel_k", 4, 2),
+    ("kernel_k", 0, 2), ("cell_lambda", -1.0, 2), ("kernel_sigma_cells", -2.0, 2),
+    ("precision", 9, 2), ("aperture_n", 33, 2),
+])
+def test_plan_create_rejects_bad_descriptors(field, value, status):
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    d, keep = _desc(**{field: value})
+    h = C.c_void_p()
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == status
+    assert h.value is None
+    assert len(lib.epic_last_error()) > 0
+
+
+def test_plan_create_rejects_null_and_odd_grid():
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    h = C.c_void_p()
+    assert lib.epic_plan_create(None, None, C.byref(h)) == 1
+    d, keep = _desc()
+    assert lib.epic_plan_create(C.byref(d), None, None) == 1
+    d, keep = _desc()
+    d.ant_pos_m = None
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 1
+    gn = np.array([31], dtype=np.int32)
+    d, keep = _desc(grid_n=gn.ctypes.data_as(C.POINTER(C.c_int32)))
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 3
+    bad = np.array([np.nan, 0, 0, 0, 0, 0, 0, 0])
+    d, keep = _desc(ant_pos_m=bad.ctypes.data_as(C.POINTER(C.c_double)))
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 2
+
+
+def test_data_calls_reject_null_handles():
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    assert lib.epic_grid(None, None, 1, None, None) == 1
+    assert lib.epic_image(None, None, 1, None, None) == 1
+    assert lib.epic_accumulate(None, None, None, None, 1, None) == 1
+    assert lib.epic_readout(None, None, None, 0, None) == 1
+    assert lib.epic_acc_create(None, None) == 1
+    assert lib.epic_acc_reset(None, None) == 1
+    assert lib.epic_plan_destroy(None) == 1
+    assert lib.epic_acc_destroy(None) == 1
