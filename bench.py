@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Throughput of the EPIC imaging path on one MI355X.
+
+Workload: the LWA-station-like observation -- 256 dual-polarisation dipoles
+in a 100 m disc, 128 channels of 25 kHz between 40 and 80 MHz, 1000 samples
+per integration of 4+4-bit complex voltages (3 point sources + noise), a
+64 x 64 aperture zero-padded to 128 x 128, 3 x 3 Gaussian kernel, XX/YY/XY
+accumulated in FP32.
+
+One step = one integration through the whole path: reset the accumulators,
+the fused grid -> transform -> Eq. 2 accumulate over all 1000 x 128 (t, c)
+pairs in one launch, and the read-out with self-term removal and
+normalisation.  The voltages are resident in HBM before timing starts.
+
+Prints one JSON line.  Diagnostics go to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(wl):
+    """Flops per integration (the roofline's numerator).
+
+    Transform: 5 n log2 n per image with n = N^2 (the FFT-equivalent
+    convention); products: 16 per pixel per (t, c) (|Ex|^2, |Ey|^2, Ex conj(Ey)
+    and their sums); gridding: 8 per kernel tap per feed (complex weight times
+    complex voltage, plus the add).
+    """
+    T, P, A, K = wl.n_time, wl.n_pol, wl.n_ant, wl.kernel_k
+    fft = prod = 0.0
+    for n in wl.grid_n:
+        n2 = float(n) * float(n)
+        fft += T * P * 5.0 * n2 * math.log2(n2)
+        prod += T * n2 * (16.0 if P == 2 else 4.0)
+    grid = T * wl.n_chan * P * A * K * K * 8.0
+    return fft + prod + grid, dict(fft=fft, products=prod, gridding=grid)
+
+
+def hbm_bytes(wl, n_prod):
+    """Algorithmic HBM bytes per step: voltages in, accumulators read and
+    written once, images written once by the read-out."""
+    img = sum(n_prod * int(n) * int(n) for n in wl.grid_n) * 4
+    return wl.samples_per_block() + 3 * img
+
+
+def traffic_from_profile(kernel_src):
+    """HBM bytes per dispatch from the committed counter summary, or None if
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "fused_lwa_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != digest:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_dispatch_scaled"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(wl, pos, n_chan=2, n_time=250):
+    """The FP64 oracle on a bounded slice of the same workload."""
+    import numpy as np
+
+    import oracle as O
+    import synth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    chans = list(range(0, wl.n_chan, max(1, wl.n_chan // n_chan)))[:n_chan]
+    v = synth.voltages(wl.with_time(n_time), pos, chans=chans)
+    t0 = time.perf_counter()
+    for i, c in enumerate(chans):
+        r = O.channel_reference(v[:, i], pos, wl.chan_freq_hz[c], int(wl.grid_n[c]),
+                                cell_lambda=wl.cell_lambda, k=wl.kernel_k,
+                                sigma=wl.kernel_sigma_cells, aperture_n=wl.aperture_n)
+        O.readout(r["acc"], r["auto"], r["count"])
+    dt = time.perf_counter() - t0
+    samples = n_chan * n_time * wl.n_pol * wl.n_ant
+    return {"value": samples / dt, "unit": "samples/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{n_chan} channels x {n_time} samples x {wl.n_pol} pol x "
+                      f"{wl.n_ant} ant of the same workload ({dt:.1f} s, FP64 NumPy)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--staged", type=int, default=100,
+                    help="samples of the staged FP32 path to time (0 = skip)")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="MiB for a plain device copy (counter calibration runs)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: channels shard across GPUs with no exchange, "
+              "and this build runs on single-GPU boxes only; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2609_03027_amd as E
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    wl = synth.workload("lwa")
+    pos = synth.antenna_layout(wl)
+    t0 = time.perf_counter()
+    volt_np = synth.voltages(wl, pos)
+    log(f"generated {volt_np.nbytes / 1e6:.1f} MB of voltages in {time.perf_counter() - t0:.1f} s")
+    volt = torch.from_numpy(volt_np).to(dev)
+
+    t0 = time.perf_counter()
+    plan = E.Plan.from_workload(wl, pos)
+    log(f"plan: {time.perf_counter() - t0:.2f} s, {plan.info['bytes_plan'] / 1e6:.1f} MB")
+    acc = E.Accumulator(plan)
+    img = torch.empty(plan.info["image_floats"], dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        acc.reset()
+        if ev is not None:
+            ev[0].record(stream)
+        E.accumulate(plan, acc, volt=volt)
+        if ev is not None:
+            ev[1].record(stream)
+        E.readout(plan, acc, img, E.REMOVE_AUTOS | E.NORMALISE)
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup step {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    step_evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(args.steps):
+        step_evs[i][0].record(stream)
+        step(evs[i])
+        step_evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
+    step_ms = [a.elapsed_time(b) for a, b in step_evs]
+    ms_per_step = wall * 1e3 / args.steps
+    log(f"timed {args.steps} steps: wall {ms_per_step:.3f} ms/step, "
+        f"fused kernel {np.mean(kern_ms):.3f} ms avg")
+
+    samples = wl.samples_per_block()
+    flops, parts = algorithmic_flops(wl)
+    kern_s = float(np.mean(kern_ms)) / 1e3
+    achieved = flops / kern_s / 1e12
+    src = os.path.join(ROOT, "paper_2609_03027_amd", "csrc", "fused.hip")
+    traffic = traffic_from_profile(src)
+    bytes_step = hbm_bytes(wl, plan.n_prod)
+    n_images = wl.n_time * wl.n_chan * wl.n_pol
+
+    out = {
+        "metric": "voltage samples imaged/sec",
+        "value": samples / (ms_per_step / 1e3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "lwa-station: 256 dual-pol dipoles in a 100 m disc, 128 x 25 kHz "
+                        "channels over 40-80 MHz, 1000 samples/integration, 4+4-bit "
+                        "voltages, 64x64 aperture zero-padded to 128x128, 3x3 Gaussian "
+                        "kernel, XX/YY/XY in FP32, fused path",
+            "n_ant": wl.n_ant, "n_pol": wl.n_pol, "n_chan": wl.n_chan,
+            "n_time": wl.n_time, "grid_n": 128, "aperture_n": 64, "parallelism": "1 GPU",
+        },
+        "images_per_s": n_images / (ms_per_step / 1e3),
+        "hbm": {"algorithmic_bytes_per_step": bytes_step,
+                "gbs": bytes_step / (ms_per_step / 1e3) / 1e9,
+                "frac": bytes_step / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_fused<64,2>",
+            "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": traffic,
+            "flops_per_launch": flops,
+            "kernel_ms": float(np.mean(kern_ms)),
+        },
+        "step_latency_ms": {"p50": float(np.percentile(step_ms, 50)),
+                            "p99": float(np.percentile(step_ms, 99))},
+    }
+
+    if args.staged > 0:
+        Ts = args.staged
+        g = torch.empty((Ts, plan.info["grid_elems_per_t"]), dtype=torch.complex64, device=dev)
+        s = torch.empty_like(g)
+        acc2 = E.Accumulator(plan)
+        vs = volt[:Ts]
+
+        def staged():
+            E.grid(plan, vs, Ts, g)
+            E.image(plan, g, Ts, s)
+            E.accumulate(plan, acc2, volt=vs, sky=s, n_time=Ts)
+        staged()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(3):
+            staged()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 3
+        sv = Ts * wl.n_chan * wl.n_pol * wl.n_ant / (ms / 1e3)
+        out["staged_fp32"] = {"value": sv, "unit": "samples/s", "samples": Ts,
+                              "ms": ms, "speedup_of_fused": out["value"] / sv}
+        log(f"staged FP32 path: {ms:.2f} ms for {Ts} samples -> {sv:.3e} samples/s")
+        del g, s
+
+    if args.copy_calib > 0:
+        n = args.copy_calib * (1 << 20) // 4
+        src_t = torch.ones(n, dtype=torch.float32, device=dev)
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calib} MiB read + written")
+
+    if not args.no_cpu:
+        log("timing the CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(wl, pos)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.3e} samples/s")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

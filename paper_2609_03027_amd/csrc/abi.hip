@@ -67,7 +67,7 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
         return fail(EPIC_ERR_NULL, "positions, frequencies and grid sizes are required");
     if (d->n_ant < 1 || d->n_ant > 65535) return fail(EPIC_ERR_ARG, "n_ant must be in [1, 65535]");
     if (d->n_pol != 1 && d->n_pol != 2) return fail(EPIC_ERR_ARG, "n_pol must be 1 or 2");
-    if (d->n_chan < 1) return fail(EPIC_ERR_ARG, "n_chan must be >= 1");
+    if (d->n_chan < 1 || d->n_chan > 65535) return fail(EPIC_ERR_ARG, "n_chan must be in [1, 65535]");
     const int K = d->kernel_k;
     if (K < 1 || K > 3) return fail(EPIC_ERR_ARG, "kernel_k must be 1, 2 or 3");
     const double cl = d->cell_lambda == 0.0 ? 0.5 : d->cell_lambda;

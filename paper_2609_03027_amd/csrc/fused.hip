@@ -132,12 +132,16 @@ template <int M> __device__ __forceinline__ int unscramble(int n) {
 // One workgroup per item (channel c, class o), looping over all n_time
 // samples.  Gather entry (uint4): x = element | last-tap-of-cell << 31,
 // y = LDS index of the folded cell, z/w = folded complex weight (float bits).
-template <int M, int P>
-__global__ __launch_bounds__(FCfg<M>::T) void k_fused(const FusedItem *__restrict__ items,
+// When `autos` is given (A <= 4 T), the class-(0,0) item of each channel also
+// adds the per-element self-term sums S_a^{pq}, exact in int32.  AR is the
+// number of element rounds whose self terms a thread keeps (A <= AR * T).
+template <int M, int P, int AR>
+__global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(const FusedItem *__restrict__ items,
                                                       const uint4 *__restrict__ entries,
                                                       const uint8_t *__restrict__ volt,
                                                       int64_t volt_t_stride, int A, int n_time,
-                                                      float *__restrict__ acc) {
+                                                      float *__restrict__ acc,
+                                                      int32_t *__restrict__ autos) {
     constexpr int T = FCfg<M>::T, RA = FCfg<M>::RA, ROW = FCfg<M>::ROW;
     constexpr int NPIX = M * M / T;
     constexpr int NPROD = P == 2 ? 4 : 1;
@@ -148,16 +152,24 @@ __global__ __launch_bounds__(FCfg<M>::T) void k_fused(const FusedItem *__restric
     float4 *stage = reinterpret_cast<float4 *>(gx + P * GSZ);
 
     const FusedItem it = items[blockIdx.x];
+    if (it.c < 0) return;
     const int tid = threadIdx.x;
 
     float2 tw[RA];
     {
-        const int j = tid / M;
+        // With M = 64 the span index j = tid / 64 is the wave index, so the
+        // twiddles are wave-uniform and can live in scalar registers.
+        const int j = M == 64 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M;
 #pragma unroll
         for (int p = 0; p < RA; ++p) {
             double sn, cs;
             sincospi(2.0 * (double)(p * j) / (double)M, &sn, &cs);
-            tw[p] = make_float2((float)cs, (float)sn);
+            float c = (float)cs, s = (float)sn;
+            if (M == 64) {
+                c = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c)));
+                s = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s)));
+            }
+            tw[p] = make_float2(c, s);
         }
     }
     for (int i = tid; i < P * GSZ; i += T) gx[i] = make_float2(0.f, 0.f);
@@ -171,10 +183,34 @@ __global__ __launch_bounds__(FCfg<M>::T) void k_fused(const FusedItem *__restric
     const uint8_t *vbase = volt + (int64_t)it.c * P * A;
     const uint4 *ent = entries + it.entry_off + tid;
     const int n_iter = it.n_iter;
+    const bool own_autos = autos != nullptr && it.ox == 0 && it.oy == 0;
+    int sa[AR][NPROD];
+#pragma unroll
+    for (int k = 0; k < AR; ++k)
+#pragma unroll
+        for (int q = 0; q < NPROD; ++q) sa[k][q] = 0;
 
     for (int t = 0; t < n_time; ++t) {
         const uint8_t *vt = vbase + (int64_t)t * volt_t_stride;
-        for (int a = tid; a < A; a += T) {
+#pragma unroll
+        for (int k = 0; k < AR; ++k) {
+            const int a = tid + k * T;
+            if (a < A) {
+                const uint32_t bx = vt[a];
+                const uint32_t by = P == 2 ? (uint32_t)vt[A + a] : 0u;
+                const int xr = dec_re(bx), xi = dec_im(bx), yr = dec_re(by), yi = dec_im(by);
+                stage[a] = make_float4((float)xr, (float)xi, (float)yr, (float)yi);
+                if (own_autos) {
+                    sa[k][0] += xr * xr + xi * xi;
+                    if (P == 2) {
+                        sa[k][1] += yr * yr + yi * yi;
+                        sa[k][2] += xr * yr + xi * yi;
+                        sa[k][3] += xi * yr - xr * yi;
+                    }
+                }
+            }
+        }
+        for (int a = tid + AR * T; a < A; a += T) {
             const uint32_t bx = vt[a];
             const uint32_t by = P == 2 ? (uint32_t)vt[A + a] : 0u;
             stage[a] = make_float4((float)dec_re(bx), (float)dec_im(bx), (float)dec_re(by),
@@ -241,6 +277,17 @@ __global__ __launch_bounds__(FCfg<M>::T) void k_fused(const FusedItem *__restric
         float *dst = acc + it.img_off + (int64_t)ky * N + kx;
 #pragma unroll
         for (int q = 0; q < NPROD; ++q) dst[q * plane] += av[k][q];
+    }
+    if (own_autos) {
+#pragma unroll
+        for (int k = 0; k < AR; ++k) {
+            const int a = tid + k * T;
+            if (a < A) {
+                int32_t *d = autos + ((int64_t)it.c * A + a) * NPROD;
+#pragma unroll
+                for (int q = 0; q < NPROD; ++q) atomicAdd(d + q, sa[k][q]);
+            }
+        }
     }
 }
 
@@ -394,10 +441,40 @@ epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vect
                     items.push_back(fi);
                 }
         }
-        // heaviest items first so the tail of the launch is short
-        std::stable_sort(items.begin(), items.end(), [](const FusedItem &x, const FusedItem &y) {
-            return x.n_iter > y.n_iter;
-        });
+        // XCD-aware order.  Workgroups are dealt to the 8 XCDs round-robin by
+        // id, so items placed at ids x, x+8, x+16, ... share one XCD and its L2.
+        // Channels go to XCD bins longest-first (a channel's items all read the
+        // same voltages); each bin lists its items heaviest first; the bins are
+        // then interleaved, padded with empty items (c = -1).
+        {
+            constexpr int NX = 8;
+            std::vector<int> chan_order;
+            std::vector<int64_t> chan_cost(p->C, 0);
+            for (const FusedItem &fi : items) chan_cost[fi.c] += 64 + fi.n_iter;
+            for (int c : chans) chan_order.push_back(c);
+            std::stable_sort(chan_order.begin(), chan_order.end(),
+                             [&](int x, int y) { return chan_cost[x] > chan_cost[y]; });
+            std::vector<int64_t> bin_cost(NX, 0);
+            std::vector<int> chan_bin(p->C, 0);
+            for (int c : chan_order) {
+                const int b = (int)(std::min_element(bin_cost.begin(), bin_cost.end()) -
+                                    bin_cost.begin());
+                chan_bin[c] = b;
+                bin_cost[b] += chan_cost[c];
+            }
+            std::vector<std::vector<FusedItem>> bins(NX);
+            for (int c : chan_order)
+                for (const FusedItem &fi : items)
+                    if (fi.c == c) bins[chan_bin[c]].push_back(fi);
+            size_t depth = 0;
+            for (auto &b : bins) depth = std::max(depth, b.size());
+            FusedItem empty{};
+            empty.c = -1;
+            std::vector<FusedItem> laid(depth * NX, empty);
+            for (int x = 0; x < NX; ++x)
+                for (size_t i = 0; i < bins[x].size(); ++i) laid[i * NX + x] = bins[x][i];
+            items.swap(laid);
+        }
         g->n_items = (int)items.size();
         g->host_items = items;
         epic_status st;
@@ -412,12 +489,12 @@ epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vect
     return EPIC_OK;
 }
 
-template <int M, int P>
-static epic_status launch_fused(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                int A, int n_time, float *acc, hipStream_t s) {
+template <int M, int P, int AR>
+static epic_status launch_fused_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
+                                   int A, int n_time, float *acc, int32_t *autos, hipStream_t s) {
     constexpr int T = FCfg<M>::T, GSZ = M * FCfg<M>::ROW;
     const size_t lds = sizeof(float2) * P * GSZ + sizeof(float4) * (size_t)A;
-    auto kern = k_fused<M, P>;
+    auto kern = k_fused<M, P, AR>;
     static int lds_max = -1;
     if (lds_max < 0) {
         int dev = 0, v = 0;
@@ -431,29 +508,47 @@ static epic_status launch_fused(const FusedGroup *g, const uint8_t *d_volt, int6
         return fail(EPIC_ERR_UNSUPPORTED, "fused path: LDS need " + std::to_string(lds) +
                                               " B above the device limit");
     hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(T), lds, s, g->items.as<FusedItem>(),
-                       g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc);
+                       g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos);
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
+}
+
+// Element rounds per thread: 1, 2 or 4; above 4 T the self terms come from a
+// separate pass (autos == nullptr).
+template <int M, int P>
+static epic_status launch_fused(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
+                                int A, int n_time, float *acc, int32_t *autos, hipStream_t s) {
+    constexpr int T = FCfg<M>::T;
+    if (A <= T) return launch_fused_ar<M, P, 1>(g, d_volt, vstride, A, n_time, acc, autos, s);
+    if (A <= 2 * T) return launch_fused_ar<M, P, 2>(g, d_volt, vstride, A, n_time, acc, autos, s);
+    return launch_fused_ar<M, P, 4>(g, d_volt, vstride, A, n_time, acc, autos, s);
 }
 
 epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                              hipStream_t s) {
     const int64_t vstride = (int64_t)p->C * p->P * p->A;
     float *a = acc->d_acc.as<float>();
+    // The fused kernel adds the self-term sums when every group's threads
+    // cover the elements in at most four rounds; otherwise a separate pass.
+    bool in_kernel = true;
+    for (const FusedGroup *g : p->groups)
+        if (p->A > 4 * threads_of(g->M)) in_kernel = false;
+    int32_t *au = in_kernel ? acc->d_autos.as<int32_t>() : nullptr;
     for (const FusedGroup *g : p->groups) {
         epic_status st = EPIC_OK;
+        const int A = p->A;
         if (p->P == 2) {
-            if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, p->A, n_time, a, s);
-            if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, p->A, n_time, a, s);
-            if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, p->A, n_time, a, s);
+            if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, A, n_time, a, au, s);
+            if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, A, n_time, a, au, s);
+            if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, A, n_time, a, au, s);
         } else {
-            if (g->M == 64) st = launch_fused<64, 1>(g, d_volt, vstride, p->A, n_time, a, s);
-            if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, p->A, n_time, a, s);
-            if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, p->A, n_time, a, s);
+            if (g->M == 64) st = launch_fused<64, 1>(g, d_volt, vstride, A, n_time, a, au, s);
+            if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, A, n_time, a, au, s);
+            if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, A, n_time, a, au, s);
         }
         if (st) return st;
     }
-    return autos_accumulate(p, acc, d_volt, n_time, s);
+    return in_kernel ? EPIC_OK : autos_accumulate(p, acc, d_volt, n_time, s);
 }
 
 epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,

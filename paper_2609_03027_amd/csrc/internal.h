@@ -106,6 +106,7 @@ struct epic_plan_s {
     epic::DevBuf d_table;    // float  [C][A][K][K][2] (optional)
     epic::DevBuf d_j0;       // int2   [C][A]
     epic::DevBuf d_w;        // double2 [C][A][K][K]  kernel weights W (not conjugated)
+    epic::DevBuf d_selfcorr; // double2 [C][(2K-1)^2][A] footprint self-correlation R_a[d]
     epic::DevBuf d_chan;     // int4   [C] {N, M, R, 0}
     epic::DevBuf d_img_off;  // int64  [C]
     epic::DevBuf d_grid_off; // int64  [C]
@@ -159,6 +160,7 @@ epic_status staged_accumulate(epic_plan p, epic_acc acc, const void *d_sky, int 
                               hipStream_t s);
 
 // readout.hip
+epic_status selfcorr_build(epic_plan p, hipStream_t s);
 epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hipStream_t s);
 
 // Decode one 4+4-bit sample (real in the high nibble).

@@ -211,10 +211,11 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
         EPIC_HIP(hipStreamSynchronize(s));
     }
 
+    if ((st = selfcorr_build(p, s))) return st;
     if ((st = fused_build(p, j0, w, s))) return st;
 
     p->bytes_plan = 0;
-    for (epic::DevBuf *b : {&p->d_pos, &p->d_freq, &p->d_table, &p->d_j0, &p->d_w, &p->d_chan,
+    for (epic::DevBuf *b : {&p->d_pos, &p->d_freq, &p->d_table, &p->d_j0, &p->d_w, &p->d_selfcorr, &p->d_chan,
                             &p->d_img_off, &p->d_grid_off, &p->d_csr_off, &p->d_csr_base,
                             &p->d_csr_ant, &p->d_csr_w, &p->d_twid, &p->d_sz_chans})
         p->bytes_plan += (int64_t)b->bytes;

@@ -14,51 +14,73 @@
 
 namespace epic {
 
-// One thread per (channel, displacement).  H layout: double2 [C][NH][D*D]
-// with NH = 1 (XX) or 3 (XX, YY, XY).
-template <int P>
-__global__ void k_auto_h(const double2 *__restrict__ w, const int32_t *__restrict__ autos, int A,
-                         int C, int K, double2 *__restrict__ H) {
+// Footprint self-correlation R_a[d] = sum_j conj(W_a(j)) W_a(j - d), one
+// thread per (element, displacement, channel); layout double2 [C][D*D][A].
+__global__ void k_selfcorr(const double2 *__restrict__ w, int A, int K, double2 *__restrict__ R) {
     const int D = 2 * K - 1;
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (d >= D * D) return;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int d = blockIdx.y, c = blockIdx.z;
+    if (a >= A) return;
     const int dx = d % D - (K - 1), dy = d / D - (K - 1);
-    constexpr int NPROD = P == 2 ? 4 : 1;
-    double2 hxx = make_double2(0, 0), hyy = make_double2(0, 0), hxy = make_double2(0, 0);
-    for (int a = 0; a < A; ++a) {
-        const double2 *wa = w + ((size_t)c * A + a) * K * K;
-        double rr = 0, ri = 0;
-        for (int ty = 0; ty < K; ++ty) {
-            const int uy = ty - dy;
-            if (uy < 0 || uy >= K) continue;
-            for (int tx = 0; tx < K; ++tx) {
-                const int ux = tx - dx;
-                if (ux < 0 || ux >= K) continue;
-                const double2 p = wa[ty * K + tx], q = wa[uy * K + ux];
-                // conj(p) * q
-                rr += p.x * q.x + p.y * q.y;
-                ri += p.x * q.y - p.y * q.x;
-            }
-        }
-        const int32_t *s = autos + ((size_t)c * A + a) * NPROD;
-        const double sxx = (double)s[0];
-        hxx.x += sxx * rr;
-        hxx.y += sxx * ri;
-        if (P == 2) {
-            const double syy = (double)s[1], sre = (double)s[2], sim = (double)s[3];
-            hyy.x += syy * rr;
-            hyy.y += syy * ri;
-            hxy.x += sre * rr - sim * ri;
-            hxy.y += sre * ri + sim * rr;
+    const double2 *wa = w + ((size_t)c * A + a) * K * K;
+    double rr = 0, ri = 0;
+    for (int ty = 0; ty < K; ++ty) {
+        const int uy = ty - dy;
+        if (uy < 0 || uy >= K) continue;
+        for (int tx = 0; tx < K; ++tx) {
+            const int ux = tx - dx;
+            if (ux < 0 || ux >= K) continue;
+            const double2 p = wa[ty * K + tx], q = wa[uy * K + ux];
+            rr += p.x * q.x + p.y * q.y;  // conj(p) * q
+            ri += p.x * q.y - p.y * q.x;
         }
     }
-    constexpr int NH = P == 2 ? 3 : 1;
-    double2 *h = H + (size_t)c * NH * D * D;
-    h[d] = hxx;
-    if (P == 2) {
-        h[D * D + d] = hyy;
-        h[2 * D * D + d] = hxy;
+    R[((size_t)c * D * D + d) * A + a] = make_double2(rr, ri);
+}
+
+// H^{pq}[d] = sum_a S_a^{pq} R_a[d]: one 256-thread block per (displacement,
+// channel) reducing over elements.  H layout double2 [C][NH][D*D], NH = 1
+// (XX) or 3 (XX, YY, XY).
+template <int P>
+__global__ __launch_bounds__(256) void k_auto_h(const double2 *__restrict__ R,
+                                                const int32_t *__restrict__ autos, int A, int K,
+                                                double2 *__restrict__ H) {
+    const int D2 = (2 * K - 1) * (2 * K - 1);
+    const int d = blockIdx.x, c = blockIdx.y;
+    constexpr int NPROD = P == 2 ? 4 : 1;
+    constexpr int NV = P == 2 ? 6 : 2;
+    double v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = 0.0;
+    const double2 *r = R + ((size_t)c * D2 + d) * A;
+    for (int a = threadIdx.x; a < A; a += blockDim.x) {
+        const double2 rv = r[a];
+        const int32_t *s = autos + ((size_t)c * A + a) * NPROD;
+        const double sxx = (double)s[0];
+        v[0] += sxx * rv.x;
+        v[1] += sxx * rv.y;
+        if (P == 2) {
+            const double syy = (double)s[1], sre = (double)s[2], sim = (double)s[3];
+            v[2] += syy * rv.x;
+            v[3] += syy * rv.y;
+            v[4] += sre * rv.x - sim * rv.y;
+            v[5] += sre * rv.y + sim * rv.x;
+        }
+    }
+    __shared__ double red[NV][256];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        constexpr int NH = P == 2 ? 3 : 1;
+        double2 *h = H + (size_t)c * NH * D2;
+        for (int q = 0; q < NH; ++q) h[q * D2 + d] = make_double2(red[2 * q][0], red[2 * q + 1][0]);
     }
 }
 
@@ -119,6 +141,17 @@ __global__ void k_readout(const float *__restrict__ acc, const double2 *__restri
     }
 }
 
+epic_status selfcorr_build(epic_plan p, hipStream_t s) {
+    const int D = 2 * p->K - 1;
+    epic_status st = p->d_selfcorr.alloc(sizeof(double2) * (size_t)p->C * D * D * p->A);
+    if (st) return st;
+    dim3 g((p->A + 255) / 256, D * D, p->C);
+    hipLaunchKernelGGL(k_selfcorr, g, dim3(256), 0, s, p->d_w.as<double2>(), p->A, p->K,
+                       p->d_selfcorr.as<double2>());
+    EPIC_HIP(hipGetLastError());
+    return EPIC_OK;
+}
+
 epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hipStream_t s) {
     const bool remove = (flags & EPIC_REMOVE_AUTOS) != 0;
     const bool norm = (flags & EPIC_NORMALISE) != 0;
@@ -127,13 +160,13 @@ epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hip
     const int D = 2 * p->K - 1;
     DevBuf &H = acc->d_h;
     if (remove) {
-        dim3 g((D * D + 63) / 64, p->C);
+        dim3 g(D * D, p->C);
         if (p->P == 2)
-            hipLaunchKernelGGL(k_auto_h<2>, g, dim3(64), 0, s, p->d_w.as<double2>(),
-                               acc->d_autos.as<int32_t>(), p->A, p->C, p->K, H.as<double2>());
+            hipLaunchKernelGGL(k_auto_h<2>, g, dim3(256), 0, s, p->d_selfcorr.as<double2>(),
+                               acc->d_autos.as<int32_t>(), p->A, p->K, H.as<double2>());
         else
-            hipLaunchKernelGGL(k_auto_h<1>, g, dim3(64), 0, s, p->d_w.as<double2>(),
-                               acc->d_autos.as<int32_t>(), p->A, p->C, p->K, H.as<double2>());
+            hipLaunchKernelGGL(k_auto_h<1>, g, dim3(256), 0, s, p->d_selfcorr.as<double2>(),
+                               acc->d_autos.as<int32_t>(), p->A, p->K, H.as<double2>());
         EPIC_HIP(hipGetLastError());
     }
     dim3 g((p->max_n * p->max_n + 255) / 256, p->C);
