@@ -326,8 +326,6 @@ __global__ void k_autos(const uint8_t *__restrict__ volt, int64_t volt_t_stride,
 }
 
 // ------------------------------------------------------------ host build
-template <int M> static constexpr int threads_for() { return FCfg<M>::T; }
-
 static int threads_of(int M) {
     return M == 64 ? FCfg<64>::T : M == 32 ? FCfg<32>::T : FCfg<16>::T;
 }
@@ -335,157 +333,186 @@ static int row_of(int M) {
     return M == 64 ? FCfg<64>::ROW : M == 32 ? FCfg<32>::ROW : FCfg<16>::ROW;
 }
 
+namespace {
+struct Tap {
+    int cell, ant;
+    float wr, wi;
+};
+}  // namespace
+
+// Gather entries of one item: the taps of class (ox, oy) folded modulo M,
+// grouped by cell; cells are dealt longest-first to the least-loaded of T
+// lanes, so each cell is summed by one lane in a fixed order and written once.
+static FusedItem build_item(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
+                            int c, int ox, int oy, int M, int T, std::vector<uint4> &all) {
+    const int A = p->A, K = p->K;
+    const int N = p->ch[c].N, R = p->ch[c].R, ROW = row_of(M);
+    std::vector<Tap> taps((size_t)A * K * K);
+    size_t n = 0;
+    for (int a = 0; a < A; ++a) {
+        const int jx0 = j0[((size_t)c * A + a) * 2];
+        const int jy0 = j0[((size_t)c * A + a) * 2 + 1];
+        for (int dy = 0; dy < K; ++dy)
+            for (int dx = 0; dx < K; ++dx) {
+                const int jx = jx0 + dx, jy = jy0 + dy;
+                const size_t wi = (((size_t)c * A + a) * K * K + dy * K + dx) * 2;
+                // conj(W) * (-1)^(jx+jy) * exp(+2 pi i (ox jx + oy jy) / N)
+                const double wr0 = w[wi], wi0 = -w[wi + 1];
+                const long ph = ((long)ox * jx + (long)oy * jy) % N;
+                const double ang = 2.0 * M_PI * (double)ph / (double)N;
+                const double sg = ((jx + jy) & 1) ? -1.0 : 1.0;
+                const double cr = std::cos(ang) * sg, ci = std::sin(ang) * sg;
+                Tap tp;
+                tp.cell = (jy % M) * ROW + (jx % M);
+                tp.ant = a;
+                tp.wr = (float)(wr0 * cr - wi0 * ci);
+                tp.wi = (float)(wr0 * ci + wi0 * cr);
+                taps[n++] = tp;
+            }
+    }
+    std::stable_sort(taps.begin(), taps.begin() + n,
+                     [](const Tap &x, const Tap &y) { return x.cell < y.cell; });
+    std::vector<std::pair<int, int>> runs;  // (start, count) per cell
+    for (size_t i = 0; i < n;) {
+        size_t k = i;
+        while (k < n && taps[k].cell == taps[i].cell) ++k;
+        runs.push_back({(int)i, (int)(k - i)});
+        i = k;
+    }
+    std::vector<int> order(runs.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return runs[x].second > runs[y].second; });
+    std::vector<std::vector<int>> lane_runs(T);
+    std::vector<int> load(T, 0);
+    using LP = std::pair<int, int>;
+    std::priority_queue<LP, std::vector<LP>, std::greater<LP>> heap;
+    for (int l = 0; l < T; ++l) heap.push({0, l});
+    for (int r : order) {
+        LP top = heap.top();
+        heap.pop();
+        lane_runs[top.second].push_back(r);
+        load[top.second] += runs[r].second;
+        heap.push({load[top.second], top.second});
+    }
+    const int n_iter = *std::max_element(load.begin(), load.end());
+    const size_t off = all.size();
+    all.resize(off + (size_t)n_iter * T, make_uint4(0u, 0u, 0u, 0u));
+    for (int l = 0; l < T; ++l) {
+        int k = 0;
+        for (int r : lane_runs[l])
+            for (int i = 0; i < runs[r].second; ++i, ++k) {
+                const Tap &tp = taps[runs[r].first + i];
+                const bool last = (i == runs[r].second - 1);
+                uint4 e;
+                e.x = (uint32_t)tp.ant | (last ? 0x80000000u : 0u);
+                e.y = (uint32_t)tp.cell;
+                e.z = __builtin_bit_cast(uint32_t, tp.wr);
+                e.w = __builtin_bit_cast(uint32_t, tp.wi);
+                all[off + (size_t)k * T + l] = e;
+            }
+    }
+    FusedItem fi{};
+    fi.c = c;
+    fi.N = N;
+    fi.R = R;
+    fi.ox = ox;
+    fi.oy = oy;
+    fi.n_iter = n_iter;
+    fi.entry_off = (int64_t)off;
+    fi.img_off = p->ch[c].img_off;
+    return fi;
+}
+
+// XCD-aware order.  Workgroups are dealt to the 8 XCDs round-robin by id, so
+// items placed at ids x, x+8, x+16, ... share one XCD and its L2.  Channels go
+// to XCD bins longest-first (a channel's items all read the same voltages);
+// each bin lists its items channel by channel; the bins are then interleaved,
+// padded with empty items (c = -1).
+static void xcd_layout(std::vector<FusedItem> &items, int C) {
+    constexpr int NX = 8;
+    std::vector<int64_t> chan_cost(C, 0);
+    std::vector<int> chans;
+    for (const FusedItem &fi : items) {
+        if (chan_cost[fi.c] == 0) chans.push_back(fi.c);
+        chan_cost[fi.c] += 64 + fi.n_iter;
+    }
+    std::stable_sort(chans.begin(), chans.end(),
+                     [&](int x, int y) { return chan_cost[x] > chan_cost[y]; });
+    std::vector<int64_t> bin_cost(NX, 0);
+    std::vector<std::vector<FusedItem>> bins(NX);
+    for (int c : chans) {
+        const int b = (int)(std::min_element(bin_cost.begin(), bin_cost.end()) - bin_cost.begin());
+        bin_cost[b] += chan_cost[c];
+        for (const FusedItem &fi : items)
+            if (fi.c == c) bins[b].push_back(fi);
+    }
+    size_t depth = 0;
+    for (auto &b : bins) depth = std::max(depth, b.size());
+    FusedItem empty{};
+    empty.c = -1;
+    std::vector<FusedItem> laid(depth * NX, empty);
+    for (int x = 0; x < NX; ++x)
+        for (size_t i = 0; i < bins[x].size(); ++i) laid[i * NX + x] = bins[x][i];
+    items.swap(laid);
+}
+
+static epic_status upload_group(FusedGroup *g, std::vector<FusedItem> &items,
+                                std::vector<uint4> &all, int C, hipStream_t s) {
+    xcd_layout(items, C);
+    g->n_items = (int)items.size();
+    g->host_items = items;
+    epic_status st;
+    if ((st = g->items.alloc(sizeof(FusedItem) * items.size()))) return st;
+    if ((st = g->entries.alloc(sizeof(uint4) * all.size()))) return st;
+    EPIC_HIP(hipMemcpyAsync(g->items.p, items.data(), sizeof(FusedItem) * items.size(),
+                            hipMemcpyHostToDevice, s));
+    EPIC_HIP(hipMemcpyAsync(g->entries.p, all.data(), sizeof(uint4) * all.size(),
+                            hipMemcpyHostToDevice, s));
+    EPIC_HIP(hipStreamSynchronize(s));
+    return EPIC_OK;
+}
+
 epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
                         hipStream_t s) {
     const int A = p->A, K = p->K;
     for (int M : {64, 32, 16}) {
-        std::vector<int> chans;
-        for (int c = 0; c < p->C; ++c)
-            if (p->ch[c].M == M) chans.push_back(c);
-        if (chans.empty()) continue;
-        const int T = threads_of(M), ROW = row_of(M);
+        std::vector<FusedItem> items;
+        std::vector<uint4> all;
+        const int T = threads_of(M);
+        for (int c = 0; c < p->C; ++c) {
+            if (p->ch[c].M != M) continue;
+            const int R = p->ch[c].R;
+            for (int oy = 0; oy < R; ++oy)
+                for (int ox = 0; ox < R; ++ox) items.push_back(build_item(p, j0, w, c, ox, oy, M, T, all));
+        }
+        if (items.empty()) continue;
         auto *g = new FusedGroup();
         g->M = M;
         p->groups.push_back(g);
-
-        struct Tap {
-            int cell, ant;
-            float wr, wi;
-        };
-        std::vector<uint4> all;
-        std::vector<FusedItem> items;
-        std::vector<Tap> taps((size_t)A * K * K);
-        std::vector<int> order;
-        for (int c : chans) {
-            const int N = p->ch[c].N, R = p->ch[c].R;
-            for (int oy = 0; oy < R; ++oy)
-                for (int ox = 0; ox < R; ++ox) {
-                    // folded taps of this class
-                    size_t n = 0;
-                    for (int a = 0; a < A; ++a) {
-                        const int jx0 = j0[((size_t)c * A + a) * 2];
-                        const int jy0 = j0[((size_t)c * A + a) * 2 + 1];
-                        for (int dy = 0; dy < K; ++dy)
-                            for (int dx = 0; dx < K; ++dx) {
-                                const int jx = jx0 + dx, jy = jy0 + dy;
-                                const size_t wi = (((size_t)c * A + a) * K * K + dy * K + dx) * 2;
-                                // conj(W) * (-1)^(jx+jy) * exp(+2 pi i (ox jx + oy jy) / N)
-                                const double wr0 = w[wi], wi0 = -w[wi + 1];
-                                const long ph = ((long)ox * jx + (long)oy * jy) % N;
-                                const double ang = 2.0 * M_PI * (double)ph / (double)N;
-                                const double sg = ((jx + jy) & 1) ? -1.0 : 1.0;
-                                const double cr = std::cos(ang) * sg, ci = std::sin(ang) * sg;
-                                Tap tp;
-                                tp.cell = (jy % M) * ROW + (jx % M);
-                                tp.ant = a;
-                                tp.wr = (float)(wr0 * cr - wi0 * ci);
-                                tp.wi = (float)(wr0 * ci + wi0 * cr);
-                                taps[n++] = tp;
-                            }
-                    }
-                    std::stable_sort(taps.begin(), taps.end(),
-                                     [](const Tap &x, const Tap &y) { return x.cell < y.cell; });
-                    // cells as runs of the sorted taps
-                    std::vector<std::pair<int, int>> runs;  // (start, count)
-                    for (size_t i = 0; i < n;) {
-                        size_t k = i;
-                        while (k < n && taps[k].cell == taps[i].cell) ++k;
-                        runs.push_back({(int)i, (int)(k - i)});
-                        i = k;
-                    }
-                    // longest-first onto the least-loaded lane
-                    order.resize(runs.size());
-                    std::iota(order.begin(), order.end(), 0);
-                    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-                        return runs[x].second > runs[y].second;
-                    });
-                    std::vector<std::vector<int>> lane_runs(T);
-                    std::vector<int> load(T, 0);
-                    using LP = std::pair<int, int>;
-                    std::priority_queue<LP, std::vector<LP>, std::greater<LP>> heap;
-                    for (int l = 0; l < T; ++l) heap.push({0, l});
-                    for (int r : order) {
-                        LP top = heap.top();
-                        heap.pop();
-                        lane_runs[top.second].push_back(r);
-                        load[top.second] += runs[r].second;
-                        heap.push({load[top.second], top.second});
-                    }
-                    const int n_iter = *std::max_element(load.begin(), load.end());
-                    const size_t off = all.size();
-                    all.resize(off + (size_t)n_iter * T, make_uint4(0u, 0u, 0u, 0u));
-                    for (int l = 0; l < T; ++l) {
-                        int k = 0;
-                        for (int r : lane_runs[l]) {
-                            for (int i = 0; i < runs[r].second; ++i, ++k) {
-                                const Tap &tp = taps[runs[r].first + i];
-                                const bool last = (i == runs[r].second - 1);
-                                uint4 e;
-                                e.x = (uint32_t)tp.ant | (last ? 0x80000000u : 0u);
-                                e.y = (uint32_t)tp.cell;
-                                e.z = __builtin_bit_cast(uint32_t, tp.wr);
-                                e.w = __builtin_bit_cast(uint32_t, tp.wi);
-                                all[off + (size_t)k * T + l] = e;
-                            }
-                        }
-                    }
-                    FusedItem fi;
-                    fi.c = c;
-                    fi.N = N;
-                    fi.R = R;
-                    fi.ox = ox;
-                    fi.oy = oy;
-                    fi.n_iter = n_iter;
-                    fi.entry_off = (int64_t)off;
-                    fi.img_off = p->ch[c].img_off;
-                    items.push_back(fi);
-                }
-        }
-        // XCD-aware order.  Workgroups are dealt to the 8 XCDs round-robin by
-        // id, so items placed at ids x, x+8, x+16, ... share one XCD and its L2.
-        // Channels go to XCD bins longest-first (a channel's items all read the
-        // same voltages); each bin lists its items heaviest first; the bins are
-        // then interleaved, padded with empty items (c = -1).
-        {
-            constexpr int NX = 8;
-            std::vector<int> chan_order;
-            std::vector<int64_t> chan_cost(p->C, 0);
-            for (const FusedItem &fi : items) chan_cost[fi.c] += 64 + fi.n_iter;
-            for (int c : chans) chan_order.push_back(c);
-            std::stable_sort(chan_order.begin(), chan_order.end(),
-                             [&](int x, int y) { return chan_cost[x] > chan_cost[y]; });
-            std::vector<int64_t> bin_cost(NX, 0);
-            std::vector<int> chan_bin(p->C, 0);
-            for (int c : chan_order) {
-                const int b = (int)(std::min_element(bin_cost.begin(), bin_cost.end()) -
-                                    bin_cost.begin());
-                chan_bin[c] = b;
-                bin_cost[b] += chan_cost[c];
-            }
-            std::vector<std::vector<FusedItem>> bins(NX);
-            for (int c : chan_order)
-                for (const FusedItem &fi : items)
-                    if (fi.c == c) bins[chan_bin[c]].push_back(fi);
-            size_t depth = 0;
-            for (auto &b : bins) depth = std::max(depth, b.size());
-            FusedItem empty{};
-            empty.c = -1;
-            std::vector<FusedItem> laid(depth * NX, empty);
-            for (int x = 0; x < NX; ++x)
-                for (size_t i = 0; i < bins[x].size(); ++i) laid[i * NX + x] = bins[x][i];
-            items.swap(laid);
-        }
-        g->n_items = (int)items.size();
-        g->host_items = items;
-        epic_status st;
-        if ((st = g->items.alloc(sizeof(FusedItem) * items.size()))) return st;
-        if ((st = g->entries.alloc(sizeof(uint4) * all.size()))) return st;
-        EPIC_HIP(hipMemcpyAsync(g->items.p, items.data(), sizeof(FusedItem) * items.size(),
-                                hipMemcpyHostToDevice, s));
-        EPIC_HIP(hipMemcpyAsync(g->entries.p, all.data(), sizeof(uint4) * all.size(),
-                                hipMemcpyHostToDevice, s));
-        EPIC_HIP(hipStreamSynchronize(s));
+        epic_status st = upload_group(g, items, all, p->C, s);
+        if (st) return st;
     }
+    return EPIC_OK;
+}
+
+// Allow a kernel the device's whole LDS once, then check the launch's need.
+static epic_status lds_ready(const void *kern, size_t lds) {
+    static int lds_max = -1;
+    static std::vector<const void *> done;
+    if (lds_max < 0) {
+        int dev = 0, v = 0;
+        EPIC_HIP(hipGetDevice(&dev));
+        EPIC_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        lds_max = v;
+    }
+    if (std::find(done.begin(), done.end(), kern) == done.end()) {
+        EPIC_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max));
+        done.push_back(kern);
+    }
+    if ((int64_t)lds > lds_max)
+        return fail(EPIC_ERR_UNSUPPORTED, "fused path: LDS need " + std::to_string(lds) +
+                                              " B above the device limit");
     return EPIC_OK;
 }
 
@@ -495,18 +522,8 @@ static epic_status launch_fused_ar(const FusedGroup *g, const uint8_t *d_volt, i
     constexpr int T = FCfg<M>::T, GSZ = M * FCfg<M>::ROW;
     const size_t lds = sizeof(float2) * P * GSZ + sizeof(float4) * (size_t)A;
     auto kern = k_fused<M, P, AR>;
-    static int lds_max = -1;
-    if (lds_max < 0) {
-        int dev = 0, v = 0;
-        EPIC_HIP(hipGetDevice(&dev));
-        EPIC_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        EPIC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, v));
-        lds_max = v;
-    }
-    if ((int64_t)lds > lds_max)
-        return fail(EPIC_ERR_UNSUPPORTED, "fused path: LDS need " + std::to_string(lds) +
-                                              " B above the device limit");
+    epic_status st = lds_ready(reinterpret_cast<const void *>(kern), lds);
+    if (st) return st;
     hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(T), lds, s, g->items.as<FusedItem>(),
                        g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos);
     EPIC_HIP(hipGetLastError());
@@ -528,7 +545,7 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
                              hipStream_t s) {
     const int64_t vstride = (int64_t)p->C * p->P * p->A;
     float *a = acc->d_acc.as<float>();
-    // The fused kernel adds the self-term sums when every group's threads
+    // The fused kernels add the self-term sums when every group's threads
     // cover the elements in at most four rounds; otherwise a separate pass.
     bool in_kernel = true;
     for (const FusedGroup *g : p->groups)

@@ -120,6 +120,21 @@ def test_lwa_channels_match_oracle():
     _check(got, ref, "lwa/staged")
 
 
+def test_lwa_single_feed_per_class_path_matches_oracle():
+    # one feed never takes the paired-class kernel, so this covers the
+    # one-class-per-item path at N = 128 (four 64 x 64 classes)
+    _say("case lwa single feed: 2 channels x 24 samples")
+    from dataclasses import replace
+    chans = [3, 120]
+    full = replace(synth.workload("lwa"), n_pol=1)
+    wl = full.subset(chans).with_time(24)
+    pos = synth.antenna_layout(full)
+    volt = synth.voltages(full.with_time(24), pos, chans=chans)
+    got = _run(wl, pos, volt)
+    ref = oracle_images(volt, pos, wl, range(len(chans)))
+    _check(got, ref, "lwa/1pol")
+
+
 def test_ska_every_grid_size_matches_oracle():
     # one channel of each grid side: 32, 48, 64, 96, 128, 192
     full = synth.workload("ska")
