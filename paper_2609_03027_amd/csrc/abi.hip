@@ -76,8 +76,6 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     if (!(sg > 0.0) || !std::isfinite(sg)) return fail(EPIC_ERR_ARG, "kernel_sigma_cells must be > 0");
     if (d->precision < EPIC_F32 || d->precision > EPIC_BF16X2_MFMA)
         return fail(EPIC_ERR_ARG, "unknown precision");
-    if (d->precision != EPIC_F32)
-        return fail(EPIC_ERR_UNSUPPORTED, "this precision is not built into the library");
     if (d->aperture_n < 0 || (d->aperture_n & 1))
         return fail(EPIC_ERR_ARG, "aperture_n must be 0 or a positive even number");
     for (int c = 0; c < d->n_chan; ++c)
@@ -254,8 +252,10 @@ epic_status epic_accumulate(epic_plan p, epic_acc a, const uint8_t *d_volt, cons
     if (d_sky) {
         st = staged_accumulate(p, a, d_sky, n_time, s);
         if (!st && d_volt) st = autos_accumulate(p, a, d_volt, n_time, s);
-    } else {
+    } else if (p->precision == EPIC_F32) {
         st = fused_accumulate(p, a, d_volt, n_time, s);
+    } else {
+        st = gemm_accumulate(p, a, d_volt, n_time, s);
     }
     if (!st) a->count += n_time;
     return st;

@@ -1,0 +1,462 @@
+// Direct DFT-as-GEMM on MFMA (the reduced-precision variants).
+//
+// Eq. 1 is linear in the element voltages: E[k] = sum_a B_a[k] E_a with
+// B_a[k] = sum_j conj(W_a(j)) exp(+2 pi i (k - N/2).(j - N/2) / N), the image
+// of element a's kernel footprint (gridding and transform folded into one
+// "beam" matrix; direct beamforming over the whole field, Sec. 1-2).  Per
+// channel this is a dense complex product E[pixel][t,p] = B[pixel][a] V[a][t,p],
+// done here as one real GEMM
+//     [Er]   [Br  -Bi] [Vr]        rows interleave (pixel, re/im),
+//     [Ei] = [Bi   Br] [Vi]        K = 2 Ap (Ap = A padded to 16 KS),
+// with the Eq. 2 products and the time sum fused into the epilogue, so the
+// sky images never leave registers.  B is built once in FP64 and rounded to
+// the operand type: FP16; BF16 hi + lo (two products, FP32 accumulate); or
+// FP8 e4m3 scaled per channel by a power of two s (results scaled by 1/s^2).
+// The int4 voltages are exact in every operand type.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace epic {
+
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Operand element storage per precision.
+template <int DT> struct Op;
+template <> struct Op<EPIC_F16_MFMA> { typedef uint16_t E; static constexpr int BYTES = 2; };
+template <> struct Op<EPIC_BF16X2_MFMA> { typedef uint16_t E; static constexpr int BYTES = 2; };
+template <> struct Op<EPIC_F8E4M3_MFMA> { typedef uint8_t E; static constexpr int BYTES = 1; };
+
+__device__ __forceinline__ uint16_t to_f16(float x) {
+    _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+    // round to nearest even
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint8_t to_e4m3(float x) {
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xFF);
+}
+
+// Position of B' element (row r, column k) in the MFMA A-operand layout of a
+// channel: [row block of 16][K step of 32][lane][8], lane = 16 (k%32 / 8) + r%16.
+__device__ __forceinline__ int64_t a_index(int64_t blk0, int KS, int r, int k) {
+    const int rb = r >> 4, rr = r & 15, ks = k >> 5, kk = k & 31;
+    const int lane = (kk >> 3) * 16 + rr;
+    return (((blk0 + rb) * KS + ks) * 64 + lane) * 8 + (kk & 7);
+}
+
+// Beam matrix of channel c in FP64, one thread per pixel, rounded into the
+// operand layout.  Phases come from an FP64 table exp(+2 pi i m / N).
+template <int DT>
+__global__ __launch_bounds__(256) void k_plan_beam(const int2 *__restrict__ j0,
+                                                   const double2 *__restrict__ w,
+                                                   const int4 *__restrict__ chan,
+                                                   const int64_t *__restrict__ blk_off, int c,
+                                                   int A, int Ap, int KS, int K,
+                                                   const float *__restrict__ scale,
+                                                   uint8_t *__restrict__ out_hi,
+                                                   uint8_t *__restrict__ out_lo) {
+    extern __shared__ double2 tw[];
+    const int N = chan[c].x;
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        double s, cs;
+        sincospi(2.0 * (double)m / (double)N, &s, &cs);
+        tw[m] = make_double2(cs, s);
+    }
+    __syncthreads();
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= N * N) return;
+    const int ky = pix / N, kx = pix % N;
+    const float sc = scale[c];
+    typedef typename Op<DT>::E E;
+    E *hi = reinterpret_cast<E *>(out_hi);
+    E *lo = reinterpret_cast<E *>(out_lo);
+    const int64_t b0 = blk_off[c];
+    for (int a = 0; a < Ap; ++a) {
+        double br = 0.0, bi = 0.0;
+        if (a < A) {
+            const int2 s0 = j0[(int64_t)c * A + a];
+            const double2 *wa = w + ((int64_t)c * A + a) * K * K;
+            for (int dy = 0; dy < K; ++dy) {
+                const long my = ((long)(ky - N / 2) * (s0.y + dy - N / 2)) % N;
+                const double2 py = tw[(my + N) % N];
+                for (int dx = 0; dx < K; ++dx) {
+                    const long mx = ((long)(kx - N / 2) * (s0.x + dx - N / 2)) % N;
+                    const double2 px = tw[(mx + N) % N];
+                    const double er = px.x * py.x - px.y * py.y;
+                    const double ei = px.x * py.y + px.y * py.x;
+                    const double2 ww = wa[dy * K + dx];  // conj(W) * e
+                    br += ww.x * er + ww.y * ei;
+                    bi += ww.x * ei - ww.y * er;
+                }
+            }
+        }
+        br *= sc;
+        bi *= sc;
+        // rows 2 pix (re) and 2 pix + 1 (im); columns a (Vr) and Ap + a (Vi)
+        const double v[4] = {br, -bi, bi, br};
+        const int rr[4] = {2 * pix, 2 * pix, 2 * pix + 1, 2 * pix + 1};
+        const int kk[4] = {a, Ap + a, a, Ap + a};
+        for (int q = 0; q < 4; ++q) {
+            const int64_t ix = a_index(b0, KS, rr[q], kk[q]);
+            const float x = (float)v[q];
+            if (DT == EPIC_F16_MFMA) {
+                hi[ix] = to_f16(x);
+            } else if (DT == EPIC_BF16X2_MFMA) {
+                const uint16_t h = to_bf16(x);
+                hi[ix] = h;
+                lo[ix] = to_bf16((float)(v[q] - (double)from_bf16(h)));
+            } else {
+                hi[ix] = to_e4m3(x);
+            }
+        }
+    }
+}
+
+// Voltages -> B operand: V'[c][col][k], col = t P + p (padded to a multiple of
+// 16 with zeros), k < Ap real parts, k >= Ap imaginary parts.
+template <int DT>
+__global__ void k_volt_operand(const uint8_t *__restrict__ volt, int64_t vstride, int A, int Ap,
+                               int P, int C, int n_time, int cols_pad,
+                               uint8_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)C * cols_pad * Ap;
+    if (i >= tot) return;
+    const int a = (int)(i % Ap);
+    const int64_t cc = i / Ap;
+    const int col = (int)(cc % cols_pad);
+    const int c = (int)(cc / cols_pad);
+    const int t = col / P, p = col % P;
+    float re = 0.f, im = 0.f;
+    if (a < A && t < n_time) {
+        const uint32_t b = volt[(int64_t)t * vstride + ((int64_t)c * P + p) * A + a];
+        re = (float)dec_re(b);
+        im = (float)dec_im(b);
+    }
+    typedef typename Op<DT>::E E;
+    E *o = reinterpret_cast<E *>(out) + ((int64_t)c * cols_pad + col) * 2 * Ap;
+    if (DT == EPIC_F16_MFMA) {
+        o[a] = to_f16(re);
+        o[Ap + a] = to_f16(im);
+    } else if (DT == EPIC_BF16X2_MFMA) {
+        o[a] = to_bf16(re);
+        o[Ap + a] = to_bf16(im);
+    } else {
+        o[a] = to_e4m3(re);
+        o[Ap + a] = to_e4m3(im);
+    }
+}
+
+template <int DT> struct Frag;
+template <> struct Frag<EPIC_F16_MFMA> {
+    typedef h8v T;
+    static __device__ __forceinline__ f4v mma(T a, T b, f4v c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Frag<EPIC_BF16X2_MFMA> {
+    typedef b8v T;
+    static __device__ __forceinline__ f4v mma(T a, T b, f4v c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Frag<EPIC_F8E4M3_MFMA> {
+    typedef long T;
+    static __device__ __forceinline__ f4v mma(T a, T b, f4v c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+    }
+};
+
+__device__ __forceinline__ float swap_pair(float x) {
+    // exchange with the neighbouring lane (lane ^ 1)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
+// One workgroup = 8 waves = 128 RB rows of B' of one channel, every column
+// tile (16 columns) of the call.  Each wave keeps its RB row blocks (x KS
+// K-steps) of the A operand in registers; column tiles are staged in LDS.
+// MFMA 16x16x32 output layout: lane l holds rows 4 (l / 16) + i, column l % 16.
+// Rows 4g + {0, 1} are pixel 2g (re, im), 4g + {2, 3} pixel 2g + 1.  With two
+// feeds the columns alternate (t, X), (t, Y): even lanes keep XX and Re XY,
+// odd lanes YY and Im XY, exchanging the other feed with lane ^ 1.
+template <int DT, int P, int RB, int KS>
+__global__ __launch_bounds__(512) void k_dftgemm(const uint8_t *__restrict__ a_hi,
+                                                 const uint8_t *__restrict__ a_lo,
+                                                 const uint8_t *__restrict__ vop,
+                                                 const int4 *__restrict__ chan,
+                                                 const int64_t *__restrict__ blk_off,
+                                                 const int64_t *__restrict__ img_off,
+                                                 const float *__restrict__ inv_s2, int Ap,
+                                                 int cols_pad, float *__restrict__ acc) {
+    typedef typename Frag<DT>::T FT;
+    typedef typename Op<DT>::E E;
+    constexpr int EB = Op<DT>::BYTES;
+    constexpr int K = 32 * KS;                  // = 2 Ap
+    constexpr int CSTRIDE = K * EB + 16;        // LDS bytes per column (padded)
+    constexpr int NPROD = P == 2 ? 4 : 1;
+    __shared__ __attribute__((aligned(16))) uint8_t tile[16 * CSTRIDE];
+
+    const int c = blockIdx.y;
+    const int N = chan[c].x;
+    const int rows = 2 * N * N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int blk_first = blockIdx.x * 8 * RB + wave * RB;
+    if (blockIdx.x * 8 * RB * 16 >= rows) return;  // whole workgroup idle
+    const bool live = blk_first * 16 < rows;
+
+    FT ah[RB][KS], al[RB][KS];
+    const int64_t b0 = blk_off[c];
+    const int nblk = rows / 16;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            // row blocks past the channel's last one load block 0 (never stored)
+            const int blk = (live && blk_first + r < nblk) ? blk_first + r : 0;
+            const int64_t ix = (((b0 + blk) * KS + s) * 64 + lane) * 8;
+            ah[r][s] = *reinterpret_cast<const FT *>(a_hi + ix * EB);
+            if (DT == EPIC_BF16X2_MFMA) al[r][s] = *reinterpret_cast<const FT *>(a_lo + ix * EB);
+        }
+
+    float sum[RB][2][2];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) sum[r][q][0] = sum[r][q][1] = 0.f;
+
+    const uint8_t *vc = vop + (int64_t)c * cols_pad * K * EB;
+    const int g = lane >> 4, col = lane & 15;
+    for (int ct = 0; ct < cols_pad; ct += 16) {
+        // stage 16 columns x K operands (16-byte pieces)
+        const int pieces = 16 * (K * EB / 16);
+        for (int i = threadIdx.x; i < pieces; i += 512) {
+            const int cl = i / (K * EB / 16), off = (i % (K * EB / 16)) * 16;
+            *reinterpret_cast<uint4 *>(tile + cl * CSTRIDE + off) =
+                *reinterpret_cast<const uint4 *>(vc + ((int64_t)(ct + cl) * K) * EB + off);
+        }
+        __syncthreads();
+        if (live) {
+            f4v d[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) d[r] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const FT b = *reinterpret_cast<const FT *>(tile + col * CSTRIDE +
+                                                           (32 * s + 8 * g) * EB);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    d[r] = Frag<DT>::mma(ah[r][s], b, d[r]);
+                    if (DT == EPIC_BF16X2_MFMA) d[r] = Frag<DT>::mma(al[r][s], b, d[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const float vr = d[r][2 * q], vi = d[r][2 * q + 1];
+                    if (P == 2) {
+                        const float ur = swap_pair(vr), ui = swap_pair(vi);
+                        // even lane: own = Ex, other = Ey; odd lane: own = Ey, other = Ex
+                        sum[r][q][0] += vr * vr + vi * vi;
+                        if ((lane & 1) == 0)
+                            sum[r][q][1] += vr * ur + vi * ui;       // Re Ex conj(Ey)
+                        else
+                            sum[r][q][1] += ui * vr - ur * vi;       // Im Ex conj(Ey)
+                    } else {
+                        sum[r][q][0] += vr * vr + vi * vi;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!live) return;
+    // reduce over the lanes of a 16-lane group that hold the same feed
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float x = sum[r][q][h];
+                if (P == 1) x += __shfl_xor(x, 1);
+                x += __shfl_xor(x, 2);
+                x += __shfl_xor(x, 4);
+                x += __shfl_xor(x, 8);
+                sum[r][q][h] = x;
+            }
+    if (col >= (P == 2 ? 2 : 1)) return;
+    const float is2 = inv_s2[c];
+    const int64_t plane = (int64_t)N * N;
+    float *ac = acc + img_off[c];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int row = (blk_first + r) * 16 + 4 * g + 2 * q;
+            if (row >= rows) continue;
+            const int pix = row >> 1;
+            if (P == 2) {
+                // lane 0 of the group: XX, Re XY; lane 1: YY, Im XY
+                const int p0 = col == 0 ? 0 : 1, p1 = col == 0 ? 2 : 3;
+                ac[p0 * plane + pix] += sum[r][q][0] * is2;
+                ac[p1 * plane + pix] += sum[r][q][1] * is2;
+            } else {
+                ac[pix] += sum[r][q][0] * is2;
+            }
+        }
+    (void)NPROD;
+}
+
+// ------------------------------------------------------------------ host
+static int ks_for(int A) {
+    for (int ks : {1, 2, 4, 8, 16})
+        if (16 * ks >= A) return ks;
+    return 0;
+}
+
+static int rb_for(int dt) { return dt == EPIC_F8E4M3_MFMA ? 4 : dt == EPIC_F16_MFMA ? 2 : 1; }
+
+template <int DT>
+static epic_status build_dt(epic_plan p, hipStream_t s) {
+    GemmPlan &gp = p->gemm;
+    const int64_t n = gp.n_blocks * gp.KS * 64 * 8;  // elements
+    epic_status st = gp.a_hi.alloc(n * Op<DT>::BYTES);
+    if (st) return st;
+    if (DT == EPIC_BF16X2_MFMA && (st = gp.a_lo.alloc(n * Op<DT>::BYTES))) return st;
+    for (int c = 0; c < p->C; ++c) {
+        const int N = p->ch[c].N;
+        // one channel per launch keeps the per-channel phase table in LDS
+        dim3 g((N * N + 255) / 256, 1);
+        hipLaunchKernelGGL(k_plan_beam<DT>, g, dim3(256), sizeof(double2) * N, s,
+                           p->d_j0.as<int2>(), p->d_w.as<double2>(), p->d_chan.as<int4>(),
+                           gp.d_blk_off.as<int64_t>(), c, p->A, gp.Ap, gp.KS, p->K,
+                           gp.d_scale.as<float>(), gp.a_hi.as<uint8_t>(), gp.a_lo.as<uint8_t>());
+        EPIC_HIP(hipGetLastError());
+    }
+    EPIC_HIP(hipStreamSynchronize(s));
+    return EPIC_OK;
+}
+
+epic_status gemm_build(epic_plan p, hipStream_t s) {
+    GemmPlan &gp = p->gemm;
+    gp.KS = ks_for(p->A);
+    if (gp.KS == 0)
+        return fail(EPIC_ERR_UNSUPPORTED, "DFT-GEMM variants need n_ant <= 256 (small arrays)");
+    for (const auto &c : p->ch)
+        if ((int64_t)c.N * c.N > 65536)
+            return fail(EPIC_ERR_UNSUPPORTED, "DFT-GEMM variants need grids of at most 256 x 256");
+    gp.Ap = 16 * gp.KS;
+    std::vector<int64_t> blk(p->C);
+    std::vector<float> scale(p->C), inv_s2(p->C);
+    int64_t nb = 0;
+    for (int c = 0; c < p->C; ++c) {
+        blk[c] = nb;
+        nb += (2LL * p->ch[c].N * p->ch[c].N + 15) / 16;
+        scale[c] = 1.0f;
+        if (p->precision == EPIC_F8E4M3_MFMA) {
+            // |B| <= sum_j |W_a(j)|; scale the largest to at most 256 (e4m3 max 448)
+            double bound = 0.0;
+            for (int a = 0; a < p->A; ++a) {
+                double sa = 0.0;
+                for (int k = 0; k < p->K * p->K; ++k) {
+                    const size_t wi = (((size_t)c * p->A + a) * p->K * p->K + k) * 2;
+                    sa += std::hypot(p->w_host[wi], p->w_host[wi + 1]);
+                }
+                bound = std::max(bound, sa);
+            }
+            const double e = bound > 0 ? std::floor(std::log2(256.0 / bound)) : 0.0;
+            scale[c] = (float)std::ldexp(1.0, (int)e);
+        }
+        inv_s2[c] = 1.0f / (scale[c] * scale[c]);
+    }
+    gp.n_blocks = nb;
+    epic_status st;
+    if ((st = gp.d_blk_off.alloc(sizeof(int64_t) * p->C))) return st;
+    if ((st = gp.d_scale.alloc(sizeof(float) * p->C))) return st;
+    if ((st = gp.d_inv_s2.alloc(sizeof(float) * p->C))) return st;
+    EPIC_HIP(hipMemcpyAsync(gp.d_blk_off.p, blk.data(), sizeof(int64_t) * p->C, hipMemcpyHostToDevice, s));
+    EPIC_HIP(hipMemcpyAsync(gp.d_scale.p, scale.data(), sizeof(float) * p->C, hipMemcpyHostToDevice, s));
+    EPIC_HIP(hipMemcpyAsync(gp.d_inv_s2.p, inv_s2.data(), sizeof(float) * p->C, hipMemcpyHostToDevice, s));
+    switch (p->precision) {
+        case EPIC_F16_MFMA: st = build_dt<EPIC_F16_MFMA>(p, s); break;
+        case EPIC_BF16X2_MFMA: st = build_dt<EPIC_BF16X2_MFMA>(p, s); break;
+        case EPIC_F8E4M3_MFMA: st = build_dt<EPIC_F8E4M3_MFMA>(p, s); break;
+        default: return fail(EPIC_ERR_UNSUPPORTED, "unknown precision");
+    }
+    if (st) return st;
+    // operand scratch for up to t_chunk samples per launch
+    const int eb = p->precision == EPIC_F8E4M3_MFMA ? 1 : 2;
+    gp.t_chunk = 256;
+    gp.cols_pad = ((gp.t_chunk * p->P + 15) / 16) * 16;
+    return gp.vbuf.alloc((size_t)p->C * gp.cols_pad * 2 * gp.Ap * eb);
+}
+
+template <int DT, int P, int RB, int KS>
+static epic_status launch_gemm(epic_plan p, float *acc, int cols_pad, hipStream_t s) {
+    GemmPlan &gp = p->gemm;
+    const int rows_max = 2 * p->max_n * p->max_n;
+    dim3 g((rows_max + 8 * RB * 16 - 1) / (8 * RB * 16), p->C);
+    hipLaunchKernelGGL((k_dftgemm<DT, P, RB, KS>), g, dim3(512), 0, s, gp.a_hi.as<uint8_t>(),
+                       gp.a_lo.as<uint8_t>(), gp.vbuf.as<uint8_t>(), p->d_chan.as<int4>(),
+                       gp.d_blk_off.as<int64_t>(), p->d_img_off.as<int64_t>(),
+                       gp.d_inv_s2.as<float>(), gp.Ap, cols_pad, acc);
+    EPIC_HIP(hipGetLastError());
+    return EPIC_OK;
+}
+
+template <int DT, int P>
+static epic_status launch_gemm_ks(epic_plan p, float *acc, int cols_pad, hipStream_t s) {
+    constexpr int RB = DT == EPIC_F8E4M3_MFMA ? 4 : DT == EPIC_F16_MFMA ? 2 : 1;
+    switch (p->gemm.KS) {
+        case 1: return launch_gemm<DT, P, RB, 1>(p, acc, cols_pad, s);
+        case 2: return launch_gemm<DT, P, RB, 2>(p, acc, cols_pad, s);
+        case 4: return launch_gemm<DT, P, RB, 4>(p, acc, cols_pad, s);
+        case 8: return launch_gemm<DT, P, RB, 8>(p, acc, cols_pad, s);
+        case 16: return launch_gemm<DT, P, RB, 16>(p, acc, cols_pad, s);
+    }
+    return fail(EPIC_ERR_UNSUPPORTED, "K steps");
+}
+
+template <int DT>
+static epic_status gemm_chunk(epic_plan p, float *acc, const uint8_t *d_volt, int nt, hipStream_t s) {
+    GemmPlan &gp = p->gemm;
+    const int cols_pad = ((nt * p->P + 15) / 16) * 16;
+    const int64_t tot = (int64_t)p->C * cols_pad * gp.Ap;
+    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    hipLaunchKernelGGL(k_volt_operand<DT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       d_volt, vstride, p->A, gp.Ap, p->P, p->C, nt, cols_pad,
+                       gp.vbuf.as<uint8_t>());
+    EPIC_HIP(hipGetLastError());
+    return p->P == 2 ? launch_gemm_ks<DT, 2>(p, acc, cols_pad, s)
+                     : launch_gemm_ks<DT, 1>(p, acc, cols_pad, s);
+}
+
+epic_status gemm_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                            hipStream_t s) {
+    GemmPlan &gp = p->gemm;
+    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    for (int t0 = 0; t0 < n_time; t0 += gp.t_chunk) {
+        const int nt = std::min(gp.t_chunk, n_time - t0);
+        const uint8_t *v = d_volt + (int64_t)t0 * vstride;
+        epic_status st;
+        switch (p->precision) {
+            case EPIC_F16_MFMA: st = gemm_chunk<EPIC_F16_MFMA>(p, acc->d_acc.as<float>(), v, nt, s); break;
+            case EPIC_BF16X2_MFMA: st = gemm_chunk<EPIC_BF16X2_MFMA>(p, acc->d_acc.as<float>(), v, nt, s); break;
+            case EPIC_F8E4M3_MFMA: st = gemm_chunk<EPIC_F8E4M3_MFMA>(p, acc->d_acc.as<float>(), v, nt, s); break;
+            default: return fail(EPIC_ERR_UNSUPPORTED, "unknown precision");
+        }
+        if (st) return st;
+    }
+    return autos_accumulate(p, acc, d_volt, n_time, s);
+}
+
+}  // namespace epic

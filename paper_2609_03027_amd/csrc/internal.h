@@ -83,6 +83,21 @@ struct FusedGroup {
     std::vector<FusedItem> host_items;
 };
 
+// Direct DFT-as-GEMM (reduced-precision variants): beam matrix per channel in
+// the MFMA A-operand layout, voltage operand scratch.
+struct GemmPlan {
+    int KS = 0;           // K steps of 32 (K = 2 Ap = 32 KS)
+    int Ap = 0;           // elements padded to 16 KS
+    int64_t n_blocks = 0; // 16-row blocks over all channels
+    int t_chunk = 0;      // samples per GEMM launch
+    int cols_pad = 0;     // operand columns per channel for a full chunk
+    DevBuf a_hi, a_lo;    // A operand (lo only for BF16 hi + lo)
+    DevBuf d_blk_off;     // int64 [C] first row block of each channel
+    DevBuf d_scale;       // float [C] power-of-two operand scale
+    DevBuf d_inv_s2;      // float [C] 1 / scale^2 applied to the sums
+    DevBuf vbuf;          // voltage operand for one chunk
+};
+
 }  // namespace epic
 
 struct epic_plan_s {
@@ -97,6 +112,7 @@ struct epic_plan_s {
     int64_t grid_elems_per_t = 0;
     std::vector<double> pos, freq;
     std::vector<int> grid_n;
+    std::vector<double> w_host;   // kernel weights as computed on the device
     std::vector<epic::Chan> ch;
     bool has_table = false;
 
@@ -123,8 +139,9 @@ struct epic_plan_s {
     std::vector<int64_t> sz_off;
     epic::DevBuf d_sz_chans; // int32 channel ids, grouped by size
 
-    // fused path
+    // fused path (FP32) or direct DFT-GEMM (MFMA precisions)
     std::vector<epic::FusedGroup *> groups;
+    epic::GemmPlan gemm;
 
     int64_t bytes_plan = 0;
     ~epic_plan_s();
@@ -158,6 +175,11 @@ epic_status staged_image(epic_plan p, const void *d_grid, int n_time, void *d_sk
                          hipStream_t s);
 epic_status staged_accumulate(epic_plan p, epic_acc acc, const void *d_sky, int n_time,
                               hipStream_t s);
+
+// dftgemm.hip
+epic_status gemm_build(epic_plan p, hipStream_t s);
+epic_status gemm_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                            hipStream_t s);
 
 // readout.hip
 epic_status selfcorr_build(epic_plan p, hipStream_t s);

@@ -212,7 +212,12 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     }
 
     if ((st = selfcorr_build(p, s))) return st;
-    if ((st = fused_build(p, j0, w, s))) return st;
+    p->w_host = w;
+    if (p->precision == EPIC_F32) {
+        if ((st = fused_build(p, j0, w, s))) return st;
+    } else {
+        if ((st = gemm_build(p, s))) return st;
+    }
 
     p->bytes_plan = 0;
     for (epic::DevBuf *b : {&p->d_pos, &p->d_freq, &p->d_table, &p->d_j0, &p->d_w, &p->d_selfcorr, &p->d_chan,
@@ -220,6 +225,9 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
                             &p->d_csr_ant, &p->d_csr_w, &p->d_twid, &p->d_sz_chans})
         p->bytes_plan += (int64_t)b->bytes;
     for (auto *g : p->groups) p->bytes_plan += (int64_t)(g->items.bytes + g->entries.bytes);
+    for (epic::DevBuf *b : {&p->gemm.a_hi, &p->gemm.a_lo, &p->gemm.vbuf, &p->gemm.d_blk_off,
+                            &p->gemm.d_scale, &p->gemm.d_inv_s2})
+        p->bytes_plan += (int64_t)b->bytes;
     return EPIC_OK;
 }
 
