@@ -81,10 +81,13 @@ def traffic_from_profile(kernel_src):
         return None
 
 
-def cpu_baseline(wl, pos, n_chan=2, n_time=250):
-    """The FP64 oracle on a bounded slice of the same workload."""
-    import numpy as np
+def cpu_baseline(wl, pos, target_s=12.0):
+    """The FP64 oracle on a bounded slice of the same workload.
 
+    A short probe (one channel, 50 samples) sets the slice so that the timed
+    run takes about ``target_s`` seconds: up to all 1000 samples of a channel,
+    then more channels spread over the band.
+    """
     import oracle as O
     import synth
     try:
@@ -92,20 +95,33 @@ def cpu_baseline(wl, pos, n_chan=2, n_time=250):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
-    chans = list(range(0, wl.n_chan, max(1, wl.n_chan // n_chan)))[:n_chan]
-    v = synth.voltages(wl.with_time(n_time), pos, chans=chans)
-    t0 = time.perf_counter()
-    for i, c in enumerate(chans):
-        r = O.channel_reference(v[:, i], pos, wl.chan_freq_hz[c], int(wl.grid_n[c]),
-                                cell_lambda=wl.cell_lambda, k=wl.kernel_k,
-                                sigma=wl.kernel_sigma_cells, aperture_n=wl.aperture_n)
-        O.readout(r["acc"], r["auto"], r["count"])
-    dt = time.perf_counter() - t0
-    samples = n_chan * n_time * wl.n_pol * wl.n_ant
+
+    def run(chans, n_time):
+        v = synth.voltages(wl.with_time(n_time), pos, chans=chans)
+        t0 = time.perf_counter()
+        for i, c in enumerate(chans):
+            r = O.channel_reference(v[:, i], pos, wl.chan_freq_hz[c], int(wl.grid_n[c]),
+                                    cell_lambda=wl.cell_lambda, k=wl.kernel_k,
+                                    sigma=wl.kernel_sigma_cells, aperture_n=wl.aperture_n)
+            O.readout(r["acc"], r["auto"], r["count"])
+        return time.perf_counter() - t0
+
+    per = wl.n_pol * wl.n_ant
+    probe = run([wl.n_chan // 2], 50)
+    rate = 50 * per / max(probe, 1e-6)
+    want = rate * target_s / per                    # (channel, sample) pairs
+    n_ch = int(min(wl.n_chan, max(1, round(want / wl.n_time))))
+    n_time = int(min(wl.n_time, max(50, want / n_ch)))
+    chans = [int(c) for c in
+             sorted(set(round(x) for x in
+                        [i * (wl.n_chan - 1) / max(1, n_ch - 1) for i in range(n_ch)]))]
+    dt = run(chans, n_time)
+    samples = len(chans) * n_time * per
     return {"value": samples / dt, "unit": "samples/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"{n_chan} channels x {n_time} samples x {wl.n_pol} pol x "
-                      f"{wl.n_ant} ant of the same workload ({dt:.1f} s, FP64 NumPy)"}
+            "sample": f"{len(chans)} channels x {n_time} samples x {wl.n_pol} pol x "
+                      f"{wl.n_ant} ant of the same workload ({dt:.1f} s, FP64 NumPy, "
+                      f"BLAS threads {threads})"}
 
 
 def main():
@@ -116,6 +132,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--staged", type=int, default=100,
                     help="samples of the staged FP32 path to time (0 = skip)")
+    ap.add_argument("--variants", type=int, default=1,
+                    help="also time the MFMA DFT-GEMM variants on the same step (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB for a plain device copy (counter calibration runs)")
     args = ap.parse_args()
@@ -254,6 +272,47 @@ def main():
                               "ms": ms, "speedup_of_fused": out["value"] / sv}
         log(f"staged FP32 path: {ms:.2f} ms for {Ts} samples -> {sv:.3e} samples/s")
         del g, s
+
+    if args.variants:
+        tol = json.load(open(os.path.join(ROOT, "tests", "tolerances.json")))
+        out["variants"] = {}
+        for name, prec, peak in (("bf16x2", E.EPIC_BF16X2_MFMA, 2500.0),
+                                 ("fp16", E.EPIC_F16_MFMA, 2500.0),
+                                 ("fp8e4m3", E.EPIC_F8E4M3_MFMA, 5000.0)):
+            t0 = time.perf_counter()
+            vplan = E.Plan.from_workload(wl, pos, precision=prec)
+            torch.cuda.synchronize()
+            tplan = time.perf_counter() - t0
+            vacc = E.Accumulator(vplan)
+            E.accumulate(vplan, vacc, volt=volt)            # warm-up
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 3
+            a.record(stream)
+            for _ in range(reps):
+                vacc.reset()
+                E.accumulate(vplan, vacc, volt=volt)
+                E.readout(vplan, vacc, img, E.REMOVE_AUTOS | E.NORMALISE)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            # executed MFMA flops: 2 M K N per channel, M = 2 N^2 rows, K = 2 Ap
+            ap = 16 * max(1, 2 ** math.ceil(math.log2(max(1, wl.n_ant) / 16)))
+            cols = wl.n_time * wl.n_pol
+            mflops = sum(2.0 * (2 * int(n) ** 2) * (2 * ap) * cols for n in wl.grid_n)
+            if prec == E.EPIC_BF16X2_MFMA:
+                mflops *= 2
+            tf = mflops / (ms / 1e3) / 1e12
+            out["variants"][name] = {
+                "value": samples / (ms / 1e3), "unit": "samples/s", "ms_per_step": ms,
+                "mfma_tflops": tf, "mfma_peak": peak, "mfma_frac": tf / peak,
+                "plan_s": tplan, "plan_bytes": vplan.info["bytes_plan"],
+                "max_err_bound": tol[name]["max"],
+                "speedup_vs_fp32": out["ms_per_step"] / ms}
+            log(f"{name}: {ms:.2f} ms/step, {tf:.0f} TFLOP/s MFMA ({tf / peak:.1%}), plan {tplan:.1f} s")
+            del vacc, vplan
+            torch.cuda.empty_cache()
+        out["variants"]["fp32_fft_max_err_bound"] = tol["fp32"]["max"]
 
     if args.copy_calib > 0:
         n = args.copy_calib * (1 << 20) // 4
