@@ -107,21 +107,71 @@ def cpu_baseline(wl, pos, target_s=12.0):
         return time.perf_counter() - t0
 
     per = wl.n_pol * wl.n_ant
-    probe = run([wl.n_chan // 2], 50)
-    rate = 50 * per / max(probe, 1e-6)
-    want = rate * target_s / per                    # (channel, sample) pairs
-    n_ch = int(min(wl.n_chan, max(1, round(want / wl.n_time))))
-    n_time = int(min(wl.n_time, max(50, want / n_ch)))
-    chans = [int(c) for c in
-             sorted(set(round(x) for x in
-                        [i * (wl.n_chan - 1) / max(1, n_ch - 1) for i in range(n_ch)]))]
+    chans, n_time = [wl.n_chan // 2], 50
     dt = run(chans, n_time)
+    for _ in range(4):
+        if dt >= 0.6 * target_s or (len(chans) == wl.n_chan and n_time == wl.n_time):
+            break
+        rate = len(chans) * n_time / max(dt, 1e-6)      # (channel, sample) pairs per s
+        want = rate * target_s
+        n_ch = int(min(wl.n_chan, max(1, round(want / wl.n_time))))
+        n_time = int(min(wl.n_time, max(50, want / n_ch)))
+        chans = [int(c) for c in
+                 sorted(set(round(x) for x in
+                            [i * (wl.n_chan - 1) / max(1, n_ch - 1) for i in range(n_ch)]))]
+        dt = run(chans, n_time)
     samples = len(chans) * n_time * per
     return {"value": samples / dt, "unit": "samples/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"{len(chans)} channels x {n_time} samples x {wl.n_pol} pol x "
                       f"{wl.n_ant} ant of the same workload ({dt:.1f} s, FP64 NumPy, "
                       f"BLAS threads {threads})"}
+
+
+def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8):
+    """Real-time streaming of LWA-like stations: blocks of ``tb`` samples
+    (1 ms at 25 kHz channels) arrive every ``period_s`` per stream; each
+    station has its own layout, plan, accumulator and device ring of blocks.
+    Returns block-latency statistics and the sustained sample rate."""
+    from dataclasses import replace
+
+    import numpy as np
+
+    import synth
+    from paper_2609_03027_amd.serve import DeviceExecutor, Server, StreamSpec
+    rings, specs = {}, []
+    for i in range(n_streams):
+        full = synth.workload("lwa")
+        wl = replace(full, seed=full.seed + 97 * i).with_time(tb)
+        pos = synth.antenna_layout(wl)
+        blocks = np.stack([synth.voltages(wl, pos, block=b) for b in range(ring)])
+        name = f"station{i}"
+        rings[name] = torch.from_numpy(blocks).cuda()
+        plan = E.Plan.from_workload(wl, pos)
+        specs.append(StreamSpec(name, plan, tb, period_s, n_blocks, 1000 // tb,
+                                deadline_s=period_s, ring=ring,
+                                bytes_needed=plan.info["bytes_acc"] + rings[name].numel()))
+    ex = DeviceExecutor(rings)
+    free, _ = torch.cuda.mem_get_info()
+    srv = Server(ex, budget_bytes=int(0.8 * free))
+    t0 = time.perf_counter()
+    for s in specs:
+        srv.submit_stream(s)
+    fin = srv.run(timeout_s=120.0)
+    wall = time.perf_counter() - t0
+    recs = [r for st in fin.values() for r in st.records]
+    st = Server.stats(recs)
+    lat = np.array([r.latency for r in recs if not r.dropped])
+    st["late"] = int(np.sum(lat > period_s))
+    st["streams"] = n_streams
+    st["block_samples"] = tb
+    st["period_ms"] = period_s * 1e3
+    kept = sum(not r.dropped for r in recs)
+    p0 = specs[0].plan
+    per_block = tb * p0.n_chan * p0.n_pol * p0.n_ant
+    st["sustained_samples_per_s"] = kept * per_block / wall
+    st["real_time_samples_per_s"] = n_streams * per_block / period_s
+    return st
 
 
 def main():
@@ -134,6 +184,8 @@ def main():
                     help="samples of the staged FP32 path to time (0 = skip)")
     ap.add_argument("--variants", type=int, default=1,
                     help="also time the MFMA DFT-GEMM variants on the same step (0 = skip)")
+    ap.add_argument("--stream-blocks", type=int, default=200,
+                    help="blocks per stream in the real-time streaming run (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB for a plain device copy (counter calibration runs)")
     args = ap.parse_args()
@@ -313,6 +365,16 @@ def main():
             del vacc, vplan
             torch.cuda.empty_cache()
         out["variants"]["fp32_fft_max_err_bound"] = tol["fp32"]["max"]
+
+    if args.stream_blocks > 0:
+        out["streaming"] = {}
+        for ns in (1, 4):
+            st = streaming(E, torch, ns, args.stream_blocks)
+            out["streaming"][str(ns)] = st
+            log(f"streaming x{ns}: p50 {st.get('p50_ms', float('nan')):.3f} ms, "
+                f"p99 {st.get('p99_ms', float('nan')):.3f} ms, dropped {st['dropped']}, "
+                f"late {st['late']} of {st['blocks']}")
+        out["p99_block_latency_ms"] = out["streaming"]["1"].get("p99_ms")
 
     if args.copy_calib > 0:
         n = args.copy_calib * (1 << 20) // 4

@@ -106,17 +106,24 @@ __global__ void k_readout(const float *__restrict__ acc, const double2 *__restri
     const int D = 2 * K - 1;
     constexpr int NH = P == 2 ? 3 : 1;
     const double2 *h = H + (size_t)c * NH * D * D;
-    // exp(+2 pi i m d / N) for each axis, argument reduced exactly mod N
+    // exp(+2 pi i (k - N/2) d / N) for d = -(K-1) .. K-1 on each axis: one
+    // exact base phase per axis (argument reduced mod N), then its powers
     double2 px[5], py[5];
-    for (int i = 0; i < D; ++i) {
-        const int dd = i - (K - 1);
-        const long mx = (((long)(kx - N / 2) * dd) % N + N) % N;
-        const long my = (((long)(ky - N / 2) * dd) % N + N) % N;
+    {
         double s, cs;
-        sincospi(2.0 * (double)mx / (double)N, &s, &cs);
-        px[i] = make_double2(cs, s);
-        sincospi(2.0 * (double)my / (double)N, &s, &cs);
-        py[i] = make_double2(cs, s);
+        sincospi(2.0 * (double)(((kx - N / 2) % N + N) % N) / (double)N, &s, &cs);
+        const double2 wx = make_double2(cs, s);
+        sincospi(2.0 * (double)(((ky - N / 2) % N + N) % N) / (double)N, &s, &cs);
+        const double2 wy = make_double2(cs, s);
+        const int c0 = K - 1;
+        px[c0] = py[c0] = make_double2(1.0, 0.0);
+        for (int m = 1; m < K; ++m) {
+            const double2 a = px[c0 + m - 1], b = py[c0 + m - 1];
+            px[c0 + m] = make_double2(a.x * wx.x - a.y * wx.y, a.x * wx.y + a.y * wx.x);
+            py[c0 + m] = make_double2(b.x * wy.x - b.y * wy.y, b.x * wy.y + b.y * wy.x);
+            px[c0 - m] = make_double2(px[c0 + m].x, -px[c0 + m].y);
+            py[c0 - m] = make_double2(py[c0 + m].x, -py[c0 + m].y);
+        }
     }
     double sxx = 0, syy = 0, sxr = 0, sxi = 0;
     for (int iy = 0; iy < D; ++iy)

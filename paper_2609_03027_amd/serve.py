@@ -1,0 +1,327 @@
+"""Streaming EPIC: continuous batching of voltage blocks from many streams.
+
+Blocks of a stream arrive on a clock (one block every ``period_s``).  Every
+admitted stream owns a device-resident accumulator and a ring of voltage
+blocks; the server keeps the Eq. 2 sums on the device across blocks and
+reads an image out after every ``blocks_per_integration`` blocks (Sec. 4:
+an output frame accumulates several processed frames).
+
+Admission is by HBM budget: a stream is admitted when its plan (unless
+already resident), accumulator and ring fit in the remaining budget, and
+waits in FIFO order otherwise; closing a stream frees its share.  Work is
+submitted as soon as a block has arrived, whatever else is in flight, on a
+queue of its own per stream, so blocks of different streams overlap on the
+device.  The kernels are deterministic (fixed reduction orders, no float
+atomics), so a stream's images do not depend on what else runs.
+
+Per block the server records arrival (the clock), submission and completion;
+latency = completion - arrival.  A block whose predecessor on the same
+stream has not yet been submitted when the ring is full is dropped (counted,
+and excluded from the sample count); a block completing after
+``deadline_s`` is counted late.
+
+Two executors: ``DeviceExecutor`` drives libepic through the C ABI on HIP
+streams; ``FakeExecutor`` models completion times on a virtual clock so the
+policy can be tested without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class StreamSpec:
+    """One incoming stream: an array/channel plan and its block cadence."""
+    name: str
+    plan: object                   # paper_2609_03027_amd.Plan (or a stand-in)
+    block_samples: int
+    period_s: float
+    n_blocks: int
+    blocks_per_integration: int
+    deadline_s: float = 1e-3
+    ring: int = 8
+    bytes_needed: int = 0          # accumulator + ring (plan counted separately)
+
+
+@dataclasses.dataclass
+class BlockRecord:
+    stream: str
+    index: int
+    arrival: float
+    submit: float = math.nan
+    done: float = math.nan
+    dropped: bool = False
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+class _Active:
+    def __init__(self, spec, handle, admit_time):
+        self.spec = spec
+        self.handle = handle
+        self.t0 = admit_time          # arrival clock of block 0
+        self.next_block = 0           # next block to consider
+        self.inflight = collections.deque()
+        self.records = []
+        self.images = []
+        self.blocks_in_integration = 0
+        self.samples_in_integration = 0
+
+
+class Server:
+    """Admission, continuous batching and latency accounting."""
+
+    def __init__(self, executor, budget_bytes: int):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.used = 0
+        self.plans_resident = {}      # id(plan) -> [bytes, users]
+        self.pending = collections.deque()
+        self.active = {}
+        self.finished = {}
+        self.refused = []
+
+    # ------------------------------------------------------------ admission
+    def _cost(self, spec):
+        pb = 0 if id(spec.plan) in self.plans_resident else self.ex.plan_bytes(spec.plan)
+        return pb + spec.bytes_needed
+
+    def submit_stream(self, spec: StreamSpec):
+        """Queue a stream for admission (FIFO).  Streams that could never fit
+        the budget are refused outright."""
+        if self.ex.plan_bytes(spec.plan) + spec.bytes_needed > self.budget:
+            self.refused.append(spec.name)
+            return False
+        self.pending.append(spec)
+        self._admit(self.ex.now())
+        return True
+
+    def _admit(self, now):
+        while self.pending:
+            spec = self.pending[0]
+            cost = self._cost(spec)
+            if self.used + cost > self.budget:
+                return
+            self.pending.popleft()
+            self.used += cost
+            pr = self.plans_resident.setdefault(id(spec.plan), [cost - spec.bytes_needed, 0])
+            pr[1] += 1
+            handle = self.ex.open(spec)
+            self.active[spec.name] = _Active(spec, handle, now)
+
+    def _close(self, st, now):
+        spec = st.spec
+        self.ex.close(st.handle)
+        self.used -= spec.bytes_needed
+        pr = self.plans_resident[id(spec.plan)]
+        pr[1] -= 1
+        if pr[1] == 0:
+            self.used -= pr[0]
+            del self.plans_resident[id(spec.plan)]
+        self.finished[spec.name] = st
+        del self.active[spec.name]
+        self._admit(now)
+
+    # ----------------------------------------------------------- scheduling
+    def step(self):
+        """One scheduling pass: retire finished work, submit arrived blocks."""
+        now = self.ex.now()
+        for name in list(self.active):
+            st = self.active[name]
+            spec = st.spec
+            # completions in order
+            while st.inflight and self.ex.done(st.inflight[0][1]):
+                rec, tok = st.inflight.popleft()
+                rec.done = self.ex.finish_time(tok)
+            # arrivals
+            while st.next_block < spec.n_blocks:
+                arr = st.t0 + st.next_block * spec.period_s
+                if arr > now:
+                    break
+                rec = BlockRecord(spec.name, st.next_block, arr)
+                st.records.append(rec)
+                st.next_block += 1
+                if len(st.inflight) >= spec.ring:
+                    rec.dropped = True          # ring full: this block is lost
+                else:
+                    rec.submit = now
+                    tok = self.ex.accumulate(st.handle, rec.index)
+                    st.inflight.append((rec, tok))
+                    st.samples_in_integration += spec.block_samples
+                st.blocks_in_integration += 1
+                if st.blocks_in_integration == spec.blocks_per_integration:
+                    st.images.append((st.samples_in_integration,
+                                      self.ex.readout(st.handle)))
+                    st.blocks_in_integration = 0
+                    st.samples_in_integration = 0
+            if st.next_block >= spec.n_blocks and not st.inflight:
+                self._close(st, now)
+        if self.pending:
+            self._admit(now)
+
+    def run(self, timeout_s=60.0, poll_s=5e-5):
+        import gc
+        was = gc.isenabled()
+        gc.disable()              # no collector pauses inside the real-time loop
+        try:
+            t_end = self.ex.now() + timeout_s
+            while (self.active or self.pending) and self.ex.now() < t_end:
+                self.step()
+                self.ex.idle(poll_s)
+            self.ex.sync()
+        finally:
+            if was:
+                gc.enable()
+        return self.finished
+
+    # ---------------------------------------------------------------- stats
+    @staticmethod
+    def stats(records):
+        lat = np.array([r.latency for r in records if not r.dropped and np.isfinite(r.done)])
+        out = {"blocks": len(records), "dropped": int(sum(r.dropped for r in records))}
+        if len(lat):
+            out.update(p50_ms=float(np.percentile(lat, 50) * 1e3),
+                       p99_ms=float(np.percentile(lat, 99) * 1e3),
+                       max_ms=float(lat.max() * 1e3))
+        return out
+
+
+# ---------------------------------------------------------------- executors
+class FakeExecutor:
+    """Virtual clock; a block takes ``cost_s`` of device time and at most
+    ``lanes`` blocks run at once (first come, first served)."""
+
+    def __init__(self, cost_s=2e-4, lanes=2, plan_bytes=1000):
+        self.t = 0.0
+        self.cost = cost_s
+        self.lanes = [0.0] * lanes
+        self._plan_bytes = plan_bytes
+        self.opened = []
+        self.closed = []
+        self.n_accum = collections.Counter()
+
+    def now(self):
+        return self.t
+
+    def idle(self, dt):
+        self.t += dt
+
+    def sync(self):
+        pass
+
+    def plan_bytes(self, plan):
+        return self._plan_bytes
+
+    def open(self, spec):
+        self.opened.append(spec.name)
+        return spec.name
+
+    def close(self, h):
+        self.closed.append(h)
+
+    def accumulate(self, h, block):
+        i = int(np.argmin(self.lanes))
+        start = max(self.t, self.lanes[i])
+        self.lanes[i] = start + self.cost
+        self.n_accum[h] += 1
+        return self.lanes[i]
+
+    def done(self, tok):
+        return tok <= self.t
+
+    def finish_time(self, tok):
+        return tok
+
+    def readout(self, h):
+        return None
+
+
+class DeviceExecutor:
+    """Runs blocks through libepic on one HIP stream per admitted stream.
+
+    ``rings[name]`` is a device tensor ``uint8 [R][T_b][C][P][A]`` of voltage
+    blocks already in HBM (the device-resident producer); block i of the
+    stream reads ring slot i % R.
+    """
+
+    def __init__(self, rings):
+        import torch
+        self.torch = torch
+        self.rings = rings
+        self.ref = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        self.ref.record()
+        torch.cuda.synchronize()
+        self.host0 = time.perf_counter()
+
+    def now(self):
+        return time.perf_counter() - self.host0
+
+    def idle(self, dt):
+        t = time.perf_counter() + dt
+        while time.perf_counter() < t:
+            pass
+
+    def sync(self):
+        self.torch.cuda.synchronize()
+
+    def plan_bytes(self, plan):
+        return int(plan.info["bytes_plan"])
+
+    def open(self, spec):
+        import paper_2609_03027_amd as E
+        torch = self.torch
+        s = torch.cuda.Stream()
+        acc = E.Accumulator(spec.plan)
+        img = torch.empty(spec.plan.info["image_floats"], dtype=torch.float32, device="cuda")
+        # pinned host images, allocated up front (pinned allocation is slow)
+        n_int = max(1, spec.n_blocks // max(1, spec.blocks_per_integration))
+        host = [torch.empty(img.shape, dtype=torch.float32, pin_memory=True)
+                for _ in range(n_int)]
+        return {"spec": spec, "stream": s, "acc": acc, "img": img, "host": host, "n_out": 0,
+                "ring": self.rings[spec.name]}
+
+    def close(self, h):
+        h["stream"].synchronize()
+        h["acc"].close()
+
+    def accumulate(self, h, block):
+        import paper_2609_03027_amd as E
+        torch = self.torch
+        ring = h["ring"]
+        with torch.cuda.stream(h["stream"]):
+            E.accumulate(h["spec"].plan, h["acc"], volt=ring[block % ring.shape[0]],
+                         stream=h["stream"])
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(h["stream"])
+        return ev
+
+    def done(self, ev):
+        return ev.query()
+
+    def finish_time(self, ev):
+        return self.ref.elapsed_time(ev) / 1e3
+
+    def readout(self, h):
+        """Read-out on the stream's own queue into pinned host memory; the
+        copy completes asynchronously (valid after ``sync``)."""
+        import paper_2609_03027_amd as E
+        torch = self.torch
+        if h["n_out"] < len(h["host"]):
+            out = h["host"][h["n_out"]]
+        else:
+            out = torch.empty(h["img"].shape, dtype=torch.float32, pin_memory=True)
+        h["n_out"] += 1
+        with torch.cuda.stream(h["stream"]):
+            E.readout(h["spec"].plan, h["acc"], h["img"], E.REMOVE_AUTOS | E.NORMALISE,
+                      stream=h["stream"])
+            out.copy_(h["img"], non_blocking=True)
+            h["acc"].reset(stream=h["stream"])
+        return out
