@@ -174,6 +174,58 @@ def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8):
     return st
 
 
+def batched(E, torch, reps=5):
+    """SKA-station-like uneven batch: 384 channels over 50-350 MHz with grid
+    sides 32..192, 512 samples per integration, all in one graph launch.
+    Eager launches vs the graph, default vs autotuned sub-transform tiles."""
+    import numpy as np
+
+    import synth
+    from paper_2609_03027_amd import autotune
+    wl = synth.workload("ska")
+    pos = synth.antenna_layout(wl)
+    t0 = time.perf_counter()
+    volt = torch.from_numpy(synth.voltages(wl, pos)).cuda()
+    log(f"ska voltages: {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    res = {"workload": "ska-batch: 256 dual-pol elements in a 38 m disc, 384 channels "
+                       "50-350 MHz, grid sides {32:2, 48:40, 64:40, 96:81, 128:81, 192:140}, "
+                       "512 samples"}
+    samples = wl.samples_per_block()
+    t0 = time.perf_counter()
+    sub, report = autotune.tune(pos, wl.chan_freq_hz, wl.grid_n, wl.n_pol,
+                                aperture_n=wl.aperture_n, use_cache=False)
+    res["autotune_s"] = time.perf_counter() - t0
+    res["autotune_choice"] = {str(n): int(m) for n, m in
+                              sorted(set(zip(wl.grid_n.tolist(), sub.tolist())))}
+    res["autotune_ms"] = {str(k): v for k, v in report.items()}
+    for label, kw in (("default", {}), ("autotuned", {"sub_n": sub})):
+        plan = E.Plan.from_workload(wl, pos, **kw)
+        acc = E.Accumulator(plan)
+        ms_eager = timed(lambda: E.accumulate(plan, acc, volt=volt))
+        g = E.Graph(plan, acc, volt)
+        ms_graph = timed(lambda: g.launch())
+        g.close()
+        res[label] = {"eager_ms": ms_eager, "graph_ms": ms_graph,
+                      "value": samples / (min(ms_eager, ms_graph) / 1e3), "unit": "samples/s"}
+        log(f"ska {label}: eager {ms_eager:.2f} ms, graph {ms_graph:.2f} ms per integration")
+        acc.close()
+        plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +236,8 @@ def main():
                     help="samples of the staged FP32 path to time (0 = skip)")
     ap.add_argument("--variants", type=int, default=1,
                     help="also time the MFMA DFT-GEMM variants on the same step (0 = skip)")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="also time the uneven SKA-like batch (0 = skip)")
     ap.add_argument("--stream-blocks", type=int, default=200,
                     help="blocks per stream in the real-time streaming run (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -365,6 +419,9 @@ def main():
             del vacc, vplan
             torch.cuda.empty_cache()
         out["variants"]["fp32_fft_max_err_bound"] = tol["fp32"]["max"]
+
+    if args.batched:
+        out["batched"] = batched(E, torch)
 
     if args.stream_blocks > 0:
         out["streaming"] = {}

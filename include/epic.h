@@ -89,10 +89,15 @@ typedef struct {
                                     support cells [dy][dx] (replaces the Gaussian); copied */
     int32_t precision;           /* epic_precision */
     uint32_t flags;              /* EPIC_PLAN_DEFAULT */
+    const int32_t *sub_n;        /* optional host [C]: side M of the sub-transforms the
+                                    FP32 fused path splits channel c into (16, 32 or 64,
+                                    dividing grid_n[c], at most 8 per axis); 0 or NULL =
+                                    the largest that divides grid_n[c] */
 } epic_plan_desc;
 
 typedef struct epic_plan_s *epic_plan;  /* opaque; owns device tables */
 typedef struct epic_acc_s *epic_acc;    /* opaque; float acc + int32 autos + count */
+typedef struct epic_graph_s *epic_graph; /* opaque; an instantiated HIP graph */
 
 typedef struct {
     int64_t image_floats;       /* sum_c n_prod N_c^2: floats in one image set */
@@ -154,6 +159,21 @@ epic_status epic_accumulate(epic_plan plan, epic_acc acc, const uint8_t *d_volt,
  * over footprint displacements d. */
 epic_status epic_readout(epic_plan plan, epic_acc acc, float *d_img, uint32_t flags,
                          void *hip_stream);
+
+/* Batching (Sec. 3: many channels processed by parallel cores; Sec. 4: an
+ * output frame accumulates several processed frames).  Captures one
+ * epic_accumulate(plan, acc, d_volt, NULL, n_time) -- every channel and
+ * every sample, the launches for different sub-transform sizes on parallel
+ * branches -- into a HIP graph instantiated for replay.  d_volt and acc are
+ * baked into the graph: each epic_graph_launch adds the same n_time samples
+ * of the same buffer (refill it between launches) and advances the count.
+ * The graph holds no memset nodes.  Capture happens on an internal stream;
+ * hip_stream is only synchronised.  A graph must be destroyed before its plan
+ * or accumulator. */
+epic_status epic_graph_create(epic_plan plan, epic_acc acc, const uint8_t *d_volt,
+                              int32_t n_time, void *hip_stream, epic_graph *out);
+epic_status epic_graph_launch(epic_graph graph, void *hip_stream);
+epic_status epic_graph_destroy(epic_graph graph);
 
 const char *epic_status_str(epic_status s);
 const char *epic_last_error(void);

@@ -29,7 +29,7 @@ EXPORTS = [
     "epic_acc_create", "epic_acc_reset", "epic_acc_destroy", "epic_acc_count",
     "epic_acc_export", "epic_acc_import", "epic_grid", "epic_image",
     "epic_accumulate", "epic_readout", "epic_status_str", "epic_last_error",
-    "epic_version",
+    "epic_version", "epic_graph_create", "epic_graph_launch", "epic_graph_destroy",
 ]
 
 
@@ -52,6 +52,7 @@ class PlanDesc(C.Structure):
         ("kernel_table", C.POINTER(C.c_float)),
         ("precision", C.c_int32),
         ("flags", C.c_uint32),
+        ("sub_n", C.POINTER(C.c_int32)),
     ]
 
 
@@ -90,6 +91,9 @@ def load() -> C.CDLL:
         "epic_image": [vp, vp, i32, vp, vp],
         "epic_accumulate": [vp, vp, vp, vp, i32, vp],
         "epic_readout": [vp, vp, vp, u32, vp],
+        "epic_graph_create": [vp, vp, vp, i32, vp, C.POINTER(vp)],
+        "epic_graph_launch": [vp, vp],
+        "epic_graph_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -130,7 +134,7 @@ class Plan:
 
     def __init__(self, pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5,
                  kernel_k=3, kernel_sigma=0.5, kernel_table=None, precision=EPIC_F32,
-                 stream=None):
+                 sub_n=None, stream=None):
         lib = load()
         self._pos = np.ascontiguousarray(pos, dtype=np.float64)
         self._freq = np.ascontiguousarray(freq_hz, dtype=np.float64)
@@ -152,6 +156,8 @@ class Plan:
                           self._table.ctypes.data_as(C.POINTER(C.c_float)))
         d.precision = int(precision)
         d.flags = 0
+        self._sub = None if sub_n is None else np.ascontiguousarray(sub_n, dtype=np.int32)
+        d.sub_n = None if self._sub is None else self._sub.ctypes.data_as(C.POINTER(C.c_int32))
         h = C.c_void_p()
         check(lib.epic_plan_create(C.byref(d), _stream(stream), C.byref(h)))
         self.handle = h
@@ -227,6 +233,33 @@ class Accumulator:
     def close(self):
         if getattr(self, "handle", None):
             check(load().epic_acc_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """One accumulate call (all channels, all samples of ``volt``) captured as
+    a HIP graph; each ``launch`` replays it on the given stream."""
+
+    def __init__(self, plan: Plan, acc: Accumulator, volt, n_time=None, stream=None):
+        n_time = volt.shape[0] if n_time is None else n_time
+        h = C.c_void_p()
+        check(load().epic_graph_create(plan.handle, acc.handle, _ptr(volt), int(n_time),
+                                       _stream(stream), C.byref(h)))
+        self.handle = h
+        self._keep = (plan, acc, volt)
+
+    def launch(self, stream=None):
+        check(load().epic_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(load().epic_graph_destroy(self.handle))
             self.handle = None
 
     def __del__(self):

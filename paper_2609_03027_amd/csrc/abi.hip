@@ -86,6 +86,14 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     for (int c = 0; c < d->n_chan; ++c)
         if (d->grid_n[c] < 8 || (d->grid_n[c] & 1))
             return fail(EPIC_ERR_GRID, "grid sides must be even and >= 8");
+    if (d->sub_n)
+        for (int c = 0; c < d->n_chan; ++c) {
+            const int m = d->sub_n[c];
+            if (m == 0) continue;
+            if ((m != 16 && m != 32 && m != 64) || d->grid_n[c] % m || d->grid_n[c] / m > 8)
+                return fail(EPIC_ERR_ARG, "sub_n must be 0, 16, 32 or 64, divide grid_n and "
+                                          "leave at most 8 sub-transforms per axis");
+        }
 
     auto *p = new epic_plan_s();
     p->A = d->n_ant;
@@ -101,6 +109,7 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     p->pos.assign(d->ant_pos_m, d->ant_pos_m + 2 * p->A);
     p->freq.assign(d->chan_freq_hz, d->chan_freq_hz + p->C);
     p->grid_n.assign(d->grid_n, d->grid_n + p->C);
+    if (d->sub_n) p->sub_n.assign(d->sub_n, d->sub_n + p->C);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     epic_status st = EPIC_OK;
     if (d->kernel_table) {
@@ -260,6 +269,89 @@ epic_status epic_accumulate(epic_plan p, epic_acc a, const uint8_t *d_volt, cons
     if (!st) a->count += n_time;
     return st;
     EPIC_GUARD_END
+}
+
+epic_status epic_graph_create(epic_plan p, epic_acc a, const uint8_t *d_volt, int32_t n_time,
+                              void *hip_stream, epic_graph *out) {
+    EPIC_GUARD_BEGIN
+    if (!out) return fail(EPIC_ERR_NULL, "out is NULL");
+    *out = nullptr;
+    if (!p || !a || !d_volt) return fail(EPIC_ERR_NULL, "plan, acc and volt are required");
+    if (a->plan != p) return fail(EPIC_ERR_MISMATCH, "accumulator belongs to another plan");
+    if (n_time < 1) return fail(EPIC_ERR_ARG, "n_time must be >= 1");
+    EPIC_HIP(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+    epic_status st = EPIC_OK;
+    if (p->precision == EPIC_F32) st = fused_accumulate(p, a, d_volt, n_time, nullptr, nullptr, true);
+    if (st) return st;
+
+    hipStream_t cs = nullptr;
+    std::vector<hipStream_t> br(p->groups.size(), nullptr);
+    std::vector<hipEvent_t> ev(p->groups.size() + 1, nullptr);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto cleanup = [&]() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto b : br)
+            if (b) (void)hipStreamDestroy(b);
+        if (cs) (void)hipStreamDestroy(cs);
+    };
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    for (size_t i = 0; e == hipSuccess && i < br.size(); ++i)
+        e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+    for (size_t i = 0; e == hipSuccess && i < ev.size(); ++i)
+        e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "graph capture setup");
+    }
+    // fork: every size group on its own branch, joined back into cs
+    e = hipEventRecord(ev[0], cs);
+    for (size_t i = 0; e == hipSuccess && i < br.size(); ++i) e = hipStreamWaitEvent(br[i], ev[0], 0);
+    if (e == hipSuccess) {
+        if (p->precision == EPIC_F32)
+            st = fused_accumulate(p, a, d_volt, n_time, cs, &br, false);
+        else
+            st = gemm_accumulate(p, a, d_volt, n_time, cs);
+    }
+    for (size_t i = 0; e == hipSuccess && !st && i < br.size(); ++i) {
+        e = hipEventRecord(ev[i + 1], br[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev[i + 1], 0);
+    }
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess && !st) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    cleanup();
+    if (st || e != hipSuccess) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        return st ? st : hip_fail(e, "graph capture");
+    }
+    auto *g = new epic_graph_s();
+    g->plan = p;
+    g->acc = a;
+    g->n_time = n_time;
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return EPIC_OK;
+    EPIC_GUARD_END
+}
+
+epic_status epic_graph_launch(epic_graph g, void *hip_stream) {
+    if (!g) return fail(EPIC_ERR_NULL, "graph is NULL");
+    EPIC_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(hip_stream)));
+    g->acc->count += g->n_time;
+    return EPIC_OK;
+}
+
+epic_status epic_graph_destroy(epic_graph g) {
+    if (!g) return fail(EPIC_ERR_NULL, "graph is NULL");
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return EPIC_OK;
 }
 
 epic_status epic_readout(epic_plan p, epic_acc a, float *d_img, uint32_t flags, void *hip_stream) {

@@ -518,12 +518,13 @@ static epic_status lds_ready(const void *kern, size_t lds) {
 
 template <int M, int P, int AR>
 static epic_status launch_fused_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                   int A, int n_time, float *acc, int32_t *autos, hipStream_t s) {
+                                   int A, int n_time, float *acc, int32_t *autos, hipStream_t s,
+                                   bool dry) {
     constexpr int T = FCfg<M>::T, GSZ = M * FCfg<M>::ROW;
     const size_t lds = sizeof(float2) * P * GSZ + sizeof(float4) * (size_t)A;
     auto kern = k_fused<M, P, AR>;
     epic_status st = lds_ready(reinterpret_cast<const void *>(kern), lds);
-    if (st) return st;
+    if (st || dry) return st;
     hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(T), lds, s, g->items.as<FusedItem>(),
                        g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos);
     EPIC_HIP(hipGetLastError());
@@ -534,38 +535,46 @@ static epic_status launch_fused_ar(const FusedGroup *g, const uint8_t *d_volt, i
 // separate pass (autos == nullptr).
 template <int M, int P>
 static epic_status launch_fused(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                int A, int n_time, float *acc, int32_t *autos, hipStream_t s) {
+                                int A, int n_time, float *acc, int32_t *autos, hipStream_t s,
+                                bool dry) {
     constexpr int T = FCfg<M>::T;
-    if (A <= T) return launch_fused_ar<M, P, 1>(g, d_volt, vstride, A, n_time, acc, autos, s);
-    if (A <= 2 * T) return launch_fused_ar<M, P, 2>(g, d_volt, vstride, A, n_time, acc, autos, s);
-    return launch_fused_ar<M, P, 4>(g, d_volt, vstride, A, n_time, acc, autos, s);
+    if (A <= T) return launch_fused_ar<M, P, 1>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
+    if (A <= 2 * T)
+        return launch_fused_ar<M, P, 2>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
+    return launch_fused_ar<M, P, 4>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
 }
 
+// Launches every size group; group i goes to branches[i] when given (graph
+// capture with parallel branches), else to s.  dry: only set up the kernels'
+// LDS allowance (done before a capture).
 epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
-                             hipStream_t s) {
+                             hipStream_t s, const std::vector<hipStream_t> *branches, bool dry) {
     const int64_t vstride = (int64_t)p->C * p->P * p->A;
-    float *a = acc->d_acc.as<float>();
+    float *a = acc ? acc->d_acc.as<float>() : nullptr;
     // The fused kernels add the self-term sums when every group's threads
     // cover the elements in at most four rounds; otherwise a separate pass.
     bool in_kernel = true;
     for (const FusedGroup *g : p->groups)
         if (p->A > 4 * threads_of(g->M)) in_kernel = false;
-    int32_t *au = in_kernel ? acc->d_autos.as<int32_t>() : nullptr;
-    for (const FusedGroup *g : p->groups) {
+    int32_t *au = (in_kernel && acc) ? acc->d_autos.as<int32_t>() : nullptr;
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        const FusedGroup *g = p->groups[gi];
+        const hipStream_t gs = branches ? (*branches)[gi] : s;
         epic_status st = EPIC_OK;
         const int A = p->A;
         if (p->P == 2) {
-            if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, A, n_time, a, au, s);
-            if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, A, n_time, a, au, s);
-            if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, A, n_time, a, au, s);
+            if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
+            if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
+            if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
         } else {
-            if (g->M == 64) st = launch_fused<64, 1>(g, d_volt, vstride, A, n_time, a, au, s);
-            if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, A, n_time, a, au, s);
-            if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, A, n_time, a, au, s);
+            if (g->M == 64) st = launch_fused<64, 1>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
+            if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
+            if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
         }
         if (st) return st;
     }
-    return in_kernel ? EPIC_OK : autos_accumulate(p, acc, d_volt, n_time, s);
+    if (dry || in_kernel) return EPIC_OK;
+    return autos_accumulate(p, acc, d_volt, n_time, s);
 }
 
 epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,

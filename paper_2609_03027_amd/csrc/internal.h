@@ -112,6 +112,7 @@ struct epic_plan_s {
     int64_t grid_elems_per_t = 0;
     std::vector<double> pos, freq;
     std::vector<int> grid_n;
+    std::vector<int> sub_n;       // requested sub-transform side per channel (0 = auto)
     std::vector<double> w_host;   // kernel weights as computed on the device
     std::vector<epic::Chan> ch;
     bool has_table = false;
@@ -147,6 +148,14 @@ struct epic_plan_s {
     ~epic_plan_s();
 };
 
+struct epic_graph_s {
+    epic_plan plan = nullptr;
+    epic_acc acc = nullptr;
+    int n_time = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct epic_acc_s {
     epic_plan plan = nullptr;
     epic::DevBuf d_acc;    // float [image_floats]
@@ -164,7 +173,8 @@ epic_status plan_build(epic_plan p, hipStream_t s);
 epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
                         hipStream_t s);
 epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
-                             hipStream_t s);
+                             hipStream_t s, const std::vector<hipStream_t> *branches = nullptr,
+                             bool dry = false);
 epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                              hipStream_t s);
 

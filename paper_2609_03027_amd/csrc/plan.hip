@@ -65,7 +65,8 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     p->max_n = 0;
     for (int c = 0; c < C; ++c) {
         const int N = p->grid_n[c];
-        const int M = pick_m(N);
+        const int want = p->sub_n.empty() ? 0 : p->sub_n[c];
+        const int M = want ? want : pick_m(N);
         if (N < 8 || (N & 1)) return fail(EPIC_ERR_GRID, "grid side must be even and >= 8");
         if (M == 0) return fail(EPIC_ERR_GRID, "grid side must be a multiple of 16");
         if (N > 1024) return fail(EPIC_ERR_UNSUPPORTED, "grid side above 1024");

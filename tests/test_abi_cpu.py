@@ -85,6 +85,27 @@ def test_plan_create_rejects_null_and_odd_grid():
     assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 2
 
 
+@pytest.mark.parametrize("sub", [24, 8, 64])
+def test_plan_create_rejects_bad_sub_transform_sides(sub):
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    s = np.array([sub], dtype=np.int32)          # grid side 32: 64 does not divide it
+    d, keep = _desc(sub_n=s.ctypes.data_as(C.POINTER(C.c_int32)))
+    h = C.c_void_p()
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 2
+    assert b"sub_n" in lib.epic_last_error()
+
+
+def test_graph_calls_reject_null_handles():
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    h = C.c_void_p()
+    assert lib.epic_graph_create(None, None, None, 1, None, C.byref(h)) == 1
+    assert lib.epic_graph_create(None, None, None, 1, None, None) == 1
+    assert lib.epic_graph_launch(None, None) == 1
+    assert lib.epic_graph_destroy(None) == 1
+
+
 def test_data_calls_reject_null_handles():
     import paper_2609_03027_amd as E
     lib = E.load()
