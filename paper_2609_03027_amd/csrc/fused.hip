@@ -67,39 +67,55 @@ template <> __device__ __forceinline__ void dft<8>(float2 *v) {
     }
 }
 
+// Grid storage in LDS: with two feeds each element is a float4 (X re, X im,
+// Y re, Y im), so one 16-byte access serves both feeds; one feed is float2.
+template <int P> struct Grid;
+template <> struct Grid<2> {
+    float4 *g;
+    __device__ __forceinline__ void load(int i, float2 &x, float2 &y) const {
+        const float4 v = g[i];
+        x = make_float2(v.x, v.y);
+        y = make_float2(v.z, v.w);
+    }
+    __device__ __forceinline__ void store(int i, float2 x, float2 y) const {
+        g[i] = make_float4(x.x, x.y, y.x, y.y);
+    }
+    __device__ __forceinline__ void zero(int i) const { g[i] = make_float4(0.f, 0.f, 0.f, 0.f); }
+};
+template <> struct Grid<1> {
+    float2 *g;
+    __device__ __forceinline__ void load(int i, float2 &x, float2 &) const { x = g[i]; }
+    __device__ __forceinline__ void store(int i, float2 x, float2) const { g[i] = x; }
+    __device__ __forceinline__ void zero(int i) const { g[i] = make_float2(0.f, 0.f); }
+};
+
 // ------------------------------------------------------------ DIF passes
 // In-place decimation-in-frequency over one axis of an M x M grid stored
 // with row pitch ROW.  Pass A (radix RA, stride M/RA) multiplies output p by
 // exp(+2 pi i p j / M); pass B (radix RB, stride 1) has unit twiddles.  After
 // both passes position n of the axis holds frequency n / RB + RA (n % RB).
-template <int M, int NG, bool ALONG_X>
-__device__ __forceinline__ void pass_a(float2 *g0, float2 *g1, int tid, const float2 *tw) {
+template <int M, int P, bool ALONG_X>
+__device__ __forceinline__ void pass_a(Grid<P> g, int tid, const float2 *tw) {
     constexpr int RA = FCfg<M>::RA, ROW = FCfg<M>::ROW, S = M / RA;
     const int line = tid % M, j = tid / M;
     const int base = ALONG_X ? line * ROW + j : j * ROW + line;
     constexpr int step = ALONG_X ? S : S * ROW;
     float2 v0[RA], v1[RA];
 #pragma unroll
-    for (int q = 0; q < RA; ++q) {
-        v0[q] = g0[base + q * step];
-        if (NG == 2) v1[q] = g1[base + q * step];
-    }
+    for (int q = 0; q < RA; ++q) g.load(base + q * step, v0[q], v1[q]);
     dft<RA>(v0);
-    if (NG == 2) dft<RA>(v1);
+    if (P == 2) dft<RA>(v1);
 #pragma unroll
     for (int p = 1; p < RA; ++p) {
         v0[p] = cmul(v0[p], tw[p]);
-        if (NG == 2) v1[p] = cmul(v1[p], tw[p]);
+        if (P == 2) v1[p] = cmul(v1[p], tw[p]);
     }
 #pragma unroll
-    for (int q = 0; q < RA; ++q) {
-        g0[base + q * step] = v0[q];
-        if (NG == 2) g1[base + q * step] = v1[q];
-    }
+    for (int q = 0; q < RA; ++q) g.store(base + q * step, v0[q], v1[q]);
 }
 
-template <int M, int NG, bool ALONG_X>
-__device__ __forceinline__ void pass_b(float2 *g0, float2 *g1, int tid) {
+template <int M, int P, bool ALONG_X>
+__device__ __forceinline__ void pass_b(Grid<P> g, int tid) {
     constexpr int T = FCfg<M>::T, RB = FCfg<M>::RB, ROW = FCfg<M>::ROW;
     constexpr int NB = M * M / (RB * T);
 #pragma unroll
@@ -110,17 +126,11 @@ __device__ __forceinline__ void pass_b(float2 *g0, float2 *g1, int tid) {
         constexpr int step = ALONG_X ? 1 : ROW;
         float2 v0[RB], v1[RB];
 #pragma unroll
-        for (int q = 0; q < RB; ++q) {
-            v0[q] = g0[base + q * step];
-            if (NG == 2) v1[q] = g1[base + q * step];
-        }
+        for (int q = 0; q < RB; ++q) g.load(base + q * step, v0[q], v1[q]);
         dft<RB>(v0);
-        if (NG == 2) dft<RB>(v1);
+        if (P == 2) dft<RB>(v1);
 #pragma unroll
-        for (int q = 0; q < RB; ++q) {
-            g0[base + q * step] = v0[q];
-            if (NG == 2) g1[base + q * step] = v1[q];
-        }
+        for (int q = 0; q < RB; ++q) g.store(base + q * step, v0[q], v1[q]);
     }
 }
 
@@ -147,9 +157,9 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
     constexpr int NPROD = P == 2 ? 4 : 1;
     constexpr int GSZ = M * ROW;
     extern __shared__ float4 smem[];
-    float2 *gx = reinterpret_cast<float2 *>(smem);
-    float2 *gy = gx + GSZ;
-    float4 *stage = reinterpret_cast<float4 *>(gx + P * GSZ);
+    Grid<P> grid;
+    grid.g = reinterpret_cast<decltype(grid.g)>(smem);
+    float4 *stage = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) + P * GSZ);
 
     const FusedItem it = items[blockIdx.x];
     if (it.c < 0) return;
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
             tw[p] = make_float2(c, s);
         }
     }
-    for (int i = tid; i < P * GSZ; i += T) gx[i] = make_float2(0.f, 0.f);
+    for (int i = tid; i < GSZ; i += T) grid.zero(i);
 
     float av[NPIX][NPROD];
 #pragma unroll
@@ -231,21 +241,20 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
                 sy.y += wr * v.w + wi * v.z;
             }
             if (e.x >> 31) {
-                gx[e.y] = sx;
-                if (P == 2) gy[e.y] = sy;
+                grid.store(e.y, sx, sy);
                 sx = make_float2(0.f, 0.f);
                 sy = make_float2(0.f, 0.f);
             }
         }
         __syncthreads();
 
-        pass_a<M, P, true>(gx, gy, tid, tw);
+        pass_a<M, P, true>(grid, tid, tw);
         __syncthreads();
-        pass_b<M, P, true>(gx, gy, tid);
+        pass_b<M, P, true>(grid, tid);
         __syncthreads();
-        pass_a<M, P, false>(gx, gy, tid, tw);
+        pass_a<M, P, false>(grid, tid, tw);
         __syncthreads();
-        pass_b<M, P, false>(gx, gy, tid);
+        pass_b<M, P, false>(grid, tid);
         __syncthreads();
 
         // Eq. 2 products into this thread's pixels; leave the grid zeroed
@@ -253,12 +262,11 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
         for (int k = 0; k < NPIX; ++k) {
             const int i = tid + k * T;
             const int idx = (i / M) * ROW + (i % M);
-            const float2 ex = gx[idx];
-            gx[idx] = make_float2(0.f, 0.f);
+            float2 ex, ey;
+            grid.load(idx, ex, ey);
+            grid.zero(idx);
             av[k][0] += ex.x * ex.x + ex.y * ex.y;
             if (P == 2) {
-                const float2 ey = gy[idx];
-                gy[idx] = make_float2(0.f, 0.f);
                 av[k][1] += ey.x * ey.x + ey.y * ey.y;
                 av[k][2] += ex.x * ey.x + ex.y * ey.y;
                 av[k][3] += ex.y * ey.x - ex.x * ey.y;

@@ -285,11 +285,13 @@ class DeviceExecutor:
         n_int = max(1, spec.n_blocks // max(1, spec.blocks_per_integration))
         host = [torch.empty(img.shape, dtype=torch.float32, pin_memory=True)
                 for _ in range(n_int)]
-        return {"spec": spec, "stream": s, "acc": acc, "img": img, "host": host, "n_out": 0,
+        return {"spec": spec, "stream": s, "copy": torch.cuda.Stream(), "copied": None,
+                "acc": acc, "img": img, "host": host, "n_out": 0,
                 "ring": self.rings[spec.name]}
 
     def close(self, h):
         h["stream"].synchronize()
+        h["copy"].synchronize()
         h["acc"].close()
 
     def accumulate(self, h, block):
@@ -310,8 +312,9 @@ class DeviceExecutor:
         return self.ref.elapsed_time(ev) / 1e3
 
     def readout(self, h):
-        """Read-out on the stream's own queue into pinned host memory; the
-        copy completes asynchronously (valid after ``sync``)."""
+        """Read-out on the stream's queue; the copy to pinned host memory runs
+        on a side queue so the next block does not wait for it (valid after
+        ``sync``)."""
         import paper_2609_03027_amd as E
         torch = self.torch
         if h["n_out"] < len(h["host"]):
@@ -319,9 +322,17 @@ class DeviceExecutor:
         else:
             out = torch.empty(h["img"].shape, dtype=torch.float32, pin_memory=True)
         h["n_out"] += 1
-        with torch.cuda.stream(h["stream"]):
-            E.readout(h["spec"].plan, h["acc"], h["img"], E.REMOVE_AUTOS | E.NORMALISE,
-                      stream=h["stream"])
+        s, cp = h["stream"], h["copy"]
+        if h["copied"] is not None:
+            s.wait_event(h["copied"])        # the previous copy still reads img
+        with torch.cuda.stream(s):
+            E.readout(h["spec"].plan, h["acc"], h["img"], E.REMOVE_AUTOS | E.NORMALISE, stream=s)
+            ready = torch.cuda.Event()
+            ready.record(s)
+            h["acc"].reset(stream=s)
+        cp.wait_event(ready)
+        with torch.cuda.stream(cp):
             out.copy_(h["img"], non_blocking=True)
-            h["acc"].reset(stream=h["stream"])
+            h["copied"] = torch.cuda.Event()
+            h["copied"].record(cp)
         return out
