@@ -153,6 +153,11 @@ def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8):
                                 bytes_needed=plan.info["bytes_acc"] + rings[name].numel()))
     ex = DeviceExecutor(rings)
     free, _ = torch.cuda.mem_get_info()
+    # warm-up: a short run of every stream through the same server path
+    warm = Server(ex, budget_bytes=int(0.8 * free))
+    for s in specs:
+        warm.submit_stream(replace(s, n_blocks=2 * s.blocks_per_integration))
+    warm.run(timeout_s=60.0)
     srv = Server(ex, budget_bytes=int(0.8 * free))
     t0 = time.perf_counter()
     for s in specs:
@@ -163,6 +168,8 @@ def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8):
     st = Server.stats(recs)
     lat = np.array([r.latency for r in recs if not r.dropped])
     st["late"] = int(np.sum(lat > period_s))
+    slow = sorted((r for r in recs if not r.dropped), key=lambda r: -r.latency)[:5]
+    st["slowest"] = [(r.stream, r.index, round(r.latency * 1e3, 3)) for r in slow]
     st["streams"] = n_streams
     st["block_samples"] = tb
     st["period_ms"] = period_s * 1e3
@@ -226,6 +233,43 @@ def batched(E, torch, reps=5):
     return res
 
 
+def large_stream(E, torch, reps=3):
+    """Large-N streaming array: 4096 dual-pol elements in a 300 m disc,
+    64 channels at 92-108 MHz, 256 x 256 grids, one block of 256 samples
+    (1.024 ms of data at 250 kHz channels) through the fused path."""
+    import synth
+    wl = synth.workload("stream")
+    pos = synth.antenna_layout(wl)
+    t0 = time.perf_counter()
+    volt = torch.from_numpy(synth.voltages(wl, pos)).cuda()
+    tgen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = E.Plan.from_workload(wl, pos)
+    tplan = time.perf_counter() - t0
+    acc = E.Accumulator(plan)
+    E.accumulate(plan, acc, volt=volt)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        E.accumulate(plan, acc, volt=volt)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    block_ms = wl.n_time / 250e3 * 1e3
+    res = {"workload": "stream-large: 4096 dual-pol elements, 300 m disc, 64 channels "
+                       "92-108 MHz, 256^2 grids, one 256-sample block",
+           "ms_per_block": ms, "block_data_ms": block_ms,
+           "real_time_fraction_one_stream": block_ms / ms,
+           "value": wl.samples_per_block() / (ms / 1e3), "unit": "samples/s",
+           "plan_s": tplan, "plan_bytes": plan.info["bytes_plan"], "gen_s": tgen}
+    log(f"large stream: {ms:.2f} ms per {block_ms:.3f} ms block "
+        f"({block_ms / ms:.2f} of real time), plan {tplan:.1f} s")
+    acc.close()
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +282,8 @@ def main():
                     help="also time the MFMA DFT-GEMM variants on the same step (0 = skip)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the uneven SKA-like batch (0 = skip)")
+    ap.add_argument("--large", type=int, default=1,
+                    help="also time one block of the 4096-element 256^2 array (0 = skip)")
     ap.add_argument("--stream-blocks", type=int, default=200,
                     help="blocks per stream in the real-time streaming run (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -422,6 +468,9 @@ def main():
 
     if args.batched:
         out["batched"] = batched(E, torch)
+
+    if args.large:
+        out["large_stream"] = large_stream(E, torch)
 
     if args.stream_blocks > 0:
         out["streaming"] = {}

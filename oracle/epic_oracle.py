@@ -43,7 +43,8 @@ C_LIGHT = 299792458.0
 __all__ = [
     "C_LIGHT", "decode_int4", "grid_geometry", "gaussian_kernel",
     "support_inside", "grid", "centred_dft_matrix", "sky", "n_products",
-    "accumulate", "antenna_autos", "antenna_beams", "auto_term", "readout",
+    "accumulate", "antenna_autos", "antenna_beams", "auto_term", "auto_term_by_element",
+    "readout",
     "fx_image", "channel_reference", "epic_reference",
 ]
 
@@ -223,6 +224,22 @@ def auto_term(S, B) -> np.ndarray:
     return np.einsum("ap,ayx->pyx", np.asarray(S, dtype=np.float64), P2)
 
 
+def auto_term_by_element(S, j0, w, n) -> np.ndarray:
+    """The same sum as ``auto_term(S, antenna_beams(j0, w, n))``, adding one
+    element's power pattern at a time so memory stays O(N^2)."""
+    F = centred_dft_matrix(n)
+    S = np.asarray(S, dtype=np.float64)
+    k = w.shape[-1]
+    wc = np.conj(w)
+    out = np.zeros((S.shape[1], n, n))
+    for a in range(S.shape[0]):
+        Fy = F[:, j0[a, 1]:j0[a, 1] + k]
+        Fx = F[:, j0[a, 0]:j0[a, 0] + k]
+        p2 = np.abs(Fy @ wc[a] @ Fx.T) ** 2
+        out += S[a][:, None, None] * p2
+    return out
+
+
 def readout(acc, auto=None, count=1, normalise=True) -> np.ndarray:
     """(acc - auto) / count: Eq. 2's average with the self terms removed."""
     out = np.array(acc, dtype=np.float64, copy=True)
@@ -306,9 +323,11 @@ def channel_reference(volt_c, pos, freq_hz, n, *, cell_lambda=0.5, k=3,
     Es = sky(G)
     acc = accumulate(Es)
     S = antenna_autos(E)
-    B = antenna_beams(j0, w, n)
-    out = dict(acc=acc, autos=S, auto=auto_term(S, B), j0=j0, w=w, x=x,
-               count=E.shape[0])
+    if len(j0) * n * n <= (1 << 24):
+        auto = auto_term(S, antenna_beams(j0, w, n))
+    else:
+        auto = auto_term_by_element(S, j0, w, n)
+    out = dict(acc=acc, autos=S, auto=auto, j0=j0, w=w, x=x, count=E.shape[0])
     if want_images:
         out["grid"] = G
         out["sky"] = Es

@@ -114,7 +114,8 @@ class Server:
             pr = self.plans_resident.setdefault(id(spec.plan), [cost - spec.bytes_needed, 0])
             pr[1] += 1
             handle = self.ex.open(spec)
-            self.active[spec.name] = _Active(spec, handle, now)
+            # the stream's clock starts once its device resources are ready
+            self.active[spec.name] = _Active(spec, handle, self.ex.now())
 
     def _close(self, st, now):
         spec = st.spec
@@ -285,6 +286,13 @@ class DeviceExecutor:
         n_int = max(1, spec.n_blocks // max(1, spec.blocks_per_integration))
         host = [torch.empty(img.shape, dtype=torch.float32, pin_memory=True)
                 for _ in range(n_int)]
+        # first use of a new queue is slow: touch it (and the kernels) now
+        with torch.cuda.stream(s):
+            ring = self.rings[spec.name]
+            E.accumulate(spec.plan, acc, volt=ring[0], stream=s)
+            E.readout(spec.plan, acc, img, E.REMOVE_AUTOS | E.NORMALISE, stream=s)
+            acc.reset(stream=s)
+        s.synchronize()
         return {"spec": spec, "stream": s, "copy": torch.cuda.Stream(), "copied": None,
                 "acc": acc, "img": img, "host": host, "n_out": 0,
                 "ring": self.rings[spec.name]}

@@ -278,3 +278,14 @@ def test_channel_reference_readout_normalises():
     E = O.decode_int4(v[:, 0])
     fx = O.fx_image(E, r["j0"], r["w"], 32, include_auto=False)
     assert np.max(np.abs((r["acc"] - r["auto"]) - fx)) <= 1e-11 * np.max(r["acc"][0])
+
+
+def test_auto_term_by_element_equals_materialised_beams():
+    rng = _rng(14)
+    n, A = 24, 7
+    j0 = rng.integers(1, n - 4, size=(A, 2))
+    w = rng.normal(size=(A, 3, 3)) + 1j * rng.normal(size=(A, 3, 3))
+    S = rng.integers(0, 500, size=(A, 4)).astype(float)
+    a = O.auto_term(S, O.antenna_beams(j0, w, n))
+    b = O.auto_term_by_element(S, j0, w, n)
+    np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-9)
