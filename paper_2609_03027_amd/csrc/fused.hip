@@ -138,6 +138,49 @@ template <int M> __device__ __forceinline__ int unscramble(int n) {
     return n / FCfg<M>::RB + FCfg<M>::RA * (n % FCfg<M>::RB);
 }
 
+// Last pass (B along y) fused with the Eq. 2 products: the thread's
+// butterflies end in registers, so their outputs go straight into its
+// accumulators av[k RB + q] and the grid is left zeroed for the next gather.
+// Output q of butterfly k sits at row blk RB + q, column line.
+template <int M, int P, int NPROD>
+__device__ __forceinline__ void pass_b_products(Grid<P> g, int tid, float (*av)[NPROD]) {
+    constexpr int T = FCfg<M>::T, RB = FCfg<M>::RB, ROW = FCfg<M>::ROW;
+    constexpr int NB = M * M / (RB * T);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int u = tid + k * T;
+        const int line = u % M, blk = u / M;
+        const int base = blk * RB * ROW + line;
+        float2 v0[RB], v1[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) g.load(base + q * ROW, v0[q], v1[q]);
+        dft<RB>(v0);
+        if (P == 2) dft<RB>(v1);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            g.zero(base + q * ROW);
+            const float2 ex = v0[q];
+            float *a = av[k * RB + q];
+            a[0] += ex.x * ex.x + ex.y * ex.y;
+            if (P == 2) {
+                const float2 ey = v1[q];
+                a[1] += ey.x * ey.x + ey.y * ey.y;
+                a[2] += ex.x * ey.x + ex.y * ey.y;
+                a[3] += ex.y * ey.x - ex.x * ey.y;
+            }
+        }
+    }
+}
+
+// Grid position (row, column) of accumulator slot s = k RB + q of a thread.
+template <int M>
+__device__ __forceinline__ void slot_position(int tid, int s, int &row, int &col) {
+    constexpr int T = FCfg<M>::T, RB = FCfg<M>::RB;
+    const int u = tid + (s / RB) * T;
+    col = u % M;
+    row = (u / M) * RB + s % RB;
+}
+
 // ------------------------------------------------------------------ kernel
 // One workgroup per item (channel c, class o), looping over all n_time
 // samples.  Gather entry (uint4): x = element | last-tap-of-cell << 31,
@@ -254,34 +297,19 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
         __syncthreads();
         pass_a<M, P, false>(grid, tid, tw);
         __syncthreads();
-        pass_b<M, P, false>(grid, tid);
-        __syncthreads();
-
-        // Eq. 2 products into this thread's pixels; leave the grid zeroed
-#pragma unroll
-        for (int k = 0; k < NPIX; ++k) {
-            const int i = tid + k * T;
-            const int idx = (i / M) * ROW + (i % M);
-            float2 ex, ey;
-            grid.load(idx, ex, ey);
-            grid.zero(idx);
-            av[k][0] += ex.x * ex.x + ex.y * ex.y;
-            if (P == 2) {
-                av[k][1] += ey.x * ey.x + ey.y * ey.y;
-                av[k][2] += ex.x * ey.x + ex.y * ey.y;
-                av[k][3] += ex.y * ey.x - ex.x * ey.y;
-            }
-        }
-        // the stage barrier of the next sample orders these LDS writes
+        // last pass + Eq. 2 products; the grid is left zeroed, and the stage
+        // barrier of the next sample orders these writes before the gather
+        pass_b_products<M, P, NPROD>(grid, tid, av);
     }
 
     const int N = it.N, R = it.R;
     const int64_t plane = (int64_t)N * N;
 #pragma unroll
     for (int k = 0; k < NPIX; ++k) {
-        const int i = tid + k * T;
-        const int ky = R * unscramble<M>(i / M) + it.oy;
-        const int kx = R * unscramble<M>(i % M) + it.ox;
+        int row, col;
+        slot_position<M>(tid, k, row, col);
+        const int ky = R * unscramble<M>(row) + it.oy;
+        const int kx = R * unscramble<M>(col) + it.ox;
         float *dst = acc + it.img_off + (int64_t)ky * N + kx;
 #pragma unroll
         for (int q = 0; q < NPROD; ++q) dst[q * plane] += av[k][q];
