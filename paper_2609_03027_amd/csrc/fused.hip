@@ -327,6 +327,195 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
     }
 }
 
+// ------------------------------------------------- paired-class kernel
+// For N = 2 M grids (M = 64) whose element rows span fewer than M rows and two
+// feeds, classes (ox, 0) and (ox, 1) share everything up to the y-pass: their
+// folded grids differ only by the per-row factor exp(+2 pi i jy / N), which
+// commutes with the transform along x.  One workgroup per (channel, ox)
+// grids once and runs the x-pass once; the first y-pass reads each column
+// segment once and writes both classes (the oy = 1 copy multiplied on load by
+// the row factors, into a second grid); the last y-pass feeds both classes'
+// products.  The span index j of every pass is the wave index, so twiddles
+// and row factors are wave-uniform (scalar registers).
+__device__ __forceinline__ float uni(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+template <int AR>
+__global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict__ items,
+                                                    const uint4 *__restrict__ entries,
+                                                    const uint8_t *__restrict__ volt,
+                                                    int64_t volt_t_stride, int A, int n_time,
+                                                    float *__restrict__ acc,
+                                                    int32_t *__restrict__ autos) {
+    constexpr int M = 64, T = 512, ROW = 65, GSZ = M * ROW, S = 8;
+    extern __shared__ float4 smem[];
+    Grid<2> g, h;
+    g.g = smem;
+    h.g = smem + GSZ;
+    float4 *stage = smem + 2 * GSZ;
+
+    const FusedItem it = items[blockIdx.x];
+    if (it.c < 0) return;
+    const int tid = threadIdx.x;
+    const int line = tid & 63;
+    const int j = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    float2 tw[8], md[8];
+    {
+        const int N = it.N;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            double sn, cs;
+            sincospi(2.0 * (double)(p * j) / (double)M, &sn, &cs);
+            tw[p] = make_float2(uni((float)cs), uni((float)sn));
+            // folded row j + 8p holds grid row jy = ylo + ((m - ylo) mod M)
+            const int m = j + S * p;
+            const int jy = it.ylo + (((m - it.ylo) % M) + M) % M;
+            sincospi(2.0 * (double)(jy % N) / (double)N, &sn, &cs);
+            md[p] = make_float2(uni((float)cs), uni((float)sn));
+        }
+    }
+    for (int i = tid; i < GSZ; i += T) g.zero(i);
+
+    float av[16][4];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) av[k][q] = 0.f;
+
+    const uint8_t *vbase = volt + (int64_t)it.c * 2 * A;
+    const uint4 *ent = entries + it.entry_off + tid;
+    const int n_iter = it.n_iter;
+    const bool own_autos = autos != nullptr && it.ox == 0;
+    int sa[AR][4];
+#pragma unroll
+    for (int k = 0; k < AR; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sa[k][q] = 0;
+
+    for (int t = 0; t < n_time; ++t) {
+        const uint8_t *vt = vbase + (int64_t)t * volt_t_stride;
+#pragma unroll
+        for (int k = 0; k < AR; ++k) {
+            const int a = tid + k * T;
+            if (a < A) {
+                const uint32_t bx = vt[a], by = vt[A + a];
+                const int xr = dec_re(bx), xi = dec_im(bx), yr = dec_re(by), yi = dec_im(by);
+                stage[a] = make_float4((float)xr, (float)xi, (float)yr, (float)yi);
+                if (own_autos) {
+                    sa[k][0] += xr * xr + xi * xi;
+                    sa[k][1] += yr * yr + yi * yi;
+                    sa[k][2] += xr * yr + xi * yi;
+                    sa[k][3] += xi * yr - xr * yi;
+                }
+            }
+        }
+        for (int a = tid + AR * T; a < A; a += T) {
+            const uint32_t bx = vt[a], by = vt[A + a];
+            stage[a] = make_float4((float)dec_re(bx), (float)dec_im(bx), (float)dec_re(by),
+                                   (float)dec_im(by));
+        }
+        __syncthreads();
+
+        {
+            float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
+            for (int k = 0; k < n_iter; ++k) {
+                const uint4 e = ent[(int64_t)k * T];
+                const float4 v = stage[e.x & 0xFFFFu];
+                const float wr = __uint_as_float(e.z), wi = __uint_as_float(e.w);
+                sx.x += wr * v.x - wi * v.y;
+                sx.y += wr * v.y + wi * v.x;
+                sy.x += wr * v.z - wi * v.w;
+                sy.y += wr * v.w + wi * v.z;
+                if (e.x >> 31) {
+                    g.store(e.y, sx, sy);
+                    sx = make_float2(0.f, 0.f);
+                    sy = make_float2(0.f, 0.f);
+                }
+            }
+        }
+        __syncthreads();
+
+        pass_a<M, 2, true>(g, tid, tw);
+        __syncthreads();
+        pass_b<M, 2, true>(g, tid);
+        __syncthreads();
+        // first y-pass for both classes: column `line`, rows j + 8 q
+        {
+            const int base = j * ROW + line;
+            float2 vx[8], vy[8], wx[8], wy[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                g.load(base + q * S * ROW, vx[q], vy[q]);
+                wx[q] = cmul(vx[q], md[q]);
+                wy[q] = cmul(vy[q], md[q]);
+            }
+            dft<8>(vx);
+            dft<8>(vy);
+            dft<8>(wx);
+            dft<8>(wy);
+#pragma unroll
+            for (int p = 1; p < 8; ++p) {
+                vx[p] = cmul(vx[p], tw[p]);
+                vy[p] = cmul(vy[p], tw[p]);
+                wx[p] = cmul(wx[p], tw[p]);
+                wy[p] = cmul(wy[p], tw[p]);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                g.store(base + q * S * ROW, vx[q], vy[q]);
+                h.store(base + q * S * ROW, wx[q], wy[q]);
+            }
+        }
+        __syncthreads();
+        // last y-pass + Eq. 2 products for both classes; g is left zeroed
+        // (h is fully rewritten by the first y-pass of the next sample)
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy) {
+            const Grid<2> b = oy ? h : g;
+            const int base = j * 8 * ROW + line;
+            float2 vx[8], vy[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) b.load(base + q * ROW, vx[q], vy[q]);
+            dft<8>(vx);
+            dft<8>(vy);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (!oy) g.zero(base + q * ROW);
+                float *a = av[oy * 8 + q];
+                a[0] += vx[q].x * vx[q].x + vx[q].y * vx[q].y;
+                a[1] += vy[q].x * vy[q].x + vy[q].y * vy[q].y;
+                a[2] += vx[q].x * vy[q].x + vx[q].y * vy[q].y;
+                a[3] += vx[q].y * vy[q].x - vx[q].x * vy[q].y;
+            }
+        }
+    }
+
+    const int N = it.N;
+    const int64_t plane = (int64_t)N * N;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int oy = s >> 3, q = s & 7;
+        const int ky = 2 * unscramble<64>(j * 8 + q) + oy;
+        const int kx = 2 * unscramble<64>(line) + it.ox;
+        float *dst = acc + it.img_off + (int64_t)ky * N + kx;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) dst[p * plane] += av[s][p];
+    }
+    if (own_autos) {
+#pragma unroll
+        for (int k = 0; k < AR; ++k) {
+            const int a = tid + k * T;
+            if (a < A) {
+                int32_t *d = autos + ((int64_t)it.c * A + a) * 4;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) atomicAdd(d + p, sa[k][p]);
+            }
+        }
+    }
+}
+
 // Per-element self-term sums S_a^{pq} = sum_t E_a^p conj(E_a^q), exact in
 // int32 (|E|^2 <= 128 per sample).  Grid: (elements, channels, time chunks).
 template <int P>
@@ -457,6 +646,7 @@ static FusedItem build_item(epic_plan p, const std::vector<int> &j0, const std::
     fi.n_iter = n_iter;
     fi.entry_off = (int64_t)off;
     fi.img_off = p->ch[c].img_off;
+    fi.ylo = 0;
     return fi;
 }
 
@@ -512,12 +702,44 @@ static epic_status upload_group(FusedGroup *g, std::vector<FusedItem> &items,
 epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
                         hipStream_t s) {
     const int A = p->A, K = p->K;
+    // Paired items: two feeds, N = 2 * 64, every element row in a 64-row window.
+    std::vector<int> pair_ylo(p->C, -1);
+    for (int c = 0; c < p->C; ++c) {
+        if (p->P != 2 || p->ch[c].M != 64 || p->ch[c].R != 2) continue;
+        int lo = 1 << 30, hi = -1;
+        for (int a = 0; a < A; ++a) {
+            const int jy = j0[((size_t)c * A + a) * 2 + 1];
+            lo = std::min(lo, jy);
+            hi = std::max(hi, jy + K - 1);
+        }
+        if (hi - lo < 64) pair_ylo[c] = lo;
+    }
+    {
+        std::vector<FusedItem> items;
+        std::vector<uint4> all;
+        for (int c = 0; c < p->C; ++c) {
+            if (pair_ylo[c] < 0) continue;
+            for (int ox = 0; ox < 2; ++ox) {
+                FusedItem fi = build_item(p, j0, w, c, ox, 0, 64, 512, all);
+                fi.ylo = pair_ylo[c];
+                items.push_back(fi);
+            }
+        }
+        if (!items.empty()) {
+            auto *g = new FusedGroup();
+            g->M = 64;
+            g->kind = 1;
+            p->groups.push_back(g);
+            epic_status st = upload_group(g, items, all, p->C, s);
+            if (st) return st;
+        }
+    }
     for (int M : {64, 32, 16}) {
         std::vector<FusedItem> items;
         std::vector<uint4> all;
         const int T = threads_of(M);
         for (int c = 0; c < p->C; ++c) {
-            if (p->ch[c].M != M) continue;
+            if (p->ch[c].M != M || pair_ylo[c] >= 0) continue;
             const int R = p->ch[c].R;
             for (int oy = 0; oy < R; ++oy)
                 for (int ox = 0; ox < R; ++ox) items.push_back(build_item(p, j0, w, c, ox, oy, M, T, all));
@@ -580,6 +802,27 @@ static epic_status launch_fused(const FusedGroup *g, const uint8_t *d_volt, int6
     return launch_fused_ar<M, P, 4>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
 }
 
+template <int AR>
+static epic_status launch_pair_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
+                                  int A, int n_time, float *acc, int32_t *autos, hipStream_t s,
+                                  bool dry) {
+    const size_t lds = sizeof(float4) * (2 * 64 * 65 + (size_t)A);
+    auto kern = k_fused_pair<AR>;
+    epic_status st = lds_ready(reinterpret_cast<const void *>(kern), lds);
+    if (st || dry) return st;
+    hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(512), lds, s, g->items.as<FusedItem>(),
+                       g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos);
+    EPIC_HIP(hipGetLastError());
+    return EPIC_OK;
+}
+
+static epic_status launch_pair(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride, int A,
+                               int n_time, float *acc, int32_t *autos, hipStream_t s, bool dry) {
+    if (A <= 512) return launch_pair_ar<1>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
+    if (A <= 1024) return launch_pair_ar<2>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
+    return launch_pair_ar<4>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
+}
+
 // Launches every size group; group i goes to branches[i] when given (graph
 // capture with parallel branches), else to s.  dry: only set up the kernels'
 // LDS allowance (done before a capture).
@@ -598,7 +841,9 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
         const hipStream_t gs = branches ? (*branches)[gi] : s;
         epic_status st = EPIC_OK;
         const int A = p->A;
-        if (p->P == 2) {
+        if (g->kind == 1) {
+            st = launch_pair(g, d_volt, vstride, A, n_time, a, au, gs, dry);
+        } else if (p->P == 2) {
             if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
             if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
             if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, A, n_time, a, au, gs, dry);

@@ -72,11 +72,14 @@ struct FusedItem {
     int32_t n_iter;      // gather iterations (entries per lane)
     int64_t entry_off;   // first entry (uint4) of this item
     int64_t img_off;     // float offset of channel c in the image set
+    int32_t ylo;         // paired items: first grid row of the M-row window
+    int32_t pad;
 };
 
 // A group of fused items that share one sub-transform size M.
 struct FusedGroup {
     int M = 0;
+    int kind = 0;     // 0: one class per item; 1: paired classes (ox, 0) + (ox, 1)
     int n_items = 0;
     DevBuf items;     // FusedItem[n_items]
     DevBuf entries;   // uint4 gather entries
