@@ -236,37 +236,48 @@ def batched(E, torch, reps=5):
 def large_stream(E, torch, reps=3):
     """Large-N streaming array: 4096 dual-pol elements in a 300 m disc,
     64 channels at 92-108 MHz, 256 x 256 grids, one block of 256 samples
-    (1.024 ms of data at 250 kHz channels) through the fused path."""
+    (1.024 ms of data at 250 kHz channels): the default plan (banded two-pass
+    path at this size) and, beside it, the fused path forced to 64 x 64
+    sub-transforms."""
     import synth
     wl = synth.workload("stream")
     pos = synth.antenna_layout(wl)
     t0 = time.perf_counter()
     volt = torch.from_numpy(synth.voltages(wl, pos)).cuda()
     tgen = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    plan = E.Plan.from_workload(wl, pos)
-    tplan = time.perf_counter() - t0
-    acc = E.Accumulator(plan)
-    E.accumulate(plan, acc, volt=volt)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
+
+    def timed(sub_n):
+        t0 = time.perf_counter()
+        plan = E.Plan.from_workload(wl, pos, sub_n=sub_n)
+        tplan = time.perf_counter() - t0
+        acc = E.Accumulator(plan)
         E.accumulate(plan, acc, volt=volt)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            E.accumulate(plan, acc, volt=volt)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        info = dict(plan.info)
+        acc.close()
+        plan.close()
+        return ms, tplan, info
+
+    ms, tplan, info = timed(None)
+    ms_fused, _, _ = timed([64] * wl.n_chan)
     block_ms = wl.n_time / 250e3 * 1e3
     res = {"workload": "stream-large: 4096 dual-pol elements, 300 m disc, 64 channels "
                        "92-108 MHz, 256^2 grids, one 256-sample block",
-           "ms_per_block": ms, "block_data_ms": block_ms,
+           "path": "banded two-pass", "ms_per_block": ms, "block_data_ms": block_ms,
            "real_time_fraction_one_stream": block_ms / ms,
            "value": wl.samples_per_block() / (ms / 1e3), "unit": "samples/s",
-           "plan_s": tplan, "plan_bytes": plan.info["bytes_plan"], "gen_s": tgen}
+           "fused64_ms_per_block": ms_fused,
+           "plan_s": tplan, "plan_bytes": info["bytes_plan"], "acc_bytes": info["bytes_acc"],
+           "gen_s": tgen}
     log(f"large stream: {ms:.2f} ms per {block_ms:.3f} ms block "
-        f"({block_ms / ms:.2f} of real time), plan {tplan:.1f} s")
-    acc.close()
-    plan.close()
+        f"({block_ms / ms:.2f} of real time; fused 64x64 {ms_fused:.2f} ms), plan {tplan:.1f} s")
     return res
 
 

@@ -69,6 +69,9 @@ typedef enum {
 /* plan flags */
 #define EPIC_PLAN_DEFAULT 0u
 
+/* sub_n value that selects the banded two-pass path for a channel */
+#define EPIC_SUB_BANDED (-1)
+
 /* readout flags */
 #define EPIC_REMOVE_AUTOS 1u   /* subtract the per-element self terms */
 #define EPIC_NORMALISE 2u      /* divide by the number of accumulated samples */
@@ -89,10 +92,14 @@ typedef struct {
                                     support cells [dy][dx] (replaces the Gaussian); copied */
     int32_t precision;           /* epic_precision */
     uint32_t flags;              /* EPIC_PLAN_DEFAULT */
-    const int32_t *sub_n;        /* optional host [C]: side M of the sub-transforms the
-                                    FP32 fused path splits channel c into (16, 32 or 64,
-                                    dividing grid_n[c], at most 8 per axis); 0 or NULL =
-                                    the largest that divides grid_n[c] */
+    const int32_t *sub_n;        /* optional host [C], FP32 only: side M of the
+                                    sub-transforms the fused path splits channel c into
+                                    (16, 32 or 64, dividing grid_n[c], at most 8 per
+                                    axis), or EPIC_SUB_BANDED for the banded two-pass
+                                    path (grid_n[c] a multiple of 32 with factors 2 and
+                                    3, at most 512); 0 or NULL = automatic: banded where
+                                    the largest M dividing grid_n[c] leaves 4 or more
+                                    sub-transforms per axis, else that M */
 } epic_plan_desc;
 
 typedef struct epic_plan_s *epic_plan;  /* opaque; owns device tables */
@@ -119,7 +126,11 @@ epic_status epic_plan_destroy(epic_plan plan);
 epic_status epic_plan_get_info(epic_plan plan, epic_plan_info *info);
 
 /* Accumulators for Eq. 2: zeroed FP32 image sums, int32 self-term sums and
- * the sample count, all device resident and owned by the handle. */
+ * the sample count, all device resident and owned by the handle, plus the
+ * working memory the plan's path needs (operand staging of the MFMA
+ * variants, row-transform scratch of the banded path; bytes_acc counts it).
+ * Accumulations into different accumulators may run concurrently on
+ * different streams; calls on one accumulator must be ordered. */
 epic_status epic_acc_create(epic_plan plan, epic_acc *out);
 epic_status epic_acc_reset(epic_acc acc, void *hip_stream);
 epic_status epic_acc_destroy(epic_acc acc);
@@ -144,8 +155,9 @@ epic_status epic_image(epic_plan plan, const void *d_grid, int32_t n_time, void 
 
 /* Eq. 1 + Eq. 2 accumulated over n_time samples.
  *   d_sky == NULL: the fused path -- grid, transform and polarisation products
- *     of every sample stay on chip; only the sums reach HBM.  Also adds the
- *     per-element self-term sums.
+ *     of every sample stay on chip; only the sums reach HBM.  Banded channels
+ *     (sub_n) pass their row transforms through the accumulator's scratch
+ *     instead.  Also adds the per-element self-term sums.
  *   d_sky != NULL: products of given sky images (layout of epic_image); the
  *     self-term sums are added too when d_volt is also given.
  * Sums are added in increasing time order; results do not depend on what

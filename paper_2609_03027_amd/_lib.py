@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libepic.so")
 EPIC_F32, EPIC_F16_MFMA, EPIC_F8E4M3_MFMA, EPIC_BF16X2_MFMA = 0, 1, 2, 3
 REMOVE_AUTOS = 1
 NORMALISE = 2
+SUB_BANDED = -1        # sub_n value: banded two-pass path for that channel
 
 STATUS = {0: "EPIC_OK", 1: "EPIC_ERR_NULL", 2: "EPIC_ERR_ARG", 3: "EPIC_ERR_GRID",
           4: "EPIC_ERR_UNSUPPORTED", 5: "EPIC_ERR_OOM", 6: "EPIC_ERR_DEVICE",

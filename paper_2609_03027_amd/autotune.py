@@ -2,9 +2,10 @@
 
 The fused kernel splits a channel's N x N transform into (N / M)^2
 sub-transforms of side M (16, 32 or 64; see the plan's ``sub_n``).  Larger
-tiles mean fewer, bigger transforms but more gather work per tile; which is
-faster depends on N, the element count and how densely the footprints cover
-the grid.  For every distinct grid side this tuner builds one-channel plans
+tiles mean fewer, bigger transforms but more gather work per tile; the
+banded two-pass path (``SUB_BANDED``) gathers every tap once but passes the
+row transforms through HBM.  Which is faster depends on N, the element count
+and how densely the footprints cover the grid.  For every distinct grid side this tuner builds one-channel plans
 for each admissible M at the highest-frequency channel of that size (the
 densest footprint coverage), times the accumulate on the device with HIP
 events, and keeps the fastest.  Results are cached as JSON keyed by the
@@ -22,8 +23,21 @@ from . import _lib as L
 C_LIGHT = 299792458.0
 
 
+def banded_ok(n: int) -> bool:
+    """Grid sides the banded path takes: multiples of 32 up to 512 with
+    factors 2 and 3 only."""
+    if n < 32 or n > 512 or n % 32:
+        return False
+    while n % 2 == 0:
+        n //= 2
+    while n % 3 == 0:
+        n //= 3
+    return n == 1
+
+
 def candidates(n: int):
-    return [m for m in (64, 32, 16) if n % m == 0 and n // m <= 8]
+    fused = [m for m in (64, 32, 16) if n % m == 0 and n // m <= 8]
+    return fused + ([L.SUB_BANDED] if banded_ok(n) else [])
 
 
 def _cache_path():

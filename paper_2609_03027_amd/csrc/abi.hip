@@ -89,10 +89,11 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     if (d->sub_n)
         for (int c = 0; c < d->n_chan; ++c) {
             const int m = d->sub_n[c];
-            if (m == 0) continue;
+            if (m == 0 || m == EPIC_SUB_BANDED) continue;
             if ((m != 16 && m != 32 && m != 64) || d->grid_n[c] % m || d->grid_n[c] / m > 8)
-                return fail(EPIC_ERR_ARG, "sub_n must be 0, 16, 32 or 64, divide grid_n and "
-                                          "leave at most 8 sub-transforms per axis");
+                return fail(EPIC_ERR_ARG, "sub_n must be 0, -1, 16, 32 or 64; 16, 32 and 64 "
+                                          "must divide grid_n and leave at most 8 "
+                                          "sub-transforms per axis");
         }
 
     auto *p = new epic_plan_s();
@@ -150,7 +151,8 @@ epic_status epic_plan_get_info(epic_plan p, epic_plan_info *info) {
     const int D = 2 * p->K - 1;
     info->bytes_acc = (int64_t)sizeof(float) * p->image_floats +
                       (int64_t)sizeof(int32_t) * info->autos_ints +
-                      (int64_t)sizeof(double2) * p->C * (p->P == 2 ? 3 : 1) * D * D;
+                      (int64_t)sizeof(double2) * p->C * (p->P == 2 ? 3 : 1) * D * D +
+                      p->work_bytes;
     info->n_prod = p->n_prod;
     info->max_grid_n = p->max_n;
     return EPIC_OK;
@@ -167,6 +169,7 @@ epic_status epic_acc_create(epic_plan p, epic_acc *out) {
     epic_status st = a->d_acc.alloc(sizeof(float) * p->image_floats);
     if (!st) st = a->d_autos.alloc(sizeof(int32_t) * (size_t)p->C * p->A * p->n_prod);
     if (!st) st = a->d_h.alloc(sizeof(double2) * (size_t)p->C * (p->P == 2 ? 3 : 1) * D * D);
+    if (!st && p->work_bytes) st = a->d_work.alloc((size_t)p->work_bytes);
     if (!st) {
         hipError_t e = hipMemset(a->d_acc.p, 0, a->d_acc.bytes);
         if (e == hipSuccess) e = hipMemset(a->d_autos.p, 0, a->d_autos.bytes);

@@ -1,0 +1,751 @@
+// Banded two-pass path for large grids with dense apertures (Eq. 1 + Eq. 2).
+//
+// When a channel's N x N transform would split into many sub-transform
+// classes (4 or more per axis), every class of the fused path re-gathers all
+// of the channel's kernel taps.  Here each tap is gathered once instead:
+//   pass 1 (k_band_rows): a workgroup grids an 8-row band of one (sample,
+//     channel) from the plan's cell -> tap table, folds in (-1)^(jx+jy),
+//     transforms the rows in LDS (Stockham, both feeds as one float4) and
+//     writes them to the accumulator's scratch; only the rows that some
+//     element footprint touches are gridded, transformed and stored;
+//   pass 2 (k_band_cols): a workgroup owns an 8-column band of one channel,
+//     loops over the samples of the chunk (the next sample's rows are loaded
+//     while the current one is transformed), transforms the columns in LDS and
+//     adds the Eq. 2 products into registers; one read-modify-write of the
+//     accumulators per chunk.
+// Grid sides N = R * R (R = 8, 16) take two-step kernels instead: pass 1
+// gathers from per-band lane lists (every lane's loads issued together),
+// both passes split each line transform into R-point DFTs in registers with
+// one padded LDS exchange (N = R x R, twiddles exp(+2 pi i q j / N) held in
+// registers), and pass 2 reads each sample's rows straight into the first
+// step's registers.  Other sides use LDS Stockham passes of radix 4, 2, 3.
+// With the input sign folded, the transform output differs from Eq. 1's
+// centred sum by (-1)^(kx+ky) times a unit constant, common to both feeds,
+// so every Eq. 2 product is unchanged and pixels keep their natural index.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace epic {
+
+namespace {
+
+constexpr int BL = 8;                    // lines per band
+constexpr int BT = 256;                  // threads per workgroup
+constexpr int MAXN = 512;                // largest banded grid side
+constexpr int MAXPIX = MAXN * BL / BT;   // pixels per thread in pass 2 at MAXN
+
+__device__ __forceinline__ float4 q_add(float4 a, float4 b) {
+    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ float4 q_sub(float4 a, float4 b) {
+    return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+}
+// both feeds times the same complex number
+__device__ __forceinline__ float4 q_mul(float4 a, float2 w) {
+    return make_float4(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x,
+                       a.z * w.x - a.w * w.y, a.z * w.y + a.w * w.x);
+}
+__device__ __forceinline__ float4 q_mul_i(float4 a) { return make_float4(-a.y, a.x, -a.w, a.z); }
+
+// One radix-R Stockham pass over BL lines (positive exponent).
+template <int R>
+__device__ __forceinline__ void stockham_pass(const float4 *src, float4 *dst, int N, int pitch,
+                                              int Ns, const float2 *__restrict__ tw) {
+    const int nb = N / R;
+    const int tstep = N / (Ns * R);
+    for (int u = threadIdx.x; u < BL * nb; u += BT) {
+        const int l = u / nb, j = u % nb;
+        const int k = j % Ns;
+        const float4 *s_in = src + l * pitch;
+        float4 *s_out = dst + l * pitch;
+        float4 v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float4 x = s_in[j + q * nb];
+            if (q) x = q_mul(x, tw[(q * k * tstep) % N]);
+            v[q] = x;
+        }
+        if constexpr (R == 2) {
+            const float4 a = v[0], b = v[1];
+            v[0] = q_add(a, b);
+            v[1] = q_sub(a, b);
+        } else if constexpr (R == 3) {
+            const float h = 0.86602540378443864676f;
+            const float4 sm = q_add(v[1], v[2]), df = q_sub(v[1], v[2]);
+            const float4 a = v[0];
+            v[0] = q_add(a, sm);
+            const float4 tt = make_float4(a.x - 0.5f * sm.x, a.y - 0.5f * sm.y,
+                                          a.z - 0.5f * sm.z, a.w - 0.5f * sm.w);
+            const float4 d = q_mul_i(df);
+            const float4 uu = make_float4(h * d.x, h * d.y, h * d.z, h * d.w);
+            v[1] = q_add(tt, uu);
+            v[2] = q_sub(tt, uu);
+        } else {
+            const float4 t0 = q_add(v[0], v[2]), t1 = q_sub(v[0], v[2]);
+            const float4 t2 = q_add(v[1], v[3]), t3 = q_mul_i(q_sub(v[1], v[3]));
+            v[0] = q_add(t0, t2);
+            v[2] = q_sub(t0, t2);
+            v[1] = q_add(t1, t3);
+            v[3] = q_sub(t1, t3);
+        }
+        const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) s_out[idxD + q * Ns] = v[q];
+    }
+}
+
+// Stockham transforms (positive exponent) of BL lines of length N in LDS,
+// line l at l * pitch, both feeds per element.  Ends synchronised; returns
+// the buffer that holds the result.
+__device__ float4 *fft_lines(float4 *src, float4 *dst, int N, int pitch, const BandRadices &rad,
+                             const float2 *__restrict__ tw) {
+    int Ns = 1;
+    for (int ps = 0; ps < rad.n; ++ps) {
+        const int r = rad.r[ps];
+        if (r == 4)
+            stockham_pass<4>(src, dst, N, pitch, Ns, tw);
+        else if (r == 2)
+            stockham_pass<2>(src, dst, N, pitch, Ns, tw);
+        else
+            stockham_pass<3>(src, dst, N, pitch, Ns, tw);
+        Ns *= r;
+        __syncthreads();
+        float4 *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    return src;
+}
+
+// cos(2 pi m / 16), m = 0..15; sin(2 pi m / 16) = cos(2 pi (m - 4) / 16)
+constexpr float kC16[16] = {1.0f,
+                            0.92387953251128674f,
+                            0.70710678118654752f,
+                            0.38268343236508977f,
+                            0.0f,
+                            -0.38268343236508977f,
+                            -0.70710678118654752f,
+                            -0.92387953251128674f,
+                            -1.0f,
+                            -0.92387953251128674f,
+                            -0.70710678118654752f,
+                            -0.38268343236508977f,
+                            0.0f,
+                            0.38268343236508977f,
+                            0.70710678118654752f,
+                            0.92387953251128674f};
+
+// a * exp(+2 pi i m / R), R dividing 16, m known at compile time
+template <int M, int R>
+__device__ __forceinline__ float4 q_rot(float4 a) {
+    constexpr int m = M % R;
+    if constexpr (m == 0) {
+        return a;
+    } else if constexpr (4 * m == R) {
+        return q_mul_i(a);
+    } else if constexpr (2 * m == R) {
+        return make_float4(-a.x, -a.y, -a.z, -a.w);
+    } else if constexpr (4 * m == 3 * R) {
+        return make_float4(a.y, -a.x, a.w, -a.z);
+    } else {
+        constexpr int i16 = m * (16 / R);
+        return q_mul(a, make_float2(kC16[i16], kC16[(i16 + 12) % 16]));
+    }
+}
+
+// 4-point DFT, positive exponent, in place
+__device__ __forceinline__ void dft4(float4 &a, float4 &b, float4 &c, float4 &d) {
+    const float4 t0 = q_add(a, c), t1 = q_sub(a, c);
+    const float4 t2 = q_add(b, d), t3 = q_mul_i(q_sub(b, d));
+    a = q_add(t0, t2);
+    c = q_sub(t0, t2);
+    b = q_add(t1, t3);
+    d = q_sub(t1, t3);
+}
+
+// v[i] *= exp(+2 pi i n2 k1 / R) for i = (R / 4) k1 + n2
+template <int R, int I>
+__device__ __forceinline__ void rot_all(float4 (&v)[R]) {
+    if constexpr (I < R) {
+        constexpr int S = R / 4;
+        v[I] = q_rot<(I % S) * (I / S), R>(v[I]);
+        rot_all<R, I + 1>(v);
+    }
+}
+
+// R-point DFT (R = 8, 16), positive exponent, natural order in and out:
+// n = (R / 4) n1 + n2, k = k1 + 4 k2; 4-point DFTs over n1, twiddles
+// exp(+2 pi i n2 k1 / R), then (R / 4)-point DFTs over n2.
+template <int R>
+__device__ __forceinline__ void dft(float4 (&v)[R]) {
+    constexpr int S = R / 4;
+#pragma unroll
+    for (int n2 = 0; n2 < S; ++n2) dft4(v[n2], v[S + n2], v[2 * S + n2], v[3 * S + n2]);
+    // v[S k1 + n2] = Y[n2][k1]
+    rot_all<R, 0>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        if constexpr (S == 4) {
+            dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+        } else {
+            const float4 a = v[2 * k1], b = v[2 * k1 + 1];
+            v[2 * k1] = q_add(a, b);
+            v[2 * k1 + 1] = q_sub(a, b);
+        }
+    }
+    // v[S k1 + k2] = X[k1 + 4 k2]
+    float4 o[R];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < S; ++k2) o[k1 + 4 * k2] = v[S * k1 + k2];
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = o[k];
+}
+
+BandRadices radices_of(int N) {
+    BandRadices r{};
+    int n = N;
+    while (n % 4 == 0) {
+        r.r[r.n++] = 4;
+        n /= 4;
+    }
+    while (n % 2 == 0) {
+        r.r[r.n++] = 2;
+        n /= 2;
+    }
+    while (n % 3 == 0) {
+        r.r[r.n++] = 3;
+        n /= 3;
+    }
+    return r;
+}
+
+}  // namespace
+
+bool banded_eligible(int N) {
+    if (N < 32 || N > MAXN || N % 32) return false;
+    int n = N;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+// Pass 1.  One workgroup per (channel, band, sample) of one grid side; the
+// flat index is spread so that each XCD takes a contiguous range of
+// (channel, band) with every sample of the chunk, keeping that range's gather
+// tables in its own L2.
+__global__ __launch_bounds__(BT) void k_band_rows(
+    const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
+    int n_chans, int max_bands, int nt, int64_t per_xcd, const int64_t *__restrict__ csr_base,
+    const int32_t *__restrict__ csr_off, const int32_t *__restrict__ csr_ant,
+    const float2 *__restrict__ csr_w, int A, int P, int N, BandRadices rad,
+    const float2 *__restrict__ tw, float4 *__restrict__ scratch, int64_t scratch_t) {
+    extern __shared__ float4 lds[];
+    const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (w >= (int64_t)n_chans * max_bands * nt) return;
+    const int t = (int)(w % nt);
+    const int64_t rest = w / nt;
+    const int band = (int)(rest % max_bands);
+    const BandChan ch = chans[rest / max_bands];
+    const int r0 = ch.row_lo + band * BL;
+    if (r0 > ch.row_hi) return;
+    float4 *b0 = lds, *b1 = lds + BL * N;
+    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A;
+    const int32_t *off = csr_off + csr_base[ch.c];
+    for (int i = threadIdx.x; i < BL * N; i += BT) {
+        const int row = r0 + i / N, col = i % N;
+        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row <= ch.row_hi) {
+            const int cell = row * N + col;
+            const int e1 = off[cell + 1];
+            for (int e = off[cell]; e < e1; ++e) {
+                const int a = csr_ant[e];
+                const float2 cw = csr_w[e];
+                const uint32_t bx = vx[a];
+                const float xr = (float)dec_re(bx), xi = (float)dec_im(bx);
+                s.x += cw.x * xr - cw.y * xi;
+                s.y += cw.x * xi + cw.y * xr;
+                if (P == 2) {
+                    const uint32_t by = vx[A + a];
+                    const float yr = (float)dec_re(by), yi = (float)dec_im(by);
+                    s.z += cw.x * yr - cw.y * yi;
+                    s.w += cw.x * yi + cw.y * yr;
+                }
+            }
+            if ((row + col) & 1) s = make_float4(-s.x, -s.y, -s.z, -s.w);
+        }
+        b0[i] = s;
+    }
+    __syncthreads();
+    const float4 *res = fft_lines(b0, b1, N, N, rad, tw);
+    float4 *out = scratch + (int64_t)t * scratch_t + ch.scratch_off;
+    for (int i = threadIdx.x; i < BL * N; i += BT) {
+        const int row = r0 + i / N;
+        if (row <= ch.row_hi) out[(int64_t)(row - ch.row_lo) * N + i % N] = res[i];
+    }
+}
+
+// Pass 2.  Grid: (N / BL column bands, channels of one grid side).  Thread
+// tid owns the band pixels i = tid + k BT (row i / BL, column i % BL),
+// k < N / 32, and loads the same positions of each sample's row transforms.
+template <int P>
+__global__ __launch_bounds__(BT) void k_band_cols(const BandChan *__restrict__ chans, int N,
+                                                  BandRadices rad, const float2 *__restrict__ tw,
+                                                  const float4 *__restrict__ scratch,
+                                                  int64_t scratch_t, int nt,
+                                                  float *__restrict__ acc) {
+    extern __shared__ float4 lds[];
+    constexpr int NPROD = P == 2 ? 4 : 1;
+    const BandChan ch = chans[blockIdx.y];
+    const int c0 = blockIdx.x * BL;
+    const int npix = N * BL / BT;
+    const int LP = N + 1;   // column pitch in LDS
+    float4 *b0 = lds, *b1 = lds + BL * LP;
+    const float4 *src = scratch + ch.scratch_off + c0;
+    float av[MAXPIX][NPROD];
+    float4 pre[MAXPIX];
+#pragma unroll
+    for (int k = 0; k < MAXPIX; ++k) {
+#pragma unroll
+        for (int q = 0; q < NPROD; ++q) av[k][q] = 0.f;
+        pre[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < MAXPIX; ++k) {
+        const int i = threadIdx.x + k * BT;
+        const int row = i / BL, col = i % BL;
+        if (k < npix && row >= ch.row_lo && row <= ch.row_hi)
+            pre[k] = src[(int64_t)(row - ch.row_lo) * N + col];
+    }
+    for (int t = 0; t < nt; ++t) {
+#pragma unroll
+        for (int k = 0; k < MAXPIX; ++k) {
+            const int i = threadIdx.x + k * BT;
+            if (k < npix) b0[(i % BL) * LP + i / BL] = pre[k];
+        }
+        __syncthreads();
+        if (t + 1 < nt) {
+            const float4 *nx = src + (int64_t)(t + 1) * scratch_t;
+#pragma unroll
+            for (int k = 0; k < MAXPIX; ++k) {
+                const int i = threadIdx.x + k * BT;
+                const int row = i / BL, col = i % BL;
+                if (k < npix && row >= ch.row_lo && row <= ch.row_hi)
+                    pre[k] = nx[(int64_t)(row - ch.row_lo) * N + col];
+            }
+        }
+        const float4 *res = fft_lines(b0, b1, N, LP, rad, tw);
+#pragma unroll
+        for (int k = 0; k < MAXPIX; ++k) {
+            if (k < npix) {
+                const int i = threadIdx.x + k * BT;
+                const float4 e = res[(i % BL) * LP + i / BL];
+                av[k][0] += e.x * e.x + e.y * e.y;
+                if (P == 2) {
+                    av[k][1] += e.z * e.z + e.w * e.w;
+                    av[k][2] += e.x * e.z + e.y * e.w;
+                    av[k][3] += e.y * e.z - e.x * e.w;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t plane = (int64_t)N * N;
+#pragma unroll
+    for (int k = 0; k < MAXPIX; ++k) {
+        if (k < npix) {
+            const int i = threadIdx.x + k * BT;
+            float *dst = acc + ch.img_off + (int64_t)(i / BL) * N + c0 + i % BL;
+#pragma unroll
+            for (int q = 0; q < NPROD; ++q) dst[q * plane] += av[k][q];
+        }
+    }
+}
+
+// ------------------------------------------------------------ N = R x R
+// Pitch (float4) of one line in the exchange buffer: positions
+// j (R + 1) + q keep the R lanes of a line in distinct LDS banks, and the
+// +2 skews neighbouring lines.
+template <int R>
+constexpr int sq_pitch() {
+    return R * (R + 1) + 2;
+}
+
+// Pass 1, N = R x R.  One workgroup per (item, sample): thread (l, j) =
+// (tid / R, tid % R) owns line l of the band in both steps.
+template <int R, int P>
+__global__ __launch_bounds__(BL * R) void k_band_rows_sq(
+    const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
+    const BandItem *__restrict__ items, int n_items, int nt, int64_t per_xcd,
+    const uint4 *__restrict__ entries, int A, const float2 *__restrict__ tw,
+    float4 *__restrict__ scratch, int64_t scratch_t) {
+    constexpr int N = R * R, T = BL * R, LP = sq_pitch<R>();
+    constexpr int UN = 8;   // gather entries in flight per lane
+    extern __shared__ float4 lds[];
+    const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (w >= (int64_t)n_items * nt) return;
+    const int t = (int)(w % nt);
+    const BandItem it = items[w / nt];
+    const BandChan ch = chans[it.chan];
+    const int tid = threadIdx.x;
+    const int l = tid / R, j = tid % R;
+    float2 twr[R];
+#pragma unroll
+    for (int q = 1; q < R; ++q) twr[q] = tw[q * j];
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < R; ++k) lds[tid + k * T] = zero;
+    __syncthreads();
+    // gather: each lane sums its own cells, entries [iter][lane]
+    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A;
+    const uint4 *ent = entries + it.entry_off + tid;
+    float4 s = zero;
+    for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
+        uint4 e[UN];
+#pragma unroll
+        for (int k = 0; k < UN; ++k)
+            e[k] = (i0 + k < it.n_iter) ? ent[(int64_t)(i0 + k) * T] : make_uint4(0u, 0u, 0u, 0u);
+        uint32_t bx[UN], by[UN];
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+            const uint32_t a = e[k].x & 0x7fffffffu;
+            bx[k] = vx[a];
+            by[k] = P == 2 ? vx[A + a] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+            const float wr = __builtin_bit_cast(float, e[k].z);
+            const float wi = __builtin_bit_cast(float, e[k].w);
+            const float xr = (float)dec_re(bx[k]), xi = (float)dec_im(bx[k]);
+            s.x += wr * xr - wi * xi;
+            s.y += wr * xi + wi * xr;
+            if (P == 2) {
+                const float yr = (float)dec_re(by[k]), yi = (float)dec_im(by[k]);
+                s.z += wr * yr - wi * yi;
+                s.w += wr * yi + wi * yr;
+            }
+            if (e[k].x & 0x80000000u) {
+                lds[e[k].y] = s;
+                s = zero;
+            }
+        }
+    }
+    __syncthreads();
+    // step 1: R-point DFTs over the elements j + q R of line l
+    float4 v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = lds[l * N + j + q * R];
+    dft<R>(v);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) lds[l * LP + j * (R + 1) + q] = v[q];
+    __syncthreads();
+    // step 2: twiddles, R-point DFTs over the step-1 outputs j + q R
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const float4 x = lds[l * LP + j + q * (R + 1)];
+        v[q] = q ? q_mul(x, twr[q]) : x;
+    }
+    dft<R>(v);
+    const int row = ch.row_lo + it.band * BL + l;
+    if (row <= ch.row_hi) {
+        float4 *out = scratch + (int64_t)t * scratch_t + ch.scratch_off +
+                      (int64_t)(row - ch.row_lo) * N + j;
+#pragma unroll
+        for (int q = 0; q < R; ++q) out[q * R] = v[q];
+    }
+}
+
+// Pass 2, N = R x R.  Grid: (N / BL column bands, channels of this side).
+// Thread (l, j) = (tid % BL, tid / BL) takes column l: rows j + q R in step 1
+// (loaded straight from the scratch, next sample in flight), pixels
+// (j + q R, c0 + l) in step 2, whose Eq. 2 products it keeps in registers.
+template <int R, int P>
+__global__ __launch_bounds__(BL * R) __attribute__((amdgpu_waves_per_eu(2))) void k_band_cols_sq(const BandChan *__restrict__ chans,
+                                                         const float2 *__restrict__ tw,
+                                                         const float4 *__restrict__ scratch,
+                                                         int64_t scratch_t, int nt,
+                                                         float *__restrict__ acc) {
+    constexpr int N = R * R, T = BL * R, LP = sq_pitch<R>();
+    constexpr int NPROD = P == 2 ? 4 : 1;
+    extern __shared__ float4 lds[];
+    float2 *twl = reinterpret_cast<float2 *>(lds + BL * LP);   // exp(+2 pi i n / N), n < N
+    const BandChan ch = chans[blockIdx.y];
+    const int c0 = blockIdx.x * BL;
+    const int tid = threadIdx.x;
+    const int l = tid % BL, j = tid / BL;
+    for (int n = tid; n < N; n += T) twl[n] = tw[n];
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 *src = scratch + ch.scratch_off + c0 + l;
+    float4 pre[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = j + q * R;
+        pre[q] = zero;
+        if (r >= ch.row_lo && r <= ch.row_hi) pre[q] = src[(int64_t)(r - ch.row_lo) * N];
+    }
+    float av[R][NPROD];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int k = 0; k < NPROD; ++k) av[q][k] = 0.f;
+    for (int t = 0; t < nt; ++t) {
+        float4 v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = pre[q];
+        if (t + 1 < nt) {
+            const float4 *nx = src + (int64_t)(t + 1) * scratch_t;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int r = j + q * R;
+                pre[q] = zero;
+                if (r >= ch.row_lo && r <= ch.row_hi) pre[q] = nx[(int64_t)(r - ch.row_lo) * N];
+            }
+        }
+        dft<R>(v);
+#pragma unroll
+        for (int q = 0; q < R; ++q) lds[l * LP + j * (R + 1) + q] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const float4 x = lds[l * LP + j + q * (R + 1)];
+            v[q] = q ? q_mul(x, twl[q * j]) : x;
+        }
+        dft<R>(v);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const float4 e = v[q];
+            av[q][0] += e.x * e.x + e.y * e.y;
+            if (P == 2) {
+                av[q][1] += e.z * e.z + e.w * e.w;
+                av[q][2] += e.x * e.z + e.y * e.w;
+                av[q][3] += e.y * e.z - e.x * e.w;
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t plane = (int64_t)N * N;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        float *dst = acc + ch.img_off + (int64_t)(j + q * R) * N + c0 + l;
+#pragma unroll
+        for (int k = 0; k < NPROD; ++k) dst[k * plane] += av[q][k];
+    }
+}
+
+static int square_radix(int N) {
+    return N == 256 ? 16 : N == 64 ? 8 : 0;
+}
+
+// Per-band lane lists of one channel: taps conj(W) (-1)^(jx+jy) of every
+// element footprint cell in the band, cell index (row - r0) N + col.
+static epic_status band_items(epic_plan p, const std::vector<int> &j0,
+                              const std::vector<double> &w, const BandChan &b, int chan_index,
+                              int T, std::vector<BandItem> &items, std::vector<uint4> &all) {
+    const int A = p->A, K = p->K, N = b.N, c = b.c;
+    const int n_bands = (b.row_hi - b.row_lo + 1 + BL - 1) / BL;
+    std::vector<std::vector<GatherTap>> per(n_bands);
+    for (int a = 0; a < A; ++a) {
+        const int jx0 = j0[((size_t)c * A + a) * 2], jy0 = j0[((size_t)c * A + a) * 2 + 1];
+        for (int dy = 0; dy < K; ++dy)
+            for (int dx = 0; dx < K; ++dx) {
+                const int row = jy0 + dy, col = jx0 + dx;
+                const int band = (row - b.row_lo) / BL, r0 = b.row_lo + band * BL;
+                const size_t wi = (((size_t)c * A + a) * K * K + dy * K + dx) * 2;
+                const double sg = ((row + col) & 1) ? -1.0 : 1.0;
+                GatherTap tp;
+                tp.cell = (row - r0) * N + col;
+                tp.ant = a;
+                tp.wr = (float)(sg * w[wi]);
+                tp.wi = (float)(-sg * w[wi + 1]);
+                per[band].push_back(tp);
+            }
+    }
+    for (int band = 0; band < n_bands; ++band) {
+        BandItem it{};
+        it.chan = chan_index;
+        it.band = band;
+        it.entry_off = (int64_t)all.size();
+        it.n_iter = lpt_pack(per[band], T, all);
+        items.push_back(it);
+    }
+    return EPIC_OK;
+}
+
+epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
+                         hipStream_t s) {
+    BandPlan &bp = p->band;
+    std::vector<int> sides;
+    for (int c = 0; c < p->C; ++c)
+        if (p->banded[c] && std::find(sides.begin(), sides.end(), p->ch[c].N) == sides.end())
+            sides.push_back(p->ch[c].N);
+    if (sides.empty()) return EPIC_OK;
+    std::vector<BandItem> items;
+    std::vector<uint4> all;
+    int64_t off = 0;
+    for (int N : sides) {
+        BandSize bs;
+        bs.N = N;
+        bs.R = square_radix(N);
+        bs.chan_off = (int64_t)bp.host.size();
+        bs.tw_off = p->twid_off[N];
+        bs.item_off = (int64_t)items.size();
+        for (int c = 0; c < p->C; ++c) {
+            if (!p->banded[c] || p->ch[c].N != N) continue;
+            int lo = 1 << 30, hi = -1;
+            for (int a = 0; a < p->A; ++a) {
+                const int jy = j0[((size_t)c * p->A + a) * 2 + 1];
+                lo = std::min(lo, jy);
+                hi = std::max(hi, jy + p->K - 1);
+            }
+            BandChan b{};
+            b.c = c;
+            b.N = N;
+            b.row_lo = lo;
+            b.row_hi = hi;
+            b.img_off = p->ch[c].img_off;
+            b.scratch_off = off;
+            off += (int64_t)(hi - lo + 1) * N;
+            // items index the channels of their own size group
+            if (bs.R)
+                band_items(p, j0, w, b, (int)(bp.host.size() - bs.chan_off), BL * bs.R, items,
+                           all);
+            bp.host.push_back(b);
+            bs.max_bands = std::max(bs.max_bands, (hi - lo + 1 + BL - 1) / BL);
+            ++bs.n;
+        }
+        bs.n_items = (int64_t)items.size() - bs.item_off;
+        bp.sizes.push_back(bs);
+    }
+    bp.n = (int)bp.host.size();
+    bp.scratch_t = off;
+    // samples per round: keep the scratch near 1 GiB
+    const int64_t per_t = off * (int64_t)sizeof(float4);
+    bp.t_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (1LL << 30) / per_t));
+    bp.scratch_bytes = per_t * bp.t_chunk;
+    epic_status st;
+    if ((st = bp.d_chans.alloc(sizeof(BandChan) * bp.host.size()))) return st;
+    EPIC_HIP(hipMemcpyAsync(bp.d_chans.p, bp.host.data(), sizeof(BandChan) * bp.host.size(),
+                            hipMemcpyHostToDevice, s));
+    if (!items.empty()) {
+        if ((st = bp.d_items.alloc(sizeof(BandItem) * items.size()))) return st;
+        if ((st = bp.d_entries.alloc(sizeof(uint4) * std::max<size_t>(1, all.size())))) return st;
+        EPIC_HIP(hipMemcpyAsync(bp.d_items.p, items.data(), sizeof(BandItem) * items.size(),
+                                hipMemcpyHostToDevice, s));
+        if (!all.empty())
+            EPIC_HIP(hipMemcpyAsync(bp.d_entries.p, all.data(), sizeof(uint4) * all.size(),
+                                    hipMemcpyHostToDevice, s));
+    }
+    EPIC_HIP(hipStreamSynchronize(s));
+    return EPIC_OK;
+}
+
+template <int R>
+static const void *rows_sq_kernel(int P) {
+    return P == 2 ? reinterpret_cast<const void *>(k_band_rows_sq<R, 2>)
+                  : reinterpret_cast<const void *>(k_band_rows_sq<R, 1>);
+}
+template <int R>
+static const void *cols_sq_kernel(int P) {
+    return P == 2 ? reinterpret_cast<const void *>(k_band_cols_sq<R, 2>)
+                  : reinterpret_cast<const void *>(k_band_cols_sq<R, 1>);
+}
+
+template <int R, int P>
+static epic_status launch_sq(epic_plan p, const BandSize &bs, const uint8_t *d_volt, int nt,
+                             float4 *scratch, float *acc, hipStream_t s) {
+    const BandPlan &bp = p->band;
+    constexpr int T = BL * R;
+    const size_t lds = sizeof(float4) * BL * sq_pitch<R>();
+    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    const int64_t total = bs.n_items * nt;
+    const int64_t per_xcd = (total + 7) / 8;
+    if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
+    const float2 *tw = p->d_twid.as<float2>() + bs.tw_off;
+    hipLaunchKernelGGL((k_band_rows_sq<R, P>), dim3((unsigned)(8 * per_xcd)), dim3(T), lds, s,
+                       d_volt, vstride, bp.d_chans.as<BandChan>() + bs.chan_off,
+                       bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, nt, per_xcd,
+                       bp.d_entries.as<uint4>(), p->A, tw, scratch, bp.scratch_t);
+    EPIC_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_band_cols_sq<R, P>), dim3(bs.N / BL, bs.n), dim3(T),
+                       lds + sizeof(float2) * bs.N, s,
+                       bp.d_chans.as<BandChan>() + bs.chan_off, tw, scratch, bp.scratch_t, nt,
+                       acc);
+    EPIC_HIP(hipGetLastError());
+    return EPIC_OK;
+}
+
+epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                              hipStream_t s, bool dry) {
+    const BandPlan &bp = p->band;
+    if (bp.n == 0) return EPIC_OK;
+    for (const BandSize &bs : bp.sizes) {
+        epic_status st = EPIC_OK;
+        if (bs.R == 16) {
+            const size_t lds = sizeof(float4) * BL * sq_pitch<16>();
+            st = lds_ready(rows_sq_kernel<16>(p->P), lds);
+            if (!st) st = lds_ready(cols_sq_kernel<16>(p->P), lds + sizeof(float2) * bs.N);
+        } else if (bs.R == 8) {
+            const size_t lds = sizeof(float4) * BL * sq_pitch<8>();
+            st = lds_ready(rows_sq_kernel<8>(p->P), lds);
+            if (!st) st = lds_ready(cols_sq_kernel<8>(p->P), lds + sizeof(float2) * bs.N);
+        } else {
+            const size_t lds1 = sizeof(float4) * 2 * BL * bs.N;
+            const size_t lds2 = sizeof(float4) * 2 * BL * (bs.N + 1);
+            st = lds_ready(reinterpret_cast<const void *>(k_band_rows), lds1);
+            if (!st)
+                st = lds_ready(p->P == 2 ? reinterpret_cast<const void *>(k_band_cols<2>)
+                                         : reinterpret_cast<const void *>(k_band_cols<1>),
+                               lds2);
+        }
+        if (st) return st;
+    }
+    if (dry) return EPIC_OK;
+    if (!acc->d_work.p || acc->d_work.bytes < (size_t)bp.scratch_bytes)
+        return fail(EPIC_ERR_ARG, "accumulator has no scratch for the banded path");
+    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    float4 *scratch = acc->d_work.as<float4>();
+    float *a = acc->d_acc.as<float>();
+    const BandChan *chans = bp.d_chans.as<BandChan>();
+    for (int t0 = 0; t0 < n_time; t0 += bp.t_chunk) {
+        const int nt = std::min(bp.t_chunk, n_time - t0);
+        const uint8_t *v = d_volt + (int64_t)t0 * vstride;
+        for (const BandSize &bs : bp.sizes) {
+            epic_status st = EPIC_OK;
+            if (bs.R == 16)
+                st = p->P == 2 ? launch_sq<16, 2>(p, bs, v, nt, scratch, a, s)
+                               : launch_sq<16, 1>(p, bs, v, nt, scratch, a, s);
+            else if (bs.R == 8)
+                st = p->P == 2 ? launch_sq<8, 2>(p, bs, v, nt, scratch, a, s)
+                               : launch_sq<8, 1>(p, bs, v, nt, scratch, a, s);
+            if (st) return st;
+            if (bs.R) continue;
+            const int64_t total = (int64_t)bs.n * bs.max_bands * nt;
+            const int64_t per_xcd = (total + 7) / 8;
+            if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
+            hipLaunchKernelGGL(k_band_rows, dim3((unsigned)(8 * per_xcd)), dim3(BT),
+                               sizeof(float4) * 2 * BL * bs.N, s, v, vstride, chans + bs.chan_off,
+                               bs.n, bs.max_bands, nt, per_xcd, p->d_csr_base.as<int64_t>(),
+                               p->d_csr_off.as<int32_t>(), p->d_csr_ant.as<int32_t>(),
+                               p->d_csr_w.as<float2>(), p->A, p->P, bs.N, radices_of(bs.N),
+                               p->d_twid.as<float2>() + bs.tw_off, scratch, bp.scratch_t);
+            EPIC_HIP(hipGetLastError());
+            const dim3 grid(bs.N / BL, bs.n);
+            const size_t lds = sizeof(float4) * 2 * BL * (bs.N + 1);
+            if (p->P == 2)
+                hipLaunchKernelGGL(k_band_cols<2>, grid, dim3(BT), lds, s, chans + bs.chan_off,
+                                   bs.N, radices_of(bs.N), p->d_twid.as<float2>() + bs.tw_off,
+                                   scratch, bp.scratch_t, nt, a);
+            else
+                hipLaunchKernelGGL(k_band_cols<1>, grid, dim3(BT), lds, s, chans + bs.chan_off,
+                                   bs.N, radices_of(bs.N), p->d_twid.as<float2>() + bs.tw_off,
+                                   scratch, bp.scratch_t, nt, a);
+            EPIC_HIP(hipGetLastError());
+        }
+    }
+    return EPIC_OK;
+}
+
+}  // namespace epic

@@ -397,16 +397,18 @@ epic_status gemm_build(epic_plan p, hipStream_t s) {
     const int eb = p->precision == EPIC_F8E4M3_MFMA ? 1 : 2;
     gp.t_chunk = 256;
     gp.cols_pad = ((gp.t_chunk * p->P + 15) / 16) * 16;
-    return gp.vbuf.alloc((size_t)p->C * gp.cols_pad * 2 * gp.Ap * eb);
+    gp.vbuf_bytes = (int64_t)p->C * gp.cols_pad * 2 * gp.Ap * eb;
+    return EPIC_OK;
 }
 
 template <int DT, int P, int RB, int KS>
-static epic_status launch_gemm(epic_plan p, float *acc, int cols_pad, hipStream_t s) {
+static epic_status launch_gemm(epic_plan p, float *acc, const uint8_t *vbuf, int cols_pad,
+                               hipStream_t s) {
     GemmPlan &gp = p->gemm;
     const int rows_max = 2 * p->max_n * p->max_n;
     dim3 g((rows_max + 8 * RB * 16 - 1) / (8 * RB * 16), p->C);
     hipLaunchKernelGGL((k_dftgemm<DT, P, RB, KS>), g, dim3(512), 0, s, gp.a_hi.as<uint8_t>(),
-                       gp.a_lo.as<uint8_t>(), gp.vbuf.as<uint8_t>(), p->d_chan.as<int4>(),
+                       gp.a_lo.as<uint8_t>(), vbuf, p->d_chan.as<int4>(),
                        gp.d_blk_off.as<int64_t>(), p->d_img_off.as<int64_t>(),
                        gp.d_inv_s2.as<float>(), gp.Ap, cols_pad, acc);
     EPIC_HIP(hipGetLastError());
@@ -414,30 +416,31 @@ static epic_status launch_gemm(epic_plan p, float *acc, int cols_pad, hipStream_
 }
 
 template <int DT, int P>
-static epic_status launch_gemm_ks(epic_plan p, float *acc, int cols_pad, hipStream_t s) {
+static epic_status launch_gemm_ks(epic_plan p, float *acc, const uint8_t *vbuf, int cols_pad,
+                                  hipStream_t s) {
     constexpr int RB = DT == EPIC_F8E4M3_MFMA ? 4 : DT == EPIC_F16_MFMA ? 2 : 1;
     switch (p->gemm.KS) {
-        case 1: return launch_gemm<DT, P, RB, 1>(p, acc, cols_pad, s);
-        case 2: return launch_gemm<DT, P, RB, 2>(p, acc, cols_pad, s);
-        case 4: return launch_gemm<DT, P, RB, 4>(p, acc, cols_pad, s);
-        case 8: return launch_gemm<DT, P, RB, 8>(p, acc, cols_pad, s);
-        case 16: return launch_gemm<DT, P, RB, 16>(p, acc, cols_pad, s);
+        case 1: return launch_gemm<DT, P, RB, 1>(p, acc, vbuf, cols_pad, s);
+        case 2: return launch_gemm<DT, P, RB, 2>(p, acc, vbuf, cols_pad, s);
+        case 4: return launch_gemm<DT, P, RB, 4>(p, acc, vbuf, cols_pad, s);
+        case 8: return launch_gemm<DT, P, RB, 8>(p, acc, vbuf, cols_pad, s);
+        case 16: return launch_gemm<DT, P, RB, 16>(p, acc, vbuf, cols_pad, s);
     }
     return fail(EPIC_ERR_UNSUPPORTED, "K steps");
 }
 
 template <int DT>
-static epic_status gemm_chunk(epic_plan p, float *acc, const uint8_t *d_volt, int nt, hipStream_t s) {
+static epic_status gemm_chunk(epic_plan p, float *acc, uint8_t *vbuf, const uint8_t *d_volt, int nt,
+                              hipStream_t s) {
     GemmPlan &gp = p->gemm;
     const int cols_pad = ((nt * p->P + 15) / 16) * 16;
     const int64_t tot = (int64_t)p->C * cols_pad * gp.Ap;
     const int64_t vstride = (int64_t)p->C * p->P * p->A;
     hipLaunchKernelGGL(k_volt_operand<DT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                       d_volt, vstride, p->A, gp.Ap, p->P, p->C, nt, cols_pad,
-                       gp.vbuf.as<uint8_t>());
+                       d_volt, vstride, p->A, gp.Ap, p->P, p->C, nt, cols_pad, vbuf);
     EPIC_HIP(hipGetLastError());
-    return p->P == 2 ? launch_gemm_ks<DT, 2>(p, acc, cols_pad, s)
-                     : launch_gemm_ks<DT, 1>(p, acc, cols_pad, s);
+    return p->P == 2 ? launch_gemm_ks<DT, 2>(p, acc, vbuf, cols_pad, s)
+                     : launch_gemm_ks<DT, 1>(p, acc, vbuf, cols_pad, s);
 }
 
 epic_status gemm_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
@@ -447,11 +450,12 @@ epic_status gemm_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, in
     for (int t0 = 0; t0 < n_time; t0 += gp.t_chunk) {
         const int nt = std::min(gp.t_chunk, n_time - t0);
         const uint8_t *v = d_volt + (int64_t)t0 * vstride;
+        uint8_t *vb = acc->d_work.as<uint8_t>();
         epic_status st;
         switch (p->precision) {
-            case EPIC_F16_MFMA: st = gemm_chunk<EPIC_F16_MFMA>(p, acc->d_acc.as<float>(), v, nt, s); break;
-            case EPIC_BF16X2_MFMA: st = gemm_chunk<EPIC_BF16X2_MFMA>(p, acc->d_acc.as<float>(), v, nt, s); break;
-            case EPIC_F8E4M3_MFMA: st = gemm_chunk<EPIC_F8E4M3_MFMA>(p, acc->d_acc.as<float>(), v, nt, s); break;
+            case EPIC_F16_MFMA: st = gemm_chunk<EPIC_F16_MFMA>(p, acc->d_acc.as<float>(), vb, v, nt, s); break;
+            case EPIC_BF16X2_MFMA: st = gemm_chunk<EPIC_BF16X2_MFMA>(p, acc->d_acc.as<float>(), vb, v, nt, s); break;
+            case EPIC_F8E4M3_MFMA: st = gemm_chunk<EPIC_F8E4M3_MFMA>(p, acc->d_acc.as<float>(), vb, v, nt, s); break;
             default: return fail(EPIC_ERR_UNSUPPORTED, "unknown precision");
         }
         if (st) return st;

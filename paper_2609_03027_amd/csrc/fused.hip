@@ -558,45 +558,14 @@ static int row_of(int M) {
     return M == 64 ? FCfg<64>::ROW : M == 32 ? FCfg<32>::ROW : FCfg<16>::ROW;
 }
 
-namespace {
-struct Tap {
-    int cell, ant;
-    float wr, wi;
-};
-}  // namespace
-
-// Gather entries of one item: the taps of class (ox, oy) folded modulo M,
-// grouped by cell; cells are dealt longest-first to the least-loaded of T
-// lanes, so each cell is summed by one lane in a fixed order and written once.
-static FusedItem build_item(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
-                            int c, int ox, int oy, int M, int T, std::vector<uint4> &all) {
-    const int A = p->A, K = p->K;
-    const int N = p->ch[c].N, R = p->ch[c].R, ROW = row_of(M);
-    std::vector<Tap> taps((size_t)A * K * K);
-    size_t n = 0;
-    for (int a = 0; a < A; ++a) {
-        const int jx0 = j0[((size_t)c * A + a) * 2];
-        const int jy0 = j0[((size_t)c * A + a) * 2 + 1];
-        for (int dy = 0; dy < K; ++dy)
-            for (int dx = 0; dx < K; ++dx) {
-                const int jx = jx0 + dx, jy = jy0 + dy;
-                const size_t wi = (((size_t)c * A + a) * K * K + dy * K + dx) * 2;
-                // conj(W) * (-1)^(jx+jy) * exp(+2 pi i (ox jx + oy jy) / N)
-                const double wr0 = w[wi], wi0 = -w[wi + 1];
-                const long ph = ((long)ox * jx + (long)oy * jy) % N;
-                const double ang = 2.0 * M_PI * (double)ph / (double)N;
-                const double sg = ((jx + jy) & 1) ? -1.0 : 1.0;
-                const double cr = std::cos(ang) * sg, ci = std::sin(ang) * sg;
-                Tap tp;
-                tp.cell = (jy % M) * ROW + (jx % M);
-                tp.ant = a;
-                tp.wr = (float)(wr0 * cr - wi0 * ci);
-                tp.wi = (float)(wr0 * ci + wi0 * cr);
-                taps[n++] = tp;
-            }
-    }
-    std::stable_sort(taps.begin(), taps.begin() + n,
-                     [](const Tap &x, const Tap &y) { return x.cell < y.cell; });
+// Cells are dealt longest-first to the least-loaded of T lanes, so each cell
+// is summed by one lane in a fixed order and written once.  Appends
+// n_iter * T entries [iter][lane] to all (padding entries are zero) and
+// returns n_iter.
+int lpt_pack(std::vector<GatherTap> &taps, int T, std::vector<uint4> &all) {
+    const size_t n = taps.size();
+    std::stable_sort(taps.begin(), taps.end(),
+                     [](const GatherTap &x, const GatherTap &y) { return x.cell < y.cell; });
     std::vector<std::pair<int, int>> runs;  // (start, count) per cell
     for (size_t i = 0; i < n;) {
         size_t k = i;
@@ -627,7 +596,7 @@ static FusedItem build_item(epic_plan p, const std::vector<int> &j0, const std::
         int k = 0;
         for (int r : lane_runs[l])
             for (int i = 0; i < runs[r].second; ++i, ++k) {
-                const Tap &tp = taps[runs[r].first + i];
+                const GatherTap &tp = taps[runs[r].first + i];
                 const bool last = (i == runs[r].second - 1);
                 uint4 e;
                 e.x = (uint32_t)tp.ant | (last ? 0x80000000u : 0u);
@@ -637,6 +606,39 @@ static FusedItem build_item(epic_plan p, const std::vector<int> &j0, const std::
                 all[off + (size_t)k * T + l] = e;
             }
     }
+    return n_iter;
+}
+
+// Gather entries of one item: the taps of class (ox, oy) folded modulo M.
+static FusedItem build_item(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
+                            int c, int ox, int oy, int M, int T, std::vector<uint4> &all) {
+    const int A = p->A, K = p->K;
+    const int N = p->ch[c].N, R = p->ch[c].R, ROW = row_of(M);
+    std::vector<GatherTap> taps;
+    taps.reserve((size_t)A * K * K);
+    for (int a = 0; a < A; ++a) {
+        const int jx0 = j0[((size_t)c * A + a) * 2];
+        const int jy0 = j0[((size_t)c * A + a) * 2 + 1];
+        for (int dy = 0; dy < K; ++dy)
+            for (int dx = 0; dx < K; ++dx) {
+                const int jx = jx0 + dx, jy = jy0 + dy;
+                const size_t wi = (((size_t)c * A + a) * K * K + dy * K + dx) * 2;
+                // conj(W) * (-1)^(jx+jy) * exp(+2 pi i (ox jx + oy jy) / N)
+                const double wr0 = w[wi], wi0 = -w[wi + 1];
+                const long ph = ((long)ox * jx + (long)oy * jy) % N;
+                const double ang = 2.0 * M_PI * (double)ph / (double)N;
+                const double sg = ((jx + jy) & 1) ? -1.0 : 1.0;
+                const double cr = std::cos(ang) * sg, ci = std::sin(ang) * sg;
+                GatherTap tp;
+                tp.cell = (jy % M) * ROW + (jx % M);
+                tp.ant = a;
+                tp.wr = (float)(wr0 * cr - wi0 * ci);
+                tp.wi = (float)(wr0 * ci + wi0 * cr);
+                taps.push_back(tp);
+            }
+    }
+    const size_t off = all.size();
+    const int n_iter = lpt_pack(taps, T, all);
     FusedItem fi{};
     fi.c = c;
     fi.N = N;
@@ -705,7 +707,7 @@ epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vect
     // Paired items: two feeds, N = 2 * 64, every element row in a 64-row window.
     std::vector<int> pair_ylo(p->C, -1);
     for (int c = 0; c < p->C; ++c) {
-        if (p->P != 2 || p->ch[c].M != 64 || p->ch[c].R != 2) continue;
+        if (p->banded[c] || p->P != 2 || p->ch[c].M != 64 || p->ch[c].R != 2) continue;
         int lo = 1 << 30, hi = -1;
         for (int a = 0; a < A; ++a) {
             const int jy = j0[((size_t)c * A + a) * 2 + 1];
@@ -739,7 +741,7 @@ epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vect
         std::vector<uint4> all;
         const int T = threads_of(M);
         for (int c = 0; c < p->C; ++c) {
-            if (p->ch[c].M != M || pair_ylo[c] >= 0) continue;
+            if (p->banded[c] || p->ch[c].M != M || pair_ylo[c] >= 0) continue;
             const int R = p->ch[c].R;
             for (int oy = 0; oy < R; ++oy)
                 for (int ox = 0; ox < R; ++ox) items.push_back(build_item(p, j0, w, c, ox, oy, M, T, all));
@@ -754,8 +756,7 @@ epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vect
     return EPIC_OK;
 }
 
-// Allow a kernel the device's whole LDS once, then check the launch's need.
-static epic_status lds_ready(const void *kern, size_t lds) {
+epic_status lds_ready(const void *kern, size_t lds) {
     static int lds_max = -1;
     static std::vector<const void *> done;
     if (lds_max < 0) {
@@ -769,7 +770,7 @@ static epic_status lds_ready(const void *kern, size_t lds) {
         done.push_back(kern);
     }
     if ((int64_t)lds > lds_max)
-        return fail(EPIC_ERR_UNSUPPORTED, "fused path: LDS need " + std::to_string(lds) +
+        return fail(EPIC_ERR_UNSUPPORTED, "LDS need " + std::to_string(lds) +
                                               " B above the device limit");
     return EPIC_OK;
 }
@@ -831,8 +832,9 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
     const int64_t vstride = (int64_t)p->C * p->P * p->A;
     float *a = acc ? acc->d_acc.as<float>() : nullptr;
     // The fused kernels add the self-term sums when every group's threads
-    // cover the elements in at most four rounds; otherwise a separate pass.
-    bool in_kernel = true;
+    // cover the elements in at most four rounds and no channel is banded;
+    // otherwise a separate pass does it for every channel.
+    bool in_kernel = p->band.n == 0;
     for (const FusedGroup *g : p->groups)
         if (p->A > 4 * threads_of(g->M)) in_kernel = false;
     int32_t *au = (in_kernel && acc) ? acc->d_autos.as<int32_t>() : nullptr;
@@ -852,6 +854,10 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
             if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
             if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
         }
+        if (st) return st;
+    }
+    if (p->band.n) {
+        epic_status st = banded_accumulate(p, acc, d_volt, n_time, s, dry);
         if (st) return st;
     }
     if (dry || in_kernel) return EPIC_OK;

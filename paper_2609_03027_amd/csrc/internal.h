@@ -98,7 +98,55 @@ struct GemmPlan {
     DevBuf d_blk_off;     // int64 [C] first row block of each channel
     DevBuf d_scale;       // float [C] power-of-two operand scale
     DevBuf d_inv_s2;      // float [C] 1 / scale^2 applied to the sums
-    DevBuf vbuf;          // voltage operand for one chunk
+    int64_t vbuf_bytes = 0; // voltage operand for one chunk (in the accumulator's work buffer)
+};
+
+// Banded two-pass path: one channel's geometry.
+struct BandChan {
+    int32_t c;
+    int32_t N;
+    int32_t row_lo, row_hi;  // grid rows touched by any element footprint
+    int64_t img_off;         // float offset of channel c in the image set
+    int64_t scratch_off;     // float4 offset of channel c in one sample of row transforms
+};
+
+// Radix sequence of an N-point transform (4s, then 2s, then 3s).
+struct BandRadices {
+    int32_t n;
+    int32_t r[12];
+};
+
+// One (channel, 8-row band) of a square-radix grid side: its gather entries.
+struct BandItem {
+    int32_t chan;            // channel within its size group's BandChan range
+    int32_t band;
+    int32_t n_iter;          // gather iterations per lane
+    int32_t pad;
+    int64_t entry_off;       // first uint4 entry
+};
+
+// Banded channels of one grid side.
+struct BandSize {
+    int N = 0;
+    int R = 0;               // N = R * R with R in {8, 16}: two-step kernels; 0: generic
+    int n = 0;               // channels
+    int max_bands = 0;       // 8-row bands of the widest footprint span
+    int64_t chan_off = 0;    // first BandChan of this size
+    int64_t tw_off = 0;      // twiddle table offset for N
+    int64_t item_off = 0;    // first BandItem (R != 0)
+    int64_t n_items = 0;
+};
+
+struct BandPlan {
+    int n = 0;               // banded channels
+    int t_chunk = 0;         // samples per pass-1/pass-2 round
+    int64_t scratch_t = 0;   // float4 per sample of row transforms
+    int64_t scratch_bytes = 0;
+    std::vector<BandSize> sizes;
+    std::vector<BandChan> host;
+    DevBuf d_chans;          // BandChan[n]
+    DevBuf d_items;          // BandItem[] of the square-radix sizes
+    DevBuf d_entries;        // uint4 gather entries of those items
 };
 
 }  // namespace epic
@@ -146,6 +194,9 @@ struct epic_plan_s {
     // fused path (FP32) or direct DFT-GEMM (MFMA precisions)
     std::vector<epic::FusedGroup *> groups;
     epic::GemmPlan gemm;
+    std::vector<char> banded;     // channel c takes the banded two-pass path
+    epic::BandPlan band;
+    int64_t work_bytes = 0;       // per-accumulator working memory the path needs
 
     int64_t bytes_plan = 0;
     ~epic_plan_s();
@@ -164,6 +215,7 @@ struct epic_acc_s {
     epic::DevBuf d_acc;    // float [image_floats]
     epic::DevBuf d_autos;  // int32 [C][A][n_prod]
     epic::DevBuf d_h;      // double2 [C][NH][(2K-1)^2] read-out scratch (self-term sums)
+    epic::DevBuf d_work;   // plan.work_bytes: operand staging / row-transform scratch
     int64_t count = 0;
 };
 
@@ -180,6 +232,23 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
                              bool dry = false);
 epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                              hipStream_t s);
+// One gather tap: destination cell (LDS index), element, complex weight.
+struct GatherTap {
+    int cell, ant;
+    float wr, wi;
+};
+// Lane-owns-cell packing of taps into [iter][lane] gather entries
+// {ant | last << 31, cell, wr, wi}; returns the iterations per lane.
+int lpt_pack(std::vector<GatherTap> &taps, int T, std::vector<uint4> &all);
+// Allow a kernel the device's whole LDS once, then check a launch's need.
+epic_status lds_ready(const void *kern, size_t lds);
+
+// banded.hip
+bool banded_eligible(int N);
+epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
+                         hipStream_t s);
+epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                              hipStream_t s, bool dry = false);
 
 // staged.hip
 epic_status staged_grid(epic_plan p, const uint8_t *d_volt, int n_time, void *d_grid,

@@ -63,15 +63,29 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     std::vector<int64_t> img_off(C), grid_off(C);
     int64_t io = 0, go = 0;
     p->max_n = 0;
+    p->banded.assign(C, 0);
     for (int c = 0; c < C; ++c) {
         const int N = p->grid_n[c];
         const int want = p->sub_n.empty() ? 0 : p->sub_n[c];
-        const int M = want ? want : pick_m(N);
+        int M = want > 0 ? want : pick_m(N);
         if (N < 8 || (N & 1)) return fail(EPIC_ERR_GRID, "grid side must be even and >= 8");
-        if (M == 0) return fail(EPIC_ERR_GRID, "grid side must be a multiple of 16");
         if (N > 1024) return fail(EPIC_ERR_UNSUPPORTED, "grid side above 1024");
-        p->ch[c] = Chan{N, M, N / M, io, go};
-        chan[c] = make_int4(N, M, N / M, 0);
+        // Banded two-pass path: on request, or by default where the fused
+        // path would split the channel into 16 or more sub-transforms.
+        if (p->precision == EPIC_F32 &&
+            (want < 0 || (want == 0 && M && N / M >= 4 && banded_eligible(N)))) {
+            if (!banded_eligible(N))
+                return fail(EPIC_ERR_UNSUPPORTED, "banded path: grid side must be a multiple "
+                                                  "of 32 with factors 2 and 3, at most 512");
+            p->banded[c] = 1;
+            M = 0;
+        } else if (want < 0) {
+            return fail(EPIC_ERR_UNSUPPORTED, "banded path needs FP32 precision");
+        } else if (M == 0) {
+            return fail(EPIC_ERR_GRID, "grid side must be a multiple of 16");
+        }
+        p->ch[c] = Chan{N, M, M ? N / M : 0, io, go};
+        chan[c] = make_int4(N, M, M ? N / M : 0, 0);
         img_off[c] = io;
         grid_off[c] = go;
         io += (int64_t)p->n_prod * N * N;
@@ -216,8 +230,11 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     p->w_host = w;
     if (p->precision == EPIC_F32) {
         if ((st = fused_build(p, j0, w, s))) return st;
+        if ((st = banded_build(p, j0, w, s))) return st;
+        p->work_bytes = p->band.scratch_bytes;
     } else {
         if ((st = gemm_build(p, s))) return st;
+        p->work_bytes = p->gemm.vbuf_bytes;
     }
 
     p->bytes_plan = 0;
@@ -226,7 +243,9 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
                             &p->d_csr_ant, &p->d_csr_w, &p->d_twid, &p->d_sz_chans})
         p->bytes_plan += (int64_t)b->bytes;
     for (auto *g : p->groups) p->bytes_plan += (int64_t)(g->items.bytes + g->entries.bytes);
-    for (epic::DevBuf *b : {&p->gemm.a_hi, &p->gemm.a_lo, &p->gemm.vbuf, &p->gemm.d_blk_off,
+    p->bytes_plan += (int64_t)(p->band.d_chans.bytes + p->band.d_items.bytes +
+                               p->band.d_entries.bytes);
+    for (epic::DevBuf *b : {&p->gemm.a_hi, &p->gemm.a_lo, &p->gemm.d_blk_off,
                             &p->gemm.d_scale, &p->gemm.d_inv_s2})
         p->bytes_plan += (int64_t)b->bytes;
     return EPIC_OK;

@@ -85,7 +85,7 @@ def test_plan_create_rejects_null_and_odd_grid():
     assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 2
 
 
-@pytest.mark.parametrize("sub", [24, 8, 64])
+@pytest.mark.parametrize("sub", [24, 8, 64, -2])
 def test_plan_create_rejects_bad_sub_transform_sides(sub):
     import paper_2609_03027_amd as E
     lib = E.load()
@@ -94,6 +94,31 @@ def test_plan_create_rejects_bad_sub_transform_sides(sub):
     h = C.c_void_p()
     assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 2
     assert b"sub_n" in lib.epic_last_error()
+
+
+@pytest.mark.parametrize("n,precision", [(48, 0), (40, 0), (1024, 0), (32, 1), (64, 3)])
+def test_plan_create_rejects_banded_requests_it_cannot_serve(n, precision):
+    """The banded path takes FP32 plans and sides 32 k (k = 2^a 3^b) up to
+    512; other requests fail before any device work."""
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    s = np.array([E.SUB_BANDED], dtype=np.int32)
+    gn = np.array([n], dtype=np.int32)
+    d, keep = _desc(sub_n=s.ctypes.data_as(C.POINTER(C.c_int32)),
+                    grid_n=gn.ctypes.data_as(C.POINTER(C.c_int32)), precision=precision)
+    h = C.c_void_p()
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 4
+    assert b"banded" in lib.epic_last_error()
+    assert not h.value
+
+
+def test_autotune_candidates_include_the_banded_path_where_it_applies():
+    from paper_2609_03027_amd import autotune
+    ok = [n for n in range(8, 1025, 2) if autotune.banded_ok(n)]
+    assert ok == [32, 64, 96, 128, 192, 256, 288, 384, 512]
+    assert autotune.candidates(256) == [64, 32, -1]
+    assert autotune.candidates(48) == [16]
+    assert autotune.candidates(96) == [32, 16, -1]
 
 
 def test_graph_calls_reject_null_handles():

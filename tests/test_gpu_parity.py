@@ -32,7 +32,8 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _run(wl, pos, volt, *, fused=True, flags=None, kernels=None, chunks=1, precision=0):
+def _run(wl, pos, volt, *, fused=True, flags=None, kernels=None, chunks=1, precision=0,
+         sub_n=None):
     """Run the GPU path on a block; returns per-channel float64 images."""
     torch = _torch()
     import paper_2609_03027_amd as E
@@ -40,7 +41,7 @@ def _run(wl, pos, volt, *, fused=True, flags=None, kernels=None, chunks=1, preci
     if kernels is not None:
         k = np.stack(kernels)                   # [C][A][K][K] complex
         table = np.stack([k.real, k.imag], axis=-1).astype(np.float32)
-    plan = E.Plan.from_workload(wl, pos, kernel_table=table, precision=precision)
+    plan = E.Plan.from_workload(wl, pos, kernel_table=table, precision=precision, sub_n=sub_n)
     acc = E.Accumulator(plan)
     dv = torch.from_numpy(np.ascontiguousarray(volt)).cuda()
     T = volt.shape[0]
