@@ -382,7 +382,7 @@ __global__ __launch_bounds__(BL * R) void k_band_rows_sq(
     const uint4 *__restrict__ entries, int A, const float2 *__restrict__ tw,
     float4 *__restrict__ scratch, int64_t scratch_t) {
     constexpr int N = R * R, T = BL * R, LP = sq_pitch<R>();
-    constexpr int UN = 8;   // gather entries in flight per lane
+    constexpr int UN = 16;  // gather entries in flight per lane
     extern __shared__ float4 lds[];
     const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (w >= (int64_t)n_items * nt) return;
@@ -400,13 +400,17 @@ __global__ __launch_bounds__(BL * R) void k_band_rows_sq(
     __syncthreads();
     // gather: each lane sums its own cells, entries [iter][lane]
     const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A;
-    const uint4 *ent = entries + it.entry_off + tid;
+    const uint4 *ent = entries + it.entry_off;
     float4 s = zero;
     for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
+        // iterations past n_iter re-read the last one and are dropped
         uint4 e[UN];
 #pragma unroll
         for (int k = 0; k < UN; ++k)
-            e[k] = (i0 + k < it.n_iter) ? ent[(int64_t)(i0 + k) * T] : make_uint4(0u, 0u, 0u, 0u);
+            e[k] = ent[(uint32_t)(min(i0 + k, it.n_iter - 1) * T + tid)];
+#pragma unroll
+        for (int k = 0; k < UN; ++k)
+            if (i0 + k >= it.n_iter) e[k] = make_uint4(0u, 0u, 0u, 0u);
         uint32_t bx[UN], by[UN];
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
@@ -478,14 +482,20 @@ __global__ __launch_bounds__(BL * R) __attribute__((amdgpu_waves_per_eu(2))) voi
     const int l = tid % BL, j = tid / BL;
     for (int n = tid; n < N; n += T) twl[n] = tw[n];
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 *src = scratch + ch.scratch_off + c0 + l;
-    float4 pre[R];
+    // Rows j + q R outside the footprint span read a clamped in-range row
+    // (no branches around the loads) and are zeroed when used.
+    uint32_t off[R], live = 0u;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = j + q * R;
-        pre[q] = zero;
-        if (r >= ch.row_lo && r <= ch.row_hi) pre[q] = src[(int64_t)(r - ch.row_lo) * N];
+        const int rc = min(max(r, ch.row_lo), ch.row_hi);
+        off[q] = (uint32_t)((rc - ch.row_lo) * N + c0 + l);
+        live |= (r >= ch.row_lo && r <= ch.row_hi) ? (1u << q) : 0u;
     }
+    const float4 *base = scratch + ch.scratch_off;
+    float4 pre[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) pre[q] = base[off[q]];
     float av[R][NPROD];
 #pragma unroll
     for (int q = 0; q < R; ++q)
@@ -494,15 +504,11 @@ __global__ __launch_bounds__(BL * R) __attribute__((amdgpu_waves_per_eu(2))) voi
     for (int t = 0; t < nt; ++t) {
         float4 v[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = pre[q];
+        for (int q = 0; q < R; ++q) v[q] = ((live >> q) & 1u) ? pre[q] : zero;
         if (t + 1 < nt) {
-            const float4 *nx = src + (int64_t)(t + 1) * scratch_t;
+            const float4 *nx = base + (int64_t)(t + 1) * scratch_t;
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const int r = j + q * R;
-                pre[q] = zero;
-                if (r >= ch.row_lo && r <= ch.row_hi) pre[q] = nx[(int64_t)(r - ch.row_lo) * N];
-            }
+            for (int q = 0; q < R; ++q) pre[q] = nx[off[q]];
         }
         dft<R>(v);
 #pragma unroll
