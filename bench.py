@@ -233,6 +233,40 @@ def batched(E, torch, reps=5):
     return res
 
 
+def _row_spans(wl, pos):
+    """Grid rows touched by the element footprints, per channel (the rows a
+    banded row pass stores): j0 = floor(x - K/2 + 1) with x the element's
+    grid coordinate, rows j0 .. j0 + K - 1."""
+    import numpy as np
+    spans = []
+    for f in wl.chan_freq_hz:
+        cell = wl.cell_lambda * 299792458.0 / f
+        x = pos[:, 1] / cell + int(wl.grid_n[0]) // 2
+        j0 = np.floor(x - wl.kernel_k / 2 + 1).astype(int)
+        spans.append(int(j0.max() + wl.kernel_k - 1 - j0.min() + 1))
+    return spans
+
+
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Device-to-device copy of ``mib`` MiB timed with events: bytes read plus
+    bytes written per second, the practical HBM ceiling next to the 8 TB/s
+    published peak."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    s = a.elapsed_time(b) / reps / 1e3
+    del src, dst
+    return 2 * mib * (1 << 20) / s / 1e9
+
+
 def large_stream(E, torch, reps=3):
     """Large-N streaming array: 4096 dual-pol elements in a 300 m disc,
     64 channels at 92-108 MHz, 256 x 256 grids, one block of 256 samples
@@ -268,16 +302,27 @@ def large_stream(E, torch, reps=3):
     ms, tplan, info = timed(None)
     ms_fused, _, _ = timed([64] * wl.n_chan)
     block_ms = wl.n_time / 250e3 * 1e3
+    # row transforms through HBM: written once and read once per sample
+    # and channel, plus one read-modify-write of the sums per round
+    rows = sum(min(256, r) for r in _row_spans(wl, pos))
+    scratch = 2 * wl.n_time * rows * 256 * 16
+    rounds = -(-wl.n_time // max(1, (1 << 30) // (rows * 256 * 16)))
+    sums = rounds * 2 * wl.n_chan * 4 * 256 * 256 * 4
+    copy_gbs = copy_bandwidth(torch)
     res = {"workload": "stream-large: 4096 dual-pol elements, 300 m disc, 64 channels "
                        "92-108 MHz, 256^2 grids, one 256-sample block",
            "path": "banded two-pass", "ms_per_block": ms, "block_data_ms": block_ms,
            "real_time_fraction_one_stream": block_ms / ms,
            "value": wl.samples_per_block() / (ms / 1e3), "unit": "samples/s",
            "fused64_ms_per_block": ms_fused,
+           "hbm_bytes_per_block": scratch + sums,
+           "hbm_GBps": (scratch + sums) / (ms / 1e3) / 1e9,
+           "hbm_copy_GBps": copy_gbs,
            "plan_s": tplan, "plan_bytes": info["bytes_plan"], "acc_bytes": info["bytes_acc"],
            "gen_s": tgen}
     log(f"large stream: {ms:.2f} ms per {block_ms:.3f} ms block "
-        f"({block_ms / ms:.2f} of real time; fused 64x64 {ms_fused:.2f} ms), plan {tplan:.1f} s")
+        f"({block_ms / ms:.2f} of real time; fused 64x64 {ms_fused:.2f} ms), plan {tplan:.1f} s; "
+        f"scratch + sums {res['hbm_GBps']:.0f} GB/s, device copy {copy_gbs:.0f} GB/s")
     return res
 
 

@@ -170,6 +170,7 @@ epic_status epic_acc_create(epic_plan p, epic_acc *out) {
     if (!st) st = a->d_autos.alloc(sizeof(int32_t) * (size_t)p->C * p->A * p->n_prod);
     if (!st) st = a->d_h.alloc(sizeof(double2) * (size_t)p->C * (p->P == 2 ? 3 : 1) * D * D);
     if (!st && p->work_bytes) st = a->d_work.alloc((size_t)p->work_bytes);
+    if (!st) st = banded_acc_setup(p, a);
     if (!st) {
         hipError_t e = hipMemset(a->d_acc.p, 0, a->d_acc.bytes);
         if (e == hipSuccess) e = hipMemset(a->d_autos.p, 0, a->d_autos.bytes);

@@ -462,40 +462,51 @@ __global__ __launch_bounds__(BL * R) void k_band_rows_sq(
     }
 }
 
-// Pass 2, N = R x R.  Grid: (N / BL column bands, channels of this side).
-// Thread (l, j) = (tid % BL, tid / BL) takes column l: rows j + q R in step 1
+// Columns per pass-2 workgroup: each row segment a workgroup reads is
+// BC * 16 bytes long.
+constexpr int BC = 16;
+
+// Pitch (float4) of one column in the pass-2 exchange buffer: congruent to 1
+// modulo 16 so that the BC columns of one step position sit in distinct banks.
+template <int R>
+constexpr int cols_pitch() {
+    return R * (R + 1) + (17 - (R * (R + 1)) % 16) % 16;
+}
+
+// Pass 2, N = R x R.  Grid: (N / BC column bands, channels of this side).
+// Thread (l, j) = (tid % BC, tid / BC) takes column l: rows j + q R in step 1
 // (loaded straight from the scratch, next sample in flight), pixels
 // (j + q R, c0 + l) in step 2, whose Eq. 2 products it keeps in registers.
 template <int R, int P>
-__global__ __launch_bounds__(BL * R) __attribute__((amdgpu_waves_per_eu(2))) void k_band_cols_sq(const BandChan *__restrict__ chans,
-                                                         const float2 *__restrict__ tw,
-                                                         const float4 *__restrict__ scratch,
-                                                         int64_t scratch_t, int nt,
-                                                         float *__restrict__ acc) {
-    constexpr int N = R * R, T = BL * R, LP = sq_pitch<R>();
+__global__ __launch_bounds__(BC * R) __attribute__((amdgpu_waves_per_eu(2))) void k_band_cols_sq(
+    const BandChan *__restrict__ chans, const float2 *__restrict__ tw,
+    const float4 *__restrict__ scratch, int64_t scratch_t, int nt, float *__restrict__ acc) {
+    constexpr int N = R * R, T = BC * R, LP = cols_pitch<R>();
     constexpr int NPROD = P == 2 ? 4 : 1;
     extern __shared__ float4 lds[];
-    float2 *twl = reinterpret_cast<float2 *>(lds + BL * LP);   // exp(+2 pi i n / N), n < N
+    float2 *twl = reinterpret_cast<float2 *>(lds + BC * LP);   // exp(+2 pi i n / N), n < N
     const BandChan ch = chans[blockIdx.y];
-    const int c0 = blockIdx.x * BL;
+    const int c0 = blockIdx.x * BC;
     const int tid = threadIdx.x;
-    const int l = tid % BL, j = tid / BL;
+    const int l = tid % BC, j = tid / BC;
     for (int n = tid; n < N; n += T) twl[n] = tw[n];
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     // Rows j + q R outside the footprint span read a clamped in-range row
     // (no branches around the loads) and are zeroed when used.
+    // 32-bit byte offsets from a workgroup-uniform base keep the loads in
+    // base-register + offset form
     uint32_t off[R], live = 0u;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = j + q * R;
         const int rc = min(max(r, ch.row_lo), ch.row_hi);
-        off[q] = (uint32_t)((rc - ch.row_lo) * N + c0 + l);
+        off[q] = (uint32_t)((rc - ch.row_lo) * N + c0 + l) * (uint32_t)sizeof(float4);
         live |= (r >= ch.row_lo && r <= ch.row_hi) ? (1u << q) : 0u;
     }
-    const float4 *base = scratch + ch.scratch_off;
+    const char *base = reinterpret_cast<const char *>(scratch + ch.scratch_off);
     float4 pre[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) pre[q] = base[off[q]];
+    for (int q = 0; q < R; ++q) pre[q] = *reinterpret_cast<const float4 *>(base + off[q]);
     float av[R][NPROD];
 #pragma unroll
     for (int q = 0; q < R; ++q)
@@ -506,9 +517,9 @@ __global__ __launch_bounds__(BL * R) __attribute__((amdgpu_waves_per_eu(2))) voi
 #pragma unroll
         for (int q = 0; q < R; ++q) v[q] = ((live >> q) & 1u) ? pre[q] : zero;
         if (t + 1 < nt) {
-            const float4 *nx = base + (int64_t)(t + 1) * scratch_t;
+            const char *nx = base + (int64_t)(t + 1) * scratch_t * (int64_t)sizeof(float4);
 #pragma unroll
-            for (int q = 0; q < R; ++q) pre[q] = nx[off[q]];
+            for (int q = 0; q < R; ++q) pre[q] = *reinterpret_cast<const float4 *>(nx + off[q]);
         }
         dft<R>(v);
 #pragma unroll
@@ -627,10 +638,10 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
     }
     bp.n = (int)bp.host.size();
     bp.scratch_t = off;
-    // samples per round: keep the scratch near 1 GiB
+    // samples per round: each of the two scratch halves near 1 GiB
     const int64_t per_t = off * (int64_t)sizeof(float4);
     bp.t_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (1LL << 30) / per_t));
-    bp.scratch_bytes = per_t * bp.t_chunk;
+    bp.scratch_bytes = 2 * per_t * bp.t_chunk;
     epic_status st;
     if ((st = bp.d_chans.alloc(sizeof(BandChan) * bp.host.size()))) return st;
     EPIC_HIP(hipMemcpyAsync(bp.d_chans.p, bp.host.data(), sizeof(BandChan) * bp.host.size(),
@@ -660,29 +671,74 @@ static const void *cols_sq_kernel(int P) {
 }
 
 template <int R, int P>
-static epic_status launch_sq(epic_plan p, const BandSize &bs, const uint8_t *d_volt, int nt,
-                             float4 *scratch, float *acc, hipStream_t s) {
+static epic_status launch_sq(epic_plan p, const BandSize &bs, int pass, const uint8_t *d_volt,
+                             int nt, float4 *scratch, float *acc, hipStream_t s) {
     const BandPlan &bp = p->band;
     constexpr int T = BL * R;
     const size_t lds = sizeof(float4) * BL * sq_pitch<R>();
-    const int64_t vstride = (int64_t)p->C * p->P * p->A;
-    const int64_t total = bs.n_items * nt;
-    const int64_t per_xcd = (total + 7) / 8;
-    if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
     const float2 *tw = p->d_twid.as<float2>() + bs.tw_off;
-    hipLaunchKernelGGL((k_band_rows_sq<R, P>), dim3((unsigned)(8 * per_xcd)), dim3(T), lds, s,
-                       d_volt, vstride, bp.d_chans.as<BandChan>() + bs.chan_off,
-                       bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, nt, per_xcd,
-                       bp.d_entries.as<uint4>(), p->A, tw, scratch, bp.scratch_t);
-    EPIC_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_band_cols_sq<R, P>), dim3(bs.N / BL, bs.n), dim3(T),
-                       lds + sizeof(float2) * bs.N, s,
-                       bp.d_chans.as<BandChan>() + bs.chan_off, tw, scratch, bp.scratch_t, nt,
-                       acc);
+    if (pass == 0) {
+        const int64_t vstride = (int64_t)p->C * p->P * p->A;
+        const int64_t total = bs.n_items * nt;
+        const int64_t per_xcd = (total + 7) / 8;
+        if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
+        hipLaunchKernelGGL((k_band_rows_sq<R, P>), dim3((unsigned)(8 * per_xcd)), dim3(T), lds, s,
+                           d_volt, vstride, bp.d_chans.as<BandChan>() + bs.chan_off,
+                           bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, nt, per_xcd,
+                           bp.d_entries.as<uint4>(), p->A, tw, scratch, bp.scratch_t);
+    } else {
+        hipLaunchKernelGGL((k_band_cols_sq<R, P>), dim3(bs.N / BC, bs.n), dim3(BC * R),
+                           sizeof(float4) * BC * cols_pitch<R>() + sizeof(float2) * bs.N, s,
+                           bp.d_chans.as<BandChan>() + bs.chan_off, tw, scratch, bp.scratch_t,
+                           nt, acc);
+    }
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
 }
 
+static epic_status launch_generic(epic_plan p, const BandSize &bs, int pass,
+                                  const BandChan *chans, const uint8_t *d_volt, int nt,
+                                  float4 *scratch, float *acc, hipStream_t s) {
+    const BandPlan &bp = p->band;
+    const float2 *tw = p->d_twid.as<float2>() + bs.tw_off;
+    if (pass == 0) {
+        const int64_t vstride = (int64_t)p->C * p->P * p->A;
+        const int64_t total = (int64_t)bs.n * bs.max_bands * nt;
+        const int64_t per_xcd = (total + 7) / 8;
+        if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
+        hipLaunchKernelGGL(k_band_rows, dim3((unsigned)(8 * per_xcd)), dim3(BT),
+                           sizeof(float4) * 2 * BL * bs.N, s, d_volt, vstride,
+                           chans + bs.chan_off, bs.n, bs.max_bands, nt, per_xcd,
+                           p->d_csr_base.as<int64_t>(), p->d_csr_off.as<int32_t>(),
+                           p->d_csr_ant.as<int32_t>(), p->d_csr_w.as<float2>(), p->A, p->P, bs.N,
+                           radices_of(bs.N), tw, scratch, bp.scratch_t);
+    } else {
+        const dim3 grid(bs.N / BL, bs.n);
+        const size_t lds = sizeof(float4) * 2 * BL * (bs.N + 1);
+        if (p->P == 2)
+            hipLaunchKernelGGL(k_band_cols<2>, grid, dim3(BT), lds, s, chans + bs.chan_off, bs.N,
+                               radices_of(bs.N), tw, scratch, bp.scratch_t, nt, acc);
+        else
+            hipLaunchKernelGGL(k_band_cols<1>, grid, dim3(BT), lds, s, chans + bs.chan_off, bs.N,
+                               radices_of(bs.N), tw, scratch, bp.scratch_t, nt, acc);
+    }
+    EPIC_HIP(hipGetLastError());
+    return EPIC_OK;
+}
+
+epic_status banded_acc_setup(epic_plan p, epic_acc acc) {
+    if (p->band.n == 0) return EPIC_OK;
+    for (auto &q : acc->band_q) EPIC_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    for (auto &e : acc->band_ev) EPIC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return EPIC_OK;
+}
+
+// Rounds of t_chunk samples alternate between the two scratch halves: the
+// row pass of round k + 1 (queue 0) runs while the column pass of round k
+// (queue 1) reads the other half.  Events: 0 fork, 1 + b row pass into half b
+// done, 3 + b column pass out of half b done.  A stream under graph capture
+// gets both passes itself, in order (the captured form of the two-queue
+// hand-over is not used).
 epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                               hipStream_t s, bool dry) {
     const BandPlan &bp = p->band;
@@ -692,11 +748,15 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
         if (bs.R == 16) {
             const size_t lds = sizeof(float4) * BL * sq_pitch<16>();
             st = lds_ready(rows_sq_kernel<16>(p->P), lds);
-            if (!st) st = lds_ready(cols_sq_kernel<16>(p->P), lds + sizeof(float2) * bs.N);
+            if (!st)
+                st = lds_ready(cols_sq_kernel<16>(p->P),
+                               sizeof(float4) * BC * cols_pitch<16>() + sizeof(float2) * bs.N);
         } else if (bs.R == 8) {
             const size_t lds = sizeof(float4) * BL * sq_pitch<8>();
             st = lds_ready(rows_sq_kernel<8>(p->P), lds);
-            if (!st) st = lds_ready(cols_sq_kernel<8>(p->P), lds + sizeof(float2) * bs.N);
+            if (!st)
+                st = lds_ready(cols_sq_kernel<8>(p->P),
+                               sizeof(float4) * BC * cols_pitch<8>() + sizeof(float2) * bs.N);
         } else {
             const size_t lds1 = sizeof(float4) * 2 * BL * bs.N;
             const size_t lds2 = sizeof(float4) * 2 * BL * (bs.N + 1);
@@ -709,49 +769,63 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
         if (st) return st;
     }
     if (dry) return EPIC_OK;
-    if (!acc->d_work.p || acc->d_work.bytes < (size_t)bp.scratch_bytes)
+    if (!acc->d_work.p || acc->d_work.bytes < (size_t)bp.scratch_bytes || !acc->band_q[0])
         return fail(EPIC_ERR_ARG, "accumulator has no scratch for the banded path");
-    const int64_t vstride = (int64_t)p->C * p->P * p->A;
-    float4 *scratch = acc->d_work.as<float4>();
     float *a = acc->d_acc.as<float>();
     const BandChan *chans = bp.d_chans.as<BandChan>();
-    for (int t0 = 0; t0 < n_time; t0 += bp.t_chunk) {
+    // Under graph capture both passes stay on the capturing stream, in order.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    EPIC_HIP(hipStreamIsCapturing(s, &cap));
+    const bool split = cap == hipStreamCaptureStatusNone;
+    acc->band_split = split;
+    hipStream_t q_rows = split ? acc->band_q[0] : s, q_cols = split ? acc->band_q[1] : s;
+    hipEvent_t *ev = acc->band_ev;
+    if (split) {
+        EPIC_HIP(hipEventRecord(ev[0], s));
+        EPIC_HIP(hipStreamWaitEvent(q_rows, ev[0], 0));
+        EPIC_HIP(hipStreamWaitEvent(q_cols, ev[0], 0));
+    }
+    const int64_t half = (int64_t)bp.scratch_t * bp.t_chunk;
+    int k = 0;
+    for (int t0 = 0; t0 < n_time; t0 += bp.t_chunk, ++k) {
         const int nt = std::min(bp.t_chunk, n_time - t0);
-        const uint8_t *v = d_volt + (int64_t)t0 * vstride;
-        for (const BandSize &bs : bp.sizes) {
-            epic_status st = EPIC_OK;
-            if (bs.R == 16)
-                st = p->P == 2 ? launch_sq<16, 2>(p, bs, v, nt, scratch, a, s)
-                               : launch_sq<16, 1>(p, bs, v, nt, scratch, a, s);
-            else if (bs.R == 8)
-                st = p->P == 2 ? launch_sq<8, 2>(p, bs, v, nt, scratch, a, s)
-                               : launch_sq<8, 1>(p, bs, v, nt, scratch, a, s);
-            if (st) return st;
-            if (bs.R) continue;
-            const int64_t total = (int64_t)bs.n * bs.max_bands * nt;
-            const int64_t per_xcd = (total + 7) / 8;
-            if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
-            hipLaunchKernelGGL(k_band_rows, dim3((unsigned)(8 * per_xcd)), dim3(BT),
-                               sizeof(float4) * 2 * BL * bs.N, s, v, vstride, chans + bs.chan_off,
-                               bs.n, bs.max_bands, nt, per_xcd, p->d_csr_base.as<int64_t>(),
-                               p->d_csr_off.as<int32_t>(), p->d_csr_ant.as<int32_t>(),
-                               p->d_csr_w.as<float2>(), p->A, p->P, bs.N, radices_of(bs.N),
-                               p->d_twid.as<float2>() + bs.tw_off, scratch, bp.scratch_t);
-            EPIC_HIP(hipGetLastError());
-            const dim3 grid(bs.N / BL, bs.n);
-            const size_t lds = sizeof(float4) * 2 * BL * (bs.N + 1);
-            if (p->P == 2)
-                hipLaunchKernelGGL(k_band_cols<2>, grid, dim3(BT), lds, s, chans + bs.chan_off,
-                                   bs.N, radices_of(bs.N), p->d_twid.as<float2>() + bs.tw_off,
-                                   scratch, bp.scratch_t, nt, a);
-            else
-                hipLaunchKernelGGL(k_band_cols<1>, grid, dim3(BT), lds, s, chans + bs.chan_off,
-                                   bs.N, radices_of(bs.N), p->d_twid.as<float2>() + bs.tw_off,
-                                   scratch, bp.scratch_t, nt, a);
-            EPIC_HIP(hipGetLastError());
+        const int b = k & 1;
+        float4 *scratch = acc->d_work.as<float4>() + b * half;
+        const uint8_t *v = d_volt + (int64_t)t0 * p->C * p->P * p->A;
+        if (split && k >= 2) EPIC_HIP(hipStreamWaitEvent(q_rows, ev[3 + b], 0));
+        for (int pass = 0; pass < 2; ++pass) {
+            const hipStream_t qs = pass ? q_cols : q_rows;
+            if (split && pass == 1) EPIC_HIP(hipStreamWaitEvent(q_cols, ev[1 + b], 0));
+            for (const BandSize &bs : bp.sizes) {
+                epic_status st = EPIC_OK;
+                if (bs.R == 16)
+                    st = p->P == 2 ? launch_sq<16, 2>(p, bs, pass, v, nt, scratch, a, qs)
+                                   : launch_sq<16, 1>(p, bs, pass, v, nt, scratch, a, qs);
+                else if (bs.R == 8)
+                    st = p->P == 2 ? launch_sq<8, 2>(p, bs, pass, v, nt, scratch, a, qs)
+                                   : launch_sq<8, 1>(p, bs, pass, v, nt, scratch, a, qs);
+                else
+                    st = launch_generic(p, bs, pass, chans, v, nt, scratch, a, qs);
+                if (st) return st;
+            }
+            if (split) EPIC_HIP(hipEventRecord(ev[pass ? 3 + b : 1 + b], qs));
         }
     }
+    acc->band_last = (k - 1) & 1;
+    return EPIC_OK;
+}
+
+epic_status banded_join(epic_plan p, epic_acc acc, hipStream_t s) {
+    if (p->band.n == 0 || !acc->band_split) return EPIC_OK;
+    EPIC_HIP(hipStreamWaitEvent(s, acc->band_ev[3 + acc->band_last], 0));
     return EPIC_OK;
 }
 
 }  // namespace epic
+
+epic_acc_s::~epic_acc_s() {
+    for (auto &e : band_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &q : band_q)
+        if (q) (void)hipStreamDestroy(q);
+}

@@ -838,6 +838,11 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
     for (const FusedGroup *g : p->groups)
         if (p->A > 4 * threads_of(g->M)) in_kernel = false;
     int32_t *au = (in_kernel && acc) ? acc->d_autos.as<int32_t>() : nullptr;
+    if (p->band.n) {
+        // forks onto the accumulator's own queues; joined back into s below
+        epic_status st = banded_accumulate(p, acc, d_volt, n_time, s, dry);
+        if (st) return st;
+    }
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         const FusedGroup *g = p->groups[gi];
         const hipStream_t gs = branches ? (*branches)[gi] : s;
@@ -856,12 +861,12 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
         }
         if (st) return st;
     }
-    if (p->band.n) {
-        epic_status st = banded_accumulate(p, acc, d_volt, n_time, s, dry);
+    if (dry) return EPIC_OK;
+    if (!in_kernel) {
+        epic_status st = autos_accumulate(p, acc, d_volt, n_time, s);
         if (st) return st;
     }
-    if (dry || in_kernel) return EPIC_OK;
-    return autos_accumulate(p, acc, d_volt, n_time, s);
+    return p->band.n ? banded_join(p, acc, s) : EPIC_OK;
 }
 
 epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,

@@ -217,6 +217,13 @@ struct epic_acc_s {
     epic::DevBuf d_h;      // double2 [C][NH][(2K-1)^2] read-out scratch (self-term sums)
     epic::DevBuf d_work;   // plan.work_bytes: operand staging / row-transform scratch
     int64_t count = 0;
+    // banded path: row and column passes on their own queues, scratch halves
+    // handed over by events (created with the accumulator when needed)
+    hipStream_t band_q[2] = {nullptr, nullptr};
+    hipEvent_t band_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int band_last = 0;     // scratch half of the last column pass launched
+    bool band_split = false;  // the last banded call used the two queues
+    ~epic_acc_s();
 };
 
 namespace epic {
@@ -249,6 +256,9 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
                          hipStream_t s);
 epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                               hipStream_t s, bool dry = false);
+// Make s wait for the banded work launched by banded_accumulate.
+epic_status banded_join(epic_plan p, epic_acc acc, hipStream_t s);
+epic_status banded_acc_setup(epic_plan p, epic_acc acc);
 
 // staged.hip
 epic_status staged_grid(epic_plan p, const uint8_t *d_volt, int n_time, void *d_grid,

@@ -26,13 +26,14 @@ def test_forced_banded_matches_oracle(name, chunks):
 
 
 def test_banded_crosses_the_sample_chunk():
-    # 300 samples: two rounds of the 256-sample chunk in one call
-    wl = synth.workload("tiny2").with_time(300)
-    _say("case banded tiny2 300 samples")
+    # 600 samples: three rounds of the 256-sample chunk in one call, so the
+    # row pass reuses a scratch half after its column pass
+    wl = synth.workload("tiny2").with_time(600)
+    _say("case banded tiny2 600 samples")
     pos = synth.antenna_layout(wl)
     volt = synth.voltages(wl, pos)
     got = _run(wl, pos, volt, sub_n=[BANDED])
-    _check(got, oracle_images(volt, pos, wl, range(wl.n_chan)), "banded-300")
+    _check(got, oracle_images(volt, pos, wl, range(wl.n_chan)), "banded-600")
 
 
 def test_square_radix_side_crosses_the_sample_chunk():
@@ -72,13 +73,22 @@ def test_banded_zero_padded_grid_matches_oracle():
     _check(got, oracle_images(volt, pos, wl, range(2)), "banded-lwa")
 
 
-def test_banded_graph_replays_equal_eager_and_runs_are_deterministic():
+@pytest.mark.parametrize("n_time", [
+    20,
+    pytest.param(600, marks=pytest.mark.skip(
+        reason="graph capture of three sample rounds crashed the host process inside "
+               "epic_graph_create when the passes ran on two queues; capture now keeps "
+               "both passes on the capturing stream, and this case stays off the GPU "
+               "until the crash is explained")),
+])
+def test_banded_graph_replays_equal_eager_and_runs_are_deterministic(n_time):
+    # 600 samples: three rounds over the two scratch halves inside one graph
     torch = _torch()
     import paper_2609_03027_amd as E
-    wl = synth.workload("tiny2").with_time(20)
+    wl = synth.workload("tiny2").with_time(n_time)
     pos = synth.antenna_layout(wl)
     volt = synth.voltages(wl, pos)
-    _say("case banded graph replay tiny2")
+    _say(f"case banded graph replay tiny2, {n_time} samples")
     plan = E.Plan.from_workload(wl, pos, sub_n=[BANDED])
     dv = torch.from_numpy(volt).cuda()
     eager, graphed = E.Accumulator(plan), E.Accumulator(plan)
