@@ -61,19 +61,29 @@ def hbm_bytes(wl, n_prod):
     return wl.samples_per_block() + 3 * img
 
 
+DEVICE_END = b"// ------------------------------------------------------------ host build"
+
+
+def kernel_digest(kernel_src):
+    """Hash of the device code of a source file: everything above its
+    host-build marker (the whole file if it has none)."""
+    text = open(kernel_src, "rb").read()
+    return hashlib.sha256(text.split(DEVICE_END, 1)[0]).hexdigest()[:16]
+
+
 def traffic_from_profile(kernel_src):
     """HBM bytes per dispatch from the committed counter summary, or None if
-    the kernel source changed since the counters were taken."""
+    the kernel's device code changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "fused_lwa_traffic.txt")
     if not os.path.exists(path):
         return None
-    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    digest = kernel_digest(kernel_src)
     vals = {}
     for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != digest:
+    if vals.get("device_code_sha256_16") != digest:
         return None
     try:
         return float(vals["hbm_bytes_per_dispatch_scaled"])

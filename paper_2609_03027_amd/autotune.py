@@ -1,15 +1,19 @@
-"""Tile autotuner for the FP32 fused path.
+"""Tile autotuner for the FP32 path.
 
 The fused kernel splits a channel's N x N transform into (N / M)^2
 sub-transforms of side M (16, 32 or 64; see the plan's ``sub_n``).  Larger
 tiles mean fewer, bigger transforms but more gather work per tile; the
 banded two-pass path (``SUB_BANDED``) gathers every tap once but passes the
-row transforms through HBM.  Which is faster depends on N, the element count
-and how densely the footprints cover the grid.  For every distinct grid side this tuner builds one-channel plans
-for each admissible M at the highest-frequency channel of that size (the
-densest footprint coverage), times the accumulate on the device with HIP
-events, and keeps the fastest.  Results are cached as JSON keyed by the
-array shape (``EPIC_AUTOTUNE_CACHE`` or ~/.cache/epic_mi355x/autotune.json).
+row transforms through HBM.  Which is faster depends on N, the element count,
+how densely the footprints cover the grid, and on what else runs beside a
+size's launch: the size groups of one plan run side by side in a graph
+launch, so a size whose own launch under-fills the device can still be best
+left as it is.  The tuner therefore times whole plans: starting from the
+default choice it tries, size by size (most work first), every admissible
+choice for that size with the others held, times a graph launch of all
+channels, and keeps a change only when it is faster by more than 2 %.
+Results are cached as JSON keyed by the batch shape (``EPIC_AUTOTUNE_CACHE``
+or ~/.cache/epic_mi355x/autotune.json).
 """
 from __future__ import annotations
 
@@ -46,77 +50,89 @@ def _cache_path():
                                        "autotune.json"))
 
 
-def _key(n, pos, freq, n_pol, kernel_k, cell_lambda, aperture_n):
-    cell = cell_lambda * C_LIGHT / freq
+def _key(grid_n, pos, freq, n_pol, kernel_k, cell_lambda, aperture_n):
+    cell = cell_lambda * C_LIGHT / float(np.max(freq))
     span = np.ptp(pos, axis=0).max() / cell           # footprint extent in cells
-    return f"N{n}-A{len(pos)}-P{n_pol}-K{kernel_k}-ap{aperture_n}-span{int(round(span / 4)) * 4}"
+    sizes = ",".join(f"{n}:{c}" for n, c in zip(*np.unique(grid_n, return_counts=True)))
+    return (f"A{len(pos)}-P{n_pol}-K{kernel_k}-ap{aperture_n}-span{int(round(span / 4)) * 4}"
+            f"-sizes{sizes}")
 
 
-def _time_plan(plan, n_pol, n_ant, n_time, reps):
+def _time_batch(pos, freq, grid_n, n_pol, sub, volt, reps, plan_kw):
     import torch
-    volt = torch.randint(0, 256, (n_time, 1, n_pol, n_ant), dtype=torch.uint8, device="cuda")
+    plan = L.Plan(pos, freq, grid_n, n_pol, sub_n=sub, **plan_kw)
     acc = L.Accumulator(plan)
-    L.accumulate(plan, acc, volt=volt)
+    g = L.Graph(plan, acc, volt)
+    g.launch()
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(reps):
-        L.accumulate(plan, acc, volt=volt)
+        g.launch()
     b.record()
     torch.cuda.synchronize()
+    g.close()
     acc.close()
+    plan.close()
     return a.elapsed_time(b) / reps
 
 
 def tune(pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5, kernel_k=3,
          kernel_sigma=0.5, n_time=64, reps=3, use_cache=True, verbose=False):
-    """Best sub-transform side per channel (array aligned with ``grid_n``).
+    """Sub-transform choice per channel (array aligned with ``grid_n``; 0 =
+    the library default, 16/32/64 = fused tile side, SUB_BANDED = banded).
 
     Returns ``(sub_n, report)``; report maps each grid side to the measured
-    milliseconds per candidate.
+    milliseconds of one graph launch over all channels per choice tried.
     """
+    import torch
     freq_hz = np.asarray(freq_hz, dtype=np.float64)
     grid_n = np.asarray(grid_n, dtype=np.int32)
     path = _cache_path()
+    key = _key(grid_n, pos, freq_hz, n_pol, kernel_k, cell_lambda, aperture_n)
     cache = {}
     if use_cache and os.path.exists(path):
         try:
             cache = json.load(open(path))
         except (OSError, ValueError):
             cache = {}
-    best, report = {}, {}
-    for n in sorted(set(int(x) for x in grid_n)):
-        idx = np.nonzero(grid_n == n)[0]
-        c = int(idx[np.argmax(freq_hz[idx])])
-        key = _key(n, pos, freq_hz[c], n_pol, kernel_k, cell_lambda, aperture_n)
-        cands = candidates(n)
-        if len(cands) == 1:
-            best[n] = cands[0]
-            continue
-        if key in cache:
-            best[n] = int(cache[key]["best"])
-            report[n] = cache[key]["ms"]
-            continue
-        ms = {}
-        for m in cands:
-            plan = L.Plan(pos, [freq_hz[c]], [n], n_pol, aperture_n=aperture_n,
-                          cell_lambda=cell_lambda, kernel_k=kernel_k,
-                          kernel_sigma=kernel_sigma, sub_n=[m])
-            ms[str(m)] = _time_plan(plan, n_pol, len(pos), n_time, reps)
-            plan.close()
-        b = int(min(ms, key=ms.get))
-        best[n] = b
-        report[n] = ms
-        cache[key] = {"best": b, "ms": ms}
-        if verbose:
-            print(f"autotune N={n}: {ms} -> {b}", flush=True)
+    sizes = sorted(set(int(x) for x in grid_n))
+    if key in cache:
+        best = {int(k): int(v) for k, v in cache[key]["best"].items()}
+        return (np.array([best[int(n)] for n in grid_n], dtype=np.int32),
+                {int(k): v for k, v in cache[key]["ms"].items()})
+    plan_kw = dict(aperture_n=aperture_n, cell_lambda=cell_lambda, kernel_k=kernel_k,
+                   kernel_sigma=kernel_sigma)
+    volt = torch.randint(0, 256, (n_time, len(grid_n), n_pol, len(pos)), dtype=torch.uint8,
+                         device="cuda")
+    choice = {n: 0 for n in sizes}
+
+    def sub_of(ch):
+        return np.array([ch[int(n)] for n in grid_n], dtype=np.int32)
+
+    base = _time_batch(pos, freq_hz, grid_n, n_pol, sub_of(choice), volt, reps, plan_kw)
+    report = {n: {"0": base} for n in sizes}
+    work = {n: int(np.sum(grid_n == n)) * n * n for n in sizes}
+    for n in sorted(sizes, key=lambda x: -work[x]):
+        for m in candidates(n):
+            trial = dict(choice)
+            trial[n] = m
+            ms = _time_batch(pos, freq_hz, grid_n, n_pol, sub_of(trial), volt, reps, plan_kw)
+            report[n][str(m)] = ms
+            if verbose:
+                print(f"autotune N={n} choice {m}: {ms:.3f} ms (best {base:.3f})", flush=True)
+            if ms < 0.98 * base:
+                base = ms
+                choice = trial
     if use_cache:
+        cache[key] = {"best": {str(k): v for k, v in choice.items()},
+                      "ms": {str(k): v for k, v in report.items()}}
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             json.dump(cache, open(path, "w"), indent=1)
         except OSError:
             pass
-    return np.array([best[int(n)] for n in grid_n], dtype=np.int32), report
+    return sub_of(choice), report
 
 
 def tuned_plan(wl, pos, **kw):

@@ -81,7 +81,7 @@ def test_autotune_picks_a_valid_tile_and_matches_oracle(tmp_path, monkeypatch):
     _say("case autotune ska sizes 64/128/192")
     sub, report = autotune.tune(pos, wl.chan_freq_hz, wl.grid_n, wl.n_pol, n_time=16, reps=2)
     for n, m in zip(wl.grid_n, sub):
-        assert m in autotune.candidates(int(n))
+        assert m == 0 or m in autotune.candidates(int(n))
     assert (tmp_path / "tune.json").exists()
     again, rep2 = autotune.tune(pos, wl.chan_freq_hz, wl.grid_n, wl.n_pol)
     assert np.array_equal(sub, again)                       # served from the cache
