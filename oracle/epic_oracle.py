@@ -189,10 +189,12 @@ def antenna_autos(E) -> np.ndarray:
     """
     E = np.asarray(E)
     P = E.shape[1]
-    xx = np.sum(np.abs(E[:, 0]) ** 2, axis=0)
+    # |E|^2 as re^2 + im^2: exact for integer samples (abs() then squaring
+    # rounds through a square root)
+    xx = np.sum(E[:, 0].real ** 2 + E[:, 0].imag ** 2, axis=0)
     if P == 1:
         return xx[:, None]
-    yy = np.sum(np.abs(E[:, 1]) ** 2, axis=0)
+    yy = np.sum(E[:, 1].real ** 2 + E[:, 1].imag ** 2, axis=0)
     xy = np.sum(E[:, 0] * np.conj(E[:, 1]), axis=0)
     return np.stack([xx, yy, xy.real, xy.imag], axis=1)
 
@@ -302,14 +304,15 @@ def fx_image(E, j0, w, n, include_auto=True) -> np.ndarray:
 # --------------------------------------------------------------------------
 def channel_reference(volt_c, pos, freq_hz, n, *, cell_lambda=0.5, k=3,
                       sigma=0.5, kernel=None, aperture_n=0,
-                      want_images=False):
+                      want_images=False, want_auto=True):
     """Reference for one channel of packed voltages ``uint8 [T][P][A]``.
 
     ``kernel`` optionally replaces the Gaussian with explicit complex weights
     [A][K][K] (the weight W_a on each support cell).  Returns a dict with
     ``acc`` (float64 [n_prod][N][N]), ``autos`` ([A][n_prod]), ``auto``
     (the self term, same shape as acc), ``j0``, ``w`` and, on request, the
-    per-sample grids and sky images.
+    per-sample grids and sky images.  ``want_auto=False`` leaves ``auto``
+    as None (its cost grows as A N^2).
     """
     E = decode_int4(volt_c)                          # [T][P][A]
     x, j0 = grid_geometry(pos, freq_hz, n, cell_lambda, k)
@@ -323,7 +326,9 @@ def channel_reference(volt_c, pos, freq_hz, n, *, cell_lambda=0.5, k=3,
     Es = sky(G)
     acc = accumulate(Es)
     S = antenna_autos(E)
-    if len(j0) * n * n <= (1 << 24):
+    if not want_auto:
+        auto = None
+    elif len(j0) * n * n <= (1 << 24):
         auto = auto_term(S, antenna_beams(j0, w, n))
     else:
         auto = auto_term_by_element(S, j0, w, n)

@@ -26,7 +26,8 @@ def oracle_images(volt, pos, wl, chans, remove_autos=True, normalise=True, kerne
         r = O.channel_reference(
             volt[:, i], pos, wl.chan_freq_hz[c], int(wl.grid_n[c]),
             cell_lambda=wl.cell_lambda, k=wl.kernel_k, sigma=wl.kernel_sigma_cells,
-            aperture_n=wl.aperture_n, kernel=None if kernels is None else kernels[i])
+            aperture_n=wl.aperture_n, kernel=None if kernels is None else kernels[i],
+            want_auto=remove_autos)
         out.append(O.readout(r["acc"], r["auto"] if remove_autos else None, r["count"],
                              normalise))
     return out

@@ -267,6 +267,20 @@ def test_autos_exact_integers_and_time_additivity():
     np.testing.assert_array_equal(S[:, 3], ixy)
 
 
+def test_autos_exact_over_every_sample_value():
+    # one sample of every byte value per element (short sums leave no room
+    # for rounding to hide): the self-term sums must be the exact integers
+    b = np.arange(256, dtype=np.uint8)
+    v = np.stack([b, b[::-1]], axis=0)[None]                      # [T=1][P=2][A=256]
+    S = O.antenna_autos(O.decode_int4(v))
+    re = np.where((v >> 4) >= 8, (v >> 4).astype(int) - 16, (v >> 4).astype(int))[0]
+    im = np.where((v & 15) >= 8, (v & 15).astype(int) - 16, (v & 15).astype(int))[0]
+    np.testing.assert_array_equal(S[:, 0], re[0] ** 2 + im[0] ** 2)
+    np.testing.assert_array_equal(S[:, 1], re[1] ** 2 + im[1] ** 2)
+    np.testing.assert_array_equal(S[:, 2], re[0] * re[1] + im[0] * im[1])
+    np.testing.assert_array_equal(S[:, 3], im[0] * re[1] - re[0] * im[1])
+
+
 def test_channel_reference_readout_normalises():
     wl = synth.workload("tiny2")
     pos = synth.antenna_layout(wl)
