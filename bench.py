@@ -277,6 +277,53 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return 2 * mib * (1 << 20) / s / 1e9
 
 
+def wide_field(E, torch, reps=3):
+    """Wide-field large array: ~20 000 dual-pol elements in a 700 m disc, one
+    781.25 kHz coarse channel at 100 MHz, 512 x 512 grid, 781 samples (1 ms
+    of data) per image, on the banded path (radix 8, three passes per axis)."""
+    import synth
+    wl = synth.workload("wide")
+    pos = synth.antenna_layout(wl)
+    volt = torch.from_numpy(synth.voltages(wl, pos)).cuda()
+    t0 = time.perf_counter()
+    plan = E.Plan.from_workload(wl, pos)
+    tplan = time.perf_counter() - t0
+    acc = E.Accumulator(plan)
+    img = torch.empty(plan.info["image_floats"], dtype=torch.float32, device="cuda")
+
+    def frame():
+        acc.reset()
+        E.accumulate(plan, acc, volt=volt)
+        E.readout(plan, acc, img, E.REMOVE_AUTOS | E.NORMALISE)
+
+    frame()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        frame()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    frame_ms = wl.n_time / 781.25e3 * 1e3
+    rows = sum(_row_spans(wl, pos))
+    n = int(wl.grid_n[0])
+    scratch = 2 * wl.n_time * rows * n * 16
+    res = {"workload": "wide-field: 20000 dual-pol elements, 700 m disc, one 781.25 kHz "
+                       "channel at 100 MHz, 512^2 grid, 781 samples (1 ms) per image",
+           "path": "banded two-pass", "ms_per_image": ms, "data_ms_per_image": frame_ms,
+           "real_time_fraction": frame_ms / ms,
+           "value": wl.samples_per_block() / (ms / 1e3), "unit": "samples/s",
+           "scratch_bytes_per_image": scratch, "scratch_GBps": scratch / (ms / 1e3) / 1e9,
+           "plan_s": tplan, "plan_bytes": plan.info["bytes_plan"],
+           "acc_bytes": plan.info["bytes_acc"]}
+    log(f"wide field: {ms:.2f} ms per {frame_ms:.3f} ms image ({frame_ms / ms:.2f} of real "
+        f"time), scratch {res['scratch_GBps']:.0f} GB/s, plan {tplan:.1f} s")
+    acc.close()
+    plan.close()
+    return res
+
+
 def large_stream(E, torch, reps=3):
     """Large-N streaming array: 4096 dual-pol elements in a 300 m disc,
     64 channels at 92-108 MHz, 256 x 256 grids, one block of 256 samples
@@ -352,6 +399,8 @@ def main():
                     help="also time one block of the 4096-element 256^2 array (0 = skip)")
     ap.add_argument("--stream-blocks", type=int, default=200,
                     help="blocks per stream in the real-time streaming run (0 = skip)")
+    ap.add_argument("--wide", type=int, default=1,
+                    help="time the 512^2 wide-field array (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB for a plain device copy (counter calibration runs)")
     args = ap.parse_args()
@@ -537,6 +586,8 @@ def main():
 
     if args.large:
         out["large_stream"] = large_stream(E, torch)
+    if args.wide:
+        out["wide_field"] = wide_field(E, torch)
 
     if args.stream_blocks > 0:
         out["streaming"] = {}

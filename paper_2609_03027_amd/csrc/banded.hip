@@ -364,39 +364,101 @@ __global__ __launch_bounds__(BT) void k_band_cols(const BandChan *__restrict__ c
     }
 }
 
-// ------------------------------------------------------------ N = R x R
-// Pitch (float4) of one line in the exchange buffer: positions
-// j (R + 1) + q keep the R lanes of a line in distinct LDS banks, and the
-// +2 skews neighbouring lines.
+// --------------------------------------------------------- N = R^NP
+// Line transforms of N = R^NP points as NP Stockham passes of radix R, each
+// an R-point DFT in registers.  Thread j of a line takes elements j + qL
+// (L = N / R) in every pass; between passes the line goes through LDS at
+// padded positions p + p / R, which keeps the lanes of a pass in distinct
+// banks.  Pass s (Ns = R^s) multiplies input q by exp(+2 pi i q (j mod Ns)
+// N / (Ns R) / N) and writes output q to (j / Ns) Ns R + j mod Ns + q Ns; the
+// last pass leaves X[j + qL] in registers in natural order.
+template <int R, int NP>
+struct Pw {
+    static constexpr int N = NP == 2 ? R * R : R * R * R;
+    static constexpr int L = N / R;
+    static constexpr int PAD = N + N / R;   // padded line length
+};
+
 template <int R>
-constexpr int sq_pitch() {
-    return R * (R + 1) + 2;
+__device__ __forceinline__ constexpr int padr(int p) {
+    return p + p / R;
 }
 
-// Pass 1, N = R x R.  One workgroup per (item, sample): thread (l, j) =
-// (tid / R, tid % R) owns line l of the band in both steps.
-template <int R, int P>
-__global__ __launch_bounds__(BL * R) void k_band_rows_sq(
+// Passes 1 .. NP-1 of one line held by thread j (pass 0 already applied to
+// v, in registers).  line: this line's LDS base; twl: exp(+2 pi i n / N).
+template <int R, int NP>
+__device__ __forceinline__ void pw_rest(float4 (&v)[R], float4 *line, int j,
+                                        const float2 *twl) {
+    constexpr int N = Pw<R, NP>::N, L = Pw<R, NP>::L;
+    int Ns = 1;
+#pragma unroll
+    for (int s = 1; s < NP; ++s) {
+        // write pass s-1 outputs
+#pragma unroll
+        for (int q = 0; q < R; ++q) line[padr<R>((j / Ns) * Ns * R + j % Ns + q * Ns)] = v[q];
+        __syncthreads();
+        Ns *= R;
+        const int k = j % Ns, tstep = N / (Ns * R);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const float4 x = line[padr<R>(j + q * L)];
+            v[q] = q ? q_mul(x, twl[(q * k * tstep) % N]) : x;
+        }
+        dft<R>(v);
+        if (s + 1 < NP) __syncthreads();   // every read of this pass before its writes
+    }
+}
+
+template <int R, int NP>
+constexpr int rows_pitch() {
+    return Pw<R, NP>::PAD + 2;
+}
+template <int R, int NP>
+constexpr int rows_threads() {
+    return BL * Pw<R, NP>::L;
+}
+// Columns per pass-2 workgroup: 16 (256-byte row segments) unless that would
+// pass 256 threads.
+template <int R, int NP>
+constexpr int cols_band() {
+    return Pw<R, NP>::L >= 32 ? 8 : 16;
+}
+template <int R, int NP>
+constexpr int cols_threads() {
+    return cols_band<R, NP>() * Pw<R, NP>::L;
+}
+// Column pitch congruent to 16 / BC modulo 16: the BC columns and 16 / BC
+// consecutive j of one 16-lane group sit in distinct banks.
+template <int R, int NP>
+constexpr int cols_pitch() {
+    constexpr int pad = Pw<R, NP>::PAD, want = 16 / cols_band<R, NP>();
+    return pad + ((want - pad % 16) % 16 + 16) % 16;
+}
+
+// Pass 1.  One workgroup per (item, sample): thread (l, j) = (tid / L,
+// tid % L) owns line l of the band.
+template <int R, int NP, int P>
+__global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
     const BandItem *__restrict__ items, int n_items, int nt, int64_t per_xcd,
     const uint4 *__restrict__ entries, int A, const float2 *__restrict__ tw,
     float4 *__restrict__ scratch, int64_t scratch_t) {
-    constexpr int N = R * R, T = BL * R, LP = sq_pitch<R>();
-    constexpr int UN = 16;  // gather entries in flight per lane
+    constexpr int N = Pw<R, NP>::N, L = Pw<R, NP>::L, T = rows_threads<R, NP>();
+    constexpr int LP = rows_pitch<R, NP>();
+    constexpr int UN = T >= 256 ? 8 : 16;  // gather entries in flight per lane
     extern __shared__ float4 lds[];
+    float2 *twl = reinterpret_cast<float2 *>(lds + BL * LP);
     const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (w >= (int64_t)n_items * nt) return;
     const int t = (int)(w % nt);
     const BandItem it = items[w / nt];
     const BandChan ch = chans[it.chan];
     const int tid = threadIdx.x;
-    const int l = tid / R, j = tid % R;
-    float2 twr[R];
-#pragma unroll
-    for (int q = 1; q < R; ++q) twr[q] = tw[q * j];
+    const int l = tid / L, j = tid % L;
+    for (int n = tid; n < N; n += T) twl[n] = tw[n];
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int k = 0; k < R; ++k) lds[tid + k * T] = zero;
+    for (int k = 0; k < BL * N / T; ++k) lds[tid + k * T] = zero;
     __syncthreads();
     // gather: each lane sums its own cells, entries [iter][lane]
     const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A;
@@ -437,100 +499,83 @@ __global__ __launch_bounds__(BL * R) void k_band_rows_sq(
         }
     }
     __syncthreads();
-    // step 1: R-point DFTs over the elements j + q R of line l
+    // pass 0 from the gathered band (plain pitch N), then the rest in LDS
     float4 v[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = lds[l * N + j + q * R];
+    for (int q = 0; q < R; ++q) v[q] = lds[l * N + j + q * L];
     dft<R>(v);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < R; ++q) lds[l * LP + j * (R + 1) + q] = v[q];
-    __syncthreads();
-    // step 2: twiddles, R-point DFTs over the step-1 outputs j + q R
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const float4 x = lds[l * LP + j + q * (R + 1)];
-        v[q] = q ? q_mul(x, twr[q]) : x;
-    }
-    dft<R>(v);
+    pw_rest<R, NP>(v, lds + l * LP, j, twl);
     const int row = ch.row_lo + it.band * BL + l;
     if (row <= ch.row_hi) {
         float4 *out = scratch + (int64_t)t * scratch_t + ch.scratch_off +
                       (int64_t)(row - ch.row_lo) * N + j;
 #pragma unroll
-        for (int q = 0; q < R; ++q) out[q * R] = v[q];
+        for (int q = 0; q < R; ++q) out[q * L] = v[q];
     }
 }
 
-// Columns per pass-2 workgroup: each row segment a workgroup reads is
-// BC * 16 bytes long.
-constexpr int BC = 16;
-
-// Pitch (float4) of one column in the pass-2 exchange buffer: congruent to 1
-// modulo 16 so that the BC columns of one step position sit in distinct banks.
-template <int R>
-constexpr int cols_pitch() {
-    return R * (R + 1) + (17 - (R * (R + 1)) % 16) % 16;
-}
-
-// Pass 2, N = R x R.  Grid: (N / BC column bands, channels of this side).
-// Thread (l, j) = (tid % BC, tid / BC) takes column l: rows j + q R in step 1
+// Pass 2.  Grid: (N / BC column bands, channels of this side, S time slices).
+// Thread (l, j) = (tid % BC, tid / BC) takes column l: rows j + qL in pass 0
 // (loaded straight from the scratch, next sample in flight), pixels
-// (j + q R, c0 + l) in step 2, whose Eq. 2 products it keeps in registers.
-template <int R, int P>
-__global__ __launch_bounds__(BC * R) __attribute__((amdgpu_waves_per_eu(2))) void k_band_cols_sq(
-    const BandChan *__restrict__ chans, const float2 *__restrict__ tw,
-    const float4 *__restrict__ scratch, int64_t scratch_t, int nt, float *__restrict__ acc) {
-    constexpr int N = R * R, T = BC * R, LP = cols_pitch<R>();
+// (j + qL, c0 + l) after the last pass, whose Eq. 2 products it keeps in
+// registers over the samples t = slice, slice + S, ... of the round.  With
+// S = 1 the sums are added to the accumulators; otherwise each slice stores
+// them to part[slice] for k_band_reduce.
+template <int R, int NP, int P>
+__global__ __launch_bounds__((cols_threads<R, NP>())) __attribute__((amdgpu_waves_per_eu(2)))
+void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict__ tw,
+                    const float4 *__restrict__ scratch, int64_t scratch_t, int nt,
+                    float *__restrict__ acc, float *__restrict__ part, int64_t part_stride) {
+    constexpr int N = Pw<R, NP>::N, L = Pw<R, NP>::L, BC = cols_band<R, NP>();
+    constexpr int T = cols_threads<R, NP>(), LP = cols_pitch<R, NP>();
     constexpr int NPROD = P == 2 ? 4 : 1;
     extern __shared__ float4 lds[];
-    float2 *twl = reinterpret_cast<float2 *>(lds + BC * LP);   // exp(+2 pi i n / N), n < N
+    float2 *twl = reinterpret_cast<float2 *>(lds + BC * LP);
     const BandChan ch = chans[blockIdx.y];
+    const int S = gridDim.z, slice = blockIdx.z;
     const int c0 = blockIdx.x * BC;
     const int tid = threadIdx.x;
     const int l = tid % BC, j = tid / BC;
     for (int n = tid; n < N; n += T) twl[n] = tw[n];
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    // Rows j + q R outside the footprint span read a clamped in-range row
-    // (no branches around the loads) and are zeroed when used.
-    // 32-bit byte offsets from a workgroup-uniform base keep the loads in
-    // base-register + offset form
+    // Rows outside the footprint span read a clamped in-range row (no
+    // branches around the loads) and are zeroed when used; 32-bit byte
+    // offsets from a workgroup-uniform base keep the loads in base + offset
+    // form.
     uint32_t off[R], live = 0u;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int r = j + q * R;
+        const int r = j + q * L;
         const int rc = min(max(r, ch.row_lo), ch.row_hi);
         off[q] = (uint32_t)((rc - ch.row_lo) * N + c0 + l) * (uint32_t)sizeof(float4);
         live |= (r >= ch.row_lo && r <= ch.row_hi) ? (1u << q) : 0u;
     }
     const char *base = reinterpret_cast<const char *>(scratch + ch.scratch_off);
+    const int64_t tstride = scratch_t * (int64_t)sizeof(float4);
     float4 pre[R];
+    if (slice < nt) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) pre[q] = *reinterpret_cast<const float4 *>(base + off[q]);
+        for (int q = 0; q < R; ++q)
+            pre[q] = *reinterpret_cast<const float4 *>(base + slice * tstride + off[q]);
+    }
     float av[R][NPROD];
 #pragma unroll
     for (int q = 0; q < R; ++q)
 #pragma unroll
         for (int k = 0; k < NPROD; ++k) av[q][k] = 0.f;
-    for (int t = 0; t < nt; ++t) {
+    float4 *line = lds + l * LP;
+    for (int t = slice; t < nt; t += S) {
         float4 v[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) v[q] = ((live >> q) & 1u) ? pre[q] : zero;
-        if (t + 1 < nt) {
-            const char *nx = base + (int64_t)(t + 1) * scratch_t * (int64_t)sizeof(float4);
+        if (t + S < nt) {
+            const char *nx = base + (int64_t)(t + S) * tstride;
 #pragma unroll
             for (int q = 0; q < R; ++q) pre[q] = *reinterpret_cast<const float4 *>(nx + off[q]);
         }
         dft<R>(v);
-#pragma unroll
-        for (int q = 0; q < R; ++q) lds[l * LP + j * (R + 1) + q] = v[q];
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const float4 x = lds[l * LP + j + q * (R + 1)];
-            v[q] = q ? q_mul(x, twl[q * j]) : x;
-        }
-        dft<R>(v);
+        pw_rest<R, NP>(v, line, j, twl);
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const float4 e = v[q];
@@ -541,19 +586,45 @@ __global__ __launch_bounds__(BC * R) __attribute__((amdgpu_waves_per_eu(2))) voi
                 av[q][3] += e.y * e.z - e.x * e.w;
             }
         }
-        __syncthreads();
+        __syncthreads();   // every read of the last pass before the next writes
     }
     const int64_t plane = (int64_t)N * N;
+    if (S == 1) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        float *dst = acc + ch.img_off + (int64_t)(j + q * R) * N + c0 + l;
+        for (int q = 0; q < R; ++q) {
+            float *dst = acc + ch.img_off + (int64_t)(j + q * L) * N + c0 + l;
 #pragma unroll
-        for (int k = 0; k < NPROD; ++k) dst[k * plane] += av[q][k];
+            for (int k = 0; k < NPROD; ++k) dst[k * plane] += av[q][k];
+        }
+    } else {
+        float *dst0 = part + slice * part_stride + (int64_t)blockIdx.y * NPROD * plane;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float *dst = dst0 + (int64_t)(j + q * L) * N + c0 + l;
+#pragma unroll
+            for (int k = 0; k < NPROD; ++k) dst[k * plane] = av[q][k];
+        }
     }
 }
 
-static int square_radix(int N) {
-    return N == 256 ? 16 : N == 64 ? 8 : 0;
+// acc[channel images] += sum over slices s = 0 .. S-1 of part[s], in that
+// order.  Grid: (pixel blocks, channels of one size group).
+__global__ __launch_bounds__(256) void k_band_reduce(const BandChan *__restrict__ chans,
+                                                     int n_floats, int S,
+                                                     const float *__restrict__ part,
+                                                     int64_t part_stride,
+                                                     float *__restrict__ acc) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_floats) return;
+    const float *src = part + (int64_t)blockIdx.y * n_floats + i;
+    float sum = 0.f;
+    for (int s = 0; s < S; ++s) sum += src[s * part_stride];
+    acc[chans[blockIdx.y].img_off + i] += sum;
+}
+
+static int pw_radix(int N, int *np) {
+    *np = N == 512 ? 3 : 2;
+    return N == 256 ? 16 : (N == 64 || N == 512) ? 8 : 0;
 }
 
 // Per-band lane lists of one channel: taps conj(W) (-1)^(jx+jy) of every
@@ -605,7 +676,7 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
     for (int N : sides) {
         BandSize bs;
         bs.N = N;
-        bs.R = square_radix(N);
+        bs.R = pw_radix(N, &bs.NP);
         bs.chan_off = (int64_t)bp.host.size();
         bs.tw_off = p->twid_off[N];
         bs.item_off = (int64_t)items.size();
@@ -627,8 +698,8 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
             off += (int64_t)(hi - lo + 1) * N;
             // items index the channels of their own size group
             if (bs.R)
-                band_items(p, j0, w, b, (int)(bp.host.size() - bs.chan_off), BL * bs.R, items,
-                           all);
+                band_items(p, j0, w, b, (int)(bp.host.size() - bs.chan_off),
+                           BL * (bs.N / bs.R), items, all);
             bp.host.push_back(b);
             bs.max_bands = std::max(bs.max_bands, (hi - lo + 1 + BL - 1) / BL);
             ++bs.n;
@@ -642,6 +713,20 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
     const int64_t per_t = off * (int64_t)sizeof(float4);
     bp.t_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (1LL << 30) / per_t));
     bp.scratch_bytes = 2 * per_t * bp.t_chunk;
+    // Column passes with fewer than 1024 workgroups split the samples of a
+    // round into S slices, each summing into its own partial image set.
+    bp.part_bytes = 0;
+    for (BandSize &bs : bp.sizes) {
+        if (!bs.R) continue;
+        const int bc = (bs.N / bs.R) >= 32 ? 8 : 16;
+        const int64_t groups = (int64_t)bs.n * (bs.N / bc);
+        bs.slices = (int)std::min<int64_t>(bp.t_chunk, std::max<int64_t>(1, (1024 + groups - 1) / groups));
+        if (bs.slices > 1) {
+            bs.part_off = bp.part_bytes / (int64_t)sizeof(float);
+            bs.part_stride = (int64_t)bs.n * p->n_prod * bs.N * bs.N;
+            bp.part_bytes += (int64_t)sizeof(float) * bs.slices * bs.part_stride;
+        }
+    }
     epic_status st;
     if ((st = bp.d_chans.alloc(sizeof(BandChan) * bp.host.size()))) return st;
     EPIC_HIP(hipMemcpyAsync(bp.d_chans.p, bp.host.data(), sizeof(BandChan) * bp.host.size(),
@@ -659,41 +744,77 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
     return EPIC_OK;
 }
 
-template <int R>
-static const void *rows_sq_kernel(int P) {
-    return P == 2 ? reinterpret_cast<const void *>(k_band_rows_sq<R, 2>)
-                  : reinterpret_cast<const void *>(k_band_rows_sq<R, 1>);
+template <int R, int NP>
+static const void *rows_pw_kernel(int P) {
+    return P == 2 ? reinterpret_cast<const void *>(k_band_rows_pw<R, NP, 2>)
+                  : reinterpret_cast<const void *>(k_band_rows_pw<R, NP, 1>);
 }
-template <int R>
-static const void *cols_sq_kernel(int P) {
-    return P == 2 ? reinterpret_cast<const void *>(k_band_cols_sq<R, 2>)
-                  : reinterpret_cast<const void *>(k_band_cols_sq<R, 1>);
+template <int R, int NP>
+static const void *cols_pw_kernel(int P) {
+    return P == 2 ? reinterpret_cast<const void *>(k_band_cols_pw<R, NP, 2>)
+                  : reinterpret_cast<const void *>(k_band_cols_pw<R, NP, 1>);
+}
+template <int R, int NP>
+static size_t rows_pw_lds() {
+    return sizeof(float4) * BL * rows_pitch<R, NP>() + sizeof(float2) * Pw<R, NP>::N;
+}
+template <int R, int NP>
+static size_t cols_pw_lds() {
+    return sizeof(float4) * cols_band<R, NP>() * cols_pitch<R, NP>() +
+           sizeof(float2) * Pw<R, NP>::N;
 }
 
-template <int R, int P>
-static epic_status launch_sq(epic_plan p, const BandSize &bs, int pass, const uint8_t *d_volt,
-                             int nt, float4 *scratch, float *acc, hipStream_t s) {
+template <int R, int NP>
+static epic_status ready_pw(int P) {
+    epic_status st = lds_ready(rows_pw_kernel<R, NP>(P), rows_pw_lds<R, NP>());
+    if (!st) st = lds_ready(cols_pw_kernel<R, NP>(P), cols_pw_lds<R, NP>());
+    return st;
+}
+
+template <int R, int NP, int P>
+static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const uint8_t *d_volt,
+                             int nt, float4 *scratch, float *part, float *acc, hipStream_t s) {
     const BandPlan &bp = p->band;
-    constexpr int T = BL * R;
-    const size_t lds = sizeof(float4) * BL * sq_pitch<R>();
     const float2 *tw = p->d_twid.as<float2>() + bs.tw_off;
+    const BandChan *chans = bp.d_chans.as<BandChan>() + bs.chan_off;
     if (pass == 0) {
         const int64_t vstride = (int64_t)p->C * p->P * p->A;
         const int64_t total = bs.n_items * nt;
         const int64_t per_xcd = (total + 7) / 8;
         if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
-        hipLaunchKernelGGL((k_band_rows_sq<R, P>), dim3((unsigned)(8 * per_xcd)), dim3(T), lds, s,
-                           d_volt, vstride, bp.d_chans.as<BandChan>() + bs.chan_off,
-                           bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, nt, per_xcd,
-                           bp.d_entries.as<uint4>(), p->A, tw, scratch, bp.scratch_t);
-    } else {
-        hipLaunchKernelGGL((k_band_cols_sq<R, P>), dim3(bs.N / BC, bs.n), dim3(BC * R),
-                           sizeof(float4) * BC * cols_pitch<R>() + sizeof(float2) * bs.N, s,
-                           bp.d_chans.as<BandChan>() + bs.chan_off, tw, scratch, bp.scratch_t,
-                           nt, acc);
+        constexpr int T = rows_threads<R, NP>();
+        const size_t lds = rows_pw_lds<R, NP>();
+        hipLaunchKernelGGL((k_band_rows_pw<R, NP, P>), dim3((unsigned)(8 * per_xcd)), dim3(T),
+                           lds, s, d_volt, vstride,
+                           chans, bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, nt,
+                           per_xcd, bp.d_entries.as<uint4>(), p->A, tw, scratch, bp.scratch_t);
+        EPIC_HIP(hipGetLastError());
+        return EPIC_OK;
     }
+    const int S = bs.slices;
+    float *pp = S > 1 ? part + bs.part_off : nullptr;
+    constexpr int BCW = cols_band<R, NP>(), TC = cols_threads<R, NP>();
+    const size_t lds = cols_pw_lds<R, NP>();
+    hipLaunchKernelGGL((k_band_cols_pw<R, NP, P>), dim3(bs.N / BCW, bs.n, S), dim3(TC), lds, s,
+                       chans, tw, scratch, bp.scratch_t, nt, acc, pp, bs.part_stride);
     EPIC_HIP(hipGetLastError());
+    if (S > 1) {
+        const int n_floats = p->n_prod * bs.N * bs.N;
+        hipLaunchKernelGGL(k_band_reduce, dim3((n_floats + 255) / 256, bs.n), dim3(256), 0, s,
+                           chans, n_floats, S, pp, bs.part_stride, acc);
+        EPIC_HIP(hipGetLastError());
+    }
     return EPIC_OK;
+}
+
+template <int P>
+static epic_status launch_pw_any(epic_plan p, const BandSize &bs, int pass,
+                                 const uint8_t *d_volt, int nt, float4 *scratch, float *part,
+                                 float *acc, hipStream_t s) {
+    if (bs.R == 16) return launch_pw<16, 2, P>(p, bs, pass, d_volt, nt, scratch, part, acc, s);
+    if (bs.R == 8 && bs.NP == 2)
+        return launch_pw<8, 2, P>(p, bs, pass, d_volt, nt, scratch, part, acc, s);
+    return launch_pw<8, 3, P>(p, bs, pass, d_volt, nt, scratch, part, acc, s);
 }
 
 static epic_status launch_generic(epic_plan p, const BandSize &bs, int pass,
@@ -746,17 +867,11 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
     for (const BandSize &bs : bp.sizes) {
         epic_status st = EPIC_OK;
         if (bs.R == 16) {
-            const size_t lds = sizeof(float4) * BL * sq_pitch<16>();
-            st = lds_ready(rows_sq_kernel<16>(p->P), lds);
-            if (!st)
-                st = lds_ready(cols_sq_kernel<16>(p->P),
-                               sizeof(float4) * BC * cols_pitch<16>() + sizeof(float2) * bs.N);
+            st = ready_pw<16, 2>(p->P);
+        } else if (bs.R == 8 && bs.NP == 2) {
+            st = ready_pw<8, 2>(p->P);
         } else if (bs.R == 8) {
-            const size_t lds = sizeof(float4) * BL * sq_pitch<8>();
-            st = lds_ready(rows_sq_kernel<8>(p->P), lds);
-            if (!st)
-                st = lds_ready(cols_sq_kernel<8>(p->P),
-                               sizeof(float4) * BC * cols_pitch<8>() + sizeof(float2) * bs.N);
+            st = ready_pw<8, 3>(p->P);
         } else {
             const size_t lds1 = sizeof(float4) * 2 * BL * bs.N;
             const size_t lds2 = sizeof(float4) * 2 * BL * (bs.N + 1);
@@ -769,8 +884,10 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
         if (st) return st;
     }
     if (dry) return EPIC_OK;
-    if (!acc->d_work.p || acc->d_work.bytes < (size_t)bp.scratch_bytes || !acc->band_q[0])
+    if (!acc->d_work.p || acc->d_work.bytes < (size_t)(bp.scratch_bytes + bp.part_bytes) ||
+        !acc->band_q[0])
         return fail(EPIC_ERR_ARG, "accumulator has no scratch for the banded path");
+    float *part = reinterpret_cast<float *>(acc->d_work.as<char>() + bp.scratch_bytes);
     float *a = acc->d_acc.as<float>();
     const BandChan *chans = bp.d_chans.as<BandChan>();
     // Under graph capture both passes stay on the capturing stream, in order.
@@ -798,12 +915,9 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
             if (split && pass == 1) EPIC_HIP(hipStreamWaitEvent(q_cols, ev[1 + b], 0));
             for (const BandSize &bs : bp.sizes) {
                 epic_status st = EPIC_OK;
-                if (bs.R == 16)
-                    st = p->P == 2 ? launch_sq<16, 2>(p, bs, pass, v, nt, scratch, a, qs)
-                                   : launch_sq<16, 1>(p, bs, pass, v, nt, scratch, a, qs);
-                else if (bs.R == 8)
-                    st = p->P == 2 ? launch_sq<8, 2>(p, bs, pass, v, nt, scratch, a, qs)
-                                   : launch_sq<8, 1>(p, bs, pass, v, nt, scratch, a, qs);
+                if (bs.R)
+                    st = p->P == 2 ? launch_pw_any<2>(p, bs, pass, v, nt, scratch, part, a, qs)
+                                   : launch_pw_any<1>(p, bs, pass, v, nt, scratch, part, a, qs);
                 else
                     st = launch_generic(p, bs, pass, chans, v, nt, scratch, a, qs);
                 if (st) return st;

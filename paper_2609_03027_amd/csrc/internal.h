@@ -116,7 +116,7 @@ struct BandRadices {
     int32_t r[12];
 };
 
-// One (channel, 8-row band) of a square-radix grid side: its gather entries.
+// One (channel, 8-row band) of a register-radix grid side: its gather entries.
 struct BandItem {
     int32_t chan;            // channel within its size group's BandChan range
     int32_t band;
@@ -128,7 +128,11 @@ struct BandItem {
 // Banded channels of one grid side.
 struct BandSize {
     int N = 0;
-    int R = 0;               // N = R * R with R in {8, 16}: two-step kernels; 0: generic
+    int R = 0;               // N = R^NP (16^2, 8^2, 8^3): register-radix kernels; 0: generic
+    int NP = 0;
+    int slices = 1;          // column-pass time slices (partial sums reduced after)
+    int64_t part_off = 0;    // float offset of this size's partial sums
+    int64_t part_stride = 0; // floats per slice
     int n = 0;               // channels
     int max_bands = 0;       // 8-row bands of the widest footprint span
     int64_t chan_off = 0;    // first BandChan of this size
@@ -141,7 +145,8 @@ struct BandPlan {
     int n = 0;               // banded channels
     int t_chunk = 0;         // samples per pass-1/pass-2 round
     int64_t scratch_t = 0;   // float4 per sample of row transforms
-    int64_t scratch_bytes = 0;
+    int64_t scratch_bytes = 0;  // two halves of row transforms
+    int64_t part_bytes = 0;     // column-pass partial sums, after the scratch
     std::vector<BandSize> sizes;
     std::vector<BandChan> host;
     DevBuf d_chans;          // BandChan[n]

@@ -231,7 +231,7 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     if (p->precision == EPIC_F32) {
         if ((st = fused_build(p, j0, w, s))) return st;
         if ((st = banded_build(p, j0, w, s))) return st;
-        p->work_bytes = p->band.scratch_bytes;
+        p->work_bytes = p->band.scratch_bytes + p->band.part_bytes;
     } else {
         if ((st = gemm_build(p, s))) return st;
         p->work_bytes = p->gemm.vbuf_bytes;

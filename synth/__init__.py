@@ -116,6 +116,13 @@ def _make_workloads():
         name="stream", n_ant=4096, n_pol=2, n_time=256, disc_diameter_m=300.0,
         min_spacing_m=1.0, chan_freq_hz=f5,
         grid_n=np.full(64, 256, dtype=np.int32), n_src=3, seed=1005)
+    # Wide-field large array: ~20 000 dual-pol elements (a few tens of
+    # SKA-Low stations' worth) in a 700 m disc, one 781.25 kHz coarse channel
+    # at 100 MHz, 512x512 grid, 781 samples = 1 ms of data per image.
+    w["wide"] = Workload(
+        name="wide", n_ant=20000, n_pol=2, n_time=781, disc_diameter_m=700.0,
+        min_spacing_m=1.0, chan_freq_hz=np.array([100e6]),
+        grid_n=np.array([512], dtype=np.int32), n_src=3, seed=1006)
     return w
 
 
