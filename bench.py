@@ -324,6 +324,24 @@ def wide_field(E, torch, reps=3):
     return res
 
 
+def fill_bandwidth(torch, mib=1024, reps=5):
+    """Device fill of ``mib`` MiB timed with events: bytes written per
+    second (the write-only ceiling of a pass that mostly stores)."""
+    n = mib * (1 << 20) // 4
+    dst = torch.empty(n, dtype=torch.float32, device="cuda")
+    dst.fill_(1.0)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for k in range(reps):
+        dst.fill_(float(k))
+    b.record()
+    torch.cuda.synchronize()
+    s = a.elapsed_time(b) / reps / 1e3
+    del dst
+    return mib * (1 << 20) / s / 1e9
+
+
 def large_stream(E, torch, reps=3):
     """Large-N streaming array: 4096 dual-pol elements in a 300 m disc,
     64 channels at 92-108 MHz, 256 x 256 grids, one block of 256 samples
@@ -366,6 +384,7 @@ def large_stream(E, torch, reps=3):
     rounds = -(-wl.n_time // max(1, (1 << 30) // (rows * 256 * 16)))
     sums = rounds * 2 * wl.n_chan * 4 * 256 * 256 * 4
     copy_gbs = copy_bandwidth(torch)
+    fill_gbs = fill_bandwidth(torch)
     res = {"workload": "stream-large: 4096 dual-pol elements, 300 m disc, 64 channels "
                        "92-108 MHz, 256^2 grids, one 256-sample block",
            "path": "banded two-pass", "ms_per_block": ms, "block_data_ms": block_ms,
@@ -375,11 +394,13 @@ def large_stream(E, torch, reps=3):
            "hbm_bytes_per_block": scratch + sums,
            "hbm_GBps": (scratch + sums) / (ms / 1e3) / 1e9,
            "hbm_copy_GBps": copy_gbs,
+           "hbm_fill_GBps": fill_gbs,
            "plan_s": tplan, "plan_bytes": info["bytes_plan"], "acc_bytes": info["bytes_acc"],
            "gen_s": tgen}
     log(f"large stream: {ms:.2f} ms per {block_ms:.3f} ms block "
         f"({block_ms / ms:.2f} of real time; fused 64x64 {ms_fused:.2f} ms), plan {tplan:.1f} s; "
-        f"scratch + sums {res['hbm_GBps']:.0f} GB/s, device copy {copy_gbs:.0f} GB/s")
+        f"scratch + sums {res['hbm_GBps']:.0f} GB/s, device copy {copy_gbs:.0f} GB/s, "
+        f"fill {fill_gbs:.0f} GB/s")
     return res
 
 

@@ -48,6 +48,14 @@ __device__ __forceinline__ float4 q_mul(float4 a, float2 w) {
 }
 __device__ __forceinline__ float4 q_mul_i(float4 a) { return make_float4(-a.y, a.x, -a.w, a.z); }
 
+// The value unchanged, but opaque to the optimiser: per-sample address
+// offsets pass through it so that loop-invariant motion does not hoist
+// loop-invariant 64-bit address sums (two VGPRs per load) out of the sample loop.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // One radix-R Stockham pass over BL lines (positive exponent).
 template <int R>
 __device__ __forceinline__ void stockham_pass(const float4 *src, float4 *dst, int N, int pitch,
@@ -174,9 +182,15 @@ __device__ __forceinline__ void rot_all(float4 (&v)[R]) {
     }
 }
 
-// R-point DFT (R = 8, 16), positive exponent, natural order in and out:
+// R-point DFT (R = 8, 16), positive exponent, natural order in, outputs
+// left where the last stage computes them: X[k] in v[dpos<R>(k)].
 // n = (R / 4) n1 + n2, k = k1 + 4 k2; 4-point DFTs over n1, twiddles
-// exp(+2 pi i n2 k1 / R), then (R / 4)-point DFTs over n2.
+// exp(+2 pi i n2 k1 / R), then (R / 4)-point DFTs over n2 in place.
+template <int R>
+__device__ __forceinline__ constexpr int dpos(int k) {
+    return (R / 4) * (k % 4) + k / 4;
+}
+
 template <int R>
 __device__ __forceinline__ void dft(float4 (&v)[R]) {
     constexpr int S = R / 4;
@@ -195,13 +209,6 @@ __device__ __forceinline__ void dft(float4 (&v)[R]) {
         }
     }
     // v[S k1 + k2] = X[k1 + 4 k2]
-    float4 o[R];
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1)
-#pragma unroll
-        for (int k2 = 0; k2 < S; ++k2) o[k1 + 4 * k2] = v[S * k1 + k2];
-#pragma unroll
-    for (int k = 0; k < R; ++k) v[k] = o[k];
 }
 
 BandRadices radices_of(int N) {
@@ -385,7 +392,8 @@ __device__ __forceinline__ constexpr int padr(int p) {
 }
 
 // Passes 1 .. NP-1 of one line held by thread j (pass 0 already applied to
-// v, in registers).  line: this line's LDS base; twl: exp(+2 pi i n / N).
+// v, in registers, outputs at dpos).  line: this line's LDS base; twl:
+// exp(+2 pi i n / N).  Leaves X[j + qL] in v[dpos<R>(q)].
 template <int R, int NP>
 __device__ __forceinline__ void pw_rest(float4 (&v)[R], float4 *line, int j,
                                         const float2 *twl) {
@@ -395,7 +403,8 @@ __device__ __forceinline__ void pw_rest(float4 (&v)[R], float4 *line, int j,
     for (int s = 1; s < NP; ++s) {
         // write pass s-1 outputs
 #pragma unroll
-        for (int q = 0; q < R; ++q) line[padr<R>((j / Ns) * Ns * R + j % Ns + q * Ns)] = v[q];
+        for (int q = 0; q < R; ++q)
+            line[padr<R>((j / Ns) * Ns * R + j % Ns + q * Ns)] = v[dpos<R>(q)];
         __syncthreads();
         Ns *= R;
         const int k = j % Ns, tstep = N / (Ns * R);
@@ -436,11 +445,13 @@ constexpr int cols_pitch() {
 }
 
 // Pass 1.  One workgroup per (item, sample): thread (l, j) = (tid / L,
-// tid % L) owns line l of the band.
+// tid % L) owns line l of the band.  (A variant that looped each workgroup
+// over a slice of samples with its gather list in registers measured slower:
+// the extra registers cost more occupancy than the reuse gained.)
 template <int R, int NP, int P>
 __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
-    const BandItem *__restrict__ items, int n_items, int nt, int64_t per_xcd,
+    const BandItem *__restrict__ items, int n_items, int G, int nt, int64_t per_xcd,
     const uint4 *__restrict__ entries, int A, const float2 *__restrict__ tw,
     float4 *__restrict__ scratch, int64_t scratch_t) {
     constexpr int N = Pw<R, NP>::N, L = Pw<R, NP>::L, T = rows_threads<R, NP>();
@@ -448,10 +459,16 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     constexpr int UN = T >= 256 ? 8 : 16;  // gather entries in flight per lane
     extern __shared__ float4 lds[];
     float2 *twl = reinterpret_cast<float2 *>(lds + BL * LP);
+    // Items come in blocks of G (one channel's bands, padded with empty
+    // items); the flat order is block, then sample, then item, so that the
+    // workgroups an XCD runs back to back share a sample's voltages and keep
+    // the block's gather lists in its L2.
     const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (w >= (int64_t)n_items * nt) return;
-    const int t = (int)(w % nt);
-    const BandItem it = items[w / nt];
+    const int64_t blk = w / ((int64_t)G * nt), rem = w % ((int64_t)G * nt);
+    const int t = (int)(rem / G);
+    const BandItem it = items[blk * G + rem % G];
+    if (it.n_iter < 0) return;
     const BandChan ch = chans[it.chan];
     const int tid = threadIdx.x;
     const int l = tid / L, j = tid % L;
@@ -460,19 +477,22 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
 #pragma unroll
     for (int k = 0; k < BL * N / T; ++k) lds[tid + k * T] = zero;
     __syncthreads();
-    // gather: each lane sums its own cells, entries [iter][lane]
+    // gather: each lane sums its own cells; every entry stores the running
+    // sum to its cell (the last entry of a cell leaves the full sum) and the
+    // last one restarts it, so the loop has no branches; padding entries
+    // point at the spare LDS slot after the band
     const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A;
     const uint4 *ent = entries + it.entry_off;
     float4 s = zero;
     for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
-        // iterations past n_iter re-read the last one and are dropped
+        // iterations past n_iter re-read the last one and become no-ops
         uint4 e[UN];
 #pragma unroll
         for (int k = 0; k < UN; ++k)
             e[k] = ent[(uint32_t)(min(i0 + k, it.n_iter - 1) * T + tid)];
 #pragma unroll
         for (int k = 0; k < UN; ++k)
-            if (i0 + k >= it.n_iter) e[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (i0 + k >= it.n_iter) e[k] = make_uint4(0u, (uint32_t)(BL * N), 0u, 0u);
         uint32_t bx[UN], by[UN];
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
@@ -492,10 +512,8 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
                 s.z += wr * yr - wi * yi;
                 s.w += wr * yi + wi * yr;
             }
-            if (e[k].x & 0x80000000u) {
-                lds[e[k].y] = s;
-                s = zero;
-            }
+            lds[e[k].y] = s;
+            if (e[k].x & 0x80000000u) s = zero;
         }
     }
     __syncthreads();
@@ -511,7 +529,7 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
         float4 *out = scratch + (int64_t)t * scratch_t + ch.scratch_off +
                       (int64_t)(row - ch.row_lo) * N + j;
 #pragma unroll
-        for (int q = 0; q < R; ++q) out[q * L] = v[q];
+        for (int q = 0; q < R; ++q) out[q * L] = v[dpos<R>(q)];
     }
 }
 
@@ -522,8 +540,18 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
 // registers over the samples t = slice, slice + S, ... of the round.  With
 // S = 1 the sums are added to the accumulators; otherwise each slice stores
 // them to part[slice] for k_band_reduce.
+// Waves per SIMD the column kernel is compiled for: two for the 16-point
+// passes (their 16 pixels x 4 sums, prefetch and transform registers need
+// up to 256 VGPRs); four for N = 8^3, where two 512-thread workgroups share
+// a CU if each stays within 128.
+template <int R, int NP>
+constexpr int cols_waves() {
+    return NP == 3 ? 4 : 2;
+}
+
 template <int R, int NP, int P>
-__global__ __launch_bounds__((cols_threads<R, NP>())) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__((cols_threads<R, NP>()))
+__attribute__((amdgpu_waves_per_eu((cols_waves<R, NP>()))))
 void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict__ tw,
                     const float4 *__restrict__ scratch, int64_t scratch_t, int nt,
                     float *__restrict__ acc, float *__restrict__ part, int64_t part_stride) {
@@ -543,21 +571,32 @@ void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict
     // branches around the loads) and are zeroed when used; 32-bit byte
     // offsets from a workgroup-uniform base keep the loads in base + offset
     // form.
-    uint32_t off[R], live = 0u;
+    // Byte offsets of the step-0 inputs: held in registers for the 16-point
+    // kernels, recomputed at each use for 8^3 (fewer live VGPRs there).
+    uint32_t live = 0u, offa[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = j + q * L;
-        const int rc = min(max(r, ch.row_lo), ch.row_hi);
-        off[q] = (uint32_t)((rc - ch.row_lo) * N + c0 + l) * (uint32_t)sizeof(float4);
         live |= (r >= ch.row_lo && r <= ch.row_hi) ? (1u << q) : 0u;
+        const int rc = min(max(r, ch.row_lo), ch.row_hi);
+        offa[q] = (uint32_t)((rc - ch.row_lo) * N + c0 + l) * (uint32_t)sizeof(float4);
     }
+    auto off = [&](int q) {
+        if constexpr (NP == 2) return offa[q];
+        const int rc = min(max(j + q * L, ch.row_lo), ch.row_hi);
+        return opaque((uint32_t)((rc - ch.row_lo) * N + c0 + l) * (uint32_t)sizeof(float4));
+    };
     const char *base = reinterpret_cast<const char *>(scratch + ch.scratch_off);
     const int64_t tstride = scratch_t * (int64_t)sizeof(float4);
+    // The 16-point kernels load the next sample while transforming the
+    // current one; the 8^3 kernel relies on its four waves per SIMD instead
+    // (the prefetch registers would not fit in 128 VGPRs).
+    constexpr bool PREF = NP == 2;
     float4 pre[R];
-    if (slice < nt) {
+    if (PREF && slice < nt) {
 #pragma unroll
         for (int q = 0; q < R; ++q)
-            pre[q] = *reinterpret_cast<const float4 *>(base + slice * tstride + off[q]);
+            pre[q] = *reinterpret_cast<const float4 *>(base + slice * tstride + off(q));
     }
     float av[R][NPROD];
 #pragma unroll
@@ -567,18 +606,23 @@ void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict
     float4 *line = lds + l * LP;
     for (int t = slice; t < nt; t += S) {
         float4 v[R];
+        if (!PREF) {
+            const char *cur = base + (int64_t)t * tstride;
+#pragma unroll
+            for (int q = 0; q < R; ++q) pre[q] = *reinterpret_cast<const float4 *>(cur + off(q));
+        }
 #pragma unroll
         for (int q = 0; q < R; ++q) v[q] = ((live >> q) & 1u) ? pre[q] : zero;
-        if (t + S < nt) {
+        if (PREF && t + S < nt) {
             const char *nx = base + (int64_t)(t + S) * tstride;
 #pragma unroll
-            for (int q = 0; q < R; ++q) pre[q] = *reinterpret_cast<const float4 *>(nx + off[q]);
+            for (int q = 0; q < R; ++q) pre[q] = *reinterpret_cast<const float4 *>(nx + off(q));
         }
         dft<R>(v);
         pw_rest<R, NP>(v, line, j, twl);
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const float4 e = v[q];
+            const float4 e = v[dpos<R>(q)];
             av[q][0] += e.x * e.x + e.y * e.y;
             if (P == 2) {
                 av[q][1] += e.z * e.z + e.w * e.w;
@@ -631,7 +675,8 @@ static int pw_radix(int N, int *np) {
 // element footprint cell in the band, cell index (row - r0) N + col.
 static epic_status band_items(epic_plan p, const std::vector<int> &j0,
                               const std::vector<double> &w, const BandChan &b, int chan_index,
-                              int T, std::vector<BandItem> &items, std::vector<uint4> &all) {
+                              int T, int G, std::vector<BandItem> &items,
+                              std::vector<uint4> &all) {
     const int A = p->A, K = p->K, N = b.N, c = b.c;
     const int n_bands = (b.row_hi - b.row_lo + 1 + BL - 1) / BL;
     std::vector<std::vector<GatherTap>> per(n_bands);
@@ -657,6 +702,18 @@ static epic_status band_items(epic_plan p, const std::vector<int> &j0,
         it.band = band;
         it.entry_off = (int64_t)all.size();
         it.n_iter = lpt_pack(per[band], T, all);
+        // the row kernel stores at every entry: padding (all-zero) entries
+        // point at the spare LDS slot after the band
+        for (size_t e = (size_t)it.entry_off; e < all.size(); ++e)
+            if (all[e].x == 0u && all[e].y == 0u && all[e].z == 0u && all[e].w == 0u)
+                all[e].y = (uint32_t)(BL * N);
+        items.push_back(it);
+    }
+    // pad the channel to whole blocks of G items with empty ones
+    for (int k = n_bands; k % G; ++k) {
+        BandItem it{};
+        it.chan = chan_index;
+        it.n_iter = -1;
         items.push_back(it);
     }
     return EPIC_OK;
@@ -680,6 +737,10 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
         bs.chan_off = (int64_t)bp.host.size();
         bs.tw_off = p->twid_off[N];
         bs.item_off = (int64_t)items.size();
+        // footprint row spans; items per block G: one channel's bands split
+        // evenly so a block's gather lists stay near 512 KB
+        std::vector<int> span_lo(p->C, 0), span_hi(p->C, -1);
+        int min_span = 1 << 30, max_bands = 1;
         for (int c = 0; c < p->C; ++c) {
             if (!p->banded[c] || p->ch[c].N != N) continue;
             int lo = 1 << 30, hi = -1;
@@ -688,6 +749,22 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
                 lo = std::min(lo, jy);
                 hi = std::max(hi, jy + p->K - 1);
             }
+            span_lo[c] = lo;
+            span_hi[c] = hi;
+            min_span = std::min(min_span, hi - lo + 1);
+            max_bands = std::max(max_bands, (hi - lo + 1 + BL - 1) / BL);
+        }
+        if (bs.R) {
+            const int T = BL * (N / bs.R);
+            const double taps = (double)p->A * p->K * p->K * BL / std::max(1, min_span);
+            const double item_bytes = 16.0 * (taps + T);
+            const int gmax = std::max(1, std::min(max_bands, (int)((512 << 10) / item_bytes)));
+            const int nblk = (max_bands + gmax - 1) / gmax;
+            bs.G = (max_bands + nblk - 1) / nblk;
+        }
+        for (int c = 0; c < p->C; ++c) {
+            if (!p->banded[c] || p->ch[c].N != N) continue;
+            const int lo = span_lo[c], hi = span_hi[c];
             BandChan b{};
             b.c = c;
             b.N = N;
@@ -699,7 +776,7 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
             // items index the channels of their own size group
             if (bs.R)
                 band_items(p, j0, w, b, (int)(bp.host.size() - bs.chan_off),
-                           BL * (bs.N / bs.R), items, all);
+                           BL * (bs.N / bs.R), bs.G, items, all);
             bp.host.push_back(b);
             bs.max_bands = std::max(bs.max_bands, (hi - lo + 1 + BL - 1) / BL);
             ++bs.n;
@@ -786,8 +863,9 @@ static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const ui
         const size_t lds = rows_pw_lds<R, NP>();
         hipLaunchKernelGGL((k_band_rows_pw<R, NP, P>), dim3((unsigned)(8 * per_xcd)), dim3(T),
                            lds, s, d_volt, vstride,
-                           chans, bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, nt,
-                           per_xcd, bp.d_entries.as<uint4>(), p->A, tw, scratch, bp.scratch_t);
+                           chans, bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, bs.G,
+                           nt, per_xcd, bp.d_entries.as<uint4>(), p->A, tw, scratch,
+                           bp.scratch_t);
         EPIC_HIP(hipGetLastError());
         return EPIC_OK;
     }

@@ -120,7 +120,7 @@ struct BandRadices {
 struct BandItem {
     int32_t chan;            // channel within its size group's BandChan range
     int32_t band;
-    int32_t n_iter;          // gather iterations per lane
+    int32_t n_iter;          // gather iterations per lane; -1: empty (block padding)
     int32_t pad;
     int64_t entry_off;       // first uint4 entry
 };
@@ -138,7 +138,8 @@ struct BandSize {
     int64_t chan_off = 0;    // first BandChan of this size
     int64_t tw_off = 0;      // twiddle table offset for N
     int64_t item_off = 0;    // first BandItem (R != 0)
-    int64_t n_items = 0;
+    int64_t n_items = 0;     // including the empty items that pad blocks
+    int G = 1;               // items per block (a channel's bands, padded)
 };
 
 struct BandPlan {
