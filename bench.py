@@ -277,6 +277,45 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return 2 * mib * (1 << 20) / s / 1e9
 
 
+def high_cadence(E, torch, reps=3):
+    """High-cadence frames (Eq. 2 over 4 samples each): the LWA-station
+    integration as 250 frames of 4 samples (160 us of data each), and the
+    wide-field array as 195 frames of 4 samples (5.12 us each) on the banded
+    path.  Frames are written to HBM as they complete."""
+    import synth
+    res = {}
+    for name, n_time, flen in (("lwa", 1000, 4), ("wide", 780, 4)):
+        wl = synth.workload(name).with_time(n_time)
+        pos = synth.antenna_layout(wl)
+        volt = torch.from_numpy(synth.voltages(wl, pos)).cuda()
+        plan = E.Plan.from_workload(wl, pos)
+        acc = E.Accumulator(plan)
+        nf = n_time // flen
+        out = torch.empty((nf, plan.info["image_floats"]), dtype=torch.float32, device="cuda")
+        E.accumulate_frames(plan, acc, volt, flen, out)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            E.accumulate_frames(plan, acc, volt, flen, out)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        sample_s = 1.0 / (25e3 if name == "lwa" else 781.25e3)
+        res[name] = {"frame_len": flen, "frames": nf, "ms": ms,
+                     "frame_data_us": flen * sample_s * 1e6,
+                     "frames_per_s": nf / (ms / 1e3),
+                     "real_time_fraction": n_time * sample_s * 1e3 / ms,
+                     "frame_bytes_GBps": out.numel() * 4 / (ms / 1e3) / 1e9}
+        log(f"frames {name}: {nf} frames of {flen} samples in {ms:.2f} ms "
+            f"({res[name]['real_time_fraction']:.2f} of real time, "
+            f"{res[name]['frame_bytes_GBps']:.0f} GB/s of frames)")
+        del out
+        acc.close()
+        plan.close()
+    return res
+
+
 def wide_field(E, torch, reps=3):
     """Wide-field large array: ~20 000 dual-pol elements in a 700 m disc, one
     781.25 kHz coarse channel at 100 MHz, 512 x 512 grid, 781 samples (1 ms
@@ -422,6 +461,8 @@ def main():
                     help="blocks per stream in the real-time streaming run (0 = skip)")
     ap.add_argument("--wide", type=int, default=1,
                     help="time the 512^2 wide-field array (0 = skip)")
+    ap.add_argument("--frames", type=int, default=1,
+                    help="time high-cadence 4-sample frames (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB for a plain device copy (counter calibration runs)")
     args = ap.parse_args()
@@ -522,7 +563,7 @@ def main():
                 "frac": bytes_step / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_fused_pair<1>",
+            "kernel": "k_fused_pair<1, false>",
             "achieved": achieved,
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
@@ -609,6 +650,8 @@ def main():
         out["large_stream"] = large_stream(E, torch)
     if args.wide:
         out["wide_field"] = wide_field(E, torch)
+    if args.frames:
+        out["high_cadence"] = high_cadence(E, torch)
 
     if args.stream_blocks > 0:
         out["streaming"] = {}

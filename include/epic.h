@@ -165,6 +165,20 @@ epic_status epic_image(epic_plan plan, const void *d_grid, int32_t n_time, void 
 epic_status epic_accumulate(epic_plan plan, epic_acc acc, const uint8_t *d_volt,
                             const void *d_sky, int32_t n_time, void *hip_stream);
 
+/* High-cadence frames (Sec. 4: transients on microsecond to millisecond
+ * scales; Eq. 2 with the average taken over frame_len samples): for each of
+ * the n_time / frame_len frames f, d_frames[f] (float[image_floats], layout
+ * of the accumulator) receives the Eq. 2 sums over samples f*frame_len ..
+ * (f+1)*frame_len - 1, without self-term removal or normalisation.  The
+ * accumulator only lends its working memory: its sums, self terms and count
+ * are unchanged.  n_time must be a multiple of frame_len (EPIC_ERR_ARG); FP32
+ * plans only, and on banded channels grid sides 64, 256 or 512 with
+ * frame_len within one scratch round (EPIC_ERR_UNSUPPORTED otherwise).  The
+ * caller owns d_frames (n_time / frame_len * image_floats floats). */
+epic_status epic_accumulate_frames(epic_plan plan, epic_acc acc, const uint8_t *d_volt,
+                                   int32_t n_time, int32_t frame_len, float *d_frames,
+                                   void *hip_stream);
+
 /* Read-out of Eq. 2: d_img = (acc - [REMOVE_AUTOS] self terms) / [NORMALISE] count.
  * The self term of element a is S_a^{pq} |B_a(k)|^2 with B_a the image of its
  * kernel footprint, evaluated exactly as sum_d H[d] exp(+2 pi i (k - N/2).d / N)

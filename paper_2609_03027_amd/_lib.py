@@ -31,6 +31,7 @@ EXPORTS = [
     "epic_acc_export", "epic_acc_import", "epic_grid", "epic_image",
     "epic_accumulate", "epic_readout", "epic_status_str", "epic_last_error",
     "epic_version", "epic_graph_create", "epic_graph_launch", "epic_graph_destroy",
+    "epic_accumulate_frames",
 ]
 
 
@@ -95,6 +96,7 @@ def load() -> C.CDLL:
         "epic_graph_create": [vp, vp, vp, i32, vp, C.POINTER(vp)],
         "epic_graph_launch": [vp, vp],
         "epic_graph_destroy": [vp],
+        "epic_accumulate_frames": [vp, vp, vp, i32, i32, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -283,6 +285,16 @@ def accumulate(plan: Plan, acc: Accumulator, volt=None, sky=None, n_time=None, s
         n_time = (volt if volt is not None else sky).shape[0]
     check(load().epic_accumulate(plan.handle, acc.handle, _ptr(volt), _ptr(sky), int(n_time),
                                  _stream(stream)))
+
+
+def accumulate_frames(plan: Plan, acc: Accumulator, volt, frame_len: int, out, n_time=None,
+                      stream=None):
+    """Eq. 2 sums of every ``frame_len`` consecutive samples into ``out``
+    (float32 ``[n_time // frame_len][image_floats]``); ``acc`` only lends its
+    working memory."""
+    n_time = volt.shape[0] if n_time is None else n_time
+    check(load().epic_accumulate_frames(plan.handle, acc.handle, _ptr(volt), int(n_time),
+                                        int(frame_len), _ptr(out), _stream(stream)))
 
 
 def readout(plan: Plan, acc: Accumulator, out, flags=REMOVE_AUTOS | NORMALISE, stream=None):

@@ -554,7 +554,8 @@ __global__ __launch_bounds__((cols_threads<R, NP>()))
 __attribute__((amdgpu_waves_per_eu((cols_waves<R, NP>()))))
 void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict__ tw,
                     const float4 *__restrict__ scratch, int64_t scratch_t, int nt,
-                    float *__restrict__ acc, float *__restrict__ part, int64_t part_stride) {
+                    float *__restrict__ acc, float *__restrict__ part, int64_t part_stride,
+                    int frame_len, float *__restrict__ frames, int64_t fstride) {
     constexpr int N = Pw<R, NP>::N, L = Pw<R, NP>::L, BC = cols_band<R, NP>();
     constexpr int T = cols_threads<R, NP>(), LP = cols_pitch<R, NP>();
     constexpr int NPROD = P == 2 ? 4 : 1;
@@ -562,6 +563,11 @@ void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict
     float2 *twl = reinterpret_cast<float2 *>(lds + BC * LP);
     const BandChan ch = chans[blockIdx.y];
     const int S = gridDim.z, slice = blockIdx.z;
+    // samples of this workgroup: every S-th from its slice, or (frame mode)
+    // the frame_len consecutive samples of frame `slice`
+    const int t_first = frame_len ? slice * frame_len : slice;
+    const int t_end = frame_len ? min(nt, t_first + frame_len) : nt;
+    const int t_step = frame_len ? 1 : S;
     const int c0 = blockIdx.x * BC;
     const int tid = threadIdx.x;
     const int l = tid % BC, j = tid / BC;
@@ -593,10 +599,10 @@ void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict
     // (the prefetch registers would not fit in 128 VGPRs).
     constexpr bool PREF = NP == 2;
     float4 pre[R];
-    if (PREF && slice < nt) {
+    if (PREF && t_first < t_end) {
 #pragma unroll
         for (int q = 0; q < R; ++q)
-            pre[q] = *reinterpret_cast<const float4 *>(base + slice * tstride + off(q));
+            pre[q] = *reinterpret_cast<const float4 *>(base + t_first * tstride + off(q));
     }
     float av[R][NPROD];
 #pragma unroll
@@ -604,7 +610,7 @@ void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict
 #pragma unroll
         for (int k = 0; k < NPROD; ++k) av[q][k] = 0.f;
     float4 *line = lds + l * LP;
-    for (int t = slice; t < nt; t += S) {
+    for (int t = t_first; t < t_end; t += t_step) {
         float4 v[R];
         if (!PREF) {
             const char *cur = base + (int64_t)t * tstride;
@@ -613,8 +619,8 @@ void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict
         }
 #pragma unroll
         for (int q = 0; q < R; ++q) v[q] = ((live >> q) & 1u) ? pre[q] : zero;
-        if (PREF && t + S < nt) {
-            const char *nx = base + (int64_t)(t + S) * tstride;
+        if (PREF && t + t_step < t_end) {
+            const char *nx = base + (int64_t)(t + t_step) * tstride;
 #pragma unroll
             for (int q = 0; q < R; ++q) pre[q] = *reinterpret_cast<const float4 *>(nx + off(q));
         }
@@ -633,7 +639,15 @@ void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict
         __syncthreads();   // every read of the last pass before the next writes
     }
     const int64_t plane = (int64_t)N * N;
-    if (S == 1) {
+    if (frame_len) {
+        float *dst0 = frames + slice * fstride + ch.img_off;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float *dst = dst0 + (int64_t)(j + q * L) * N + c0 + l;
+#pragma unroll
+            for (int k = 0; k < NPROD; ++k) dst[k * plane] = av[q][k];
+        }
+    } else if (S == 1) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             float *dst = acc + ch.img_off + (int64_t)(j + q * L) * N + c0 + l;
@@ -850,7 +864,8 @@ static epic_status ready_pw(int P) {
 
 template <int R, int NP, int P>
 static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const uint8_t *d_volt,
-                             int nt, float4 *scratch, float *part, float *acc, hipStream_t s) {
+                             int nt, float4 *scratch, float *part, float *acc,
+                             const FrameOut &fo, hipStream_t s) {
     const BandPlan &bp = p->band;
     const float2 *tw = p->d_twid.as<float2>() + bs.tw_off;
     const BandChan *chans = bp.d_chans.as<BandChan>() + bs.chan_off;
@@ -869,14 +884,16 @@ static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const ui
         EPIC_HIP(hipGetLastError());
         return EPIC_OK;
     }
-    const int S = bs.slices;
-    float *pp = S > 1 ? part + bs.part_off : nullptr;
+    // frame mode: one slice per frame of the round, stored to its image set
+    const int S = fo.len ? nt / fo.len : bs.slices;
+    float *pp = (!fo.len && S > 1) ? part + bs.part_off : nullptr;
     constexpr int BCW = cols_band<R, NP>(), TC = cols_threads<R, NP>();
     const size_t lds = cols_pw_lds<R, NP>();
     hipLaunchKernelGGL((k_band_cols_pw<R, NP, P>), dim3(bs.N / BCW, bs.n, S), dim3(TC), lds, s,
-                       chans, tw, scratch, bp.scratch_t, nt, acc, pp, bs.part_stride);
+                       chans, tw, scratch, bp.scratch_t, nt, acc, pp, bs.part_stride, fo.len,
+                       fo.out, fo.stride);
     EPIC_HIP(hipGetLastError());
-    if (S > 1) {
+    if (!fo.len && S > 1) {
         const int n_floats = p->n_prod * bs.N * bs.N;
         hipLaunchKernelGGL(k_band_reduce, dim3((n_floats + 255) / 256, bs.n), dim3(256), 0, s,
                            chans, n_floats, S, pp, bs.part_stride, acc);
@@ -888,11 +905,11 @@ static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const ui
 template <int P>
 static epic_status launch_pw_any(epic_plan p, const BandSize &bs, int pass,
                                  const uint8_t *d_volt, int nt, float4 *scratch, float *part,
-                                 float *acc, hipStream_t s) {
-    if (bs.R == 16) return launch_pw<16, 2, P>(p, bs, pass, d_volt, nt, scratch, part, acc, s);
+                                 float *acc, const FrameOut &fo, hipStream_t s) {
+    if (bs.R == 16) return launch_pw<16, 2, P>(p, bs, pass, d_volt, nt, scratch, part, acc, fo, s);
     if (bs.R == 8 && bs.NP == 2)
-        return launch_pw<8, 2, P>(p, bs, pass, d_volt, nt, scratch, part, acc, s);
-    return launch_pw<8, 3, P>(p, bs, pass, d_volt, nt, scratch, part, acc, s);
+        return launch_pw<8, 2, P>(p, bs, pass, d_volt, nt, scratch, part, acc, fo, s);
+    return launch_pw<8, 3, P>(p, bs, pass, d_volt, nt, scratch, part, acc, fo, s);
 }
 
 static epic_status launch_generic(epic_plan p, const BandSize &bs, int pass,
@@ -939,9 +956,20 @@ epic_status banded_acc_setup(epic_plan p, epic_acc acc) {
 // gets both passes itself, in order (the captured form of the two-queue
 // hand-over is not used).
 epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
-                              hipStream_t s, bool dry) {
+                              hipStream_t s, bool dry, const FrameOut &fo) {
     const BandPlan &bp = p->band;
     if (bp.n == 0) return EPIC_OK;
+    // rounds hold whole frames in frame mode
+    const int round = fo.len ? (bp.t_chunk / fo.len) * fo.len : bp.t_chunk;
+    if (fo.len) {
+        if (round == 0)
+            return fail(EPIC_ERR_UNSUPPORTED, "banded path: frame longer than a scratch round (" +
+                                                  std::to_string(bp.t_chunk) + " samples)");
+        for (const BandSize &bs : bp.sizes)
+            if (!bs.R)
+                return fail(EPIC_ERR_UNSUPPORTED,
+                            "frame mode on the banded path needs a grid side of 64, 256 or 512");
+    }
     for (const BandSize &bs : bp.sizes) {
         epic_status st = EPIC_OK;
         if (bs.R == 16) {
@@ -982,8 +1010,10 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
     }
     const int64_t half = (int64_t)bp.scratch_t * bp.t_chunk;
     int k = 0;
-    for (int t0 = 0; t0 < n_time; t0 += bp.t_chunk, ++k) {
-        const int nt = std::min(bp.t_chunk, n_time - t0);
+    for (int t0 = 0; t0 < n_time; t0 += round, ++k) {
+        const int nt = std::min(round, n_time - t0);
+        FrameOut fr = fo;
+        if (fo.len) fr.out = fo.out + (int64_t)(t0 / fo.len) * fo.stride;
         const int b = k & 1;
         float4 *scratch = acc->d_work.as<float4>() + b * half;
         const uint8_t *v = d_volt + (int64_t)t0 * p->C * p->P * p->A;
@@ -994,8 +1024,8 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
             for (const BandSize &bs : bp.sizes) {
                 epic_status st = EPIC_OK;
                 if (bs.R)
-                    st = p->P == 2 ? launch_pw_any<2>(p, bs, pass, v, nt, scratch, part, a, qs)
-                                   : launch_pw_any<1>(p, bs, pass, v, nt, scratch, part, a, qs);
+                    st = p->P == 2 ? launch_pw_any<2>(p, bs, pass, v, nt, scratch, part, a, fr, qs)
+                                   : launch_pw_any<1>(p, bs, pass, v, nt, scratch, part, a, fr, qs);
                 else
                     st = launch_generic(p, bs, pass, chans, v, nt, scratch, a, qs);
                 if (st) return st;

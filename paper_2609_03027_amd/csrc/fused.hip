@@ -188,13 +188,18 @@ __device__ __forceinline__ void slot_position(int tid, int s, int &row, int &col
 // When `autos` is given (A <= 4 T), the class-(0,0) item of each channel also
 // adds the per-element self-term sums S_a^{pq}, exact in int32.  AR is the
 // number of element rounds whose self terms a thread keeps (A <= AR * T).
-template <int M, int P, int AR>
+// FR: frame mode -- every frame_len samples the sums are stored to
+// frames[t / frame_len] (stride fstride floats) and restarted; acc is not
+// touched.
+template <int M, int P, int AR, bool FR>
 __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(const FusedItem *__restrict__ items,
                                                       const uint4 *__restrict__ entries,
                                                       const uint8_t *__restrict__ volt,
                                                       int64_t volt_t_stride, int A, int n_time,
                                                       float *__restrict__ acc,
-                                                      int32_t *__restrict__ autos) {
+                                                      int32_t *__restrict__ autos,
+                                                      int frame_len, float *__restrict__ frames,
+                                                      int64_t fstride) {
     constexpr int T = FCfg<M>::T, RA = FCfg<M>::RA, ROW = FCfg<M>::ROW;
     constexpr int NPIX = M * M / T;
     constexpr int NPROD = P == 2 ? 4 : 1;
@@ -300,19 +305,39 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
         // last pass + Eq. 2 products; the grid is left zeroed, and the stage
         // barrier of the next sample orders these writes before the gather
         pass_b_products<M, P, NPROD>(grid, tid, av);
+        if (FR && (t + 1) % frame_len == 0) {
+            const int N = it.N, R = it.R;
+            const int64_t plane = (int64_t)N * N;
+            float *fr = frames + (int64_t)(t / frame_len) * fstride + it.img_off;
+#pragma unroll
+            for (int k = 0; k < NPIX; ++k) {
+                int row, col;
+                slot_position<M>(tid, k, row, col);
+                const int ky = R * unscramble<M>(row) + it.oy;
+                const int kx = R * unscramble<M>(col) + it.ox;
+                float *dst = fr + (int64_t)ky * N + kx;
+#pragma unroll
+                for (int q = 0; q < NPROD; ++q) {
+                    dst[q * plane] = av[k][q];
+                    av[k][q] = 0.f;
+                }
+            }
+        }
     }
 
     const int N = it.N, R = it.R;
     const int64_t plane = (int64_t)N * N;
+    if (!FR) {
 #pragma unroll
-    for (int k = 0; k < NPIX; ++k) {
-        int row, col;
-        slot_position<M>(tid, k, row, col);
-        const int ky = R * unscramble<M>(row) + it.oy;
-        const int kx = R * unscramble<M>(col) + it.ox;
-        float *dst = acc + it.img_off + (int64_t)ky * N + kx;
+        for (int k = 0; k < NPIX; ++k) {
+            int row, col;
+            slot_position<M>(tid, k, row, col);
+            const int ky = R * unscramble<M>(row) + it.oy;
+            const int kx = R * unscramble<M>(col) + it.ox;
+            float *dst = acc + it.img_off + (int64_t)ky * N + kx;
 #pragma unroll
-        for (int q = 0; q < NPROD; ++q) dst[q * plane] += av[k][q];
+            for (int q = 0; q < NPROD; ++q) dst[q * plane] += av[k][q];
+        }
     }
     if (own_autos) {
 #pragma unroll
@@ -341,13 +366,14 @@ __device__ __forceinline__ float uni(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-template <int AR>
+template <int AR, bool FR>
 __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict__ items,
                                                     const uint4 *__restrict__ entries,
                                                     const uint8_t *__restrict__ volt,
                                                     int64_t volt_t_stride, int A, int n_time,
                                                     float *__restrict__ acc,
-                                                    int32_t *__restrict__ autos) {
+                                                    int32_t *__restrict__ autos, int frame_len,
+                                                    float *__restrict__ frames, int64_t fstride) {
     constexpr int M = 64, T = 512, ROW = 65, GSZ = M * ROW, S = 8;
     extern __shared__ float4 smem[];
     Grid<2> g, h;
@@ -490,18 +516,37 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
                 a[3] += vx[q].y * vy[q].x - vx[q].x * vy[q].y;
             }
         }
+        if (FR && (t + 1) % frame_len == 0) {
+            const int N = it.N;
+            const int64_t plane = (int64_t)N * N;
+            float *fr = frames + (int64_t)(t / frame_len) * fstride + it.img_off;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int oy = s >> 3, q = s & 7;
+                const int ky = 2 * unscramble<64>(j * 8 + q) + oy;
+                const int kx = 2 * unscramble<64>(line) + it.ox;
+                float *dst = fr + (int64_t)ky * N + kx;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    dst[p * plane] = av[s][p];
+                    av[s][p] = 0.f;
+                }
+            }
+        }
     }
 
     const int N = it.N;
     const int64_t plane = (int64_t)N * N;
+    if (!FR) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int oy = s >> 3, q = s & 7;
-        const int ky = 2 * unscramble<64>(j * 8 + q) + oy;
-        const int kx = 2 * unscramble<64>(line) + it.ox;
-        float *dst = acc + it.img_off + (int64_t)ky * N + kx;
+        for (int s = 0; s < 16; ++s) {
+            const int oy = s >> 3, q = s & 7;
+            const int ky = 2 * unscramble<64>(j * 8 + q) + oy;
+            const int kx = 2 * unscramble<64>(line) + it.ox;
+            float *dst = acc + it.img_off + (int64_t)ky * N + kx;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) dst[p * plane] += av[s][p];
+            for (int p = 0; p < 4; ++p) dst[p * plane] += av[s][p];
+        }
     }
     if (own_autos) {
 #pragma unroll
@@ -775,72 +820,99 @@ epic_status lds_ready(const void *kern, size_t lds) {
     return EPIC_OK;
 }
 
-template <int M, int P, int AR>
-static epic_status launch_fused_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                   int A, int n_time, float *acc, int32_t *autos, hipStream_t s,
-                                   bool dry) {
+template <int M, int P, int AR, bool FR>
+static epic_status launch_fused_fr(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
+                                   int A, int n_time, float *acc, int32_t *autos,
+                                   const FrameOut &fo, hipStream_t s, bool dry) {
     constexpr int T = FCfg<M>::T, GSZ = M * FCfg<M>::ROW;
     const size_t lds = sizeof(float2) * P * GSZ + sizeof(float4) * (size_t)A;
-    auto kern = k_fused<M, P, AR>;
+    auto kern = k_fused<M, P, AR, FR>;
     epic_status st = lds_ready(reinterpret_cast<const void *>(kern), lds);
     if (st || dry) return st;
     hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(T), lds, s, g->items.as<FusedItem>(),
-                       g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos);
+                       g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos, fo.len,
+                       fo.out, fo.stride);
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
+}
+
+template <int M, int P, int AR>
+static epic_status launch_fused_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
+                                   int A, int n_time, float *acc, int32_t *autos,
+                                   const FrameOut &fo, hipStream_t s, bool dry) {
+    return fo.len ? launch_fused_fr<M, P, AR, true>(g, d_volt, vstride, A, n_time, acc, autos,
+                                                    fo, s, dry)
+                  : launch_fused_fr<M, P, AR, false>(g, d_volt, vstride, A, n_time, acc, autos,
+                                                     fo, s, dry);
 }
 
 // Element rounds per thread: 1, 2 or 4; above 4 T the self terms come from a
 // separate pass (autos == nullptr).
 template <int M, int P>
 static epic_status launch_fused(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                int A, int n_time, float *acc, int32_t *autos, hipStream_t s,
-                                bool dry) {
+                                int A, int n_time, float *acc, int32_t *autos,
+                                const FrameOut &fo, hipStream_t s, bool dry) {
     constexpr int T = FCfg<M>::T;
-    if (A <= T) return launch_fused_ar<M, P, 1>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
+    if (A <= T)
+        return launch_fused_ar<M, P, 1>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
     if (A <= 2 * T)
-        return launch_fused_ar<M, P, 2>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
-    return launch_fused_ar<M, P, 4>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
+        return launch_fused_ar<M, P, 2>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
+    return launch_fused_ar<M, P, 4>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
 }
 
-template <int AR>
-static epic_status launch_pair_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                  int A, int n_time, float *acc, int32_t *autos, hipStream_t s,
-                                  bool dry) {
+template <int AR, bool FR>
+static epic_status launch_pair_fr(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
+                                  int A, int n_time, float *acc, int32_t *autos,
+                                  const FrameOut &fo, hipStream_t s, bool dry) {
     const size_t lds = sizeof(float4) * (2 * 64 * 65 + (size_t)A);
-    auto kern = k_fused_pair<AR>;
+    auto kern = k_fused_pair<AR, FR>;
     epic_status st = lds_ready(reinterpret_cast<const void *>(kern), lds);
     if (st || dry) return st;
     hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(512), lds, s, g->items.as<FusedItem>(),
-                       g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos);
+                       g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos, fo.len,
+                       fo.out, fo.stride);
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
 }
 
+template <int AR>
+static epic_status launch_pair_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
+                                  int A, int n_time, float *acc, int32_t *autos,
+                                  const FrameOut &fo, hipStream_t s, bool dry) {
+    return fo.len ? launch_pair_fr<AR, true>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry)
+                  : launch_pair_fr<AR, false>(g, d_volt, vstride, A, n_time, acc, autos, fo, s,
+                                              dry);
+}
+
 static epic_status launch_pair(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride, int A,
-                               int n_time, float *acc, int32_t *autos, hipStream_t s, bool dry) {
-    if (A <= 512) return launch_pair_ar<1>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
-    if (A <= 1024) return launch_pair_ar<2>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
-    return launch_pair_ar<4>(g, d_volt, vstride, A, n_time, acc, autos, s, dry);
+                               int n_time, float *acc, int32_t *autos, const FrameOut &fo,
+                               hipStream_t s, bool dry) {
+    if (A <= 512) return launch_pair_ar<1>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
+    if (A <= 1024) return launch_pair_ar<2>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
+    return launch_pair_ar<4>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
 }
 
 // Launches every size group; group i goes to branches[i] when given (graph
 // capture with parallel branches), else to s.  dry: only set up the kernels'
-// LDS allowance (done before a capture).
+// LDS allowance (done before a capture).  fo.len > 0: frame mode -- every
+// fo.len samples the sums go to the next image set of fo.out, the
+// accumulator's sums and self terms are left alone.
 epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
-                             hipStream_t s, const std::vector<hipStream_t> *branches, bool dry) {
+                             hipStream_t s, const std::vector<hipStream_t> *branches, bool dry,
+                             const FrameOut &fo) {
     const int64_t vstride = (int64_t)p->C * p->P * p->A;
-    float *a = acc ? acc->d_acc.as<float>() : nullptr;
+    const bool frames = fo.len > 0;
+    float *a = acc && !frames ? acc->d_acc.as<float>() : nullptr;
     // The fused kernels add the self-term sums when every group's threads
     // cover the elements in at most four rounds and no channel is banded;
     // otherwise a separate pass does it for every channel.
     bool in_kernel = p->band.n == 0;
     for (const FusedGroup *g : p->groups)
         if (p->A > 4 * threads_of(g->M)) in_kernel = false;
-    int32_t *au = (in_kernel && acc) ? acc->d_autos.as<int32_t>() : nullptr;
+    int32_t *au = (in_kernel && acc && !frames) ? acc->d_autos.as<int32_t>() : nullptr;
     if (p->band.n) {
         // forks onto the accumulator's own queues; joined back into s below
-        epic_status st = banded_accumulate(p, acc, d_volt, n_time, s, dry);
+        epic_status st = banded_accumulate(p, acc, d_volt, n_time, s, dry, fo);
         if (st) return st;
     }
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
@@ -849,20 +921,20 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
         epic_status st = EPIC_OK;
         const int A = p->A;
         if (g->kind == 1) {
-            st = launch_pair(g, d_volt, vstride, A, n_time, a, au, gs, dry);
+            st = launch_pair(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
         } else if (p->P == 2) {
-            if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
-            if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
-            if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
+            if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
+            if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
+            if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
         } else {
-            if (g->M == 64) st = launch_fused<64, 1>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
-            if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
-            if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, A, n_time, a, au, gs, dry);
+            if (g->M == 64) st = launch_fused<64, 1>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
+            if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
+            if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
         }
         if (st) return st;
     }
     if (dry) return EPIC_OK;
-    if (!in_kernel) {
+    if (!in_kernel && !frames) {
         epic_status st = autos_accumulate(p, acc, d_volt, n_time, s);
         if (st) return st;
     }

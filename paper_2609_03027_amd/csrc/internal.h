@@ -237,12 +237,20 @@ namespace epic {
 // plan.hip
 epic_status plan_build(epic_plan p, hipStream_t s);
 
+// Frame mode of an accumulate: len > 0 writes the Eq. 2 sums of every len
+// consecutive samples to out + (t / len) * stride instead of the accumulator.
+struct FrameOut {
+    int len = 0;
+    float *out = nullptr;
+    int64_t stride = 0;
+};
+
 // fused.hip
 epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
                         hipStream_t s);
 epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                              hipStream_t s, const std::vector<hipStream_t> *branches = nullptr,
-                             bool dry = false);
+                             bool dry = false, const FrameOut &fo = FrameOut());
 epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                              hipStream_t s);
 // One gather tap: destination cell (LDS index), element, complex weight.
@@ -261,7 +269,7 @@ bool banded_eligible(int N);
 epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
                          hipStream_t s);
 epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
-                              hipStream_t s, bool dry = false);
+                              hipStream_t s, bool dry = false, const FrameOut &fo = FrameOut());
 // Make s wait for the banded work launched by banded_accumulate.
 epic_status banded_join(epic_plan p, epic_acc acc, hipStream_t s);
 epic_status banded_acc_setup(epic_plan p, epic_acc acc);

@@ -189,7 +189,7 @@ def sky_sources(wl: Workload, seed: int | None = None):
 
 
 def complex_voltages(wl: Workload, pos: np.ndarray, lm: np.ndarray,
-                     block: int = 0, chans=None, noise: float = 1.0):
+                     block: int = 0, chans=None, noise: float = 1.0, transient=None):
     """Unquantised complex voltages ``complex128 [T][C][P][A]``.
 
     Each source has unit amplitude and a fresh random phase per sample;
@@ -197,6 +197,11 @@ def complex_voltages(wl: Workload, pos: np.ndarray, lm: np.ndarray,
     draw independent X/Y phases.  Noise is circular complex Gaussian with
     E|n|^2 = ``noise``.  Channel ``c`` draws from its own stream seeded by
     ``(seed, block, c)``, so any channel subset reproduces the same values.
+
+    ``transient`` = ``(t0, t1, l, m, amplitude)`` adds an unpolarised point
+    source of that amplitude at (l, m), present only in samples t0 <= t < t1,
+    with its own random phases (drawn after everything else, so the other
+    values do not change).
     """
     chans = np.arange(wl.n_chan) if chans is None else np.asarray(chans)
     T, P, A, S = wl.n_time, wl.n_pol, wl.n_ant, wl.n_src
@@ -214,6 +219,13 @@ def complex_voltages(wl: Workload, pos: np.ndarray, lm: np.ndarray,
         if noise > 0:
             g = rng.standard_normal(size=(T, P, A, 2)) * np.sqrt(noise / 2)
             v = v + (g[..., 0] + 1j * g[..., 1])
+        if transient is not None:
+            t0, t1, tl, tm, amp = transient
+            tgeo = np.exp(-2j * np.pi * (pos @ np.array([tl, tm])) / lam)        # (A,)
+            tph = rng.uniform(0.0, 2 * np.pi, size=(T, P))
+            on = np.zeros(T)
+            on[int(t0):int(t1)] = amp
+            v = v + (on[:, None] * np.exp(1j * tph))[:, :, None] * tgeo[None, None, :]
         out[:, ci] = v
     return out
 
@@ -239,9 +251,11 @@ def pack_int4(q: np.ndarray) -> np.ndarray:
 
 def voltages(wl: Workload, pos: np.ndarray | None = None,
              lm: np.ndarray | None = None, block: int = 0, chans=None,
-             noise: float = 1.0) -> np.ndarray:
-    """Packed 4+4-bit voltages ``uint8 [T][C][P][A]`` for one block."""
+             noise: float = 1.0, transient=None) -> np.ndarray:
+    """Packed 4+4-bit voltages ``uint8 [T][C][P][A]`` for one block
+    (``transient``: see ``complex_voltages``)."""
     pos = antenna_layout(wl) if pos is None else pos
     lm = sky_sources(wl) if lm is None else lm
-    v = complex_voltages(wl, pos, lm, block=block, chans=chans, noise=noise)
+    v = complex_voltages(wl, pos, lm, block=block, chans=chans, noise=noise,
+                         transient=transient)
     return pack_int4(quantise(v, wl.n_src, noise))

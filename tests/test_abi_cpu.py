@@ -137,6 +137,7 @@ def test_data_calls_reject_null_handles():
     assert lib.epic_grid(None, None, 1, None, None) == 1
     assert lib.epic_image(None, None, 1, None, None) == 1
     assert lib.epic_accumulate(None, None, None, None, 1, None) == 1
+    assert lib.epic_accumulate_frames(None, None, None, 8, 4, None, None) == 1
     assert lib.epic_readout(None, None, None, 0, None) == 1
     assert lib.epic_acc_create(None, None) == 1
     assert lib.epic_acc_reset(None, None) == 1

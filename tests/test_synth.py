@@ -41,3 +41,12 @@ def test_workload_tables():
     assert lwa.samples_per_block() == 1000 * 128 * 2 * 256
     st = synth.workload("stream")
     assert st.n_chan == 64 and int(st.grid_n[0]) == 256
+
+
+def test_transient_changes_only_its_samples():
+    wl = synth.workload("tiny2")
+    pos = synth.antenna_layout(wl)
+    a = synth.voltages(wl, pos)
+    b = synth.voltages(wl, pos, transient=(8, 12, 0.2, -0.1, 3.0))
+    changed = np.nonzero((a != b).any(axis=(1, 2, 3)))[0]
+    assert changed.min() >= 8 and changed.max() <= 11 and len(changed) >= 3
