@@ -20,7 +20,9 @@
  *   errors are returned, faults surface on a later call as EPIC_ERR_DEVICE.
  * - Voltages: uint8 volt[t][c][p][a], one byte per complex sample, real
  *   part in the high nibble, imaginary part in the low nibble, both two's
- *   complement (0x8 decodes to -8).
+ *   complement (0x8 decodes to -8).  With the plan flag EPIC_VOLT_8BIT:
+ *   int8 volt[t][c][p][a][2], real byte then imaginary byte (8 + 8 bits, the
+ *   digitisation of the paper's synthetic test, Sec. 4).
  * - Grid geometry (the reading of Eq. 1 the library implements): channel c
  *   has wavelength lambda_c = 299792458 / f_c, cell = cell_lambda * lambda_c,
  *   grid side N_c (even).  Element a sits at x_a = pos_a / cell + N_c / 2
@@ -33,7 +35,9 @@
  *     grid / sky : complex64 [t][c][p][N_c][N_c]     (P * N_c^2 per c)
  *     images     : float32   [c][n_prod][N_c][N_c]   (n_prod = 1 if P = 1,
  *                  else 4: XX, YY, Re XY, Im XY with XY = Ex conj(Ey))
- *     autos      : int32     [c][a][n_prod]  sum_t E_a^p conj(E_a^q)
+ *     autos      : int32     [c][a][n_prod]  sum_t E_a^p conj(E_a^q), exact
+ *                  while the sums fit int32 (4+4 bit: 2^31 / 128 samples;
+ *                  8+8 bit: 2^31 / 32768 = 65536 samples per accumulator)
  * - A plan is immutable after creation and may be used from several threads
  *   and streams.  An accumulator must not be used on two streams at once.
  */
@@ -68,6 +72,7 @@ typedef enum {
 
 /* plan flags */
 #define EPIC_PLAN_DEFAULT 0u
+#define EPIC_VOLT_8BIT 1u      /* 8+8-bit voltages (2 bytes per sample); not with FP8 */
 
 /* sub_n value that selects the banded two-pass path for a channel */
 #define EPIC_SUB_BANDED (-1)
@@ -91,7 +96,7 @@ typedef struct {
     const float *kernel_table;   /* optional host [C][A][K][K][2]: complex W_a on its
                                     support cells [dy][dx] (replaces the Gaussian); copied */
     int32_t precision;           /* epic_precision */
-    uint32_t flags;              /* EPIC_PLAN_DEFAULT */
+    uint32_t flags;              /* EPIC_PLAN_DEFAULT or EPIC_VOLT_8BIT */
     const int32_t *sub_n;        /* optional host [C], FP32 only: side M of the
                                     sub-transforms the fused path splits channel c into
                                     (16, 32 or 64, dividing grid_n[c], at most 8 per

@@ -45,13 +45,29 @@ __all__ = [
     "support_inside", "grid", "centred_dft_matrix", "sky", "n_products",
     "accumulate", "antenna_autos", "antenna_beams", "auto_term", "auto_term_by_element",
     "readout",
-    "fx_image", "channel_reference", "epic_reference",
+    "fx_image", "channel_reference", "epic_reference", "decode_int8", "decode_voltages",
 ]
 
 
 # --------------------------------------------------------------------------
 # Voltages
 # --------------------------------------------------------------------------
+def decode_int8(v) -> np.ndarray:
+    """8+8-bit samples ``int8 [..., 2]`` (real, imaginary) -> complex integer
+    (the digitisation of the paper's synthetic test, Sec. 4)."""
+    v = np.asarray(v, dtype=np.int8).astype(np.float64)
+    return v[..., 0] + 1j * v[..., 1]
+
+
+def decode_voltages(v) -> np.ndarray:
+    """Either format: packed 4+4-bit bytes, or int8 (re, im) pairs in a
+    trailing axis of length 2."""
+    v = np.asarray(v)
+    if v.dtype == np.int8 and v.shape[-1] == 2:
+        return decode_int8(v)
+    return decode_int4(v)
+
+
 def decode_int4(b) -> np.ndarray:
     """4+4-bit packed byte -> complex integer (Sec. 4 digitised voltages).
 
@@ -305,7 +321,8 @@ def fx_image(E, j0, w, n, include_auto=True) -> np.ndarray:
 def channel_reference(volt_c, pos, freq_hz, n, *, cell_lambda=0.5, k=3,
                       sigma=0.5, kernel=None, aperture_n=0,
                       want_images=False, want_auto=True):
-    """Reference for one channel of packed voltages ``uint8 [T][P][A]``.
+    """Reference for one channel of voltages ``uint8 [T][P][A]`` (4+4 bit) or
+    ``int8 [T][P][A][2]`` (8+8 bit).
 
     ``kernel`` optionally replaces the Gaussian with explicit complex weights
     [A][K][K] (the weight W_a on each support cell).  Returns a dict with
@@ -314,7 +331,7 @@ def channel_reference(volt_c, pos, freq_hz, n, *, cell_lambda=0.5, k=3,
     per-sample grids and sky images.  ``want_auto=False`` leaves ``auto``
     as None (its cost grows as A N^2).
     """
-    E = decode_int4(volt_c)                          # [T][P][A]
+    E = decode_voltages(volt_c)                      # [T][P][A]
     x, j0 = grid_geometry(pos, freq_hz, n, cell_lambda, k)
     if not support_inside(j0, k, n, aperture_n):
         raise ValueError("an element's kernel support leaves the gridded region")

@@ -19,6 +19,7 @@ EPIC_F32, EPIC_F16_MFMA, EPIC_F8E4M3_MFMA, EPIC_BF16X2_MFMA = 0, 1, 2, 3
 REMOVE_AUTOS = 1
 NORMALISE = 2
 SUB_BANDED = -1        # sub_n value: banded two-pass path for that channel
+VOLT_8BIT = 1          # plan flag: 8+8-bit voltages, int8 [t][c][p][a][2]
 
 STATUS = {0: "EPIC_OK", 1: "EPIC_ERR_NULL", 2: "EPIC_ERR_ARG", 3: "EPIC_ERR_GRID",
           4: "EPIC_ERR_UNSUPPORTED", 5: "EPIC_ERR_OOM", 6: "EPIC_ERR_DEVICE",
@@ -137,7 +138,7 @@ class Plan:
 
     def __init__(self, pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5,
                  kernel_k=3, kernel_sigma=0.5, kernel_table=None, precision=EPIC_F32,
-                 sub_n=None, stream=None):
+                 sub_n=None, volt_bits=4, stream=None):
         lib = load()
         self._pos = np.ascontiguousarray(pos, dtype=np.float64)
         self._freq = np.ascontiguousarray(freq_hz, dtype=np.float64)
@@ -158,7 +159,9 @@ class Plan:
         d.kernel_table = (None if self._table is None else
                           self._table.ctypes.data_as(C.POINTER(C.c_float)))
         d.precision = int(precision)
-        d.flags = 0
+        if volt_bits not in (4, 8):
+            raise ValueError("volt_bits must be 4 or 8")
+        d.flags = VOLT_8BIT if volt_bits == 8 else 0
         self._sub = None if sub_n is None else np.ascontiguousarray(sub_n, dtype=np.int32)
         d.sub_n = None if self._sub is None else self._sub.ctypes.data_as(C.POINTER(C.c_int32))
         h = C.c_void_p()
@@ -174,9 +177,11 @@ class Plan:
         self.img_off = np.concatenate([[0], np.cumsum(self.n_prod * n2)[:-1]])
         self.grid_off = np.concatenate([[0], np.cumsum(self.n_pol * n2)[:-1]])
         self.precision = precision
+        self.volt_bits = volt_bits
 
     @classmethod
     def from_workload(cls, wl, pos, **kw):
+        kw.setdefault("volt_bits", getattr(wl, "volt_bits", 4))
         return cls(pos, wl.chan_freq_hz, wl.grid_n, wl.n_pol, aperture_n=wl.aperture_n,
                    cell_lambda=wl.cell_lambda, kernel_k=wl.kernel_k,
                    kernel_sigma=wl.kernel_sigma_cells, **kw)

@@ -76,6 +76,9 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     if (!(sg > 0.0) || !std::isfinite(sg)) return fail(EPIC_ERR_ARG, "kernel_sigma_cells must be > 0");
     if (d->precision < EPIC_F32 || d->precision > EPIC_BF16X2_MFMA)
         return fail(EPIC_ERR_ARG, "unknown precision");
+    if (d->flags & ~EPIC_VOLT_8BIT) return fail(EPIC_ERR_ARG, "unknown plan flags");
+    if ((d->flags & EPIC_VOLT_8BIT) && d->precision == EPIC_F8E4M3_MFMA)
+        return fail(EPIC_ERR_UNSUPPORTED, "8+8-bit voltages are not exact in FP8 operands");
     if (d->aperture_n < 0 || (d->aperture_n & 1))
         return fail(EPIC_ERR_ARG, "aperture_n must be 0 or a positive even number");
     for (int c = 0; c < d->n_chan; ++c)
@@ -106,6 +109,7 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     p->sigma = sg;
     p->precision = d->precision;
     p->flags = d->flags;
+    p->vb = (d->flags & EPIC_VOLT_8BIT) ? 2 : 1;
     p->n_prod = p->P == 2 ? 4 : 1;
     p->pos.assign(d->ant_pos_m, d->ant_pos_m + 2 * p->A);
     p->freq.assign(d->chan_freq_hz, d->chan_freq_hz + p->C);

@@ -248,7 +248,7 @@ __global__ __launch_bounds__(BT) void k_band_rows(
     int n_chans, int max_bands, int nt, int64_t per_xcd, const int64_t *__restrict__ csr_base,
     const int32_t *__restrict__ csr_off, const int32_t *__restrict__ csr_ant,
     const float2 *__restrict__ csr_w, int A, int P, int N, BandRadices rad,
-    const float2 *__restrict__ tw, float4 *__restrict__ scratch, int64_t scratch_t) {
+    const float2 *__restrict__ tw, float4 *__restrict__ scratch, int64_t scratch_t, int vb) {
     extern __shared__ float4 lds[];
     const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (w >= (int64_t)n_chans * max_bands * nt) return;
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(BT) void k_band_rows(
     const int r0 = ch.row_lo + band * BL;
     if (r0 > ch.row_hi) return;
     float4 *b0 = lds, *b1 = lds + BL * N;
-    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A;
+    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * vb;
     const int32_t *off = csr_off + csr_base[ch.c];
     for (int i = threadIdx.x; i < BL * N; i += BT) {
         const int row = r0 + i / N, col = i % N;
@@ -270,13 +270,13 @@ __global__ __launch_bounds__(BT) void k_band_rows(
             for (int e = off[cell]; e < e1; ++e) {
                 const int a = csr_ant[e];
                 const float2 cw = csr_w[e];
-                const uint32_t bx = vx[a];
-                const float xr = (float)dec_re(bx), xi = (float)dec_im(bx);
+                const int2 x = volt_at(vx, a, vb);
+                const float xr = (float)x.x, xi = (float)x.y;
                 s.x += cw.x * xr - cw.y * xi;
                 s.y += cw.x * xi + cw.y * xr;
                 if (P == 2) {
-                    const uint32_t by = vx[A + a];
-                    const float yr = (float)dec_re(by), yi = (float)dec_im(by);
+                    const int2 y = volt_at(vx, A + a, vb);
+                    const float yr = (float)y.x, yi = (float)y.y;
                     s.z += cw.x * yr - cw.y * yi;
                     s.w += cw.x * yi + cw.y * yr;
                 }
@@ -453,7 +453,7 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
     const BandItem *__restrict__ items, int n_items, int G, int nt, int64_t per_xcd,
     const uint4 *__restrict__ entries, int A, const float2 *__restrict__ tw,
-    float4 *__restrict__ scratch, int64_t scratch_t) {
+    float4 *__restrict__ scratch, int64_t scratch_t, int vb) {
     constexpr int N = Pw<R, NP>::N, L = Pw<R, NP>::L, T = rows_threads<R, NP>();
     constexpr int LP = rows_pitch<R, NP>();
     constexpr int UN = T >= 256 ? 8 : 16;  // gather entries in flight per lane
@@ -481,7 +481,7 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     // sum to its cell (the last entry of a cell leaves the full sum) and the
     // last one restarts it, so the loop has no branches; padding entries
     // point at the spare LDS slot after the band
-    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A;
+    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * vb;
     const uint4 *ent = entries + it.entry_off;
     float4 s = zero;
     for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
@@ -497,18 +497,20 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
             const uint32_t a = e[k].x & 0x7fffffffu;
-            bx[k] = vx[a];
-            by[k] = P == 2 ? vx[A + a] : 0u;
+            bx[k] = volt_raw(vx, a, vb);
+            by[k] = P == 2 ? volt_raw(vx, A + a, vb) : 0u;
         }
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
             const float wr = __builtin_bit_cast(float, e[k].z);
             const float wi = __builtin_bit_cast(float, e[k].w);
-            const float xr = (float)dec_re(bx[k]), xi = (float)dec_im(bx[k]);
+            const int2 x = volt_dec(bx[k], vb);
+            const float xr = (float)x.x, xi = (float)x.y;
             s.x += wr * xr - wi * xi;
             s.y += wr * xi + wi * xr;
             if (P == 2) {
-                const float yr = (float)dec_re(by[k]), yi = (float)dec_im(by[k]);
+                const int2 y = volt_dec(by[k], vb);
+                const float yr = (float)y.x, yi = (float)y.y;
                 s.z += wr * yr - wi * yi;
                 s.w += wr * yi + wi * yr;
             }
@@ -870,7 +872,7 @@ static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const ui
     const float2 *tw = p->d_twid.as<float2>() + bs.tw_off;
     const BandChan *chans = bp.d_chans.as<BandChan>() + bs.chan_off;
     if (pass == 0) {
-        const int64_t vstride = (int64_t)p->C * p->P * p->A;
+        const int64_t vstride = p->vstride();
         const int64_t total = bs.n_items * nt;
         const int64_t per_xcd = (total + 7) / 8;
         if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
@@ -880,7 +882,7 @@ static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const ui
                            lds, s, d_volt, vstride,
                            chans, bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, bs.G,
                            nt, per_xcd, bp.d_entries.as<uint4>(), p->A, tw, scratch,
-                           bp.scratch_t);
+                           bp.scratch_t, p->vb);
         EPIC_HIP(hipGetLastError());
         return EPIC_OK;
     }
@@ -918,7 +920,7 @@ static epic_status launch_generic(epic_plan p, const BandSize &bs, int pass,
     const BandPlan &bp = p->band;
     const float2 *tw = p->d_twid.as<float2>() + bs.tw_off;
     if (pass == 0) {
-        const int64_t vstride = (int64_t)p->C * p->P * p->A;
+        const int64_t vstride = p->vstride();
         const int64_t total = (int64_t)bs.n * bs.max_bands * nt;
         const int64_t per_xcd = (total + 7) / 8;
         if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
@@ -927,7 +929,7 @@ static epic_status launch_generic(epic_plan p, const BandSize &bs, int pass,
                            chans + bs.chan_off, bs.n, bs.max_bands, nt, per_xcd,
                            p->d_csr_base.as<int64_t>(), p->d_csr_off.as<int32_t>(),
                            p->d_csr_ant.as<int32_t>(), p->d_csr_w.as<float2>(), p->A, p->P, bs.N,
-                           radices_of(bs.N), tw, scratch, bp.scratch_t);
+                           radices_of(bs.N), tw, scratch, bp.scratch_t, p->vb);
     } else {
         const dim3 grid(bs.N / BL, bs.n);
         const size_t lds = sizeof(float4) * 2 * BL * (bs.N + 1);
@@ -1016,7 +1018,7 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
         if (fo.len) fr.out = fo.out + (int64_t)(t0 / fo.len) * fo.stride;
         const int b = k & 1;
         float4 *scratch = acc->d_work.as<float4>() + b * half;
-        const uint8_t *v = d_volt + (int64_t)t0 * p->C * p->P * p->A;
+        const uint8_t *v = d_volt + (int64_t)t0 * p->vstride();
         if (split && k >= 2) EPIC_HIP(hipStreamWaitEvent(q_rows, ev[3 + b], 0));
         for (int pass = 0; pass < 2; ++pass) {
             const hipStream_t qs = pass ? q_cols : q_rows;

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_plan_beam(const int2 *__restrict__ j0,
 template <int DT>
 __global__ void k_volt_operand(const uint8_t *__restrict__ volt, int64_t vstride, int A, int Ap,
                                int P, int C, int n_time, int cols_pad,
-                               uint8_t *__restrict__ out) {
+                               uint8_t *__restrict__ out, int vb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = (int64_t)C * cols_pad * Ap;
     if (i >= tot) return;
@@ -137,9 +137,9 @@ __global__ void k_volt_operand(const uint8_t *__restrict__ volt, int64_t vstride
     const int t = col / P, p = col % P;
     float re = 0.f, im = 0.f;
     if (a < A && t < n_time) {
-        const uint32_t b = volt[(int64_t)t * vstride + ((int64_t)c * P + p) * A + a];
-        re = (float)dec_re(b);
-        im = (float)dec_im(b);
+        const int2 x = volt_at(volt + (int64_t)t * vstride, ((int64_t)c * P + p) * A + a, vb);
+        re = (float)x.x;
+        im = (float)x.y;
     }
     typedef typename Op<DT>::E E;
     E *o = reinterpret_cast<E *>(out) + ((int64_t)c * cols_pad + col) * 2 * Ap;
@@ -435,9 +435,9 @@ static epic_status gemm_chunk(epic_plan p, float *acc, uint8_t *vbuf, const uint
     GemmPlan &gp = p->gemm;
     const int cols_pad = ((nt * p->P + 15) / 16) * 16;
     const int64_t tot = (int64_t)p->C * cols_pad * gp.Ap;
-    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    const int64_t vstride = p->vstride();
     hipLaunchKernelGGL(k_volt_operand<DT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                       d_volt, vstride, p->A, gp.Ap, p->P, p->C, nt, cols_pad, vbuf);
+                       d_volt, vstride, p->A, gp.Ap, p->P, p->C, nt, cols_pad, vbuf, p->vb);
     EPIC_HIP(hipGetLastError());
     return p->P == 2 ? launch_gemm_ks<DT, 2>(p, acc, vbuf, cols_pad, s)
                      : launch_gemm_ks<DT, 1>(p, acc, vbuf, cols_pad, s);
@@ -446,7 +446,7 @@ static epic_status gemm_chunk(epic_plan p, float *acc, uint8_t *vbuf, const uint
 epic_status gemm_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                             hipStream_t s) {
     GemmPlan &gp = p->gemm;
-    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    const int64_t vstride = p->vstride();
     for (int t0 = 0; t0 < n_time; t0 += gp.t_chunk) {
         const int nt = std::min(gp.t_chunk, n_time - t0);
         const uint8_t *v = d_volt + (int64_t)t0 * vstride;

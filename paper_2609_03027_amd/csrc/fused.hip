@@ -199,7 +199,7 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
                                                       float *__restrict__ acc,
                                                       int32_t *__restrict__ autos,
                                                       int frame_len, float *__restrict__ frames,
-                                                      int64_t fstride) {
+                                                      int64_t fstride, int vb) {
     constexpr int T = FCfg<M>::T, RA = FCfg<M>::RA, ROW = FCfg<M>::ROW;
     constexpr int NPIX = M * M / T;
     constexpr int NPROD = P == 2 ? 4 : 1;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
         for (int q = 0; q < NPROD; ++q) av[k][q] = 0.f;
 
-    const uint8_t *vbase = volt + (int64_t)it.c * P * A;
+    const uint8_t *vbase = volt + (int64_t)it.c * P * A * vb;
     const uint4 *ent = entries + it.entry_off + tid;
     const int n_iter = it.n_iter;
     const bool own_autos = autos != nullptr && it.ox == 0 && it.oy == 0;
@@ -254,9 +254,9 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
         for (int k = 0; k < AR; ++k) {
             const int a = tid + k * T;
             if (a < A) {
-                const uint32_t bx = vt[a];
-                const uint32_t by = P == 2 ? (uint32_t)vt[A + a] : 0u;
-                const int xr = dec_re(bx), xi = dec_im(bx), yr = dec_re(by), yi = dec_im(by);
+                const int2 vx = volt_at(vt, a, vb);
+                const int2 vy = P == 2 ? volt_at(vt, A + a, vb) : make_int2(0, 0);
+                const int xr = vx.x, xi = vx.y, yr = vy.x, yi = vy.y;
                 stage[a] = make_float4((float)xr, (float)xi, (float)yr, (float)yi);
                 if (own_autos) {
                     sa[k][0] += xr * xr + xi * xi;
@@ -269,10 +269,9 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
             }
         }
         for (int a = tid + AR * T; a < A; a += T) {
-            const uint32_t bx = vt[a];
-            const uint32_t by = P == 2 ? (uint32_t)vt[A + a] : 0u;
-            stage[a] = make_float4((float)dec_re(bx), (float)dec_im(bx), (float)dec_re(by),
-                                   (float)dec_im(by));
+            const int2 vx = volt_at(vt, a, vb);
+            const int2 vy = P == 2 ? volt_at(vt, A + a, vb) : make_int2(0, 0);
+            stage[a] = make_float4((float)vx.x, (float)vx.y, (float)vy.x, (float)vy.y);
         }
         __syncthreads();
 
@@ -373,7 +372,8 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
                                                     int64_t volt_t_stride, int A, int n_time,
                                                     float *__restrict__ acc,
                                                     int32_t *__restrict__ autos, int frame_len,
-                                                    float *__restrict__ frames, int64_t fstride) {
+                                                    float *__restrict__ frames, int64_t fstride,
+                                                    int vb) {
     constexpr int M = 64, T = 512, ROW = 65, GSZ = M * ROW, S = 8;
     extern __shared__ float4 smem[];
     Grid<2> g, h;
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
 #pragma unroll
         for (int q = 0; q < 4; ++q) av[k][q] = 0.f;
 
-    const uint8_t *vbase = volt + (int64_t)it.c * 2 * A;
+    const uint8_t *vbase = volt + (int64_t)it.c * 2 * A * vb;
     const uint4 *ent = entries + it.entry_off + tid;
     const int n_iter = it.n_iter;
     const bool own_autos = autos != nullptr && it.ox == 0;
@@ -426,8 +426,8 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
         for (int k = 0; k < AR; ++k) {
             const int a = tid + k * T;
             if (a < A) {
-                const uint32_t bx = vt[a], by = vt[A + a];
-                const int xr = dec_re(bx), xi = dec_im(bx), yr = dec_re(by), yi = dec_im(by);
+                const int2 vx = volt_at(vt, a, vb), vy = volt_at(vt, A + a, vb);
+                const int xr = vx.x, xi = vx.y, yr = vy.x, yi = vy.y;
                 stage[a] = make_float4((float)xr, (float)xi, (float)yr, (float)yi);
                 if (own_autos) {
                     sa[k][0] += xr * xr + xi * xi;
@@ -438,9 +438,8 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
             }
         }
         for (int a = tid + AR * T; a < A; a += T) {
-            const uint32_t bx = vt[a], by = vt[A + a];
-            stage[a] = make_float4((float)dec_re(bx), (float)dec_im(bx), (float)dec_re(by),
-                                   (float)dec_im(by));
+            const int2 vx = volt_at(vt, a, vb), vy = volt_at(vt, A + a, vb);
+            stage[a] = make_float4((float)vx.x, (float)vx.y, (float)vy.x, (float)vy.y);
         }
         __syncthreads();
 
@@ -565,21 +564,22 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
 // int32 (|E|^2 <= 128 per sample).  Grid: (elements, channels, time chunks).
 template <int P>
 __global__ void k_autos(const uint8_t *__restrict__ volt, int64_t volt_t_stride, int A,
-                        int n_time, int t_chunk, int32_t *__restrict__ autos) {
+                        int n_time, int t_chunk, int vb, int32_t *__restrict__ autos) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (a >= A) return;
     const int t0 = blockIdx.z * t_chunk;
     const int t1 = min(n_time, t0 + t_chunk);
     int sxx = 0, syy = 0, sre = 0, sim = 0;
-    const uint8_t *v = volt + (int64_t)c * P * A + a;
+    const uint8_t *v = volt + (int64_t)c * P * A * vb;
     for (int t = t0; t < t1; ++t) {
-        const uint32_t bx = v[(int64_t)t * volt_t_stride];
-        const int xr = dec_re(bx), xi = dec_im(bx);
+        const uint8_t *vt = v + (int64_t)t * volt_t_stride;
+        const int2 x = volt_at(vt, a, vb);
+        const int xr = x.x, xi = x.y;
         sxx += xr * xr + xi * xi;
         if (P == 2) {
-            const uint32_t by = v[(int64_t)t * volt_t_stride + A];
-            const int yr = dec_re(by), yi = dec_im(by);
+            const int2 y = volt_at(vt, A + a, vb);
+            const int yr = y.x, yi = y.y;
             syy += yr * yr + yi * yi;
             sre += xr * yr + xi * yi;
             sim += xi * yr - xr * yi;
@@ -822,7 +822,7 @@ epic_status lds_ready(const void *kern, size_t lds) {
 
 template <int M, int P, int AR, bool FR>
 static epic_status launch_fused_fr(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                   int A, int n_time, float *acc, int32_t *autos,
+                                   int A, int vb, int n_time, float *acc, int32_t *autos,
                                    const FrameOut &fo, hipStream_t s, bool dry) {
     constexpr int T = FCfg<M>::T, GSZ = M * FCfg<M>::ROW;
     const size_t lds = sizeof(float2) * P * GSZ + sizeof(float4) * (size_t)A;
@@ -831,38 +831,38 @@ static epic_status launch_fused_fr(const FusedGroup *g, const uint8_t *d_volt, i
     if (st || dry) return st;
     hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(T), lds, s, g->items.as<FusedItem>(),
                        g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos, fo.len,
-                       fo.out, fo.stride);
+                       fo.out, fo.stride, vb);
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
 }
 
 template <int M, int P, int AR>
 static epic_status launch_fused_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                   int A, int n_time, float *acc, int32_t *autos,
+                                   int A, int vb, int n_time, float *acc, int32_t *autos,
                                    const FrameOut &fo, hipStream_t s, bool dry) {
-    return fo.len ? launch_fused_fr<M, P, AR, true>(g, d_volt, vstride, A, n_time, acc, autos,
-                                                    fo, s, dry)
-                  : launch_fused_fr<M, P, AR, false>(g, d_volt, vstride, A, n_time, acc, autos,
-                                                     fo, s, dry);
+    return fo.len ? launch_fused_fr<M, P, AR, true>(g, d_volt, vstride, A, vb, n_time, acc,
+                                                    autos, fo, s, dry)
+                  : launch_fused_fr<M, P, AR, false>(g, d_volt, vstride, A, vb, n_time, acc,
+                                                     autos, fo, s, dry);
 }
 
 // Element rounds per thread: 1, 2 or 4; above 4 T the self terms come from a
 // separate pass (autos == nullptr).
 template <int M, int P>
 static epic_status launch_fused(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                int A, int n_time, float *acc, int32_t *autos,
+                                int A, int vb, int n_time, float *acc, int32_t *autos,
                                 const FrameOut &fo, hipStream_t s, bool dry) {
     constexpr int T = FCfg<M>::T;
     if (A <= T)
-        return launch_fused_ar<M, P, 1>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
+        return launch_fused_ar<M, P, 1>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
     if (A <= 2 * T)
-        return launch_fused_ar<M, P, 2>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
-    return launch_fused_ar<M, P, 4>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
+        return launch_fused_ar<M, P, 2>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
+    return launch_fused_ar<M, P, 4>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
 }
 
 template <int AR, bool FR>
 static epic_status launch_pair_fr(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                  int A, int n_time, float *acc, int32_t *autos,
+                                  int A, int vb, int n_time, float *acc, int32_t *autos,
                                   const FrameOut &fo, hipStream_t s, bool dry) {
     const size_t lds = sizeof(float4) * (2 * 64 * 65 + (size_t)A);
     auto kern = k_fused_pair<AR, FR>;
@@ -870,26 +870,29 @@ static epic_status launch_pair_fr(const FusedGroup *g, const uint8_t *d_volt, in
     if (st || dry) return st;
     hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(512), lds, s, g->items.as<FusedItem>(),
                        g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos, fo.len,
-                       fo.out, fo.stride);
+                       fo.out, fo.stride, vb);
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
 }
 
 template <int AR>
 static epic_status launch_pair_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
-                                  int A, int n_time, float *acc, int32_t *autos,
+                                  int A, int vb, int n_time, float *acc, int32_t *autos,
                                   const FrameOut &fo, hipStream_t s, bool dry) {
-    return fo.len ? launch_pair_fr<AR, true>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry)
-                  : launch_pair_fr<AR, false>(g, d_volt, vstride, A, n_time, acc, autos, fo, s,
-                                              dry);
+    return fo.len
+               ? launch_pair_fr<AR, true>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry)
+               : launch_pair_fr<AR, false>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s,
+                                           dry);
 }
 
 static epic_status launch_pair(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride, int A,
-                               int n_time, float *acc, int32_t *autos, const FrameOut &fo,
+                               int vb, int n_time, float *acc, int32_t *autos, const FrameOut &fo,
                                hipStream_t s, bool dry) {
-    if (A <= 512) return launch_pair_ar<1>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
-    if (A <= 1024) return launch_pair_ar<2>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
-    return launch_pair_ar<4>(g, d_volt, vstride, A, n_time, acc, autos, fo, s, dry);
+    if (A <= 512)
+        return launch_pair_ar<1>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
+    if (A <= 1024)
+        return launch_pair_ar<2>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
+    return launch_pair_ar<4>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
 }
 
 // Launches every size group; group i goes to branches[i] when given (graph
@@ -900,7 +903,7 @@ static epic_status launch_pair(const FusedGroup *g, const uint8_t *d_volt, int64
 epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                              hipStream_t s, const std::vector<hipStream_t> *branches, bool dry,
                              const FrameOut &fo) {
-    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    const int64_t vstride = p->vstride();
     const bool frames = fo.len > 0;
     float *a = acc && !frames ? acc->d_acc.as<float>() : nullptr;
     // The fused kernels add the self-term sums when every group's threads
@@ -921,15 +924,15 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
         epic_status st = EPIC_OK;
         const int A = p->A;
         if (g->kind == 1) {
-            st = launch_pair(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
+            st = launch_pair(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
         } else if (p->P == 2) {
-            if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
-            if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
-            if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
+            if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
         } else {
-            if (g->M == 64) st = launch_fused<64, 1>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
-            if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
-            if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, A, n_time, a, au, fo, gs, dry);
+            if (g->M == 64) st = launch_fused<64, 1>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
         }
         if (st) return st;
     }
@@ -943,16 +946,16 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
 
 epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                              hipStream_t s) {
-    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    const int64_t vstride = p->vstride();
     const int t_chunk = 64;
     dim3 grid((p->A + 255) / 256, p->C, (n_time + t_chunk - 1) / t_chunk);
     if (grid.z > 65535) return fail(EPIC_ERR_ARG, "n_time too large for one call");
     if (p->P == 2)
         hipLaunchKernelGGL(k_autos<2>, grid, dim3(256), 0, s, d_volt, vstride, p->A, n_time,
-                           t_chunk, acc->d_autos.as<int32_t>());
+                           t_chunk, p->vb, acc->d_autos.as<int32_t>());
     else
         hipLaunchKernelGGL(k_autos<1>, grid, dim3(256), 0, s, d_volt, vstride, p->A, n_time,
-                           t_chunk, acc->d_autos.as<int32_t>());
+                           t_chunk, p->vb, acc->d_autos.as<int32_t>());
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
 }

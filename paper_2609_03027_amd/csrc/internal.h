@@ -159,6 +159,7 @@ struct BandPlan {
 
 struct epic_plan_s {
     int A = 0, P = 0, C = 0, K = 0;
+    int vb = 1;                   // bytes per voltage sample (1: 4+4 bit, 2: 8+8 bit)
     int aperture_n = 0;
     double cell_lambda = 0.5, sigma = 0.5;
     int precision = 0;
@@ -203,6 +204,7 @@ struct epic_plan_s {
     std::vector<char> banded;     // channel c takes the banded two-pass path
     epic::BandPlan band;
     int64_t work_bytes = 0;       // per-accumulator working memory the path needs
+    int64_t vstride() const { return (int64_t)C * P * A * vb; }  // bytes per time sample
 
     int64_t bytes_plan = 0;
     ~epic_plan_s();
@@ -294,5 +296,21 @@ epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hip
 // Decode one 4+4-bit sample (real in the high nibble).
 __device__ __forceinline__ int dec_re(uint32_t b) { return ((int32_t)(b << 24)) >> 28; }
 __device__ __forceinline__ int dec_im(uint32_t b) { return ((int32_t)(b << 28)) >> 28; }
+
+// Voltage samples are vb bytes each: vb = 1, one 4+4-bit byte; vb = 2, an
+// 8-bit real byte followed by an 8-bit imaginary byte.  idx counts samples.
+// volt_raw loads the bytes (so loads can be issued together), volt_dec
+// turns them into (re, im).
+__device__ __forceinline__ uint32_t volt_raw(const uint8_t *p, int64_t idx, int vb) {
+    if (vb == 2) return *reinterpret_cast<const uint16_t *>(p + 2 * idx);
+    return p[idx];
+}
+__device__ __forceinline__ int2 volt_dec(uint32_t raw, int vb) {
+    if (vb == 2) return make_int2((int)(int8_t)(raw & 0xffu), (int)(int8_t)(raw >> 8));
+    return make_int2(dec_re(raw), dec_im(raw));
+}
+__device__ __forceinline__ int2 volt_at(const uint8_t *p, int64_t idx, int vb) {
+    return volt_dec(volt_raw(p, idx, vb), vb);
+}
 
 }  // namespace epic

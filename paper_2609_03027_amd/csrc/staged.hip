@@ -16,7 +16,7 @@ __global__ void k_grid_csr(const uint8_t *__restrict__ volt, int64_t volt_t_stri
                            const int4 *__restrict__ chan, const int64_t *__restrict__ grid_off,
                            const int64_t *__restrict__ csr_base, const int32_t *__restrict__ csr_off,
                            const int32_t *__restrict__ csr_ant, const float2 *__restrict__ csr_w,
-                           int A, int P, int64_t grid_t_stride, float2 *__restrict__ grid) {
+                           int A, int P, int64_t grid_t_stride, float2 *__restrict__ grid, int vb) {
     const int c = blockIdx.y;
     const int N = chan[c].x;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -24,11 +24,11 @@ __global__ void k_grid_csr(const uint8_t *__restrict__ volt, int64_t volt_t_stri
     const int t = blockIdx.z / P, p = blockIdx.z % P;
     const int32_t *off = csr_off + csr_base[c];
     const int e0 = off[cell], e1 = off[cell + 1];
-    const uint8_t *v = volt + (int64_t)t * volt_t_stride + ((int64_t)c * P + p) * A;
+    const uint8_t *v = volt + (int64_t)t * volt_t_stride + ((int64_t)c * P + p) * A * vb;
     float2 s = make_float2(0.f, 0.f);
     for (int e = e0; e < e1; ++e) {
-        const uint32_t b = v[csr_ant[e]];
-        const float er = (float)dec_re(b), ei = (float)dec_im(b);
+        const int2 x = volt_at(v, csr_ant[e], vb);
+        const float er = (float)x.x, ei = (float)x.y;
         const float2 w = csr_w[e];
         s.x += w.x * er - w.y * ei;
         s.y += w.x * ei + w.y * er;
@@ -206,7 +206,7 @@ static Radices radices_of(int N) {
 
 epic_status staged_grid(epic_plan p, const uint8_t *d_volt, int n_time, void *d_grid,
                         hipStream_t s) {
-    const int64_t vstride = (int64_t)p->C * p->P * p->A;
+    const int64_t vstride = p->vstride();
     const int max_cells = p->max_n * p->max_n;
     const int tp_max = 65535 / p->P;
     for (int t0 = 0; t0 < n_time; t0 += tp_max) {
@@ -217,7 +217,8 @@ epic_status staged_grid(epic_plan p, const uint8_t *d_volt, int n_time, void *d_
                            p->d_csr_base.as<int64_t>(), p->d_csr_off.as<int32_t>(),
                            p->d_csr_ant.as<int32_t>(), p->d_csr_w.as<float2>(), p->A, p->P,
                            p->grid_elems_per_t,
-                           static_cast<float2 *>(d_grid) + (int64_t)t0 * p->grid_elems_per_t);
+                           static_cast<float2 *>(d_grid) + (int64_t)t0 * p->grid_elems_per_t,
+                           p->vb);
         EPIC_HIP(hipGetLastError());
     }
     return EPIC_OK;

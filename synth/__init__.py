@@ -26,7 +26,7 @@ C_LIGHT = 299792458.0  # m/s
 
 __all__ = [
     "Workload", "WORKLOADS", "workload", "antenna_layout", "sky_sources",
-    "voltages", "complex_voltages", "quantise", "pack_int4", "C_LIGHT",
+    "voltages", "complex_voltages", "quantise", "quantise8", "pack_int4", "C_LIGHT",
 ]
 
 
@@ -52,6 +52,8 @@ class Workload:
     kernel_sigma_cells: float = 0.5
     n_src: int = 2
     seed: int = 1000
+    volt_bits: int = 4        # 4: one 4+4-bit byte per sample; 8: int8 (re, im) pairs
+    noise: float = 1.0        # thermal noise power per element and feed
 
     @property
     def n_chan(self) -> int:
@@ -123,6 +125,14 @@ def _make_workloads():
         name="wide", n_ant=20000, n_pol=2, n_time=781, disc_diameter_m=700.0,
         min_spacing_m=1.0, chan_freq_hz=np.array([100e6]),
         grid_n=np.array([512], dtype=np.int32), n_src=3, seed=1006)
+    # AAVS2-like station, the paper's own synthetic test (Sec. 4): 256 dual-pol
+    # elements in a 38 m station at 159 MHz, three persistent sources, no
+    # thermal noise, 8+8-bit voltages, 64x64 images.
+    w["aavs2"] = Workload(
+        name="aavs2", n_ant=256, n_pol=2, n_time=1000, disc_diameter_m=38.0,
+        min_spacing_m=1.0, chan_freq_hz=np.array([159e6]),
+        grid_n=np.array([64], dtype=np.int32), kernel_k=2, n_src=3, seed=1007,
+        volt_bits=8, noise=0.0)
     return w
 
 
@@ -242,6 +252,16 @@ def quantise(v: np.ndarray, n_src: int, noise: float = 1.0) -> np.ndarray:
     return np.stack([re, im], axis=-1)
 
 
+def quantise8(v: np.ndarray, n_src: int, noise: float = 1.0) -> np.ndarray:
+    """8+8-bit digitisation: about 32 levels per component sigma, rounded
+    (ties to even) and clipped to [-127, 127].  Returns ``int8 [..., 2]``."""
+    sigma = np.sqrt((n_src + noise) / 2.0)
+    s = 32.0 / sigma
+    re = np.clip(np.rint(s * v.real), -127, 127).astype(np.int8)
+    im = np.clip(np.rint(s * v.imag), -127, 127).astype(np.int8)
+    return np.stack([re, im], axis=-1)
+
+
 def pack_int4(q: np.ndarray) -> np.ndarray:
     """Pack ``int8 [..., 2]`` (re, im) into one byte: re high nibble, im low."""
     re = q[..., 0].astype(np.int16) & 0xF
@@ -251,11 +271,15 @@ def pack_int4(q: np.ndarray) -> np.ndarray:
 
 def voltages(wl: Workload, pos: np.ndarray | None = None,
              lm: np.ndarray | None = None, block: int = 0, chans=None,
-             noise: float = 1.0, transient=None) -> np.ndarray:
-    """Packed 4+4-bit voltages ``uint8 [T][C][P][A]`` for one block
-    (``transient``: see ``complex_voltages``)."""
+             noise: float | None = None, transient=None) -> np.ndarray:
+    """Digitised voltages for one block: packed 4+4-bit ``uint8 [T][C][P][A]``,
+    or ``int8 [T][C][P][A][2]`` for 8+8-bit workloads (``transient``: see
+    ``complex_voltages``; ``noise`` defaults to the workload's)."""
     pos = antenna_layout(wl) if pos is None else pos
     lm = sky_sources(wl) if lm is None else lm
+    noise = wl.noise if noise is None else noise
     v = complex_voltages(wl, pos, lm, block=block, chans=chans, noise=noise,
                          transient=transient)
+    if wl.volt_bits == 8:
+        return quantise8(v, wl.n_src, noise)
     return pack_int4(quantise(v, wl.n_src, noise))

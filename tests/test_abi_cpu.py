@@ -112,6 +112,17 @@ def test_plan_create_rejects_banded_requests_it_cannot_serve(n, precision):
     assert not h.value
 
 
+def test_plan_flags_validated_before_device_work():
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    h = C.c_void_p()
+    d, keep = _desc(flags=2)
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 2
+    d, keep = _desc(flags=E.VOLT_8BIT, precision=E.EPIC_F8E4M3_MFMA)
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 4
+    assert b"FP8" in lib.epic_last_error()
+
+
 def test_autotune_candidates_include_the_banded_path_where_it_applies():
     from paper_2609_03027_amd import autotune
     ok = [n for n in range(8, 1025, 2) if autotune.banded_ok(n)]

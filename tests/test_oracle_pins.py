@@ -303,3 +303,21 @@ def test_auto_term_by_element_equals_materialised_beams():
     a = O.auto_term(S, O.antenna_beams(j0, w, n))
     b = O.auto_term_by_element(S, j0, w, n)
     np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-9)
+
+
+def test_decode_int8_exhaustive_and_same_image_as_4bit():
+    # every (re, im) byte pair against struct's signed-byte reading
+    import struct
+    pairs = np.array([(r, i) for r in range(256) for i in range(0, 256, 17)], dtype=np.uint8)
+    got = O.decode_int8(pairs.view(np.int8))
+    want = np.array([struct.unpack("b", bytes([r]))[0] + 1j * struct.unpack("b", bytes([i]))[0]
+                     for r, i in pairs])
+    np.testing.assert_array_equal(got, want)
+    # the same integers given in either format give the same channel image
+    rng = _rng(21)
+    q = rng.integers(-7, 8, size=(6, 2, 9, 2)).astype(np.int8)       # [T][P][A][2]
+    pos = rng.uniform(-4, 4, size=(9, 2))
+    r4 = O.channel_reference(synth.pack_int4(q), pos, 60e6, 32)
+    r8 = O.channel_reference(q, pos, 60e6, 32)
+    np.testing.assert_array_equal(r4["acc"], r8["acc"])
+    np.testing.assert_array_equal(r4["autos"], r8["autos"])
