@@ -80,6 +80,8 @@ typedef enum {
 /* readout flags */
 #define EPIC_REMOVE_AUTOS 1u   /* subtract the per-element self terms */
 #define EPIC_NORMALISE 2u      /* divide by the number of accumulated samples */
+#define EPIC_STOKES 4u         /* two feeds: planes I = XX + YY, Q = XX - YY, U = 2 Re XY,
+                                  V = -2 Im XY (linear feeds, XY = Ex conj(Ey)) */
 
 typedef struct {
     int32_t n_ant;               /* A >= 1 */
@@ -184,7 +186,9 @@ epic_status epic_accumulate_frames(epic_plan plan, epic_acc acc, const uint8_t *
                                    int32_t n_time, int32_t frame_len, float *d_frames,
                                    void *hip_stream);
 
-/* Read-out of Eq. 2: d_img = (acc - [REMOVE_AUTOS] self terms) / [NORMALISE] count.
+/* Read-out of Eq. 2: d_img = (acc - [REMOVE_AUTOS] self terms) / [NORMALISE] count,
+ * as XX, YY, Re XY, Im XY or, with EPIC_STOKES (two feeds only, EPIC_ERR_ARG
+ * otherwise), as the pseudo-Stokes planes I, Q, U, V.
  * The self term of element a is S_a^{pq} |B_a(k)|^2 with B_a the image of its
  * kernel footprint, evaluated exactly as sum_d H[d] exp(+2 pi i (k - N/2).d / N)
  * over footprint displacements d. */

@@ -46,6 +46,7 @@ __all__ = [
     "accumulate", "antenna_autos", "antenna_beams", "auto_term", "auto_term_by_element",
     "readout",
     "fx_image", "channel_reference", "epic_reference", "decode_int8", "decode_voltages",
+    "pseudo_stokes",
 ]
 
 
@@ -271,6 +272,15 @@ def readout(acc, auto=None, count=1, normalise=True) -> np.ndarray:
 # --------------------------------------------------------------------------
 # FX route (pairwise visibilities) -- the brute-force equivalence check
 # --------------------------------------------------------------------------
+def pseudo_stokes(img) -> np.ndarray:
+    """Pseudo-Stokes planes of a two-feed image set [XX, YY, Re XY, Im XY]
+    (linear feeds, XY = Ex conj(Ey)): I = XX + YY, Q = XX - YY,
+    U = XY + YX = 2 Re XY, V = i (XY - YX) = -2 Im XY."""
+    img = np.asarray(img, dtype=np.float64)
+    xx, yy, xr, xi = img
+    return np.stack([xx + yy, xx - yy, 2 * xr, -2 * xi])
+
+
 def fx_image(E, j0, w, n, include_auto=True) -> np.ndarray:
     """Image from explicit visibilities gridded with the correlated kernel.
 

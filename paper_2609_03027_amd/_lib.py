@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libepic.so")
 EPIC_F32, EPIC_F16_MFMA, EPIC_F8E4M3_MFMA, EPIC_BF16X2_MFMA = 0, 1, 2, 3
 REMOVE_AUTOS = 1
 NORMALISE = 2
+STOKES = 4             # read-out flag: I, Q, U, V planes instead of XX, YY, Re XY, Im XY
 SUB_BANDED = -1        # sub_n value: banded two-pass path for that channel
 VOLT_8BIT = 1          # plan flag: 8+8-bit voltages, int8 [t][c][p][a][2]
 

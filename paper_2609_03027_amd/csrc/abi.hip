@@ -387,7 +387,8 @@ epic_status epic_readout(epic_plan p, epic_acc a, float *d_img, uint32_t flags, 
     EPIC_GUARD_BEGIN
     if (!p || !a || !d_img) return fail(EPIC_ERR_NULL, "plan, acc and img are required");
     if (a->plan != p) return fail(EPIC_ERR_MISMATCH, "accumulator belongs to another plan");
-    if (flags & ~(EPIC_REMOVE_AUTOS | EPIC_NORMALISE)) return fail(EPIC_ERR_ARG, "unknown flags");
+    if (flags & ~(EPIC_REMOVE_AUTOS | EPIC_NORMALISE | EPIC_STOKES))
+        return fail(EPIC_ERR_ARG, "unknown flags");
     return readout(p, a, d_img, flags, static_cast<hipStream_t>(hip_stream));
     EPIC_GUARD_END
 }

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_auto_h(const double2 *__restrict__ R,
 template <int P>
 __global__ void k_readout(const float *__restrict__ acc, const double2 *__restrict__ H,
                           const int4 *__restrict__ chan, const int64_t *__restrict__ img_off, int K,
-                          int remove, float scale, float *__restrict__ img) {
+                          int remove, int stokes, float scale, float *__restrict__ img) {
     const int c = blockIdx.y;
     const int N = chan[c].x;
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
@@ -98,9 +98,30 @@ __global__ void k_readout(const float *__restrict__ acc, const double2 *__restri
     constexpr int NPROD = P == 2 ? 4 : 1;
     const float *a = acc + img_off[c] + pix;
     float *o = img + img_off[c] + pix;
+    // products (XX, YY, Re XY, Im XY) -> output planes: as they are, or the
+    // pseudo-Stokes set I = XX + YY, Q = XX - YY, U = 2 Re XY, V = -2 Im XY
+    auto put = [&](double xx, double yy, double xr, double xi) {
+        if (P == 2 && stokes) {
+            o[0] = (float)((xx + yy) * scale);
+            o[plane] = (float)((xx - yy) * scale);
+            o[2 * plane] = (float)(2.0 * xr * scale);
+            o[3 * plane] = (float)(-2.0 * xi * scale);
+        } else {
+            o[0] = (float)(xx * scale);
+            if (P == 2) {
+                o[plane] = (float)(yy * scale);
+                o[2 * plane] = (float)(xr * scale);
+                o[3 * plane] = (float)(xi * scale);
+            }
+        }
+    };
     if (!remove) {
+        if (P == 2 && stokes) {
+            put(a[0], a[plane], a[2 * plane], a[3 * plane]);
+        } else {
 #pragma unroll
-        for (int q = 0; q < NPROD; ++q) o[q * plane] = a[q * plane] * scale;
+            for (int q = 0; q < NPROD; ++q) o[q * plane] = a[q * plane] * scale;
+        }
         return;
     }
     const int D = 2 * K - 1;
@@ -140,12 +161,11 @@ __global__ void k_readout(const float *__restrict__ acc, const double2 *__restri
                 sxi += hc.x * ei + hc.y * er;
             }
         }
-    o[0] = (float)(((double)a[0] - sxx) * scale);
-    if (P == 2) {
-        o[plane] = (float)(((double)a[plane] - syy) * scale);
-        o[2 * plane] = (float)(((double)a[2 * plane] - sxr) * scale);
-        o[3 * plane] = (float)(((double)a[3 * plane] - sxi) * scale);
-    }
+    if (P == 2)
+        put((double)a[0] - sxx, (double)a[plane] - syy, (double)a[2 * plane] - sxr,
+            (double)a[3 * plane] - sxi);
+    else
+        put((double)a[0] - sxx, 0.0, 0.0, 0.0);
 }
 
 epic_status selfcorr_build(epic_plan p, hipStream_t s) {
@@ -162,6 +182,8 @@ epic_status selfcorr_build(epic_plan p, hipStream_t s) {
 epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hipStream_t s) {
     const bool remove = (flags & EPIC_REMOVE_AUTOS) != 0;
     const bool norm = (flags & EPIC_NORMALISE) != 0;
+    const int stokes = (flags & EPIC_STOKES) ? 1 : 0;
+    if (stokes && p->P != 2) return fail(EPIC_ERR_ARG, "pseudo-Stokes needs two feeds");
     if (norm && acc->count <= 0) return fail(EPIC_ERR_ARG, "normalise requested with no samples");
     const float scale = norm ? (float)(1.0 / (double)acc->count) : 1.0f;
     const int D = 2 * p->K - 1;
@@ -180,11 +202,11 @@ epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hip
     if (p->P == 2)
         hipLaunchKernelGGL(k_readout<2>, g, dim3(256), 0, s, acc->d_acc.as<float>(),
                            H.as<double2>(), p->d_chan.as<int4>(), p->d_img_off.as<int64_t>(), p->K,
-                           remove ? 1 : 0, scale, d_img);
+                           remove ? 1 : 0, stokes, scale, d_img);
     else
         hipLaunchKernelGGL(k_readout<1>, g, dim3(256), 0, s, acc->d_acc.as<float>(),
                            H.as<double2>(), p->d_chan.as<int4>(), p->d_img_off.as<int64_t>(), p->K,
-                           remove ? 1 : 0, scale, d_img);
+                           remove ? 1 : 0, stokes, scale, d_img);
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
 }

@@ -321,3 +321,29 @@ def test_decode_int8_exhaustive_and_same_image_as_4bit():
     r8 = O.channel_reference(q, pos, 60e6, 32)
     np.testing.assert_array_equal(r4["acc"], r8["acc"])
     np.testing.assert_array_equal(r4["autos"], r8["autos"])
+
+
+def test_pseudo_stokes_of_one_fully_polarised_source_is_rank_one():
+    # one noiseless source with Y = X exp(i pi/4): the coherency at every
+    # pixel is rank one, so I^2 = Q^2 + U^2 + V^2, and V follows the sign of
+    # Im(Ex conj(Ey)) = -sin(pi/4) |X|^2
+    rng = _rng(31)
+    A, T = 9, 5
+    pos = rng.uniform(-3, 3, size=(A, 2))
+    lam = 299792458.0 / 60e6
+    geo = np.exp(-2j * np.pi * (pos @ np.array([0.2, -0.1])) / lam)
+    ph = rng.uniform(0, 2 * np.pi, size=T)
+    ex = np.exp(1j * ph)[:, None] * geo[None]
+    q = np.stack([np.rint(4 * ex), np.rint(4 * ex * np.exp(1j * np.pi / 4))], axis=1)
+    v = np.stack([q.real, q.imag], axis=-1).astype(np.int8)             # [T][2][A][2]
+    E = O.decode_int8(v)
+    # make the two feeds exactly proportional: Y := X * (1 + 1j)
+    v[:, 1, :, 0] = (E[:, 0].real - E[:, 0].imag).astype(np.int8)
+    v[:, 1, :, 1] = (E[:, 0].real + E[:, 0].imag).astype(np.int8)
+    r = O.channel_reference(v, pos, 60e6, 16, want_auto=False)
+    I, Q, U, V = O.pseudo_stokes(r["acc"])
+    np.testing.assert_allclose(I ** 2, Q ** 2 + U ** 2 + V ** 2, rtol=1e-9, atol=1e-6 * I.max() ** 2)
+    # Y = (1 + i) X: XX = |X|^2, YY = 2|X|^2, XY = (1 - i)|X|^2 -> U = 2 XX, V = 2 XX, Q = -XX
+    np.testing.assert_allclose(U, 2 * r["acc"][0], atol=1e-9 * I.max())
+    np.testing.assert_allclose(V, 2 * r["acc"][0], atol=1e-9 * I.max())
+    np.testing.assert_allclose(Q, -r["acc"][0], atol=1e-9 * I.max())
