@@ -10,8 +10,10 @@ What it computes (paper: Sec. 2, Eq. 1 and Eq. 2):
 
 * Eq. 1, inner sum: each calibrated voltage E_e^p is spread onto a regular
   aperture grid r_j with the conjugate of its element's gridding kernel,
-  G^p[j] = sum_e W_e*(r_j - r_e) E_e^p.  The kernel here is diagonal in
-  polarisation (the same kernel for both feeds).
+  G^p[j] = sum_e W_e*(r_j - r_e) E_e^p.  The default kernel is diagonal in
+  polarisation (the same kernel for both feeds); the ``*_jones`` functions
+  take the full form of Eq. 1, G^alpha[j] = sum_e sum_p W_e^{alpha p}*(r_j -
+  r_e) E_e^p, with four complex kernels per element.
 * Eq. 1, outer sum: a 2D Fourier sum with the positive exponent,
   E^p[k] = sum_j dA_j exp(+2 pi i s_k . r_j / lambda) G^p[j], written on
   centred integer indices as exp(+2 pi i (k - N/2).(j - N/2) / N), with the
@@ -46,7 +48,8 @@ __all__ = [
     "accumulate", "antenna_autos", "antenna_beams", "auto_term", "auto_term_by_element",
     "readout",
     "fx_image", "channel_reference", "epic_reference", "decode_int8", "decode_voltages",
-    "pseudo_stokes",
+    "pseudo_stokes", "grid_jones", "antenna_beams_jones", "auto_term_jones",
+    "fx_image_jones",
 ]
 
 
@@ -147,6 +150,28 @@ def grid(E, j0, w, n) -> np.ndarray:
         for dy in range(k):
             for dx in range(k):
                 G[..., j0[a, 1] + dy, j0[a, 0] + dx] += wc[a, dy, dx] * E[..., a]
+    return G
+
+
+def grid_jones(E, j0, wj, n) -> np.ndarray:
+    """Eq. 1 inner sum with polarisation mixing:
+    G^alpha[j] = sum_a sum_p conj(W_a^{alpha p}(j)) E_a^p.
+
+    ``E`` is complex [..., 2, A] (feed p, element); ``wj`` is complex
+    [A][2][2][K][K] indexed (element, alpha, p, dy, dx).  Returns complex128
+    [..., 2, N, N] (output polarisation alpha).
+    """
+    E = np.asarray(E, dtype=np.complex128)
+    A = E.shape[-1]
+    k = wj.shape[-1]
+    G = np.zeros(E.shape[:-2] + (2, n, n), dtype=np.complex128)
+    wc = np.conj(wj)
+    for a in range(A):
+        for al in range(2):
+            for p in range(2):
+                for dy in range(k):
+                    for dx in range(k):
+                        G[..., al, j0[a, 1] + dy, j0[a, 0] + dx] += wc[a, al, p, dy, dx] * E[..., p, a]
     return G
 
 
@@ -259,6 +284,49 @@ def auto_term_by_element(S, j0, w, n) -> np.ndarray:
     return out
 
 
+def antenna_beams_jones(j0, wj, n) -> np.ndarray:
+    """B_a^{alpha p}[k]: the Eq. 1 image of element a's footprint for feed p
+    into output polarisation alpha.  Returns complex128 [A][2][2][N][N]."""
+    F = centred_dft_matrix(n)
+    A, k = wj.shape[0], wj.shape[-1]
+    B = np.zeros((A, 2, 2, n, n), dtype=np.complex128)
+    wc = np.conj(wj)
+    for a in range(A):
+        Fy = F[:, j0[a, 1]:j0[a, 1] + k]
+        Fx = F[:, j0[a, 0]:j0[a, 0] + k]
+        for al in range(2):
+            for p in range(2):
+                B[a, al, p] = Fy @ wc[a, al, p] @ Fx.T
+    return B
+
+
+def auto_term_jones(S, Bj) -> np.ndarray:
+    """Self terms with polarisation mixing.  Element a alone contributes
+    E^alpha = sum_p B_a^{alpha p} E_a^p to every pixel, so its share of
+    sum_t E^alpha conj(E^beta) is sum_{p,q} S_a^{pq} B_a^{alpha p}
+    conj(B_a^{beta q}), with S_a^{yx} = conj(S_a^{xy}).  ``S`` is [A][4]
+    (XX, YY, Re XY, Im XY) as from ``antenna_autos``; returns float64
+    [4][N][N] in the same product order."""
+    S = np.asarray(S, dtype=np.float64)
+    sxy = S[:, 2] + 1j * S[:, 3]
+    Sm = np.empty((S.shape[0], 2, 2), dtype=np.complex128)
+    Sm[:, 0, 0] = S[:, 0]
+    Sm[:, 1, 1] = S[:, 1]
+    Sm[:, 0, 1] = sxy
+    Sm[:, 1, 0] = np.conj(sxy)
+
+    def one(al, be):
+        out = np.zeros(Bj.shape[-2:], dtype=np.complex128)
+        for p in range(2):
+            for q in range(2):
+                out += np.einsum("a,ayx->yx", Sm[:, p, q],
+                                 Bj[:, al, p] * np.conj(Bj[:, be, q]))
+        return out
+
+    xx, yy, xy = one(0, 0), one(1, 1), one(0, 1)
+    return np.stack([xx.real, yy.real, xy.real, xy.imag])
+
+
 def readout(acc, auto=None, count=1, normalise=True) -> np.ndarray:
     """(acc - auto) / count: Eq. 2's average with the self terms removed."""
     out = np.array(acc, dtype=np.float64, copy=True)
@@ -325,17 +393,58 @@ def fx_image(E, j0, w, n, include_auto=True) -> np.ndarray:
     return np.stack([xx.real, yy.real, xy.real, xy.imag])
 
 
+def fx_image_jones(E, j0, wj, n, include_auto=True) -> np.ndarray:
+    """FX route with polarisation mixing: every pairwise visibility
+    V_ab^{pq} = sum_t E_a^p conj(E_b^q) is placed at displacement
+    d = ja - jb with weight conj(W_a^{alpha p}(ja)) W_b^{beta q}(jb), summed
+    over p and q for output product alpha beta, then Fourier transformed as
+    in ``fx_image``.  Returns float64 [4][N][N] (XX, YY, Re XY, Im XY)."""
+    E = np.asarray(E, dtype=np.complex128)
+    T, P, A = E.shape
+    k = wj.shape[-1]
+    wc = np.conj(wj)
+    m = 2 * n - 1
+    kk = np.arange(n) - n // 2
+    dd = np.arange(m) - (n - 1)
+    Q = np.exp(2j * np.pi * np.mod(np.outer(kk, dd), n) / n)
+    V = np.einsum("tpa,tqb->pqab", E, np.conj(E))     # V[p][q][a][b]
+
+    def one(al, be):
+        D = np.zeros((m, m), dtype=np.complex128)
+        for a in range(A):
+            for b in range(A):
+                if a == b and not include_auto:
+                    continue
+                for p in range(2):
+                    for q in range(2):
+                        v = V[p, q, a, b]
+                        for ay in range(k):
+                            for ax in range(k):
+                                ca = wc[a, al, p, ay, ax] * v
+                                for by in range(k):
+                                    for bx in range(k):
+                                        dy = (j0[a, 1] + ay) - (j0[b, 1] + by) + n - 1
+                                        dx = (j0[a, 0] + ax) - (j0[b, 0] + bx) + n - 1
+                                        D[dy, dx] += ca * wj[b, be, q, by, bx]
+        return Q @ D @ Q.T
+
+    xx, yy, xy = one(0, 0), one(1, 1), one(0, 1)
+    return np.stack([xx.real, yy.real, xy.real, xy.imag])
+
+
 # --------------------------------------------------------------------------
 # Whole path for one channel / a whole block
 # --------------------------------------------------------------------------
 def channel_reference(volt_c, pos, freq_hz, n, *, cell_lambda=0.5, k=3,
                       sigma=0.5, kernel=None, aperture_n=0,
-                      want_images=False, want_auto=True):
+                      want_images=False, want_auto=True, jones=None):
     """Reference for one channel of voltages ``uint8 [T][P][A]`` (4+4 bit) or
     ``int8 [T][P][A][2]`` (8+8 bit).
 
     ``kernel`` optionally replaces the Gaussian with explicit complex weights
-    [A][K][K] (the weight W_a on each support cell).  Returns a dict with
+    [A][K][K] (the weight W_a on each support cell).  ``jones`` (two feeds
+    only) instead gives the four kernels W_a^{alpha p} per element, complex
+    [A][2][2][K][K], and the grids mix the feeds as in Eq. 1.  Returns a dict with
     ``acc`` (float64 [n_prod][N][N]), ``autos`` ([A][n_prod]), ``auto``
     (the self term, same shape as acc), ``j0``, ``w`` and, on request, the
     per-sample grids and sky images.  ``want_auto=False`` leaves ``auto``
@@ -345,16 +454,27 @@ def channel_reference(volt_c, pos, freq_hz, n, *, cell_lambda=0.5, k=3,
     x, j0 = grid_geometry(pos, freq_hz, n, cell_lambda, k)
     if not support_inside(j0, k, n, aperture_n):
         raise ValueError("an element's kernel support leaves the gridded region")
-    if kernel is None:
-        w = gaussian_kernel(x, j0, k, sigma)
+    if jones is not None:
+        if E.shape[1] != 2:
+            raise ValueError("Jones kernels need two feeds")
+        w = np.asarray(jones, dtype=np.complex128)
+        G = grid_jones(E, j0, w, n)                  # [T][2][N][N]
     else:
-        w = np.asarray(kernel, dtype=np.complex128)
-    G = grid(E, j0, w, n)                            # [T][P][N][N]
+        w = gaussian_kernel(x, j0, k, sigma) if kernel is None else \
+            np.asarray(kernel, dtype=np.complex128)
+        G = grid(E, j0, w, n)                        # [T][P][N][N]
     Es = sky(G)
     acc = accumulate(Es)
     S = antenna_autos(E)
     if not want_auto:
         auto = None
+    elif jones is not None:
+        # linear in the elements: sum over blocks of elements keeps memory low
+        auto = np.zeros_like(acc)
+        step = max(1, (1 << 22) // (4 * n * n))
+        for a0 in range(0, len(j0), step):
+            sl = slice(a0, a0 + step)
+            auto += auto_term_jones(S[sl], antenna_beams_jones(j0[sl], w[sl], n))
     elif len(j0) * n * n <= (1 << 24):
         auto = auto_term(S, antenna_beams(j0, w, n))
     else:
@@ -368,8 +488,9 @@ def channel_reference(volt_c, pos, freq_hz, n, *, cell_lambda=0.5, k=3,
 
 def epic_reference(volt, pos, freq_hz, grid_n, *, cell_lambda=0.5, k=3,
                    sigma=0.5, kernels=None, aperture_n=0, chans=None,
-                   remove_autos=True, normalise=True):
-    """Read-out images for a block ``uint8 [T][C][P][A]``.
+                   remove_autos=True, normalise=True, jones=None):
+    """Read-out images for a block ``uint8 [T][C][P][A]``; ``kernels`` and
+    ``jones`` are per-channel lists as in ``channel_reference``.
 
     Returns a list over the requested channels of float64 [n_prod][N_c][N_c]
     images, (acc - auto) / T with the optional steps as flagged.
@@ -382,7 +503,7 @@ def epic_reference(volt, pos, freq_hz, grid_n, *, cell_lambda=0.5, k=3,
         r = channel_reference(
             volt[:, c], pos, freq_hz[c], int(grid_n[c]), cell_lambda=cell_lambda,
             k=k, sigma=sigma, kernel=None if kernels is None else kernels[c],
-            aperture_n=aperture_n)
+            aperture_n=aperture_n, jones=None if jones is None else jones[c])
         out.append(readout(r["acc"], r["auto"] if remove_autos else None,
                            r["count"], normalise))
     return out

@@ -20,14 +20,15 @@ def image_errors(got, ref):
             np.sqrt(np.mean(d ** 2, axis=(1, 2))) / rms)
 
 
-def oracle_images(volt, pos, wl, chans, remove_autos=True, normalise=True, kernels=None):
+def oracle_images(volt, pos, wl, chans, remove_autos=True, normalise=True, kernels=None,
+                  jones=None):
     out = []
     for i, c in enumerate(chans):
         r = O.channel_reference(
             volt[:, i], pos, wl.chan_freq_hz[c], int(wl.grid_n[c]),
             cell_lambda=wl.cell_lambda, k=wl.kernel_k, sigma=wl.kernel_sigma_cells,
             aperture_n=wl.aperture_n, kernel=None if kernels is None else kernels[i],
-            want_auto=remove_autos)
+            want_auto=remove_autos, jones=None if jones is None else jones[i])
         out.append(O.readout(r["acc"], r["auto"] if remove_autos else None, r["count"],
                              normalise))
     return out
