@@ -73,6 +73,15 @@ typedef enum {
 /* plan flags */
 #define EPIC_PLAN_DEFAULT 0u
 #define EPIC_VOLT_8BIT 1u      /* 8+8-bit voltages (2 bytes per sample); not with FP8 */
+#define EPIC_JONES 2u          /* full polarimetric gridding (Sec. 2, Eq. 1 with W_e^{alpha p}):
+                                  each output polarisation alpha grids both feeds p with its
+                                  own complex kernel.  Needs n_pol = 2, EPIC_F32 and a
+                                  kernel_table of four kernels per element (layout below).
+                                  Channels run on the fused path (EPIC_SUB_BANDED and
+                                  automatic banded selection are not taken: a sub_n of
+                                  EPIC_SUB_BANDED fails with EPIC_ERR_UNSUPPORTED).  The
+                                  self terms removed at read-out are
+                                  sum_a sum_pq S_a^{pq} B_a^{alpha p} conj(B_a^{beta q}). */
 
 /* sub_n value that selects the banded two-pass path for a channel */
 #define EPIC_SUB_BANDED (-1)
@@ -96,9 +105,12 @@ typedef struct {
     int32_t kernel_k;            /* support side K, 1..3 */
     double kernel_sigma_cells;   /* Gaussian width in cells (0 -> 0.5) */
     const float *kernel_table;   /* optional host [C][A][K][K][2]: complex W_a on its
-                                    support cells [dy][dx] (replaces the Gaussian); copied */
+                                    support cells [dy][dx] (replaces the Gaussian); with
+                                    EPIC_JONES required, host [C][A][2][2][K][K][2]: W_a^{alpha p}
+                                    indexed [alpha][p][dy][dx] (alpha = output polarisation,
+                                    p = feed; 0 = x, 1 = y); copied */
     int32_t precision;           /* epic_precision */
-    uint32_t flags;              /* EPIC_PLAN_DEFAULT or EPIC_VOLT_8BIT */
+    uint32_t flags;              /* EPIC_PLAN_DEFAULT or an OR of EPIC_VOLT_8BIT, EPIC_JONES */
     const int32_t *sub_n;        /* optional host [C], FP32 only: side M of the
                                     sub-transforms the fused path splits channel c into
                                     (16, 32 or 64, dividing grid_n[c], at most 8 per

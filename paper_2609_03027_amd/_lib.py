@@ -21,6 +21,7 @@ NORMALISE = 2
 STOKES = 4             # read-out flag: I, Q, U, V planes instead of XX, YY, Re XY, Im XY
 SUB_BANDED = -1        # sub_n value: banded two-pass path for that channel
 VOLT_8BIT = 1          # plan flag: 8+8-bit voltages, int8 [t][c][p][a][2]
+JONES = 2              # plan flag: four kernels W^{alpha p} per element (two feeds)
 
 STATUS = {0: "EPIC_OK", 1: "EPIC_ERR_NULL", 2: "EPIC_ERR_ARG", 3: "EPIC_ERR_GRID",
           4: "EPIC_ERR_UNSUPPORTED", 5: "EPIC_ERR_OOM", 6: "EPIC_ERR_DEVICE",
@@ -139,13 +140,19 @@ class Plan:
 
     def __init__(self, pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5,
                  kernel_k=3, kernel_sigma=0.5, kernel_table=None, precision=EPIC_F32,
-                 sub_n=None, volt_bits=4, stream=None):
+                 sub_n=None, volt_bits=4, jones=False, stream=None):
         lib = load()
         self._pos = np.ascontiguousarray(pos, dtype=np.float64)
         self._freq = np.ascontiguousarray(freq_hz, dtype=np.float64)
         self._gn = np.ascontiguousarray(grid_n, dtype=np.int32)
         self._table = None if kernel_table is None else np.ascontiguousarray(
             kernel_table, dtype=np.float32)
+        # kernel_table: [C][A][K][K][2], or with jones [C][A][2][2][K][K][2]
+        if self._table is not None:
+            want = ((self._freq.shape[0], self._pos.shape[0]) + ((2, 2) if jones else ())
+                    + (int(kernel_k), int(kernel_k), 2))
+            if self._table.shape != want:
+                raise ValueError(f"kernel_table shape {self._table.shape}, expected {want}")
         d = PlanDesc()
         d.n_ant = self._pos.shape[0]
         d.n_pol = int(n_pol)
@@ -162,7 +169,7 @@ class Plan:
         d.precision = int(precision)
         if volt_bits not in (4, 8):
             raise ValueError("volt_bits must be 4 or 8")
-        d.flags = VOLT_8BIT if volt_bits == 8 else 0
+        d.flags = (VOLT_8BIT if volt_bits == 8 else 0) | (JONES if jones else 0)
         self._sub = None if sub_n is None else np.ascontiguousarray(sub_n, dtype=np.int32)
         d.sub_n = None if self._sub is None else self._sub.ctypes.data_as(C.POINTER(C.c_int32))
         h = C.c_void_p()
@@ -179,6 +186,7 @@ class Plan:
         self.grid_off = np.concatenate([[0], np.cumsum(self.n_pol * n2)[:-1]])
         self.precision = precision
         self.volt_bits = volt_bits
+        self.jones = bool(jones)
 
     @classmethod
     def from_workload(cls, wl, pos, **kw):

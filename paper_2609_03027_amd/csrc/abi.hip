@@ -76,7 +76,17 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     if (!(sg > 0.0) || !std::isfinite(sg)) return fail(EPIC_ERR_ARG, "kernel_sigma_cells must be > 0");
     if (d->precision < EPIC_F32 || d->precision > EPIC_BF16X2_MFMA)
         return fail(EPIC_ERR_ARG, "unknown precision");
-    if (d->flags & ~EPIC_VOLT_8BIT) return fail(EPIC_ERR_ARG, "unknown plan flags");
+    if (d->flags & ~(EPIC_VOLT_8BIT | EPIC_JONES)) return fail(EPIC_ERR_ARG, "unknown plan flags");
+    if (d->flags & EPIC_JONES) {
+        if (d->n_pol != 2) return fail(EPIC_ERR_ARG, "Jones kernels need two feeds");
+        if (!d->kernel_table) return fail(EPIC_ERR_NULL, "Jones kernels need a kernel table");
+        if (d->precision != EPIC_F32)
+            return fail(EPIC_ERR_UNSUPPORTED, "Jones kernels run on the FP32 path only");
+        if (d->sub_n)
+            for (int c = 0; c < d->n_chan; ++c)
+                if (d->sub_n[c] == EPIC_SUB_BANDED)
+                    return fail(EPIC_ERR_UNSUPPORTED, "the banded path does not take Jones kernels");
+    }
     if ((d->flags & EPIC_VOLT_8BIT) && d->precision == EPIC_F8E4M3_MFMA)
         return fail(EPIC_ERR_UNSUPPORTED, "8+8-bit voltages are not exact in FP8 operands");
     if (d->aperture_n < 0 || (d->aperture_n & 1))
@@ -110,6 +120,7 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     p->precision = d->precision;
     p->flags = d->flags;
     p->vb = (d->flags & EPIC_VOLT_8BIT) ? 2 : 1;
+    p->J = (d->flags & EPIC_JONES) ? 4 : 1;
     p->n_prod = p->P == 2 ? 4 : 1;
     p->pos.assign(d->ant_pos_m, d->ant_pos_m + 2 * p->A);
     p->freq.assign(d->chan_freq_hz, d->chan_freq_hz + p->C);
@@ -119,7 +130,7 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     epic_status st = EPIC_OK;
     if (d->kernel_table) {
         p->has_table = true;
-        const size_t n = (size_t)p->C * p->A * K * K * 2;
+        const size_t n = (size_t)p->C * p->A * p->J * K * K * 2;
         st = p->d_table.alloc(sizeof(float) * n);
         if (!st) {
             hipError_t e = hipMemcpyAsync(p->d_table.p, d->kernel_table, sizeof(float) * n,

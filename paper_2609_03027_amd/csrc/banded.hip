@@ -704,7 +704,7 @@ static epic_status band_items(epic_plan p, const std::vector<int> &j0,
                 const int band = (row - b.row_lo) / BL, r0 = b.row_lo + band * BL;
                 const size_t wi = (((size_t)c * A + a) * K * K + dy * K + dx) * 2;
                 const double sg = ((row + col) & 1) ? -1.0 : 1.0;
-                GatherTap tp;
+                GatherTap tp{};
                 tp.cell = (row - r0) * N + col;
                 tp.ant = a;
                 tp.wr = (float)(sg * w[wi]);

@@ -181,6 +181,22 @@ __device__ __forceinline__ void slot_position(int tid, int s, int &row, int &col
     row = (u / M) * RB + s % RB;
 }
 
+// The rest of a Jones tap (the x <- x term is added by the caller): with the
+// staged feeds v = (Ex re, Ex im, Ey re, Ey im) and folded conjugate weights
+// from rows e1 = (xy, yx) and e2 = (yy, -), sx += w_xy Ey and
+// sy += w_yx Ex + w_yy Ey.
+__device__ __forceinline__ void jones_taps(const uint4 *r1, const uint4 *r2, const float4 v,
+                                           float2 &sx, float2 &sy) {
+    const uint4 e1 = *r1, e2 = *r2;
+    const float ar = __uint_as_float(e1.x), ai = __uint_as_float(e1.y);
+    const float br = __uint_as_float(e1.z), bi = __uint_as_float(e1.w);
+    const float cr = __uint_as_float(e2.x), ci = __uint_as_float(e2.y);
+    sx.x += ar * v.z - ai * v.w;
+    sx.y += ar * v.w + ai * v.z;
+    sy.x += br * v.x - bi * v.y + cr * v.z - ci * v.w;
+    sy.y += br * v.y + bi * v.x + cr * v.w + ci * v.z;
+}
+
 // ------------------------------------------------------------------ kernel
 // One workgroup per item (channel c, class o), looping over all n_time
 // samples.  Gather entry (uint4): x = element | last-tap-of-cell << 31,
@@ -190,8 +206,10 @@ __device__ __forceinline__ void slot_position(int tid, int s, int &row, int &col
 // number of element rounds whose self terms a thread keeps (A <= AR * T).
 // FR: frame mode -- every frame_len samples the sums are stored to
 // frames[t / frame_len] (stride fstride floats) and restarted; acc is not
-// touched.
-template <int M, int P, int AR, bool FR>
+// touched.  JN: Jones kernels (two feeds) -- each tap has three entry rows
+// holding the weights x<-x, x<-y, y<-x, y<-y, and both feeds feed both
+// grids.
+template <int M, int P, int AR, bool FR, bool JN>
 __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(const FusedItem *__restrict__ items,
                                                       const uint4 *__restrict__ entries,
                                                       const uint8_t *__restrict__ volt,
@@ -278,12 +296,14 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
         // gather: this lane owns whole cells, so every cell is written once
         float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
         for (int k = 0; k < n_iter; ++k) {
-            const uint4 e = ent[(int64_t)k * T];
+            const uint4 e = ent[(int64_t)k * (JN ? 3 : 1) * T];
             const float4 v = stage[e.x & 0xFFFFu];
             const float wr = __uint_as_float(e.z), wi = __uint_as_float(e.w);
             sx.x += wr * v.x - wi * v.y;
             sx.y += wr * v.y + wi * v.x;
-            if (P == 2) {
+            if (JN) {
+                jones_taps(ent + ((int64_t)k * 3 + 1) * T, ent + ((int64_t)k * 3 + 2) * T, v, sx, sy);
+            } else if (P == 2) {
                 sy.x += wr * v.z - wi * v.w;
                 sy.y += wr * v.w + wi * v.z;
             }
@@ -365,7 +385,7 @@ __device__ __forceinline__ float uni(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-template <int AR, bool FR>
+template <int AR, bool FR, bool JN>
 __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict__ items,
                                                     const uint4 *__restrict__ entries,
                                                     const uint8_t *__restrict__ volt,
@@ -446,13 +466,18 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
         {
             float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
             for (int k = 0; k < n_iter; ++k) {
-                const uint4 e = ent[(int64_t)k * T];
+                const uint4 e = ent[(int64_t)k * (JN ? 3 : 1) * T];
                 const float4 v = stage[e.x & 0xFFFFu];
                 const float wr = __uint_as_float(e.z), wi = __uint_as_float(e.w);
                 sx.x += wr * v.x - wi * v.y;
                 sx.y += wr * v.y + wi * v.x;
-                sy.x += wr * v.z - wi * v.w;
-                sy.y += wr * v.w + wi * v.z;
+                if (JN) {
+                    jones_taps(ent + ((int64_t)k * 3 + 1) * T, ent + ((int64_t)k * 3 + 2) * T, v,
+                               sx, sy);
+                } else {
+                    sy.x += wr * v.z - wi * v.w;
+                    sy.y += wr * v.w + wi * v.z;
+                }
                 if (e.x >> 31) {
                     g.store(e.y, sx, sy);
                     sx = make_float2(0.f, 0.f);
@@ -605,9 +630,9 @@ static int row_of(int M) {
 
 // Cells are dealt longest-first to the least-loaded of T lanes, so each cell
 // is summed by one lane in a fixed order and written once.  Appends
-// n_iter * T entries [iter][lane] to all (padding entries are zero) and
-// returns n_iter.
-int lpt_pack(std::vector<GatherTap> &taps, int T, std::vector<uint4> &all) {
+// n_iter * T entries [iter][lane] (jones: n_iter * 3 * T, [iter][row][lane])
+// to all (padding entries are zero) and returns n_iter.
+int lpt_pack(std::vector<GatherTap> &taps, int T, std::vector<uint4> &all, bool jones) {
     const size_t n = taps.size();
     std::stable_sort(taps.begin(), taps.end(),
                      [](const GatherTap &x, const GatherTap &y) { return x.cell < y.cell; });
@@ -636,7 +661,9 @@ int lpt_pack(std::vector<GatherTap> &taps, int T, std::vector<uint4> &all) {
     }
     const int n_iter = *std::max_element(load.begin(), load.end());
     const size_t off = all.size();
-    all.resize(off + (size_t)n_iter * T, make_uint4(0u, 0u, 0u, 0u));
+    const int rows = jones ? 3 : 1;
+    all.resize(off + (size_t)n_iter * rows * T, make_uint4(0u, 0u, 0u, 0u));
+    auto bits = [](float f) { return __builtin_bit_cast(uint32_t, f); };
     for (int l = 0; l < T; ++l) {
         int k = 0;
         for (int r : lane_runs[l])
@@ -646,18 +673,25 @@ int lpt_pack(std::vector<GatherTap> &taps, int T, std::vector<uint4> &all) {
                 uint4 e;
                 e.x = (uint32_t)tp.ant | (last ? 0x80000000u : 0u);
                 e.y = (uint32_t)tp.cell;
-                e.z = __builtin_bit_cast(uint32_t, tp.wr);
-                e.w = __builtin_bit_cast(uint32_t, tp.wi);
-                all[off + (size_t)k * T + l] = e;
+                e.z = bits(tp.wr);
+                e.w = bits(tp.wi);
+                all[off + (size_t)k * rows * T + l] = e;
+                if (jones) {
+                    all[off + ((size_t)k * 3 + 1) * T + l] =
+                        make_uint4(bits(tp.m[0]), bits(tp.m[1]), bits(tp.m[2]), bits(tp.m[3]));
+                    all[off + ((size_t)k * 3 + 2) * T + l] =
+                        make_uint4(bits(tp.m[4]), bits(tp.m[5]), 0u, 0u);
+                }
             }
     }
     return n_iter;
 }
 
-// Gather entries of one item: the taps of class (ox, oy) folded modulo M.
+// Gather entries of one item: the taps of class (ox, oy) folded modulo M
+// (with Jones kernels all four weights of a tap carry the same fold factor).
 static FusedItem build_item(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
                             int c, int ox, int oy, int M, int T, std::vector<uint4> &all) {
-    const int A = p->A, K = p->K;
+    const int A = p->A, K = p->K, J = p->J;
     const int N = p->ch[c].N, R = p->ch[c].R, ROW = row_of(M);
     std::vector<GatherTap> taps;
     taps.reserve((size_t)A * K * K);
@@ -667,23 +701,29 @@ static FusedItem build_item(epic_plan p, const std::vector<int> &j0, const std::
         for (int dy = 0; dy < K; ++dy)
             for (int dx = 0; dx < K; ++dx) {
                 const int jx = jx0 + dx, jy = jy0 + dy;
-                const size_t wi = (((size_t)c * A + a) * K * K + dy * K + dx) * 2;
                 // conj(W) * (-1)^(jx+jy) * exp(+2 pi i (ox jx + oy jy) / N)
-                const double wr0 = w[wi], wi0 = -w[wi + 1];
                 const long ph = ((long)ox * jx + (long)oy * jy) % N;
                 const double ang = 2.0 * M_PI * (double)ph / (double)N;
                 const double sg = ((jx + jy) & 1) ? -1.0 : 1.0;
                 const double cr = std::cos(ang) * sg, ci = std::sin(ang) * sg;
+                float fw[8] = {};
+                for (int m = 0; m < J; ++m) {
+                    const size_t wi = ((((size_t)c * A + a) * J + m) * K * K + dy * K + dx) * 2;
+                    const double wr0 = w[wi], wi0 = -w[wi + 1];
+                    fw[2 * m] = (float)(wr0 * cr - wi0 * ci);
+                    fw[2 * m + 1] = (float)(wr0 * ci + wi0 * cr);
+                }
                 GatherTap tp;
                 tp.cell = (jy % M) * ROW + (jx % M);
                 tp.ant = a;
-                tp.wr = (float)(wr0 * cr - wi0 * ci);
-                tp.wi = (float)(wr0 * ci + wi0 * cr);
+                tp.wr = fw[0];
+                tp.wi = fw[1];
+                for (int m = 0; m < 6; ++m) tp.m[m] = fw[2 + m];
                 taps.push_back(tp);
             }
     }
     const size_t off = all.size();
-    const int n_iter = lpt_pack(taps, T, all);
+    const int n_iter = lpt_pack(taps, T, all, J == 4);
     FusedItem fi{};
     fi.c = c;
     fi.N = N;
@@ -820,13 +860,13 @@ epic_status lds_ready(const void *kern, size_t lds) {
     return EPIC_OK;
 }
 
-template <int M, int P, int AR, bool FR>
+template <int M, int P, int AR, bool FR, bool JN>
 static epic_status launch_fused_fr(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
                                    int A, int vb, int n_time, float *acc, int32_t *autos,
                                    const FrameOut &fo, hipStream_t s, bool dry) {
     constexpr int T = FCfg<M>::T, GSZ = M * FCfg<M>::ROW;
     const size_t lds = sizeof(float2) * P * GSZ + sizeof(float4) * (size_t)A;
-    auto kern = k_fused<M, P, AR, FR>;
+    auto kern = k_fused<M, P, AR, FR, JN>;
     epic_status st = lds_ready(reinterpret_cast<const void *>(kern), lds);
     if (st || dry) return st;
     hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(T), lds, s, g->items.as<FusedItem>(),
@@ -836,36 +876,38 @@ static epic_status launch_fused_fr(const FusedGroup *g, const uint8_t *d_volt, i
     return EPIC_OK;
 }
 
-template <int M, int P, int AR>
+template <int M, int P, int AR, bool JN>
 static epic_status launch_fused_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
                                    int A, int vb, int n_time, float *acc, int32_t *autos,
                                    const FrameOut &fo, hipStream_t s, bool dry) {
-    return fo.len ? launch_fused_fr<M, P, AR, true>(g, d_volt, vstride, A, vb, n_time, acc,
-                                                    autos, fo, s, dry)
-                  : launch_fused_fr<M, P, AR, false>(g, d_volt, vstride, A, vb, n_time, acc,
-                                                     autos, fo, s, dry);
+    return fo.len ? launch_fused_fr<M, P, AR, true, JN>(g, d_volt, vstride, A, vb, n_time, acc,
+                                                        autos, fo, s, dry)
+                  : launch_fused_fr<M, P, AR, false, JN>(g, d_volt, vstride, A, vb, n_time, acc,
+                                                         autos, fo, s, dry);
 }
 
 // Element rounds per thread: 1, 2 or 4; above 4 T the self terms come from a
 // separate pass (autos == nullptr).
-template <int M, int P>
+template <int M, int P, bool JN>
 static epic_status launch_fused(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
                                 int A, int vb, int n_time, float *acc, int32_t *autos,
                                 const FrameOut &fo, hipStream_t s, bool dry) {
     constexpr int T = FCfg<M>::T;
     if (A <= T)
-        return launch_fused_ar<M, P, 1>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
+        return launch_fused_ar<M, P, 1, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s,
+                                            dry);
     if (A <= 2 * T)
-        return launch_fused_ar<M, P, 2>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
-    return launch_fused_ar<M, P, 4>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
+        return launch_fused_ar<M, P, 2, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s,
+                                            dry);
+    return launch_fused_ar<M, P, 4, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
 }
 
-template <int AR, bool FR>
+template <int AR, bool FR, bool JN>
 static epic_status launch_pair_fr(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
                                   int A, int vb, int n_time, float *acc, int32_t *autos,
                                   const FrameOut &fo, hipStream_t s, bool dry) {
     const size_t lds = sizeof(float4) * (2 * 64 * 65 + (size_t)A);
-    auto kern = k_fused_pair<AR, FR>;
+    auto kern = k_fused_pair<AR, FR, JN>;
     epic_status st = lds_ready(reinterpret_cast<const void *>(kern), lds);
     if (st || dry) return st;
     hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(512), lds, s, g->items.as<FusedItem>(),
@@ -875,24 +917,25 @@ static epic_status launch_pair_fr(const FusedGroup *g, const uint8_t *d_volt, in
     return EPIC_OK;
 }
 
-template <int AR>
+template <int AR, bool JN>
 static epic_status launch_pair_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
                                   int A, int vb, int n_time, float *acc, int32_t *autos,
                                   const FrameOut &fo, hipStream_t s, bool dry) {
-    return fo.len
-               ? launch_pair_fr<AR, true>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry)
-               : launch_pair_fr<AR, false>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s,
-                                           dry);
+    return fo.len ? launch_pair_fr<AR, true, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos,
+                                                 fo, s, dry)
+                  : launch_pair_fr<AR, false, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos,
+                                                  fo, s, dry);
 }
 
+template <bool JN>
 static epic_status launch_pair(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride, int A,
                                int vb, int n_time, float *acc, int32_t *autos, const FrameOut &fo,
                                hipStream_t s, bool dry) {
     if (A <= 512)
-        return launch_pair_ar<1>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
+        return launch_pair_ar<1, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
     if (A <= 1024)
-        return launch_pair_ar<2>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
-    return launch_pair_ar<4>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
+        return launch_pair_ar<2, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
+    return launch_pair_ar<4, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
 }
 
 // Launches every size group; group i goes to branches[i] when given (graph
@@ -923,16 +966,23 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
         const hipStream_t gs = branches ? (*branches)[gi] : s;
         epic_status st = EPIC_OK;
         const int A = p->A;
-        if (g->kind == 1) {
-            st = launch_pair(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
+        const int vb = p->vb;
+        if (g->kind == 1 && p->J == 4) {
+            st = launch_pair<true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+        } else if (g->kind == 1) {
+            st = launch_pair<false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+        } else if (p->J == 4) {
+            if (g->M == 64) st = launch_fused<64, 2, true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 32) st = launch_fused<32, 2, true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 16) st = launch_fused<16, 2, true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
         } else if (p->P == 2) {
-            if (g->M == 64) st = launch_fused<64, 2>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
-            if (g->M == 32) st = launch_fused<32, 2>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
-            if (g->M == 16) st = launch_fused<16, 2>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 64) st = launch_fused<64, 2, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 32) st = launch_fused<32, 2, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 16) st = launch_fused<16, 2, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
         } else {
-            if (g->M == 64) st = launch_fused<64, 1>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
-            if (g->M == 32) st = launch_fused<32, 1>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
-            if (g->M == 16) st = launch_fused<16, 1>(g, d_volt, vstride, A, p->vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 64) st = launch_fused<64, 1, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 32) st = launch_fused<32, 1, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 16) st = launch_fused<16, 1, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
         }
         if (st) return st;
     }

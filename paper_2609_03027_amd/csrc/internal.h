@@ -160,6 +160,7 @@ struct BandPlan {
 struct epic_plan_s {
     int A = 0, P = 0, C = 0, K = 0;
     int vb = 1;                   // bytes per voltage sample (1: 4+4 bit, 2: 8+8 bit)
+    int J = 1;                    // kernels per element: 1, or 4 (Jones: alpha p = xx, xy, yx, yy)
     int aperture_n = 0;
     double cell_lambda = 0.5, sigma = 0.5;
     int precision = 0;
@@ -178,10 +179,11 @@ struct epic_plan_s {
     // device tables
     epic::DevBuf d_pos;      // double [A][2]
     epic::DevBuf d_freq;     // double [C]
-    epic::DevBuf d_table;    // float  [C][A][K][K][2] (optional)
+    epic::DevBuf d_table;    // float  [C][A][J][K][K][2] (optional)
     epic::DevBuf d_j0;       // int2   [C][A]
-    epic::DevBuf d_w;        // double2 [C][A][K][K]  kernel weights W (not conjugated)
+    epic::DevBuf d_w;        // double2 [C][A][J][K][K]  kernel weights W (not conjugated)
     epic::DevBuf d_selfcorr; // double2 [C][(2K-1)^2][A] footprint self-correlation R_a[d]
+                             // (not built for Jones kernels: read-out uses d_w)
     epic::DevBuf d_chan;     // int4   [C] {N, M, R, 0}
     epic::DevBuf d_img_off;  // int64  [C]
     epic::DevBuf d_grid_off; // int64  [C]
@@ -190,7 +192,7 @@ struct epic_plan_s {
     epic::DevBuf d_csr_off;  // int32 [sum_c N_c^2 + C]  (per channel N_c^2 + 1 offsets)
     epic::DevBuf d_csr_base; // int64 [C] start of channel c in d_csr_off
     epic::DevBuf d_csr_ant;  // int32 [total taps]
-    epic::DevBuf d_csr_w;    // float2 [total taps] conj(W)
+    epic::DevBuf d_csr_w;    // float2 [total taps][J] conj(W)
     epic::DevBuf d_twid;     // float2 per distinct N: exp(+2 pi i n / N), n < N
     std::vector<int64_t> twid_off;  // indexed by N (-1 if unused)
     // channels grouped by grid side (staged transform launches)
@@ -255,14 +257,18 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
                              bool dry = false, const FrameOut &fo = FrameOut());
 epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                              hipStream_t s);
-// One gather tap: destination cell (LDS index), element, complex weight.
+// One gather tap: destination cell (LDS index), element, complex weight
+// (x-to-x with Jones kernels, whose other three weights xy, yx, yy are in m).
 struct GatherTap {
     int cell, ant;
     float wr, wi;
+    float m[6];
 };
 // Lane-owns-cell packing of taps into [iter][lane] gather entries
-// {ant | last << 31, cell, wr, wi}; returns the iterations per lane.
-int lpt_pack(std::vector<GatherTap> &taps, int T, std::vector<uint4> &all);
+// {ant | last << 31, cell, wr, wi}; returns the iterations per lane.  With
+// jones each iteration has three rows [iter][3][lane]: that entry, then
+// {xy re, xy im, yx re, yx im} and {yy re, yy im, 0, 0}.
+int lpt_pack(std::vector<GatherTap> &taps, int T, std::vector<uint4> &all, bool jones = false);
 // Allow a kernel the device's whole LDS once, then check a launch's need.
 epic_status lds_ready(const void *kern, size_t lds);
 

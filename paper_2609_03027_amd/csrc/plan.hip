@@ -11,10 +11,11 @@ namespace epic {
 
 // One thread per (channel, element).  x = pos / cell + N/2 in grid units,
 // support start j0 = floor(x - K/2 + 1); weights either the unit-sum Gaussian
-// of width sigma cells or the caller's complex table.
+// of width sigma cells or the caller's complex table (J kernels per element:
+// 1, or the four Jones kernels alpha p = xx, xy, yx, yy).
 __global__ void k_plan_geometry(const double *__restrict__ pos, const double *__restrict__ freq,
                                 const int4 *__restrict__ chan, const float *__restrict__ table,
-                                int A, int C, int K, double cell_lambda, double sigma,
+                                int A, int C, int K, int J, double cell_lambda, double sigma,
                                 int2 *__restrict__ j0_out, double2 *__restrict__ w_out) {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
     int c = blockIdx.y;
@@ -28,10 +29,11 @@ __global__ void k_plan_geometry(const double *__restrict__ pos, const double *__
     const int jy = (int)floor(xy - 0.5 * K + 1.0);
     const size_t ca = (size_t)c * A + a;
     j0_out[ca] = make_int2(jx, jy);
-    double2 *w = w_out + ca * K * K;
+    double2 *w = w_out + ca * J * K * K;
     if (table) {
-        const float *tb = table + ca * K * K * 2;
-        for (int i = 0; i < K * K; ++i) w[i] = make_double2((double)tb[2 * i], (double)tb[2 * i + 1]);
+        const float *tb = table + ca * J * K * K * 2;
+        for (int i = 0; i < J * K * K; ++i)
+            w[i] = make_double2((double)tb[2 * i], (double)tb[2 * i + 1]);
         return;
     }
     const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
@@ -71,8 +73,9 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
         if (N < 8 || (N & 1)) return fail(EPIC_ERR_GRID, "grid side must be even and >= 8");
         if (N > 1024) return fail(EPIC_ERR_UNSUPPORTED, "grid side above 1024");
         // Banded two-pass path: on request, or by default where the fused
-        // path would split the channel into 16 or more sub-transforms.
-        if (p->precision == EPIC_F32 &&
+        // path would split the channel into 16 or more sub-transforms (not
+        // with Jones kernels, which only the fused and staged gathers take).
+        if (p->precision == EPIC_F32 && p->J == 1 &&
             (want < 0 || (want == 0 && M && N / M >= 4 && banded_eligible(N)))) {
             if (!banded_eligible(N))
                 return fail(EPIC_ERR_UNSUPPORTED, "banded path: grid side must be a multiple "
@@ -80,7 +83,8 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
             p->banded[c] = 1;
             M = 0;
         } else if (want < 0) {
-            return fail(EPIC_ERR_UNSUPPORTED, "banded path needs FP32 precision");
+            return fail(EPIC_ERR_UNSUPPORTED, p->J > 1 ? "the banded path does not take Jones kernels"
+                                                       : "banded path needs FP32 precision");
         } else if (M == 0) {
             return fail(EPIC_ERR_GRID, "grid side must be a multiple of 16");
         }
@@ -102,7 +106,7 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     if ((st = p->d_img_off.alloc(sizeof(int64_t) * C))) return st;
     if ((st = p->d_grid_off.alloc(sizeof(int64_t) * C))) return st;
     if ((st = p->d_j0.alloc(sizeof(int2) * (size_t)C * A))) return st;
-    if ((st = p->d_w.alloc(sizeof(double2) * (size_t)C * A * K * K))) return st;
+    if ((st = p->d_w.alloc(sizeof(double2) * (size_t)C * A * p->J * K * K))) return st;
     EPIC_HIP(hipMemcpyAsync(p->d_pos.p, p->pos.data(), sizeof(double) * 2 * A, hipMemcpyHostToDevice, s));
     EPIC_HIP(hipMemcpyAsync(p->d_freq.p, p->freq.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
     EPIC_HIP(hipMemcpyAsync(p->d_chan.p, chan.data(), sizeof(int4) * C, hipMemcpyHostToDevice, s));
@@ -112,12 +116,13 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     dim3 grid((A + 255) / 256, C);
     hipLaunchKernelGGL(k_plan_geometry, grid, dim3(256), 0, s, p->d_pos.as<double>(),
                        p->d_freq.as<double>(), p->d_chan.as<int4>(),
-                       p->has_table ? p->d_table.as<float>() : nullptr, A, C, K, p->cell_lambda,
+                       p->has_table ? p->d_table.as<float>() : nullptr, A, C, K, p->J, p->cell_lambda,
                        p->sigma, p->d_j0.as<int2>(), p->d_w.as<double2>());
     EPIC_HIP(hipGetLastError());
 
     std::vector<int> j0((size_t)C * A * 2);
-    std::vector<double> w((size_t)C * A * K * K * 2);
+    const int J = p->J;
+    std::vector<double> w((size_t)C * A * J * K * K * 2);
     EPIC_HIP(hipMemcpyAsync(j0.data(), p->d_j0.p, sizeof(int) * j0.size(), hipMemcpyDeviceToHost, s));
     EPIC_HIP(hipMemcpyAsync(w.data(), p->d_w.p, sizeof(double) * w.size(), hipMemcpyDeviceToHost, s));
     EPIC_HIP(hipStreamSynchronize(s));
@@ -136,7 +141,8 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
         }
     }
 
-    // Staged gather tables: for each channel, cell -> (element, conj(W)).
+    // Staged gather tables: for each channel, cell -> (element, conj(W)),
+    // J weights per tap.
     {
         std::vector<int64_t> base(C);
         int64_t n_off = 0, n_taps = (int64_t)C * A * K * K;
@@ -146,7 +152,7 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
         }
         std::vector<int32_t> off(n_off, 0);
         std::vector<int32_t> ant(n_taps);
-        std::vector<float> wc(2 * n_taps);
+        std::vector<float> wc(2 * J * n_taps);
         int64_t tap0 = 0;
         for (int c = 0; c < C; ++c) {
             const int N = p->ch[c].N;
@@ -164,10 +170,13 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
                     for (int dx = 0; dx < K; ++dx) {
                         const int cell = (jy + dy) * N + (jx + dx);
                         const int64_t e = tap0 + fill[cell]++;
-                        const size_t wi = (((size_t)c * A + a) * K * K + dy * K + dx) * 2;
                         ant[e] = a;
-                        wc[2 * e] = (float)w[wi];
-                        wc[2 * e + 1] = (float)(-w[wi + 1]);
+                        for (int m = 0; m < J; ++m) {
+                            const size_t wi =
+                                ((((size_t)c * A + a) * J + m) * K * K + dy * K + dx) * 2;
+                            wc[2 * (e * J + m)] = (float)w[wi];
+                            wc[2 * (e * J + m) + 1] = (float)(-w[wi + 1]);
+                        }
                     }
             }
             // offsets become absolute tap indices
@@ -177,11 +186,11 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
         if ((st = p->d_csr_off.alloc(sizeof(int32_t) * n_off))) return st;
         if ((st = p->d_csr_base.alloc(sizeof(int64_t) * C))) return st;
         if ((st = p->d_csr_ant.alloc(sizeof(int32_t) * n_taps))) return st;
-        if ((st = p->d_csr_w.alloc(sizeof(float) * 2 * n_taps))) return st;
+        if ((st = p->d_csr_w.alloc(sizeof(float) * 2 * J * n_taps))) return st;
         EPIC_HIP(hipMemcpyAsync(p->d_csr_off.p, off.data(), sizeof(int32_t) * n_off, hipMemcpyHostToDevice, s));
         EPIC_HIP(hipMemcpyAsync(p->d_csr_base.p, base.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, s));
         EPIC_HIP(hipMemcpyAsync(p->d_csr_ant.p, ant.data(), sizeof(int32_t) * n_taps, hipMemcpyHostToDevice, s));
-        EPIC_HIP(hipMemcpyAsync(p->d_csr_w.p, wc.data(), sizeof(float) * 2 * n_taps, hipMemcpyHostToDevice, s));
+        EPIC_HIP(hipMemcpyAsync(p->d_csr_w.p, wc.data(), sizeof(float) * 2 * J * n_taps, hipMemcpyHostToDevice, s));
         EPIC_HIP(hipStreamSynchronize(s));
     }
 
@@ -226,7 +235,7 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
         EPIC_HIP(hipStreamSynchronize(s));
     }
 
-    if ((st = selfcorr_build(p, s))) return st;
+    if (J == 1 && (st = selfcorr_build(p, s))) return st;
     p->w_host = w;
     if (p->precision == EPIC_F32) {
         if ((st = fused_build(p, j0, w, s))) return st;

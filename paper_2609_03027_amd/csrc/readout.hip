@@ -9,7 +9,8 @@
 // sum_a S_a^{pq} |B_a[k]|^2 = sum_d H^{pq}[d] exp(...), H^{pq}[d] =
 // sum_a S_a^{pq} R_a[d], so a (2K-1)^2-term sum per pixel evaluates it
 // exactly.  H and the per-pixel sum are formed in FP64 from the exact int32
-// self-term sums.
+// self-term sums.  With Jones kernels (four per element) the same expansion
+// holds per pair of kernels; see k_auto_h_jones.
 #include "internal.h"
 
 namespace epic {
@@ -81,6 +82,69 @@ __global__ __launch_bounds__(256) void k_auto_h(const double2 *__restrict__ R,
         constexpr int NH = P == 2 ? 3 : 1;
         double2 *h = H + (size_t)c * NH * D2;
         for (int q = 0; q < NH; ++q) h[q * D2 + d] = make_double2(red[2 * q][0], red[2 * q + 1][0]);
+    }
+}
+
+// Jones kernels: element a alone puts sum_p B_a^{alpha p} E_a^p on every
+// pixel, so its self term of product alpha beta is
+//   sum_{p,q} S_a^{pq} B_a^{alpha p} conj(B_a^{beta q})
+//     = sum_d [sum_{p,q} S_a^{pq} R_a^{alpha p, beta q}[d]] exp(+2 pi i (k - N/2).d / N),
+//   R_a^{alpha p, beta q}[d] = sum_j conj(W_a^{alpha p}(j)) W_a^{beta q}(j - d),
+// with S_a^{yx} = conj(S_a^{xy}).  The R terms are formed here from the
+// weights (J = 4 per element, alpha p = xx, xy, yx, yy) instead of a stored
+// table.  One 256-thread block per (displacement, channel); H layout as for
+// k_auto_h<2>: double2 [C][3][D*D] for XX, YY, XY.
+__global__ __launch_bounds__(256) void k_auto_h_jones(const double2 *__restrict__ w,
+                                                      const int32_t *__restrict__ autos, int A,
+                                                      int K, double2 *__restrict__ H) {
+    const int D = 2 * K - 1, D2 = D * D;
+    const int d = blockIdx.x, c = blockIdx.y;
+    const int dx = d % D - (K - 1), dy = d / D - (K - 1);
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int a = threadIdx.x; a < A; a += blockDim.x) {
+        const int32_t *s = autos + ((size_t)c * A + a) * 4;
+        // S[p][q] = sum_t E^p conj(E^q)
+        const double2 S[2][2] = {{make_double2((double)s[0], 0.0), make_double2((double)s[2], (double)s[3])},
+                                 {make_double2((double)s[2], -(double)s[3]), make_double2((double)s[1], 0.0)}};
+        const double2 *wa = w + ((size_t)c * A + a) * 4 * K * K;
+        for (int ty = 0; ty < K; ++ty) {
+            const int uy = ty - dy;
+            if (uy < 0 || uy >= K) continue;
+            for (int tx = 0; tx < K; ++tx) {
+                const int ux = tx - dx;
+                if (ux < 0 || ux >= K) continue;
+#pragma unroll
+                for (int ab = 0; ab < 3; ++ab) {
+                    const int al = ab == 1 ? 1 : 0, be = ab == 0 ? 0 : 1;
+#pragma unroll
+                    for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+                        for (int qq = 0; qq < 2; ++qq) {
+                            const double2 P = wa[(al * 2 + pp) * K * K + ty * K + tx];
+                            const double2 Q = wa[(be * 2 + qq) * K * K + uy * K + ux];
+                            // r = conj(P) Q, then v += S[p][q] r
+                            const double rr = P.x * Q.x + P.y * Q.y, ri = P.x * Q.y - P.y * Q.x;
+                            const double2 sv = S[pp][qq];
+                            v[2 * ab] += sv.x * rr - sv.y * ri;
+                            v[2 * ab + 1] += sv.x * ri + sv.y * rr;
+                        }
+                }
+            }
+        }
+    }
+    __shared__ double red[6][256];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double2 *h = H + (size_t)c * 3 * D2;
+        for (int q = 0; q < 3; ++q) h[q * D2 + d] = make_double2(red[2 * q][0], red[2 * q + 1][0]);
     }
 }
 
@@ -190,7 +254,10 @@ epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hip
     DevBuf &H = acc->d_h;
     if (remove) {
         dim3 g(D * D, p->C);
-        if (p->P == 2)
+        if (p->J == 4)
+            hipLaunchKernelGGL(k_auto_h_jones, g, dim3(256), 0, s, p->d_w.as<double2>(),
+                               acc->d_autos.as<int32_t>(), p->A, p->K, H.as<double2>());
+        else if (p->P == 2)
             hipLaunchKernelGGL(k_auto_h<2>, g, dim3(256), 0, s, p->d_selfcorr.as<double2>(),
                                acc->d_autos.as<int32_t>(), p->A, p->K, H.as<double2>());
         else

@@ -10,13 +10,15 @@
 namespace epic {
 
 // Gather gridding: one thread per output cell, summing conj(W) E over the
-// cell's taps from the plan's CSR table.  Every cell is written.
-// Grid: (cell blocks, channels, n_time * P).
+// cell's taps from the plan's CSR table.  Every cell is written.  With Jones
+// kernels (J = 4) output polarisation p sums conj(W^{p x}) E^x + conj(W^{p y})
+// E^y over the taps.  Grid: (cell blocks, channels, n_time * P).
 __global__ void k_grid_csr(const uint8_t *__restrict__ volt, int64_t volt_t_stride,
                            const int4 *__restrict__ chan, const int64_t *__restrict__ grid_off,
                            const int64_t *__restrict__ csr_base, const int32_t *__restrict__ csr_off,
                            const int32_t *__restrict__ csr_ant, const float2 *__restrict__ csr_w,
-                           int A, int P, int64_t grid_t_stride, float2 *__restrict__ grid, int vb) {
+                           int A, int P, int J, int64_t grid_t_stride, float2 *__restrict__ grid,
+                           int vb) {
     const int c = blockIdx.y;
     const int N = chan[c].x;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -24,14 +26,25 @@ __global__ void k_grid_csr(const uint8_t *__restrict__ volt, int64_t volt_t_stri
     const int t = blockIdx.z / P, p = blockIdx.z % P;
     const int32_t *off = csr_off + csr_base[c];
     const int e0 = off[cell], e1 = off[cell + 1];
-    const uint8_t *v = volt + (int64_t)t * volt_t_stride + ((int64_t)c * P + p) * A * vb;
     float2 s = make_float2(0.f, 0.f);
-    for (int e = e0; e < e1; ++e) {
-        const int2 x = volt_at(v, csr_ant[e], vb);
-        const float er = (float)x.x, ei = (float)x.y;
-        const float2 w = csr_w[e];
-        s.x += w.x * er - w.y * ei;
-        s.y += w.x * ei + w.y * er;
+    if (J == 4) {
+        const uint8_t *v = volt + (int64_t)t * volt_t_stride + (int64_t)c * 2 * A * vb;
+        for (int e = e0; e < e1; ++e) {
+            const int a = csr_ant[e];
+            const int2 x = volt_at(v, a, vb), y = volt_at(v, A + a, vb);
+            const float2 wx = csr_w[4 * e + 2 * p], wy = csr_w[4 * e + 2 * p + 1];
+            s.x += wx.x * (float)x.x - wx.y * (float)x.y + wy.x * (float)y.x - wy.y * (float)y.y;
+            s.y += wx.x * (float)x.y + wx.y * (float)x.x + wy.x * (float)y.y + wy.y * (float)y.x;
+        }
+    } else {
+        const uint8_t *v = volt + (int64_t)t * volt_t_stride + ((int64_t)c * P + p) * A * vb;
+        for (int e = e0; e < e1; ++e) {
+            const int2 x = volt_at(v, csr_ant[e], vb);
+            const float er = (float)x.x, ei = (float)x.y;
+            const float2 w = csr_w[e];
+            s.x += w.x * er - w.y * ei;
+            s.y += w.x * ei + w.y * er;
+        }
     }
     grid[(int64_t)t * grid_t_stride + grid_off[c] + (int64_t)p * N * N + cell] = s;
 }
@@ -216,7 +229,7 @@ epic_status staged_grid(epic_plan p, const uint8_t *d_volt, int n_time, void *d_
                            vstride, p->d_chan.as<int4>(), p->d_grid_off.as<int64_t>(),
                            p->d_csr_base.as<int64_t>(), p->d_csr_off.as<int32_t>(),
                            p->d_csr_ant.as<int32_t>(), p->d_csr_w.as<float2>(), p->A, p->P,
-                           p->grid_elems_per_t,
+                           p->J, p->grid_elems_per_t,
                            static_cast<float2 *>(d_grid) + (int64_t)t0 * p->grid_elems_per_t,
                            p->vb);
         EPIC_HIP(hipGetLastError());

@@ -116,11 +116,36 @@ def test_plan_flags_validated_before_device_work():
     import paper_2609_03027_amd as E
     lib = E.load()
     h = C.c_void_p()
-    d, keep = _desc(flags=2)
+    d, keep = _desc(flags=8)
     assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 2
     d, keep = _desc(flags=E.VOLT_8BIT, precision=E.EPIC_F8E4M3_MFMA)
     assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 4
     assert b"FP8" in lib.epic_last_error()
+
+
+def test_jones_plans_validated_before_device_work():
+    """Jones kernels need two feeds, a kernel table, FP32, and no banded
+    channel; each request outside that fails with its own status."""
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    h = C.c_void_p()
+    table = np.zeros((1, 4, 2, 2, 3, 3, 2), dtype=np.float32)
+    tp = table.ctypes.data_as(C.POINTER(C.c_float))
+    d, keep = _desc(flags=E.JONES, kernel_table=tp)            # one feed
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 2
+    assert b"two feeds" in lib.epic_last_error()
+    d, keep = _desc(flags=E.JONES, n_pol=2)                    # no table
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 1
+    d, keep = _desc(flags=E.JONES, n_pol=2, kernel_table=tp, precision=E.EPIC_F16_MFMA)
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 4
+    s = np.array([E.SUB_BANDED], dtype=np.int32)
+    d, keep = _desc(flags=E.JONES, n_pol=2, kernel_table=tp,
+                    sub_n=s.ctypes.data_as(C.POINTER(C.c_int32)))
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 4
+    assert b"banded" in lib.epic_last_error()
+    assert not h.value
+    with pytest.raises(ValueError):                            # binding checks the shape
+        E.Plan(np.zeros((4, 2)), [60e6], [32], 2, kernel_table=table[:, :, 0], jones=True)
 
 
 def test_autotune_candidates_include_the_banded_path_where_it_applies():

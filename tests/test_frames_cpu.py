@@ -7,7 +7,7 @@ import oracle as O
 import synth
 
 
-def frame_sums(volt_c, pos, wl, c, frame_len):
+def frame_sums(volt_c, pos, wl, c, frame_len, jones=None):
     T = volt_c.shape[0]
     out = []
     for f in range(T // frame_len):
@@ -15,7 +15,7 @@ def frame_sums(volt_c, pos, wl, c, frame_len):
                                 wl.chan_freq_hz[c], int(wl.grid_n[c]),
                                 cell_lambda=wl.cell_lambda, k=wl.kernel_k,
                                 sigma=wl.kernel_sigma_cells, aperture_n=wl.aperture_n,
-                                want_auto=False)
+                                want_auto=False, jones=jones)
         out.append(r["acc"])
     return np.stack(out)
 

@@ -33,15 +33,19 @@ def _say(msg):
 
 
 def _run(wl, pos, volt, *, fused=True, flags=None, kernels=None, chunks=1, precision=0,
-         sub_n=None):
-    """Run the GPU path on a block; returns per-channel float64 images."""
+         sub_n=None, jones=None):
+    """Run the GPU path on a block; returns per-channel float64 images.
+    ``kernels`` ([A][K][K] complex per channel) or ``jones`` ([A][2][2][K][K]
+    complex per channel) replace the Gaussian."""
     torch = _torch()
     import paper_2609_03027_amd as E
     table = None
-    if kernels is not None:
-        k = np.stack(kernels)                   # [C][A][K][K] complex
+    tabs = kernels if jones is None else jones
+    if tabs is not None:
+        k = np.stack(tabs)                      # [C][A]([2][2])[K][K] complex
         table = np.stack([k.real, k.imag], axis=-1).astype(np.float32)
-    plan = E.Plan.from_workload(wl, pos, kernel_table=table, precision=precision, sub_n=sub_n)
+    plan = E.Plan.from_workload(wl, pos, kernel_table=table, precision=precision, sub_n=sub_n,
+                                jones=jones is not None)
     acc = E.Accumulator(plan)
     dv = torch.from_numpy(np.ascontiguousarray(volt)).cuda()
     T = volt.shape[0]
