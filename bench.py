@@ -316,6 +316,48 @@ def high_cadence(E, torch, reps=3):
     return res
 
 
+def polarimetric(E, torch, ms_diag, reps=5):
+    """The LWA-station integration with full polarimetric gridding: four
+    complex kernels per element (a fixed 3 x 3 footprint times a per-element
+    2 x 2 matrix near the identity with complex leakage), each output
+    polarisation gridding both feeds.  Same voltages and grids as the
+    headline step; the gather does four complex multiply-adds per tap
+    instead of two."""
+    import numpy as np
+    import synth
+    wl = synth.workload("lwa")
+    pos = synth.antenna_layout(wl)
+    volt = torch.from_numpy(synth.voltages(wl, pos)).cuda()
+    rng = np.random.default_rng(77)
+    A, C = wl.n_ant, wl.n_chan
+    foot = np.outer([0.25, 0.5, 0.25], [0.25, 0.5, 0.25])
+    jm = np.eye(2)[None, None] + 0.2 * (rng.normal(size=(C, A, 2, 2)) +
+                                        1j * rng.normal(size=(C, A, 2, 2)))
+    k = jm[..., None, None] * foot
+    table = np.stack([k.real, k.imag], axis=-1).astype(np.float32)
+    t0 = time.perf_counter()
+    plan = E.Plan.from_workload(wl, pos, kernel_table=table, jones=True)
+    tplan = time.perf_counter() - t0
+    acc = E.Accumulator(plan)
+    E.accumulate(plan, acc, volt=volt)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        E.accumulate(plan, acc, volt=volt)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    samples = wl.n_time * wl.n_chan * wl.n_pol * wl.n_ant
+    res = {"ms_per_integration": ms, "samples_per_s": samples / (ms / 1e3),
+           "vs_diagonal_kernel": ms / ms_diag, "plan_s": tplan}
+    log(f"jones lwa: {ms:.2f} ms per integration ({ms / ms_diag:.2f} x the diagonal kernel), "
+        f"plan {tplan:.1f} s")
+    acc.close()
+    plan.close()
+    return res
+
+
 def wide_field(E, torch, reps=3):
     """Wide-field large array: ~20 000 dual-pol elements in a 700 m disc, one
     781.25 kHz coarse channel at 100 MHz, 512 x 512 grid, 781 samples (1 ms
@@ -463,6 +505,8 @@ def main():
                     help="time the 512^2 wide-field array (0 = skip)")
     ap.add_argument("--frames", type=int, default=1,
                     help="time high-cadence 4-sample frames (0 = skip)")
+    ap.add_argument("--jones", type=int, default=1,
+                    help="time the LWA step with full polarimetric (Jones) kernels (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB for a plain device copy (counter calibration runs)")
     args = ap.parse_args()
@@ -652,6 +696,8 @@ def main():
         out["wide_field"] = wide_field(E, torch)
     if args.frames:
         out["high_cadence"] = high_cadence(E, torch)
+    if args.jones:
+        out["polarimetric"] = polarimetric(E, torch, out["roofline"]["kernel_ms"])
 
     if args.stream_blocks > 0:
         out["streaming"] = {}

@@ -67,8 +67,28 @@ typedef enum {
     EPIC_F32 = 0,           /* FP32 gridding + FFT on the vector units */
     EPIC_F16_MFMA = 1,      /* direct DFT-as-GEMM on MFMA, FP16 operands, FP32 accumulate */
     EPIC_F8E4M3_MFMA = 2,   /* same with FP8 e4m3 operands, per-channel power-of-two scale */
-    EPIC_BF16X2_MFMA = 3    /* same with the beam matrix split into BF16 hi + lo */
+    EPIC_BF16X2_MFMA = 3,   /* same with the beam matrix split into BF16 hi + lo */
+    EPIC_FIXED16 = 4        /* low-bitwidth path on 64 x 64 grids (Sec. 3 FFT core with a
+                               configurable scaling scheme): kernel weights quantised to
+                               8+8 bits with one power-of-two scale 2^sw, exact integer
+                               gridding, a rounding shift by sg bits to 16-bit grid values,
+                               then 6 + 6 radix-2 DIF stages (rows, then columns) in 16-bit
+                               fixed point: stage s writes sat16(rsh(a + c, b_s)) and
+                               sat16(rsh((a - c) w, ts + b_s)) with twiddles
+                               w_n = rint(2^ts exp(+2 pi i n / 64)), ts = twiddle bits - 1,
+                               rsh(x, k) = (x + 2^(k-1)) >> k (round half up), b_s bit s of
+                               the stage mask (bits 0-5 rows, 6-11 columns).  Products of
+                               the integer sky values are summed exactly (FP64) and added
+                               to the FP32 accumulator once per call, times
+                               2^(2 (halving stages + sg - sw)).  Every grid side must be 64;
+                               not with EPIC_JONES, frames or the banded path.  The staged
+                               primitives (epic_grid, epic_image) stay FP32 and use the
+                               quantised kernel; read-out removes the self terms of the
+                               quantised kernel. */
 } epic_precision;
+
+/* EPIC_FIXED16 settings: -1 selects the default */
+#define EPIC_FIXED_DEFAULT (-1)
 
 /* plan flags */
 #define EPIC_PLAN_DEFAULT 0u
@@ -119,6 +139,13 @@ typedef struct {
                                     3, at most 512); 0 or NULL = automatic: banded where
                                     the largest M dividing grid_n[c] leaves 4 or more
                                     sub-transforms per axis, else that M */
+    /* EPIC_FIXED16 only (ignored otherwise): */
+    int32_t fixed_twiddle_bits;  /* 2..15 (0 -> 8): twiddles carry bits - 1 fraction bits */
+    int32_t fixed_stage_shifts;  /* 0..4095: bit s halves after stage s (0-5 along x, 6-11
+                                    along y); EPIC_FIXED_DEFAULT = 4095 (every stage) */
+    int32_t fixed_grid_shift;    /* 0..30 bits dropped (rounding) from the exact gridded
+                                    sums; EPIC_FIXED_DEFAULT = the smallest shift with which
+                                    no cell of any channel can saturate at the voltage width */
 } epic_plan_desc;
 
 typedef struct epic_plan_s *epic_plan;  /* opaque; owns device tables */
@@ -133,6 +160,10 @@ typedef struct {
     int64_t bytes_acc;          /* device bytes one accumulator holds */
     int32_t n_prod;             /* 1 or 4 */
     int32_t max_grid_n;
+    int32_t fixed_kernel_shift; /* EPIC_FIXED16: sw, weights quantised as rint(W 2^sw) */
+    int32_t fixed_grid_shift;   /* EPIC_FIXED16: sg in use */
+    int32_t fixed_scale_exp2;   /* EPIC_FIXED16: sums are scaled by 2^this into the acc */
+    int32_t fixed_slices;       /* EPIC_FIXED16: time slices per call (workgroups per channel) */
 } epic_plan_info;
 
 /* Plan setup (Eq. 1 gridding geometry; Sec. 4 grid spacing).  Copies the

@@ -15,7 +15,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libepic.so")
 
-EPIC_F32, EPIC_F16_MFMA, EPIC_F8E4M3_MFMA, EPIC_BF16X2_MFMA = 0, 1, 2, 3
+EPIC_F32, EPIC_F16_MFMA, EPIC_F8E4M3_MFMA, EPIC_BF16X2_MFMA, EPIC_FIXED16 = 0, 1, 2, 3, 4
+FIXED_DEFAULT = -1     # EPIC_FIXED16 stage mask / grid shift: library default
 REMOVE_AUTOS = 1
 NORMALISE = 2
 STOKES = 4             # read-out flag: I, Q, U, V planes instead of XX, YY, Re XY, Im XY
@@ -58,6 +59,9 @@ class PlanDesc(C.Structure):
         ("precision", C.c_int32),
         ("flags", C.c_uint32),
         ("sub_n", C.POINTER(C.c_int32)),
+        ("fixed_twiddle_bits", C.c_int32),
+        ("fixed_stage_shifts", C.c_int32),
+        ("fixed_grid_shift", C.c_int32),
     ]
 
 
@@ -66,6 +70,8 @@ class PlanInfo(C.Structure):
         ("image_floats", C.c_int64), ("grid_elems_per_t", C.c_int64),
         ("autos_ints", C.c_int64), ("bytes_plan", C.c_int64),
         ("bytes_acc", C.c_int64), ("n_prod", C.c_int32), ("max_grid_n", C.c_int32),
+        ("fixed_kernel_shift", C.c_int32), ("fixed_grid_shift", C.c_int32),
+        ("fixed_scale_exp2", C.c_int32), ("fixed_slices", C.c_int32),
     ]
 
 
@@ -140,7 +146,8 @@ class Plan:
 
     def __init__(self, pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5,
                  kernel_k=3, kernel_sigma=0.5, kernel_table=None, precision=EPIC_F32,
-                 sub_n=None, volt_bits=4, jones=False, stream=None):
+                 sub_n=None, volt_bits=4, jones=False, twiddle_bits=8,
+                 stage_shifts=FIXED_DEFAULT, grid_shift=FIXED_DEFAULT, stream=None):
         lib = load()
         self._pos = np.ascontiguousarray(pos, dtype=np.float64)
         self._freq = np.ascontiguousarray(freq_hz, dtype=np.float64)
@@ -170,6 +177,10 @@ class Plan:
         if volt_bits not in (4, 8):
             raise ValueError("volt_bits must be 4 or 8")
         d.flags = (VOLT_8BIT if volt_bits == 8 else 0) | (JONES if jones else 0)
+        # EPIC_FIXED16 settings (ignored by the other precisions)
+        d.fixed_twiddle_bits = int(twiddle_bits)
+        d.fixed_stage_shifts = int(stage_shifts)
+        d.fixed_grid_shift = int(grid_shift)
         self._sub = None if sub_n is None else np.ascontiguousarray(sub_n, dtype=np.int32)
         d.sub_n = None if self._sub is None else self._sub.ctypes.data_as(C.POINTER(C.c_int32))
         h = C.c_void_p()

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libepic.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["abi.hip", "plan.hip", "fused.hip", "banded.hip", "staged.hip", "readout.hip", "dftgemm.hip"]
+SOURCES = ["abi.hip", "plan.hip", "fused.hip", "banded.hip", "staged.hip", "readout.hip", "dftgemm.hip",
+           "fixed.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

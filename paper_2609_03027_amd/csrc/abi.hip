@@ -74,8 +74,29 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     const double sg = d->kernel_sigma_cells == 0.0 ? 0.5 : d->kernel_sigma_cells;
     if (!(cl > 0.0) || !std::isfinite(cl)) return fail(EPIC_ERR_ARG, "cell_lambda must be > 0");
     if (!(sg > 0.0) || !std::isfinite(sg)) return fail(EPIC_ERR_ARG, "kernel_sigma_cells must be > 0");
-    if (d->precision < EPIC_F32 || d->precision > EPIC_BF16X2_MFMA)
+    if (d->precision < EPIC_F32 || d->precision > EPIC_FIXED16)
         return fail(EPIC_ERR_ARG, "unknown precision");
+    if (d->precision == EPIC_FIXED16) {
+        const int tb = d->fixed_twiddle_bits;
+        if (tb != 0 && (tb < 2 || tb > 15))
+            return fail(EPIC_ERR_ARG, "fixed_twiddle_bits must be 0 or 2..15");
+        if (d->fixed_stage_shifts != EPIC_FIXED_DEFAULT &&
+            (d->fixed_stage_shifts < 0 || d->fixed_stage_shifts > 4095))
+            return fail(EPIC_ERR_ARG, "fixed_stage_shifts must be -1 or 0..4095");
+        if (d->fixed_grid_shift != EPIC_FIXED_DEFAULT &&
+            (d->fixed_grid_shift < 0 || d->fixed_grid_shift > 30))
+            return fail(EPIC_ERR_ARG, "fixed_grid_shift must be -1 or 0..30");
+        for (int c = 0; c < d->n_chan; ++c)
+            if (d->grid_n[c] != 64)
+                return fail(EPIC_ERR_UNSUPPORTED, "the fixed-point path runs 64 x 64 grids");
+        if (d->sub_n)
+            for (int c = 0; c < d->n_chan; ++c)
+                if (d->sub_n[c] != 0 && d->sub_n[c] != 64)
+                    return fail(EPIC_ERR_UNSUPPORTED,
+                                "the fixed-point path runs whole 64 x 64 transforms");
+        if ((size_t)d->n_ant * 8 + 64 * 65 * 8 > 160 * 1024)
+            return fail(EPIC_ERR_UNSUPPORTED, "too many elements for the fixed-point kernel's LDS");
+    }
     if (d->flags & ~(EPIC_VOLT_8BIT | EPIC_JONES)) return fail(EPIC_ERR_ARG, "unknown plan flags");
     if (d->flags & EPIC_JONES) {
         if (d->n_pol != 2) return fail(EPIC_ERR_ARG, "Jones kernels need two feeds");
@@ -121,6 +142,12 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     p->flags = d->flags;
     p->vb = (d->flags & EPIC_VOLT_8BIT) ? 2 : 1;
     p->J = (d->flags & EPIC_JONES) ? 4 : 1;
+    if (p->precision == EPIC_FIXED16) {
+        p->fixed.ts = (d->fixed_twiddle_bits ? d->fixed_twiddle_bits : 8) - 1;
+        p->fixed.mask = d->fixed_stage_shifts == EPIC_FIXED_DEFAULT ? 0xFFFu
+                                                                    : (uint32_t)d->fixed_stage_shifts;
+        p->fixed.sg = d->fixed_grid_shift;   // -1: chosen at build
+    }
     p->n_prod = p->P == 2 ? 4 : 1;
     p->pos.assign(d->ant_pos_m, d->ant_pos_m + 2 * p->A);
     p->freq.assign(d->chan_freq_hz, d->chan_freq_hz + p->C);
@@ -170,6 +197,11 @@ epic_status epic_plan_get_info(epic_plan p, epic_plan_info *info) {
                       p->work_bytes;
     info->n_prod = p->n_prod;
     info->max_grid_n = p->max_n;
+    const bool fx = p->precision == EPIC_FIXED16;
+    info->fixed_kernel_shift = fx ? p->fixed.sw : 0;
+    info->fixed_grid_shift = fx ? p->fixed.sg : 0;
+    info->fixed_scale_exp2 = fx ? p->fixed.exp2 : 0;
+    info->fixed_slices = fx ? p->fixed.slices : 0;
     return EPIC_OK;
 }
 
@@ -282,6 +314,8 @@ epic_status epic_accumulate(epic_plan p, epic_acc a, const uint8_t *d_volt, cons
         if (!st && d_volt) st = autos_accumulate(p, a, d_volt, n_time, s);
     } else if (p->precision == EPIC_F32) {
         st = fused_accumulate(p, a, d_volt, n_time, s);
+    } else if (p->precision == EPIC_FIXED16) {
+        st = fixed_accumulate(p, a, d_volt, n_time, s);
     } else {
         st = gemm_accumulate(p, a, d_volt, n_time, s);
     }
@@ -322,6 +356,7 @@ epic_status epic_graph_create(epic_plan p, epic_acc a, const uint8_t *d_volt, in
     EPIC_HIP(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
     epic_status st = EPIC_OK;
     if (p->precision == EPIC_F32) st = fused_accumulate(p, a, d_volt, n_time, nullptr, nullptr, true);
+    if (p->precision == EPIC_FIXED16) st = fixed_accumulate(p, a, d_volt, n_time, nullptr, true);
     if (st) return st;
 
     hipStream_t cs = nullptr;
@@ -352,6 +387,8 @@ epic_status epic_graph_create(epic_plan p, epic_acc a, const uint8_t *d_volt, in
     if (e == hipSuccess) {
         if (p->precision == EPIC_F32)
             st = fused_accumulate(p, a, d_volt, n_time, cs, &br, false);
+        else if (p->precision == EPIC_FIXED16)
+            st = fixed_accumulate(p, a, d_volt, n_time, cs);
         else
             st = gemm_accumulate(p, a, d_volt, n_time, cs);
     }

@@ -155,6 +155,19 @@ struct BandPlan {
     DevBuf d_entries;        // uint4 gather entries of those items
 };
 
+// Low-bitwidth path (EPIC_FIXED16): one gather item per channel (64 x 64
+// grids), integer weights in the entries, the twiddle table and settings.
+struct FixedPlan {
+    DevBuf items;       // FusedItem[n_items]
+    DevBuf entries;     // uint4 gather entries, integer weights
+    DevBuf tw;          // int2[32]: rint(2^ts exp(+2 pi i n / 64))
+    int n_items = 0;
+    int slices = 1;     // time slices per call
+    int ts = 7, sw = 0, sg = -1, exp2 = 0;
+    uint32_t mask = 0xFFFu;
+    int64_t part_bytes = 0;  // FP64 partial sums [slices][channels][n_prod][4096]
+};
+
 }  // namespace epic
 
 struct epic_plan_s {
@@ -203,6 +216,7 @@ struct epic_plan_s {
     // fused path (FP32) or direct DFT-GEMM (MFMA precisions)
     std::vector<epic::FusedGroup *> groups;
     epic::GemmPlan gemm;
+    epic::FixedPlan fixed;
     std::vector<char> banded;     // channel c takes the banded two-pass path
     epic::BandPlan band;
     int64_t work_bytes = 0;       // per-accumulator working memory the path needs
@@ -294,6 +308,13 @@ epic_status staged_accumulate(epic_plan p, epic_acc acc, const void *d_sky, int 
 epic_status gemm_build(epic_plan p, hipStream_t s);
 epic_status gemm_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                             hipStream_t s);
+
+// fixed.hip
+int fixed_kernel_shift(const std::vector<double> &w);
+epic_status fixed_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
+                        hipStream_t s);
+epic_status fixed_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                             hipStream_t s, bool dry = false);
 
 // readout.hip
 epic_status selfcorr_build(epic_plan p, hipStream_t s);

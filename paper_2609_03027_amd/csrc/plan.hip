@@ -127,6 +127,22 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     EPIC_HIP(hipMemcpyAsync(w.data(), p->d_w.p, sizeof(double) * w.size(), hipMemcpyDeviceToHost, s));
     EPIC_HIP(hipStreamSynchronize(s));
 
+    // Low-bitwidth path: the kernel becomes its 8+8-bit quantisation
+    // q = rint(W 2^sw) with one scale for the plan; every later table (the
+    // staged gather, the self terms) uses the effective weights q 2^-sw.
+    if (p->precision == EPIC_FIXED16) {
+        const int sw = fixed_kernel_shift(w);
+        bool any = false;
+        for (double v : w) any = any || v != 0.0;
+        if (!any) return fail(EPIC_ERR_ARG, "the kernel is zero everywhere");
+        const double up = std::ldexp(1.0, sw), down = std::ldexp(1.0, -sw);
+        for (double &v : w) v = std::nearbyint(v * up) * down;
+        p->fixed.sw = sw;
+        EPIC_HIP(hipMemcpyAsync(p->d_w.p, w.data(), sizeof(double) * w.size(),
+                                hipMemcpyHostToDevice, s));
+        EPIC_HIP(hipStreamSynchronize(s));
+    }
+
     // Every support must lie inside the gridded region (no wrap-around).
     for (int c = 0; c < C; ++c) {
         const int N = p->ch[c].N;
@@ -241,6 +257,9 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
         if ((st = fused_build(p, j0, w, s))) return st;
         if ((st = banded_build(p, j0, w, s))) return st;
         p->work_bytes = p->band.scratch_bytes + p->band.part_bytes;
+    } else if (p->precision == EPIC_FIXED16) {
+        if ((st = fixed_build(p, j0, w, s))) return st;
+        p->work_bytes = p->fixed.part_bytes;
     } else {
         if ((st = gemm_build(p, s))) return st;
         p->work_bytes = p->gemm.vbuf_bytes;
@@ -255,7 +274,8 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     p->bytes_plan += (int64_t)(p->band.d_chans.bytes + p->band.d_items.bytes +
                                p->band.d_entries.bytes);
     for (epic::DevBuf *b : {&p->gemm.a_hi, &p->gemm.a_lo, &p->gemm.d_blk_off,
-                            &p->gemm.d_scale, &p->gemm.d_inv_s2})
+                            &p->gemm.d_scale, &p->gemm.d_inv_s2, &p->fixed.items,
+                            &p->fixed.entries, &p->fixed.tw})
         p->bytes_plan += (int64_t)b->bytes;
     return EPIC_OK;
 }

@@ -179,3 +179,29 @@ def test_data_calls_reject_null_handles():
     assert lib.epic_acc_reset(None, None) == 1
     assert lib.epic_plan_destroy(None) == 1
     assert lib.epic_acc_destroy(None) == 1
+
+
+@pytest.mark.parametrize("over,status,word", [
+    (dict(), 4, b"64 x 64"),                                       # grid side 32
+    (dict(grid=64, fixed_twiddle_bits=16), 2, b"twiddle"),
+    (dict(grid=64, fixed_stage_shifts=4096), 2, b"stage"),
+    (dict(grid=64, fixed_grid_shift=31), 2, b"grid_shift"),
+    (dict(grid=64, sub=-1), 4, b"whole"),
+    (dict(grid=64, flags=2, n_pol=2), 1, b"table"),                # Jones needs a table first
+])
+def test_fixed_point_plans_validated_before_device_work(over, status, word):
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    h = C.c_void_p()
+    over = dict(over)
+    gn = np.array([over.pop("grid", 32)], dtype=np.int32)
+    keep = [gn]
+    if "sub" in over:
+        s = np.array([over.pop("sub")], dtype=np.int32)
+        keep.append(s)
+        over["sub_n"] = s.ctypes.data_as(C.POINTER(C.c_int32))
+    d, k2 = _desc(precision=E.EPIC_FIXED16, grid_n=gn.ctypes.data_as(C.POINTER(C.c_int32)),
+                  **over)
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == status
+    assert word in lib.epic_last_error()
+    assert not h.value
