@@ -358,6 +358,68 @@ def polarimetric(E, torch, ms_diag, reps=5):
     return res
 
 
+def low_bitwidth(E, torch, reps=5):
+    """The low-bitwidth path against FP32 on the paper's own set-up widened
+    to a band: the AAVS2-like station (256 dual-pol elements, 38 m) over 64
+    channels of 64 x 64 grids around 159 MHz, 8+8-bit voltages, a 2 x 2
+    complex kernel, 1000 samples per integration.  Both paths image the same
+    voltages with the same kernel; the SNR of the fixed-point image is taken
+    against the FP32 one (which sits within 1e-6 of the exact image)."""
+    import dataclasses
+
+    import numpy as np
+    import synth
+    base = synth.workload("aavs2")
+    C = 64
+    freq = 155e6 + (np.arange(C) + 0.5) * 125e3
+    wl = dataclasses.replace(base, chan_freq_hz=freq, grid_n=np.full(C, 64), n_time=1000)
+    pos = synth.antenna_layout(wl)
+    volt = torch.from_numpy(synth.voltages(wl, pos)).cuda()
+    rng = np.random.default_rng(78)
+    K = wl.kernel_k
+    foot = np.full((K, K), 1.0 / (K * K))
+    k = foot[None, None] * np.exp(1j * rng.uniform(0, 2 * np.pi, size=(C, wl.n_ant)))[..., None, None]
+    table = np.stack([k.real, k.imag], axis=-1).astype(np.float32)
+    samples = wl.n_time * C * wl.n_pol * wl.n_ant
+    res = {"workload": "aavs2-band: 256 dual-pol elements, 38 m, 64 x 64 grids, 64 channels "
+                       "155-163 MHz, 1000 samples, 8+8-bit voltages, K=2 complex kernel"}
+    imgs = {}
+    for name, kw in (("fp32", dict(precision=E.EPIC_F32)),
+                     ("fixed16_tw8_alt", dict(precision=E.EPIC_FIXED16, twiddle_bits=8,
+                                              stage_shifts=0x555)),
+                     ("fixed16_tw15_alt", dict(precision=E.EPIC_FIXED16, twiddle_bits=15,
+                                               stage_shifts=0x555))):
+        plan = E.Plan.from_workload(wl, pos, kernel_table=table, **kw)
+        acc = E.Accumulator(plan)
+        E.accumulate(plan, acc, volt=volt)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            E.accumulate(plan, acc, volt=volt)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        acc.reset()
+        E.accumulate(plan, acc, volt=volt)
+        img = torch.empty(plan.info["image_floats"], dtype=torch.float32, device="cuda")
+        E.readout(plan, acc, img, E.NORMALISE)
+        torch.cuda.synchronize()
+        imgs[name] = img.double()
+        res[name] = {"ms_per_integration": ms, "samples_per_s": samples / (ms / 1e3)}
+        acc.close()
+        plan.close()
+    ref = imgs["fp32"]
+    for name in ("fixed16_tw8_alt", "fixed16_tw15_alt"):
+        err = imgs[name] - ref
+        res[name]["snr_db_vs_fp32"] = float(10 * torch.log10((ref ** 2).sum() / (err ** 2).sum()))
+        res[name]["speedup_vs_fp32"] = res["fp32"]["ms_per_integration"] / res[name]["ms_per_integration"]
+        log(f"low bitwidth {name}: {res[name]['ms_per_integration']:.2f} ms per integration "
+            f"({res[name]['speedup_vs_fp32']:.2f} x FP32 at {res['fp32']['ms_per_integration']:.2f} ms), "
+            f"SNR {res[name]['snr_db_vs_fp32']:.1f} dB")
+    return res
+
+
 def wide_field(E, torch, reps=3):
     """Wide-field large array: ~20 000 dual-pol elements in a 700 m disc, one
     781.25 kHz coarse channel at 100 MHz, 512 x 512 grid, 781 samples (1 ms
@@ -507,6 +569,8 @@ def main():
                     help="time high-cadence 4-sample frames (0 = skip)")
     ap.add_argument("--jones", type=int, default=1,
                     help="time the LWA step with full polarimetric (Jones) kernels (0 = skip)")
+    ap.add_argument("--fixed", type=int, default=1,
+                    help="time the low-bitwidth (16-bit fixed-point) path against FP32 (0 = skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB for a plain device copy (counter calibration runs)")
     args = ap.parse_args()
@@ -698,6 +762,8 @@ def main():
         out["high_cadence"] = high_cadence(E, torch)
     if args.jones:
         out["polarimetric"] = polarimetric(E, torch, out["roofline"]["kernel_ms"])
+    if args.fixed:
+        out["low_bitwidth"] = low_bitwidth(E, torch)
 
     if args.stream_blocks > 0:
         out["streaming"] = {}
