@@ -498,9 +498,9 @@ def large_stream(E, torch, reps=3):
     volt = torch.from_numpy(synth.voltages(wl, pos)).cuda()
     tgen = time.perf_counter() - t0
 
-    def timed(sub_n):
+    def timed(sub_n, precision=E.EPIC_F32, images=None):
         t0 = time.perf_counter()
-        plan = E.Plan.from_workload(wl, pos, sub_n=sub_n)
+        plan = E.Plan.from_workload(wl, pos, sub_n=sub_n, precision=precision)
         tplan = time.perf_counter() - t0
         acc = E.Accumulator(plan)
         E.accumulate(plan, acc, volt=volt)
@@ -513,12 +513,33 @@ def large_stream(E, torch, reps=3):
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / reps
         info = dict(plan.info)
+        if images is not None:
+            acc.reset()
+            E.accumulate(plan, acc, volt=volt)
+            img = torch.empty(plan.info["image_floats"], dtype=torch.float32, device="cuda")
+            E.readout(plan, acc, img, E.NORMALISE)
+            torch.cuda.synchronize()
+            images.append(img)
         acc.close()
         plan.close()
         return ms, tplan, info
 
-    ms, tplan, info = timed(None)
+    imgs = []
+    ms, tplan, info = timed(None, images=imgs)
     ms_fused, _, _ = timed([64] * wl.n_chan)
+    # FP16 four-step MFMA transform on the same block (banded path, FP16
+    # scratch); executed MFMA flops: 8 MFMAs of 16x16x16 per line and feed,
+    # over the footprint rows (row pass) and all 256 columns (column pass)
+    ms_f16, tplan16, _ = timed(None, precision=E.EPIC_F16_MFMA, images=imgs)
+    spans = _row_spans(wl, pos)
+    mf_flops = wl.n_time * sum(min(256, r) + 256 for r in spans) * wl.n_pol * 8 * 2 * 16 ** 3
+    ref, f16 = imgs[0].double(), imgs[1].double()
+    n2 = 256 * 256
+    err = 0.0
+    for c in range(wl.n_chan):
+        o = c * 4 * n2
+        co = ref[o:o + 2 * n2].abs().max()
+        err = max(err, float((f16[o:o + 4 * n2] - ref[o:o + 4 * n2]).abs().max() / co))
     block_ms = wl.n_time / 250e3 * 1e3
     # row transforms through HBM: written once and read once per sample
     # and channel, plus one read-modify-write of the sums per round
@@ -539,11 +560,22 @@ def large_stream(E, torch, reps=3):
            "hbm_copy_GBps": copy_gbs,
            "hbm_fill_GBps": fill_gbs,
            "plan_s": tplan, "plan_bytes": info["bytes_plan"], "acc_bytes": info["bytes_acc"],
-           "gen_s": tgen}
+           "gen_s": tgen,
+           "fp16_fourstep": {"ms_per_block": ms_f16, "speedup_vs_fp32": ms / ms_f16,
+                             "real_time_fraction_one_stream": block_ms / ms_f16,
+                             "mfma_tflops": mf_flops / (ms_f16 / 1e3) / 1e12,
+                             "mfma_frac": mf_flops / (ms_f16 / 1e3) / 1e12 / 2500.0,
+                             "hbm_bytes_per_block": scratch // 2 + sums,
+                             "hbm_GBps": (scratch // 2 + sums) / (ms_f16 / 1e3) / 1e9,
+                             "max_err_vs_fp32": err, "plan_s": tplan16}}
     log(f"large stream: {ms:.2f} ms per {block_ms:.3f} ms block "
         f"({block_ms / ms:.2f} of real time; fused 64x64 {ms_fused:.2f} ms), plan {tplan:.1f} s; "
         f"scratch + sums {res['hbm_GBps']:.0f} GB/s, device copy {copy_gbs:.0f} GB/s, "
         f"fill {fill_gbs:.0f} GB/s")
+    r16 = res["fp16_fourstep"]
+    log(f"large stream fp16 four-step MFMA: {ms_f16:.2f} ms per block ({ms / ms_f16:.2f} x FP32), "
+        f"{r16['mfma_tflops']:.0f} TFLOP/s MFMA ({r16['mfma_frac']:.1%}), "
+        f"{r16['hbm_GBps']:.0f} GB/s scratch + sums, max error vs FP32 {err:.1e}")
     return res
 
 

@@ -312,7 +312,7 @@ epic_status epic_accumulate(epic_plan p, epic_acc a, const uint8_t *d_volt, cons
     if (d_sky) {
         st = staged_accumulate(p, a, d_sky, n_time, s);
         if (!st && d_volt) st = autos_accumulate(p, a, d_volt, n_time, s);
-    } else if (p->precision == EPIC_F32) {
+    } else if (p->precision == EPIC_F32 || p->band_only()) {
         st = fused_accumulate(p, a, d_volt, n_time, s);
     } else if (p->precision == EPIC_FIXED16) {
         st = fixed_accumulate(p, a, d_volt, n_time, s);
@@ -355,7 +355,8 @@ epic_status epic_graph_create(epic_plan p, epic_acc a, const uint8_t *d_volt, in
     if (n_time < 1) return fail(EPIC_ERR_ARG, "n_time must be >= 1");
     EPIC_HIP(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
     epic_status st = EPIC_OK;
-    if (p->precision == EPIC_F32) st = fused_accumulate(p, a, d_volt, n_time, nullptr, nullptr, true);
+    if (p->precision == EPIC_F32 || p->band_only())
+        st = fused_accumulate(p, a, d_volt, n_time, nullptr, nullptr, true);
     if (p->precision == EPIC_FIXED16) st = fixed_accumulate(p, a, d_volt, n_time, nullptr, true);
     if (st) return st;
 
@@ -385,7 +386,7 @@ epic_status epic_graph_create(epic_plan p, epic_acc a, const uint8_t *d_volt, in
     e = hipEventRecord(ev[0], cs);
     for (size_t i = 0; e == hipSuccess && i < br.size(); ++i) e = hipStreamWaitEvent(br[i], ev[0], 0);
     if (e == hipSuccess) {
-        if (p->precision == EPIC_F32)
+        if (p->precision == EPIC_F32 || p->band_only())
             st = fused_accumulate(p, a, d_volt, n_time, cs, &br, false);
         else if (p->precision == EPIC_FIXED16)
             st = fixed_accumulate(p, a, d_volt, n_time, cs);

@@ -23,6 +23,7 @@
 // centred sum by (-1)^(kx+ky) times a unit constant, common to both feeds,
 // so every Eq. 2 product is unchanged and pixels keep their natural index.
 #include <algorithm>
+#include <cmath>
 
 #include "internal.h"
 
@@ -682,6 +683,269 @@ __global__ __launch_bounds__(256) void k_band_reduce(const BandChan *__restrict_
     acc[chans[blockIdx.y].img_off + i] += sum;
 }
 
+// ------------------------------------------ FP16 four-step MFMA, N = 256
+// Precision EPIC_F16_MFMA on 256 x 256 banded channels: each 256-point line
+// transform is the four-step split 256 = 16 x 16 (x[16 n1 + n2] ->
+// X[k1 + 16 k2]) with both 16-point DFT steps on the matrix cores
+// (v_mfma_f32_16x16x16_f16, FP16 operands, FP32 accumulation), one wave per
+// line, and the row transforms stored to the scratch in FP16.  Written
+// transposed, the two steps chain in registers:
+//   step 1: D1 = X^T F     (A = X^T: lane holds x[16 (4g + j) + a],
+//                           B = F:   lane holds F[a][4g + j]),
+//           so lane (a, g) ends with Y[k1 = a][n2 = 4g + i], i = 0..3;
+//   twiddle: Y'[k1][n2] = Y[k1][n2] exp(+2 pi i k1 n2 / 256)   (FP32);
+//   step 2: D2 = F Y'^T   (A = F, the same registers; B = Y'^T, which is
+//                           exactly the lane's step-1 result),
+//           so lane (a, g) ends with X[a + 16 (4g + i)],
+// with a = lane % 16, g = lane / 16 and F[a][b] = exp(+2 pi i a b / 16)
+// (symmetric).  Complex products take four real MFMAs (Re = Ar Br - Ai Bi,
+// Im = Ar Bi + Ai Br).  Every FP16 rounding point is preceded by an exact
+// power-of-two scale: the gridded values by 2^-si (so their bound fits
+// FP16), each 16-point step's output by 1/16 (so no stage can grow past its
+// input bound); the column pass's products are multiplied back by
+// 2^(24 + 2 si).
+typedef _Float16 mf_h4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+struct MfConst {
+    mf_h4 fr, fi, nfi;   // F[a][4g + j]: real, imaginary, minus imaginary
+    float2 tw[4];        // exp(+2 pi i a (4g + i) / 256) / 16
+};
+
+__device__ __forceinline__ MfConst mf_consts(int lane) {
+    MfConst k;
+    const int a = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double sn, cs;
+        sincospi(2.0 * (double)((a * (4 * g + j)) & 15) / 16.0, &sn, &cs);
+        k.fr[j] = (_Float16)(float)cs;
+        k.fi[j] = (_Float16)(float)sn;
+        k.nfi[j] = (_Float16)(float)-sn;
+        sincospi(2.0 * (double)(a * (4 * g + j)) / 256.0, &sn, &cs);
+        k.tw[j] = make_float2((float)cs * 0.0625f, (float)sn * 0.0625f);
+    }
+    return k;
+}
+
+__device__ __forceinline__ mf_f4 mfma16(mf_h4 a, mf_h4 b, mf_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// One 256-point line transform of one feed: (xr, xi) = the lane's step-1 A
+// operand, x[16 (4g + j) + a]; returns X[a + 16 (4g + i)] in (er, ei).
+__device__ __forceinline__ void mf_line(const MfConst &k, mf_h4 xr, mf_h4 xi, mf_f4 &er,
+                                        mf_f4 &ei) {
+    const mf_f4 z = {0.f, 0.f, 0.f, 0.f};
+    mf_f4 dr = mfma16(xr, k.fr, z);
+    dr = mfma16(xi, k.nfi, dr);
+    mf_f4 di = mfma16(xr, k.fi, z);
+    di = mfma16(xi, k.fr, di);
+    mf_h4 br, bi;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float2 w = k.tw[i];
+        br[i] = (_Float16)(dr[i] * w.x - di[i] * w.y);
+        bi[i] = (_Float16)(dr[i] * w.y + di[i] * w.x);
+    }
+    er = mfma16(k.fr, br, z);
+    er = mfma16(k.nfi, bi, er);
+    ei = mfma16(k.fr, bi, z);
+    ei = mfma16(k.fi, br, ei);
+}
+
+// FP16 scratch cell: both feeds, (x re, x im), (y re, y im) as half pairs.
+__device__ __forceinline__ uint32_t h2bits(float a, float b) {
+    const _Float16 ha = (_Float16)a, hb = (_Float16)b;
+    return (uint32_t)__builtin_bit_cast(uint16_t, ha) |
+           ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+}
+__device__ __forceinline__ _Float16 h_lo(uint32_t v) {
+    return __builtin_bit_cast(_Float16, (uint16_t)(v & 0xffffu));
+}
+__device__ __forceinline__ _Float16 h_hi(uint32_t v) {
+    return __builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
+}
+
+// Pass 1, FP16 four-step.  Same items, gather and launch shape as
+// k_band_rows_pw<16, 2, P> (128 threads, 8-row bands); then wave w
+// transforms rows w, w + 2, ... of the band and writes them to the scratch
+// as FP16 cells (uint2 per cell, cell index as in the FP32 scratch).
+template <int P>
+__global__ __launch_bounds__(128) void k_band_rows_mf(
+    const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
+    const BandItem *__restrict__ items, int n_items, int G, int nt, int64_t per_xcd,
+    const uint4 *__restrict__ entries, int A, uint2 *__restrict__ scratch, int64_t scratch_t,
+    int vb, float in_scale) {
+    constexpr int N = 256, T = 128, UN = 16;
+    extern __shared__ float4 lds[];   // BL * N cells + the spare slot
+    const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (w >= (int64_t)n_items * nt) return;
+    const int64_t blk = w / ((int64_t)G * nt), rem = w % ((int64_t)G * nt);
+    const int t = (int)(rem / G);
+    const BandItem it = items[blk * G + rem % G];
+    if (it.n_iter < 0) return;
+    const BandChan ch = chans[it.chan];
+    const int tid = threadIdx.x;
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = tid; i <= BL * N; i += T) lds[i] = zero;
+    __syncthreads();
+    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * vb;
+    const uint4 *ent = entries + it.entry_off;
+    float4 s = zero;
+    for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
+        uint4 e[UN];
+#pragma unroll
+        for (int k = 0; k < UN; ++k)
+            e[k] = ent[(uint32_t)(min(i0 + k, it.n_iter - 1) * T + tid)];
+#pragma unroll
+        for (int k = 0; k < UN; ++k)
+            if (i0 + k >= it.n_iter) e[k] = make_uint4(0u, (uint32_t)(BL * N), 0u, 0u);
+        uint32_t bx[UN], by[UN];
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+            const uint32_t a = e[k].x & 0x7fffffffu;
+            bx[k] = volt_raw(vx, a, vb);
+            by[k] = P == 2 ? volt_raw(vx, A + a, vb) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+            const float wr = __builtin_bit_cast(float, e[k].z);
+            const float wi = __builtin_bit_cast(float, e[k].w);
+            const int2 x = volt_dec(bx[k], vb);
+            const float xr = (float)x.x, xi = (float)x.y;
+            s.x += wr * xr - wi * xi;
+            s.y += wr * xi + wi * xr;
+            if (P == 2) {
+                const int2 y = volt_dec(by[k], vb);
+                const float yr = (float)y.x, yi = (float)y.y;
+                s.z += wr * yr - wi * yi;
+                s.w += wr * yi + wi * yr;
+            }
+            lds[e[k].y] = s;
+            if (e[k].x & 0x80000000u) s = zero;
+        }
+    }
+    __syncthreads();
+    const int lane = tid & 63, wv = tid >> 6;
+    const int a = lane & 15, g = lane >> 4;
+    const MfConst k = mf_consts(lane);
+    for (int l = wv; l < BL; l += 2) {
+        const int row = ch.row_lo + it.band * BL + l;
+        if (row > ch.row_hi) break;
+        mf_h4 xr, xi, yr, yi;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float4 v = lds[l * N + 16 * (4 * g + j) + a];
+            xr[j] = (_Float16)(v.x * in_scale);
+            xi[j] = (_Float16)(v.y * in_scale);
+            yr[j] = (_Float16)(v.z * in_scale);
+            yi[j] = (_Float16)(v.w * in_scale);
+        }
+        mf_f4 er, ei, fr2, fi2;
+        mf_line(k, xr, xi, er, ei);
+        if (P == 2) mf_line(k, yr, yi, fr2, fi2);
+        uint2 *out = scratch + (int64_t)t * scratch_t + ch.scratch_off +
+                     (int64_t)(row - ch.row_lo) * N + a;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t hx = h2bits(er[i] * 0.0625f, ei[i] * 0.0625f);
+            const uint32_t hy = P == 2 ? h2bits(fr2[i] * 0.0625f, fi2[i] * 0.0625f) : 0u;
+            out[16 * (4 * g + i)] = make_uint2(hx, hy);
+        }
+    }
+}
+
+// Pass 2, FP16 four-step.  Grid and slices as k_band_cols_pw<16, 2, P>:
+// 16 columns per workgroup of 256 threads.  Per sample the workgroup loads
+// the 16-column strip of every footprint row (coalesced 128-byte row
+// segments) into LDS, column-major; wave w then transforms columns w,
+// w + 4, w + 8, w + 12 and keeps the Eq. 2 products of its pixels
+// (a + 16 (4g + i), c0 + col) in registers.
+constexpr int MF_BC = 16, MF_LP = 256 + 2;
+
+template <int P>
+__global__ __launch_bounds__(256) void k_band_cols_mf(
+    const BandChan *__restrict__ chans, const uint2 *__restrict__ scratch, int64_t scratch_t,
+    int nt, float *__restrict__ acc, float *__restrict__ part, int64_t part_stride,
+    float out_scale) {
+    constexpr int N = 256, T = 256;
+    constexpr int NPROD = P == 2 ? 4 : 1;
+    extern __shared__ uint2 tile[];   // [MF_BC][MF_LP]
+    const BandChan ch = chans[blockIdx.y];
+    const int S = gridDim.z, slice = blockIdx.z;
+    const int c0 = blockIdx.x * MF_BC;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int a = lane & 15, g = lane >> 4;
+    const MfConst k = mf_consts(lane);
+    float av[4][4][NPROD];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < NPROD; ++q) av[c][i][q] = 0.f;
+    const uint2 *base = scratch + ch.scratch_off + c0;
+    for (int t = slice; t < nt; t += S) {
+        const uint2 *src = base + (int64_t)t * scratch_t;
+        // 256 rows x 8 column pairs; rows outside the footprint span are zero
+#pragma unroll
+        for (int r8 = 0; r8 < 8; ++r8) {
+            const int i = tid + r8 * T;
+            const int row = i >> 3, cp = i & 7;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (row >= ch.row_lo && row <= ch.row_hi)
+                v = *reinterpret_cast<const uint4 *>(src + (int64_t)(row - ch.row_lo) * N + 2 * cp);
+            tile[(2 * cp) * MF_LP + row] = make_uint2(v.x, v.y);
+            tile[(2 * cp + 1) * MF_LP + row] = make_uint2(v.z, v.w);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int col = wv + 4 * c;
+            mf_h4 xr, xi, yr, yi;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint2 v = tile[col * MF_LP + 16 * (4 * g + j) + a];
+                xr[j] = h_lo(v.x);
+                xi[j] = h_hi(v.x);
+                yr[j] = h_lo(v.y);
+                yi[j] = h_hi(v.y);
+            }
+            mf_f4 er, ei, fr2, fi2;
+            mf_line(k, xr, xi, er, ei);
+            if (P == 2) mf_line(k, yr, yi, fr2, fi2);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                av[c][i][0] += er[i] * er[i] + ei[i] * ei[i];
+                if (P == 2) {
+                    av[c][i][1] += fr2[i] * fr2[i] + fi2[i] * fi2[i];
+                    av[c][i][2] += er[i] * fr2[i] + ei[i] * fi2[i];
+                    av[c][i][3] += ei[i] * fr2[i] - er[i] * fi2[i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t plane = (int64_t)N * N;
+    float *dst0 = S == 1 ? acc + ch.img_off
+                         : part + slice * part_stride + (int64_t)blockIdx.y * NPROD * plane;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float *dst = dst0 + (int64_t)(a + 16 * (4 * g + i)) * N + c0 + wv + 4 * c;
+#pragma unroll
+            for (int q = 0; q < NPROD; ++q) {
+                const float v = av[c][i][q] * out_scale;
+                if (S == 1)
+                    dst[q * plane] += v;
+                else
+                    dst[q * plane] = v;
+            }
+        }
+}
+
 static int pw_radix(int N, int *np) {
     *np = N == 512 ? 3 : 2;
     return N == 256 ? 16 : (N == 64 || N == 512) ? 8 : 0;
@@ -802,6 +1066,31 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
     }
     bp.n = (int)bp.host.size();
     bp.scratch_t = off;
+    if (p->precision == EPIC_F16_MFMA) {
+        // FP16 operands: bound every gridded cell's modulus by
+        // sum over its taps of |W| |E|max, and scale it to at most 2^15
+        const double emax = (p->vb == 2 ? 128.0 : 8.0) * std::sqrt(2.0);
+        double bmax = 0.0;
+        for (const BandChan &b : bp.host) {
+            std::vector<double> cell((size_t)b.N * b.N, 0.0);
+            for (int a = 0; a < p->A; ++a) {
+                const int jx0 = j0[((size_t)b.c * p->A + a) * 2];
+                const int jy0 = j0[((size_t)b.c * p->A + a) * 2 + 1];
+                for (int dy = 0; dy < p->K; ++dy)
+                    for (int dx = 0; dx < p->K; ++dx) {
+                        const size_t wi =
+                            (((size_t)b.c * p->A + a) * p->K * p->K + dy * p->K + dx) * 2;
+                        cell[(size_t)(jy0 + dy) * b.N + jx0 + dx] +=
+                            std::hypot(w[wi], w[wi + 1]) * emax;
+                    }
+            }
+            for (double v : cell) bmax = std::max(bmax, v);
+        }
+        int si = 0;
+        while (bmax * std::ldexp(1.0, -si) > 32768.0) ++si;
+        bp.mf_in = (float)std::ldexp(1.0, -si);
+        bp.mf_out = (float)std::ldexp(1.0, 24 + 2 * si);
+    }
     // samples per round: each of the two scratch halves near 1 GiB
     const int64_t per_t = off * (int64_t)sizeof(float4);
     bp.t_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (1LL << 30) / per_t));
@@ -904,10 +1193,60 @@ static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const ui
     return EPIC_OK;
 }
 
+constexpr size_t kRowsMfLds = sizeof(float4) * (BL * 256 + 1);
+constexpr size_t kColsMfLds = sizeof(uint2) * MF_BC * MF_LP;
+
+static epic_status ready_mf(int P) {
+    epic_status st = lds_ready(P == 2 ? reinterpret_cast<const void *>(k_band_rows_mf<2>)
+                                      : reinterpret_cast<const void *>(k_band_rows_mf<1>),
+                               kRowsMfLds);
+    if (!st)
+        st = lds_ready(P == 2 ? reinterpret_cast<const void *>(k_band_cols_mf<2>)
+                              : reinterpret_cast<const void *>(k_band_cols_mf<1>),
+                       kColsMfLds);
+    return st;
+}
+
+// FP16 four-step MFMA passes (256 x 256 channels of EPIC_F16_MFMA plans):
+// same grids and items as launch_pw<16, 2, P>; the scratch holds FP16 cells.
+template <int P>
+static epic_status launch_mf(epic_plan p, const BandSize &bs, int pass, const uint8_t *d_volt,
+                             int nt, float4 *scratch, float *part, float *acc, hipStream_t s) {
+    const BandPlan &bp = p->band;
+    const BandChan *chans = bp.d_chans.as<BandChan>() + bs.chan_off;
+    uint2 *sc = reinterpret_cast<uint2 *>(scratch);
+    if (pass == 0) {
+        const int64_t total = bs.n_items * nt;
+        const int64_t per_xcd = (total + 7) / 8;
+        if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
+        hipLaunchKernelGGL(k_band_rows_mf<P>, dim3((unsigned)(8 * per_xcd)), dim3(128),
+                           kRowsMfLds, s, d_volt, p->vstride(), chans,
+                           bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, bs.G, nt,
+                           per_xcd, bp.d_entries.as<uint4>(), p->A, sc, bp.scratch_t, p->vb,
+                           bp.mf_in);
+        EPIC_HIP(hipGetLastError());
+        return EPIC_OK;
+    }
+    const int S = bs.slices;
+    float *pp = S > 1 ? part + bs.part_off : nullptr;
+    hipLaunchKernelGGL(k_band_cols_mf<P>, dim3(bs.N / MF_BC, bs.n, S), dim3(256), kColsMfLds, s,
+                       chans, sc, bp.scratch_t, nt, acc, pp, bs.part_stride, bp.mf_out);
+    EPIC_HIP(hipGetLastError());
+    if (S > 1) {
+        const int n_floats = p->n_prod * bs.N * bs.N;
+        hipLaunchKernelGGL(k_band_reduce, dim3((n_floats + 255) / 256, bs.n), dim3(256), 0, s,
+                           chans, n_floats, S, pp, bs.part_stride, acc);
+        EPIC_HIP(hipGetLastError());
+    }
+    return EPIC_OK;
+}
+
 template <int P>
 static epic_status launch_pw_any(epic_plan p, const BandSize &bs, int pass,
                                  const uint8_t *d_volt, int nt, float4 *scratch, float *part,
                                  float *acc, const FrameOut &fo, hipStream_t s) {
+    if (p->precision == EPIC_F16_MFMA)
+        return launch_mf<P>(p, bs, pass, d_volt, nt, scratch, part, acc, s);
     if (bs.R == 16) return launch_pw<16, 2, P>(p, bs, pass, d_volt, nt, scratch, part, acc, fo, s);
     if (bs.R == 8 && bs.NP == 2)
         return launch_pw<8, 2, P>(p, bs, pass, d_volt, nt, scratch, part, acc, fo, s);
@@ -974,7 +1313,9 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
     }
     for (const BandSize &bs : bp.sizes) {
         epic_status st = EPIC_OK;
-        if (bs.R == 16) {
+        if (p->precision == EPIC_F16_MFMA) {
+            st = ready_mf(p->P);
+        } else if (bs.R == 16) {
             st = ready_pw<16, 2>(p->P);
         } else if (bs.R == 8 && bs.NP == 2) {
             st = ready_pw<8, 2>(p->P);

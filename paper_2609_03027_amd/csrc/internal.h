@@ -153,6 +153,9 @@ struct BandPlan {
     DevBuf d_chans;          // BandChan[n]
     DevBuf d_items;          // BandItem[] of the square-radix sizes
     DevBuf d_entries;        // uint4 gather entries of those items
+    // EPIC_F16_MFMA plans (256 x 256, FP16 four-step): exact power-of-two
+    // scale of the gridded values into FP16, and of the products back
+    float mf_in = 1.0f, mf_out = 1.0f;
 };
 
 // Low-bitwidth path (EPIC_FIXED16): one gather item per channel (64 x 64
@@ -221,6 +224,13 @@ struct epic_plan_s {
     epic::BandPlan band;
     int64_t work_bytes = 0;       // per-accumulator working memory the path needs
     int64_t vstride() const { return (int64_t)C * P * A * vb; }  // bytes per time sample
+    // an FP16 plan whose channels all take the banded four-step transform
+    bool band_only() const {
+        if (precision != EPIC_F16_MFMA || banded.empty()) return false;
+        for (char b : banded)
+            if (!b) return false;
+        return true;
+    }
 
     int64_t bytes_plan = 0;
     ~epic_plan_s();

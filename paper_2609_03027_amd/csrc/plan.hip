@@ -75,13 +75,20 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
         // Banded two-pass path: on request, or by default where the fused
         // path would split the channel into 16 or more sub-transforms (not
         // with Jones kernels, which only the fused and staged gathers take).
-        if (p->precision == EPIC_F32 && p->J == 1 &&
+        // FP16 plans send 256 x 256 channels to the banded path's four-step
+        // MFMA transform.
+        if (p->precision == EPIC_F16_MFMA && N == 256 && want <= 0) {
+            p->banded[c] = 1;
+            M = 0;
+        } else if (p->precision == EPIC_F32 && p->J == 1 &&
             (want < 0 || (want == 0 && M && N / M >= 4 && banded_eligible(N)))) {
             if (!banded_eligible(N))
                 return fail(EPIC_ERR_UNSUPPORTED, "banded path: grid side must be a multiple "
                                                   "of 32 with factors 2 and 3, at most 512");
             p->banded[c] = 1;
             M = 0;
+        } else if (want < 0 && p->precision == EPIC_F16_MFMA) {
+            return fail(EPIC_ERR_UNSUPPORTED, "the FP16 banded path runs 256 x 256 grids");
         } else if (want < 0) {
             return fail(EPIC_ERR_UNSUPPORTED, p->J > 1 ? "the banded path does not take Jones kernels"
                                                        : "banded path needs FP32 precision");
@@ -98,6 +105,14 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     }
     p->image_floats = io;
     p->grid_elems_per_t = go;
+    if (p->precision == EPIC_F16_MFMA) {
+        int nb = 0;
+        for (int c = 0; c < C; ++c) nb += p->banded[c];
+        if (nb && nb != C)
+            return fail(EPIC_ERR_UNSUPPORTED,
+                        "an FP16 plan takes one path for all channels: the four-step banded "
+                        "transform for 256 x 256 grids, the DFT-GEMM otherwise");
+    }
 
     epic_status st;
     if ((st = p->d_pos.alloc(sizeof(double) * 2 * A))) return st;
@@ -253,7 +268,7 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
 
     if (J == 1 && (st = selfcorr_build(p, s))) return st;
     p->w_host = w;
-    if (p->precision == EPIC_F32) {
+    if (p->precision == EPIC_F32 || p->band_only()) {
         if ((st = fused_build(p, j0, w, s))) return st;
         if ((st = banded_build(p, j0, w, s))) return st;
         p->work_bytes = p->band.scratch_bytes + p->band.part_bytes;

@@ -1,0 +1,42 @@
+"""FP16 four-step MFMA transform on 256 x 256 channels (precision
+EPIC_F16_MFMA, banded path): the 4096-element streaming array and a small
+array on a 256^2 grid, 4- and 8-bit voltages, several calls, against the
+FP64 oracle to the stated FP16 four-step bound."""
+import dataclasses
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import oracle_images
+from test_gpu_parity import _check, _run, _say
+
+pytestmark = pytest.mark.gpu
+
+TOL = json.load(open(os.path.join(os.path.dirname(__file__), "tolerances.json")))["fp16_fourstep"]
+
+
+def test_stream_array_fp16_fourstep_matches_oracle():
+    full = synth.workload("stream")
+    chans = [63]
+    _say("case fp16 four-step: stream array, 4096 elements, 256^2, channel 63, 3 samples")
+    wl = full.subset(chans).with_time(3)
+    pos = synth.antenna_layout(full)
+    volt = synth.voltages(full.with_time(3), pos, chans=chans)
+    got = _run(wl, pos, volt, precision=1)
+    _check(got, oracle_images(volt, pos, wl, range(1)), "fp16-4step-stream", TOL["max"],
+           TOL["rms"])
+
+
+@pytest.mark.parametrize("bits", [4, 8])
+def test_small_array_256_grid_fp16_fourstep_in_calls(bits):
+    wl = dataclasses.replace(synth.workload("tiny2"), grid_n=np.array([256]), n_time=24,
+                             volt_bits=bits)
+    pos = synth.antenna_layout(wl)
+    volt = synth.voltages(wl, pos)
+    _say(f"case fp16 four-step: 16 elements on 256^2, {bits}-bit, 24 samples in 3 calls")
+    ref = oracle_images(volt, pos, wl, [0])
+    _check(_run(wl, pos, volt, precision=1, chunks=3), ref, f"fp16-4step-{bits}bit",
+           TOL["max"], TOL["rms"])
