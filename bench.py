@@ -545,8 +545,11 @@ def large_stream(E, torch, reps=3):
     # and channel, plus one read-modify-write of the sums per round
     rows = sum(min(256, r) for r in _row_spans(wl, pos))
     scratch = 2 * wl.n_time * rows * 256 * 16
-    rounds = -(-wl.n_time // max(1, (1 << 30) // (rows * 256 * 16)))
+    rounds = -(-wl.n_time // max(1, (8 << 30) // (rows * 256 * 16)))
     sums = rounds * 2 * wl.n_chan * 4 * 256 * 256 * 4
+    # FP16 four-step: 8-byte cells, so twice the samples per round
+    rounds16 = -(-wl.n_time // max(1, (8 << 30) // (rows * 256 * 8)))
+    sums16 = rounds16 * 2 * wl.n_chan * 4 * 256 * 256 * 4
     copy_gbs = copy_bandwidth(torch)
     fill_gbs = fill_bandwidth(torch)
     res = {"workload": "stream-large: 4096 dual-pol elements, 300 m disc, 64 channels "
@@ -565,8 +568,8 @@ def large_stream(E, torch, reps=3):
                              "real_time_fraction_one_stream": block_ms / ms_f16,
                              "mfma_tflops": mf_flops / (ms_f16 / 1e3) / 1e12,
                              "mfma_frac": mf_flops / (ms_f16 / 1e3) / 1e12 / 2500.0,
-                             "hbm_bytes_per_block": scratch // 2 + sums,
-                             "hbm_GBps": (scratch // 2 + sums) / (ms_f16 / 1e3) / 1e9,
+                             "hbm_bytes_per_block": scratch // 2 + sums16,
+                             "hbm_GBps": (scratch // 2 + sums16) / (ms_f16 / 1e3) / 1e9,
                              "max_err_vs_fp32": err, "plan_s": tplan16}}
     log(f"large stream: {ms:.2f} ms per {block_ms:.3f} ms block "
         f"({block_ms / ms:.2f} of real time; fused 64x64 {ms_fused:.2f} ms), plan {tplan:.1f} s; "

@@ -712,20 +712,9 @@ struct MfConst {
     float2 tw[4];        // exp(+2 pi i a (4g + i) / 256) / 16
 };
 
-__device__ __forceinline__ MfConst mf_consts(int lane) {
-    MfConst k;
-    const int a = lane & 15, g = lane >> 4;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        double sn, cs;
-        sincospi(2.0 * (double)((a * (4 * g + j)) & 15) / 16.0, &sn, &cs);
-        k.fr[j] = (_Float16)(float)cs;
-        k.fi[j] = (_Float16)(float)sn;
-        k.nfi[j] = (_Float16)(float)-sn;
-        sincospi(2.0 * (double)(a * (4 * g + j)) / 256.0, &sn, &cs);
-        k.tw[j] = make_float2((float)cs * 0.0625f, (float)sn * 0.0625f);
-    }
-    return k;
+// Per-lane constants, from the plan's 64-entry table (built on the host).
+__device__ __forceinline__ MfConst mf_consts(const MfConst *__restrict__ tab, int lane) {
+    return tab[lane];
 }
 
 __device__ __forceinline__ mf_f4 mfma16(mf_h4 a, mf_h4 b, mf_f4 c) {
@@ -768,17 +757,21 @@ __device__ __forceinline__ _Float16 h_hi(uint32_t v) {
 }
 
 // Pass 1, FP16 four-step.  Same items, gather and launch shape as
-// k_band_rows_pw<16, 2, P> (128 threads, 8-row bands); then wave w
-// transforms rows w, w + 2, ... of the band and writes them to the scratch
-// as FP16 cells (uint2 per cell, cell index as in the FP32 scratch).
+// k_band_rows_pw<16, 2, P> (128 threads, 8-row bands), but the band is kept
+// in LDS as FP16 cells: each running FP32 cell sum is scaled and rounded at
+// its store (the last store of a cell leaves fl16(2^-si x the full sum),
+// exactly the step-1 operand), which halves the LDS per workgroup and
+// doubles the workgroups a CU holds.  Wave w then transforms rows w, w + 2,
+// ... of the band and writes them to the scratch as FP16 cells (uint2 per
+// cell, cell index as in the FP32 scratch).
 template <int P>
 __global__ __launch_bounds__(128) void k_band_rows_mf(
     const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
     const BandItem *__restrict__ items, int n_items, int G, int nt, int64_t per_xcd,
     const uint4 *__restrict__ entries, int A, uint2 *__restrict__ scratch, int64_t scratch_t,
-    int vb, float in_scale) {
+    int vb, float in_scale, const MfConst *__restrict__ mfc) {
     constexpr int N = 256, T = 128, UN = 16;
-    extern __shared__ float4 lds[];   // BL * N cells + the spare slot
+    extern __shared__ uint2 band16[];   // BL * N FP16 cells + the spare slot
     const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (w >= (int64_t)n_items * nt) return;
     const int64_t blk = w / ((int64_t)G * nt), rem = w % ((int64_t)G * nt);
@@ -788,7 +781,7 @@ __global__ __launch_bounds__(128) void k_band_rows_mf(
     const BandChan ch = chans[it.chan];
     const int tid = threadIdx.x;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int i = tid; i <= BL * N; i += T) lds[i] = zero;
+    for (int i = tid; i <= BL * N; i += T) band16[i] = make_uint2(0u, 0u);
     __syncthreads();
     const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * vb;
     const uint4 *ent = entries + it.entry_off;
@@ -822,25 +815,26 @@ __global__ __launch_bounds__(128) void k_band_rows_mf(
                 s.z += wr * yr - wi * yi;
                 s.w += wr * yi + wi * yr;
             }
-            lds[e[k].y] = s;
+            band16[e[k].y] = make_uint2(h2bits(s.x * in_scale, s.y * in_scale),
+                                     h2bits(s.z * in_scale, s.w * in_scale));
             if (e[k].x & 0x80000000u) s = zero;
         }
     }
     __syncthreads();
     const int lane = tid & 63, wv = tid >> 6;
     const int a = lane & 15, g = lane >> 4;
-    const MfConst k = mf_consts(lane);
+    const MfConst k = mf_consts(mfc, lane);
     for (int l = wv; l < BL; l += 2) {
         const int row = ch.row_lo + it.band * BL + l;
         if (row > ch.row_hi) break;
         mf_h4 xr, xi, yr, yi;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const float4 v = lds[l * N + 16 * (4 * g + j) + a];
-            xr[j] = (_Float16)(v.x * in_scale);
-            xi[j] = (_Float16)(v.y * in_scale);
-            yr[j] = (_Float16)(v.z * in_scale);
-            yi[j] = (_Float16)(v.w * in_scale);
+            const uint2 v = band16[l * N + 16 * (4 * g + j) + a];
+            xr[j] = h_lo(v.x);
+            xi[j] = h_hi(v.x);
+            yr[j] = h_lo(v.y);
+            yi[j] = h_hi(v.y);
         }
         mf_f4 er, ei, fr2, fi2;
         mf_line(k, xr, xi, er, ei);
@@ -868,7 +862,7 @@ template <int P>
 __global__ __launch_bounds__(256) void k_band_cols_mf(
     const BandChan *__restrict__ chans, const uint2 *__restrict__ scratch, int64_t scratch_t,
     int nt, float *__restrict__ acc, float *__restrict__ part, int64_t part_stride,
-    float out_scale) {
+    float out_scale, const MfConst *__restrict__ mfc) {
     constexpr int N = 256, T = 256;
     constexpr int NPROD = P == 2 ? 4 : 1;
     extern __shared__ uint2 tile[];   // [MF_BC][MF_LP]
@@ -877,7 +871,7 @@ __global__ __launch_bounds__(256) void k_band_cols_mf(
     const int c0 = blockIdx.x * MF_BC;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int a = lane & 15, g = lane >> 4;
-    const MfConst k = mf_consts(lane);
+    const MfConst k = mf_consts(mfc, lane);
     float av[4][4][NPROD];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
@@ -886,20 +880,33 @@ __global__ __launch_bounds__(256) void k_band_cols_mf(
 #pragma unroll
             for (int q = 0; q < NPROD; ++q) av[c][i][q] = 0.f;
     const uint2 *base = scratch + ch.scratch_off + c0;
-    for (int t = slice; t < nt; t += S) {
+    // 256 rows x 8 column pairs per sample (rows outside the footprint span
+    // are zero); the next sample's strip is loaded into registers while the
+    // current one is transformed
+    uint4 pre[8];
+    auto load_strip = [&](int t) {
         const uint2 *src = base + (int64_t)t * scratch_t;
-        // 256 rows x 8 column pairs; rows outside the footprint span are zero
 #pragma unroll
         for (int r8 = 0; r8 < 8; ++r8) {
             const int i = tid + r8 * T;
             const int row = i >> 3, cp = i & 7;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            pre[r8] = make_uint4(0u, 0u, 0u, 0u);
             if (row >= ch.row_lo && row <= ch.row_hi)
-                v = *reinterpret_cast<const uint4 *>(src + (int64_t)(row - ch.row_lo) * N + 2 * cp);
-            tile[(2 * cp) * MF_LP + row] = make_uint2(v.x, v.y);
-            tile[(2 * cp + 1) * MF_LP + row] = make_uint2(v.z, v.w);
+                pre[r8] = *reinterpret_cast<const uint4 *>(src + (int64_t)(row - ch.row_lo) * N +
+                                                           2 * cp);
+        }
+    };
+    if (slice < nt) load_strip(slice);
+    for (int t = slice; t < nt; t += S) {
+#pragma unroll
+        for (int r8 = 0; r8 < 8; ++r8) {
+            const int i = tid + r8 * T;
+            const int row = i >> 3, cp = i & 7;
+            tile[(2 * cp) * MF_LP + row] = make_uint2(pre[r8].x, pre[r8].y);
+            tile[(2 * cp + 1) * MF_LP + row] = make_uint2(pre[r8].z, pre[r8].w);
         }
         __syncthreads();
+        if (t + S < nt) load_strip(t + S);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int col = wv + 4 * c;
@@ -1090,10 +1097,30 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
         while (bmax * std::ldexp(1.0, -si) > 32768.0) ++si;
         bp.mf_in = (float)std::ldexp(1.0, -si);
         bp.mf_out = (float)std::ldexp(1.0, 24 + 2 * si);
+        // per-lane DFT-16 fragments and twiddles (lane = a + 16 g)
+        std::vector<MfConst> tab(64);
+        for (int lane = 0; lane < 64; ++lane) {
+            const int a = lane & 15, g = lane >> 4;
+            for (int j = 0; j < 4; ++j) {
+                const double f = 2.0 * M_PI * (double)((a * (4 * g + j)) & 15) / 16.0;
+                tab[lane].fr[j] = (_Float16)(float)std::cos(f);
+                tab[lane].fi[j] = (_Float16)(float)std::sin(f);
+                tab[lane].nfi[j] = (_Float16)(float)-std::sin(f);
+                const double u = 2.0 * M_PI * (double)(a * (4 * g + j)) / 256.0;
+                tab[lane].tw[j] = make_float2((float)std::cos(u) * 0.0625f,
+                                              (float)std::sin(u) * 0.0625f);
+            }
+        }
+        epic_status st0 = bp.d_mf.alloc(sizeof(MfConst) * tab.size());
+        if (st0) return st0;
+        EPIC_HIP(hipMemcpyAsync(bp.d_mf.p, tab.data(), sizeof(MfConst) * tab.size(),
+                                hipMemcpyHostToDevice, s));
     }
-    // samples per round: each of the two scratch halves near 1 GiB
-    const int64_t per_t = off * (int64_t)sizeof(float4);
-    bp.t_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (1LL << 30) / per_t));
+    // samples per round: each of the two scratch halves near 1 GiB (cells
+    // are float4, or two FP16 pairs on the FP16 four-step path)
+    bp.elem_bytes = p->precision == EPIC_F16_MFMA ? 8 : (int)sizeof(float4);
+    const int64_t per_t = off * (int64_t)bp.elem_bytes;
+    bp.t_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (8LL << 30) / per_t));
     bp.scratch_bytes = 2 * per_t * bp.t_chunk;
     // Column passes with fewer than 1024 workgroups split the samples of a
     // round into S slices, each summing into its own partial image set.
@@ -1193,7 +1220,7 @@ static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const ui
     return EPIC_OK;
 }
 
-constexpr size_t kRowsMfLds = sizeof(float4) * (BL * 256 + 1);
+constexpr size_t kRowsMfLds = sizeof(uint2) * (BL * 256 + 1);
 constexpr size_t kColsMfLds = sizeof(uint2) * MF_BC * MF_LP;
 
 static epic_status ready_mf(int P) {
@@ -1223,14 +1250,15 @@ static epic_status launch_mf(epic_plan p, const BandSize &bs, int pass, const ui
                            kRowsMfLds, s, d_volt, p->vstride(), chans,
                            bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, bs.G, nt,
                            per_xcd, bp.d_entries.as<uint4>(), p->A, sc, bp.scratch_t, p->vb,
-                           bp.mf_in);
+                           bp.mf_in, bp.d_mf.as<MfConst>());
         EPIC_HIP(hipGetLastError());
         return EPIC_OK;
     }
     const int S = bs.slices;
     float *pp = S > 1 ? part + bs.part_off : nullptr;
     hipLaunchKernelGGL(k_band_cols_mf<P>, dim3(bs.N / MF_BC, bs.n, S), dim3(256), kColsMfLds, s,
-                       chans, sc, bp.scratch_t, nt, acc, pp, bs.part_stride, bp.mf_out);
+                       chans, sc, bp.scratch_t, nt, acc, pp, bs.part_stride, bp.mf_out,
+                       bp.d_mf.as<MfConst>());
     EPIC_HIP(hipGetLastError());
     if (S > 1) {
         const int n_floats = p->n_prod * bs.N * bs.N;
@@ -1351,14 +1379,14 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
         EPIC_HIP(hipStreamWaitEvent(q_rows, ev[0], 0));
         EPIC_HIP(hipStreamWaitEvent(q_cols, ev[0], 0));
     }
-    const int64_t half = (int64_t)bp.scratch_t * bp.t_chunk;
+    const int64_t half = (int64_t)bp.elem_bytes * bp.scratch_t * bp.t_chunk;   // bytes
     int k = 0;
     for (int t0 = 0; t0 < n_time; t0 += round, ++k) {
         const int nt = std::min(round, n_time - t0);
         FrameOut fr = fo;
         if (fo.len) fr.out = fo.out + (int64_t)(t0 / fo.len) * fo.stride;
         const int b = k & 1;
-        float4 *scratch = acc->d_work.as<float4>() + b * half;
+        float4 *scratch = reinterpret_cast<float4 *>(acc->d_work.as<char>() + b * half);
         const uint8_t *v = d_volt + (int64_t)t0 * p->vstride();
         if (split && k >= 2) EPIC_HIP(hipStreamWaitEvent(q_rows, ev[3 + b], 0));
         for (int pass = 0; pass < 2; ++pass) {

@@ -145,7 +145,8 @@ struct BandSize {
 struct BandPlan {
     int n = 0;               // banded channels
     int t_chunk = 0;         // samples per pass-1/pass-2 round
-    int64_t scratch_t = 0;   // float4 per sample of row transforms
+    int64_t scratch_t = 0;   // cells per sample of row transforms
+    int elem_bytes = 16;     // bytes per scratch cell: float4, or 8 (FP16 four-step)
     int64_t scratch_bytes = 0;  // two halves of row transforms
     int64_t part_bytes = 0;     // column-pass partial sums, after the scratch
     std::vector<BandSize> sizes;
@@ -156,6 +157,7 @@ struct BandPlan {
     // EPIC_F16_MFMA plans (256 x 256, FP16 four-step): exact power-of-two
     // scale of the gridded values into FP16, and of the products back
     float mf_in = 1.0f, mf_out = 1.0f;
+    DevBuf d_mf;             // per-lane DFT-16 fragments and twiddles (64 entries)
 };
 
 // Low-bitwidth path (EPIC_FIXED16): one gather item per channel (64 x 64

@@ -205,3 +205,20 @@ def test_fixed_point_plans_validated_before_device_work(over, status, word):
     assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == status
     assert word in lib.epic_last_error()
     assert not h.value
+
+
+def test_fp16_plans_take_one_path_for_all_channels():
+    """FP16 plans send 256 x 256 channels to the banded four-step transform
+    and everything else to the DFT-GEMM; a plan needing both is refused, as
+    is a banded request for another side."""
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    h = C.c_void_p()
+    gn = np.array([256, 64], dtype=np.int32)
+    freq = np.array([60e6, 61e6])
+    d, keep = _desc(n_chan=2, grid_n=gn.ctypes.data_as(C.POINTER(C.c_int32)),
+                    chan_freq_hz=freq.ctypes.data_as(C.POINTER(C.c_double)),
+                    precision=E.EPIC_F16_MFMA)
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 4
+    assert b"one path" in lib.epic_last_error()
+    assert not h.value

@@ -40,3 +40,14 @@ def test_small_array_256_grid_fp16_fourstep_in_calls(bits):
     ref = oracle_images(volt, pos, wl, [0])
     _check(_run(wl, pos, volt, precision=1, chunks=3), ref, f"fp16-4step-{bits}bit",
            TOL["max"], TOL["rms"])
+
+
+def test_fp16_fourstep_rounds_alternate_scratch_halves():
+    # 300 samples on a 256^2 grid: two rounds of the banded path (256 + 44
+    # samples), the second in the other half of the FP16 scratch
+    wl = dataclasses.replace(synth.workload("tiny2"), grid_n=np.array([256]), n_time=300)
+    pos = synth.antenna_layout(wl)
+    volt = synth.voltages(wl, pos)
+    _say("case fp16 four-step: 16 elements on 256^2, 300 samples in one call (two rounds)")
+    _check(_run(wl, pos, volt, precision=1), oracle_images(volt, pos, wl, [0]),
+           "fp16-4step-rounds", TOL["max"], TOL["rms"])

@@ -67,9 +67,17 @@ def test_lwa_channels_dftgemm(dt):
 
 
 def test_dftgemm_rejects_large_arrays():
+    # The DFT-GEMM variants hold a beam matrix per element and refuse arrays
+    # above 256 elements; an FP16 plan on 256 x 256 grids takes the four-step
+    # banded transform instead, which has no such limit.
     import paper_2609_03027_amd as E
     wl = synth.workload("stream")
     pos = synth.antenna_layout(wl)[:300]
-    with pytest.raises(E.EpicError) as ei:
-        E.Plan(pos, [100e6], [256], 2, precision=F16)
-    assert ei.value.status == 4
+    for prec, f, n in ((F16, 50e6, 128), (E.EPIC_BF16X2_MFMA, 100e6, 256),
+                       (E.EPIC_F8E4M3_MFMA, 50e6, 128)):
+        with pytest.raises(E.EpicError) as ei:
+            E.Plan(pos, [f], [n], 2, precision=prec)
+        assert ei.value.status == 4, prec
+    plan = E.Plan(pos, [100e6], [256], 2, precision=F16)
+    assert plan.info["bytes_acc"] > 0
+    plan.close()
