@@ -740,9 +740,20 @@ def main():
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / 3
         sv = Ts * wl.n_chan * wl.n_pol * wl.n_ant / (ms / 1e3)
+        # algorithmic HBM bytes of the staged form: per (t, c) the grid is
+        # written, read and the sky written by the transform, the sky read by
+        # the accumulation (complex64 per feed and pixel); per call the sums
+        # are read and written once
+        n2 = int(np.sum(wl.grid_n.astype(np.int64) ** 2))
+        st_bytes = Ts * 4 * wl.n_pol * n2 * 8 + 2 * 4 * plan.info["image_floats"]
         out["staged_fp32"] = {"value": sv, "unit": "samples/s", "samples": Ts,
-                              "ms": ms, "speedup_of_fused": out["value"] / sv}
-        log(f"staged FP32 path: {ms:.2f} ms for {Ts} samples -> {sv:.3e} samples/s")
+                              "ms": ms, "speedup_of_fused": out["value"] / sv,
+                              "hbm_bytes": st_bytes,
+                              "hbm_GBps": st_bytes / (ms / 1e3) / 1e9,
+                              "hbm_frac": st_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+        log(f"staged FP32 path: {ms:.2f} ms for {Ts} samples -> {sv:.3e} samples/s, "
+            f"{st_bytes / (ms / 1e3) / 1e9:.0f} GB/s of grid and sky traffic "
+            f"({st_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS:.1%} of HBM peak)")
         del g, s
 
     if args.variants:

@@ -61,12 +61,67 @@ struct Radices {
     int r[8];
 };
 
+// R-point DFT with the positive exponent on v[0..R-1] in place (R = 2, 3, 4).
+template <int R> __device__ __forceinline__ void s_dft(float2 *v);
+template <> __device__ __forceinline__ void s_dft<2>(float2 *v) {
+    const float2 a = v[0], b = v[1];
+    v[0] = s_cadd(a, b);
+    v[1] = s_csub(a, b);
+}
+template <> __device__ __forceinline__ void s_dft<3>(float2 *v) {
+    const float h = 0.86602540378443864676f;
+    const float2 sm = s_cadd(v[1], v[2]), df = s_csub(v[1], v[2]);
+    const float2 a = v[0];
+    v[0] = s_cadd(a, sm);
+    const float2 tt = make_float2(a.x - 0.5f * sm.x, a.y - 0.5f * sm.y);
+    const float2 uu = make_float2(-h * df.y, h * df.x);
+    v[1] = s_cadd(tt, uu);
+    v[2] = s_csub(tt, uu);
+}
+template <> __device__ __forceinline__ void s_dft<4>(float2 *v) {
+    const float2 t0 = s_cadd(v[0], v[2]), t1 = s_csub(v[0], v[2]);
+    const float2 t2 = s_cadd(v[1], v[3]);
+    const float2 d = s_csub(v[1], v[3]);
+    const float2 t3 = make_float2(-d.y, d.x);
+    v[0] = s_cadd(t0, t2);
+    v[2] = s_csub(t0, t2);
+    v[1] = s_cadd(t1, t3);
+    v[3] = s_csub(t1, t3);
+}
+
+// One radix-R Stockham pass over `lines` lines of length N (positive
+// exponent), line l at l * pitch, from src to dst.
+template <int R>
+__device__ __forceinline__ void s_pass(const float2 *src, float2 *dst, int lines, int N,
+                                       int pitch, int Ns, const float2 *__restrict__ tw) {
+    const int nb = N / R;
+    const int tstep = N / (Ns * R);
+    for (int u = threadIdx.x; u < lines * nb; u += blockDim.x) {
+        const int l = u / nb, j = u % nb;
+        const int k = j % Ns;
+        const float2 *s_in = src + l * pitch;
+        float2 *s_out = dst + l * pitch;
+        float2 v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float2 x = s_in[j + q * nb];
+            if (q) x = s_cmul(x, tw[(q * k * tstep) % N]);
+            v[q] = x;
+        }
+        s_dft<R>(v);
+        const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) s_out[idxD + q * Ns] = v[q];
+    }
+}
+
 // Batched 1D transforms along one axis of N x N images, Stockham passes in
 // LDS with the positive exponent.  Inputs are multiplied by (-1)^j and
 // outputs by (-1)^k, which turns the plain transform into the centred one
 // of Eq. 1 (the two per-axis constants exp(i pi N/2) multiply to one over
 // the two axes).  Grid: (line blocks, images); images are (t, channel of
-// this size, p) in that order.
+// this size, p) in that order.  Used for grid sides above 128; smaller
+// images take k_fft2d.
 __global__ __launch_bounds__(256) void k_fft_lines(const float2 *in, float2 *out,
                                                    const int32_t *__restrict__ chans, int n_chans,
                                                    const int64_t *__restrict__ grid_off, int P,
@@ -104,45 +159,12 @@ __global__ __launch_bounds__(256) void k_fft_lines(const float2 *in, float2 *out
     float2 *src = b0, *dst = b1;
     for (int ps = 0; ps < rad.n; ++ps) {
         const int r = rad.r[ps];
-        const int nb = N / r;
-        const int tstep = N / (Ns * r);
-        for (int u = threadIdx.x; u < LPB * nb; u += blockDim.x) {
-            const int l = u / nb, j = u % nb;
-            const int k = j % Ns;
-            const float2 *s_in = src + l * N;
-            float2 *s_out = dst + l * N;
-            float2 v[4];
-            for (int q = 0; q < r; ++q) {
-                float2 x = s_in[j + q * nb];
-                if (q) x = s_cmul(x, tw[(q * k * tstep) % N]);
-                v[q] = x;
-            }
-            if (r == 2) {
-                const float2 a = v[0], b = v[1];
-                v[0] = s_cadd(a, b);
-                v[1] = s_csub(a, b);
-            } else if (r == 3) {
-                const float h = 0.86602540378443864676f;
-                const float2 sm = s_cadd(v[1], v[2]), df = s_csub(v[1], v[2]);
-                const float2 a = v[0];
-                v[0] = s_cadd(a, sm);
-                const float2 tt = make_float2(a.x - 0.5f * sm.x, a.y - 0.5f * sm.y);
-                const float2 uu = make_float2(-h * df.y, h * df.x);
-                v[1] = s_cadd(tt, uu);
-                v[2] = s_csub(tt, uu);
-            } else {
-                const float2 t0 = s_cadd(v[0], v[2]), t1 = s_csub(v[0], v[2]);
-                const float2 t2 = s_cadd(v[1], v[3]);
-                const float2 d = s_csub(v[1], v[3]);
-                const float2 t3 = make_float2(-d.y, d.x);
-                v[0] = s_cadd(t0, t2);
-                v[2] = s_csub(t0, t2);
-                v[1] = s_cadd(t1, t3);
-                v[3] = s_csub(t1, t3);
-            }
-            const int idxD = (j / Ns) * Ns * r + k;
-            for (int q = 0; q < r; ++q) s_out[idxD + q * Ns] = v[q];
-        }
+        if (r == 4)
+            s_pass<4>(src, dst, LPB, N, N, Ns, tw);
+        else if (r == 2)
+            s_pass<2>(src, dst, LPB, N, N, Ns, tw);
+        else
+            s_pass<3>(src, dst, LPB, N, N, Ns, tw);
         Ns *= r;
         __syncthreads();
         float2 *tmp = src;
@@ -164,6 +186,99 @@ __global__ __launch_bounds__(256) void k_fft_lines(const float2 *in, float2 *out
         float2 v = src[l * N + k];
         if (k & 1) v = make_float2(-v.x, -v.y);
         out[addr] = v;
+    }
+}
+
+// In-place radix-R Stockham pass over the N lines of an N x N image in LDS
+// (row pitch `pitch`, odd): every butterfly's inputs go to registers before
+// any output is written (one barrier between), so the pass needs no second
+// buffer.  Consecutive lanes take consecutive lines on both axes, so every
+// access of a wave strides by the pitch (along x) or by one (along y) and
+// 32 lanes of 8-byte accesses fall in distinct bank pairs.  At most MAXB
+// butterflies per thread (N^2 / R / blockDim).
+template <int R, int MAXB>
+__device__ __forceinline__ void s_pass_inplace(float2 *buf, int N, int pitch, int Ns,
+                                               bool along_x, const float2 *__restrict__ tw) {
+    const int nb = N / R, total = N * nb;
+    const int tstep = N / (Ns * R);
+    float2 v[MAXB][R];
+    int ob[MAXB];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int u = threadIdx.x + b * blockDim.x;
+        if (u < total) {
+            const int l = u % N;
+            const int j = u / N;
+            const int k = j % Ns;
+            const int stride = along_x ? 1 : pitch;
+            const int line = along_x ? l * pitch : l;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                float2 x = buf[line + (j + q * nb) * stride];
+                if (q) x = s_cmul(x, tw[(q * k * tstep) % N]);
+                v[b][q] = x;
+            }
+            s_dft<R>(v[b]);
+            ob[b] = line + ((j / Ns) * Ns * R + k) * stride;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int u = threadIdx.x + b * blockDim.x;
+        if (u < total) {
+            const int stride = along_x ? 1 : pitch;
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[ob[b] + q * Ns * stride] = v[b][q];
+        }
+    }
+    __syncthreads();
+}
+
+// One workgroup (1024 threads) per image of side N <= 128: the image is read
+// from HBM once, multiplied by (-1)^(jx+jy), transformed along x then y in
+// LDS (row pitch N + 1), multiplied by (-1)^(kx+ky) and written once.
+// Grid: images (t, channel of this size, p).
+__global__ __launch_bounds__(1024) void k_fft2d(const float2 *in, float2 *out,
+                                               const int32_t *__restrict__ chans, int n_chans,
+                                               const int64_t *__restrict__ grid_off, int P,
+                                               int64_t grid_t_stride, int N, Radices rad,
+                                               const float2 *__restrict__ tw) {
+    extern __shared__ float2 sbuf[];
+    const int pitch = N + 1;
+    float2 *twl = sbuf + N * pitch;
+    const int img = blockIdx.x;
+    const int p = img % P;
+    const int ci = (img / P) % n_chans;
+    const int t = img / (P * n_chans);
+    const int c = chans[ci];
+    const int64_t base = (int64_t)t * grid_t_stride + grid_off[c] + (int64_t)p * N * N;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) twl[n] = tw[n];
+    for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
+        const int r = i / N, col = i % N;
+        float2 v = in[base + i];
+        if ((r + col) & 1) v = make_float2(-v.x, -v.y);
+        sbuf[r * pitch + col] = v;
+    }
+    __syncthreads();
+    for (int ax = 0; ax < 2; ++ax) {
+        int Ns = 1;
+        for (int ps = 0; ps < rad.n; ++ps) {
+            const int r = rad.r[ps];
+            if (r == 4)
+                s_pass_inplace<4, 4>(sbuf, N, pitch, Ns, ax == 0, twl);
+            else if (r == 2)
+                s_pass_inplace<2, 8>(sbuf, N, pitch, Ns, ax == 0, twl);
+            else
+                s_pass_inplace<3, 6>(sbuf, N, pitch, Ns, ax == 0, twl);
+            Ns *= r;
+        }
+    }
+    for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
+        const int r = i / N, col = i % N;
+        float2 v = sbuf[r * pitch + col];
+        if ((r + col) & 1) v = make_float2(-v.x, -v.y);
+        out[base + i] = v;
     }
 }
 
@@ -249,6 +364,24 @@ epic_status staged_image(epic_plan p, const void *d_grid, int n_time, void *d_sk
             if (N % d == 0) LPB = d;
         const int32_t *chans = p->d_sz_chans.as<int32_t>() + p->sz_off[gi];
         const int64_t imgs_per_t = (int64_t)n_chans * p->P;
+        const float2 *twd = p->d_twid.as<float2>() + p->twid_off[N];
+        if (N <= 128) {
+            // whole images in LDS: one read and one write per image
+            const size_t lds2 = sizeof(float2) * ((size_t)N * (N + 1) + N);
+            epic_status st = lds_ready(reinterpret_cast<const void *>(k_fft2d), lds2);
+            if (st) return st;
+            const int64_t t_max2 = std::max<int64_t>(1, 0x7fffffff / imgs_per_t);
+            for (int t0 = 0; t0 < n_time; t0 += (int)std::min<int64_t>(t_max2, n_time)) {
+                const int nt = (int)std::min<int64_t>(t_max2, n_time - t0);
+                const float2 *gin = static_cast<const float2 *>(d_grid) + (int64_t)t0 * p->grid_elems_per_t;
+                float2 *gout = static_cast<float2 *>(d_sky) + (int64_t)t0 * p->grid_elems_per_t;
+                hipLaunchKernelGGL(k_fft2d, dim3((unsigned)(imgs_per_t * nt)), dim3(1024), lds2, s,
+                                   gin, gout, chans, n_chans, p->d_grid_off.as<int64_t>(), p->P,
+                                   p->grid_elems_per_t, N, rad, twd);
+                EPIC_HIP(hipGetLastError());
+            }
+            continue;
+        }
         const int t_max = (int)std::max<int64_t>(1, 65535 / imgs_per_t);
         const size_t lds = sizeof(float2) * 2 * LPB * N;
         const float2 *tw = p->d_twid.as<float2>() + p->twid_off[N];
