@@ -49,6 +49,57 @@ __global__ void k_grid_csr(const uint8_t *__restrict__ volt, int64_t volt_t_stri
     grid[(int64_t)t * grid_t_stride + grid_off[c] + (int64_t)p * N * N + cell] = s;
 }
 
+// The same gridding for one kernel per element (J = 1), one thread per
+// (cell, channel) covering both feeds and TT consecutive samples: the cell's
+// CSR range and taps are read once for all of them.  Grid: (cell blocks,
+// channels, sample groups of TT).
+template <int P, int TT>
+__global__ void k_grid_csr_t(const uint8_t *__restrict__ volt, int64_t volt_t_stride,
+                             const int4 *__restrict__ chan, const int64_t *__restrict__ grid_off,
+                             const int64_t *__restrict__ csr_base,
+                             const int32_t *__restrict__ csr_off,
+                             const int32_t *__restrict__ csr_ant, const float2 *__restrict__ csr_w,
+                             int A, int n_time, int64_t grid_t_stride, float2 *__restrict__ grid,
+                             int vb) {
+    const int c = blockIdx.y;
+    const int N = chan[c].x;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= N * N) return;
+    const int t0 = blockIdx.z * TT;
+    const int nt = min(TT, n_time - t0);
+    const int32_t *off = csr_off + csr_base[c];
+    const int e0 = off[cell], e1 = off[cell + 1];
+    const uint8_t *v = volt + (int64_t)t0 * volt_t_stride + (int64_t)c * P * A * vb;
+    float2 s[TT][P];
+#pragma unroll
+    for (int k = 0; k < TT; ++k)
+#pragma unroll
+        for (int p = 0; p < P; ++p) s[k][p] = make_float2(0.f, 0.f);
+    for (int e = e0; e < e1; ++e) {
+        const int a = csr_ant[e];
+        const float2 w = csr_w[e];
+#pragma unroll
+        for (int k = 0; k < TT; ++k) {
+            if (k < nt) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const int2 x = volt_at(v + (int64_t)k * volt_t_stride, (int64_t)p * A + a, vb);
+                    const float er = (float)x.x, ei = (float)x.y;
+                    s[k][p].x += w.x * er - w.y * ei;
+                    s[k][p].y += w.x * ei + w.y * er;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TT; ++k)
+        if (k < nt)
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                grid[(int64_t)(t0 + k) * grid_t_stride + grid_off[c] + (int64_t)p * N * N + cell] =
+                    s[k][p];
+}
+
 // --------------------------------------------------------------- FFT
 __device__ __forceinline__ float2 s_cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 s_csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -235,50 +286,186 @@ __device__ __forceinline__ void s_pass_inplace(float2 *buf, int N, int pitch, in
     __syncthreads();
 }
 
-// One workgroup (1024 threads) per image of side N <= 128: the image is read
-// from HBM once, multiplied by (-1)^(jx+jy), transformed along x then y in
-// LDS (row pitch N + 1), multiplied by (-1)^(kx+ky) and written once.
-// Grid: images (t, channel of this size, p).
+// Persistent workgroups of 1024 threads over images of side N <= 128: each
+// image is read from HBM once, multiplied by (-1)^(jx+jy), transformed along
+// x then y in LDS (row pitch N + 1), multiplied by (-1)^(kx+ky) and written
+// once.  The next image's elements are loaded into registers while the
+// current one is transformed.  Images are (t, channel of this size, p);
+// workgroup w takes images w, w + gridDim.x, ...
+constexpr int kFft2dPer = 16;   // elements per thread: N^2 <= 16384 over 1024 threads
+
 __global__ __launch_bounds__(1024) void k_fft2d(const float2 *in, float2 *out,
-                                               const int32_t *__restrict__ chans, int n_chans,
-                                               const int64_t *__restrict__ grid_off, int P,
-                                               int64_t grid_t_stride, int N, Radices rad,
-                                               const float2 *__restrict__ tw) {
+                                                const int32_t *__restrict__ chans, int n_chans,
+                                                const int64_t *__restrict__ grid_off, int P,
+                                                int64_t grid_t_stride, int N, int64_t n_img,
+                                                Radices rad, const float2 *__restrict__ tw) {
     extern __shared__ float2 sbuf[];
     const int pitch = N + 1;
     float2 *twl = sbuf + N * pitch;
-    const int img = blockIdx.x;
-    const int p = img % P;
-    const int ci = (img / P) % n_chans;
-    const int t = img / (P * n_chans);
-    const int c = chans[ci];
-    const int64_t base = (int64_t)t * grid_t_stride + grid_off[c] + (int64_t)p * N * N;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) twl[n] = tw[n];
-    for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
-        const int r = i / N, col = i % N;
-        float2 v = in[base + i];
-        if ((r + col) & 1) v = make_float2(-v.x, -v.y);
-        sbuf[r * pitch + col] = v;
+    const int tid = threadIdx.x, NN = N * N;
+    for (int n = tid; n < N; n += blockDim.x) twl[n] = tw[n];
+    auto base_of = [&](int64_t img) {
+        const int p = (int)(img % P);
+        const int ci = (int)((img / P) % n_chans);
+        const int64_t t = img / ((int64_t)P * n_chans);
+        return t * grid_t_stride + grid_off[chans[ci]] + (int64_t)p * NN;
+    };
+    float2 pre[kFft2dPer];
+    auto load = [&](int64_t img) {
+        const float2 *src = in + base_of(img);
+#pragma unroll
+        for (int k = 0; k < kFft2dPer; ++k) {
+            const int i = tid + k * 1024;
+            if (i < NN) pre[k] = src[i];
+        }
+    };
+    int64_t img = blockIdx.x;
+    if (img < n_img) load(img);
+    for (; img < n_img; img += gridDim.x) {
+#pragma unroll
+        for (int k = 0; k < kFft2dPer; ++k) {
+            const int i = tid + k * 1024;
+            if (i < NN) {
+                const int r = i / N, col = i % N;
+                float2 v = pre[k];
+                if ((r + col) & 1) v = make_float2(-v.x, -v.y);
+                sbuf[r * pitch + col] = v;
+            }
+        }
+        __syncthreads();
+        if (img + gridDim.x < n_img) load(img + gridDim.x);
+        for (int ax = 0; ax < 2; ++ax) {
+            int Ns = 1;
+            for (int ps = 0; ps < rad.n; ++ps) {
+                const int r = rad.r[ps];
+                if (r == 4)
+                    s_pass_inplace<4, 4>(sbuf, N, pitch, Ns, ax == 0, twl);
+                else if (r == 2)
+                    s_pass_inplace<2, 8>(sbuf, N, pitch, Ns, ax == 0, twl);
+                else
+                    s_pass_inplace<3, 6>(sbuf, N, pitch, Ns, ax == 0, twl);
+                Ns *= r;
+            }
+        }
+        float2 *dst = out + base_of(img);
+        for (int i = tid; i < NN; i += blockDim.x) {
+            const int r = i / N, col = i % N;
+            float2 v = sbuf[r * pitch + col];
+            if ((r + col) & 1) v = make_float2(-v.x, -v.y);
+            dst[i] = v;
+        }
+        __syncthreads();   // every read of this image before the next one's writes
     }
-    __syncthreads();
-    for (int ax = 0; ax < 2; ++ax) {
-        int Ns = 1;
-        for (int ps = 0; ps < rad.n; ++ps) {
-            const int r = rad.r[ps];
-            if (r == 4)
-                s_pass_inplace<4, 4>(sbuf, N, pitch, Ns, ax == 0, twl);
-            else if (r == 2)
-                s_pass_inplace<2, 8>(sbuf, N, pitch, Ns, ax == 0, twl);
-            else
-                s_pass_inplace<3, 6>(sbuf, N, pitch, Ns, ax == 0, twl);
-            Ns *= r;
+}
+
+// The same transform for power-of-two sides N <= 128 with N a template
+// constant: the radix schedule (4, 4, ..., then 2 if needed) and every index
+// division become compile-time shifts and masks.  PF: the next image is
+// prefetched into registers during the transform (N < 128; at N = 128 the
+// 16 prefetch registers per thread would spill, so the image is loaded at
+// the start of its turn instead).
+template <int N, int T, int R, int NS>
+__device__ __forceinline__ void p2_pass(float2 *buf, bool along_x, const float2 *__restrict__ tw) {
+    constexpr int pitch = N + 1, nb = N / R, total = N * nb;
+    constexpr int MAXB = (total + T - 1) / T, tstep = N / (NS * R);
+    float2 v[MAXB][R];
+    int ob[MAXB];
+    const int stride = along_x ? 1 : pitch;
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int u = threadIdx.x + b * T;
+        if (total % T == 0 || u < total) {
+            const int l = u % N, j = u / N, k = j % NS;
+            const int line = along_x ? l * pitch : l;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                float2 x = buf[line + (j + q * nb) * stride];
+                if (q) x = s_cmul(x, tw[(q * k * tstep) % N]);
+                v[b][q] = x;
+            }
+            s_dft<R>(v[b]);
+            ob[b] = line + ((j / NS) * NS * R + k) * stride;
         }
     }
-    for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
-        const int r = i / N, col = i % N;
-        float2 v = sbuf[r * pitch + col];
-        if ((r + col) & 1) v = make_float2(-v.x, -v.y);
-        out[base + i] = v;
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int u = threadIdx.x + b * T;
+        if (total % T == 0 || u < total) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[ob[b] + q * NS * stride] = v[b][q];
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int T, int NS>
+__device__ __forceinline__ void p2_passes(float2 *buf, bool along_x, const float2 *__restrict__ tw) {
+    if constexpr (NS * 4 <= N) {
+        p2_pass<N, T, 4, NS>(buf, along_x, tw);
+        p2_passes<N, T, NS * 4>(buf, along_x, tw);
+    } else if constexpr (NS * 2 <= N) {
+        p2_pass<N, T, 2, NS>(buf, along_x, tw);
+        p2_passes<N, T, NS * 2>(buf, along_x, tw);
+    }
+}
+
+template <int N, int T, bool PF>
+__global__ __launch_bounds__(T) void k_fft2d_p2(const float2 *in, float2 *out,
+                                                   const int32_t *__restrict__ chans, int n_chans,
+                                                   const int64_t *__restrict__ grid_off, int P,
+                                                   int64_t grid_t_stride, int64_t n_img,
+                                                   const float2 *__restrict__ tw) {
+    constexpr int pitch = N + 1, NN = N * N, PER = (NN + T - 1) / T;
+    extern __shared__ float2 sbuf[];
+    float2 *twl = sbuf + N * pitch;
+    const int tid = threadIdx.x;
+    for (int n = tid; n < N; n += T) twl[n] = tw[n];
+    auto base_of = [&](int64_t img) {
+        const int p = (int)(img % P);
+        const int ci = (int)((img / P) % n_chans);
+        const int64_t t = img / ((int64_t)P * n_chans);
+        return t * grid_t_stride + grid_off[chans[ci]] + (int64_t)p * NN;
+    };
+    float2 pre[PER];
+    auto load = [&](int64_t img) {
+        const float2 *src = in + base_of(img);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + k * T;
+            if (NN % T == 0 || i < NN) pre[k] = src[i];
+        }
+    };
+    int64_t img = blockIdx.x;
+    if (PF && img < n_img) load(img);
+    for (; img < n_img; img += gridDim.x) {
+        if (!PF) load(img);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + k * T;
+            if (NN % T == 0 || i < NN) {
+                const int r = i / N, col = i % N;
+                float2 v = pre[k];
+                if ((r + col) & 1) v = make_float2(-v.x, -v.y);
+                sbuf[r * pitch + col] = v;
+            }
+        }
+        __syncthreads();
+        if (PF && img + gridDim.x < n_img) load(img + gridDim.x);
+        p2_passes<N, T, 1>(sbuf, true, twl);
+        p2_passes<N, T, 1>(sbuf, false, twl);
+        float2 *dst = out + base_of(img);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + k * T;
+            if (NN % T == 0 || i < NN) {
+                const int r = i / N, col = i % N;
+                float2 v = sbuf[r * pitch + col];
+                if ((r + col) & 1) v = make_float2(-v.x, -v.y);
+                dst[i] = v;
+            }
+        }
+        __syncthreads();   // every read of this image before the next one's writes
     }
 }
 
@@ -336,6 +523,32 @@ epic_status staged_grid(epic_plan p, const uint8_t *d_volt, int n_time, void *d_
                         hipStream_t s) {
     const int64_t vstride = p->vstride();
     const int max_cells = p->max_n * p->max_n;
+    if (p->J == 1) {
+        constexpr int TT = 4;
+        const int64_t groups = (n_time + TT - 1) / TT;
+        for (int64_t g0 = 0; g0 < groups; g0 += 65535) {
+            const int ng = (int)std::min<int64_t>(65535, groups - g0);
+            const int t0 = (int)(g0 * TT);
+            const int nt = std::min(n_time - t0, ng * TT);
+            dim3 grid((max_cells + 255) / 256, p->C, ng);
+            const uint8_t *v = d_volt + (int64_t)t0 * vstride;
+            float2 *gout = static_cast<float2 *>(d_grid) + (int64_t)t0 * p->grid_elems_per_t;
+            if (p->P == 2)
+                hipLaunchKernelGGL((k_grid_csr_t<2, TT>), grid, dim3(256), 0, s, v, vstride,
+                                   p->d_chan.as<int4>(), p->d_grid_off.as<int64_t>(),
+                                   p->d_csr_base.as<int64_t>(), p->d_csr_off.as<int32_t>(),
+                                   p->d_csr_ant.as<int32_t>(), p->d_csr_w.as<float2>(), p->A, nt,
+                                   p->grid_elems_per_t, gout, p->vb);
+            else
+                hipLaunchKernelGGL((k_grid_csr_t<1, TT>), grid, dim3(256), 0, s, v, vstride,
+                                   p->d_chan.as<int4>(), p->d_grid_off.as<int64_t>(),
+                                   p->d_csr_base.as<int64_t>(), p->d_csr_off.as<int32_t>(),
+                                   p->d_csr_ant.as<int32_t>(), p->d_csr_w.as<float2>(), p->A, nt,
+                                   p->grid_elems_per_t, gout, p->vb);
+            EPIC_HIP(hipGetLastError());
+        }
+        return EPIC_OK;
+    }
     const int tp_max = 65535 / p->P;
     for (int t0 = 0; t0 < n_time; t0 += tp_max) {
         const int nt = std::min(tp_max, n_time - t0);
@@ -366,20 +579,47 @@ epic_status staged_image(epic_plan p, const void *d_grid, int n_time, void *d_sk
         const int64_t imgs_per_t = (int64_t)n_chans * p->P;
         const float2 *twd = p->d_twid.as<float2>() + p->twid_off[N];
         if (N <= 128) {
-            // whole images in LDS: one read and one write per image
+            // whole images in LDS: one read and one write per image;
+            // persistent workgroups, one per CU (the LDS holds one image)
             const size_t lds2 = sizeof(float2) * ((size_t)N * (N + 1) + N);
             epic_status st = lds_ready(reinterpret_cast<const void *>(k_fft2d), lds2);
             if (st) return st;
-            const int64_t t_max2 = std::max<int64_t>(1, 0x7fffffff / imgs_per_t);
-            for (int t0 = 0; t0 < n_time; t0 += (int)std::min<int64_t>(t_max2, n_time)) {
-                const int nt = (int)std::min<int64_t>(t_max2, n_time - t0);
-                const float2 *gin = static_cast<const float2 *>(d_grid) + (int64_t)t0 * p->grid_elems_per_t;
-                float2 *gout = static_cast<float2 *>(d_sky) + (int64_t)t0 * p->grid_elems_per_t;
-                hipLaunchKernelGGL(k_fft2d, dim3((unsigned)(imgs_per_t * nt)), dim3(1024), lds2, s,
-                                   gin, gout, chans, n_chans, p->d_grid_off.as<int64_t>(), p->P,
-                                   p->grid_elems_per_t, N, rad, twd);
+            int dev = 0, n_cu = 0;
+            EPIC_HIP(hipGetDevice(&dev));
+            EPIC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+            const int64_t n_img = imgs_per_t * n_time;
+            const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_img, n_cu));
+            const void *kp2 = N == 128  ? reinterpret_cast<const void *>(k_fft2d_p2<128, 1024, false>)
+                              : N == 64 ? reinterpret_cast<const void *>(k_fft2d_p2<64, 1024, true>)
+                              : N == 32 ? reinterpret_cast<const void *>(k_fft2d_p2<32, 1024, true>)
+                              : N == 16 ? reinterpret_cast<const void *>(k_fft2d_p2<16, 1024, true>)
+                                        : nullptr;
+            if (kp2) {
+                if ((st = lds_ready(kp2, lds2))) return st;
+                const float2 *gi = static_cast<const float2 *>(d_grid);
+                float2 *go = static_cast<float2 *>(d_sky);
+                const int64_t *goff = p->d_grid_off.as<int64_t>();
+                const int64_t gts = p->grid_elems_per_t;
+                if (N == 128)
+                    hipLaunchKernelGGL((k_fft2d_p2<128, 1024, false>), dim3(blocks), dim3(1024), lds2, s,
+                                       gi, go, chans, n_chans, goff, p->P, gts, n_img, twd);
+                else if (N == 64)
+                    hipLaunchKernelGGL((k_fft2d_p2<64, 1024, true>), dim3(blocks), dim3(1024), lds2, s,
+                                       gi, go, chans, n_chans, goff, p->P, gts, n_img, twd);
+                else if (N == 32)
+                    hipLaunchKernelGGL((k_fft2d_p2<32, 1024, true>), dim3(blocks), dim3(1024), lds2, s,
+                                       gi, go, chans, n_chans, goff, p->P, gts, n_img, twd);
+                else
+                    hipLaunchKernelGGL((k_fft2d_p2<16, 1024, true>), dim3(blocks), dim3(1024), lds2, s,
+                                       gi, go, chans, n_chans, goff, p->P, gts, n_img, twd);
                 EPIC_HIP(hipGetLastError());
+                continue;
             }
+            hipLaunchKernelGGL(k_fft2d, dim3(blocks), dim3(1024), lds2, s,
+                               static_cast<const float2 *>(d_grid), static_cast<float2 *>(d_sky),
+                               chans, n_chans, p->d_grid_off.as<int64_t>(), p->P,
+                               p->grid_elems_per_t, N, n_img, rad, twd);
+            EPIC_HIP(hipGetLastError());
             continue;
         }
         const int t_max = (int)std::max<int64_t>(1, 65535 / imgs_per_t);
