@@ -286,14 +286,12 @@ __device__ __forceinline__ void s_pass_inplace(float2 *buf, int N, int pitch, in
     __syncthreads();
 }
 
-// Persistent workgroups of 1024 threads over images of side N <= 128: each
-// image is read from HBM once, multiplied by (-1)^(jx+jy), transformed along
-// x then y in LDS (row pitch N + 1), multiplied by (-1)^(kx+ky) and written
-// once.  The next image's elements are loaded into registers while the
-// current one is transformed.  Images are (t, channel of this size, p);
-// workgroup w takes images w, w + gridDim.x, ...
-constexpr int kFft2dPer = 16;   // elements per thread: N^2 <= 16384 over 1024 threads
-
+// Persistent workgroups of 1024 threads over images of side N <= 128 that
+// are not powers of two (radix 3 among the passes): each image is read from
+// HBM once, multiplied by (-1)^(jx+jy), transformed along x then y in LDS
+// (row pitch N + 1), multiplied by (-1)^(kx+ky) and written once.  Images
+// are (t, channel of this size, p); workgroup w takes images w,
+// w + gridDim.x, ...
 __global__ __launch_bounds__(1024) void k_fft2d(const float2 *in, float2 *out,
                                                 const int32_t *__restrict__ chans, int n_chans,
                                                 const int64_t *__restrict__ grid_off, int P,
@@ -310,30 +308,15 @@ __global__ __launch_bounds__(1024) void k_fft2d(const float2 *in, float2 *out,
         const int64_t t = img / ((int64_t)P * n_chans);
         return t * grid_t_stride + grid_off[chans[ci]] + (int64_t)p * NN;
     };
-    float2 pre[kFft2dPer];
-    auto load = [&](int64_t img) {
+    for (int64_t img = blockIdx.x; img < n_img; img += gridDim.x) {
         const float2 *src = in + base_of(img);
-#pragma unroll
-        for (int k = 0; k < kFft2dPer; ++k) {
-            const int i = tid + k * 1024;
-            if (i < NN) pre[k] = src[i];
-        }
-    };
-    int64_t img = blockIdx.x;
-    if (img < n_img) load(img);
-    for (; img < n_img; img += gridDim.x) {
-#pragma unroll
-        for (int k = 0; k < kFft2dPer; ++k) {
-            const int i = tid + k * 1024;
-            if (i < NN) {
-                const int r = i / N, col = i % N;
-                float2 v = pre[k];
-                if ((r + col) & 1) v = make_float2(-v.x, -v.y);
-                sbuf[r * pitch + col] = v;
-            }
+        for (int i = tid; i < NN; i += blockDim.x) {
+            const int r = i / N, col = i % N;
+            float2 v = src[i];
+            if ((r + col) & 1) v = make_float2(-v.x, -v.y);
+            sbuf[r * pitch + col] = v;
         }
         __syncthreads();
-        if (img + gridDim.x < n_img) load(img + gridDim.x);
         for (int ax = 0; ax < 2; ++ax) {
             int Ns = 1;
             for (int ps = 0; ps < rad.n; ++ps) {
