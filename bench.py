@@ -706,7 +706,7 @@ def main():
                 "frac": bytes_step / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_fused_pair<1, false>",
+            "kernel": "k_fused_pair<1, false, false>",
             "achieved": achieved,
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
