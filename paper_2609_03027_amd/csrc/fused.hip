@@ -208,7 +208,10 @@ __device__ __forceinline__ void jones_taps(const uint4 *r1, const uint4 *r2, con
 // frames[t / frame_len] (stride fstride floats) and restarted; acc is not
 // touched.  JN: Jones kernels (two feeds) -- each tap has three entry rows
 // holding the weights x<-x, x<-y, y<-x, y<-y, and both feeds feed both
-// grids.
+// grids.  Time slices: workgroup b takes item b % n_items and samples
+// [s tps, (s + 1) tps) of slice s = b / n_items; with `part` given it stores
+// its sums to part + s part_stride + it.part_off (k_fused_reduce adds the
+// slices), else it adds them to acc.
 template <int M, int P, int AR, bool FR, bool JN>
 __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(const FusedItem *__restrict__ items,
                                                       const uint4 *__restrict__ entries,
@@ -217,7 +220,9 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
                                                       float *__restrict__ acc,
                                                       int32_t *__restrict__ autos,
                                                       int frame_len, float *__restrict__ frames,
-                                                      int64_t fstride, int vb) {
+                                                      int64_t fstride, int vb, int n_items,
+                                                      int tps, float *__restrict__ part,
+                                                      int64_t part_stride) {
     constexpr int T = FCfg<M>::T, RA = FCfg<M>::RA, ROW = FCfg<M>::ROW;
     constexpr int NPIX = M * M / T;
     constexpr int NPROD = P == 2 ? 4 : 1;
@@ -227,9 +232,11 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
     grid.g = reinterpret_cast<decltype(grid.g)>(smem);
     float4 *stage = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) + P * GSZ);
 
-    const FusedItem it = items[blockIdx.x];
+    const int slice = blockIdx.x / n_items;
+    const FusedItem it = items[blockIdx.x % n_items];
     if (it.c < 0) return;
     const int tid = threadIdx.x;
+    const int t_begin = slice * tps, t_stop = min(n_time, t_begin + tps);
 
     float2 tw[RA];
     {
@@ -266,7 +273,7 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
         for (int q = 0; q < NPROD; ++q) sa[k][q] = 0;
 
-    for (int t = 0; t < n_time; ++t) {
+    for (int t = t_begin; t < t_stop; ++t) {
         const uint8_t *vt = vbase + (int64_t)t * volt_t_stride;
 #pragma unroll
         for (int k = 0; k < AR; ++k) {
@@ -347,15 +354,21 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
     const int N = it.N, R = it.R;
     const int64_t plane = (int64_t)N * N;
     if (!FR) {
+        float *base = part ? part + slice * part_stride + it.part_off : acc + it.img_off;
 #pragma unroll
         for (int k = 0; k < NPIX; ++k) {
             int row, col;
             slot_position<M>(tid, k, row, col);
             const int ky = R * unscramble<M>(row) + it.oy;
             const int kx = R * unscramble<M>(col) + it.ox;
-            float *dst = acc + it.img_off + (int64_t)ky * N + kx;
+            float *dst = base + (int64_t)ky * N + kx;
 #pragma unroll
-            for (int q = 0; q < NPROD; ++q) dst[q * plane] += av[k][q];
+            for (int q = 0; q < NPROD; ++q) {
+                if (part)
+                    dst[q * plane] = av[k][q];
+                else
+                    dst[q * plane] += av[k][q];
+            }
         }
     }
     if (own_autos) {
@@ -620,6 +633,22 @@ __global__ void k_autos(const uint8_t *__restrict__ volt, int64_t volt_t_stride,
     }
 }
 
+// acc[img_off + i] += sum over slices s = 0 .. S-1 of part[s part_stride +
+// part_off + i], in slice order, for every channel of one fused group.
+// Grid: (float blocks, channels of the group).
+__global__ __launch_bounds__(256) void k_fused_reduce(const GroupChan *__restrict__ chans, int S,
+                                                      const float *__restrict__ part,
+                                                      int64_t part_stride,
+                                                      float *__restrict__ acc) {
+    const GroupChan g = chans[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < g.n_floats;
+         i += (int64_t)gridDim.x * 256) {
+        float s = 0.f;
+        for (int k = 0; k < S; ++k) s += part[k * part_stride + g.part_off + i];
+        acc[g.img_off + i] += s;
+    }
+}
+
 // ------------------------------------------------------------ host build
 static int threads_of(int M) {
     return M == 64 ? FCfg<64>::T : M == 32 ? FCfg<32>::T : FCfg<16>::T;
@@ -770,12 +799,57 @@ static void xcd_layout(std::vector<FusedItem> &items, int C) {
     items.swap(laid);
 }
 
-static epic_status upload_group(FusedGroup *g, std::vector<FusedItem> &items,
+// Time slices of a one-class-per-item group: enough workgroups for about
+// four waves per SIMD (1024 SIMDs), at most 16 slices; each channel's
+// images get a place in the group's partial image set.
+static epic_status slice_group(epic_plan p, FusedGroup *g, std::vector<FusedItem> &items,
+                               hipStream_t s) {
+    const int waves_per_wg = threads_of(g->M) / 64;
+    int64_t real = 0;
+    for (const FusedItem &fi : items) real += fi.c >= 0;
+    const int64_t waves = real * waves_per_wg;
+    g->slices = (int)std::max<int64_t>(1, std::min<int64_t>(16, (4096 + waves - 1) / std::max<int64_t>(1, waves)));
+    if (g->kind != 0) g->slices = 1;
+    std::vector<int64_t> off(p->C, -1);
+    std::vector<GroupChan> chans;
+    int64_t n = 0;
+    for (FusedItem &fi : items) {
+        if (fi.c < 0) continue;
+        if (off[fi.c] < 0) {
+            off[fi.c] = n;
+            const int64_t nf = (int64_t)p->n_prod * fi.N * fi.N;
+            chans.push_back(GroupChan{fi.img_off, n, nf});
+            n += nf;
+        }
+        fi.part_off = off[fi.c];
+    }
+    g->part_floats = n;
+    g->n_chans = (int)chans.size();
+    epic_status st;
+    if ((st = g->chans.alloc(sizeof(GroupChan) * std::max<size_t>(1, chans.size())))) return st;
+    if (!chans.empty())
+        EPIC_HIP(hipMemcpyAsync(g->chans.p, chans.data(), sizeof(GroupChan) * chans.size(),
+                                hipMemcpyHostToDevice, s));
+    return EPIC_OK;
+}
+
+// Place the sliced groups' partial image sets in the accumulator's working
+// memory after what the plan already needs there.
+void fused_assign_work(epic_plan p) {
+    for (FusedGroup *g : p->groups) {
+        if (g->slices <= 1) continue;
+        g->work_off = (p->work_bytes + 255) / 256 * 256;
+        p->work_bytes = g->work_off + (int64_t)sizeof(float) * g->slices * g->part_floats;
+    }
+}
+
+static epic_status upload_group(epic_plan p, FusedGroup *g, std::vector<FusedItem> &items,
                                 std::vector<uint4> &all, int C, hipStream_t s) {
     xcd_layout(items, C);
+    epic_status st;
+    if ((st = slice_group(p, g, items, s))) return st;
     g->n_items = (int)items.size();
     g->host_items = items;
-    epic_status st;
     if ((st = g->items.alloc(sizeof(FusedItem) * items.size()))) return st;
     if ((st = g->entries.alloc(sizeof(uint4) * all.size()))) return st;
     EPIC_HIP(hipMemcpyAsync(g->items.p, items.data(), sizeof(FusedItem) * items.size(),
@@ -817,7 +891,7 @@ epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vect
             g->M = 64;
             g->kind = 1;
             p->groups.push_back(g);
-            epic_status st = upload_group(g, items, all, p->C, s);
+            epic_status st = upload_group(p, g, items, all, p->C, s);
             if (st) return st;
         }
     }
@@ -835,7 +909,7 @@ epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vect
         auto *g = new FusedGroup();
         g->M = M;
         p->groups.push_back(g);
-        epic_status st = upload_group(g, items, all, p->C, s);
+        epic_status st = upload_group(p, g, items, all, p->C, s);
         if (st) return st;
     }
     return EPIC_OK;
@@ -860,30 +934,41 @@ epic_status lds_ready(const void *kern, size_t lds) {
     return EPIC_OK;
 }
 
+// `part`: the group's partial image sets (time slices), or nullptr.
 template <int M, int P, int AR, bool FR, bool JN>
 static epic_status launch_fused_fr(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
                                    int A, int vb, int n_time, float *acc, int32_t *autos,
-                                   const FrameOut &fo, hipStream_t s, bool dry) {
+                                   const FrameOut &fo, hipStream_t s, bool dry, float *part) {
     constexpr int T = FCfg<M>::T, GSZ = M * FCfg<M>::ROW;
     const size_t lds = sizeof(float2) * P * GSZ + sizeof(float4) * (size_t)A;
     auto kern = k_fused<M, P, AR, FR, JN>;
     epic_status st = lds_ready(reinterpret_cast<const void *>(kern), lds);
     if (st || dry) return st;
-    hipLaunchKernelGGL(kern, dim3(g->n_items), dim3(T), lds, s, g->items.as<FusedItem>(),
+    // slices in use: at most one per sample
+    const bool sliced = part && !FR && g->slices > 1 && acc;
+    const int tps = sliced ? (n_time + g->slices - 1) / g->slices : n_time;
+    const int used = sliced ? (n_time + tps - 1) / tps : 1;
+    hipLaunchKernelGGL(kern, dim3(g->n_items * used), dim3(T), lds, s, g->items.as<FusedItem>(),
                        g->entries.as<uint4>(), d_volt, vstride, A, n_time, acc, autos, fo.len,
-                       fo.out, fo.stride, vb);
+                       fo.out, fo.stride, vb, g->n_items, tps, sliced ? part : nullptr,
+                       g->part_floats);
     EPIC_HIP(hipGetLastError());
+    if (sliced) {
+        hipLaunchKernelGGL(k_fused_reduce, dim3(64, g->n_chans), dim3(256), 0, s,
+                           g->chans.as<GroupChan>(), used, part, g->part_floats, acc);
+        EPIC_HIP(hipGetLastError());
+    }
     return EPIC_OK;
 }
 
 template <int M, int P, int AR, bool JN>
 static epic_status launch_fused_ar(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
                                    int A, int vb, int n_time, float *acc, int32_t *autos,
-                                   const FrameOut &fo, hipStream_t s, bool dry) {
+                                   const FrameOut &fo, hipStream_t s, bool dry, float *part) {
     return fo.len ? launch_fused_fr<M, P, AR, true, JN>(g, d_volt, vstride, A, vb, n_time, acc,
-                                                        autos, fo, s, dry)
+                                                        autos, fo, s, dry, nullptr)
                   : launch_fused_fr<M, P, AR, false, JN>(g, d_volt, vstride, A, vb, n_time, acc,
-                                                         autos, fo, s, dry);
+                                                         autos, fo, s, dry, part);
 }
 
 // Element rounds per thread: 1, 2 or 4; above 4 T the self terms come from a
@@ -891,15 +976,16 @@ static epic_status launch_fused_ar(const FusedGroup *g, const uint8_t *d_volt, i
 template <int M, int P, bool JN>
 static epic_status launch_fused(const FusedGroup *g, const uint8_t *d_volt, int64_t vstride,
                                 int A, int vb, int n_time, float *acc, int32_t *autos,
-                                const FrameOut &fo, hipStream_t s, bool dry) {
+                                const FrameOut &fo, hipStream_t s, bool dry, float *part) {
     constexpr int T = FCfg<M>::T;
     if (A <= T)
         return launch_fused_ar<M, P, 1, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s,
-                                            dry);
+                                            dry, part);
     if (A <= 2 * T)
         return launch_fused_ar<M, P, 2, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s,
-                                            dry);
-    return launch_fused_ar<M, P, 4, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
+                                            dry, part);
+    return launch_fused_ar<M, P, 4, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry,
+                                        part);
 }
 
 template <int AR, bool FR, bool JN>
@@ -967,22 +1053,25 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
         epic_status st = EPIC_OK;
         const int A = p->A;
         const int vb = p->vb;
+        float *part = (acc && g->slices > 1)
+                          ? reinterpret_cast<float *>(acc->d_work.as<char>() + g->work_off)
+                          : nullptr;
         if (g->kind == 1 && p->J == 4) {
             st = launch_pair<true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
         } else if (g->kind == 1) {
             st = launch_pair<false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
         } else if (p->J == 4) {
-            if (g->M == 64) st = launch_fused<64, 2, true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
-            if (g->M == 32) st = launch_fused<32, 2, true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
-            if (g->M == 16) st = launch_fused<16, 2, true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 64) st = launch_fused<64, 2, true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry, part);
+            if (g->M == 32) st = launch_fused<32, 2, true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry, part);
+            if (g->M == 16) st = launch_fused<16, 2, true>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry, part);
         } else if (p->P == 2) {
-            if (g->M == 64) st = launch_fused<64, 2, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
-            if (g->M == 32) st = launch_fused<32, 2, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
-            if (g->M == 16) st = launch_fused<16, 2, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 64) st = launch_fused<64, 2, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry, part);
+            if (g->M == 32) st = launch_fused<32, 2, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry, part);
+            if (g->M == 16) st = launch_fused<16, 2, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry, part);
         } else {
-            if (g->M == 64) st = launch_fused<64, 1, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
-            if (g->M == 32) st = launch_fused<32, 1, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
-            if (g->M == 16) st = launch_fused<16, 1, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry);
+            if (g->M == 64) st = launch_fused<64, 1, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry, part);
+            if (g->M == 32) st = launch_fused<32, 1, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry, part);
+            if (g->M == 16) st = launch_fused<16, 1, false>(g, d_volt, vstride, A, vb, n_time, a, au, fo, gs, dry, part);
         }
         if (st) return st;
     }

@@ -74,6 +74,12 @@ struct FusedItem {
     int64_t img_off;     // float offset of channel c in the image set
     int32_t ylo;         // paired items: first grid row of the M-row window
     int32_t pad;
+    int64_t part_off;    // float offset of channel c in its group's partial image set
+};
+
+// One channel of a fused group, for the reduction of time-slice partial sums.
+struct GroupChan {
+    int64_t img_off, part_off, n_floats;
 };
 
 // A group of fused items that share one sub-transform size M.
@@ -84,6 +90,15 @@ struct FusedGroup {
     DevBuf items;     // FusedItem[n_items]
     DevBuf entries;   // uint4 gather entries
     std::vector<FusedItem> host_items;
+    // Time slices: with too few waves to fill the chip, each item's samples
+    // are split over `slices` workgroups, each storing its Eq. 2 sums to its
+    // own partial image set (part_floats floats, in the accumulator's working
+    // memory at byte offset work_off); k_fused_reduce adds them in order.
+    int slices = 1;
+    int64_t part_floats = 0;
+    int64_t work_off = 0;
+    int n_chans = 0;
+    DevBuf chans;     // GroupChan[n_chans]
 };
 
 // Direct DFT-as-GEMM (reduced-precision variants): beam matrix per channel in
@@ -283,6 +298,7 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
                              bool dry = false, const FrameOut &fo = FrameOut());
 epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                              hipStream_t s);
+void fused_assign_work(epic_plan p);
 // One gather tap: destination cell (LDS index), element, complex weight
 // (x-to-x with Jones kernels, whose other three weights xy, yx, yy are in m).
 struct GatherTap {

@@ -272,6 +272,7 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
         if ((st = fused_build(p, j0, w, s))) return st;
         if ((st = banded_build(p, j0, w, s))) return st;
         p->work_bytes = p->band.scratch_bytes + p->band.part_bytes;
+        fused_assign_work(p);
     } else if (p->precision == EPIC_FIXED16) {
         if ((st = fixed_build(p, j0, w, s))) return st;
         p->work_bytes = p->fixed.part_bytes;
@@ -285,7 +286,8 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
                             &p->d_img_off, &p->d_grid_off, &p->d_csr_off, &p->d_csr_base,
                             &p->d_csr_ant, &p->d_csr_w, &p->d_twid, &p->d_sz_chans})
         p->bytes_plan += (int64_t)b->bytes;
-    for (auto *g : p->groups) p->bytes_plan += (int64_t)(g->items.bytes + g->entries.bytes);
+    for (auto *g : p->groups)
+        p->bytes_plan += (int64_t)(g->items.bytes + g->entries.bytes + g->chans.bytes);
     p->bytes_plan += (int64_t)(p->band.d_chans.bytes + p->band.d_items.bytes +
                                p->band.d_entries.bytes + p->band.d_mf.bytes);
     for (epic::DevBuf *b : {&p->gemm.a_hi, &p->gemm.a_lo, &p->gemm.d_blk_off,
