@@ -799,17 +799,61 @@ static void xcd_layout(std::vector<FusedItem> &items, int C) {
     items.swap(laid);
 }
 
-// Time slices of a one-class-per-item group: enough workgroups for about
-// four waves per SIMD (1024 SIMDs), at most 16 slices; each channel's
-// images get a place in the group's partial image set.
+// Workgroups of a one-class-per-item group's kernel that the device runs at
+// once (occupancy API over all CUs), or 0 if unknown.
+template <int M, int P, bool JN>
+static int64_t fused_slots_t(int A) {
+    constexpr int T = FCfg<M>::T, GSZ = M * FCfg<M>::ROW;
+    const size_t lds = sizeof(float2) * P * GSZ + sizeof(float4) * (size_t)A;
+    const void *k = A <= T       ? reinterpret_cast<const void *>(k_fused<M, P, 1, false, JN>)
+                    : A <= 2 * T ? reinterpret_cast<const void *>(k_fused<M, P, 2, false, JN>)
+                                 : reinterpret_cast<const void *>(k_fused<M, P, 4, false, JN>);
+    if (lds_ready(k, lds)) return 0;
+    int dev = 0, n_cu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, T, lds) != hipSuccess)
+        return 0;
+    return (int64_t)n_cu * per_cu;
+}
+
+static int64_t fused_slots(epic_plan p, int M) {
+    const bool jn = p->J == 4;
+    if (p->P == 1) {
+        return M == 64 ? fused_slots_t<64, 1, false>(p->A)
+               : M == 32 ? fused_slots_t<32, 1, false>(p->A) : fused_slots_t<16, 1, false>(p->A);
+    }
+    if (jn)
+        return M == 64 ? fused_slots_t<64, 2, true>(p->A)
+               : M == 32 ? fused_slots_t<32, 2, true>(p->A) : fused_slots_t<16, 2, true>(p->A);
+    return M == 64 ? fused_slots_t<64, 2, false>(p->A)
+           : M == 32 ? fused_slots_t<32, 2, false>(p->A) : fused_slots_t<16, 2, false>(p->A);
+}
+
+// Time slices of a one-class-per-item group: at least enough workgroups for
+// about four waves per SIMD (1024 SIMDs), then the fewest slices (at most 16)
+// whose last round of resident workgroups is at least 90 % full; each
+// channel's images get a place in the group's partial image set.
 static epic_status slice_group(epic_plan p, FusedGroup *g, std::vector<FusedItem> &items,
                                hipStream_t s) {
     const int waves_per_wg = threads_of(g->M) / 64;
     int64_t real = 0;
     for (const FusedItem &fi : items) real += fi.c >= 0;
     const int64_t waves = real * waves_per_wg;
-    g->slices = (int)std::max<int64_t>(1, std::min<int64_t>(16, (4096 + waves - 1) / std::max<int64_t>(1, waves)));
-    if (g->kind != 0) g->slices = 1;
+    int S = (int)std::max<int64_t>(1, std::min<int64_t>(16, (4096 + waves - 1) / std::max<int64_t>(1, waves)));
+    const int64_t slots = g->kind == 0 ? fused_slots(p, g->M) : 0;
+    if (slots > 0) {
+        // workgroups launched = padded items x slices
+        const int64_t wgs = (int64_t)items.size();
+        for (int s2 = S; s2 <= 16; ++s2) {
+            const double rounds = (double)(wgs * s2) / (double)slots;
+            if (rounds / std::ceil(rounds) >= 0.9 || s2 == 16) {
+                S = s2;
+                break;
+            }
+        }
+    }
+    g->slices = g->kind == 0 ? S : 1;
     std::vector<int64_t> off(p->C, -1);
     std::vector<GroupChan> chans;
     int64_t n = 0;
