@@ -2,6 +2,8 @@
 registers) against the FP64 oracle: forced on small grids, mixed with fused
 channels of other sizes, across sample-chunk boundaries, under graph capture,
 and its determinism."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -46,6 +48,20 @@ def test_square_radix_side_crosses_the_sample_chunk():
     _say("case banded square radix N=64, 300 samples")
     got = _run(wl, pos, volt, sub_n=[BANDED], chunks=2)
     _check(got, oracle_images(volt, pos, wl, range(1)), "banded-sq64")
+
+
+@pytest.mark.parametrize("n_ant,n_pol", [(256, 1), (250, 2)])
+def test_square_radix_single_feed_and_odd_element_count(n_ant, n_pol):
+    # one feed (no y block in the gather), and an element count whose
+    # voltage blocks are not a multiple of 16 bytes
+    full = dataclasses.replace(synth.workload("ska"), n_ant=n_ant, n_pol=n_pol)
+    chans = [int(np.nonzero(full.grid_n == 64)[0][-1])]
+    wl = full.subset(chans).with_time(10)
+    pos = synth.antenna_layout(full)
+    volt = synth.voltages(full.with_time(10), pos, chans=chans)
+    _say(f"case banded square radix N=64, {n_ant} elements x {n_pol} feeds, 10 samples")
+    got = _run(wl, pos, volt, sub_n=[BANDED], chunks=2)
+    _check(got, oracle_images(volt, pos, wl, range(1)), f"banded-sq64-{n_ant}x{n_pol}")
 
 
 def test_banded_and_fused_channels_of_mixed_sizes():

@@ -51,3 +51,16 @@ def test_fp16_fourstep_rounds_alternate_scratch_halves():
     _say("case fp16 four-step: 16 elements on 256^2, 300 samples in one call (two rounds)")
     _check(_run(wl, pos, volt, precision=1), oracle_images(volt, pos, wl, [0]),
            "fp16-4step-rounds", TOL["max"], TOL["rms"])
+
+
+@pytest.mark.parametrize("n_ant,n_pol", [(15, 2), (16, 1)])
+def test_fp16_fourstep_odd_element_count_and_single_feed(n_ant, n_pol):
+    # an element count whose voltage blocks are not a multiple of 16 bytes,
+    # and one feed (k_band_rows_mf<1> / k_band_cols_mf<1>)
+    wl = dataclasses.replace(synth.workload("tiny2"), grid_n=np.array([256]), n_time=12,
+                             n_ant=n_ant, n_pol=n_pol)
+    pos = synth.antenna_layout(wl)
+    volt = synth.voltages(wl, pos)
+    _say(f"case fp16 four-step: {n_ant} elements x {n_pol} feeds on 256^2, 12 samples in 2 calls")
+    _check(_run(wl, pos, volt, precision=1, chunks=2), oracle_images(volt, pos, wl, [0]),
+           f"fp16-4step-{n_ant}x{n_pol}", TOL["max"], TOL["rms"])
