@@ -24,11 +24,21 @@ typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// Operand element storage per precision.
+// Operand element storage per precision, and the K extent of one MFMA step
+// (16 x 16 x 32 for FP16 / BF16, 16 x 16 x 128 for FP8).
 template <int DT> struct Op;
-template <> struct Op<EPIC_F16_MFMA> { typedef uint16_t E; static constexpr int BYTES = 2; };
-template <> struct Op<EPIC_BF16X2_MFMA> { typedef uint16_t E; static constexpr int BYTES = 2; };
-template <> struct Op<EPIC_F8E4M3_MFMA> { typedef uint8_t E; static constexpr int BYTES = 1; };
+template <> struct Op<EPIC_F16_MFMA> {
+    typedef uint16_t E;
+    static constexpr int BYTES = 2, KSTEP = 32;
+};
+template <> struct Op<EPIC_BF16X2_MFMA> {
+    typedef uint16_t E;
+    static constexpr int BYTES = 2, KSTEP = 32;
+};
+template <> struct Op<EPIC_F8E4M3_MFMA> {
+    typedef uint8_t E;
+    static constexpr int BYTES = 1, KSTEP = 128;
+};
 
 __device__ __forceinline__ uint16_t to_f16(float x) {
     _Float16 h = (_Float16)x;
@@ -46,11 +56,17 @@ __device__ __forceinline__ uint8_t to_e4m3(float x) {
 }
 
 // Position of B' element (row r, column k) in the MFMA A-operand layout of a
-// channel: [row block of 16][K step of 32][lane][8], lane = 16 (k%32 / 8) + r%16.
+// channel: [row block of 16][K step of S][lane][S / 4], lane = 16 (k%S / (S/4))
+// + r%16, with S = Op::KSTEP; KS counts K in units of 32.  Lane l of the
+// B operand holds the same k range of column l % 16, so the products pair
+// equal k whatever order the hardware sums a step in.
+template <int S>
 __device__ __forceinline__ int64_t a_index(int64_t blk0, int KS, int r, int k) {
-    const int rb = r >> 4, rr = r & 15, ks = k >> 5, kk = k & 31;
-    const int lane = (kk >> 3) * 16 + rr;
-    return (((blk0 + rb) * KS + ks) * 64 + lane) * 8 + (kk & 7);
+    constexpr int Q = S / 4;
+    const int nks = KS * 32 / S;
+    const int rb = r >> 4, rr = r & 15, ks = k / S, kk = k % S;
+    const int lane = (kk / Q) * 16 + rr;
+    return (((blk0 + rb) * nks + ks) * 64 + lane) * Q + (kk % Q);
 }
 
 // Beam matrix of channel c in FP64, one thread per pixel, rounded into the
@@ -106,7 +122,7 @@ __global__ __launch_bounds__(256) void k_plan_beam(const int2 *__restrict__ j0,
         const int rr[4] = {2 * pix, 2 * pix, 2 * pix + 1, 2 * pix + 1};
         const int kk[4] = {a, Ap + a, a, Ap + a};
         for (int q = 0; q < 4; ++q) {
-            const int64_t ix = a_index(b0, KS, rr[q], kk[q]);
+            const int64_t ix = a_index<Op<DT>::KSTEP>(b0, KS, rr[q], kk[q]);
             const float x = (float)v[q];
             if (DT == EPIC_F16_MFMA) {
                 hi[ix] = to_f16(x);
@@ -168,10 +184,12 @@ template <> struct Frag<EPIC_BF16X2_MFMA> {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
 };
+typedef int i8v __attribute__((ext_vector_type(8)));
 template <> struct Frag<EPIC_F8E4M3_MFMA> {
-    typedef long T;
+    typedef i8v T;
+    // e4m3 operands (format 0) without block scales
     static __device__ __forceinline__ f4v mma(T a, T b, f4v c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
     }
 };
 
@@ -182,13 +200,19 @@ __device__ __forceinline__ float swap_pair(float x) {
 
 // One workgroup = 8 waves = 128 RB rows of B' of one channel, every column
 // tile (16 columns) of the call.  Each wave keeps its RB row blocks (x KS
-// K-steps) of the A operand in registers; column tiles are staged in LDS.
+// K-steps) of the A operand in registers; column tiles are staged in LDS,
+// double-buffered: the next tile's global loads are issued before the
+// current tile's products and written to the other buffer after them, so
+// one barrier per tile remains and the loads overlap the matrix cores.
+// The A operand alone takes 128 VGPRs, so one workgroup (two waves per
+// SIMD) is what a CU holds; the kernel may use up to 256 VGPRs.
 // MFMA 16x16x32 output layout: lane l holds rows 4 (l / 16) + i, column l % 16.
 // Rows 4g + {0, 1} are pixel 2g (re, im), 4g + {2, 3} pixel 2g + 1.  With two
 // feeds the columns alternate (t, X), (t, Y): even lanes keep XX and Re XY,
 // odd lanes YY and Im XY, exchanging the other feed with lane ^ 1.
 template <int DT, int P, int RB, int KS>
-__global__ __launch_bounds__(512) void k_dftgemm(const uint8_t *__restrict__ a_hi,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_dftgemm(const uint8_t *__restrict__ a_hi,
                                                  const uint8_t *__restrict__ a_lo,
                                                  const uint8_t *__restrict__ vop,
                                                  const int4 *__restrict__ chan,
@@ -198,11 +222,15 @@ __global__ __launch_bounds__(512) void k_dftgemm(const uint8_t *__restrict__ a_h
                                                  int cols_pad, float *__restrict__ acc) {
     typedef typename Frag<DT>::T FT;
     typedef typename Op<DT>::E E;
-    constexpr int EB = Op<DT>::BYTES;
+    constexpr int EB = Op<DT>::BYTES, S = Op<DT>::KSTEP, Q = S / 4;
     constexpr int K = 32 * KS;                  // = 2 Ap
+    constexpr int NKS = K / S;                  // MFMA steps along K
+    static_assert(K % S == 0, "K must be a whole number of MFMA steps");
     constexpr int CSTRIDE = K * EB + 16;        // LDS bytes per column (padded)
     constexpr int NPROD = P == 2 ? 4 : 1;
-    __shared__ __attribute__((aligned(16))) uint8_t tile[16 * CSTRIDE];
+    constexpr int PIECES = 16 * (K * EB / 16);            // 16-byte pieces per tile
+    constexpr int PPT = (PIECES + 511) / 512;             // per thread
+    __shared__ __attribute__((aligned(16))) uint8_t tiles[2][16 * CSTRIDE];
 
     const int c = blockIdx.y;
     const int N = chan[c].x;
@@ -212,16 +240,16 @@ __global__ __launch_bounds__(512) void k_dftgemm(const uint8_t *__restrict__ a_h
     if (blockIdx.x * 8 * RB * 16 >= rows) return;  // whole workgroup idle
     const bool live = blk_first * 16 < rows;
 
-    FT ah[RB][KS], al[RB][KS];
+    FT ah[RB][NKS], al[RB][NKS];
     const int64_t b0 = blk_off[c];
     const int nblk = rows / 16;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
+        for (int s = 0; s < NKS; ++s) {
             // row blocks past the channel's last one load block 0 (never stored)
             const int blk = (live && blk_first + r < nblk) ? blk_first + r : 0;
-            const int64_t ix = (((b0 + blk) * KS + s) * 64 + lane) * 8;
+            const int64_t ix = (((b0 + blk) * NKS + s) * 64 + lane) * Q;
             ah[r][s] = *reinterpret_cast<const FT *>(a_hi + ix * EB);
             if (DT == EPIC_BF16X2_MFMA) al[r][s] = *reinterpret_cast<const FT *>(a_lo + ix * EB);
         }
@@ -234,23 +262,42 @@ __global__ __launch_bounds__(512) void k_dftgemm(const uint8_t *__restrict__ a_h
 
     const uint8_t *vc = vop + (int64_t)c * cols_pad * K * EB;
     const int g = lane >> 4, col = lane & 15;
-    for (int ct = 0; ct < cols_pad; ct += 16) {
-        // stage 16 columns x K operands (16-byte pieces)
-        const int pieces = 16 * (K * EB / 16);
-        for (int i = threadIdx.x; i < pieces; i += 512) {
+    // 16 columns x K operands of a tile, as 16-byte pieces: piece i is
+    // column i / (K EB / 16) at byte offset 16 (i % (K EB / 16))
+    uint4 pre[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        pre[u] = make_uint4(0u, 0u, 0u, 0u);
+        const int i = threadIdx.x + 512 * u;
+        if (i < PIECES) {
             const int cl = i / (K * EB / 16), off = (i % (K * EB / 16)) * 16;
-            *reinterpret_cast<uint4 *>(tile + cl * CSTRIDE + off) =
-                *reinterpret_cast<const uint4 *>(vc + ((int64_t)(ct + cl) * K) * EB + off);
+            *reinterpret_cast<uint4 *>(tiles[0] + cl * CSTRIDE + off) =
+                *reinterpret_cast<const uint4 *>(vc + (int64_t)cl * K * EB + off);
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    for (int ct = 0, buf = 0; ct < cols_pad; ct += 16, buf ^= 1) {
+        const uint8_t *tile = tiles[buf];
+        const bool more = ct + 16 < cols_pad;
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < PPT; ++u) {
+                const int i = threadIdx.x + 512 * u;
+                if (i < PIECES) {
+                    const int cl = i / (K * EB / 16), off = (i % (K * EB / 16)) * 16;
+                    pre[u] = *reinterpret_cast<const uint4 *>(
+                        vc + ((int64_t)(ct + 16 + cl) * K) * EB + off);
+                }
+            }
+        }
         if (live) {
             f4v d[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) d[r] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
+            for (int s = 0; s < NKS; ++s) {
                 const FT b = *reinterpret_cast<const FT *>(tile + col * CSTRIDE +
-                                                           (32 * s + 8 * g) * EB);
+                                                           (S * s + Q * g) * EB);
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
                     d[r] = Frag<DT>::mma(ah[r][s], b, d[r]);
@@ -273,6 +320,17 @@ __global__ __launch_bounds__(512) void k_dftgemm(const uint8_t *__restrict__ a_h
                     } else {
                         sum[r][q][0] += vr * vr + vi * vi;
                     }
+                }
+            }
+        }
+        // the other buffer was last read before the previous barrier
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < PPT; ++u) {
+                const int i = threadIdx.x + 512 * u;
+                if (i < PIECES) {
+                    const int cl = i / (K * EB / 16), off = (i % (K * EB / 16)) * 16;
+                    *reinterpret_cast<uint4 *>(tiles[buf ^ 1] + cl * CSTRIDE + off) = pre[u];
                 }
             }
         }
@@ -328,7 +386,7 @@ static int rb_for(int dt) { return dt == EPIC_F8E4M3_MFMA ? 4 : dt == EPIC_F16_M
 template <int DT>
 static epic_status build_dt(epic_plan p, hipStream_t s) {
     GemmPlan &gp = p->gemm;
-    const int64_t n = gp.n_blocks * gp.KS * 64 * 8;  // elements
+    const int64_t n = gp.n_blocks * gp.KS * 64 * 8;  // elements (16 rows x 32 KS each)
     epic_status st = gp.a_hi.alloc(n * Op<DT>::BYTES);
     if (st) return st;
     if (DT == EPIC_BF16X2_MFMA && (st = gp.a_lo.alloc(n * Op<DT>::BYTES))) return st;
@@ -351,6 +409,8 @@ epic_status gemm_build(epic_plan p, hipStream_t s) {
     gp.KS = ks_for(p->A);
     if (gp.KS == 0)
         return fail(EPIC_ERR_UNSUPPORTED, "DFT-GEMM variants need n_ant <= 256 (small arrays)");
+    // FP8 steps take 128 of K = 2 Ap: pad to at least 64 elements
+    if (p->precision == EPIC_F8E4M3_MFMA) gp.KS = std::max(gp.KS, 4);
     for (const auto &c : p->ch)
         if ((int64_t)c.N * c.N > 65536)
             return fail(EPIC_ERR_UNSUPPORTED, "DFT-GEMM variants need grids of at most 256 x 256");
@@ -393,9 +453,11 @@ epic_status gemm_build(epic_plan p, hipStream_t s) {
         default: return fail(EPIC_ERR_UNSUPPORTED, "unknown precision");
     }
     if (st) return st;
-    // operand scratch for up to t_chunk samples per launch
+    // operand scratch for up to t_chunk samples per launch: every launch
+    // reads the whole beam matrix once (4.3 GB in FP16 for 128 channels of
+    // 128^2 and 256 elements), so launches take up to 1024 samples
     const int eb = p->precision == EPIC_F8E4M3_MFMA ? 1 : 2;
-    gp.t_chunk = 256;
+    gp.t_chunk = 1024;
     gp.cols_pad = ((gp.t_chunk * p->P + 15) / 16) * 16;
     gp.vbuf_bytes = (int64_t)p->C * gp.cols_pad * 2 * gp.Ap * eb;
     return EPIC_OK;
@@ -419,9 +481,10 @@ template <int DT, int P>
 static epic_status launch_gemm_ks(epic_plan p, float *acc, const uint8_t *vbuf, int cols_pad,
                                   hipStream_t s) {
     constexpr int RB = DT == EPIC_F8E4M3_MFMA ? 4 : DT == EPIC_F16_MFMA ? 2 : 1;
+    constexpr bool F8 = DT == EPIC_F8E4M3_MFMA;
     switch (p->gemm.KS) {
-        case 1: return launch_gemm<DT, P, RB, 1>(p, acc, vbuf, cols_pad, s);
-        case 2: return launch_gemm<DT, P, RB, 2>(p, acc, vbuf, cols_pad, s);
+        case 1: return launch_gemm<DT, P, RB, F8 ? 4 : 1>(p, acc, vbuf, cols_pad, s);
+        case 2: return launch_gemm<DT, P, RB, F8 ? 4 : 2>(p, acc, vbuf, cols_pad, s);
         case 4: return launch_gemm<DT, P, RB, 4>(p, acc, vbuf, cols_pad, s);
         case 8: return launch_gemm<DT, P, RB, 8>(p, acc, vbuf, cols_pad, s);
         case 16: return launch_gemm<DT, P, RB, 16>(p, acc, vbuf, cols_pad, s);

@@ -66,6 +66,20 @@ def test_lwa_channels_dftgemm(dt):
     assert emax <= TOL[dt][0] and erms <= TOL[dt][1]
 
 
+@pytest.mark.parametrize("dt", [F16, F8])
+def test_dftgemm_call_longer_than_one_launch(dt):
+    # 1100 samples in one call: two launches of the sample chunk (1024 + 76),
+    # 138 double-buffered column tiles in the first
+    wl = synth.workload("tiny2").with_time(1100)
+    pos = synth.antenna_layout(wl)
+    volt = synth.voltages(wl, pos)
+    _say(f"case dftgemm tiny2 {NAMES[dt]} 1100 samples in one call")
+    got = _run(wl, pos, volt, precision=dt)
+    ref = oracle_images(volt, pos, wl, range(wl.n_chan))
+    emax, erms = _record(f"tiny2-1100/{NAMES[dt]}", got, ref)
+    assert emax <= TOL[dt][0] and erms <= TOL[dt][1]
+
+
 def test_dftgemm_rejects_large_arrays():
     # The DFT-GEMM variants hold a beam matrix per element and refuse arrays
     # above 256 elements; an FP16 plan on 256 x 256 grids takes the four-step
