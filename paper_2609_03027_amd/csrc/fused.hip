@@ -197,6 +197,44 @@ __device__ __forceinline__ void jones_taps(const uint4 *r1, const uint4 *r2, con
     sy.y += br * v.y + bi * v.x + cr * v.w + ci * v.z;
 }
 
+// One sample's gather.  Each lane owns whole cells; it loads GB entries at
+// once (their L2 latencies overlap) and then applies them.  Every entry
+// stores the running sum to its cell (the cell's last entry leaves the full
+// sum, padding entries write a slot no pass reads) and the last one restarts
+// it, so the loop body has no per-lane branches.  Entry: x = element |
+// last-tap-of-cell << 31, y = LDS index of the folded cell, z/w = folded
+// complex weight; with Jones kernels rows 1 and 2 follow at +T and +2T.
+template <int T, int P, bool JN>
+__device__ __forceinline__ void gather_cells(Grid<P> grid, const uint4 *ent, int n_iter,
+                                             const float4 *stage) {
+    constexpr int GB = 8, RS = JN ? 3 : 1;
+    float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
+    for (int k0 = 0; k0 < n_iter; k0 += GB) {
+        uint4 e[GB];
+#pragma unroll
+        for (int k = 0; k < GB; ++k) e[k] = ent[(int64_t)min(k0 + k, n_iter - 1) * RS * T];
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            if (k0 + k >= n_iter) break;            // uniform: n_iter is per item
+            const float4 v = stage[e[k].x & 0xFFFFu];
+            const float wr = __uint_as_float(e[k].z), wi = __uint_as_float(e[k].w);
+            sx.x += wr * v.x - wi * v.y;
+            sx.y += wr * v.y + wi * v.x;
+            if (JN) {
+                const int64_t r = (int64_t)(k0 + k) * 3 * T;
+                jones_taps(ent + r + T, ent + r + 2 * T, v, sx, sy);
+            } else if (P == 2) {
+                sy.x += wr * v.z - wi * v.w;
+                sy.y += wr * v.w + wi * v.z;
+            }
+            grid.store(e[k].y, sx, sy);
+            const bool last = (e[k].x >> 31) != 0u;
+            sx = last ? make_float2(0.f, 0.f) : sx;
+            sy = last ? make_float2(0.f, 0.f) : sy;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ kernel
 // One workgroup per item (channel c, class o), looping over all n_time
 // samples.  Gather entry (uint4): x = element | last-tap-of-cell << 31,
@@ -273,14 +311,27 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
         for (int q = 0; q < NPROD; ++q) sa[k][q] = 0;
 
+    // this sample's voltages for elements tid + k T, loaded one sample ahead
+    // (during the previous sample's gather and transform)
+    uint32_t rx[AR], ry[AR];
+#pragma unroll
+    for (int k = 0; k < AR; ++k) {
+        const int a = tid + k * T;
+        rx[k] = ry[k] = 0u;
+        if (a < A && t_begin < t_stop) {
+            const uint8_t *v0 = vbase + (int64_t)t_begin * volt_t_stride;
+            rx[k] = volt_raw(v0, a, vb);
+            ry[k] = P == 2 ? volt_raw(v0, A + a, vb) : 0u;
+        }
+    }
     for (int t = t_begin; t < t_stop; ++t) {
         const uint8_t *vt = vbase + (int64_t)t * volt_t_stride;
 #pragma unroll
         for (int k = 0; k < AR; ++k) {
             const int a = tid + k * T;
             if (a < A) {
-                const int2 vx = volt_at(vt, a, vb);
-                const int2 vy = P == 2 ? volt_at(vt, A + a, vb) : make_int2(0, 0);
+                const int2 vx = volt_dec(rx[k], vb);
+                const int2 vy = P == 2 ? volt_dec(ry[k], vb) : make_int2(0, 0);
                 const int xr = vx.x, xi = vx.y, yr = vy.x, yi = vy.y;
                 stage[a] = make_float4((float)xr, (float)xi, (float)yr, (float)yi);
                 if (own_autos) {
@@ -300,26 +351,18 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
         }
         __syncthreads();
 
-        // gather: this lane owns whole cells, so every cell is written once
-        float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
-        for (int k = 0; k < n_iter; ++k) {
-            const uint4 e = ent[(int64_t)k * (JN ? 3 : 1) * T];
-            const float4 v = stage[e.x & 0xFFFFu];
-            const float wr = __uint_as_float(e.z), wi = __uint_as_float(e.w);
-            sx.x += wr * v.x - wi * v.y;
-            sx.y += wr * v.y + wi * v.x;
-            if (JN) {
-                jones_taps(ent + ((int64_t)k * 3 + 1) * T, ent + ((int64_t)k * 3 + 2) * T, v, sx, sy);
-            } else if (P == 2) {
-                sy.x += wr * v.z - wi * v.w;
-                sy.y += wr * v.w + wi * v.z;
-            }
-            if (e.x >> 31) {
-                grid.store(e.y, sx, sy);
-                sx = make_float2(0.f, 0.f);
-                sy = make_float2(0.f, 0.f);
+        if (t + 1 < t_stop) {
+            const uint8_t *vn = vt + volt_t_stride;
+#pragma unroll
+            for (int k = 0; k < AR; ++k) {
+                const int a = tid + k * T;
+                if (a < A) {
+                    rx[k] = volt_raw(vn, a, vb);
+                    ry[k] = P == 2 ? volt_raw(vn, A + a, vb) : 0u;
+                }
             }
         }
+        gather_cells<T, P, JN>(grid, ent, n_iter, stage);
         __syncthreads();
 
         pass_a<M, P, true>(grid, tid, tw);
@@ -453,13 +496,24 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
 #pragma unroll
         for (int q = 0; q < 4; ++q) sa[k][q] = 0;
 
+    // this sample's voltages for elements tid + k T, loaded one sample ahead
+    uint32_t rx[AR], ry[AR];
+#pragma unroll
+    for (int k = 0; k < AR; ++k) {
+        const int a = tid + k * T;
+        rx[k] = ry[k] = 0u;
+        if (a < A && n_time > 0) {
+            rx[k] = volt_raw(vbase, a, vb);
+            ry[k] = volt_raw(vbase, A + a, vb);
+        }
+    }
     for (int t = 0; t < n_time; ++t) {
         const uint8_t *vt = vbase + (int64_t)t * volt_t_stride;
 #pragma unroll
         for (int k = 0; k < AR; ++k) {
             const int a = tid + k * T;
             if (a < A) {
-                const int2 vx = volt_at(vt, a, vb), vy = volt_at(vt, A + a, vb);
+                const int2 vx = volt_dec(rx[k], vb), vy = volt_dec(ry[k], vb);
                 const int xr = vx.x, xi = vx.y, yr = vy.x, yi = vy.y;
                 stage[a] = make_float4((float)xr, (float)xi, (float)yr, (float)yi);
                 if (own_autos) {
@@ -476,28 +530,18 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
         }
         __syncthreads();
 
-        {
-            float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
-            for (int k = 0; k < n_iter; ++k) {
-                const uint4 e = ent[(int64_t)k * (JN ? 3 : 1) * T];
-                const float4 v = stage[e.x & 0xFFFFu];
-                const float wr = __uint_as_float(e.z), wi = __uint_as_float(e.w);
-                sx.x += wr * v.x - wi * v.y;
-                sx.y += wr * v.y + wi * v.x;
-                if (JN) {
-                    jones_taps(ent + ((int64_t)k * 3 + 1) * T, ent + ((int64_t)k * 3 + 2) * T, v,
-                               sx, sy);
-                } else {
-                    sy.x += wr * v.z - wi * v.w;
-                    sy.y += wr * v.w + wi * v.z;
-                }
-                if (e.x >> 31) {
-                    g.store(e.y, sx, sy);
-                    sx = make_float2(0.f, 0.f);
-                    sy = make_float2(0.f, 0.f);
+        if (t + 1 < n_time) {
+            const uint8_t *vn = vt + volt_t_stride;
+#pragma unroll
+            for (int k = 0; k < AR; ++k) {
+                const int a = tid + k * T;
+                if (a < A) {
+                    rx[k] = volt_raw(vn, a, vb);
+                    ry[k] = volt_raw(vn, A + a, vb);
                 }
             }
         }
+        gather_cells<T, 2, JN>(g, ent, n_iter, stage);
         __syncthreads();
 
         pass_a<M, 2, true>(g, tid, tw);
@@ -753,6 +797,15 @@ static FusedItem build_item(epic_plan p, const std::vector<int> &j0, const std::
     }
     const size_t off = all.size();
     const int n_iter = lpt_pack(taps, T, all, J == 4);
+    // The kernels store the running sum at every entry, so padding (all-zero)
+    // entries point at a slot no pass reads: column M of row (lane mod M).
+    const int rows = J == 4 ? 3 : 1;
+    for (int k = 0; k < n_iter; ++k)
+        for (int l = 0; l < T; ++l) {
+            uint4 &e = all[off + (size_t)k * rows * T + l];
+            if (e.x == 0u && e.y == 0u && e.z == 0u && e.w == 0u)
+                e.y = (uint32_t)((l % M) * ROW + M);
+        }
     FusedItem fi{};
     fi.c = c;
     fi.N = N;
