@@ -204,15 +204,33 @@ __device__ __forceinline__ void jones_taps(const uint4 *r1, const uint4 *r2, con
 // it, so the loop body has no per-lane branches.  Entry: x = element |
 // last-tap-of-cell << 31, y = LDS index of the folded cell, z/w = folded
 // complex weight; with Jones kernels rows 1 and 2 follow at +T and +2T.
+constexpr int GB = 8;   // gather entries in flight per lane
+
+// The entry addresses do not change from sample to sample; the offset
+// passes through an empty asm so the loads are not hoisted out of the
+// sample loop (holding every entry in registers would cost occupancy).
+__device__ __forceinline__ int opaque_zero() {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+}
+
+template <int T, bool JN>
+__device__ __forceinline__ void gather_load(uint4 (&e)[GB], const uint4 *ent, int k0, int n_iter) {
+    const uint4 *p = ent + opaque_zero();
+#pragma unroll
+    for (int k = 0; k < GB; ++k) e[k] = p[(int64_t)min(k0 + k, n_iter - 1) * (JN ? 3 : 1) * T];
+}
+
+// The caller loads the first batch (gather_load(e, ent, 0, n_iter)) ahead of
+// the barrier that publishes the staged voltages, so its latency overlaps
+// the wait; later batches are loaded here.
 template <int T, int P, bool JN>
 __device__ __forceinline__ void gather_cells(Grid<P> grid, const uint4 *ent, int n_iter,
-                                             const float4 *stage) {
-    constexpr int GB = 8, RS = JN ? 3 : 1;
+                                             const float4 *stage, uint4 (&e)[GB]) {
     float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
     for (int k0 = 0; k0 < n_iter; k0 += GB) {
-        uint4 e[GB];
-#pragma unroll
-        for (int k = 0; k < GB; ++k) e[k] = ent[(int64_t)min(k0 + k, n_iter - 1) * RS * T];
+        if (k0) gather_load<T, JN>(e, ent, k0, n_iter);
 #pragma unroll
         for (int k = 0; k < GB; ++k) {
             if (k0 + k >= n_iter) break;            // uniform: n_iter is per item
@@ -326,6 +344,8 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
     }
     for (int t = t_begin; t < t_stop; ++t) {
         const uint8_t *vt = vbase + (int64_t)t * volt_t_stride;
+        uint4 e[GB];
+        gather_load<T, JN>(e, ent, 0, n_iter);
 #pragma unroll
         for (int k = 0; k < AR; ++k) {
             const int a = tid + k * T;
@@ -362,7 +382,7 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
                 }
             }
         }
-        gather_cells<T, P, JN>(grid, ent, n_iter, stage);
+        gather_cells<T, P, JN>(grid, ent, n_iter, stage, e);
         __syncthreads();
 
         pass_a<M, P, true>(grid, tid, tw);
@@ -509,6 +529,8 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
     }
     for (int t = 0; t < n_time; ++t) {
         const uint8_t *vt = vbase + (int64_t)t * volt_t_stride;
+        uint4 e[GB];
+        gather_load<T, JN>(e, ent, 0, n_iter);
 #pragma unroll
         for (int k = 0; k < AR; ++k) {
             const int a = tid + k * T;
@@ -541,7 +563,7 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
                 }
             }
         }
-        gather_cells<T, 2, JN>(g, ent, n_iter, stage);
+        gather_cells<T, 2, JN>(g, ent, n_iter, stage, e);
         __syncthreads();
 
         pass_a<M, 2, true>(g, tid, tw);
