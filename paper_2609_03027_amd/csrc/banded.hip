@@ -57,6 +57,15 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
     return x;
 }
 
+// Raw voltage sample idx (x feed: element a, y feed: A + a) of one (sample,
+// channel) block; VB = bytes per complex sample.  The 32-bit offset lets
+// the load add it to the block's uniform base address directly.
+template <int VB>
+__device__ __forceinline__ uint32_t vraw(const uint8_t *p, uint32_t idx) {
+    if (VB == 2) return *reinterpret_cast<const uint16_t *>(p + 2u * idx);
+    return p[idx];
+}
+
 // One radix-R Stockham pass over BL lines (positive exponent).
 template <int R>
 __device__ __forceinline__ void stockham_pass(const float4 *src, float4 *dst, int N, int pitch,
@@ -449,12 +458,12 @@ constexpr int cols_pitch() {
 // tid % L) owns line l of the band.  (A variant that looped each workgroup
 // over a slice of samples with its gather list in registers measured slower:
 // the extra registers cost more occupancy than the reuse gained.)
-template <int R, int NP, int P>
+template <int R, int NP, int P, int VB>
 __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
     const BandItem *__restrict__ items, int n_items, int G, int nt, int64_t per_xcd,
     const uint4 *__restrict__ entries, int A, const float2 *__restrict__ tw,
-    float4 *__restrict__ scratch, int64_t scratch_t, int vb) {
+    float4 *__restrict__ scratch, int64_t scratch_t) {
     constexpr int N = Pw<R, NP>::N, L = Pw<R, NP>::L, T = rows_threads<R, NP>();
     constexpr int LP = rows_pitch<R, NP>();
     constexpr int UN = T >= 256 ? 8 : 16;  // gather entries in flight per lane
@@ -482,7 +491,7 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     // sum to its cell (the last entry of a cell leaves the full sum) and the
     // last one restarts it, so the loop has no branches; padding entries
     // point at the spare LDS slot after the band
-    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * vb;
+    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * VB;
     const uint4 *ent = entries + it.entry_off;
     float4 s = zero;
     for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
@@ -498,19 +507,19 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
             const uint32_t a = e[k].x & 0x7fffffffu;
-            bx[k] = volt_raw(vx, a, vb);
-            by[k] = P == 2 ? volt_raw(vx, A + a, vb) : 0u;
+            bx[k] = vraw<VB>(vx, a);
+            by[k] = P == 2 ? vraw<VB>(vx, (uint32_t)A + a) : 0u;
         }
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
             const float wr = __builtin_bit_cast(float, e[k].z);
             const float wi = __builtin_bit_cast(float, e[k].w);
-            const int2 x = volt_dec(bx[k], vb);
+            const int2 x = volt_dec(bx[k], VB);
             const float xr = (float)x.x, xi = (float)x.y;
             s.x += wr * xr - wi * xi;
             s.y += wr * xi + wi * xr;
             if (P == 2) {
-                const int2 y = volt_dec(by[k], vb);
+                const int2 y = volt_dec(by[k], VB);
                 const float yr = (float)y.x, yi = (float)y.y;
                 s.z += wr * yr - wi * yi;
                 s.w += wr * yi + wi * yr;
@@ -764,12 +773,12 @@ __device__ __forceinline__ _Float16 h_hi(uint32_t v) {
 // doubles the workgroups a CU holds.  Wave w then transforms rows w, w + 2,
 // ... of the band and writes them to the scratch as FP16 cells (uint2 per
 // cell, cell index as in the FP32 scratch).
-template <int P>
+template <int P, int VB>
 __global__ __launch_bounds__(128) void k_band_rows_mf(
     const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
     const BandItem *__restrict__ items, int n_items, int G, int nt, int64_t per_xcd,
     const uint4 *__restrict__ entries, int A, uint2 *__restrict__ scratch, int64_t scratch_t,
-    int vb, float in_scale, const MfConst *__restrict__ mfc) {
+    float in_scale, const MfConst *__restrict__ mfc) {
     constexpr int N = 256, T = 128, UN = 16;
     extern __shared__ uint2 band16[];   // BL * N FP16 cells + the spare slot
     const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -783,7 +792,7 @@ __global__ __launch_bounds__(128) void k_band_rows_mf(
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int i = tid; i <= BL * N; i += T) band16[i] = make_uint2(0u, 0u);
     __syncthreads();
-    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * vb;
+    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * VB;
     const uint4 *ent = entries + it.entry_off;
     float4 s = zero;
     for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
@@ -798,19 +807,19 @@ __global__ __launch_bounds__(128) void k_band_rows_mf(
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
             const uint32_t a = e[k].x & 0x7fffffffu;
-            bx[k] = volt_raw(vx, a, vb);
-            by[k] = P == 2 ? volt_raw(vx, A + a, vb) : 0u;
+            bx[k] = vraw<VB>(vx, a);
+            by[k] = P == 2 ? vraw<VB>(vx, (uint32_t)A + a) : 0u;
         }
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
             const float wr = __builtin_bit_cast(float, e[k].z);
             const float wi = __builtin_bit_cast(float, e[k].w);
-            const int2 x = volt_dec(bx[k], vb);
+            const int2 x = volt_dec(bx[k], VB);
             const float xr = (float)x.x, xi = (float)x.y;
             s.x += wr * xr - wi * xi;
             s.y += wr * xi + wi * xr;
             if (P == 2) {
-                const int2 y = volt_dec(by[k], vb);
+                const int2 y = volt_dec(by[k], VB);
                 const float yr = (float)y.x, yi = (float)y.y;
                 s.z += wr * yr - wi * yi;
                 s.w += wr * yi + wi * yr;
@@ -1154,9 +1163,12 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
 }
 
 template <int R, int NP>
-static const void *rows_pw_kernel(int P) {
-    return P == 2 ? reinterpret_cast<const void *>(k_band_rows_pw<R, NP, 2>)
-                  : reinterpret_cast<const void *>(k_band_rows_pw<R, NP, 1>);
+static const void *rows_pw_kernel(int P, int vb) {
+    if (vb == 2)
+        return P == 2 ? reinterpret_cast<const void *>(k_band_rows_pw<R, NP, 2, 2>)
+                      : reinterpret_cast<const void *>(k_band_rows_pw<R, NP, 1, 2>);
+    return P == 2 ? reinterpret_cast<const void *>(k_band_rows_pw<R, NP, 2, 1>)
+                  : reinterpret_cast<const void *>(k_band_rows_pw<R, NP, 1, 1>);
 }
 template <int R, int NP>
 static const void *cols_pw_kernel(int P) {
@@ -1175,7 +1187,8 @@ static size_t cols_pw_lds() {
 
 template <int R, int NP>
 static epic_status ready_pw(int P) {
-    epic_status st = lds_ready(rows_pw_kernel<R, NP>(P), rows_pw_lds<R, NP>());
+    epic_status st = lds_ready(rows_pw_kernel<R, NP>(P, 1), rows_pw_lds<R, NP>());
+    if (!st) st = lds_ready(rows_pw_kernel<R, NP>(P, 2), rows_pw_lds<R, NP>());
     if (!st) st = lds_ready(cols_pw_kernel<R, NP>(P), cols_pw_lds<R, NP>());
     return st;
 }
@@ -1194,11 +1207,16 @@ static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const ui
         if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
         constexpr int T = rows_threads<R, NP>();
         const size_t lds = rows_pw_lds<R, NP>();
-        hipLaunchKernelGGL((k_band_rows_pw<R, NP, P>), dim3((unsigned)(8 * per_xcd)), dim3(T),
-                           lds, s, d_volt, vstride,
-                           chans, bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, bs.G,
-                           nt, per_xcd, bp.d_entries.as<uint4>(), p->A, tw, scratch,
-                           bp.scratch_t, p->vb);
+        const BandItem *items = bp.d_items.as<BandItem>() + bs.item_off;
+        const uint4 *ent = bp.d_entries.as<uint4>();
+        if (p->vb == 2)
+            hipLaunchKernelGGL((k_band_rows_pw<R, NP, P, 2>), dim3((unsigned)(8 * per_xcd)),
+                               dim3(T), lds, s, d_volt, vstride, chans, items, (int)bs.n_items,
+                               bs.G, nt, per_xcd, ent, p->A, tw, scratch, bp.scratch_t);
+        else
+            hipLaunchKernelGGL((k_band_rows_pw<R, NP, P, 1>), dim3((unsigned)(8 * per_xcd)),
+                               dim3(T), lds, s, d_volt, vstride, chans, items, (int)bs.n_items,
+                               bs.G, nt, per_xcd, ent, p->A, tw, scratch, bp.scratch_t);
         EPIC_HIP(hipGetLastError());
         return EPIC_OK;
     }
@@ -1224,9 +1242,14 @@ constexpr size_t kRowsMfLds = sizeof(uint2) * (BL * 256 + 1);
 constexpr size_t kColsMfLds = sizeof(uint2) * MF_BC * MF_LP;
 
 static epic_status ready_mf(int P) {
-    epic_status st = lds_ready(P == 2 ? reinterpret_cast<const void *>(k_band_rows_mf<2>)
-                                      : reinterpret_cast<const void *>(k_band_rows_mf<1>),
-                               kRowsMfLds);
+    epic_status st = EPIC_OK;
+    for (int vb = 1; vb <= 2 && !st; ++vb) {
+        const void *k = P == 2 ? (vb == 2 ? reinterpret_cast<const void *>(k_band_rows_mf<2, 2>)
+                                          : reinterpret_cast<const void *>(k_band_rows_mf<2, 1>))
+                               : (vb == 2 ? reinterpret_cast<const void *>(k_band_rows_mf<1, 2>)
+                                          : reinterpret_cast<const void *>(k_band_rows_mf<1, 1>));
+        st = lds_ready(k, kRowsMfLds);
+    }
     if (!st)
         st = lds_ready(P == 2 ? reinterpret_cast<const void *>(k_band_cols_mf<2>)
                               : reinterpret_cast<const void *>(k_band_cols_mf<1>),
@@ -1246,11 +1269,18 @@ static epic_status launch_mf(epic_plan p, const BandSize &bs, int pass, const ui
         const int64_t total = bs.n_items * nt;
         const int64_t per_xcd = (total + 7) / 8;
         if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
-        hipLaunchKernelGGL(k_band_rows_mf<P>, dim3((unsigned)(8 * per_xcd)), dim3(128),
-                           kRowsMfLds, s, d_volt, p->vstride(), chans,
-                           bp.d_items.as<BandItem>() + bs.item_off, (int)bs.n_items, bs.G, nt,
-                           per_xcd, bp.d_entries.as<uint4>(), p->A, sc, bp.scratch_t, p->vb,
-                           bp.mf_in, bp.d_mf.as<MfConst>());
+        const BandItem *items = bp.d_items.as<BandItem>() + bs.item_off;
+        const uint4 *ent = bp.d_entries.as<uint4>();
+        if (p->vb == 2)
+            hipLaunchKernelGGL((k_band_rows_mf<P, 2>), dim3((unsigned)(8 * per_xcd)), dim3(128),
+                               kRowsMfLds, s, d_volt, p->vstride(), chans, items, (int)bs.n_items,
+                               bs.G, nt, per_xcd, ent, p->A, sc, bp.scratch_t, bp.mf_in,
+                               bp.d_mf.as<MfConst>());
+        else
+            hipLaunchKernelGGL((k_band_rows_mf<P, 1>), dim3((unsigned)(8 * per_xcd)), dim3(128),
+                               kRowsMfLds, s, d_volt, p->vstride(), chans, items, (int)bs.n_items,
+                               bs.G, nt, per_xcd, ent, p->A, sc, bp.scratch_t, bp.mf_in,
+                               bp.d_mf.as<MfConst>());
         EPIC_HIP(hipGetLastError());
         return EPIC_OK;
     }
