@@ -612,8 +612,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: channels shard across GPUs with no exchange, "
-              "and this build runs on single-GPU boxes only; use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only (channels would shard across GPUs with no "
+              "exchange; no multi-GPU path is implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -1,7 +1,8 @@
 """Reduced-precision variants (direct DFT-as-GEMM on MFMA) against the FP64
 oracle.  Tolerances per operand type, from the rounding of the beam matrix
 (the int4 voltages are exact in every type) with the time sums in FP32;
-the measured errors are written to gpurun_out/precision_errors.json.
+with EPIC_RESULTS_DIR set, the measured errors are also written to
+precision_errors.json in that directory.
 """
 import json
 import os
@@ -30,9 +31,11 @@ def _record(key, got, ref):
     erms = max(float(image_errors(g, r)[1].max()) for g, r in zip(got, ref))
     _RESULTS[key] = {"max": emax, "rms": erms}
     _say(f"{key}: max {emax:.3e} rms {erms:.3e}")
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "precision_errors.json"), "w") as f:
-        json.dump(_RESULTS, f, indent=1)
+    out = os.environ.get("EPIC_RESULTS_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "precision_errors.json"), "w") as f:
+            json.dump(_RESULTS, f, indent=1)
     return emax, erms
 
 
