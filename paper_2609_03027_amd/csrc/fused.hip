@@ -225,12 +225,20 @@ __device__ __forceinline__ void gather_load(uint4 (&e)[GB], const uint4 *ent, in
 // The caller loads the first batch (gather_load(e, ent, 0, n_iter)) ahead of
 // the barrier that publishes the staged voltages, so its latency overlaps
 // the wait; later batches are loaded here.
-template <int T, int P, bool JN>
+template <int T, int P, bool JN, int NT = 0>
 __device__ __forceinline__ void gather_cells(Grid<P> grid, const uint4 *ent, int n_iter,
-                                             const float4 *stage, uint4 (&e)[GB]) {
+                                             const float4 *stage, uint4 (&e)[GB],
+                                             const uint4 *tail = nullptr) {
     float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
     for (int k0 = 0; k0 < n_iter; k0 += GB) {
-        if (k0) gather_load<T, JN>(e, ent, k0, n_iter);
+        if (k0 == GB && NT && n_iter <= GB + NT) {
+            // entries GB .. n_iter - 1 are held in registers for the whole
+            // sample loop (they are the same every sample)
+#pragma unroll
+            for (int k = 0; k < GB; ++k) e[k] = k < NT ? tail[k] : e[k];
+        } else if (k0) {
+            gather_load<T, JN>(e, ent, k0, n_iter);
+        }
 #pragma unroll
         for (int k = 0; k < GB; ++k) {
             if (k0 + k >= n_iter) break;            // uniform: n_iter is per item
@@ -527,6 +535,13 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
             ry[k] = volt_raw(vbase, A + a, vb);
         }
     }
+    // lists longer than one batch (up to GB + NT entries; the LWA plan's
+    // reach 10) keep their tail in registers across the sample loop
+    constexpr int NT = (JN || AR > 2) ? 0 : 4;
+    uint4 tail[NT > 0 ? NT : 1];
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+        tail[k] = n_iter > GB ? ent[(int64_t)min(GB + k, n_iter - 1) * T] : make_uint4(0u, 0u, 0u, 0u);
     for (int t = 0; t < n_time; ++t) {
         const uint8_t *vt = vbase + (int64_t)t * volt_t_stride;
         uint4 e[GB];
@@ -563,7 +578,7 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
                 }
             }
         }
-        gather_cells<T, 2, JN>(g, ent, n_iter, stage, e);
+        gather_cells<T, 2, JN, NT>(g, ent, n_iter, stage, e, tail);
         __syncthreads();
 
         pass_a<M, 2, true>(g, tid, tw);
@@ -818,10 +833,16 @@ static FusedItem build_item(epic_plan p, const std::vector<int> &j0, const std::
             }
     }
     const size_t off = all.size();
-    const int n_iter = lpt_pack(taps, T, all, J == 4);
+    int n_iter = lpt_pack(taps, T, all, J == 4);
+    const int rows = J == 4 ? 3 : 1;
+    // the kernels load the first entries of every list unconditionally: an
+    // item always has at least one (padding) row
+    if (n_iter == 0) {
+        all.resize(off + (size_t)rows * T, make_uint4(0u, 0u, 0u, 0u));
+        n_iter = 1;
+    }
     // The kernels store the running sum at every entry, so padding (all-zero)
     // entries point at a slot no pass reads: column M of row (lane mod M).
-    const int rows = J == 4 ? 3 : 1;
     for (int k = 0; k < n_iter; ++k)
         for (int l = 0; l < T; ++l) {
             uint4 &e = all[off + (size_t)k * rows * T + l];
