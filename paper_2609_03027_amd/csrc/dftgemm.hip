@@ -221,7 +221,6 @@ void k_dftgemm(const uint8_t *__restrict__ a_hi,
                                                  const float *__restrict__ inv_s2, int Ap,
                                                  int cols_pad, float *__restrict__ acc) {
     typedef typename Frag<DT>::T FT;
-    typedef typename Op<DT>::E E;
     constexpr int EB = Op<DT>::BYTES, S = Op<DT>::KSTEP, Q = S / 4;
     constexpr int K = 32 * KS;                  // = 2 Ap
     constexpr int NKS = K / S;                  // MFMA steps along K
@@ -381,7 +380,6 @@ static int ks_for(int A) {
     return 0;
 }
 
-static int rb_for(int dt) { return dt == EPIC_F8E4M3_MFMA ? 4 : dt == EPIC_F16_MFMA ? 2 : 1; }
 
 template <int DT>
 static epic_status build_dt(epic_plan p, hipStream_t s) {
