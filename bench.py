@@ -158,16 +158,21 @@ def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8):
         name = f"station{i}"
         rings[name] = torch.from_numpy(blocks).cuda()
         plan = E.Plan.from_workload(wl, pos)
+        # independent stations are not phase-locked: their block arrivals
+        # are spread evenly over one period
         specs.append(StreamSpec(name, plan, tb, period_s, n_blocks, 1000 // tb,
                                 deadline_s=period_s, ring=ring,
-                                bytes_needed=plan.info["bytes_acc"] + rings[name].numel()))
+                                bytes_needed=plan.info["bytes_acc"] + rings[name].numel(),
+                                phase_s=i * period_s / n_streams))
     ex = DeviceExecutor(rings)
     free, _ = torch.cuda.mem_get_info()
-    # warm-up: a short run of every stream through the same server path
+    # warm-up: an untimed run of every stream through the same server path,
+    # as long as the timed one (a first full-length run in a process showed
+    # stalls of about 10 ms at read-outs; a second one does not)
     warm = Server(ex, budget_bytes=int(0.8 * free))
     for s in specs:
-        warm.submit_stream(replace(s, n_blocks=2 * s.blocks_per_integration))
-    warm.run(timeout_s=60.0)
+        warm.submit_stream(s)
+    warm.run(timeout_s=120.0)
     srv = Server(ex, budget_bytes=int(0.8 * free))
     t0 = time.perf_counter()
     for s in specs:

@@ -46,6 +46,7 @@ class StreamSpec:
     deadline_s: float = 1e-3
     ring: int = 8
     bytes_needed: int = 0          # accumulator + ring (plan counted separately)
+    phase_s: float = 0.0           # arrival of block 0 after the stream's clock starts
 
 
 @dataclasses.dataclass
@@ -66,7 +67,7 @@ class _Active:
     def __init__(self, spec, handle, admit_time):
         self.spec = spec
         self.handle = handle
-        self.t0 = admit_time          # arrival clock of block 0
+        self.t0 = admit_time          # arrival clock of block 0 (None: not started)
         self.next_block = 0           # next block to consider
         self.inflight = collections.deque()
         self.records = []
@@ -114,8 +115,11 @@ class Server:
             pr = self.plans_resident.setdefault(id(spec.plan), [cost - spec.bytes_needed, 0])
             pr[1] += 1
             handle = self.ex.open(spec)
-            # the stream's clock starts once its device resources are ready
-            self.active[spec.name] = _Active(spec, handle, self.ex.now())
+            # The stream's clock starts at the first scheduling pass that sees
+            # it: once its device resources are ready and the server is running
+            # (streams admitted before run() would otherwise count the set-up
+            # of the streams admitted after them as arrival time).
+            self.active[spec.name] = _Active(spec, handle, None)
 
     def _close(self, st, now):
         spec = st.spec
@@ -137,13 +141,15 @@ class Server:
         for name in list(self.active):
             st = self.active[name]
             spec = st.spec
+            if st.t0 is None:
+                st.t0 = now
             # completions in order
             while st.inflight and self.ex.done(st.inflight[0][1]):
                 rec, tok = st.inflight.popleft()
                 rec.done = self.ex.finish_time(tok)
             # arrivals
             while st.next_block < spec.n_blocks:
-                arr = st.t0 + st.next_block * spec.period_s
+                arr = st.t0 + spec.phase_s + st.next_block * spec.period_s
                 if arr > now:
                     break
                 rec = BlockRecord(spec.name, st.next_block, arr)
@@ -286,14 +292,22 @@ class DeviceExecutor:
         n_int = max(1, spec.n_blocks // max(1, spec.blocks_per_integration))
         host = [torch.empty(img.shape, dtype=torch.float32, pin_memory=True)
                 for _ in range(n_int)]
-        # first use of a new queue is slow: touch it (and the kernels) now
+        # first use of a new queue is slow: touch both queues (and the
+        # kernels) now; so is the first copy into a new pinned buffer (in a
+        # first run it held up every stream's blocks for about 10 ms), so
+        # each image buffer takes one copy on the copy queue here
+        cp = torch.cuda.Stream()
         with torch.cuda.stream(s):
             ring = self.rings[spec.name]
             E.accumulate(spec.plan, acc, volt=ring[0], stream=s)
             E.readout(spec.plan, acc, img, E.REMOVE_AUTOS | E.NORMALISE, stream=s)
             acc.reset(stream=s)
         s.synchronize()
-        return {"spec": spec, "stream": s, "copy": torch.cuda.Stream(), "copied": None,
+        with torch.cuda.stream(cp):
+            for hb in host:
+                hb.copy_(img, non_blocking=True)
+        cp.synchronize()
+        return {"spec": spec, "stream": s, "copy": cp, "copied": None,
                 "acc": acc, "img": img, "host": host, "n_out": 0,
                 "ring": self.rings[spec.name]}
 

@@ -81,3 +81,41 @@ def test_blocks_of_later_streams_overlap_earlier_ones():
         assert Server.stats(fin[name].records)["dropped"] == 0
     lat = np.array([r.latency for r in fin["b"].records])
     assert np.all(lat >= 5e-4 - 1e-12)
+
+
+class _SlowOpen(FakeExecutor):
+    """Stream set-up takes virtual time (queue creation, pinned buffers)."""
+
+    def __init__(self, open_s, **kw):
+        super().__init__(**kw)
+        self.open_s = open_s
+
+    def open(self, spec):
+        self.t += self.open_s
+        return super().open(spec)
+
+
+def test_stream_clock_starts_when_the_server_runs():
+    # Four streams admitted before run(), each taking 5 ms to open: the first
+    # one's blocks must not be counted as arriving during the others' set-up
+    ex = _SlowOpen(5e-3, cost_s=1e-4, lanes=4, plan_bytes=1000)
+    srv = Server(ex, budget_bytes=10 ** 9)
+    for i in range(4):
+        assert srv.submit_stream(_spec(f"s{i}", _Plan(), n_blocks=20, ring=2))
+    fin = srv.run(timeout_s=1.0, poll_s=1e-5)
+    recs = [r for st in fin.values() for r in st.records]
+    st = Server.stats(recs)
+    assert st["dropped"] == 0
+    assert st["max_ms"] < 1.0, st
+
+
+def test_stream_phase_offsets_arrivals():
+    ex = FakeExecutor(cost_s=1e-4, lanes=1, plan_bytes=10)
+    srv = Server(ex, budget_bytes=10 ** 6)
+    from dataclasses import replace
+    srv.submit_stream(replace(_spec("a", _Plan(), n_blocks=3), phase_s=0.0))
+    srv.submit_stream(replace(_spec("b", _Plan(), n_blocks=3), phase_s=5e-4))
+    fin = srv.run(timeout_s=1.0, poll_s=1e-5)
+    arr = {n: [r.arrival for r in st.records] for n, st in fin.items()}
+    assert np.allclose(np.diff(arr["a"]), 1e-3) and np.allclose(np.diff(arr["b"]), 1e-3)
+    assert abs((arr["b"][0] - arr["a"][0]) - 5e-4) < 2e-5
