@@ -282,9 +282,10 @@ epic_status epic_acc_import(epic_acc a, const float *d_acc, const int32_t *d_aut
 epic_status epic_grid(epic_plan p, const uint8_t *d_volt, int32_t n_time, void *d_grid,
                       void *hip_stream) {
     EPIC_GUARD_BEGIN
-    if (!p || !d_volt || !d_grid) return fail(EPIC_ERR_NULL, "plan, volt and grid are required");
+    if (!p) return fail(EPIC_ERR_NULL, "plan is required");
     if (n_time < 0) return fail(EPIC_ERR_ARG, "n_time must be >= 0");
-    if (n_time == 0) return EPIC_OK;
+    if (n_time == 0) return EPIC_OK;              // nothing is read or written
+    if (!d_volt || !d_grid) return fail(EPIC_ERR_NULL, "volt and grid are required");
     return staged_grid(p, d_volt, n_time, d_grid, static_cast<hipStream_t>(hip_stream));
     EPIC_GUARD_END
 }
@@ -292,9 +293,10 @@ epic_status epic_grid(epic_plan p, const uint8_t *d_volt, int32_t n_time, void *
 epic_status epic_image(epic_plan p, const void *d_grid, int32_t n_time, void *d_sky,
                        void *hip_stream) {
     EPIC_GUARD_BEGIN
-    if (!p || !d_grid || !d_sky) return fail(EPIC_ERR_NULL, "plan, grid and sky are required");
+    if (!p) return fail(EPIC_ERR_NULL, "plan is required");
     if (n_time < 0) return fail(EPIC_ERR_ARG, "n_time must be >= 0");
-    if (n_time == 0) return EPIC_OK;
+    if (n_time == 0) return EPIC_OK;              // nothing is read or written
+    if (!d_grid || !d_sky) return fail(EPIC_ERR_NULL, "grid and sky are required");
     return staged_image(p, d_grid, n_time, d_sky, static_cast<hipStream_t>(hip_stream));
     EPIC_GUARD_END
 }
@@ -304,9 +306,9 @@ epic_status epic_accumulate(epic_plan p, epic_acc a, const uint8_t *d_volt, cons
     EPIC_GUARD_BEGIN
     if (!p || !a) return fail(EPIC_ERR_NULL, "plan and acc are required");
     if (a->plan != p) return fail(EPIC_ERR_MISMATCH, "accumulator belongs to another plan");
-    if (!d_volt && !d_sky) return fail(EPIC_ERR_NULL, "volt or sky is required");
     if (n_time < 0) return fail(EPIC_ERR_ARG, "n_time must be >= 0");
-    if (n_time == 0) return EPIC_OK;
+    if (n_time == 0) return EPIC_OK;              // nothing is read; sums and count unchanged
+    if (!d_volt && !d_sky) return fail(EPIC_ERR_NULL, "volt or sky is required");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     epic_status st;
     if (d_sky) {

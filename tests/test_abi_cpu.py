@@ -181,6 +181,16 @@ def test_data_calls_reject_null_handles():
     assert lib.epic_acc_destroy(None) == 1
 
 
+def test_zero_sample_calls_need_no_data_pointers():
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    # a zero-sample call still needs its plan handle (the GPU edge-case
+    # tests cover zero-sample calls on a real plan with NULL data)
+    assert lib.epic_grid(None, None, 0, None, None) == 1
+    assert lib.epic_image(None, None, 0, None, None) == 1
+    assert lib.epic_accumulate(None, None, None, None, 0, None) == 1
+
+
 @pytest.mark.parametrize("over,status,word", [
     (dict(), 4, b"64 x 64"),                                       # grid side 32
     (dict(grid=64, fixed_twiddle_bits=16), 2, b"twiddle"),
