@@ -193,9 +193,10 @@ epic_status epic_acc_export(epic_acc acc, float *d_acc, int32_t *d_autos, int64_
 epic_status epic_acc_import(epic_acc acc, const float *d_acc, const int32_t *d_autos,
                             int64_t count, void *hip_stream);
 
-/* Calls with n_time == 0 (epic_grid, epic_image, epic_accumulate) do
- * nothing and return EPIC_OK; their data pointers may then be NULL (the plan
- * and accumulator handles are still checked).  n_time < 0 is EPIC_ERR_ARG. */
+/* Calls with n_time == 0 (epic_grid, epic_image, epic_accumulate,
+ * epic_accumulate_frames) do nothing and return EPIC_OK; their data pointers
+ * may then be NULL (the plan and accumulator handles, and frame_len, are
+ * still checked).  n_time < 0 is EPIC_ERR_ARG. */
 
 /* Eq. 1 inner sum for n_time samples: d_grid[t][c][p][jy][jx] =
  * sum_a conj(W_a(j)) E_a^p (complex64).  Writes every grid element. */

@@ -330,14 +330,14 @@ epic_status epic_accumulate_frames(epic_plan p, epic_acc a, const uint8_t *d_vol
                                    int32_t n_time, int32_t frame_len, float *d_frames,
                                    void *hip_stream) {
     EPIC_GUARD_BEGIN
-    if (!p || !a || !d_volt || !d_frames)
-        return fail(EPIC_ERR_NULL, "plan, acc, volt and frames are required");
+    if (!p || !a) return fail(EPIC_ERR_NULL, "plan and acc are required");
     if (a->plan != p) return fail(EPIC_ERR_MISMATCH, "accumulator belongs to another plan");
     if (n_time < 0 || frame_len < 1) return fail(EPIC_ERR_ARG, "n_time >= 0 and frame_len >= 1");
     if (n_time % frame_len) return fail(EPIC_ERR_ARG, "n_time must be a multiple of frame_len");
     if (p->precision != EPIC_F32)
         return fail(EPIC_ERR_UNSUPPORTED, "frame mode runs on the FP32 path only");
-    if (n_time == 0) return EPIC_OK;
+    if (n_time == 0) return EPIC_OK;              // no frames
+    if (!d_volt || !d_frames) return fail(EPIC_ERR_NULL, "volt and frames are required");
     FrameOut fo;
     fo.len = frame_len;
     fo.out = d_frames;

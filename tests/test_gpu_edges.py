@@ -27,6 +27,8 @@ def test_zero_sample_calls_change_nothing():
     out = torch.empty(plan.info["image_floats"], dtype=torch.float32, device="cuda")
     with pytest.raises(E.EpicError):
         E.readout(plan, acc, out, E.NORMALISE)          # nothing to average yet
+    frames = torch.empty((0, plan.info["image_floats"]), dtype=torch.float32, device="cuda")
+    E.accumulate_frames(plan, acc, dv[:0], 4, frames)   # no frames
     E.accumulate(plan, acc, volt=dv)
     E.accumulate(plan, acc, volt=dv[8:])                # empty slice at the end
     E.readout(plan, acc, out, E.REMOVE_AUTOS | E.NORMALISE)
