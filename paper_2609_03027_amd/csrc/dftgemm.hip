@@ -478,7 +478,7 @@ static epic_status launch_gemm(epic_plan p, float *acc, const uint8_t *vbuf, int
 template <int DT, int P>
 static epic_status launch_gemm_ks(epic_plan p, float *acc, const uint8_t *vbuf, int cols_pad,
                                   hipStream_t s) {
-    constexpr int RB = DT == EPIC_F8E4M3_MFMA ? 4 : DT == EPIC_F16_MFMA ? 2 : 1;
+    constexpr int RB = DT == EPIC_F8E4M3_MFMA ? 4 : DT == EPIC_F16_MFMA ? 3 : 1;
     constexpr bool F8 = DT == EPIC_F8E4M3_MFMA;
     switch (p->gemm.KS) {
         case 1: return launch_gemm<DT, P, RB, F8 ? 4 : 1>(p, acc, vbuf, cols_pad, s);
