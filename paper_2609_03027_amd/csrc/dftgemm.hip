@@ -210,6 +210,32 @@ __device__ __forceinline__ float swap_pair(float x) {
 // Rows 4g + {0, 1} are pixel 2g (re, im), 4g + {2, 3} pixel 2g + 1.  With two
 // feeds the columns alternate (t, X), (t, Y): even lanes keep XX and Re XY,
 // odd lanes YY and Im XY, exchanging the other feed with lane ^ 1.
+// Eq. 2 products of one 16-column tile, summed over its columns: each lane
+// holds rows 4 g .. 4 g + 3 of column l % 16 (pixel re/im pairs; even columns
+// feed x, odd feed y).  Even lane: own = Ex, other = Ey; odd lane: own = Ey,
+// other = Ex.  The sender picks what it passes so that both lanes take the
+// same two products: the odd lane sends Ey as it is (even lane: Re Ex conj(Ey)
+// = xr yr + xi yi), the even lane sends -i Ex = (xi, -xr) (odd lane:
+// Im Ex conj(Ey) = yr xi - yi xr).
+template <int P, int RB>
+__device__ __forceinline__ void tile_products(const f4v (&d)[RB], float (&sum)[RB][2][2],
+                                              bool odd) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const float vr = d[r][2 * q], vi = d[r][2 * q + 1];
+            sum[r][q][0] = fmaf(vr, vr, sum[r][q][0]);
+            sum[r][q][0] = fmaf(vi, vi, sum[r][q][0]);
+            if (P == 2) {
+                const float a = swap_pair(odd ? vr : vi);
+                const float b = swap_pair(odd ? vi : -vr);
+                sum[r][q][1] = fmaf(vr, a, sum[r][q][1]);
+                sum[r][q][1] = fmaf(vi, b, sum[r][q][1]);
+            }
+        }
+}
+
 template <int DT, int P, int RB, int KS>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void k_dftgemm(const uint8_t *__restrict__ a_hi,
@@ -258,6 +284,7 @@ void k_dftgemm(const uint8_t *__restrict__ a_hi,
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int q = 0; q < 2; ++q) sum[r][q][0] = sum[r][q][1] = 0.f;
+    const bool odd = (lane & 1) != 0;
 
     const uint8_t *vc = vop + (int64_t)c * cols_pad * K * EB;
     const int g = lane >> 4, col = lane & 15;
@@ -303,24 +330,7 @@ void k_dftgemm(const uint8_t *__restrict__ a_hi,
                     if (DT == EPIC_BF16X2_MFMA) d[r] = Frag<DT>::mma(al[r][s], b, d[r]);
                 }
             }
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const float vr = d[r][2 * q], vi = d[r][2 * q + 1];
-                    if (P == 2) {
-                        const float ur = swap_pair(vr), ui = swap_pair(vi);
-                        // even lane: own = Ex, other = Ey; odd lane: own = Ey, other = Ex
-                        sum[r][q][0] += vr * vr + vi * vi;
-                        if ((lane & 1) == 0)
-                            sum[r][q][1] += vr * ur + vi * ui;       // Re Ex conj(Ey)
-                        else
-                            sum[r][q][1] += ui * vr - ur * vi;       // Im Ex conj(Ey)
-                    } else {
-                        sum[r][q][0] += vr * vr + vi * vi;
-                    }
-                }
-            }
+            tile_products<P, RB>(d, sum, odd);
         }
         // the other buffer was last read before the previous barrier
         if (more) {
