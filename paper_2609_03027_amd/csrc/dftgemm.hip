@@ -236,7 +236,7 @@ __device__ __forceinline__ void tile_products(const f4v (&d)[RB], float (&sum)[R
         }
 }
 
-template <int DT, int P, int RB, int KS>
+template <int DT, int P, int RB, int KS, int CT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void k_dftgemm(const uint8_t *__restrict__ a_hi,
                                                  const uint8_t *__restrict__ a_lo,
@@ -253,9 +253,10 @@ void k_dftgemm(const uint8_t *__restrict__ a_hi,
     static_assert(K % S == 0, "K must be a whole number of MFMA steps");
     constexpr int CSTRIDE = K * EB + 16;        // LDS bytes per column (padded)
     constexpr int NPROD = P == 2 ? 4 : 1;
-    constexpr int PIECES = 16 * (K * EB / 16);            // 16-byte pieces per tile
+    constexpr int CW = 16 * CT;                 // columns staged per barrier
+    constexpr int PIECES = CW * (K * EB / 16);            // 16-byte pieces per stage
     constexpr int PPT = (PIECES + 511) / 512;             // per thread
-    __shared__ __attribute__((aligned(16))) uint8_t tiles[2][16 * CSTRIDE];
+    __shared__ __attribute__((aligned(16))) uint8_t tiles[2][CW * CSTRIDE];
 
     const int c = blockIdx.y;
     const int N = chan[c].x;
@@ -302,9 +303,9 @@ void k_dftgemm(const uint8_t *__restrict__ a_hi,
         }
     }
     __syncthreads();
-    for (int ct = 0, buf = 0; ct < cols_pad; ct += 16, buf ^= 1) {
+    for (int ct = 0, buf = 0; ct < cols_pad; ct += CW, buf ^= 1) {
         const uint8_t *tile = tiles[buf];
-        const bool more = ct + 16 < cols_pad;
+        const bool more = ct + CW < cols_pad;
         if (more) {
 #pragma unroll
             for (int u = 0; u < PPT; ++u) {
@@ -312,25 +313,28 @@ void k_dftgemm(const uint8_t *__restrict__ a_hi,
                 if (i < PIECES) {
                     const int cl = i / (K * EB / 16), off = (i % (K * EB / 16)) * 16;
                     pre[u] = *reinterpret_cast<const uint4 *>(
-                        vc + ((int64_t)(ct + 16 + cl) * K) * EB + off);
+                        vc + ((int64_t)(ct + CW + cl) * K) * EB + off);
                 }
             }
         }
         if (live) {
-            f4v d[RB];
 #pragma unroll
-            for (int r = 0; r < RB; ++r) d[r] = f4v{0.f, 0.f, 0.f, 0.f};
+            for (int h = 0; h < CT; ++h) {
+                const uint8_t *sub = tile + (16 * h + col) * CSTRIDE;
+                f4v d[RB];
 #pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                const FT b = *reinterpret_cast<const FT *>(tile + col * CSTRIDE +
-                                                           (S * s + Q * g) * EB);
+                for (int r = 0; r < RB; ++r) d[r] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    d[r] = Frag<DT>::mma(ah[r][s], b, d[r]);
-                    if (DT == EPIC_BF16X2_MFMA) d[r] = Frag<DT>::mma(al[r][s], b, d[r]);
+                for (int s = 0; s < NKS; ++s) {
+                    const FT b = *reinterpret_cast<const FT *>(sub + (S * s + Q * g) * EB);
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) {
+                        d[r] = Frag<DT>::mma(ah[r][s], b, d[r]);
+                        if (DT == EPIC_BF16X2_MFMA) d[r] = Frag<DT>::mma(al[r][s], b, d[r]);
+                    }
                 }
+                tile_products<P, RB>(d, sum, odd);
             }
-            tile_products<P, RB>(d, sum, odd);
         }
         // the other buffer was last read before the previous barrier
         if (more) {
@@ -471,13 +475,13 @@ epic_status gemm_build(epic_plan p, hipStream_t s) {
     return EPIC_OK;
 }
 
-template <int DT, int P, int RB, int KS>
+template <int DT, int P, int RB, int KS, int CT>
 static epic_status launch_gemm(epic_plan p, float *acc, const uint8_t *vbuf, int cols_pad,
                                hipStream_t s) {
     GemmPlan &gp = p->gemm;
     const int rows_max = 2 * p->max_n * p->max_n;
     dim3 g((rows_max + 8 * RB * 16 - 1) / (8 * RB * 16), p->C);
-    hipLaunchKernelGGL((k_dftgemm<DT, P, RB, KS>), g, dim3(512), 0, s, gp.a_hi.as<uint8_t>(),
+    hipLaunchKernelGGL((k_dftgemm<DT, P, RB, KS, CT>), g, dim3(512), 0, s, gp.a_hi.as<uint8_t>(),
                        gp.a_lo.as<uint8_t>(), vbuf, p->d_chan.as<int4>(),
                        gp.d_blk_off.as<int64_t>(), p->d_img_off.as<int64_t>(),
                        gp.d_inv_s2.as<float>(), gp.Ap, cols_pad, acc);
@@ -485,17 +489,25 @@ static epic_status launch_gemm(epic_plan p, float *acc, const uint8_t *vbuf, int
     return EPIC_OK;
 }
 
+// 16-column tiles staged per barrier: two for FP8, whose tiles are the
+// shortest in MFMA time, so the barrier and the LDS round trip weigh most
+// (FP16's three row blocks leave no registers for the wider prefetch, and
+// BF16 hi+lo did not gain); launches round the column count up to a whole
+// number of stages (the operand buffer holds t_chunk P columns, a multiple
+// of 32)
+template <int DT> constexpr int gemm_ct() { return DT == EPIC_F8E4M3_MFMA ? 2 : 1; }
+
 template <int DT, int P>
 static epic_status launch_gemm_ks(epic_plan p, float *acc, const uint8_t *vbuf, int cols_pad,
                                   hipStream_t s) {
     constexpr int RB = DT == EPIC_F8E4M3_MFMA ? 4 : DT == EPIC_F16_MFMA ? 3 : 1;
     constexpr bool F8 = DT == EPIC_F8E4M3_MFMA;
     switch (p->gemm.KS) {
-        case 1: return launch_gemm<DT, P, RB, F8 ? 4 : 1>(p, acc, vbuf, cols_pad, s);
-        case 2: return launch_gemm<DT, P, RB, F8 ? 4 : 2>(p, acc, vbuf, cols_pad, s);
-        case 4: return launch_gemm<DT, P, RB, 4>(p, acc, vbuf, cols_pad, s);
-        case 8: return launch_gemm<DT, P, RB, 8>(p, acc, vbuf, cols_pad, s);
-        case 16: return launch_gemm<DT, P, RB, 16>(p, acc, vbuf, cols_pad, s);
+        case 1: return launch_gemm<DT, P, RB, F8 ? 4 : 1, gemm_ct<DT>()>(p, acc, vbuf, cols_pad, s);
+        case 2: return launch_gemm<DT, P, RB, F8 ? 4 : 2, gemm_ct<DT>()>(p, acc, vbuf, cols_pad, s);
+        case 4: return launch_gemm<DT, P, RB, 4, gemm_ct<DT>()>(p, acc, vbuf, cols_pad, s);
+        case 8: return launch_gemm<DT, P, RB, 8, gemm_ct<DT>()>(p, acc, vbuf, cols_pad, s);
+        case 16: return launch_gemm<DT, P, RB, 16, gemm_ct<DT>()>(p, acc, vbuf, cols_pad, s);
     }
     return fail(EPIC_ERR_UNSUPPORTED, "K steps");
 }
@@ -504,7 +516,8 @@ template <int DT>
 static epic_status gemm_chunk(epic_plan p, float *acc, uint8_t *vbuf, const uint8_t *d_volt, int nt,
                               hipStream_t s) {
     GemmPlan &gp = p->gemm;
-    const int cols_pad = ((nt * p->P + 15) / 16) * 16;
+    const int cw = 16 * gemm_ct<DT>();
+    const int cols_pad = ((nt * p->P + cw - 1) / cw) * cw;
     const int64_t tot = (int64_t)p->C * cols_pad * gp.Ap;
     const int64_t vstride = p->vstride();
     hipLaunchKernelGGL(k_volt_operand<DT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
