@@ -71,8 +71,9 @@ def test_lwa_channels_dftgemm(dt):
 
 @pytest.mark.parametrize("dt", [F16, F8])
 def test_dftgemm_call_longer_than_one_launch(dt):
-    # 1100 samples in one call: two launches of the sample chunk (1024 + 76),
-    # 138 double-buffered column tiles in the first
+    # 1100 samples in one call: two launches of the sample chunk (1024 + 76
+    # samples, 2048 + 152 columns: 128 + 10 column tiles of 16, staged one or
+    # two per barrier)
     wl = synth.workload("tiny2").with_time(1100)
     pos = synth.antenna_layout(wl)
     volt = synth.voltages(wl, pos)
@@ -80,6 +81,21 @@ def test_dftgemm_call_longer_than_one_launch(dt):
     got = _run(wl, pos, volt, precision=dt)
     ref = oracle_images(volt, pos, wl, range(wl.n_chan))
     emax, erms = _record(f"tiny2-1100/{NAMES[dt]}", got, ref)
+    assert emax <= TOL[dt][0] and erms <= TOL[dt][1]
+
+
+@pytest.mark.parametrize("name,n_time", [("tiny", 37), ("tiny2", 19)])
+@pytest.mark.parametrize("dt", [F16, BF16X2, F8])
+def test_dftgemm_ragged_column_stage(name, n_time, dt):
+    # 37 one-feed or 38 two-feed columns: the last 16-column tile, and for FP8
+    # the last two-tile stage, are partly padding
+    wl = synth.workload(name).with_time(n_time)
+    pos = synth.antenna_layout(wl)
+    volt = synth.voltages(wl, pos)
+    _say(f"case dftgemm {name} {NAMES[dt]} {n_time} samples")
+    got = _run(wl, pos, volt, precision=dt)
+    ref = oracle_images(volt, pos, wl, range(wl.n_chan))
+    emax, erms = _record(f"{name}-{n_time}/{NAMES[dt]}", got, ref)
     assert emax <= TOL[dt][0] and erms <= TOL[dt][1]
 
 
