@@ -137,37 +137,57 @@ __global__ __launch_bounds__(256) void k_plan_beam(const int2 *__restrict__ j0,
     }
 }
 
-// Voltages -> B operand: V'[c][col][k], col = t P + p (padded to a multiple of
-// 16 with zeros), k < Ap real parts, k >= Ap imaginary parts.
+// Voltages -> B operand: V'[c][col][k], col = t P + p (padded to a whole
+// number of column stages with zeros), k < Ap real parts, k >= Ap imaginary
+// parts.  Each thread converts four consecutive elements (Ap = 16 KS is a
+// multiple of four) and stores them with one 4-byte (FP8) or 8-byte store
+// per part.
 template <int DT>
 __global__ void k_volt_operand(const uint8_t *__restrict__ volt, int64_t vstride, int A, int Ap,
                                int P, int C, int n_time, int cols_pad,
                                uint8_t *__restrict__ out, int vb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t tot = (int64_t)C * cols_pad * Ap;
+    const int Aq = Ap / 4;
+    const int64_t tot = (int64_t)C * cols_pad * Aq;
     if (i >= tot) return;
-    const int a = (int)(i % Ap);
-    const int64_t cc = i / Ap;
+    const int a0 = (int)(i % Aq) * 4;
+    const int64_t cc = i / Aq;
     const int col = (int)(cc % cols_pad);
     const int c = (int)(cc / cols_pad);
     const int t = col / P, p = col % P;
-    float re = 0.f, im = 0.f;
-    if (a < A && t < n_time) {
-        const int2 x = volt_at(volt + (int64_t)t * vstride, ((int64_t)c * P + p) * A + a, vb);
-        re = (float)x.x;
-        im = (float)x.y;
-    }
     typedef typename Op<DT>::E E;
-    E *o = reinterpret_cast<E *>(out) + ((int64_t)c * cols_pad + col) * 2 * Ap;
-    if (DT == EPIC_F16_MFMA) {
-        o[a] = to_f16(re);
-        o[Ap + a] = to_f16(im);
-    } else if (DT == EPIC_BF16X2_MFMA) {
-        o[a] = to_bf16(re);
-        o[Ap + a] = to_bf16(im);
+    E re[4], im[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int a = a0 + j;
+        float xr = 0.f, xi = 0.f;
+        if (a < A && t < n_time) {
+            const int2 x = volt_at(volt + (int64_t)t * vstride, ((int64_t)c * P + p) * A + a, vb);
+            xr = (float)x.x;
+            xi = (float)x.y;
+        }
+        if (DT == EPIC_F16_MFMA) {
+            re[j] = to_f16(xr);
+            im[j] = to_f16(xi);
+        } else if (DT == EPIC_BF16X2_MFMA) {
+            re[j] = to_bf16(xr);
+            im[j] = to_bf16(xi);
+        } else {
+            re[j] = to_e4m3(xr);
+            im[j] = to_e4m3(xi);
+        }
+    }
+    E *o = reinterpret_cast<E *>(out) + ((int64_t)c * cols_pad + col) * 2 * Ap + a0;
+    if (sizeof(E) == 1) {
+        *reinterpret_cast<uint32_t *>(o) = (uint32_t)re[0] | (uint32_t)re[1] << 8 |
+                                           (uint32_t)re[2] << 16 | (uint32_t)re[3] << 24;
+        *reinterpret_cast<uint32_t *>(o + Ap) = (uint32_t)im[0] | (uint32_t)im[1] << 8 |
+                                                (uint32_t)im[2] << 16 | (uint32_t)im[3] << 24;
     } else {
-        o[a] = to_e4m3(re);
-        o[Ap + a] = to_e4m3(im);
+        *reinterpret_cast<uint2 *>(o) = make_uint2((uint32_t)re[0] | (uint32_t)re[1] << 16,
+                                                   (uint32_t)re[2] | (uint32_t)re[3] << 16);
+        *reinterpret_cast<uint2 *>(o + Ap) = make_uint2((uint32_t)im[0] | (uint32_t)im[1] << 16,
+                                                        (uint32_t)im[2] | (uint32_t)im[3] << 16);
     }
 }
 
@@ -518,7 +538,7 @@ static epic_status gemm_chunk(epic_plan p, float *acc, uint8_t *vbuf, const uint
     GemmPlan &gp = p->gemm;
     const int cw = 16 * gemm_ct<DT>();
     const int cols_pad = ((nt * p->P + cw - 1) / cw) * cw;
-    const int64_t tot = (int64_t)p->C * cols_pad * gp.Ap;
+    const int64_t tot = (int64_t)p->C * cols_pad * (gp.Ap / 4);
     const int64_t vstride = p->vstride();
     hipLaunchKernelGGL(k_volt_operand<DT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                        d_volt, vstride, p->A, gp.Ap, p->P, p->C, nt, cols_pad, vbuf, p->vb);
