@@ -148,10 +148,13 @@ __global__ __launch_bounds__(256) void k_auto_h_jones(const double2 *__restrict_
     }
 }
 
-// One thread per (channel, pixel): img = (acc - remove * self) * scale.
-template <int P>
+// One thread per (channel, pixel): img = (acc - remove * self) * scale.  The
+// kernel side K is a template argument so that the displacement loops unroll:
+// the phase powers stay in registers and the channel's H terms are loaded
+// together rather than one loop step at a time.
+template <int P, int K>
 __global__ void k_readout(const float *__restrict__ acc, const double2 *__restrict__ H,
-                          const int4 *__restrict__ chan, const int64_t *__restrict__ img_off, int K,
+                          const int4 *__restrict__ chan, const int64_t *__restrict__ img_off,
                           int remove, int stokes, float scale, float *__restrict__ img) {
     const int c = blockIdx.y;
     const int N = chan[c].x;
@@ -188,12 +191,12 @@ __global__ void k_readout(const float *__restrict__ acc, const double2 *__restri
         }
         return;
     }
-    const int D = 2 * K - 1;
+    constexpr int D = 2 * K - 1;
     constexpr int NH = P == 2 ? 3 : 1;
     const double2 *h = H + (size_t)c * NH * D * D;
     // exp(+2 pi i (k - N/2) d / N) for d = -(K-1) .. K-1 on each axis: one
     // exact base phase per axis (argument reduced mod N), then its powers
-    double2 px[5], py[5];
+    double2 px[D], py[D];
     {
         double s, cs;
         sincospi(2.0 * (double)(((kx - N / 2) % N + N) % N) / (double)N, &s, &cs);
@@ -202,6 +205,7 @@ __global__ void k_readout(const float *__restrict__ acc, const double2 *__restri
         const double2 wy = make_double2(cs, s);
         const int c0 = K - 1;
         px[c0] = py[c0] = make_double2(1.0, 0.0);
+#pragma unroll
         for (int m = 1; m < K; ++m) {
             const double2 a = px[c0 + m - 1], b = py[c0 + m - 1];
             px[c0 + m] = make_double2(a.x * wx.x - a.y * wx.y, a.x * wx.y + a.y * wx.x);
@@ -211,7 +215,9 @@ __global__ void k_readout(const float *__restrict__ acc, const double2 *__restri
         }
     }
     double sxx = 0, syy = 0, sxr = 0, sxi = 0;
+#pragma unroll
     for (int iy = 0; iy < D; ++iy)
+#pragma unroll
         for (int ix = 0; ix < D; ++ix) {
             const double er = px[ix].x * py[iy].x - px[ix].y * py[iy].y;
             const double ei = px[ix].x * py[iy].y + px[ix].y * py[iy].x;
@@ -266,14 +272,23 @@ epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hip
         EPIC_HIP(hipGetLastError());
     }
     dim3 g((p->max_n * p->max_n + 255) / 256, p->C);
-    if (p->P == 2)
-        hipLaunchKernelGGL(k_readout<2>, g, dim3(256), 0, s, acc->d_acc.as<float>(),
-                           H.as<double2>(), p->d_chan.as<int4>(), p->d_img_off.as<int64_t>(), p->K,
-                           remove ? 1 : 0, stokes, scale, d_img);
-    else
-        hipLaunchKernelGGL(k_readout<1>, g, dim3(256), 0, s, acc->d_acc.as<float>(),
-                           H.as<double2>(), p->d_chan.as<int4>(), p->d_img_off.as<int64_t>(), p->K,
-                           remove ? 1 : 0, stokes, scale, d_img);
+    const float *a = acc->d_acc.as<float>();
+    const double2 *h = H.as<double2>();
+    const int4 *ch = p->d_chan.as<int4>();
+    const int64_t *off = p->d_img_off.as<int64_t>();
+    const int rm = remove ? 1 : 0;
+#define EPIC_READOUT(PP, KK) \
+    hipLaunchKernelGGL((k_readout<PP, KK>), g, dim3(256), 0, s, a, h, ch, off, rm, stokes, scale, d_img)
+    switch (p->P * 4 + p->K) {
+        case 9: EPIC_READOUT(2, 1); break;
+        case 10: EPIC_READOUT(2, 2); break;
+        case 11: EPIC_READOUT(2, 3); break;
+        case 5: EPIC_READOUT(1, 1); break;
+        case 6: EPIC_READOUT(1, 2); break;
+        case 7: EPIC_READOUT(1, 3); break;
+        default: return fail(EPIC_ERR_UNSUPPORTED, "read-out: feeds or kernel size");
+    }
+#undef EPIC_READOUT
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
 }
