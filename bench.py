@@ -91,8 +91,47 @@ def traffic_from_profile(kernel_src):
         return None
 
 
+def cpu_model():
+    """Host CPU model string and logical core count, read at run time."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, os.cpu_count() or 1
+
+
+def cpu_fft_leg(wl, pos, chans, n_time, workers):
+    """CPU FFT baseline on the same slice as the oracle: FP64 gridding, the
+    library FFT (scipy, ``workers`` threads) in place of the direct DFT,
+    Eq. 2 sums and self-term removal.  E[k] = N^2 fftshift(ifft2(ifftshift(G)))
+    is the centred transform of Eq. 1.  Returns seconds."""
+    import scipy.fft as F
+
+    import oracle as O
+    import synth
+    v = synth.voltages(wl.with_time(n_time), pos, chans=chans)
+    t0 = time.perf_counter()
+    for i, c in enumerate(chans):
+        n = int(wl.grid_n[c])
+        E = O.decode_voltages(v[:, i])
+        x, j0 = O.grid_geometry(pos, wl.chan_freq_hz[c], n, wl.cell_lambda, wl.kernel_k)
+        w = O.gaussian_kernel(x, j0, wl.kernel_k, wl.kernel_sigma_cells)
+        G = O.grid(E, j0, w, n)
+        Es = F.fftshift(F.ifft2(F.ifftshift(G, axes=(-2, -1)), workers=workers),
+                        axes=(-2, -1)) * float(n * n)
+        acc = O.accumulate(Es)
+        auto = O.auto_term(O.antenna_autos(E), O.antenna_beams(j0, w, n))
+        O.readout(acc, auto, n_time)
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(wl, pos, target_s=12.0):
-    """The FP64 oracle on a bounded slice of the same workload.
+    """The FP64 oracle on a bounded slice of the same workload, and beside it
+    a CPU FFT baseline on the same slice.
 
     A short probe (one channel, 50 samples) sets the slice so that the timed
     run takes about ``target_s`` seconds: up to all 1000 samples of a channel,
@@ -131,11 +170,18 @@ def cpu_baseline(wl, pos, target_s=12.0):
                             [i * (wl.n_chan - 1) / max(1, n_ch - 1) for i in range(n_ch)]))]
         dt = run(chans, n_time)
     samples = len(chans) * n_time * per
+    model, ncpu = cpu_model()
+    dt_fft = cpu_fft_leg(wl, pos, chans, n_time, ncpu)
     return {"value": samples / dt, "unit": "samples/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"{len(chans)} channels x {n_time} samples x {wl.n_pol} pol x "
                       f"{wl.n_ant} ant of the same workload ({dt:.1f} s, FP64 NumPy, "
-                      f"BLAS threads {threads})"}
+                      f"BLAS threads {threads})",
+            "cpu_model": model, "cpu_logical_cores": ncpu,
+            "fft": {"value": samples / dt_fft, "unit": "samples/s", "cores": ncpu,
+                    "kind": "FP64 gridding + scipy.fft.ifft2 (workers = cores) + Eq. 2 sums "
+                            "+ self-term removal",
+                    "sample": f"same slice, {dt_fft:.1f} s"}}
 
 
 def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8):
@@ -193,6 +239,128 @@ def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8):
     per_block = tb * p0.n_chan * p0.n_pol * p0.n_ant
     st["sustained_samples_per_s"] = kept * per_block / wall
     st["real_time_samples_per_s"] = n_streams * per_block / period_s
+    return st
+
+
+def image_error(got, ref):
+    """Max and RMS image error relative to the co-pol reference of the same
+    channel: max|dI| / max|I_ref XX, YY| and RMS(dI) / RMS(I_ref XX, YY), over
+    every product (XY planes are normalised by the co-pol figures too)."""
+    import numpy as np
+    co = ref[:min(2, ref.shape[0])]
+    d = got - ref
+    return (float(np.max(np.abs(d)) / np.max(np.abs(co))),
+            float(np.sqrt(np.mean(d ** 2)) / np.sqrt(np.mean(co ** 2))))
+
+
+def oracle_errors(wl, pos, volt, chans, gpu, remove_autos=True):
+    """Errors of GPU read-outs against the FP64 oracle on sampled channels.
+
+    ``volt`` holds the sampled channels' voltages ``[T][len(chans)]...``;
+    ``gpu`` maps a label to ``(plan, image tensor)`` read out with
+    normalisation (and self-term removal when ``remove_autos``).  Returns
+    ``{label: {"max": m, "rms": r, "channels": [...], "samples": T}}`` with
+    the worst channel's figures."""
+    import numpy as np
+
+    import oracle as O
+    refs = []
+    for i, c in enumerate(chans):
+        r = O.channel_reference(volt[:, i], pos, wl.chan_freq_hz[c], int(wl.grid_n[c]),
+                                cell_lambda=wl.cell_lambda, k=wl.kernel_k,
+                                sigma=wl.kernel_sigma_cells, aperture_n=wl.aperture_n,
+                                want_auto=remove_autos)
+        refs.append(O.readout(r["acc"], r["auto"] if remove_autos else None, r["count"]))
+    out = {}
+    for label, (plan, img) in gpu.items():
+        host = img.cpu()
+        worst = (0.0, 0.0)
+        for i, c in enumerate(chans):
+            got = plan.channel_image(host, c).numpy().astype(np.float64)
+            e = image_error(got, refs[i])
+            worst = (max(worst[0], e[0]), max(worst[1], e[1]))
+        out[label] = {"max": worst[0], "rms": worst[1], "channels": list(chans),
+                      "samples": int(volt.shape[0]),
+                      "self_terms_removed": bool(remove_autos)}
+    return out
+
+
+_STREAM_BLOCKS = {}
+
+
+def stream_blocks(torch, n=2):
+    """Device copies of blocks 0..n-1 of the 4096-element streaming array
+    (256 samples x 64 channels x 2 feeds, 134 MB each), generated once per
+    process."""
+    import synth
+    if n not in _STREAM_BLOCKS:
+        wl = synth.workload("stream")
+        pos = synth.antenna_layout(wl)
+        t0 = time.perf_counter()
+        blocks = [torch.from_numpy(synth.voltages(wl, pos, block=b)) for b in range(n)]
+        _STREAM_BLOCKS[n] = (wl, pos, torch.stack(blocks).cuda(), time.perf_counter() - t0)
+    return _STREAM_BLOCKS[n]
+
+
+def streaming_large(E, torch, n_streams, n_chan=64, n_blocks=60, ring=2, warm_blocks=6):
+    """The streaming large-N configuration through the server: blocks of 256
+    samples (1.024 ms at 250 kHz channels) of the 4096-element array arrive
+    every 1.024 ms from ``n_streams`` streams, on FP16 plans (256^2 grids,
+    four-step MFMA transform), device-resident rings and accumulators,
+    admission by the plans' footprint.  ``n_chan`` < 64 runs the first
+    channels only (one GPU's share when channels are spread over GPUs).
+
+    Returns p50 / p99 / max block latency, dropped and late blocks, the share
+    of arrived data imaged and the host-side attribution of the slowest
+    blocks."""
+    import numpy as np
+
+    from paper_2609_03027_amd.serve import DeviceExecutor, Server, StreamSpec
+    wl, pos, blocks, gen_s = stream_blocks(torch)
+    tb, period = wl.n_time, wl.n_time / 250e3
+    chans = list(range(n_chan))
+    sub = wl.subset(chans)
+    plan = E.Plan.from_workload(sub, pos, precision=E.EPIC_F16_MFMA)
+    ring_t = blocks if n_chan == wl.n_chan else blocks[:, :, :n_chan].contiguous()
+    rings = {f"s{i}": ring_t for i in range(n_streams)}
+    ex = DeviceExecutor(rings)
+    free, _ = torch.cuda.mem_get_info()
+
+    def specs(nb):
+        return [StreamSpec(f"s{i}", plan, tb, period, nb, nb, deadline_s=period, ring=ring,
+                           phase_s=i * period / n_streams) for i in range(n_streams)]
+
+    warm = Server(ex, budget_bytes=int(0.8 * free))
+    for sp in specs(warm_blocks):
+        warm.submit_stream(sp)
+    warm.run(timeout_s=60.0)
+    srv = Server(ex, budget_bytes=int(0.8 * free))
+    for sp in specs(n_blocks):
+        assert srv.submit_stream(sp)
+    t0 = time.perf_counter()
+    fin = srv.run(timeout_s=120.0)
+    wall = time.perf_counter() - t0
+    recs = [r for st in fin.values() for r in st.records]
+    st = Server.stats(recs)
+    kept = [r for r in recs if not r.dropped]
+    lat = np.array([r.latency for r in kept])
+    st["late"] = int(np.sum(lat > period))
+    st.update(srv.host_stats(recs))
+    slow = sorted(kept, key=lambda r: -r.latency)[:3]
+    st["slowest"] = [{"stream": r.stream, "block": r.index, "latency_ms": round(r.latency * 1e3, 3),
+                      "pass_gap_ms": round(r.pass_gap * 1e3, 3),
+                      "call_ms": round(r.call_s * 1e3, 3),
+                      "queued_ms": round((r.submit - r.arrival) * 1e3, 3)} for r in slow]
+    per_block = sub.samples_per_block()
+    st.update(streams=n_streams, channels=n_chan, block_samples=tb, period_ms=period * 1e3,
+              ring=ring, imaged_fraction=len(kept) / max(1, len(recs)),
+              sustained_samples_per_s=len(kept) * per_block / wall,
+              real_time_samples_per_s=n_streams * per_block / period,
+              bytes_admitted=srv.need[f"s0"] * n_streams + plan.footprint(tb)["bytes_plan"])
+    st["real_time_fraction"] = st["sustained_samples_per_s"] / st["real_time_samples_per_s"]
+    plan.close()
+    del ex, rings
+    torch.cuda.empty_cache()
     return st
 
 
@@ -497,11 +665,8 @@ def large_stream(E, torch, reps=3):
     path at this size) and, beside it, the fused path forced to 64 x 64
     sub-transforms."""
     import synth
-    wl = synth.workload("stream")
-    pos = synth.antenna_layout(wl)
-    t0 = time.perf_counter()
-    volt = torch.from_numpy(synth.voltages(wl, pos)).cuda()
-    tgen = time.perf_counter() - t0
+    wl, pos, blocks, tgen = stream_blocks(torch)
+    volt = blocks[0]
 
     def timed(sub_n, precision=E.EPIC_F32, images=None):
         t0 = time.perf_counter()
@@ -580,6 +745,19 @@ def large_stream(E, torch, reps=3):
         f"({block_ms / ms:.2f} of real time; fused 64x64 {ms_fused:.2f} ms), plan {tplan:.1f} s; "
         f"scratch + sums {res['hbm_GBps']:.0f} GB/s, device copy {copy_gbs:.0f} GB/s, "
         f"fill {fill_gbs:.0f} GB/s")
+    # 32 samples of two channels through the FP16 four-step plan, read out
+    # without self-term removal (whose oracle costs A N^2 per channel), for
+    # the measured-error comparison against the oracle
+    p16 = E.Plan.from_workload(wl, pos, precision=E.EPIC_F16_MFMA)
+    a16 = E.Accumulator(p16)
+    E.accumulate(p16, a16, volt=volt[:32])
+    i16 = torch.empty(p16.info["image_floats"], dtype=torch.float32, device="cuda")
+    E.readout(p16, a16, i16, E.NORMALISE)
+    torch.cuda.synchronize()
+    a16.close()
+    echans = [0, wl.n_chan - 1]
+    res["_err_gpu"] = (wl.with_time(32), pos, volt[:32].cpu().numpy()[:, echans], echans,
+                       {"fp16_fft_fourstep": (p16, i16)})
     r16 = res["fp16_fourstep"]
     log(f"large stream fp16 four-step MFMA: {ms_f16:.2f} ms per block ({ms / ms_f16:.2f} x FP32), "
         f"{r16['mfma_tflops']:.0f} TFLOP/s MFMA ({r16['mfma_frac']:.1%}), "
@@ -611,6 +789,11 @@ def main():
                     help="time the LWA step with full polarimetric (Jones) kernels (0 = skip)")
     ap.add_argument("--fixed", type=int, default=1,
                     help="time the low-bitwidth (16-bit fixed-point) path against FP32 (0 = skip)")
+    ap.add_argument("--stream5-blocks", type=int, default=60,
+                    help="blocks per stream of the 4096-element array through the server "
+                         "(0 = skip)")
+    ap.add_argument("--errors", type=int, default=1,
+                    help="measure image errors per operand type against the oracle (CPU)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="MiB for a plain device copy (counter calibration runs)")
     args = ap.parse_args()
@@ -669,6 +852,7 @@ def main():
         step_evs[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
+    err_gpu = {"fp32_fft_fused": (plan, img.clone())}
     kern_ms = [a.elapsed_time(b) for a, b in evs]
     step_ms = [a.elapsed_time(b) for a, b in step_evs]
     ms_per_step = wall * 1e3 / args.steps
@@ -744,6 +928,11 @@ def main():
         b.record(stream)
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / 3
+        acc2.reset()
+        staged()
+        img_st = torch.empty_like(img)
+        E.readout(plan, acc2, img_st, E.REMOVE_AUTOS | E.NORMALISE)
+        staged_err_gpu = {"fp32_fft_staged": (plan, img_st)}
         sv = Ts * wl.n_chan * wl.n_pol * wl.n_ant / (ms / 1e3)
         # algorithmic HBM bytes of the staged form: per (t, c) the grid is
         # written, read and the sky written by the transform, the sky read by
@@ -764,11 +953,12 @@ def main():
     if args.variants:
         tol = json.load(open(os.path.join(ROOT, "tests", "tolerances.json")))
         out["variants"] = {}
-        for name, prec, peak in (("bf16x2", E.EPIC_BF16X2_MFMA, 2500.0),
-                                 ("fp16", E.EPIC_F16_MFMA, 2500.0),
-                                 ("fp8e4m3", E.EPIC_F8E4M3_MFMA, 5000.0)):
+        for name, prec, peak, xf in (("bf16x2", E.EPIC_BF16X2_MFMA, 2500.0, E.XFORM_DFT_DIRECT),
+                                     ("fp16", E.EPIC_F16_MFMA, 2500.0, E.XFORM_DFT_DIRECT),
+                                     ("fp8e4m3", E.EPIC_F8E4M3_MFMA, 5000.0,
+                                      E.XFORM_DFT_DIRECT)):
             t0 = time.perf_counter()
-            vplan = E.Plan.from_workload(wl, pos, precision=prec)
+            vplan = E.Plan.from_workload(wl, pos, precision=prec, xform=xf)
             torch.cuda.synchronize()
             tplan = time.perf_counter() - t0
             vacc = E.Accumulator(vplan)
@@ -798,6 +988,7 @@ def main():
                 "max_err_bound": tol[name]["max"],
                 "speedup_vs_fp32": out["ms_per_step"] / ms}
             log(f"{name}: {ms:.2f} ms/step, {tf:.0f} TFLOP/s MFMA ({tf / peak:.1%}), plan {tplan:.1f} s")
+            err_gpu[f"{name}_dft_direct"] = (plan, img.clone())
             del vacc, vplan
             torch.cuda.empty_cache()
         out["variants"]["fp32_fft_max_err_bound"] = tol["fp32"]["max"]
@@ -816,15 +1007,38 @@ def main():
     if args.fixed:
         out["low_bitwidth"] = low_bitwidth(E, torch)
 
+    if args.stream5_blocks > 0:
+        # the streaming large-N configuration itself, then one GPU's share of
+        # it when its 64 channels are spread over 8 GPUs (8 channels x 4 streams)
+        out["streaming_large"] = {
+            "workload": "stream-large through the server: 4096 dual-pol elements, 300 m disc, "
+                        "256^2 grids, FP16 four-step MFMA plans, 256-sample blocks every "
+                        "1.024 ms per stream, device rings, footprint-budgeted admission"}
+        for ns, nch in ((1, 64), (4, 64), (4, 8)):
+            st = streaming_large(E, torch, ns, n_chan=nch, n_blocks=args.stream5_blocks)
+            out["streaming_large"][f"{ns}x{nch}ch"] = st
+            log(f"stream-large x{ns} ({nch} ch): p50 {st.get('p50_ms', float('nan')):.2f} ms, "
+                f"p99 {st.get('p99_ms', float('nan')):.2f} ms, dropped {st['dropped']} of "
+                f"{st['blocks']}, {st['real_time_fraction']:.2f} of real time; host: pass "
+                f"{st['max_pass_ms']:.2f} ms, gap {st['max_pass_gap_ms']:.2f} ms")
+        head = out["streaming_large"]["1x64ch"]
+        out["p99_block_latency_ms"] = head.get("p99_ms")
+        out["p99_block_latency_workload"] = (
+            "stream-large: one stream of 256-sample blocks of the 4096-element array, 64 "
+            "channels of 256^2, FP16 four-step, every 1.024 ms; blocks beyond a ring of "
+            f"{head['ring']} in flight are dropped ({head['dropped']} of {head['blocks']})")
     if args.stream_blocks > 0:
-        out["streaming"] = {}
+        out["streaming"] = {"workload": "lwa-station 25-sample blocks (1 ms at 25 kHz), FP32 "
+                                        "fused path, 1 and 4 stations"}
         for ns in (1, 4):
             st = streaming(E, torch, ns, args.stream_blocks)
             out["streaming"][str(ns)] = st
             log(f"streaming x{ns}: p50 {st.get('p50_ms', float('nan')):.3f} ms, "
                 f"p99 {st.get('p99_ms', float('nan')):.3f} ms, dropped {st['dropped']}, "
                 f"late {st['late']} of {st['blocks']}")
-        out["p99_block_latency_ms"] = out["streaming"]["1"].get("p99_ms")
+        if "p99_block_latency_ms" not in out:
+            out["p99_block_latency_ms"] = out["streaming"]["1"].get("p99_ms")
+            out["p99_block_latency_workload"] = "lwa-station 25-sample blocks, one station"
 
     if args.copy_calib > 0:
         n = args.copy_calib * (1 << 20) // 4
@@ -837,7 +1051,27 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(wl, pos)
-        log(f"cpu baseline: {out['cpu_baseline']['value']:.3e} samples/s")
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.3e} samples/s, FFT leg "
+            f"{out['cpu_baseline']['fft']['value']:.3e} samples/s")
+        if args.errors:
+            # measured image errors per operand type and transform form, on
+            # two sampled channels against the FP64 oracle
+            t0 = time.perf_counter()
+            chans = [0, wl.n_chan - 1]
+            errs = oracle_errors(wl, pos, volt_np[:, chans], chans, err_gpu)
+            if args.staged > 0:
+                errs.update(oracle_errors(wl, pos, volt_np[:args.staged, chans], chans,
+                                          staged_err_gpu))
+            if "large_stream" in out and "_err_gpu" in out["large_stream"]:
+                lw, lpos, lvolt, lchans, lgpu = out["large_stream"].pop("_err_gpu")
+                errs.update(oracle_errors(lw, lpos, lvolt, lchans, lgpu, remove_autos=False))
+            out["errors"] = errs
+            for k, v in errs.items():
+                log(f"error {k}: max {v['max']:.2e} rms {v['rms']:.2e} "
+                    f"({v['samples']} samples, channels {v['channels']})")
+            log(f"oracle errors: {time.perf_counter() - t0:.1f} s")
+    if "large_stream" in out:
+        out["large_stream"].pop("_err_gpu", None)
 
     print(json.dumps(out), flush=True)
 

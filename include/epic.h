@@ -36,8 +36,14 @@
  *     images     : float32   [c][n_prod][N_c][N_c]   (n_prod = 1 if P = 1,
  *                  else 4: XX, YY, Re XY, Im XY with XY = Ex conj(Ey))
  *     autos      : int32     [c][a][n_prod]  sum_t E_a^p conj(E_a^q), exact
- *                  while the sums fit int32 (4+4 bit: 2^31 / 128 samples;
- *                  8+8 bit: 2^31 / 32768 = 65536 samples per accumulator)
+ *                  while the sums fit int32.  One sample adds at most
+ *                  e_max = 2 * 8^2 = 128 (4+4 bit: -8 - 8i) or 2 * 128^2 = 32768
+ *                  (8+8 bit: -128 - 128i) to a sum, so an accumulator takes at
+ *                  most EPIC_MAX_SAMPLES_4BIT = floor((2^31 - 1) / 128) =
+ *                  16 777 215 or EPIC_MAX_SAMPLES_8BIT = 65 535 samples; calls
+ *                  that would pass the limit fail with EPIC_ERR_ARG before any
+ *                  device work (epic_accumulate, epic_graph_launch,
+ *                  epic_acc_import).
  * - A plan is immutable after creation and may be used from several threads
  *   and streams.  An accumulator must not be used on two streams at once.
  */
@@ -87,6 +93,36 @@ typedef enum {
                                quantised kernel. */
 } epic_precision;
 
+/* Largest sample count one accumulator takes (exact int32 self-term sums). */
+#define EPIC_MAX_SAMPLES_4BIT 16777215LL
+#define EPIC_MAX_SAMPLES_8BIT 65535LL
+
+/* Form of the Eq. 1 outer sum (the spatial Fourier transform), chosen
+ * independently of the operand precision.  Not every pair is built:
+ *   EPIC_XFORM_AUTO           FP32 and EPIC_FIXED16: FFT; FP16: the four-step
+ *                             FFT on 256 x 256 grids, the direct DFT-GEMM on
+ *                             other sides; FP8, BF16 hi+lo: the direct DFT-GEMM.
+ *   EPIC_XFORM_FFT            FP32 (fused, banded and staged radix FFTs),
+ *                             EPIC_FIXED16 (fixed-point radix 2), FP16 on
+ *                             256 x 256 grids only (four-step 16 x 16 on MFMA).
+ *   EPIC_XFORM_DFT_DIRECT     FP16, FP8, BF16 hi+lo: E = B V with B the
+ *                             pixels x elements beam matrix (A <= 256, N <= 256).
+ *   EPIC_XFORM_DFT_SEPARABLE  FP16, BF16 hi+lo: each sample's grid G is
+ *                             transformed as F G F^T with the centred DFT
+ *                             matrix F restricted to the columns of the
+ *                             gridded region (aperture pruning): 8 Na^2 N +
+ *                             8 N^2 Na flops per image instead of 8 N^2 A.
+ *                             Grid sides 64 or 128 with a gridded region of
+ *                             at most 64 x 64 (aperture_n, or the grid side),
+ *                             two feeds.
+ * Any other pair fails plan creation with EPIC_ERR_UNSUPPORTED. */
+typedef enum {
+    EPIC_XFORM_AUTO = 0,
+    EPIC_XFORM_FFT = 1,
+    EPIC_XFORM_DFT_DIRECT = 2,
+    EPIC_XFORM_DFT_SEPARABLE = 3
+} epic_xform;
+
 /* EPIC_FIXED16 settings: -1 selects the default */
 #define EPIC_FIXED_DEFAULT (-1)
 
@@ -118,7 +154,12 @@ typedef struct {
     int32_t n_chan;              /* C >= 1 */
     const double *ant_pos_m;     /* host [A][2] (east, north) metres; copied */
     const double *chan_freq_hz;  /* host [C] channel centre frequencies; copied */
-    const int32_t *grid_n;       /* host [C] FFT side per channel (even) */
+    const int32_t *grid_n;       /* host [C] FFT side per channel (even), or NULL: the
+                                    smallest of 32, 48, 64, 96, 128, 192, 256, 384, 512
+                                    with N_c >= 2 ceil(D / cell_c + K), D = 2 max_a
+                                    max(|east_a|, |north_a|) the side of the centred
+                                    square holding every element (EPIC_ERR_GRID if
+                                    none fits); epic_plan_grid_sides reads them back */
     int32_t aperture_n;          /* 0: gridded region = whole grid; else the side of the
                                     central region every support must fit in */
     double cell_lambda;          /* grid cell in wavelengths (0 -> 0.5) */
@@ -146,6 +187,13 @@ typedef struct {
     int32_t fixed_grid_shift;    /* 0..30 bits dropped (rounding) from the exact gridded
                                     sums; EPIC_FIXED_DEFAULT = the smallest shift with which
                                     no cell of any channel can saturate at the voltage width */
+    int32_t xform;               /* an epic_xform value; 0 = EPIC_XFORM_AUTO */
+    int64_t volt_stride_t;       /* bytes between consecutive time samples of the voltage
+                                    input; 0 = C * P * A * (1 or 2 bytes), the packed
+                                    layout.  Otherwise at least that and a multiple of the
+                                    bytes per sample (EPIC_ERR_ARG): the [c][p][a] block of
+                                    each sample is packed, samples may be spaced further
+                                    apart (a ring with headers, a larger capture buffer) */
 } epic_plan_desc;
 
 typedef struct epic_plan_s *epic_plan;  /* opaque; owns device tables */
@@ -174,6 +222,19 @@ typedef struct {
 epic_status epic_plan_create(const epic_plan_desc *desc, void *hip_stream, epic_plan *out);
 epic_status epic_plan_destroy(epic_plan plan);
 epic_status epic_plan_get_info(epic_plan plan, epic_plan_info *info);
+/* Host copy of the plan's grid side per channel (host int32 [C]); with a NULL
+ * grid_n in the descriptor this is where the chosen sides are read. */
+epic_status epic_plan_grid_sides(epic_plan plan, int32_t *grid_n);
+/* Device memory a stream of this plan needs (HBM-budget admission):
+ *   *bytes_plan      the plan's tables (shared by every accumulator of the plan);
+ *   *bytes_per_acc   one accumulator: sums, self terms, read-out scratch and the
+ *                    working memory of the plan's path (banded row-transform
+ *                    scratch, MFMA operand staging, time-slice partial sums);
+ *   *bytes_per_block one block of block_samples voltage samples in the input
+ *                    layout ((block_samples - 1) * stride + C P A bytes per sample).
+ * Any output pointer may be NULL.  block_samples >= 1 (EPIC_ERR_ARG). */
+epic_status epic_plan_footprint(epic_plan plan, int32_t block_samples, int64_t *bytes_plan,
+                                int64_t *bytes_per_acc, int64_t *bytes_per_block);
 
 /* Accumulators for Eq. 2: zeroed FP32 image sums, int32 self-term sums and
  * the sample count, all device resident and owned by the handle, plus the
@@ -192,6 +253,10 @@ epic_status epic_acc_export(epic_acc acc, float *d_acc, int32_t *d_autos, int64_
                             void *hip_stream);
 epic_status epic_acc_import(epic_acc acc, const float *d_acc, const int32_t *d_autos,
                             int64_t count, void *hip_stream);
+/* Checkpoint / resume (Eq. 2 sums are plain state): export the three parts
+ * after any call, import them into an accumulator of the same plan, and
+ * further calls give bit for bit the sums of an uninterrupted run.  count
+ * above the plan's EPIC_MAX_SAMPLES_* limit is EPIC_ERR_ARG. */
 
 /* Calls with n_time == 0 (epic_grid, epic_image, epic_accumulate,
  * epic_accumulate_frames) do nothing and return EPIC_OK; their data pointers
@@ -252,7 +317,9 @@ epic_status epic_readout(epic_plan plan, epic_acc acc, float *d_img, uint32_t fl
  * of the same buffer (refill it between launches) and advances the count.
  * The graph holds no memset nodes.  Capture happens on an internal stream;
  * hip_stream is only synchronised.  A graph must be destroyed before its plan
- * or accumulator. */
+ * or accumulator.  Plans with banded channels capture at most two scratch
+ * rounds (2 t_chunk samples, 512 for most plans): longer captures fail with
+ * EPIC_ERR_UNSUPPORTED before capture begins. */
 epic_status epic_graph_create(epic_plan plan, epic_acc acc, const uint8_t *d_volt,
                               int32_t n_time, void *hip_stream, epic_graph *out);
 epic_status epic_graph_launch(epic_graph graph, void *hip_stream);

@@ -47,7 +47,7 @@ __all__ = [
     "support_inside", "grid", "centred_dft_matrix", "sky", "n_products",
     "accumulate", "antenna_autos", "antenna_beams", "auto_term", "auto_term_by_element",
     "readout",
-    "fx_image", "channel_reference", "epic_reference", "decode_int8", "decode_voltages",
+    "fx_image", "channel_reference", "decode_int8", "decode_voltages",
     "pseudo_stokes", "grid_jones", "antenna_beams_jones", "auto_term_jones",
     "fx_image_jones",
 ]
@@ -483,27 +483,4 @@ def channel_reference(volt_c, pos, freq_hz, n, *, cell_lambda=0.5, k=3,
     if want_images:
         out["grid"] = G
         out["sky"] = Es
-    return out
-
-
-def epic_reference(volt, pos, freq_hz, grid_n, *, cell_lambda=0.5, k=3,
-                   sigma=0.5, kernels=None, aperture_n=0, chans=None,
-                   remove_autos=True, normalise=True, jones=None):
-    """Read-out images for a block ``uint8 [T][C][P][A]``; ``kernels`` and
-    ``jones`` are per-channel lists as in ``channel_reference``.
-
-    Returns a list over the requested channels of float64 [n_prod][N_c][N_c]
-    images, (acc - auto) / T with the optional steps as flagged.
-    """
-    volt = np.asarray(volt)
-    C = volt.shape[1]
-    chans = range(C) if chans is None else chans
-    out = []
-    for c in chans:
-        r = channel_reference(
-            volt[:, c], pos, freq_hz[c], int(grid_n[c]), cell_lambda=cell_lambda,
-            k=k, sigma=sigma, kernel=None if kernels is None else kernels[c],
-            aperture_n=aperture_n, jones=None if jones is None else jones[c])
-        out.append(readout(r["acc"], r["auto"] if remove_autos else None,
-                           r["count"], normalise))
     return out

@@ -16,6 +16,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libepic.so")
 
 EPIC_F32, EPIC_F16_MFMA, EPIC_F8E4M3_MFMA, EPIC_BF16X2_MFMA, EPIC_FIXED16 = 0, 1, 2, 3, 4
+# transform form (epic_xform)
+XFORM_AUTO, XFORM_FFT, XFORM_DFT_DIRECT, XFORM_DFT_SEPARABLE = 0, 1, 2, 3
+# largest sample count per accumulator (exact int32 self-term sums)
+MAX_SAMPLES_4BIT, MAX_SAMPLES_8BIT = 16777215, 65535
 FIXED_DEFAULT = -1     # EPIC_FIXED16 stage mask / grid shift: library default
 REMOVE_AUTOS = 1
 NORMALISE = 2
@@ -35,7 +39,7 @@ EXPORTS = [
     "epic_acc_export", "epic_acc_import", "epic_grid", "epic_image",
     "epic_accumulate", "epic_readout", "epic_status_str", "epic_last_error",
     "epic_version", "epic_graph_create", "epic_graph_launch", "epic_graph_destroy",
-    "epic_accumulate_frames",
+    "epic_accumulate_frames", "epic_plan_footprint", "epic_plan_grid_sides",
 ]
 
 
@@ -62,6 +66,8 @@ class PlanDesc(C.Structure):
         ("fixed_twiddle_bits", C.c_int32),
         ("fixed_stage_shifts", C.c_int32),
         ("fixed_grid_shift", C.c_int32),
+        ("xform", C.c_int32),
+        ("volt_stride_t", C.c_int64),
     ]
 
 
@@ -106,6 +112,8 @@ def load() -> C.CDLL:
         "epic_graph_launch": [vp, vp],
         "epic_graph_destroy": [vp],
         "epic_accumulate_frames": [vp, vp, vp, i32, i32, vp, vp],
+        "epic_plan_footprint": [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
+        "epic_plan_grid_sides": [vp, C.POINTER(i32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -147,11 +155,15 @@ class Plan:
     def __init__(self, pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5,
                  kernel_k=3, kernel_sigma=0.5, kernel_table=None, precision=EPIC_F32,
                  sub_n=None, volt_bits=4, jones=False, twiddle_bits=8,
-                 stage_shifts=FIXED_DEFAULT, grid_shift=FIXED_DEFAULT, stream=None):
+                 stage_shifts=FIXED_DEFAULT, grid_shift=FIXED_DEFAULT, xform=XFORM_AUTO,
+                 volt_stride=0, stream=None):
+        """``grid_n`` None: the library picks each channel's side (see
+        ``epic_plan_desc.grid_n``); ``volt_stride``: bytes between time
+        samples of the voltage input (0 = packed)."""
         lib = load()
         self._pos = np.ascontiguousarray(pos, dtype=np.float64)
         self._freq = np.ascontiguousarray(freq_hz, dtype=np.float64)
-        self._gn = np.ascontiguousarray(grid_n, dtype=np.int32)
+        self._gn = None if grid_n is None else np.ascontiguousarray(grid_n, dtype=np.int32)
         self._table = None if kernel_table is None else np.ascontiguousarray(
             kernel_table, dtype=np.float32)
         # kernel_table: [C][A][K][K][2], or with jones [C][A][2][2][K][K][2]
@@ -166,7 +178,7 @@ class Plan:
         d.n_chan = self._freq.shape[0]
         d.ant_pos_m = self._pos.ctypes.data_as(C.POINTER(C.c_double))
         d.chan_freq_hz = self._freq.ctypes.data_as(C.POINTER(C.c_double))
-        d.grid_n = self._gn.ctypes.data_as(C.POINTER(C.c_int32))
+        d.grid_n = None if self._gn is None else self._gn.ctypes.data_as(C.POINTER(C.c_int32))
         d.aperture_n = int(aperture_n)
         d.cell_lambda = float(cell_lambda)
         d.kernel_k = int(kernel_k)
@@ -181,6 +193,8 @@ class Plan:
         d.fixed_twiddle_bits = int(twiddle_bits)
         d.fixed_stage_shifts = int(stage_shifts)
         d.fixed_grid_shift = int(grid_shift)
+        d.xform = int(xform)
+        d.volt_stride_t = int(volt_stride)
         self._sub = None if sub_n is None else np.ascontiguousarray(sub_n, dtype=np.int32)
         d.sub_n = None if self._sub is None else self._sub.ctypes.data_as(C.POINTER(C.c_int32))
         h = C.c_void_p()
@@ -191,13 +205,24 @@ class Plan:
         self.info = {k: getattr(info, k) for k, _ in PlanInfo._fields_}
         self.n_ant, self.n_pol, self.n_chan = d.n_ant, d.n_pol, d.n_chan
         self.n_prod = info.n_prod
-        self.grid_n = self._gn.copy()
+        gn = np.zeros(d.n_chan, dtype=np.int32)
+        check(lib.epic_plan_grid_sides(h, gn.ctypes.data_as(C.POINTER(C.c_int32))))
+        self.grid_n = gn
         n2 = self.grid_n.astype(np.int64) ** 2
         self.img_off = np.concatenate([[0], np.cumsum(self.n_prod * n2)[:-1]])
         self.grid_off = np.concatenate([[0], np.cumsum(self.n_pol * n2)[:-1]])
         self.precision = precision
         self.volt_bits = volt_bits
         self.jones = bool(jones)
+        self.xform = int(xform)
+
+    def footprint(self, block_samples: int = 1) -> dict:
+        """Device bytes for admission: the plan's tables, one accumulator and
+        one block of ``block_samples`` voltage samples."""
+        bp, ba, bb = C.c_int64(), C.c_int64(), C.c_int64()
+        check(load().epic_plan_footprint(self.handle, int(block_samples), C.byref(bp),
+                                         C.byref(ba), C.byref(bb)))
+        return {"bytes_plan": bp.value, "bytes_per_acc": ba.value, "bytes_per_block": bb.value}
 
     @classmethod
     def from_workload(cls, wl, pos, **kw):

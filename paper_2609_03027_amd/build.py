@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libepic.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["abi.hip", "plan.hip", "fused.hip", "banded.hip", "staged.hip", "readout.hip", "dftgemm.hip",
-           "fixed.hip"]
+           "fixed.hip", "sep.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -1,6 +1,7 @@
 // extern "C" entry points of libepic.so (declared in include/epic.h).
 // Argument checks happen here, before any device work; no C++ exception
 // crosses the boundary.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -37,6 +38,38 @@ using namespace epic;
         return fail(EPIC_ERR_DEVICE, "unexpected internal error");           \
     }
 
+namespace {
+
+// Largest sample count whose int32 self-term sums stay exact: one sample adds
+// at most 2 * 8^2 (4+4 bit) or 2 * 128^2 (8+8 bit) to a sum.
+int64_t max_samples(epic_plan p) {
+    return p->vb == 2 ? EPIC_MAX_SAMPLES_8BIT : EPIC_MAX_SAMPLES_4BIT;
+}
+
+epic_status count_guard(epic_plan p, int64_t have, int64_t add) {
+    if (have + add > max_samples(p))
+        return fail(EPIC_ERR_ARG, "the accumulator would hold " + std::to_string(have + add) +
+                                      " samples, above the " + std::to_string(max_samples(p)) +
+                                      " for which the int32 self-term sums stay exact");
+    return EPIC_OK;
+}
+
+// Grid side rule for a NULL grid_n: the smallest supported side N with
+// N >= 2 ceil(D / cell + K), D the side of the centred square that holds
+// every element.
+int auto_grid_side(const double *pos, int A, double freq, double cell_lambda, int K) {
+    static const int sizes[] = {32, 48, 64, 96, 128, 192, 256, 384, 512};
+    double ext = 0.0;
+    for (int i = 0; i < 2 * A; ++i) ext = std::max(ext, std::fabs(pos[i]));
+    const double cell = cell_lambda * kCLight / freq;
+    const double need = 2.0 * std::ceil(2.0 * ext / cell + K);
+    for (int n : sizes)
+        if (n >= need) return n;
+    return 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *epic_version(void) { return "epic-mi355x 0.1 (gfx950)"; }
@@ -63,8 +96,8 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     if (!out) return fail(EPIC_ERR_NULL, "out is NULL");
     *out = nullptr;
     if (!d) return fail(EPIC_ERR_NULL, "descriptor is NULL");
-    if (!d->ant_pos_m || !d->chan_freq_hz || !d->grid_n)
-        return fail(EPIC_ERR_NULL, "positions, frequencies and grid sizes are required");
+    if (!d->ant_pos_m || !d->chan_freq_hz)
+        return fail(EPIC_ERR_NULL, "positions and frequencies are required");
     if (d->n_ant < 1 || d->n_ant > 65535) return fail(EPIC_ERR_ARG, "n_ant must be in [1, 65535]");
     if (d->n_pol != 1 && d->n_pol != 2) return fail(EPIC_ERR_ARG, "n_pol must be 1 or 2");
     if (d->n_chan < 1 || d->n_chan > 65535) return fail(EPIC_ERR_ARG, "n_chan must be in [1, 65535]");
@@ -74,6 +107,29 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     const double sg = d->kernel_sigma_cells == 0.0 ? 0.5 : d->kernel_sigma_cells;
     if (!(cl > 0.0) || !std::isfinite(cl)) return fail(EPIC_ERR_ARG, "cell_lambda must be > 0");
     if (!(sg > 0.0) || !std::isfinite(sg)) return fail(EPIC_ERR_ARG, "kernel_sigma_cells must be > 0");
+    for (int c = 0; c < d->n_chan; ++c)
+        if (!(d->chan_freq_hz[c] > 0.0) || !std::isfinite(d->chan_freq_hz[c]))
+            return fail(EPIC_ERR_ARG, "channel frequencies must be finite and > 0");
+    for (int i = 0; i < 2 * d->n_ant; ++i)
+        if (!std::isfinite(d->ant_pos_m[i])) return fail(EPIC_ERR_ARG, "positions must be finite");
+    std::vector<int32_t> sides(d->n_chan);
+    for (int c = 0; c < d->n_chan; ++c) {
+        sides[c] = d->grid_n ? d->grid_n[c]
+                             : auto_grid_side(d->ant_pos_m, d->n_ant, d->chan_freq_hz[c], cl, K);
+        if (sides[c] == 0)
+            return fail(EPIC_ERR_GRID, "channel " + std::to_string(c) +
+                                           ": the array needs a grid side above 512");
+    }
+    const int32_t *grid_n = sides.data();
+    if (d->xform < EPIC_XFORM_AUTO || d->xform > EPIC_XFORM_DFT_SEPARABLE)
+        return fail(EPIC_ERR_ARG, "unknown xform");
+    {
+        const int64_t vb = (d->flags & EPIC_VOLT_8BIT) ? 2 : 1;
+        const int64_t packed = (int64_t)d->n_chan * d->n_pol * d->n_ant * vb;
+        if (d->volt_stride_t != 0 && (d->volt_stride_t < packed || d->volt_stride_t % vb))
+            return fail(EPIC_ERR_ARG, "volt_stride_t must be 0, or at least C * P * A * bytes "
+                                      "per sample and a multiple of the bytes per sample");
+    }
     if (d->precision < EPIC_F32 || d->precision > EPIC_FIXED16)
         return fail(EPIC_ERR_ARG, "unknown precision");
     if (d->precision == EPIC_FIXED16) {
@@ -87,7 +143,7 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
             (d->fixed_grid_shift < 0 || d->fixed_grid_shift > 30))
             return fail(EPIC_ERR_ARG, "fixed_grid_shift must be -1 or 0..30");
         for (int c = 0; c < d->n_chan; ++c)
-            if (d->grid_n[c] != 64)
+            if (grid_n[c] != 64)
                 return fail(EPIC_ERR_UNSUPPORTED, "the fixed-point path runs 64 x 64 grids");
         if (d->sub_n)
             for (int c = 0; c < d->n_chan; ++c)
@@ -113,18 +169,13 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     if (d->aperture_n < 0 || (d->aperture_n & 1))
         return fail(EPIC_ERR_ARG, "aperture_n must be 0 or a positive even number");
     for (int c = 0; c < d->n_chan; ++c)
-        if (!(d->chan_freq_hz[c] > 0.0) || !std::isfinite(d->chan_freq_hz[c]))
-            return fail(EPIC_ERR_ARG, "channel frequencies must be finite and > 0");
-    for (int i = 0; i < 2 * d->n_ant; ++i)
-        if (!std::isfinite(d->ant_pos_m[i])) return fail(EPIC_ERR_ARG, "positions must be finite");
-    for (int c = 0; c < d->n_chan; ++c)
-        if (d->grid_n[c] < 8 || (d->grid_n[c] & 1))
+        if (grid_n[c] < 8 || (grid_n[c] & 1))
             return fail(EPIC_ERR_GRID, "grid sides must be even and >= 8");
     if (d->sub_n)
         for (int c = 0; c < d->n_chan; ++c) {
             const int m = d->sub_n[c];
             if (m == 0 || m == EPIC_SUB_BANDED) continue;
-            if ((m != 16 && m != 32 && m != 64) || d->grid_n[c] % m || d->grid_n[c] / m > 8)
+            if ((m != 16 && m != 32 && m != 64) || grid_n[c] % m || grid_n[c] / m > 8)
                 return fail(EPIC_ERR_ARG, "sub_n must be 0, -1, 16, 32 or 64; 16, 32 and 64 "
                                           "must divide grid_n and leave at most 8 "
                                           "sub-transforms per axis");
@@ -151,7 +202,9 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     p->n_prod = p->P == 2 ? 4 : 1;
     p->pos.assign(d->ant_pos_m, d->ant_pos_m + 2 * p->A);
     p->freq.assign(d->chan_freq_hz, d->chan_freq_hz + p->C);
-    p->grid_n.assign(d->grid_n, d->grid_n + p->C);
+    p->grid_n.assign(grid_n, grid_n + p->C);
+    p->xform = d->xform;
+    p->volt_stride = d->volt_stride_t;
     if (d->sub_n) p->sub_n.assign(d->sub_n, d->sub_n + p->C);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     epic_status st = EPIC_OK;
@@ -202,6 +255,27 @@ epic_status epic_plan_get_info(epic_plan p, epic_plan_info *info) {
     info->fixed_grid_shift = fx ? p->fixed.sg : 0;
     info->fixed_scale_exp2 = fx ? p->fixed.exp2 : 0;
     info->fixed_slices = fx ? p->fixed.slices : 0;
+    return EPIC_OK;
+}
+
+epic_status epic_plan_grid_sides(epic_plan p, int32_t *grid_n) {
+    if (!p || !grid_n) return fail(EPIC_ERR_NULL, "plan or grid_n is NULL");
+    for (int c = 0; c < p->C; ++c) grid_n[c] = p->grid_n[c];
+    return EPIC_OK;
+}
+
+epic_status epic_plan_footprint(epic_plan p, int32_t block_samples, int64_t *bytes_plan,
+                                int64_t *bytes_per_acc, int64_t *bytes_per_block) {
+    if (!p) return fail(EPIC_ERR_NULL, "plan is NULL");
+    if (block_samples < 1) return fail(EPIC_ERR_ARG, "block_samples must be >= 1");
+    epic_plan_info info;
+    epic_status st = epic_plan_get_info(p, &info);
+    if (st) return st;
+    if (bytes_plan) *bytes_plan = info.bytes_plan;
+    if (bytes_per_acc) *bytes_per_acc = info.bytes_acc;
+    if (bytes_per_block)
+        *bytes_per_block = (int64_t)(block_samples - 1) * p->vstride() +
+                           (int64_t)p->C * p->P * p->A * p->vb;
     return EPIC_OK;
 }
 
@@ -271,6 +345,7 @@ epic_status epic_acc_import(epic_acc a, const float *d_acc, const int32_t *d_aut
                             void *hip_stream) {
     if (!a) return fail(EPIC_ERR_NULL, "acc is NULL");
     if (count < 0) return fail(EPIC_ERR_ARG, "count must be >= 0");
+    if (epic_status st = count_guard(a->plan, 0, count)) return st;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     if (d_acc) EPIC_HIP(hipMemcpyAsync(a->d_acc.p, d_acc, a->d_acc.bytes, hipMemcpyDeviceToDevice, s));
     if (d_autos)
@@ -309,6 +384,7 @@ epic_status epic_accumulate(epic_plan p, epic_acc a, const uint8_t *d_volt, cons
     if (n_time < 0) return fail(EPIC_ERR_ARG, "n_time must be >= 0");
     if (n_time == 0) return EPIC_OK;              // nothing is read; sums and count unchanged
     if (!d_volt && !d_sky) return fail(EPIC_ERR_NULL, "volt or sky is required");
+    if (epic_status st = count_guard(p, a->count, n_time)) return st;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     epic_status st;
     if (d_sky) {
@@ -318,6 +394,8 @@ epic_status epic_accumulate(epic_plan p, epic_acc a, const uint8_t *d_volt, cons
         st = fused_accumulate(p, a, d_volt, n_time, s);
     } else if (p->precision == EPIC_FIXED16) {
         st = fixed_accumulate(p, a, d_volt, n_time, s);
+    } else if (p->xform == EPIC_XFORM_DFT_SEPARABLE) {
+        st = sep_accumulate(p, a, d_volt, n_time, s);
     } else {
         st = gemm_accumulate(p, a, d_volt, n_time, s);
     }
@@ -355,6 +433,12 @@ epic_status epic_graph_create(epic_plan p, epic_acc a, const uint8_t *d_volt, in
     if (!p || !a || !d_volt) return fail(EPIC_ERR_NULL, "plan, acc and volt are required");
     if (a->plan != p) return fail(EPIC_ERR_MISMATCH, "accumulator belongs to another plan");
     if (n_time < 1) return fail(EPIC_ERR_ARG, "n_time must be >= 1");
+    if (n_time > max_samples(p))
+        return fail(EPIC_ERR_ARG, "n_time is above the accumulator's sample limit");
+    if (p->band.n && n_time > 2 * (int64_t)p->band.t_chunk)
+        return fail(EPIC_ERR_UNSUPPORTED,
+                    "graph capture of a banded accumulate longer than two scratch rounds (" +
+                        std::to_string(2 * p->band.t_chunk) + " samples) is not supported");
     EPIC_HIP(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
     epic_status st = EPIC_OK;
     if (p->precision == EPIC_F32 || p->band_only())
@@ -392,6 +476,8 @@ epic_status epic_graph_create(epic_plan p, epic_acc a, const uint8_t *d_volt, in
             st = fused_accumulate(p, a, d_volt, n_time, cs, &br, false);
         else if (p->precision == EPIC_FIXED16)
             st = fixed_accumulate(p, a, d_volt, n_time, cs);
+        else if (p->xform == EPIC_XFORM_DFT_SEPARABLE)
+            st = sep_accumulate(p, a, d_volt, n_time, cs);
         else
             st = gemm_accumulate(p, a, d_volt, n_time, cs);
     }
@@ -421,6 +507,7 @@ epic_status epic_graph_create(epic_plan p, epic_acc a, const uint8_t *d_volt, in
 
 epic_status epic_graph_launch(epic_graph g, void *hip_stream) {
     if (!g) return fail(EPIC_ERR_NULL, "graph is NULL");
+    if (epic_status st = count_guard(g->plan, g->acc->count, g->n_time)) return st;
     EPIC_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(hip_stream)));
     g->acc->count += g->n_time;
     return EPIC_OK;

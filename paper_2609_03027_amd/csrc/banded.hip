@@ -1351,9 +1351,12 @@ epic_status banded_acc_setup(epic_plan p, epic_acc acc) {
 // Rounds of t_chunk samples alternate between the two scratch halves: the
 // row pass of round k + 1 (queue 0) runs while the column pass of round k
 // (queue 1) reads the other half.  Events: 0 fork, 1 + b row pass into half b
-// done, 3 + b column pass out of half b done.  A stream under graph capture
-// gets both passes itself, in order (the captured form of the two-queue
-// hand-over is not used).
+// done, 3 + b column pass out of half b done, 5 the row queue's last pass
+// done.  banded_join makes the caller's stream wait on both queues' last
+// events: each queue that forked from the caller's stream is joined back
+// into it directly.  A stream under graph capture gets both passes itself,
+// in order, with no events (epic_graph_create refuses banded captures of
+// more than two rounds).
 epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                               hipStream_t s, bool dry, const FrameOut &fo) {
     const BandPlan &bp = p->band;
@@ -1397,12 +1400,11 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
     float *part = reinterpret_cast<float *>(acc->d_work.as<char>() + bp.scratch_bytes);
     float *a = acc->d_acc.as<float>();
     const BandChan *chans = bp.d_chans.as<BandChan>();
-    // Under graph capture both passes stay on the capturing stream, in order.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     EPIC_HIP(hipStreamIsCapturing(s, &cap));
     const bool split = cap == hipStreamCaptureStatusNone;
     acc->band_split = split;
-    hipStream_t q_rows = split ? acc->band_q[0] : s, q_cols = split ? acc->band_q[1] : s;
+    const hipStream_t q_rows = split ? acc->band_q[0] : s, q_cols = split ? acc->band_q[1] : s;
     hipEvent_t *ev = acc->band_ev;
     if (split) {
         EPIC_HIP(hipEventRecord(ev[0], s));
@@ -1410,8 +1412,9 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
         EPIC_HIP(hipStreamWaitEvent(q_cols, ev[0], 0));
     }
     const int64_t half = (int64_t)bp.elem_bytes * bp.scratch_t * bp.t_chunk;   // bytes
+    epic_status st = EPIC_OK;
     int k = 0;
-    for (int t0 = 0; t0 < n_time; t0 += round, ++k) {
+    for (int t0 = 0; t0 < n_time && !st; t0 += round, ++k) {
         const int nt = std::min(round, n_time - t0);
         FrameOut fr = fo;
         if (fo.len) fr.out = fo.out + (int64_t)(t0 / fo.len) * fo.stride;
@@ -1419,27 +1422,35 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
         float4 *scratch = reinterpret_cast<float4 *>(acc->d_work.as<char>() + b * half);
         const uint8_t *v = d_volt + (int64_t)t0 * p->vstride();
         if (split && k >= 2) EPIC_HIP(hipStreamWaitEvent(q_rows, ev[3 + b], 0));
-        for (int pass = 0; pass < 2; ++pass) {
+        for (int pass = 0; pass < 2 && !st; ++pass) {
             const hipStream_t qs = pass ? q_cols : q_rows;
             if (split && pass == 1) EPIC_HIP(hipStreamWaitEvent(q_cols, ev[1 + b], 0));
             for (const BandSize &bs : bp.sizes) {
-                epic_status st = EPIC_OK;
                 if (bs.R)
                     st = p->P == 2 ? launch_pw_any<2>(p, bs, pass, v, nt, scratch, part, a, fr, qs)
                                    : launch_pw_any<1>(p, bs, pass, v, nt, scratch, part, a, fr, qs);
                 else
                     st = launch_generic(p, bs, pass, chans, v, nt, scratch, a, qs);
-                if (st) return st;
+                if (st) break;
             }
+            // recorded also after a failed launch, so that banded_join still
+            // sees both queues end
             if (split) EPIC_HIP(hipEventRecord(ev[pass ? 3 + b : 1 + b], qs));
         }
+        acc->band_last = b;
     }
-    acc->band_last = (k - 1) & 1;
-    return EPIC_OK;
+    if (split) {
+        // a failed row pass leaves the column queue's last event of this call
+        // unrecorded: record it now so every queue has a join point
+        if (st) EPIC_HIP(hipEventRecord(ev[3 + acc->band_last], q_cols));
+        EPIC_HIP(hipEventRecord(ev[5], q_rows));
+    }
+    return st;
 }
 
 epic_status banded_join(epic_plan p, epic_acc acc, hipStream_t s) {
     if (p->band.n == 0 || !acc->band_split) return EPIC_OK;
+    EPIC_HIP(hipStreamWaitEvent(s, acc->band_ev[5], 0));
     EPIC_HIP(hipStreamWaitEvent(s, acc->band_ev[3 + acc->band_last], 0));
     return EPIC_OK;
 }

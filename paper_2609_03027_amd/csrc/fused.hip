@@ -20,6 +20,8 @@
 #include <numeric>
 #include <queue>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace epic {
@@ -1056,8 +1058,11 @@ epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vect
 }
 
 epic_status lds_ready(const void *kern, size_t lds) {
+    // first calls may come from several host threads at once
+    static std::mutex mu;
     static int lds_max = -1;
     static std::vector<const void *> done;
+    std::lock_guard<std::mutex> lock(mu);
     if (lds_max < 0) {
         int dev = 0, v = 0;
         EPIC_HIP(hipGetDevice(&dev));
@@ -1184,8 +1189,12 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
     int32_t *au = (in_kernel && acc && !frames) ? acc->d_autos.as<int32_t>() : nullptr;
     if (p->band.n) {
         // forks onto the accumulator's own queues; joined back into s below
+        // (and here when it fails, so no queue is left forked)
         epic_status st = banded_accumulate(p, acc, d_volt, n_time, s, dry, fo);
-        if (st) return st;
+        if (st) {
+            if (!dry) (void)banded_join(p, acc, s);
+            return st;
+        }
     }
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         const FusedGroup *g = p->groups[gi];

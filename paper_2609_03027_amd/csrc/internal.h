@@ -175,6 +175,22 @@ struct BandPlan {
     DevBuf d_mf;             // per-lane DFT-16 fragments and twiddles (64 entries)
 };
 
+// Separable DFT-GEMM (EPIC_XFORM_DFT_SEPARABLE): per channel the centred DFT
+// matrix restricted to the gridded region's columns, in the MFMA operand
+// layouts, and the channels' gather tables.
+struct SepPlan {
+    int Na = 0;              // gridded region side (<= 64)
+    int N = 0;               // grid side (64 or 128), the same for every channel
+    int lo = 0;              // first grid row / column of the gridded region
+    DevBuf fy;               // step-2 A operand (F rows x region columns), hi [+ lo]
+    DevBuf fx;               // step-1 B operand, hi [+ lo]
+    DevBuf items;            // per channel: gather item (FusedItem)
+    DevBuf entries;          // uint4 gather entries (cells of the Na x Na region)
+    int n_items = 0;
+    int t_slices = 1;        // time slices per channel (partial sums reduced after)
+    int64_t part_floats = 0; // floats in one slice's partial image set
+};
+
 // Low-bitwidth path (EPIC_FIXED16): one gather item per channel (64 x 64
 // grids), integer weights in the entries, the twiddle table and settings.
 struct FixedPlan {
@@ -240,7 +256,11 @@ struct epic_plan_s {
     std::vector<char> banded;     // channel c takes the banded two-pass path
     epic::BandPlan band;
     int64_t work_bytes = 0;       // per-accumulator working memory the path needs
-    int64_t vstride() const { return (int64_t)C * P * A * vb; }  // bytes per time sample
+    int xform = 0;                // epic_xform, resolved at build (never AUTO after it)
+    int64_t volt_stride = 0;      // bytes between time samples (0: packed)
+    // bytes between time samples of the voltage input
+    int64_t vstride() const { return volt_stride ? volt_stride : (int64_t)C * P * A * vb; }
+    epic::SepPlan sep;            // separable DFT-GEMM tables (EPIC_XFORM_DFT_SEPARABLE)
     // an FP16 plan whose channels all take the banded four-step transform
     bool band_only() const {
         if (precision != EPIC_F16_MFMA || banded.empty()) return false;
@@ -271,7 +291,7 @@ struct epic_acc_s {
     // banded path: row and column passes on their own queues, scratch halves
     // handed over by events (created with the accumulator when needed)
     hipStream_t band_q[2] = {nullptr, nullptr};
-    hipEvent_t band_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t band_ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int band_last = 0;     // scratch half of the last column pass launched
     bool band_split = false;  // the last banded call used the two queues
     ~epic_acc_s();
@@ -336,6 +356,12 @@ epic_status staged_accumulate(epic_plan p, epic_acc acc, const void *d_sky, int 
 epic_status gemm_build(epic_plan p, hipStream_t s);
 epic_status gemm_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                             hipStream_t s);
+
+// sep.hip
+epic_status sep_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
+                      hipStream_t s);
+epic_status sep_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                           hipStream_t s);
 
 // fixed.hip
 int fixed_kernel_shift(const std::vector<double> &w);

@@ -66,6 +66,37 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     int64_t io = 0, go = 0;
     p->max_n = 0;
     p->banded.assign(C, 0);
+    // Transform form: EPIC_XFORM_AUTO resolves per precision; FP16 plans take
+    // the four-step FFT when every grid side is 256.
+    {
+        const int pr = p->precision;
+        bool all256 = true, any256 = false;
+        for (int c = 0; c < C; ++c) {
+            all256 = all256 && p->grid_n[c] == 256;
+            any256 = any256 || p->grid_n[c] == 256;
+        }
+        int x = p->xform;
+        if (x == EPIC_XFORM_AUTO && pr == EPIC_F16_MFMA && any256 && !all256)
+            return fail(EPIC_ERR_UNSUPPORTED,
+                        "an FP16 plan takes one path for all channels: the four-step banded "
+                        "transform for 256 x 256 grids, the DFT-GEMM otherwise (or name the "
+                        "transform form)");
+        if (x == EPIC_XFORM_AUTO)
+            x = (pr == EPIC_F32 || pr == EPIC_FIXED16 || (pr == EPIC_F16_MFMA && all256))
+                    ? EPIC_XFORM_FFT
+                    : EPIC_XFORM_DFT_DIRECT;
+        const bool ok =
+            (x == EPIC_XFORM_FFT &&
+             (pr == EPIC_F32 || pr == EPIC_FIXED16 || (pr == EPIC_F16_MFMA && all256))) ||
+            (x == EPIC_XFORM_DFT_DIRECT && pr != EPIC_F32 && pr != EPIC_FIXED16) ||
+            (x == EPIC_XFORM_DFT_SEPARABLE && (pr == EPIC_F16_MFMA || pr == EPIC_BF16X2_MFMA));
+        if (!ok)
+            return fail(EPIC_ERR_UNSUPPORTED,
+                        "this precision has no such transform form (FFT: FP32, fixed point, "
+                        "FP16 on 256 x 256 grids; direct DFT-GEMM: FP16, FP8, BF16 hi+lo; "
+                        "separable DFT-GEMM: FP16, BF16 hi+lo)");
+        p->xform = x;
+    }
     for (int c = 0; c < C; ++c) {
         const int N = p->grid_n[c];
         const int want = p->sub_n.empty() ? 0 : p->sub_n[c];
@@ -77,7 +108,7 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
         // with Jones kernels, which only the fused and staged gathers take).
         // FP16 plans send 256 x 256 channels to the banded path's four-step
         // MFMA transform.
-        if (p->precision == EPIC_F16_MFMA && N == 256 && want <= 0) {
+        if (p->precision == EPIC_F16_MFMA && p->xform == EPIC_XFORM_FFT && want <= 0) {
             p->banded[c] = 1;
             M = 0;
         } else if (p->precision == EPIC_F32 && p->J == 1 &&
@@ -276,6 +307,9 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     } else if (p->precision == EPIC_FIXED16) {
         if ((st = fixed_build(p, j0, w, s))) return st;
         p->work_bytes = p->fixed.part_bytes;
+    } else if (p->xform == EPIC_XFORM_DFT_SEPARABLE) {
+        if ((st = sep_build(p, j0, w, s))) return st;
+        p->work_bytes = (int64_t)sizeof(float) * p->sep.t_slices * p->sep.part_floats;
     } else {
         if ((st = gemm_build(p, s))) return st;
         p->work_bytes = p->gemm.vbuf_bytes;
@@ -292,7 +326,8 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
                                p->band.d_entries.bytes + p->band.d_mf.bytes);
     for (epic::DevBuf *b : {&p->gemm.a_hi, &p->gemm.a_lo, &p->gemm.d_blk_off,
                             &p->gemm.d_scale, &p->gemm.d_inv_s2, &p->fixed.items,
-                            &p->fixed.entries, &p->fixed.tw})
+                            &p->fixed.entries, &p->fixed.tw, &p->sep.fy, &p->sep.fx,
+                            &p->sep.items, &p->sep.entries})
         p->bytes_plan += (int64_t)b->bytes;
     return EPIC_OK;
 }

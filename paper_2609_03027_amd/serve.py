@@ -15,7 +15,11 @@ device.  The kernels are deterministic (fixed reduction orders, no float
 atomics), so a stream's images do not depend on what else runs.
 
 Per block the server records arrival (the clock), submission and completion;
-latency = completion - arrival.  A block whose predecessor on the same
+latency = completion - arrival.  It also records host-side times, so that a
+late block can be attributed: when the scheduling pass that submitted it
+began and how long after the previous pass, and how long the host spent in
+the accumulate call and, for the block that closes an integration, in the
+read-out and copy calls.  A block whose predecessor on the same
 stream has not yet been submitted when the ring is full is dropped (counted,
 and excluded from the sample count); a block completing after
 ``deadline_s`` is counted late.
@@ -45,7 +49,8 @@ class StreamSpec:
     blocks_per_integration: int
     deadline_s: float = 1e-3
     ring: int = 8
-    bytes_needed: int = 0          # accumulator + ring (plan counted separately)
+    bytes_needed: int = 0          # accumulator + ring (plan counted separately);
+                                   # 0: asked of the executor (the plan's footprint)
     phase_s: float = 0.0           # arrival of block 0 after the stream's clock starts
 
 
@@ -57,6 +62,10 @@ class BlockRecord:
     submit: float = math.nan
     done: float = math.nan
     dropped: bool = False
+    pass_start: float = math.nan   # scheduling pass that handled the block
+    pass_gap: float = math.nan     # since the previous pass began
+    call_s: float = math.nan       # host time inside the accumulate call
+    readout_call_s: float = math.nan   # host time in read-out + copy calls after it
 
     @property
     def latency(self):
@@ -88,16 +97,25 @@ class Server:
         self.active = {}
         self.finished = {}
         self.refused = []
+        self.need = {}                # stream name -> bytes besides the plan
+        self.last_pass = math.nan
+        self.max_pass_s = 0.0         # longest scheduling pass (host)
+        self.max_gap_s = 0.0          # longest gap between pass starts
 
     # ------------------------------------------------------------ admission
+    def _need(self, spec):
+        if spec.name not in self.need:
+            self.need[spec.name] = spec.bytes_needed or self.ex.stream_bytes(spec)
+        return self.need[spec.name]
+
     def _cost(self, spec):
         pb = 0 if id(spec.plan) in self.plans_resident else self.ex.plan_bytes(spec.plan)
-        return pb + spec.bytes_needed
+        return pb + self._need(spec)
 
     def submit_stream(self, spec: StreamSpec):
         """Queue a stream for admission (FIFO).  Streams that could never fit
         the budget are refused outright."""
-        if self.ex.plan_bytes(spec.plan) + spec.bytes_needed > self.budget:
+        if self.ex.plan_bytes(spec.plan) + self._need(spec) > self.budget:
             self.refused.append(spec.name)
             return False
         self.pending.append(spec)
@@ -112,7 +130,7 @@ class Server:
                 return
             self.pending.popleft()
             self.used += cost
-            pr = self.plans_resident.setdefault(id(spec.plan), [cost - spec.bytes_needed, 0])
+            pr = self.plans_resident.setdefault(id(spec.plan), [cost - self._need(spec), 0])
             pr[1] += 1
             handle = self.ex.open(spec)
             # The stream's clock starts at the first scheduling pass that sees
@@ -124,7 +142,7 @@ class Server:
     def _close(self, st, now):
         spec = st.spec
         self.ex.close(st.handle)
-        self.used -= spec.bytes_needed
+        self.used -= self._need(spec)
         pr = self.plans_resident[id(spec.plan)]
         pr[1] -= 1
         if pr[1] == 0:
@@ -138,6 +156,10 @@ class Server:
     def step(self):
         """One scheduling pass: retire finished work, submit arrived blocks."""
         now = self.ex.now()
+        gap = now - self.last_pass
+        if gap > self.max_gap_s:
+            self.max_gap_s = gap
+        self.last_pass = now
         for name in list(self.active):
             st = self.active[name]
             spec = st.spec
@@ -152,26 +174,33 @@ class Server:
                 arr = st.t0 + spec.phase_s + st.next_block * spec.period_s
                 if arr > now:
                     break
-                rec = BlockRecord(spec.name, st.next_block, arr)
+                rec = BlockRecord(spec.name, st.next_block, arr, pass_start=now, pass_gap=gap)
                 st.records.append(rec)
                 st.next_block += 1
                 if len(st.inflight) >= spec.ring:
                     rec.dropped = True          # ring full: this block is lost
                 else:
                     rec.submit = now
+                    h0 = self.ex.now()
                     tok = self.ex.accumulate(st.handle, rec.index)
+                    rec.call_s = self.ex.now() - h0
                     st.inflight.append((rec, tok))
                     st.samples_in_integration += spec.block_samples
                 st.blocks_in_integration += 1
                 if st.blocks_in_integration == spec.blocks_per_integration:
+                    h0 = self.ex.now()
                     st.images.append((st.samples_in_integration,
                                       self.ex.readout(st.handle)))
+                    rec.readout_call_s = self.ex.now() - h0
                     st.blocks_in_integration = 0
                     st.samples_in_integration = 0
             if st.next_block >= spec.n_blocks and not st.inflight:
                 self._close(st, now)
         if self.pending:
             self._admit(now)
+        took = self.ex.now() - now
+        if took > self.max_pass_s:
+            self.max_pass_s = took
 
     def run(self, timeout_s=60.0, poll_s=5e-5):
         import gc
@@ -199,6 +228,18 @@ class Server:
                        max_ms=float(lat.max() * 1e3))
         return out
 
+    def host_stats(self, records):
+        """Where host time went: the longest scheduling pass and gap between
+        passes, and the longest accumulate and read-out calls."""
+        def mx(v):
+            v = [x for x in v if np.isfinite(x)]
+            return float(max(v) * 1e3) if v else None
+        return {"max_pass_ms": self.max_pass_s * 1e3,
+                "max_pass_gap_ms": (self.max_gap_s * 1e3 if np.isfinite(self.max_gap_s)
+                                    else None),
+                "max_accumulate_call_ms": mx([r.call_s for r in records]),
+                "max_readout_call_ms": mx([r.readout_call_s for r in records])}
+
 
 # ---------------------------------------------------------------- executors
 class FakeExecutor:
@@ -225,6 +266,9 @@ class FakeExecutor:
 
     def plan_bytes(self, plan):
         return self._plan_bytes
+
+    def stream_bytes(self, spec):
+        return 0
 
     def open(self, spec):
         self.opened.append(spec.name)
@@ -280,7 +324,13 @@ class DeviceExecutor:
         self.torch.cuda.synchronize()
 
     def plan_bytes(self, plan):
-        return int(plan.info["bytes_plan"])
+        return int(plan.footprint(1)["bytes_plan"])
+
+    def stream_bytes(self, spec):
+        """Accumulator (with its working memory) plus the ring's blocks, from
+        the plan's footprint query."""
+        fp = spec.plan.footprint(spec.block_samples)
+        return int(fp["bytes_per_acc"] + spec.ring * fp["bytes_per_block"])
 
     def open(self, spec):
         import paper_2609_03027_amd as E

@@ -32,3 +32,45 @@ def oracle_images(volt, pos, wl, chans, remove_autos=True, normalise=True, kerne
         out.append(O.readout(r["acc"], r["auto"] if remove_autos else None, r["count"],
                              normalise))
     return out
+
+
+U32 = 2.0 ** -24      # unit roundoff of FP32
+
+
+def fp32_guard(n, k, n_time):
+    """Regression guard for the FP32 paths' max error (relative to the co-pol
+    peak), well below the 1e-4 acceptance bound.
+
+    Per pixel, the gridded cell carries the rounding of up to K^2 products per
+    element, the transform about log2(N^2) roundings of a radix FFT, and
+    |E|^2 doubles the relative error of E; the FP32 time sum of n_time
+    non-negative terms adds at most (n_time - 1) roundings relative to the sum.
+    Hence (2 (log2 N^2 + K^2) + n_time) u with u = 2^-24.
+    """
+    import math
+    return (2.0 * (math.log2(float(n) * n) + k * k) + n_time) * U32
+
+
+def code_voltages(n_time, n_chan, n_pol, n_ant, bits):
+    """Voltages that take every input code: with 4-bit samples every byte
+    0x00..0xFF (so -8 in both nibbles) appears on each feed of each channel
+    once n_time * n_ant >= 256; with 8-bit samples every int8 value -128..127
+    appears in both parts, with (-128, -128) on both feeds (where idx % 256
+    is 0)."""
+    t = np.arange(n_time)[:, None, None]
+    c = np.arange(n_chan)[None, :, None]
+    a = np.arange(n_ant)[None, None, :]
+    idx = t * n_ant + a + 17 * c
+    if bits == 4:
+        out = np.empty((n_time, n_chan, n_pol, n_ant), dtype=np.uint8)
+        out[:, :, 0] = idx % 256
+        if n_pol == 2:
+            out[:, :, 1] = (7 * idx + 3) % 256
+        return out
+    out = np.empty((n_time, n_chan, n_pol, n_ant, 2), dtype=np.int8)
+    out[:, :, 0, :, 0] = (idx % 256 - 128).astype(np.int8)
+    out[:, :, 0, :, 1] = ((7 * idx) % 256 - 128).astype(np.int8)
+    if n_pol == 2:
+        out[:, :, 1, :, 0] = out[:, :, 0, :, 1]
+        out[:, :, 1, :, 1] = ((11 * idx) % 256 - 128).astype(np.int8)
+    return out

@@ -232,3 +232,43 @@ def test_fp16_plans_take_one_path_for_all_channels():
     assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 4
     assert b"one path" in lib.epic_last_error()
     assert not h.value
+
+
+@pytest.mark.parametrize("over,status,msg", [
+    ({"xform": 7}, 2, b"xform"),
+    ({"xform": 2}, 4, b"transform form"),                      # FP32 has no DFT-GEMM
+    ({"xform": 3, "precision": 2}, 4, b"transform form"),      # no separable FP8
+    ({"xform": 1, "precision": 1}, 4, b"transform form"),      # FP16 FFT needs 256 x 256
+    ({"xform": 1, "precision": 3}, 4, b"transform form"),
+    ({"volt_stride_t": 3}, 2, b"volt_stride_t"),               # below C P A = 4 bytes
+    ({"volt_stride_t": 5, "flags": 1}, 2, b"volt_stride_t"),   # 8-bit: below 8 bytes
+    ({"volt_stride_t": 9, "flags": 1}, 2, b"volt_stride_t"),   # 8-bit: odd stride
+])
+def test_transform_form_and_stride_are_checked_before_device_work(over, status, msg):
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    d, keep = _desc(**over)
+    h = C.c_void_p()
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == status
+    assert msg in lib.epic_last_error(), lib.epic_last_error()
+    assert not h.value
+
+
+def test_null_grid_n_refuses_an_array_too_large_for_any_side():
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    pos = np.array([[0.0, 0.0], [400.0, -400.0]])
+    d, keep = _desc(n_ant=2, ant_pos_m=pos.ctypes.data_as(C.POINTER(C.c_double)))
+    d.grid_n = None
+    h = C.c_void_p()
+    # 800 m across at 60 MHz is 320 cells: 2 (320 + 3) > 512
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 3
+    assert b"above 512" in lib.epic_last_error()
+
+
+def test_footprint_and_grid_sides_check_their_arguments():
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    v = C.c_int64()
+    assert lib.epic_plan_footprint(None, 1, C.byref(v), None, None) == 1
+    assert lib.epic_plan_grid_sides(None, None) == 1

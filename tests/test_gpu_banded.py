@@ -91,14 +91,17 @@ def test_banded_zero_padded_grid_matches_oracle():
 
 @pytest.mark.parametrize("n_time", [
     20,
+    300,
     pytest.param(600, marks=pytest.mark.skip(
-        reason="graph capture of three sample rounds crashed the host process inside "
-               "epic_graph_create when the passes ran on two queues; capture now keeps "
-               "both passes on the capturing stream, and this case stays off the GPU "
-               "until the crash is explained")),
+        reason="a three-round banded capture crashed the host inside epic_graph_create, "
+               "with both passes on the capturing stream and, after joining both queues "
+               "directly, on the two queues too; the cause is not known, so captures of "
+               "more than two rounds now fail with EPIC_ERR_UNSUPPORTED before capture "
+               "begins and this case stays off the GPU")),
 ])
 def test_banded_graph_replays_equal_eager_and_runs_are_deterministic(n_time):
-    # 600 samples: three rounds over the two scratch halves inside one graph
+    # 300 samples: two rounds over the two scratch halves inside one graph
+    # (under capture both passes run in order on the capturing stream)
     torch = _torch()
     import paper_2609_03027_amd as E
     wl = synth.workload("tiny2").with_time(n_time)
@@ -134,3 +137,17 @@ def test_banded_graph_replays_equal_eager_and_runs_are_deterministic(n_time):
     again.export(a2, None)
     torch.cuda.synchronize()
     assert torch.equal(a1, a2)
+
+
+def test_banded_capture_of_more_than_two_rounds_is_refused_before_capture():
+    torch = _torch()
+    import paper_2609_03027_amd as E
+    wl = synth.workload("tiny2").with_time(600)
+    pos = synth.antenna_layout(wl)
+    _say("case banded capture refusal: 600 samples (three rounds)")
+    plan = E.Plan.from_workload(wl, pos, sub_n=[BANDED])
+    acc = E.Accumulator(plan)
+    dv = torch.zeros((600, wl.n_pol * wl.n_ant), dtype=torch.uint8, device="cuda")
+    with pytest.raises(E.EpicError) as e:
+        E.Graph(plan, acc, dv)
+    assert e.value.status == 4 and "two scratch rounds" in str(e.value)

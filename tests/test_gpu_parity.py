@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 import synth
-from helpers import image_errors, oracle_images
+from helpers import fp32_guard, image_errors, oracle_images
 
 pytestmark = pytest.mark.gpu
 
@@ -84,6 +84,9 @@ def test_tiny_matches_oracle(name, fused):
     got = _run(wl, pos, volt, fused=fused)
     ref = oracle_images(volt, pos, wl, range(wl.n_chan))
     _check(got, ref, f"{name}/fused={fused}")
+    # regression guard near the FP32 rounding level, far below the 1e-4 bound
+    guard = fp32_guard(int(wl.grid_n[0]), wl.kernel_k, wl.n_time)
+    assert image_errors(got[0], ref[0])[0].max() <= guard, guard
     # raw sums (no removal, no normalisation) as well
     got = _run(wl, pos, volt, fused=fused, flags=0)
     ref = oracle_images(volt, pos, wl, range(wl.n_chan), remove_autos=False, normalise=False)
