@@ -308,6 +308,23 @@ epic_status epic_accumulate_frames(epic_plan plan, epic_acc acc, const uint8_t *
 epic_status epic_readout(epic_plan plan, epic_acc acc, float *d_img, uint32_t flags,
                          void *hip_stream);
 
+/* Read-out for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same read-out as epic_readout, from state the caller holds (for example an
+ * exported checkpoint), with no accumulator handle.  d_acc: float
+ * [image_floats] Eq. 2 sums; d_autos: int32 [autos_ints] self-term sums
+ * (read only with EPIC_REMOVE_AUTOS, may be NULL otherwise); count: samples
+ * in the sums (> 0 with EPIC_NORMALISE); d_img: float [image_floats] output;
+ * flags as epic_readout.  All device pointers are the caller's.
+ * The FP64 self-term table lives in a 1 MiB array inside the library, one per
+ * GPU, held until the process ends: plans needing more (C * (P == 2 ? 3 : 1) *
+ * (2K - 1)^2 * 16 bytes > 1 MiB, e.g. more than 873 dual-feed channels at
+ * K = 3) fail with EPIC_ERR_BUDGET.  Calls neither allocate nor free memory.
+ * Calls on one GPU share that array: calls that overlap on one GPU (different
+ * streams, different host threads) race and must be ordered by the caller. */
+epic_status epic_readout_noalloc(epic_plan plan, const float *d_acc, const int32_t *d_autos,
+                                 int64_t count, float *d_img, uint32_t flags, void *hip_stream);
+
 /* Batching (Sec. 3: many channels processed by parallel cores; Sec. 4: an
  * output frame accumulates several processed frames).  Captures one
  * epic_accumulate(plan, acc, d_volt, NULL, n_time) -- every channel and

@@ -8,5 +8,5 @@ from ._lib import (  # noqa: F401
     FIXED_DEFAULT, MAX_SAMPLES_4BIT, MAX_SAMPLES_8BIT, NORMALISE, XFORM_AUTO, XFORM_DFT_DIRECT,
     XFORM_DFT_SEPARABLE, XFORM_FFT,
     JONES, REMOVE_AUTOS, STOKES, SUB_BANDED, VOLT_8BIT, Accumulator, EpicError, Graph, Plan, accumulate,
-    accumulate_frames, grid, image, load, readout,
+    accumulate_frames, grid, image, load, readout, readout_noalloc,
 )

@@ -40,6 +40,7 @@ EXPORTS = [
     "epic_accumulate", "epic_readout", "epic_status_str", "epic_last_error",
     "epic_version", "epic_graph_create", "epic_graph_launch", "epic_graph_destroy",
     "epic_accumulate_frames", "epic_plan_footprint", "epic_plan_grid_sides",
+    "epic_readout_noalloc",
 ]
 
 
@@ -114,6 +115,7 @@ def load() -> C.CDLL:
         "epic_accumulate_frames": [vp, vp, vp, i32, i32, vp, vp],
         "epic_plan_footprint": [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
         "epic_plan_grid_sides": [vp, C.POINTER(i32)],
+        "epic_readout_noalloc": [vp, vp, vp, i64, vp, u32, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -349,3 +351,11 @@ def accumulate_frames(plan: Plan, acc: Accumulator, volt, frame_len: int, out, n
 
 def readout(plan: Plan, acc: Accumulator, out, flags=REMOVE_AUTOS | NORMALISE, stream=None):
     check(load().epic_readout(plan.handle, acc.handle, _ptr(out), int(flags), _stream(stream)))
+
+
+def readout_noalloc(plan: Plan, acc_sums, autos, count: int, out,
+                    flags=REMOVE_AUTOS | NORMALISE, stream=None):
+    """``epic_readout_noalloc``: read-out of caller-held state (sums, self-term
+    sums, count) into ``out`` with no device allocation in the library."""
+    check(load().epic_readout_noalloc(plan.handle, _ptr(acc_sums), _ptr(autos), int(count),
+                                      _ptr(out), int(flags), _stream(stream)))

@@ -531,4 +531,18 @@ epic_status epic_readout(epic_plan p, epic_acc a, float *d_img, uint32_t flags, 
     EPIC_GUARD_END
 }
 
+epic_status epic_readout_noalloc(epic_plan p, const float *d_acc, const int32_t *d_autos,
+                                 int64_t count, float *d_img, uint32_t flags, void *hip_stream) {
+    EPIC_GUARD_BEGIN
+    if (!p || !d_acc || !d_img) return fail(EPIC_ERR_NULL, "plan, acc and img are required");
+    if ((flags & EPIC_REMOVE_AUTOS) && !d_autos)
+        return fail(EPIC_ERR_NULL, "self-term removal needs the self-term sums");
+    if (flags & ~(EPIC_REMOVE_AUTOS | EPIC_NORMALISE | EPIC_STOKES))
+        return fail(EPIC_ERR_ARG, "unknown flags");
+    if (count < 0) return fail(EPIC_ERR_ARG, "count must be >= 0");
+    return readout_noalloc(p, d_acc, d_autos, count, d_img, flags,
+                           static_cast<hipStream_t>(hip_stream));
+    EPIC_GUARD_END
+}
+
 }  // extern "C"

@@ -373,6 +373,8 @@ epic_status fixed_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
 // readout.hip
 epic_status selfcorr_build(epic_plan p, hipStream_t s);
 epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hipStream_t s);
+epic_status readout_noalloc(epic_plan p, const float *d_acc, const int32_t *d_autos,
+                            int64_t count, float *d_img, uint32_t flags, hipStream_t s);
 
 // Decode one 4+4-bit sample (real in the high nibble).
 __device__ __forceinline__ int dec_re(uint32_t b) { return ((int32_t)(b << 24)) >> 28; }

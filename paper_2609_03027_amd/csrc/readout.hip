@@ -11,6 +11,8 @@
 // exactly.  H and the per-pixel sum are formed in FP64 from the exact int32
 // self-term sums.  With Jones kernels (four per element) the same expansion
 // holds per pair of kernels; see k_auto_h_jones.
+#include <mutex>
+
 #include "internal.h"
 
 namespace epic {
@@ -249,31 +251,32 @@ epic_status selfcorr_build(epic_plan p, hipStream_t s) {
     return EPIC_OK;
 }
 
-epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hipStream_t s) {
+// The read-out proper: sums `a`, self-term sums `autos` (read only when
+// removing), sample count, and `H` the [C][NH][D*D] FP64 table k_auto_h fills.
+static epic_status readout_core(epic_plan p, const float *a, const int32_t *autos, int64_t count,
+                                double2 *H, float *d_img, uint32_t flags, hipStream_t s) {
     const bool remove = (flags & EPIC_REMOVE_AUTOS) != 0;
     const bool norm = (flags & EPIC_NORMALISE) != 0;
     const int stokes = (flags & EPIC_STOKES) ? 1 : 0;
     if (stokes && p->P != 2) return fail(EPIC_ERR_ARG, "pseudo-Stokes needs two feeds");
-    if (norm && acc->count <= 0) return fail(EPIC_ERR_ARG, "normalise requested with no samples");
-    const float scale = norm ? (float)(1.0 / (double)acc->count) : 1.0f;
+    if (norm && count <= 0) return fail(EPIC_ERR_ARG, "normalise requested with no samples");
+    const float scale = norm ? (float)(1.0 / (double)count) : 1.0f;
     const int D = 2 * p->K - 1;
-    DevBuf &H = acc->d_h;
     if (remove) {
         dim3 g(D * D, p->C);
         if (p->J == 4)
-            hipLaunchKernelGGL(k_auto_h_jones, g, dim3(256), 0, s, p->d_w.as<double2>(),
-                               acc->d_autos.as<int32_t>(), p->A, p->K, H.as<double2>());
+            hipLaunchKernelGGL(k_auto_h_jones, g, dim3(256), 0, s, p->d_w.as<double2>(), autos,
+                               p->A, p->K, H);
         else if (p->P == 2)
-            hipLaunchKernelGGL(k_auto_h<2>, g, dim3(256), 0, s, p->d_selfcorr.as<double2>(),
-                               acc->d_autos.as<int32_t>(), p->A, p->K, H.as<double2>());
+            hipLaunchKernelGGL(k_auto_h<2>, g, dim3(256), 0, s, p->d_selfcorr.as<double2>(), autos,
+                               p->A, p->K, H);
         else
-            hipLaunchKernelGGL(k_auto_h<1>, g, dim3(256), 0, s, p->d_selfcorr.as<double2>(),
-                               acc->d_autos.as<int32_t>(), p->A, p->K, H.as<double2>());
+            hipLaunchKernelGGL(k_auto_h<1>, g, dim3(256), 0, s, p->d_selfcorr.as<double2>(), autos,
+                               p->A, p->K, H);
         EPIC_HIP(hipGetLastError());
     }
     dim3 g((p->max_n * p->max_n + 255) / 256, p->C);
-    const float *a = acc->d_acc.as<float>();
-    const double2 *h = H.as<double2>();
+    const double2 *h = H;
     const int4 *ch = p->d_chan.as<int4>();
     const int64_t *off = p->d_img_off.as<int64_t>();
     const int rm = remove ? 1 : 0;
@@ -291,6 +294,57 @@ epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hip
 #undef EPIC_READOUT
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
+}
+
+epic_status readout(epic_plan p, epic_acc acc, float *d_img, uint32_t flags, hipStream_t s) {
+    return readout_core(p, acc->d_acc.as<float>(), acc->d_autos.as<int32_t>(), acc->count,
+                        acc->d_h.as<double2>(), d_img, flags, s);
+}
+
+// Read-out without allocation: the self-term table H lives in this
+// file-scope device array (one copy per GPU, held until the process ends).
+// In host code `scratch` names a host-side stand-in, never the device copy;
+// the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocH = 65536;   // double2 entries: 1 MiB
+static __device__ __align__(256) double2 scratch[kNoAllocH];
+
+static std::mutex g_scratch_mu;
+static double2 *g_scratch_ptr[64] = {};
+
+static epic_status scratch_ptr(double2 **out) {
+    int dev = 0;
+    EPIC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(EPIC_ERR_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<double2 *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return EPIC_OK;
+}
+
+int64_t readout_noalloc_max_channels(epic_plan p) {
+    const int D = 2 * p->K - 1;
+    return (int64_t)(kNoAllocH / (size_t)((p->P == 2 ? 3 : 1) * D * D));
+}
+
+epic_status readout_noalloc(epic_plan p, const float *d_acc, const int32_t *d_autos,
+                            int64_t count, float *d_img, uint32_t flags, hipStream_t s) {
+    const int D = 2 * p->K - 1;
+    const size_t need = (size_t)p->C * (p->P == 2 ? 3 : 1) * D * D;
+    if (need > kNoAllocH)
+        return fail(EPIC_ERR_BUDGET, "read-out without allocation: the self-term table needs " +
+                                         std::to_string(need * sizeof(double2)) +
+                                         " bytes, above the library's 1 MiB scratch (at most " +
+                                         std::to_string(readout_noalloc_max_channels(p)) +
+                                         " channels for this plan)");
+    double2 *h = nullptr;
+    epic_status st = scratch_ptr(&h);
+    if (st) return st;
+    return readout_core(p, d_acc, d_autos, count, h, d_img, flags, s);
 }
 
 }  // namespace epic
