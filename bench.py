@@ -184,7 +184,7 @@ def cpu_baseline(wl, pos, target_s=12.0):
                     "sample": f"same slice, {dt_fft:.1f} s"}}
 
 
-def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8):
+def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8, warm_blocks=20):
     """Real-time streaming of LWA-like stations: blocks of ``tb`` samples
     (1 ms at 25 kHz channels) arrive every ``period_s`` per stream; each
     station has its own layout, plan, accumulator and device ring of blocks.
@@ -212,12 +212,14 @@ def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8):
                                 phase_s=i * period_s / n_streams))
     ex = DeviceExecutor(rings)
     free, _ = torch.cuda.mem_get_info()
-    # warm-up: an untimed run of every stream through the same server path,
-    # as long as the timed one (a first full-length run in a process showed
-    # stalls of about 10 ms at read-outs; a second one does not)
+    # warm-up: a short untimed run of every stream through the same server
+    # path (kernels loaded, queues and pinned buffers touched); the timed
+    # run's host-side record attributes any stall that remains
+    from dataclasses import replace as dc_replace
     warm = Server(ex, budget_bytes=int(0.8 * free))
     for s in specs:
-        warm.submit_stream(s)
+        warm.submit_stream(dc_replace(s, n_blocks=min(n_blocks, warm_blocks),
+                                      blocks_per_integration=min(n_blocks, warm_blocks)))
     warm.run(timeout_s=120.0)
     srv = Server(ex, budget_bytes=int(0.8 * free))
     t0 = time.perf_counter()
@@ -229,8 +231,14 @@ def streaming(E, torch, n_streams, n_blocks, tb=25, period_s=1e-3, ring=8):
     st = Server.stats(recs)
     lat = np.array([r.latency for r in recs if not r.dropped])
     st["late"] = int(np.sum(lat > period_s))
+    st.update(srv.host_stats(recs))
     slow = sorted((r for r in recs if not r.dropped), key=lambda r: -r.latency)[:5]
-    st["slowest"] = [(r.stream, r.index, round(r.latency * 1e3, 3)) for r in slow]
+    st["slowest"] = [{"stream": r.stream, "block": r.index,
+                      "latency_ms": round(r.latency * 1e3, 3),
+                      "queued_ms": round((r.submit - r.arrival) * 1e3, 3),
+                      "pass_gap_ms": round(r.pass_gap * 1e3, 3),
+                      "call_ms": round(r.call_s * 1e3, 3)} for r in slow]
+    st["warmup_blocks"] = min(n_blocks, warm_blocks)
     st["streams"] = n_streams
     st["block_samples"] = tb
     st["period_ms"] = period_s * 1e3
@@ -394,6 +402,7 @@ def batched(E, torch, reps=5):
                        "50-350 MHz, grid sides {32:2, 48:40, 64:40, 96:81, 128:81, 192:140}, "
                        "512 samples"}
     samples = wl.samples_per_block()
+    flops, _ = algorithmic_flops(wl)        # FFT-equivalent + products + gridding
     t0 = time.perf_counter()
     sub, report = autotune.tune(pos, wl.chan_freq_hz, wl.grid_n, wl.n_pol,
                                 aperture_n=wl.aperture_n, use_cache=False)
@@ -401,15 +410,23 @@ def batched(E, torch, reps=5):
     res["autotune_choice"] = {str(n): int(m) for n, m in
                               sorted(set(zip(wl.grid_n.tolist(), sub.tolist())))}
     res["autotune_ms"] = {str(k): v for k, v in report.items()}
-    for label, kw in (("default", {}), ("autotuned", {"sub_n": sub})):
+    res["autotune_launch"] = report.get("launch", {}).get("choice")
+    for label, kw in (("default", {}),
+                      ("autotuned", {"sub_n": sub, "batch_queue": autotune.use_queue(report)}),
+                      ("queue", {"batch_queue": True})):
         plan = E.Plan.from_workload(wl, pos, **kw)
         acc = E.Accumulator(plan)
         ms_eager = timed(lambda: E.accumulate(plan, acc, volt=volt))
         g = E.Graph(plan, acc, volt)
         ms_graph = timed(lambda: g.launch())
         g.close()
+        best = min(ms_eager, ms_graph)
         res[label] = {"eager_ms": ms_eager, "graph_ms": ms_graph,
-                      "value": samples / (min(ms_eager, ms_graph) / 1e3), "unit": "samples/s"}
+                      "value": samples / (best / 1e3), "unit": "samples/s",
+                      "roofline": {"bound": "alu", "achieved": flops / (best / 1e3) / 1e12,
+                                   "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": flops / (best / 1e3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                                   "flops_per_integration": flops}}
         log(f"ska {label}: eager {ms_eager:.2f} ms, graph {ms_graph:.2f} ms per integration")
         acc.close()
         plan.close()
@@ -956,7 +973,11 @@ def main():
         for name, prec, peak, xf in (("bf16x2", E.EPIC_BF16X2_MFMA, 2500.0, E.XFORM_DFT_DIRECT),
                                      ("fp16", E.EPIC_F16_MFMA, 2500.0, E.XFORM_DFT_DIRECT),
                                      ("fp8e4m3", E.EPIC_F8E4M3_MFMA, 5000.0,
-                                      E.XFORM_DFT_DIRECT)):
+                                      E.XFORM_DFT_DIRECT),
+                                     ("fp16_sep", E.EPIC_F16_MFMA, 2500.0,
+                                      E.XFORM_DFT_SEPARABLE),
+                                     ("bf16x2_sep", E.EPIC_BF16X2_MFMA, 2500.0,
+                                      E.XFORM_DFT_SEPARABLE)):
             t0 = time.perf_counter()
             vplan = E.Plan.from_workload(wl, pos, precision=prec, xform=xf)
             torch.cuda.synchronize()
@@ -974,21 +995,33 @@ def main():
             b.record(stream)
             torch.cuda.synchronize()
             ms = a.elapsed_time(b) / reps
-            # executed MFMA flops: 2 M K N per channel, M = 2 N^2 rows, K = 2 Ap
-            ap = 16 * max(1, 2 ** math.ceil(math.log2(max(1, wl.n_ant) / 16)))
-            cols = wl.n_time * wl.n_pol
-            mflops = sum(2.0 * (2 * int(n) ** 2) * (2 * ap) * cols for n in wl.grid_n)
-            if prec == E.EPIC_BF16X2_MFMA:
-                mflops *= 2
+            if xf == E.XFORM_DFT_SEPARABLE:
+                # executed MFMA flops per (t, c): step 1 2 (4 NA)(2 NA) N, step 2
+                # 2 (2 N)(2 NA)(2 N) (both feeds; NA the region side padded to
+                # 32 or 64); BF16 hi + lo takes three products per step
+                na = 32 if wl.aperture_n <= 32 else 64
+                mflops = sum(wl.n_time * (16.0 * na * na * int(n) + 16.0 * int(n) ** 2 * na)
+                             for n in wl.grid_n)
+                if prec == E.EPIC_BF16X2_MFMA:
+                    mflops *= 3
+            else:
+                # executed MFMA flops: 2 M K N per channel, M = 2 N^2 rows, K = 2 Ap
+                ap = 16 * max(1, 2 ** math.ceil(math.log2(max(1, wl.n_ant) / 16)))
+                cols = wl.n_time * wl.n_pol
+                mflops = sum(2.0 * (2 * int(n) ** 2) * (2 * ap) * cols for n in wl.grid_n)
+                if prec == E.EPIC_BF16X2_MFMA:
+                    mflops *= 2
             tf = mflops / (ms / 1e3) / 1e12
             out["variants"][name] = {
+                "xform": "dft_separable" if xf == E.XFORM_DFT_SEPARABLE else "dft_direct",
                 "value": samples / (ms / 1e3), "unit": "samples/s", "ms_per_step": ms,
                 "mfma_tflops": tf, "mfma_peak": peak, "mfma_frac": tf / peak,
                 "plan_s": tplan, "plan_bytes": vplan.info["bytes_plan"],
                 "max_err_bound": tol[name]["max"],
                 "speedup_vs_fp32": out["ms_per_step"] / ms}
             log(f"{name}: {ms:.2f} ms/step, {tf:.0f} TFLOP/s MFMA ({tf / peak:.1%}), plan {tplan:.1f} s")
-            err_gpu[f"{name}_dft_direct"] = (plan, img.clone())
+            err_gpu[name if xf == E.XFORM_DFT_SEPARABLE else f"{name}_dft_direct"] = (
+                plan, img.clone())
             del vacc, vplan
             torch.cuda.empty_cache()
         out["variants"]["fp32_fft_max_err_bound"] = tol["fp32"]["max"]

@@ -139,6 +139,17 @@ typedef enum {
                                   self terms removed at read-out are
                                   sum_a sum_pq S_a^{pq} B_a^{alpha p} conj(B_a^{beta q}). */
 
+#define EPIC_BATCH_QUEUE 4u    /* batching (Sec. 3: parallel cores over many channels): every
+                                  fused FP32 item of every channel and grid size runs in one
+                                  persistent launch -- workgroups take units from a device
+                                  work queue, largest transforms first (64 x 64 classes, then
+                                  bundles of four 32 x 32 or eight 16 x 16 classes of one
+                                  channel).  Classes are not paired and samples are not split
+                                  into time slices (each class owns its pixels, so results are
+                                  deterministic).  FP32, one kernel per element; not with
+                                  EPIC_JONES (EPIC_ERR_UNSUPPORTED).  Banded channels and
+                                  frame mode keep their own launches. */
+
 /* sub_n value that selects the banded two-pass path for a channel */
 #define EPIC_SUB_BANDED (-1)
 
@@ -171,7 +182,8 @@ typedef struct {
                                     indexed [alpha][p][dy][dx] (alpha = output polarisation,
                                     p = feed; 0 = x, 1 = y); copied */
     int32_t precision;           /* epic_precision */
-    uint32_t flags;              /* EPIC_PLAN_DEFAULT or an OR of EPIC_VOLT_8BIT, EPIC_JONES */
+    uint32_t flags;              /* EPIC_PLAN_DEFAULT or an OR of EPIC_VOLT_8BIT, EPIC_JONES,
+                                    EPIC_BATCH_QUEUE */
     const int32_t *sub_n;        /* optional host [C], FP32 only: side M of the
                                     sub-transforms the fused path splits channel c into
                                     (16, 32 or 64, dividing grid_n[c], at most 8 per

@@ -27,6 +27,7 @@ STOKES = 4             # read-out flag: I, Q, U, V planes instead of XX, YY, Re 
 SUB_BANDED = -1        # sub_n value: banded two-pass path for that channel
 VOLT_8BIT = 1          # plan flag: 8+8-bit voltages, int8 [t][c][p][a][2]
 JONES = 2              # plan flag: four kernels W^{alpha p} per element (two feeds)
+BATCH_QUEUE = 4        # plan flag: every fused item in one persistent work-queue launch
 
 STATUS = {0: "EPIC_OK", 1: "EPIC_ERR_NULL", 2: "EPIC_ERR_ARG", 3: "EPIC_ERR_GRID",
           4: "EPIC_ERR_UNSUPPORTED", 5: "EPIC_ERR_OOM", 6: "EPIC_ERR_DEVICE",
@@ -158,7 +159,7 @@ class Plan:
                  kernel_k=3, kernel_sigma=0.5, kernel_table=None, precision=EPIC_F32,
                  sub_n=None, volt_bits=4, jones=False, twiddle_bits=8,
                  stage_shifts=FIXED_DEFAULT, grid_shift=FIXED_DEFAULT, xform=XFORM_AUTO,
-                 volt_stride=0, stream=None):
+                 volt_stride=0, batch_queue=False, stream=None):
         """``grid_n`` None: the library picks each channel's side (see
         ``epic_plan_desc.grid_n``); ``volt_stride``: bytes between time
         samples of the voltage input (0 = packed)."""
@@ -190,7 +191,8 @@ class Plan:
         d.precision = int(precision)
         if volt_bits not in (4, 8):
             raise ValueError("volt_bits must be 4 or 8")
-        d.flags = (VOLT_8BIT if volt_bits == 8 else 0) | (JONES if jones else 0)
+        d.flags = ((VOLT_8BIT if volt_bits == 8 else 0) | (JONES if jones else 0) |
+                   (BATCH_QUEUE if batch_queue else 0))
         # EPIC_FIXED16 settings (ignored by the other precisions)
         d.fixed_twiddle_bits = int(twiddle_bits)
         d.fixed_stage_shifts = int(stage_shifts)

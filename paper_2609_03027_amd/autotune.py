@@ -11,8 +11,12 @@ launch, so a size whose own launch under-fills the device can still be best
 left as it is.  The tuner therefore times whole plans: starting from the
 default choice it tries, size by size (most work first), every admissible
 choice for that size with the others held, times a graph launch of all
-channels, and keeps a change only when it is faster by more than 2 %.
-Results are cached as JSON keyed by the batch shape (``EPIC_AUTOTUNE_CACHE``
+channels, and keeps a change only when it is faster by more than 2 %.  A
+second knob is the launch form: with the chosen tiles it times the plan as
+one launch per size group (classes paired where they can be, samples split
+into time slices where a group under-fills the device) and as one persistent
+work-queue launch over every item (``BATCH_QUEUE``), and keeps the faster
+(again only past 2 %).  Results are cached as JSON keyed by the batch shape (``EPIC_AUTOTUNE_CACHE``
 or ~/.cache/epic_mi355x/autotune.json).
 """
 from __future__ import annotations
@@ -58,9 +62,9 @@ def _key(grid_n, pos, freq, n_pol, kernel_k, cell_lambda, aperture_n):
             f"-sizes{sizes}")
 
 
-def _time_batch(pos, freq, grid_n, n_pol, sub, volt, reps, plan_kw):
+def _time_batch(pos, freq, grid_n, n_pol, sub, volt, reps, plan_kw, queue=False):
     import torch
-    plan = L.Plan(pos, freq, grid_n, n_pol, sub_n=sub, **plan_kw)
+    plan = L.Plan(pos, freq, grid_n, n_pol, sub_n=sub, batch_queue=queue, **plan_kw)
     acc = L.Accumulator(plan)
     g = L.Graph(plan, acc, volt)
     g.launch()
@@ -83,7 +87,9 @@ def tune(pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5, kernel_k
     the library default, 16/32/64 = fused tile side, SUB_BANDED = banded).
 
     Returns ``(sub_n, report)``; report maps each grid side to the measured
-    milliseconds of one graph launch over all channels per choice tried.
+    milliseconds of one graph launch over all channels per choice tried, and
+    ``report["launch"]`` holds the launch-form comparison, its ``"choice"``
+    being ``"queue"`` or ``"groups"`` (see ``use_queue``).
     """
     import torch
     freq_hz = np.asarray(freq_hz, dtype=np.float64)
@@ -97,10 +103,11 @@ def tune(pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5, kernel_k
         except (OSError, ValueError):
             cache = {}
     sizes = sorted(set(int(x) for x in grid_n))
-    if key in cache:
+    if key in cache and "launch" in cache[key]:
         best = {int(k): int(v) for k, v in cache[key]["best"].items()}
-        return (np.array([best[int(n)] for n in grid_n], dtype=np.int32),
-                {int(k): v for k, v in cache[key]["ms"].items()})
+        rep = {int(k): v for k, v in cache[key]["ms"].items()}
+        rep["launch"] = cache[key]["launch"]
+        return np.array([best[int(n)] for n in grid_n], dtype=np.int32), rep
     plan_kw = dict(aperture_n=aperture_n, cell_lambda=cell_lambda, kernel_k=kernel_k,
                    kernel_sigma=kernel_sigma)
     volt = torch.randint(0, 256, (n_time, len(grid_n), n_pol, len(pos)), dtype=torch.uint8,
@@ -124,9 +131,20 @@ def tune(pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5, kernel_k
             if ms < 0.98 * base:
                 base = ms
                 choice = trial
+    # launch form with the chosen tiles (the queue takes fused channels only)
+    launch = {"groups": base}
+    if n_pol in (1, 2):
+        q = _time_batch(pos, freq_hz, grid_n, n_pol, sub_of(choice), volt, reps, plan_kw,
+                        queue=True)
+        launch["queue"] = q
+        if verbose:
+            print(f"autotune launch form: groups {base:.3f} ms, queue {q:.3f} ms", flush=True)
+    launch["choice"] = "queue" if launch.get("queue", base) < 0.98 * base else "groups"
+    report["launch"] = launch
     if use_cache:
         cache[key] = {"best": {str(k): v for k, v in choice.items()},
-                      "ms": {str(k): v for k, v in report.items()}}
+                      "ms": {str(k): v for k, v in report.items() if k != "launch"},
+                      "launch": launch}
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             json.dump(cache, open(path, "w"), indent=1)
@@ -135,9 +153,15 @@ def tune(pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5, kernel_k
     return sub_of(choice), report
 
 
+def use_queue(report) -> bool:
+    """Whether the tuned launch form is the persistent work queue."""
+    return report.get("launch", {}).get("choice") == "queue"
+
+
 def tuned_plan(wl, pos, **kw):
-    """A plan for a synth workload with autotuned sub-transform sides."""
-    sub, _ = tune(pos, wl.chan_freq_hz, wl.grid_n, wl.n_pol, aperture_n=wl.aperture_n,
-                  cell_lambda=wl.cell_lambda, kernel_k=wl.kernel_k,
-                  kernel_sigma=wl.kernel_sigma_cells, **kw)
-    return L.Plan.from_workload(wl, pos, sub_n=sub)
+    """A plan for a synth workload with autotuned sub-transform sides and
+    launch form."""
+    sub, report = tune(pos, wl.chan_freq_hz, wl.grid_n, wl.n_pol, aperture_n=wl.aperture_n,
+                       cell_lambda=wl.cell_lambda, kernel_k=wl.kernel_k,
+                       kernel_sigma=wl.kernel_sigma_cells, **kw)
+    return L.Plan.from_workload(wl, pos, sub_n=sub, batch_queue=use_queue(report))

@@ -153,7 +153,11 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
         if ((size_t)d->n_ant * 8 + 64 * 65 * 8 > 160 * 1024)
             return fail(EPIC_ERR_UNSUPPORTED, "too many elements for the fixed-point kernel's LDS");
     }
-    if (d->flags & ~(EPIC_VOLT_8BIT | EPIC_JONES)) return fail(EPIC_ERR_ARG, "unknown plan flags");
+    if (d->flags & ~(EPIC_VOLT_8BIT | EPIC_JONES | EPIC_BATCH_QUEUE))
+        return fail(EPIC_ERR_ARG, "unknown plan flags");
+    if ((d->flags & EPIC_BATCH_QUEUE) && (d->precision != EPIC_F32 || (d->flags & EPIC_JONES)))
+        return fail(EPIC_ERR_UNSUPPORTED,
+                    "the batch queue runs FP32 plans with one kernel per element");
     if (d->flags & EPIC_JONES) {
         if (d->n_pol != 2) return fail(EPIC_ERR_ARG, "Jones kernels need two feeds");
         if (!d->kernel_table) return fail(EPIC_ERR_NULL, "Jones kernels need a kernel table");

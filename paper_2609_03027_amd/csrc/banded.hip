@@ -23,6 +23,7 @@
 // centred sum by (-1)^(kx+ky) times a unit constant, common to both feeds,
 // so every Eq. 2 product is unchanged and pixels keep their natural index.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 
 #include "internal.h"
@@ -777,10 +778,13 @@ template <int P, int VB>
 __global__ __launch_bounds__(128) void k_band_rows_mf(
     const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
     const BandItem *__restrict__ items, int n_items, int G, int nt, int64_t per_xcd,
-    const uint4 *__restrict__ entries, int A, uint2 *__restrict__ scratch, int64_t scratch_t,
-    float in_scale, const MfConst *__restrict__ mfc) {
+    const uint4 *__restrict__ entries, const int32_t *__restrict__ ants, int A,
+    uint2 *__restrict__ scratch, int64_t scratch_t, float in_scale,
+    const MfConst *__restrict__ mfc) {
     constexpr int N = 256, T = 128, UN = 16;
-    extern __shared__ uint2 band16[];   // BL * N FP16 cells + the spare slot
+    // BL * N FP16 cells + the spare slot, then the band's staged voltages
+    extern __shared__ uint2 band16[];
+    float4 *vst = reinterpret_cast<float4 *>(band16 + BL * N + 2);
     const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (w >= (int64_t)n_items * nt) return;
     const int64_t blk = w / ((int64_t)G * nt), rem = w % ((int64_t)G * nt);
@@ -791,8 +795,17 @@ __global__ __launch_bounds__(128) void k_band_rows_mf(
     const int tid = threadIdx.x;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int i = tid; i <= BL * N; i += T) band16[i] = make_uint2(0u, 0u);
-    __syncthreads();
+    // the voltages of the elements that meet this band, decoded once (the
+    // entries index this list), instead of two scattered loads per tap
     const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * VB;
+    const int32_t *al = ants + it.ant_off;
+    for (int i = tid; i < it.n_ants; i += T) {
+        const uint32_t a = (uint32_t)al[i];
+        const int2 x = volt_dec(vraw<VB>(vx, a), VB);
+        const int2 y = P == 2 ? volt_dec(vraw<VB>(vx, (uint32_t)A + a), VB) : make_int2(0, 0);
+        vst[i] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
+    }
+    __syncthreads();
     const uint4 *ent = entries + it.entry_off;
     float4 s = zero;
     for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
@@ -803,26 +816,16 @@ __global__ __launch_bounds__(128) void k_band_rows_mf(
 #pragma unroll
         for (int k = 0; k < UN; ++k)
             if (i0 + k >= it.n_iter) e[k] = make_uint4(0u, (uint32_t)(BL * N), 0u, 0u);
-        uint32_t bx[UN], by[UN];
-#pragma unroll
-        for (int k = 0; k < UN; ++k) {
-            const uint32_t a = e[k].x & 0x7fffffffu;
-            bx[k] = vraw<VB>(vx, a);
-            by[k] = P == 2 ? vraw<VB>(vx, (uint32_t)A + a) : 0u;
-        }
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
             const float wr = __builtin_bit_cast(float, e[k].z);
             const float wi = __builtin_bit_cast(float, e[k].w);
-            const int2 x = volt_dec(bx[k], VB);
-            const float xr = (float)x.x, xi = (float)x.y;
-            s.x += wr * xr - wi * xi;
-            s.y += wr * xi + wi * xr;
+            const float4 v = vst[e[k].x & 0x7fffffffu];
+            s.x += wr * v.x - wi * v.y;
+            s.y += wr * v.y + wi * v.x;
             if (P == 2) {
-                const int2 y = volt_dec(by[k], VB);
-                const float yr = (float)y.x, yi = (float)y.y;
-                s.z += wr * yr - wi * yi;
-                s.w += wr * yi + wi * yr;
+                s.z += wr * v.z - wi * v.w;
+                s.w += wr * v.w + wi * v.z;
             }
             band16[e[k].y] = make_uint2(h2bits(s.x * in_scale, s.y * in_scale),
                                      h2bits(s.z * in_scale, s.w * in_scale));
@@ -969,10 +972,13 @@ static int pw_radix(int N, int *np) {
 
 // Per-band lane lists of one channel: taps conj(W) (-1)^(jx+jy) of every
 // element footprint cell in the band, cell index (row - r0) N + col.
+// compact: gather entries index the band's own element list (appended to
+// ants), whose voltages the FP16 four-step row pass stages once per sample.
 static epic_status band_items(epic_plan p, const std::vector<int> &j0,
                               const std::vector<double> &w, const BandChan &b, int chan_index,
                               int T, int G, std::vector<BandItem> &items,
-                              std::vector<uint4> &all) {
+                              std::vector<uint4> &all, bool compact,
+                              std::vector<int32_t> &ants) {
     const int A = p->A, K = p->K, N = b.N, c = b.c;
     const int n_bands = (b.row_hi - b.row_lo + 1 + BL - 1) / BL;
     std::vector<std::vector<GatherTap>> per(n_bands);
@@ -996,6 +1002,20 @@ static epic_status band_items(epic_plan p, const std::vector<int> &j0,
         BandItem it{};
         it.chan = chan_index;
         it.band = band;
+        if (compact) {
+            // ascending element list of the band; taps refer to list slots
+            std::vector<int> slot(A, -1);
+            it.ant_off = (int64_t)ants.size();
+            for (const GatherTap &tp : per[band]) slot[tp.ant] = 0;
+            int n = 0;
+            for (int a = 0; a < A; ++a)
+                if (slot[a] == 0) {
+                    slot[a] = n++;
+                    ants.push_back(a);
+                }
+            for (GatherTap &tp : per[band]) tp.ant = slot[tp.ant];
+            it.n_ants = n;
+        }
         it.entry_off = (int64_t)all.size();
         it.n_iter = lpt_pack(per[band], T, all);
         // the row kernel stores at every entry: padding (all-zero) entries
@@ -1025,6 +1045,8 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
     if (sides.empty()) return EPIC_OK;
     std::vector<BandItem> items;
     std::vector<uint4> all;
+    std::vector<int32_t> ants;
+    const bool compact = p->precision == EPIC_F16_MFMA;
     int64_t off = 0;
     for (int N : sides) {
         BandSize bs;
@@ -1072,7 +1094,7 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
             // items index the channels of their own size group
             if (bs.R)
                 band_items(p, j0, w, b, (int)(bp.host.size() - bs.chan_off),
-                           BL * (bs.N / bs.R), bs.G, items, all);
+                           BL * (bs.N / bs.R), bs.G, items, all, compact, ants);
             bp.host.push_back(b);
             bs.max_bands = std::max(bs.max_bands, (hi - lo + 1 + BL - 1) / BL);
             ++bs.n;
@@ -1130,6 +1152,12 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
     bp.elem_bytes = p->precision == EPIC_F16_MFMA ? 8 : (int)sizeof(float4);
     const int64_t per_t = off * (int64_t)bp.elem_bytes;
     bp.t_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (8LL << 30) / per_t));
+    // EPIC_BAND_ROUND (samples, > 0) caps the round: shorter rounds keep a
+    // round's row transforms small enough for the memory-side cache
+    if (const char *env = std::getenv("EPIC_BAND_ROUND")) {
+        const int cap = std::atoi(env);
+        if (cap > 0) bp.t_chunk = std::min(bp.t_chunk, cap);
+    }
     bp.scratch_bytes = 2 * per_t * bp.t_chunk;
     // Column passes with fewer than 1024 workgroups split the samples of a
     // round into S slices, each summing into its own partial image set.
@@ -1149,6 +1177,14 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
     if ((st = bp.d_chans.alloc(sizeof(BandChan) * bp.host.size()))) return st;
     EPIC_HIP(hipMemcpyAsync(bp.d_chans.p, bp.host.data(), sizeof(BandChan) * bp.host.size(),
                             hipMemcpyHostToDevice, s));
+    if (compact) {
+        bp.mf_max_ants = 0;
+        for (const BandItem &it : items) bp.mf_max_ants = std::max(bp.mf_max_ants, it.n_ants);
+        if ((st = bp.d_ants.alloc(sizeof(int32_t) * std::max<size_t>(1, ants.size())))) return st;
+        if (!ants.empty())
+            EPIC_HIP(hipMemcpyAsync(bp.d_ants.p, ants.data(), sizeof(int32_t) * ants.size(),
+                                    hipMemcpyHostToDevice, s));
+    }
     if (!items.empty()) {
         if ((st = bp.d_items.alloc(sizeof(BandItem) * items.size()))) return st;
         if ((st = bp.d_entries.alloc(sizeof(uint4) * std::max<size_t>(1, all.size())))) return st;
@@ -1238,7 +1274,7 @@ static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const ui
     return EPIC_OK;
 }
 
-constexpr size_t kRowsMfLds = sizeof(uint2) * (BL * 256 + 1);
+constexpr size_t kRowsMfLds = sizeof(uint2) * (BL * 256 + 2);   // + the staged voltages
 constexpr size_t kColsMfLds = sizeof(uint2) * MF_BC * MF_LP;
 
 static epic_status ready_mf(int P) {
@@ -1248,7 +1284,7 @@ static epic_status ready_mf(int P) {
                                           : reinterpret_cast<const void *>(k_band_rows_mf<2, 1>))
                                : (vb == 2 ? reinterpret_cast<const void *>(k_band_rows_mf<1, 2>)
                                           : reinterpret_cast<const void *>(k_band_rows_mf<1, 1>));
-        st = lds_ready(k, kRowsMfLds);
+        st = lds_ready(k, kRowsMfLds + sizeof(float4) * 4096);
     }
     if (!st)
         st = lds_ready(P == 2 ? reinterpret_cast<const void *>(k_band_cols_mf<2>)
@@ -1271,15 +1307,19 @@ static epic_status launch_mf(epic_plan p, const BandSize &bs, int pass, const ui
         if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
         const BandItem *items = bp.d_items.as<BandItem>() + bs.item_off;
         const uint4 *ent = bp.d_entries.as<uint4>();
+        const int32_t *ants = bp.d_ants.as<int32_t>();
+        const size_t lds = kRowsMfLds + sizeof(float4) * (size_t)bp.mf_max_ants;
+        if (bp.mf_max_ants > 4096)
+            return fail(EPIC_ERR_UNSUPPORTED, "FP16 four-step: more than 4096 elements in a band");
         if (p->vb == 2)
             hipLaunchKernelGGL((k_band_rows_mf<P, 2>), dim3((unsigned)(8 * per_xcd)), dim3(128),
-                               kRowsMfLds, s, d_volt, p->vstride(), chans, items, (int)bs.n_items,
-                               bs.G, nt, per_xcd, ent, p->A, sc, bp.scratch_t, bp.mf_in,
+                               lds, s, d_volt, p->vstride(), chans, items, (int)bs.n_items,
+                               bs.G, nt, per_xcd, ent, ants, p->A, sc, bp.scratch_t, bp.mf_in,
                                bp.d_mf.as<MfConst>());
         else
             hipLaunchKernelGGL((k_band_rows_mf<P, 1>), dim3((unsigned)(8 * per_xcd)), dim3(128),
-                               kRowsMfLds, s, d_volt, p->vstride(), chans, items, (int)bs.n_items,
-                               bs.G, nt, per_xcd, ent, p->A, sc, bp.scratch_t, bp.mf_in,
+                               lds, s, d_volt, p->vstride(), chans, items, (int)bs.n_items,
+                               bs.G, nt, per_xcd, ent, ants, p->A, sc, bp.scratch_t, bp.mf_in,
                                bp.d_mf.as<MfConst>());
         EPIC_HIP(hipGetLastError());
         return EPIC_OK;

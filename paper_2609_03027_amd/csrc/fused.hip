@@ -278,31 +278,28 @@ __device__ __forceinline__ void gather_cells(Grid<P> grid, const uint4 *ent, int
 // [s tps, (s + 1) tps) of slice s = b / n_items; with `part` given it stores
 // its sums to part + s part_stride + it.part_off (k_fused_reduce adds the
 // slices), else it adds them to acc.
+// The work of one item for samples [t_begin, t_stop), run by the T threads
+// tid = 0 .. T - 1 of one workgroup (or of a wave-aligned part of a larger
+// one, which then holds every barrier with it): `gsm` is its grid in LDS,
+// `stage` the staged voltages of the item's channel (parts running items of
+// the same channel may share one stage: they write the same values).  With
+// store false the sums and self terms are computed but not written.
 template <int M, int P, int AR, bool FR, bool JN>
-__global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(const FusedItem *__restrict__ items,
-                                                      const uint4 *__restrict__ entries,
-                                                      const uint8_t *__restrict__ volt,
-                                                      int64_t volt_t_stride, int A, int n_time,
-                                                      float *__restrict__ acc,
-                                                      int32_t *__restrict__ autos,
-                                                      int frame_len, float *__restrict__ frames,
-                                                      int64_t fstride, int vb, int n_items,
-                                                      int tps, float *__restrict__ part,
-                                                      int64_t part_stride) {
-    constexpr int T = FCfg<M>::T, RA = FCfg<M>::RA, ROW = FCfg<M>::ROW;
+__device__ __forceinline__ void fused_item(const FusedItem &it,
+                                           const uint4 *__restrict__ entries,
+                                           const uint8_t *__restrict__ volt,
+                                           int64_t volt_t_stride, int A, int t_begin, int t_stop,
+                                           float *__restrict__ acc, int32_t *__restrict__ autos,
+                                           int frame_len, float *__restrict__ frames,
+                                           int64_t fstride, int vb, int slice,
+                                           float *__restrict__ part, int64_t part_stride, int tid,
+                                           float4 *gsm, float4 *stage, bool store) {
+    constexpr int T = FCfg<M>::T, RA = FCfg<M>::RA;
     constexpr int NPIX = M * M / T;
     constexpr int NPROD = P == 2 ? 4 : 1;
-    constexpr int GSZ = M * ROW;
-    extern __shared__ float4 smem[];
+    constexpr int GSZ = M * FCfg<M>::ROW;
     Grid<P> grid;
-    grid.g = reinterpret_cast<decltype(grid.g)>(smem);
-    float4 *stage = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) + P * GSZ);
-
-    const int slice = blockIdx.x / n_items;
-    const FusedItem it = items[blockIdx.x % n_items];
-    if (it.c < 0) return;
-    const int tid = threadIdx.x;
-    const int t_begin = slice * tps, t_stop = min(n_time, t_begin + tps);
+    grid.g = reinterpret_cast<decltype(grid.g)>(gsm);
 
     float2 tw[RA];
     {
@@ -332,7 +329,7 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
     const uint8_t *vbase = volt + (int64_t)it.c * P * A * vb;
     const uint4 *ent = entries + it.entry_off + tid;
     const int n_iter = it.n_iter;
-    const bool own_autos = autos != nullptr && it.ox == 0 && it.oy == 0;
+    const bool own_autos = store && autos != nullptr && it.ox == 0 && it.oy == 0;
     int sa[AR][NPROD];
 #pragma unroll
     for (int k = 0; k < AR; ++k)
@@ -426,7 +423,7 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
 
     const int N = it.N, R = it.R;
     const int64_t plane = (int64_t)N * N;
-    if (!FR) {
+    if (!FR && store) {
         float *base = part ? part + slice * part_stride + it.part_off : acc + it.img_off;
 #pragma unroll
         for (int k = 0; k < NPIX; ++k) {
@@ -456,6 +453,96 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
         }
     }
 }
+
+template <int M, int P, int AR, bool FR, bool JN>
+__global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(const FusedItem *__restrict__ items,
+                                                      const uint4 *__restrict__ entries,
+                                                      const uint8_t *__restrict__ volt,
+                                                      int64_t volt_t_stride, int A, int n_time,
+                                                      float *__restrict__ acc,
+                                                      int32_t *__restrict__ autos,
+                                                      int frame_len, float *__restrict__ frames,
+                                                      int64_t fstride, int vb, int n_items,
+                                                      int tps, float *__restrict__ part,
+                                                      int64_t part_stride) {
+    constexpr int GSZ = M * FCfg<M>::ROW;
+    extern __shared__ float4 smem[];
+    float4 *stage = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) + P * GSZ);
+    const int slice = blockIdx.x / n_items;
+    const FusedItem it = items[blockIdx.x % n_items];
+    if (it.c < 0) return;
+    const int t_begin = slice * tps, t_stop = min(n_time, t_begin + tps);
+    fused_item<M, P, AR, FR, JN>(it, entries, volt, volt_t_stride, A, t_begin, t_stop, acc, autos,
+                                 frame_len, frames, fstride, vb, slice, part, part_stride,
+                                 (int)threadIdx.x, smem, stage, true);
+}
+
+// ------------------------------------------------- persistent work queue
+// Every fused class item of a plan in one launch (EPIC_BATCH_QUEUE).  Each
+// 512-thread workgroup takes the next unit from a device counter until the
+// table is used up, so the exit condition is the same for every wave and no
+// workgroup waits for another.  A unit is one 64 x 64 item (all 512 threads),
+// or a bundle of four 32 x 32 (128 threads each) or eight 16 x 16 (64 each)
+// items of one channel: the parts run side by side, hold every barrier
+// together (their sample loops are the same length) and share one staging
+// of the channel's voltages (each part writes the same values to it).  Unused
+// slots of a bundle rerun its last item without storing.  Units are ordered
+// largest transform first.  Self terms come from the separate pass.
+constexpr int kQueueGrid = 4224;   // float2 per feed: max(64 x 65, 4 x 32 x 33, 8 x 16 x 17)
+
+template <int P>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_queue(
+    const QueueUnit *__restrict__ units, int n_units, unsigned int *__restrict__ head,
+    const FusedItem *__restrict__ it64, const uint4 *__restrict__ e64,
+    const FusedItem *__restrict__ it32, const uint4 *__restrict__ e32,
+    const FusedItem *__restrict__ it16, const uint4 *__restrict__ e16,
+    const uint8_t *__restrict__ volt, int64_t vstride, int A, int n_time, int vb,
+    float *__restrict__ acc) {
+    extern __shared__ float4 smem[];
+    float4 *stage = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) + P * kQueueGrid);
+    // the unit number, after the stage (dynamic LDS only: the whole allowance
+    // is given to the dynamic part)
+    int &cur = *reinterpret_cast<int *>(stage + A);
+    const int tid0 = threadIdx.x;
+    for (;;) {
+        if (tid0 == 0) cur = (int)atomicAdd(head, 1u);
+        __syncthreads();
+        const int u = cur;
+        __syncthreads();                  // every thread has read cur
+        if (u >= n_units) break;          // the same for the whole workgroup
+        const QueueUnit *q = units + u;
+        const int M = q->M, n = q->n;
+        // per unit, so the bodies' thread-dependent set-up (twiddles, LDS
+        // addresses) is not hoisted out of the unit loop and kept live across it
+        const int tid = tid0 + opaque_zero();
+        if (M == 64) {
+            const FusedItem it = it64[q->idx[0]];
+            fused_item<64, P, 1, false, false>(it, e64, volt, vstride, A, 0, n_time, acc, nullptr,
+                                               0, nullptr, 0, vb, 0, nullptr, 0, tid, smem, stage,
+                                               true);
+        } else if (M == 32) {
+            // part index and grid base are wave-uniform
+            const int part = __builtin_amdgcn_readfirstlane(tid >> 7);
+            const FusedItem it = it32[q->idx[min(part, n - 1)]];
+            float4 *g = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) +
+                                                   part * P * 32 * FCfg<32>::ROW);
+            fused_item<32, P, 1, false, false>(it, e32, volt, vstride, A, 0, n_time, acc, nullptr,
+                                               0, nullptr, 0, vb, 0, nullptr, 0, tid & 127, g,
+                                               stage, part < n);
+        } else {
+            const int part = __builtin_amdgcn_readfirstlane(tid >> 6);
+            const FusedItem it = it16[q->idx[min(part, n - 1)]];
+            float4 *g = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) +
+                                                   part * P * 16 * FCfg<16>::ROW);
+            fused_item<16, P, 1, false, false>(it, e16, volt, vstride, A, 0, n_time, acc, nullptr,
+                                               0, nullptr, 0, vb, 0, nullptr, 0, tid & 63, g,
+                                               stage, part < n);
+        }
+        __syncthreads();                  // the unit's last LDS reads before the next unit
+    }
+}
+
+__global__ void k_queue_reset(unsigned int *head) { *head = 0u; }
 
 // ------------------------------------------------- paired-class kernel
 // For N = 2 M grids (M = 64) whose element rows span fewer than M rows and two
@@ -983,6 +1070,12 @@ void fused_assign_work(epic_plan p) {
         g->work_off = (p->work_bytes + 255) / 256 * 256;
         p->work_bytes = g->work_off + (int64_t)sizeof(float) * g->slices * g->part_floats;
     }
+    if (p->flags & EPIC_BATCH_QUEUE) {
+        // the queue counter, one per accumulator (launches on different
+        // accumulators may run at once)
+        p->queue_off = (p->work_bytes + 255) / 256 * 256;
+        p->work_bytes = p->queue_off + 256;
+    }
 }
 
 static epic_status upload_group(epic_plan p, FusedGroup *g, std::vector<FusedItem> &items,
@@ -1002,12 +1095,47 @@ static epic_status upload_group(epic_plan p, FusedGroup *g, std::vector<FusedIte
     return EPIC_OK;
 }
 
+// The work queue of an EPIC_BATCH_QUEUE plan: every real item of the size
+// groups, 64 x 64 items first, then same-channel bundles of 32 x 32 and
+// 16 x 16 items (longest processing time first); no time slices.
+static epic_status queue_build(epic_plan p, hipStream_t s) {
+    std::vector<QueueUnit> units;
+    for (int M : {64, 32, 16}) {
+        const int B = M == 64 ? 1 : M == 32 ? 4 : 8;
+        for (FusedGroup *g : p->groups) {
+            if (g->M != M || g->kind != 0) continue;
+            g->slices = 1;
+            std::vector<std::vector<int>> per(p->C);
+            for (int i = 0; i < g->n_items; ++i)
+                if (g->host_items[i].c >= 0) per[g->host_items[i].c].push_back(i);
+            for (int c = 0; c < p->C; ++c)
+                for (size_t k = 0; k < per[c].size(); k += B) {
+                    QueueUnit u{};
+                    u.M = M;
+                    u.n = (int)std::min<size_t>(B, per[c].size() - k);
+                    for (int j = 0; j < 8; ++j) u.idx[j] = per[c][k + std::min(j, u.n - 1)];
+                    units.push_back(u);
+                }
+        }
+    }
+    p->n_units = (int)units.size();
+    epic_status st = p->d_units.alloc(sizeof(QueueUnit) * std::max<size_t>(1, units.size()));
+    if (st) return st;
+    if (!units.empty())
+        EPIC_HIP(hipMemcpyAsync(p->d_units.p, units.data(), sizeof(QueueUnit) * units.size(),
+                                hipMemcpyHostToDevice, s));
+    EPIC_HIP(hipStreamSynchronize(s));
+    return EPIC_OK;
+}
+
 epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vector<double> &w,
                         hipStream_t s) {
     const int A = p->A, K = p->K;
     // Paired items: two feeds, N = 2 * 64, every element row in a 64-row window.
     std::vector<int> pair_ylo(p->C, -1);
+    const bool queue = (p->flags & EPIC_BATCH_QUEUE) != 0;
     for (int c = 0; c < p->C; ++c) {
+        if (queue) break;                 // the queue takes single-class items only
         if (p->banded[c] || p->P != 2 || p->ch[c].M != 64 || p->ch[c].R != 2) continue;
         int lo = 1 << 30, hi = -1;
         for (int a = 0; a < A; ++a) {
@@ -1054,6 +1182,7 @@ epic_status fused_build(epic_plan p, const std::vector<int> &j0, const std::vect
         epic_status st = upload_group(p, g, items, all, p->C, s);
         if (st) return st;
     }
+    if (queue) return queue_build(p, s);
     return EPIC_OK;
 }
 
@@ -1169,6 +1298,46 @@ static epic_status launch_pair(const FusedGroup *g, const uint8_t *d_volt, int64
     return launch_pair_ar<4, JN>(g, d_volt, vstride, A, vb, n_time, acc, autos, fo, s, dry);
 }
 
+// One persistent launch over the plan's work queue (EPIC_BATCH_QUEUE).
+static epic_status queue_launch(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
+                                hipStream_t s, bool dry) {
+    const void *kern = p->P == 2 ? reinterpret_cast<const void *>(k_fused_queue<2>)
+                                 : reinterpret_cast<const void *>(k_fused_queue<1>);
+    const size_t lds = sizeof(float2) * p->P * kQueueGrid + sizeof(float4) * ((size_t)p->A + 1);
+    epic_status st = lds_ready(kern, lds);
+    if (st || dry || p->n_units == 0) return st;
+    const FusedItem *it[3] = {nullptr, nullptr, nullptr};
+    const uint4 *en[3] = {nullptr, nullptr, nullptr};
+    for (const FusedGroup *g : p->groups) {
+        if (g->kind != 0) continue;
+        const int k = g->M == 64 ? 0 : g->M == 32 ? 1 : 2;
+        it[k] = g->items.as<FusedItem>();
+        en[k] = g->entries.as<uint4>();
+    }
+    int dev = 0, n_cu = 0, per_cu = 0;
+    EPIC_HIP(hipGetDevice(&dev));
+    EPIC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    EPIC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 512, lds));
+    const int wgs = std::max(1, std::min(p->n_units, n_cu * std::max(1, per_cu)));
+    unsigned int *head = reinterpret_cast<unsigned int *>(acc->d_work.as<char>() + p->queue_off);
+    if (!acc->d_work.p || acc->d_work.bytes < (size_t)p->queue_off + 256)
+        return fail(EPIC_ERR_ARG, "accumulator has no work-queue counter");
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, head);
+    EPIC_HIP(hipGetLastError());
+    if (p->P == 2)
+        hipLaunchKernelGGL(k_fused_queue<2>, dim3(wgs), dim3(512), lds, s,
+                           p->d_units.as<QueueUnit>(), p->n_units, head, it[0], en[0], it[1],
+                           en[1], it[2], en[2], d_volt, p->vstride(), p->A, n_time, p->vb,
+                           acc->d_acc.as<float>());
+    else
+        hipLaunchKernelGGL(k_fused_queue<1>, dim3(wgs), dim3(512), lds, s,
+                           p->d_units.as<QueueUnit>(), p->n_units, head, it[0], en[0], it[1],
+                           en[1], it[2], en[2], d_volt, p->vstride(), p->A, n_time, p->vb,
+                           acc->d_acc.as<float>());
+    EPIC_HIP(hipGetLastError());
+    return EPIC_OK;
+}
+
 // Launches every size group; group i goes to branches[i] when given (graph
 // capture with parallel branches), else to s.  dry: only set up the kernels'
 // LDS allowance (done before a capture).  fo.len > 0: frame mode -- every
@@ -1195,6 +1364,14 @@ epic_status fused_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
             if (!dry) (void)banded_join(p, acc, s);
             return st;
         }
+    }
+    if ((p->flags & EPIC_BATCH_QUEUE) && !frames) {
+        epic_status st = queue_launch(p, acc, d_volt, n_time, s, dry);
+        if (st) return st;
+        if (dry) return EPIC_OK;
+        st = autos_accumulate(p, acc, d_volt, n_time, s);
+        if (st) return st;
+        return p->band.n ? banded_join(p, acc, s) : EPIC_OK;
     }
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         const FusedGroup *g = p->groups[gi];

@@ -82,6 +82,16 @@ struct GroupChan {
     int64_t img_off, part_off, n_floats;
 };
 
+// One unit of the persistent work queue (EPIC_BATCH_QUEUE): a 64 x 64 class
+// item, or a bundle of up to 4 (32 x 32) or 8 (16 x 16) class items of one
+// channel that a 512-thread workgroup runs side by side (indices into the
+// item table of the size's group; unused slots repeat the last item).
+struct QueueUnit {
+    int32_t M;
+    int32_t n;
+    int32_t idx[8];
+};
+
 // A group of fused items that share one sub-transform size M.
 struct FusedGroup {
     int M = 0;
@@ -136,8 +146,9 @@ struct BandItem {
     int32_t chan;            // channel within its size group's BandChan range
     int32_t band;
     int32_t n_iter;          // gather iterations per lane; -1: empty (block padding)
-    int32_t pad;
+    int32_t n_ants;          // FP16 four-step: elements touching the band (staged per sample)
     int64_t entry_off;       // first uint4 entry
+    int64_t ant_off;         // FP16 four-step: first of the band's element indices
 };
 
 // Banded channels of one grid side.
@@ -173,6 +184,10 @@ struct BandPlan {
     // scale of the gridded values into FP16, and of the products back
     float mf_in = 1.0f, mf_out = 1.0f;
     DevBuf d_mf;             // per-lane DFT-16 fragments and twiddles (64 entries)
+    // FP16 four-step row pass: per band the ascending list of elements whose
+    // footprint meets it; gather entries index this list, not the elements
+    DevBuf d_ants;           // int32 element indices
+    int mf_max_ants = 0;     // longest list (sizes the LDS staging)
 };
 
 // Separable DFT-GEMM (EPIC_XFORM_DFT_SEPARABLE): per channel the centred DFT
@@ -187,6 +202,7 @@ struct SepPlan {
     DevBuf items;            // per channel: gather item (FusedItem)
     DevBuf entries;          // uint4 gather entries (cells of the Na x Na region)
     int n_items = 0;
+    int sa = 0, sb = 0;      // power-of-two scales 2^-sa (grid) and 2^-sb (H) before rounding
     int t_slices = 1;        // time slices per channel (partial sums reduced after)
     int64_t part_floats = 0; // floats in one slice's partial image set
 };
@@ -251,6 +267,10 @@ struct epic_plan_s {
 
     // fused path (FP32) or direct DFT-GEMM (MFMA precisions)
     std::vector<epic::FusedGroup *> groups;
+    // EPIC_BATCH_QUEUE: every fused item in one persistent launch
+    epic::DevBuf d_units;         // QueueUnit[n_units], largest transforms first
+    int n_units = 0;
+    int64_t queue_off = 0;        // byte offset of the queue counter in the acc's work memory
     epic::GemmPlan gemm;
     epic::FixedPlan fixed;
     std::vector<char> banded;     // channel c takes the banded two-pass path

@@ -323,11 +323,12 @@ epic_status plan_build(epic_plan p, hipStream_t s) {
     for (auto *g : p->groups)
         p->bytes_plan += (int64_t)(g->items.bytes + g->entries.bytes + g->chans.bytes);
     p->bytes_plan += (int64_t)(p->band.d_chans.bytes + p->band.d_items.bytes +
-                               p->band.d_entries.bytes + p->band.d_mf.bytes);
+                               p->band.d_entries.bytes + p->band.d_mf.bytes +
+                               p->band.d_ants.bytes);
     for (epic::DevBuf *b : {&p->gemm.a_hi, &p->gemm.a_lo, &p->gemm.d_blk_off,
                             &p->gemm.d_scale, &p->gemm.d_inv_s2, &p->fixed.items,
                             &p->fixed.entries, &p->fixed.tw, &p->sep.fy, &p->sep.fx,
-                            &p->sep.items, &p->sep.entries})
+                            &p->sep.items, &p->sep.entries, &p->d_units})
         p->bytes_plan += (int64_t)b->bytes;
     return EPIC_OK;
 }

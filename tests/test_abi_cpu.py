@@ -272,3 +272,16 @@ def test_footprint_and_grid_sides_check_their_arguments():
     v = C.c_int64()
     assert lib.epic_plan_footprint(None, 1, C.byref(v), None, None) == 1
     assert lib.epic_plan_grid_sides(None, None) == 1
+
+
+def test_batch_queue_needs_fp32_single_kernels():
+    import paper_2609_03027_amd as E
+    lib = E.load()
+    h = C.c_void_p()
+    d, keep = _desc(flags=4, precision=1)
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 4
+    assert b"batch queue" in lib.epic_last_error()
+    tab = np.zeros((1, 4, 2, 2, 3, 3, 2), dtype=np.float32)
+    d, keep = _desc(flags=4 | 2, n_pol=2,
+                    kernel_table=tab.ctypes.data_as(C.POINTER(C.c_float)))
+    assert lib.epic_plan_create(C.byref(d), None, C.byref(h)) == 4
