@@ -490,14 +490,22 @@ __global__ __launch_bounds__(FCfg<M>::T) __attribute__((amdgpu_waves_per_eu(4)))
 // largest transform first.  Self terms come from the separate pass.
 constexpr int kQueueGrid = 4224;   // float2 per feed: max(64 x 65, 4 x 32 x 33, 8 x 16 x 17)
 
+// Per size (64, 32, 16): items, entries, samples per slice, slices in use
+// and the partial image sets when there is more than one.
+struct QueueSizes {
+    const FusedItem *it[3];
+    const uint4 *e[3];
+    float *part[3];
+    int64_t pstride[3];
+    int tps[3];
+    int used[3];
+};
+
 template <int P>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_queue(
     const QueueUnit *__restrict__ units, int n_units, unsigned int *__restrict__ head,
-    const FusedItem *__restrict__ it64, const uint4 *__restrict__ e64,
-    const FusedItem *__restrict__ it32, const uint4 *__restrict__ e32,
-    const FusedItem *__restrict__ it16, const uint4 *__restrict__ e16,
-    const uint8_t *__restrict__ volt, int64_t vstride, int A, int n_time, int vb,
-    float *__restrict__ acc) {
+    const QueueSizes qs, const uint8_t *__restrict__ volt, int64_t vstride, int A, int n_time,
+    int vb, float *__restrict__ acc) {
     extern __shared__ float4 smem[];
     float4 *stage = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) + P * kQueueGrid);
     // the unit number, after the stage (dynamic LDS only: the whole allowance
@@ -511,32 +519,38 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         __syncthreads();                  // every thread has read cur
         if (u >= n_units) break;          // the same for the whole workgroup
         const QueueUnit *q = units + u;
-        const int M = q->M, n = q->n;
+        const int M = q->M, n = q->n, sl = q->slice;
         // per unit, so the bodies' thread-dependent set-up (twiddles, LDS
         // addresses) is not hoisted out of the unit loop and kept live across it
         const int tid = tid0 + opaque_zero();
         if (M == 64) {
-            const FusedItem it = it64[q->idx[0]];
-            fused_item<64, P, 1, false, false>(it, e64, volt, vstride, A, 0, n_time, acc, nullptr,
-                                               0, nullptr, 0, vb, 0, nullptr, 0, tid, smem, stage,
-                                               true);
+            if (sl >= qs.used[0]) continue;   // a slice beyond this call's samples
+            const int t_begin = sl * qs.tps[0], t_stop = min(n_time, t_begin + qs.tps[0]);
+            const FusedItem it = qs.it[0][q->idx[0]];
+            fused_item<64, P, 1, false, false>(it, qs.e[0], volt, vstride, A, t_begin, t_stop,
+                                               acc, nullptr, 0, nullptr, 0, vb, sl, qs.part[0],
+                                               qs.pstride[0], tid, smem, stage, true);
         } else if (M == 32) {
-            // part index and grid base are wave-uniform
-            const int part = __builtin_amdgcn_readfirstlane(tid >> 7);
-            const FusedItem it = it32[q->idx[min(part, n - 1)]];
+            if (sl >= qs.used[1]) continue;
+            const int t_begin = sl * qs.tps[1], t_stop = min(n_time, t_begin + qs.tps[1]);
+            // sub-group index and grid base are wave-uniform
+            const int sub = __builtin_amdgcn_readfirstlane(tid >> 7);
+            const FusedItem it = qs.it[1][q->idx[min(sub, n - 1)]];
             float4 *g = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) +
-                                                   part * P * 32 * FCfg<32>::ROW);
-            fused_item<32, P, 1, false, false>(it, e32, volt, vstride, A, 0, n_time, acc, nullptr,
-                                               0, nullptr, 0, vb, 0, nullptr, 0, tid & 127, g,
-                                               stage, part < n);
+                                                   sub * P * 32 * FCfg<32>::ROW);
+            fused_item<32, P, 1, false, false>(it, qs.e[1], volt, vstride, A, t_begin, t_stop,
+                                               acc, nullptr, 0, nullptr, 0, vb, sl, qs.part[1],
+                                               qs.pstride[1], tid & 127, g, stage, sub < n);
         } else {
-            const int part = __builtin_amdgcn_readfirstlane(tid >> 6);
-            const FusedItem it = it16[q->idx[min(part, n - 1)]];
+            if (sl >= qs.used[2]) continue;
+            const int t_begin = sl * qs.tps[2], t_stop = min(n_time, t_begin + qs.tps[2]);
+            const int sub = __builtin_amdgcn_readfirstlane(tid >> 6);
+            const FusedItem it = qs.it[2][q->idx[min(sub, n - 1)]];
             float4 *g = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) +
-                                                   part * P * 16 * FCfg<16>::ROW);
-            fused_item<16, P, 1, false, false>(it, e16, volt, vstride, A, 0, n_time, acc, nullptr,
-                                               0, nullptr, 0, vb, 0, nullptr, 0, tid & 63, g,
-                                               stage, part < n);
+                                                   sub * P * 16 * FCfg<16>::ROW);
+            fused_item<16, P, 1, false, false>(it, qs.e[2], volt, vstride, A, t_begin, t_stop,
+                                               acc, nullptr, 0, nullptr, 0, vb, sl, qs.part[2],
+                                               qs.pstride[2], tid & 63, g, stage, sub < n);
         }
         __syncthreads();                  // the unit's last LDS reads before the next unit
     }
@@ -1099,25 +1113,37 @@ static epic_status upload_group(epic_plan p, FusedGroup *g, std::vector<FusedIte
 // groups, 64 x 64 items first, then same-channel bundles of 32 x 32 and
 // 16 x 16 items (longest processing time first); no time slices.
 static epic_status queue_build(epic_plan p, hipStream_t s) {
-    std::vector<QueueUnit> units;
+    // per size: units of one slice; a unit's cost ~ its transform's work x
+    // the samples of a slice, so sort by M^2 log M / slices, largest first
+    struct Keyed {
+        double cost;
+        QueueUnit u;
+    };
+    std::vector<Keyed> keyed;
     for (int M : {64, 32, 16}) {
         const int B = M == 64 ? 1 : M == 32 ? 4 : 8;
         for (FusedGroup *g : p->groups) {
             if (g->M != M || g->kind != 0) continue;
-            g->slices = 1;
             std::vector<std::vector<int>> per(p->C);
             for (int i = 0; i < g->n_items; ++i)
                 if (g->host_items[i].c >= 0) per[g->host_items[i].c].push_back(i);
-            for (int c = 0; c < p->C; ++c)
-                for (size_t k = 0; k < per[c].size(); k += B) {
-                    QueueUnit u{};
-                    u.M = M;
-                    u.n = (int)std::min<size_t>(B, per[c].size() - k);
-                    for (int j = 0; j < 8; ++j) u.idx[j] = per[c][k + std::min(j, u.n - 1)];
-                    units.push_back(u);
-                }
+            const double cost = (double)M * M * std::log2((double)M) / g->slices;
+            for (int sl = 0; sl < g->slices; ++sl)
+                for (int c = 0; c < p->C; ++c)
+                    for (size_t k = 0; k < per[c].size(); k += B) {
+                        QueueUnit u{};
+                        u.M = M;
+                        u.n = (int)std::min<size_t>(B, per[c].size() - k);
+                        u.slice = sl;
+                        for (int j = 0; j < 8; ++j) u.idx[j] = per[c][k + std::min(j, u.n - 1)];
+                        keyed.push_back({cost, u});
+                    }
         }
     }
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const Keyed &x, const Keyed &y) { return x.cost > y.cost; });
+    std::vector<QueueUnit> units;
+    for (const Keyed &k : keyed) units.push_back(k.u);
     p->n_units = (int)units.size();
     epic_status st = p->d_units.alloc(sizeof(QueueUnit) * std::max<size_t>(1, units.size()));
     if (st) return st;
@@ -1306,13 +1332,20 @@ static epic_status queue_launch(epic_plan p, epic_acc acc, const uint8_t *d_volt
     const size_t lds = sizeof(float2) * p->P * kQueueGrid + sizeof(float4) * ((size_t)p->A + 1);
     epic_status st = lds_ready(kern, lds);
     if (st || dry || p->n_units == 0) return st;
-    const FusedItem *it[3] = {nullptr, nullptr, nullptr};
-    const uint4 *en[3] = {nullptr, nullptr, nullptr};
+    QueueSizes qs{};
+    const FusedGroup *grp[3] = {nullptr, nullptr, nullptr};
     for (const FusedGroup *g : p->groups) {
         if (g->kind != 0) continue;
         const int k = g->M == 64 ? 0 : g->M == 32 ? 1 : 2;
-        it[k] = g->items.as<FusedItem>();
-        en[k] = g->entries.as<uint4>();
+        grp[k] = g;
+        qs.it[k] = g->items.as<FusedItem>();
+        qs.e[k] = g->entries.as<uint4>();
+        // slices in use for this call: at most one per sample
+        qs.tps[k] = (n_time + g->slices - 1) / g->slices;
+        qs.used[k] = (n_time + qs.tps[k] - 1) / qs.tps[k];
+        qs.part[k] = qs.used[k] > 1 ? reinterpret_cast<float *>(acc->d_work.as<char>() + g->work_off)
+                                    : nullptr;
+        qs.pstride[k] = g->part_floats;
     }
     int dev = 0, n_cu = 0, per_cu = 0;
     EPIC_HIP(hipGetDevice(&dev));
@@ -1326,15 +1359,21 @@ static epic_status queue_launch(epic_plan p, epic_acc acc, const uint8_t *d_volt
     EPIC_HIP(hipGetLastError());
     if (p->P == 2)
         hipLaunchKernelGGL(k_fused_queue<2>, dim3(wgs), dim3(512), lds, s,
-                           p->d_units.as<QueueUnit>(), p->n_units, head, it[0], en[0], it[1],
-                           en[1], it[2], en[2], d_volt, p->vstride(), p->A, n_time, p->vb,
-                           acc->d_acc.as<float>());
+                           p->d_units.as<QueueUnit>(), p->n_units, head, qs, d_volt,
+                           p->vstride(), p->A, n_time, p->vb, acc->d_acc.as<float>());
     else
         hipLaunchKernelGGL(k_fused_queue<1>, dim3(wgs), dim3(512), lds, s,
-                           p->d_units.as<QueueUnit>(), p->n_units, head, it[0], en[0], it[1],
-                           en[1], it[2], en[2], d_volt, p->vstride(), p->A, n_time, p->vb,
-                           acc->d_acc.as<float>());
+                           p->d_units.as<QueueUnit>(), p->n_units, head, qs, d_volt,
+                           p->vstride(), p->A, n_time, p->vb, acc->d_acc.as<float>());
     EPIC_HIP(hipGetLastError());
+    // sliced sizes: add the partial image sets in slice order
+    for (int k = 0; k < 3; ++k) {
+        if (!grp[k] || !qs.part[k]) continue;
+        hipLaunchKernelGGL(k_fused_reduce, dim3(64, grp[k]->n_chans), dim3(256), 0, s,
+                           grp[k]->chans.as<GroupChan>(), qs.used[k], qs.part[k],
+                           grp[k]->part_floats, acc->d_acc.as<float>());
+        EPIC_HIP(hipGetLastError());
+    }
     return EPIC_OK;
 }
 

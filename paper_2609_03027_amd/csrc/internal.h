@@ -85,10 +85,13 @@ struct GroupChan {
 // One unit of the persistent work queue (EPIC_BATCH_QUEUE): a 64 x 64 class
 // item, or a bundle of up to 4 (32 x 32) or 8 (16 x 16) class items of one
 // channel that a 512-thread workgroup runs side by side (indices into the
-// item table of the size's group; unused slots repeat the last item).
+// item table of the size's group; unused slots repeat the last item), over
+// one time slice of the samples (the group's slices, as in its own launch).
 struct QueueUnit {
     int32_t M;
     int32_t n;
+    int32_t slice;          // time slice of the group's samples this unit takes
+    int32_t pad;
     int32_t idx[8];
 };
 
