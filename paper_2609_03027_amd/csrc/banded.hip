@@ -774,6 +774,8 @@ __device__ __forceinline__ _Float16 h_hi(uint32_t v) {
 // doubles the workgroups a CU holds.  Wave w then transforms rows w, w + 2,
 // ... of the band and writes them to the scratch as FP16 cells (uint2 per
 // cell, cell index as in the FP32 scratch).
+constexpr int MF_TS = 4;   // samples per row-pass workgroup
+
 template <int P, int VB>
 __global__ __launch_bounds__(128) void k_band_rows_mf(
     const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
@@ -785,79 +787,85 @@ __global__ __launch_bounds__(128) void k_band_rows_mf(
     // BL * N FP16 cells + the spare slot, then the band's staged voltages
     extern __shared__ uint2 band16[];
     float4 *vst = reinterpret_cast<float4 *>(band16 + BL * N + 2);
+    // a workgroup takes MF_TS consecutive samples of its band: the band is
+    // zeroed once (every sample rewrites the same cells, those with taps)
+    const int64_t nts = (nt + MF_TS - 1) / MF_TS;
     const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (w >= (int64_t)n_items * nt) return;
-    const int64_t blk = w / ((int64_t)G * nt), rem = w % ((int64_t)G * nt);
-    const int t = (int)(rem / G);
+    if (w >= (int64_t)n_items * nts) return;
+    const int64_t blk = w / ((int64_t)G * nts), rem = w % ((int64_t)G * nts);
+    const int t0 = (int)(rem / G) * MF_TS, t1 = min(nt, t0 + MF_TS);
     const BandItem it = items[blk * G + rem % G];
     if (it.n_iter < 0) return;
     const BandChan ch = chans[it.chan];
     const int tid = threadIdx.x;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int i = tid; i <= BL * N; i += T) band16[i] = make_uint2(0u, 0u);
-    // the voltages of the elements that meet this band, decoded once (the
-    // entries index this list), instead of two scattered loads per tap
-    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * VB;
-    const int32_t *al = ants + it.ant_off;
-    for (int i = tid; i < it.n_ants; i += T) {
-        const uint32_t a = (uint32_t)al[i];
-        const int2 x = volt_dec(vraw<VB>(vx, a), VB);
-        const int2 y = P == 2 ? volt_dec(vraw<VB>(vx, (uint32_t)A + a), VB) : make_int2(0, 0);
-        vst[i] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
-    }
-    __syncthreads();
-    const uint4 *ent = entries + it.entry_off;
-    float4 s = zero;
-    for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
-        uint4 e[UN];
-#pragma unroll
-        for (int k = 0; k < UN; ++k)
-            e[k] = ent[(uint32_t)(min(i0 + k, it.n_iter - 1) * T + tid)];
-#pragma unroll
-        for (int k = 0; k < UN; ++k)
-            if (i0 + k >= it.n_iter) e[k] = make_uint4(0u, (uint32_t)(BL * N), 0u, 0u);
-#pragma unroll
-        for (int k = 0; k < UN; ++k) {
-            const float wr = __builtin_bit_cast(float, e[k].z);
-            const float wi = __builtin_bit_cast(float, e[k].w);
-            const float4 v = vst[e[k].x & 0x7fffffffu];
-            s.x += wr * v.x - wi * v.y;
-            s.y += wr * v.y + wi * v.x;
-            if (P == 2) {
-                s.z += wr * v.z - wi * v.w;
-                s.w += wr * v.w + wi * v.z;
-            }
-            band16[e[k].y] = make_uint2(h2bits(s.x * in_scale, s.y * in_scale),
-                                     h2bits(s.z * in_scale, s.w * in_scale));
-            if (e[k].x & 0x80000000u) s = zero;
-        }
-    }
-    __syncthreads();
     const int lane = tid & 63, wv = tid >> 6;
     const int a = lane & 15, g = lane >> 4;
     const MfConst k = mf_consts(mfc, lane);
-    for (int l = wv; l < BL; l += 2) {
-        const int row = ch.row_lo + it.band * BL + l;
-        if (row > ch.row_hi) break;
-        mf_h4 xr, xi, yr, yi;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint2 v = band16[l * N + 16 * (4 * g + j) + a];
-            xr[j] = h_lo(v.x);
-            xi[j] = h_hi(v.x);
-            yr[j] = h_lo(v.y);
-            yi[j] = h_hi(v.y);
+    const int32_t *al = ants + it.ant_off;
+    const uint4 *ent = entries + it.entry_off;
+    for (int t = t0; t < t1; ++t) {
+        if (t > t0) __syncthreads();   // the previous sample's rows have been read
+        // the voltages of the elements that meet this band, decoded once (the
+        // entries index this list), instead of two scattered loads per tap
+        const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * VB;
+        for (int i = tid; i < it.n_ants; i += T) {
+            const uint32_t ai = (uint32_t)al[i];
+            const int2 x = volt_dec(vraw<VB>(vx, ai), VB);
+            const int2 y = P == 2 ? volt_dec(vraw<VB>(vx, (uint32_t)A + ai), VB) : make_int2(0, 0);
+            vst[i] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
         }
-        mf_f4 er, ei, fr2, fi2;
-        mf_line(k, xr, xi, er, ei);
-        if (P == 2) mf_line(k, yr, yi, fr2, fi2);
-        uint2 *out = scratch + (int64_t)t * scratch_t + ch.scratch_off +
-                     (int64_t)(row - ch.row_lo) * N + a;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t hx = h2bits(er[i] * 0.0625f, ei[i] * 0.0625f);
-            const uint32_t hy = P == 2 ? h2bits(fr2[i] * 0.0625f, fi2[i] * 0.0625f) : 0u;
-            out[16 * (4 * g + i)] = make_uint2(hx, hy);
+        __syncthreads();
+        float4 s = zero;
+        for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
+            uint4 e[UN];
+    #pragma unroll
+            for (int k = 0; k < UN; ++k)
+                e[k] = ent[(uint32_t)(min(i0 + k, it.n_iter - 1) * T + tid)];
+    #pragma unroll
+            for (int k = 0; k < UN; ++k)
+                if (i0 + k >= it.n_iter) e[k] = make_uint4(0u, (uint32_t)(BL * N), 0u, 0u);
+    #pragma unroll
+            for (int k = 0; k < UN; ++k) {
+                const float wr = __builtin_bit_cast(float, e[k].z);
+                const float wi = __builtin_bit_cast(float, e[k].w);
+                const float4 v = vst[e[k].x & 0x7fffffffu];
+                s.x += wr * v.x - wi * v.y;
+                s.y += wr * v.y + wi * v.x;
+                if (P == 2) {
+                    s.z += wr * v.z - wi * v.w;
+                    s.w += wr * v.w + wi * v.z;
+                }
+                band16[e[k].y] = make_uint2(h2bits(s.x * in_scale, s.y * in_scale),
+                                         h2bits(s.z * in_scale, s.w * in_scale));
+                if (e[k].x & 0x80000000u) s = zero;
+            }
+        }
+        __syncthreads();
+        for (int l = wv; l < BL; l += 2) {
+            const int row = ch.row_lo + it.band * BL + l;
+            if (row > ch.row_hi) break;
+            mf_h4 xr, xi, yr, yi;
+    #pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint2 v = band16[l * N + 16 * (4 * g + j) + a];
+                xr[j] = h_lo(v.x);
+                xi[j] = h_hi(v.x);
+                yr[j] = h_lo(v.y);
+                yi[j] = h_hi(v.y);
+            }
+            mf_f4 er, ei, fr2, fi2;
+            mf_line(k, xr, xi, er, ei);
+            if (P == 2) mf_line(k, yr, yi, fr2, fi2);
+            uint2 *out = scratch + (int64_t)t * scratch_t + ch.scratch_off +
+                         (int64_t)(row - ch.row_lo) * N + a;
+    #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t hx = h2bits(er[i] * 0.0625f, ei[i] * 0.0625f);
+                const uint32_t hy = P == 2 ? h2bits(fr2[i] * 0.0625f, fi2[i] * 0.0625f) : 0u;
+                out[16 * (4 * g + i)] = make_uint2(hx, hy);
+            }
         }
     }
 }
@@ -1302,7 +1310,7 @@ static epic_status launch_mf(epic_plan p, const BandSize &bs, int pass, const ui
     const BandChan *chans = bp.d_chans.as<BandChan>() + bs.chan_off;
     uint2 *sc = reinterpret_cast<uint2 *>(scratch);
     if (pass == 0) {
-        const int64_t total = bs.n_items * nt;
+        const int64_t total = bs.n_items * ((nt + MF_TS - 1) / MF_TS);
         const int64_t per_xcd = (total + 7) / 8;
         if (8 * per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "banded path: grid too large");
         const BandItem *items = bp.d_items.as<BandItem>() + bs.item_off;

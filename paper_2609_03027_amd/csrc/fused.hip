@@ -548,9 +548,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             const FusedItem it = qs.it[2][q->idx[min(sub, n - 1)]];
             float4 *g = reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) +
                                                    sub * P * 16 * FCfg<16>::ROW);
+            // parts of different channels stage into their own slot after
+            // the eight 16 x 16 grids (inside the grid area the other sizes use)
+            float4 *st = q->own_stage ? reinterpret_cast<float4 *>(reinterpret_cast<float2 *>(smem) +
+                                                                   8 * P * 16 * FCfg<16>::ROW) +
+                                            sub * A
+                                      : stage;
             fused_item<16, P, 1, false, false>(it, qs.e[2], volt, vstride, A, t_begin, t_stop,
                                                acc, nullptr, 0, nullptr, 0, vb, sl, qs.part[2],
-                                               qs.pstride[2], tid & 63, g, stage, sub < n);
+                                               qs.pstride[2], tid & 63, g, st, sub < n);
         }
         __syncthreads();                  // the unit's last LDS reads before the next unit
     }
@@ -1128,14 +1134,28 @@ static epic_status queue_build(epic_plan p, hipStream_t s) {
             for (int i = 0; i < g->n_items; ++i)
                 if (g->host_items[i].c >= 0) per[g->host_items[i].c].push_back(i);
             const double cost = (double)M * M * std::log2((double)M) / g->slices;
-            for (int sl = 0; sl < g->slices; ++sl)
+            // 16 x 16 bundles of any channels when eight stagings fit beside
+            // the eight grids in the grid area: 8 A float4 <= P (kQueueGrid -
+            // 8 x 16 x 17) float2
+            const bool cross =
+                M == 16 && (int64_t)8 * p->A * 16 <= (int64_t)p->P * (kQueueGrid - 8 * 16 * 17) * 8;
+            std::vector<std::vector<int>> lists;
+            if (cross) {
+                lists.emplace_back();
                 for (int c = 0; c < p->C; ++c)
-                    for (size_t k = 0; k < per[c].size(); k += B) {
+                    lists.back().insert(lists.back().end(), per[c].begin(), per[c].end());
+            } else {
+                lists = per;
+            }
+            for (int sl = 0; sl < g->slices; ++sl)
+                for (const std::vector<int> &li : lists)
+                    for (size_t k = 0; k < li.size(); k += B) {
                         QueueUnit u{};
                         u.M = M;
-                        u.n = (int)std::min<size_t>(B, per[c].size() - k);
+                        u.n = (int)std::min<size_t>(B, li.size() - k);
                         u.slice = sl;
-                        for (int j = 0; j < 8; ++j) u.idx[j] = per[c][k + std::min(j, u.n - 1)];
+                        u.own_stage = cross ? 1 : 0;
+                        for (int j = 0; j < 8; ++j) u.idx[j] = li[k + std::min(j, u.n - 1)];
                         keyed.push_back({cost, u});
                     }
         }

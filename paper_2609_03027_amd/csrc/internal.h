@@ -87,11 +87,14 @@ struct GroupChan {
 // channel that a 512-thread workgroup runs side by side (indices into the
 // item table of the size's group; unused slots repeat the last item), over
 // one time slice of the samples (the group's slices, as in its own launch).
+// 16 x 16 bundles may take items of different channels when every part's
+// staged voltages fit beside the bundle's grids.
 struct QueueUnit {
     int32_t M;
     int32_t n;
     int32_t slice;          // time slice of the group's samples this unit takes
-    int32_t pad;
+    int32_t own_stage;      // 16 x 16 bundles: parts from different channels, each
+                            // staging its own voltages
     int32_t idx[8];
 };
 
