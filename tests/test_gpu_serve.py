@@ -77,3 +77,39 @@ def test_budget_admits_streams_in_turn_on_device():
     assert set(fin) == {"s0", "s1", "s2"}
     for n in fin:
         assert len(fin[n].images) == 1
+
+
+def test_fp16_fourstep_stream_alone_equals_in_mix():
+    """Streaming on the FP16 four-step banded path (256^2 grids): each stream's
+    accumulator forks its row and column passes onto its own two queues; a
+    stream's image is bit for bit the same alone and among three others."""
+    torch = _torch()
+    import dataclasses
+
+    import paper_2609_03027_amd as E
+    from paper_2609_03027_amd.serve import DeviceExecutor, Server, StreamSpec
+    _say("case serve: FP16 four-step 256^2 plans, alone vs mix of 4 streams")
+    tb, nb = 16, 4
+    streams = {}
+    for i in range(4):
+        base = synth.workload("tiny2")
+        wl = dataclasses.replace(base, grid_n=np.array([256]), seed=base.seed + 31 * i,
+                                 n_time=tb)
+        pos = synth.antenna_layout(wl)
+        blocks = np.stack([synth.voltages(wl, pos, block=b) for b in range(nb)])
+        plan = E.Plan.from_workload(wl, pos, precision=E.EPIC_F16_MFMA)
+        streams[f"f{i}"] = (plan, torch.from_numpy(blocks).cuda())
+
+    def serve(names):
+        ex = DeviceExecutor({n: streams[n][1] for n in names})
+        srv = Server(ex, budget_bytes=1 << 40)
+        for n in names:
+            srv.submit_stream(StreamSpec(n, streams[n][0], tb, 1e-3, nb, nb, ring=nb))
+        return srv.run(timeout_s=30.0)
+
+    alone = serve(["f0"])
+    mix = serve(["f0", "f1", "f2", "f3"])
+    a, m = alone["f0"].images, mix["f0"].images
+    assert len(a) == len(m) == 1 and a[0][0] == m[0][0] == nb * tb
+    assert torch.equal(a[0][1], m[0][1])
+    assert all(sum(r.dropped for r in mix[n].records) == 0 for n in mix)
