@@ -696,29 +696,34 @@ __global__ __launch_bounds__(256) void k_band_reduce(const BandChan *__restrict_
 // ------------------------------------------ FP16 four-step MFMA, N = 256
 // Precision EPIC_F16_MFMA on 256 x 256 banded channels: each 256-point line
 // transform is the four-step split 256 = 16 x 16 (x[16 n1 + n2] ->
-// X[k1 + 16 k2]) with both 16-point DFT steps on the matrix cores
-// (v_mfma_f32_16x16x16_f16, FP16 operands, FP32 accumulation), one wave per
-// line, and the row transforms stored to the scratch in FP16.  Written
-// transposed, the two steps chain in registers:
-//   step 1: D1 = X^T F     (A = X^T: lane holds x[16 (4g + j) + a],
-//                           B = F:   lane holds F[a][4g + j]),
-//           so lane (a, g) ends with Y[k1 = a][n2 = 4g + i], i = 0..3;
+// X[k1 + 16 k2]) with both 16-point DFT steps on the matrix cores, one wave
+// per line, and the row transforms stored to the scratch in FP16.  Each
+// complex 16-point step is two real v_mfma_f32_16x16x32_f16 (FP16
+// operands, FP32 accumulation) whose K = 32 runs over (re/im, n): an
+// operand lane l = a + 16 g holds k = 8 g + j, which is taken to mean the
+// real part (j < 4) or the imaginary part (j >= 4) of n = 4 g + (j & 3).
+// With that order the two steps chain in registers:
+//   step 1: D1 = X^T F  (A = X^T: lane holds x[16 (4g + j) + a], re then
+//                        im; B = [Fr; -Fi] for the real part, [Fi; Fr] for
+//                        the imaginary part), so lane (a, g) ends with
+//                        Y[k1 = a][n2 = 4g + i], i = 0..3;
 //   twiddle: Y'[k1][n2] = Y[k1][n2] exp(+2 pi i k1 n2 / 256)   (FP32);
-//   step 2: D2 = F Y'^T   (A = F, the same registers; B = Y'^T, which is
-//                           exactly the lane's step-1 result),
-//           so lane (a, g) ends with X[a + 16 (4g + i)],
+//   step 2: D2 = F Y'^T (A = the same two constant operands; B = Y'^T,
+//                        which is exactly the lane's step-1 result, re then
+//                        im), so lane (a, g) ends with X[a + 16 (4g + i)],
 // with a = lane % 16, g = lane / 16 and F[a][b] = exp(+2 pi i a b / 16)
-// (symmetric).  Complex products take four real MFMAs (Re = Ar Br - Ai Bi,
-// Im = Ar Bi + Ai Br).  Every FP16 rounding point is preceded by an exact
+// (symmetric).  Every FP16 rounding point is preceded by an exact
 // power-of-two scale: the gridded values by 2^-si (so their bound fits
 // FP16), each 16-point step's output by 1/16 (so no stage can grow past its
 // input bound); the column pass's products are multiplied back by
 // 2^(24 + 2 si).
 typedef _Float16 mf_h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 mf_h8 __attribute__((ext_vector_type(8)));
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 
 struct MfConst {
-    mf_h4 fr, fi, nfi;   // F[a][4g + j]: real, imaginary, minus imaginary
+    mf_h8 fre;           // (Fr, -Fi)[a][4g + j], j = 0..3
+    mf_h8 fim;           // (Fi, Fr)[a][4g + j]
     float2 tw[4];        // exp(+2 pi i a (4g + i) / 256) / 16
 };
 
@@ -727,8 +732,8 @@ __device__ __forceinline__ MfConst mf_consts(const MfConst *__restrict__ tab, in
     return tab[lane];
 }
 
-__device__ __forceinline__ mf_f4 mfma16(mf_h4 a, mf_h4 b, mf_f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+__device__ __forceinline__ mf_f4 mfma32(mf_h8 a, mf_h8 b, mf_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
 // One 256-point line transform of one feed: (xr, xi) = the lane's step-1 A
@@ -736,10 +741,9 @@ __device__ __forceinline__ mf_f4 mfma16(mf_h4 a, mf_h4 b, mf_f4 c) {
 __device__ __forceinline__ void mf_line(const MfConst &k, mf_h4 xr, mf_h4 xi, mf_f4 &er,
                                         mf_f4 &ei) {
     const mf_f4 z = {0.f, 0.f, 0.f, 0.f};
-    mf_f4 dr = mfma16(xr, k.fr, z);
-    dr = mfma16(xi, k.nfi, dr);
-    mf_f4 di = mfma16(xr, k.fi, z);
-    di = mfma16(xi, k.fr, di);
+    const mf_h8 x = __builtin_shufflevector(xr, xi, 0, 1, 2, 3, 4, 5, 6, 7);
+    const mf_f4 dr = mfma32(x, k.fre, z);
+    const mf_f4 di = mfma32(x, k.fim, z);
     mf_h4 br, bi;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -747,17 +751,18 @@ __device__ __forceinline__ void mf_line(const MfConst &k, mf_h4 xr, mf_h4 xi, mf
         br[i] = (_Float16)(dr[i] * w.x - di[i] * w.y);
         bi[i] = (_Float16)(dr[i] * w.y + di[i] * w.x);
     }
-    er = mfma16(k.fr, br, z);
-    er = mfma16(k.nfi, bi, er);
-    ei = mfma16(k.fr, bi, z);
-    ei = mfma16(k.fi, br, ei);
+    const mf_h8 y = __builtin_shufflevector(br, bi, 0, 1, 2, 3, 4, 5, 6, 7);
+    er = mfma32(k.fre, y, z);
+    ei = mfma32(k.fim, y, z);
 }
 
 // FP16 scratch cell: both feeds, (x re, x im), (y re, y im) as half pairs.
+typedef _Float16 mf_h2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t h2bits(float a, float b) {
-    const _Float16 ha = (_Float16)a, hb = (_Float16)b;
-    return (uint32_t)__builtin_bit_cast(uint16_t, ha) |
-           ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+    mf_h2 h;
+    h.x = (_Float16)a;
+    h.y = (_Float16)b;
+    return __builtin_bit_cast(uint32_t, h);
 }
 __device__ __forceinline__ _Float16 h_lo(uint32_t v) {
     return __builtin_bit_cast(_Float16, (uint16_t)(v & 0xffffu));
@@ -768,22 +773,45 @@ __device__ __forceinline__ _Float16 h_hi(uint32_t v) {
 
 // Pass 1, FP16 four-step.  Same items, gather and launch shape as
 // k_band_rows_pw<16, 2, P> (128 threads, 8-row bands), but the band is kept
-// in LDS as FP16 cells: each running FP32 cell sum is scaled and rounded at
-// its store (the last store of a cell leaves fl16(2^-si x the full sum),
-// exactly the step-1 operand), which halves the LDS per workgroup and
-// doubles the workgroups a CU holds.  Wave w then transforms rows w, w + 2,
-// ... of the band and writes them to the scratch as FP16 cells (uint2 per
-// cell, cell index as in the FP32 scratch).
-constexpr int MF_TS = 4;   // samples per row-pass workgroup
+// in LDS as FP16 cells: each running FP32 cell sum (of weights that carry
+// 2^-si) is rounded at its store (the last store of a cell leaves
+// fl16(2^-si x the full sum), exactly the step-1 operand), which halves the
+// LDS per workgroup and doubles the workgroups a CU holds.  Wave w then
+// transforms rows w, w + 2, ... of the band and writes them to the scratch
+// as FP16 cells (uint2 per cell, cell index as in the FP32 scratch).  A
+// workgroup runs MF_TS consecutive samples of its band; a lane list of at
+// most MF_UN entries is loaded once for all of them, and the next sample's
+// voltage codes are loaded while the current sample is gathered.
+constexpr int MF_TS = 8;   // samples per row-pass workgroup
+constexpr int MF_UN = 16;  // gather entries a lane holds in registers
+
+// One gather tap: s += 2^-si conj(W) (-1)^(jx+jy) E for both feeds (FMA
+// chains; the plan folds the exact power of two 2^-si into the weights),
+// then the cell's running sum is stored rounded to FP16; a cell's last tap
+// starts the next cell's sum at zero.
+template <int P>
+__device__ __forceinline__ void mf_tap(const uint4 e, const float4 *vst, uint2 *band16,
+                                       float4 &s) {
+    const float wr = __builtin_bit_cast(float, e.z);
+    const float wi = __builtin_bit_cast(float, e.w);
+    const float4 v = vst[e.x & 0x7fffffffu];
+    s.x = fmaf(-wi, v.y, fmaf(wr, v.x, s.x));
+    s.y = fmaf(wi, v.x, fmaf(wr, v.y, s.y));
+    if (P == 2) {
+        s.z = fmaf(-wi, v.w, fmaf(wr, v.z, s.z));
+        s.w = fmaf(wi, v.z, fmaf(wr, v.w, s.w));
+    }
+    band16[e.y] = make_uint2(h2bits(s.x, s.y), h2bits(s.z, s.w));
+    if (e.x & 0x80000000u) s = make_float4(0.f, 0.f, 0.f, 0.f);
+}
 
 template <int P, int VB>
-__global__ __launch_bounds__(128) void k_band_rows_mf(
+__global__ __launch_bounds__(128, 3) void k_band_rows_mf(
     const uint8_t *__restrict__ volt, int64_t vstride, const BandChan *__restrict__ chans,
     const BandItem *__restrict__ items, int n_items, int G, int nt, int64_t per_xcd,
     const uint4 *__restrict__ entries, const int32_t *__restrict__ ants, int A,
-    uint2 *__restrict__ scratch, int64_t scratch_t, float in_scale,
-    const MfConst *__restrict__ mfc) {
-    constexpr int N = 256, T = 128, UN = 16;
+    uint2 *__restrict__ scratch, int64_t scratch_t, const MfConst *__restrict__ mfc) {
+    constexpr int N = 256, T = 128;
     // BL * N FP16 cells + the spare slot, then the band's staged voltages
     extern __shared__ uint2 band16[];
     float4 *vst = reinterpret_cast<float4 *>(band16 + BL * N + 2);
@@ -798,51 +826,73 @@ __global__ __launch_bounds__(128) void k_band_rows_mf(
     if (it.n_iter < 0) return;
     const BandChan ch = chans[it.chan];
     const int tid = threadIdx.x;
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int i = tid; i <= BL * N; i += T) band16[i] = make_uint2(0u, 0u);
     const int lane = tid & 63, wv = tid >> 6;
     const int a = lane & 15, g = lane >> 4;
     const MfConst k = mf_consts(mfc, lane);
     const int32_t *al = ants + it.ant_off;
     const uint4 *ent = entries + it.entry_off;
+    const uint8_t *vc = volt + (int64_t)ch.c * P * A * VB;
+    // the voltages of the elements that meet this band are decoded once per
+    // sample into LDS (the entries index this list); a lane's first two
+    // elements are read one sample ahead, the rest when staged
+    uint32_t ai[2] = {0u, 0u}, rx[2] = {0u, 0u}, ry[2] = {0u, 0u};
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        if (tid + j * T < it.n_ants) ai[j] = (uint32_t)al[tid + j * T];
+    auto fetch = [&](int t) {
+        const uint8_t *vx = vc + (int64_t)t * vstride;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            if (tid + j * T < it.n_ants) {
+                rx[j] = vraw<VB>(vx, ai[j]);
+                if (P == 2) ry[j] = vraw<VB>(vx, (uint32_t)A + ai[j]);
+            }
+    };
+    if (t0 < t1) fetch(t0);
+    // a lane list of at most MF_UN entries is read once for all the samples
+    const bool held = it.n_iter <= MF_UN;
+    uint4 eh[MF_UN];
+#pragma unroll
+    for (int j = 0; j < MF_UN; ++j) {
+        eh[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (held && j < it.n_iter) eh[j] = ent[(uint32_t)(j * T + tid)];
+    }
     for (int t = t0; t < t1; ++t) {
         if (t > t0) __syncthreads();   // the previous sample's rows have been read
-        // the voltages of the elements that meet this band, decoded once (the
-        // entries index this list), instead of two scattered loads per tap
-        const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * VB;
-        for (int i = tid; i < it.n_ants; i += T) {
-            const uint32_t ai = (uint32_t)al[i];
-            const int2 x = volt_dec(vraw<VB>(vx, ai), VB);
-            const int2 y = P == 2 ? volt_dec(vraw<VB>(vx, (uint32_t)A + ai), VB) : make_int2(0, 0);
-            vst[i] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
-        }
-        __syncthreads();
-        float4 s = zero;
-        for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
-            uint4 e[UN];
-    #pragma unroll
-            for (int k = 0; k < UN; ++k)
-                e[k] = ent[(uint32_t)(min(i0 + k, it.n_iter - 1) * T + tid)];
-    #pragma unroll
-            for (int k = 0; k < UN; ++k)
-                if (i0 + k >= it.n_iter) e[k] = make_uint4(0u, (uint32_t)(BL * N), 0u, 0u);
-    #pragma unroll
-            for (int k = 0; k < UN; ++k) {
-                const float wr = __builtin_bit_cast(float, e[k].z);
-                const float wi = __builtin_bit_cast(float, e[k].w);
-                const float4 v = vst[e[k].x & 0x7fffffffu];
-                s.x += wr * v.x - wi * v.y;
-                s.y += wr * v.y + wi * v.x;
-                if (P == 2) {
-                    s.z += wr * v.z - wi * v.w;
-                    s.w += wr * v.w + wi * v.z;
-                }
-                band16[e[k].y] = make_uint2(h2bits(s.x * in_scale, s.y * in_scale),
-                                         h2bits(s.z * in_scale, s.w * in_scale));
-                if (e[k].x & 0x80000000u) s = zero;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            if (tid + j * T < it.n_ants) {
+                const int2 x = volt_dec(rx[j], VB);
+                const int2 y = P == 2 ? volt_dec(ry[j], VB) : make_int2(0, 0);
+                vst[tid + j * T] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
+            }
+        if (it.n_ants > 2 * T) {
+            const uint8_t *vx = vc + (int64_t)t * vstride;
+            for (int i = tid + 2 * T; i < it.n_ants; i += T) {
+                const uint32_t an = (uint32_t)al[i];
+                const int2 x = volt_dec(vraw<VB>(vx, an), VB);
+                const int2 y = P == 2 ? volt_dec(vraw<VB>(vx, (uint32_t)A + an), VB)
+                                      : make_int2(0, 0);
+                vst[i] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
             }
         }
         __syncthreads();
+        if (t + 1 < t1) fetch(t + 1);
+        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+        // (a longer list is streamed through the same registers)
+        for (int i0 = 0; i0 < it.n_iter; i0 += MF_UN) {
+            if (!held) {
+#pragma unroll
+                for (int j = 0; j < MF_UN; ++j)
+                    eh[j] = ent[(uint32_t)(min(i0 + j, it.n_iter - 1) * T + tid)];
+            }
+#pragma unroll
+            for (int j = 0; j < MF_UN; ++j)
+                if (i0 + j < it.n_iter) mf_tap<P>(eh[j], vst, band16, s);
+        }
+        __syncthreads();
+#pragma unroll 1
         for (int l = wv; l < BL; l += 2) {
             const int row = ch.row_lo + it.band * BL + l;
             if (row > ch.row_hi) break;
@@ -879,7 +929,7 @@ __global__ __launch_bounds__(128) void k_band_rows_mf(
 constexpr int MF_BC = 16, MF_LP = 256 + 2;
 
 template <int P>
-__global__ __launch_bounds__(256) void k_band_cols_mf(
+__global__ __launch_bounds__(256, 2) void k_band_cols_mf(
     const BandChan *__restrict__ chans, const uint2 *__restrict__ scratch, int64_t scratch_t,
     int nt, float *__restrict__ acc, float *__restrict__ part, int64_t part_stride,
     float out_scale, const MfConst *__restrict__ mfc) {
@@ -944,11 +994,11 @@ __global__ __launch_bounds__(256) void k_band_cols_mf(
             if (P == 2) mf_line(k, yr, yi, fr2, fi2);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                av[c][i][0] += er[i] * er[i] + ei[i] * ei[i];
+                av[c][i][0] = fmaf(er[i], er[i], fmaf(ei[i], ei[i], av[c][i][0]));
                 if (P == 2) {
-                    av[c][i][1] += fr2[i] * fr2[i] + fi2[i] * fi2[i];
-                    av[c][i][2] += er[i] * fr2[i] + ei[i] * fi2[i];
-                    av[c][i][3] += ei[i] * fr2[i] - er[i] * fi2[i];
+                    av[c][i][1] = fmaf(fr2[i], fr2[i], fmaf(fi2[i], fi2[i], av[c][i][1]));
+                    av[c][i][2] = fmaf(er[i], fr2[i], fmaf(ei[i], fi2[i], av[c][i][2]));
+                    av[c][i][3] = fmaf(ei[i], fr2[i], fmaf(-er[i], fi2[i], av[c][i][3]));
                 }
             }
         }
@@ -1136,15 +1186,23 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
         while (bmax * std::ldexp(1.0, -si) > 32768.0) ++si;
         bp.mf_in = (float)std::ldexp(1.0, -si);
         bp.mf_out = (float)std::ldexp(1.0, 24 + 2 * si);
+        // the row pass rounds each cell's running sum as it stands: the
+        // gather weights carry the exact scale 2^-si (padding entries are 0)
+        for (uint4 &e : all) {
+            e.z = __builtin_bit_cast(uint32_t, __builtin_bit_cast(float, e.z) * bp.mf_in);
+            e.w = __builtin_bit_cast(uint32_t, __builtin_bit_cast(float, e.w) * bp.mf_in);
+        }
         // per-lane DFT-16 fragments and twiddles (lane = a + 16 g)
         std::vector<MfConst> tab(64);
         for (int lane = 0; lane < 64; ++lane) {
             const int a = lane & 15, g = lane >> 4;
             for (int j = 0; j < 4; ++j) {
                 const double f = 2.0 * M_PI * (double)((a * (4 * g + j)) & 15) / 16.0;
-                tab[lane].fr[j] = (_Float16)(float)std::cos(f);
-                tab[lane].fi[j] = (_Float16)(float)std::sin(f);
-                tab[lane].nfi[j] = (_Float16)(float)-std::sin(f);
+                const _Float16 c = (_Float16)(float)std::cos(f), sn = (_Float16)(float)std::sin(f);
+                tab[lane].fre[j] = c;
+                tab[lane].fre[4 + j] = -sn;
+                tab[lane].fim[j] = sn;
+                tab[lane].fim[4 + j] = c;
                 const double u = 2.0 * M_PI * (double)(a * (4 * g + j)) / 256.0;
                 tab[lane].tw[j] = make_float2((float)std::cos(u) * 0.0625f,
                                               (float)std::sin(u) * 0.0625f);
@@ -1322,12 +1380,12 @@ static epic_status launch_mf(epic_plan p, const BandSize &bs, int pass, const ui
         if (p->vb == 2)
             hipLaunchKernelGGL((k_band_rows_mf<P, 2>), dim3((unsigned)(8 * per_xcd)), dim3(128),
                                lds, s, d_volt, p->vstride(), chans, items, (int)bs.n_items,
-                               bs.G, nt, per_xcd, ent, ants, p->A, sc, bp.scratch_t, bp.mf_in,
+                               bs.G, nt, per_xcd, ent, ants, p->A, sc, bp.scratch_t,
                                bp.d_mf.as<MfConst>());
         else
             hipLaunchKernelGGL((k_band_rows_mf<P, 1>), dim3((unsigned)(8 * per_xcd)), dim3(128),
                                lds, s, d_volt, p->vstride(), chans, items, (int)bs.n_items,
-                               bs.G, nt, per_xcd, ent, ants, p->A, sc, bp.scratch_t, bp.mf_in,
+                               bs.G, nt, per_xcd, ent, ants, p->A, sc, bp.scratch_t,
                                bp.d_mf.as<MfConst>());
         EPIC_HIP(hipGetLastError());
         return EPIC_OK;
