@@ -712,11 +712,12 @@ __global__ __launch_bounds__(256) void k_band_reduce(const BandChan *__restrict_
 //                        which is exactly the lane's step-1 result, re then
 //                        im), so lane (a, g) ends with X[a + 16 (4g + i)],
 // with a = lane % 16, g = lane / 16 and F[a][b] = exp(+2 pi i a b / 16)
-// (symmetric).  Every FP16 rounding point is preceded by an exact
-// power-of-two scale: the gridded values by 2^-si (so their bound fits
-// FP16), each 16-point step's output by 1/16 (so no stage can grow past its
-// input bound); the column pass's products are multiplied back by
-// 2^(24 + 2 si).
+// (symmetric).  Every FP16 rounding point stays inside the FP16 range by
+// exact powers of two: the gridded values are scaled by 2^-si so that their
+// bound is at most 2^11; a 16-point step can grow its input bound at most
+// 16-fold, and the first step's output is scaled by 1/16 (in the twiddles)
+// before it is rounded, so a line's output (rounded unscaled) stays below
+// 2^15; the column pass's products are multiplied back by 2^(16 + 2 si).
 typedef _Float16 mf_h4 __attribute__((ext_vector_type(4)));
 typedef _Float16 mf_h8 __attribute__((ext_vector_type(8)));
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
@@ -786,23 +787,30 @@ constexpr int MF_TS = 8;   // samples per row-pass workgroup
 constexpr int MF_UN = 16;  // gather entries a lane holds in registers
 
 // One gather tap: s += 2^-si conj(W) (-1)^(jx+jy) E for both feeds (FMA
-// chains; the plan folds the exact power of two 2^-si into the weights),
-// then the cell's running sum is stored rounded to FP16; a cell's last tap
-// starts the next cell's sum at zero.
+// chains; the plan folds the exact power of two 2^-si into the weights), v
+// being the tap's staged voltages; then the cell's running sum is stored
+// rounded to FP16, and a cell's last tap starts the next cell's sum at zero.
+// A padding entry (weights 0, cell = the spare slot after the band) changes
+// nothing.
 template <int P>
-__device__ __forceinline__ void mf_tap(const uint4 e, const float4 *vst, uint2 *band16,
+__device__ __forceinline__ void mf_tap(const uint4 e, const float4 v, uint2 *band16,
                                        float4 &s) {
     const float wr = __builtin_bit_cast(float, e.z);
     const float wi = __builtin_bit_cast(float, e.w);
-    const float4 v = vst[e.x & 0x7fffffffu];
     s.x = fmaf(-wi, v.y, fmaf(wr, v.x, s.x));
     s.y = fmaf(wi, v.x, fmaf(wr, v.y, s.y));
     if (P == 2) {
         s.z = fmaf(-wi, v.w, fmaf(wr, v.z, s.z));
         s.w = fmaf(wi, v.z, fmaf(wr, v.w, s.w));
     }
+    // the sums themselves are kept in FP32 (no fused convert-on-FMA copy)
+    asm volatile("" : "+v"(s.x), "+v"(s.y), "+v"(s.z), "+v"(s.w));
     band16[e.y] = make_uint2(h2bits(s.x, s.y), h2bits(s.z, s.w));
-    if (e.x & 0x80000000u) s = make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool last = (int)e.x < 0;
+    s.x = last ? 0.f : s.x;
+    s.y = last ? 0.f : s.y;
+    s.z = last ? 0.f : s.z;
+    s.w = last ? 0.f : s.w;
 }
 
 template <int P, int VB>
@@ -850,12 +858,14 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
             }
     };
     if (t0 < t1) fetch(t0);
-    // a lane list of at most MF_UN entries is read once for all the samples
+    // a lane list of at most MF_UN entries is read once for all the samples;
+    // list positions past its end hold padding entries
     const bool held = it.n_iter <= MF_UN;
+    const uint4 pad = make_uint4(0u, (uint32_t)(BL * N), 0u, 0u);
     uint4 eh[MF_UN];
 #pragma unroll
     for (int j = 0; j < MF_UN; ++j) {
-        eh[j] = make_uint4(0u, 0u, 0u, 0u);
+        eh[j] = pad;
         if (held && j < it.n_iter) eh[j] = ent[(uint32_t)(j * T + tid)];
     }
     for (int t = t0; t < t1; ++t) {
@@ -880,16 +890,24 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
         __syncthreads();
         if (t + 1 < t1) fetch(t + 1);
         float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-        // (a longer list is streamed through the same registers)
+        // (a longer list is streamed through the same registers); taps go in
+        // pairs, both voltage reads issued first
         for (int i0 = 0; i0 < it.n_iter; i0 += MF_UN) {
             if (!held) {
 #pragma unroll
-                for (int j = 0; j < MF_UN; ++j)
-                    eh[j] = ent[(uint32_t)(min(i0 + j, it.n_iter - 1) * T + tid)];
+                for (int j = 0; j < MF_UN; ++j) {
+                    const uint4 x = ent[(uint32_t)(min(i0 + j, it.n_iter - 1) * T + tid)];
+                    eh[j] = i0 + j < it.n_iter ? x : pad;
+                }
             }
 #pragma unroll
-            for (int j = 0; j < MF_UN; ++j)
-                if (i0 + j < it.n_iter) mf_tap<P>(eh[j], vst, band16, s);
+            for (int j = 0; j < MF_UN; j += 2)
+                if (i0 + j < it.n_iter) {
+                    const float4 v0 = vst[eh[j].x & 0x7fffffffu];
+                    const float4 v1 = vst[eh[j + 1].x & 0x7fffffffu];
+                    mf_tap<P>(eh[j], v0, band16, s);
+                    mf_tap<P>(eh[j + 1], v1, band16, s);
+                }
         }
         __syncthreads();
 #pragma unroll 1
@@ -912,8 +930,8 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
                          (int64_t)(row - ch.row_lo) * N + a;
     #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const uint32_t hx = h2bits(er[i] * 0.0625f, ei[i] * 0.0625f);
-                const uint32_t hy = P == 2 ? h2bits(fr2[i] * 0.0625f, fi2[i] * 0.0625f) : 0u;
+                const uint32_t hx = h2bits(er[i], ei[i]);
+                const uint32_t hy = P == 2 ? h2bits(fr2[i], fi2[i]) : 0u;
                 out[16 * (4 * g + i)] = make_uint2(hx, hy);
             }
         }
@@ -1183,9 +1201,9 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
             for (double v : cell) bmax = std::max(bmax, v);
         }
         int si = 0;
-        while (bmax * std::ldexp(1.0, -si) > 32768.0) ++si;
+        while (bmax * std::ldexp(1.0, -si) > 2048.0) ++si;
         bp.mf_in = (float)std::ldexp(1.0, -si);
-        bp.mf_out = (float)std::ldexp(1.0, 24 + 2 * si);
+        bp.mf_out = (float)std::ldexp(1.0, 16 + 2 * si);
         // the row pass rounds each cell's running sum as it stands: the
         // gather weights carry the exact scale 2^-si (padding entries are 0)
         for (uint4 &e : all) {
