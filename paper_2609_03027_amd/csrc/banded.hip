@@ -939,19 +939,20 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
 }
 
 // Pass 2, FP16 four-step.  Grid and slices as k_band_cols_pw<16, 2, P>:
-// 16 columns per workgroup of 256 threads.  Per sample the workgroup loads
+// 16 columns per workgroup of 512 threads.  Per sample the workgroup loads
 // the 16-column strip of every footprint row (coalesced 128-byte row
-// segments) into LDS, column-major; wave w then transforms columns w,
-// w + 4, w + 8, w + 12 and keeps the Eq. 2 products of its pixels
-// (a + 16 (4g + i), c0 + col) in registers.
-constexpr int MF_BC = 16, MF_LP = 256 + 2;
+// segments) into LDS, column-major; wave w (of eight) then transforms
+// columns w and w + 8 and keeps the Eq. 2 products of its pixels
+// (a + 16 (4g + i), c0 + col) in registers.  Two columns a wave keep the
+// registers within a quarter of the file: four waves per SIMD.
+constexpr int MF_BC = 16, MF_LP = 256 + 2, MF_CT = 512;
 
 template <int P>
-__global__ __launch_bounds__(256, 2) void k_band_cols_mf(
+__global__ __launch_bounds__(MF_CT, 4) void k_band_cols_mf(
     const BandChan *__restrict__ chans, const uint2 *__restrict__ scratch, int64_t scratch_t,
     int nt, float *__restrict__ acc, float *__restrict__ part, int64_t part_stride,
     float out_scale, const MfConst *__restrict__ mfc) {
-    constexpr int N = 256, T = 256;
+    constexpr int N = 256, T = MF_CT, NW = T / 64, NC = MF_BC / NW, NL = N * 8 / T;
     constexpr int NPROD = P == 2 ? 4 : 1;
     extern __shared__ uint2 tile[];   // [MF_BC][MF_LP]
     const BandChan ch = chans[blockIdx.y];
@@ -960,9 +961,9 @@ __global__ __launch_bounds__(256, 2) void k_band_cols_mf(
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int a = lane & 15, g = lane >> 4;
     const MfConst k = mf_consts(mfc, lane);
-    float av[4][4][NPROD];
+    float av[NC][4][NPROD];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -971,11 +972,11 @@ __global__ __launch_bounds__(256, 2) void k_band_cols_mf(
     // 256 rows x 8 column pairs per sample (rows outside the footprint span
     // are zero); the next sample's strip is loaded into registers while the
     // current one is transformed
-    uint4 pre[8];
+    uint4 pre[NL];
     auto load_strip = [&](int t) {
         const uint2 *src = base + (int64_t)t * scratch_t;
 #pragma unroll
-        for (int r8 = 0; r8 < 8; ++r8) {
+        for (int r8 = 0; r8 < NL; ++r8) {
             const int i = tid + r8 * T;
             const int row = i >> 3, cp = i & 7;
             pre[r8] = make_uint4(0u, 0u, 0u, 0u);
@@ -987,7 +988,7 @@ __global__ __launch_bounds__(256, 2) void k_band_cols_mf(
     if (slice < nt) load_strip(slice);
     for (int t = slice; t < nt; t += S) {
 #pragma unroll
-        for (int r8 = 0; r8 < 8; ++r8) {
+        for (int r8 = 0; r8 < NL; ++r8) {
             const int i = tid + r8 * T;
             const int row = i >> 3, cp = i & 7;
             tile[(2 * cp) * MF_LP + row] = make_uint2(pre[r8].x, pre[r8].y);
@@ -996,8 +997,8 @@ __global__ __launch_bounds__(256, 2) void k_band_cols_mf(
         __syncthreads();
         if (t + S < nt) load_strip(t + S);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int col = wv + 4 * c;
+        for (int c = 0; c < NC; ++c) {
+            const int col = wv + NW * c;
             mf_h4 xr, xi, yr, yi;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -1026,10 +1027,10 @@ __global__ __launch_bounds__(256, 2) void k_band_cols_mf(
     float *dst0 = S == 1 ? acc + ch.img_off
                          : part + slice * part_stride + (int64_t)blockIdx.y * NPROD * plane;
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            float *dst = dst0 + (int64_t)(a + 16 * (4 * g + i)) * N + c0 + wv + 4 * c;
+            float *dst = dst0 + (int64_t)(a + 16 * (4 * g + i)) * N + c0 + wv + NW * c;
 #pragma unroll
             for (int q = 0; q < NPROD; ++q) {
                 const float v = av[c][i][q] * out_scale;
@@ -1410,7 +1411,7 @@ static epic_status launch_mf(epic_plan p, const BandSize &bs, int pass, const ui
     }
     const int S = bs.slices;
     float *pp = S > 1 ? part + bs.part_off : nullptr;
-    hipLaunchKernelGGL(k_band_cols_mf<P>, dim3(bs.N / MF_BC, bs.n, S), dim3(256), kColsMfLds, s,
+    hipLaunchKernelGGL(k_band_cols_mf<P>, dim3(bs.N / MF_BC, bs.n, S), dim3(MF_CT), kColsMfLds, s,
                        chans, sc, bp.scratch_t, nt, acc, pp, bs.part_stride, bp.mf_out,
                        bp.d_mf.as<MfConst>());
     EPIC_HIP(hipGetLastError());
