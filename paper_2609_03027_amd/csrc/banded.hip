@@ -793,15 +793,16 @@ constexpr int MF_UN = 16;  // gather entries a lane holds in registers
 // A padding entry (weights 0, cell = the spare slot after the band) changes
 // nothing.
 template <int P>
-__device__ __forceinline__ void mf_tap(const uint4 e, const float4 v, uint2 *band16,
+__device__ __forceinline__ void mf_tap(const uint4 e, const mf_h4 hv, uint2 *band16,
                                        float4 &s) {
     const float wr = __builtin_bit_cast(float, e.z);
     const float wi = __builtin_bit_cast(float, e.w);
-    s.x = fmaf(-wi, v.y, fmaf(wr, v.x, s.x));
-    s.y = fmaf(wi, v.x, fmaf(wr, v.y, s.y));
+    const float vx = (float)hv.x, vy = (float)hv.y, vz = (float)hv.z, vw = (float)hv.w;
+    s.x = fmaf(-wi, vy, fmaf(wr, vx, s.x));
+    s.y = fmaf(wi, vx, fmaf(wr, vy, s.y));
     if (P == 2) {
-        s.z = fmaf(-wi, v.w, fmaf(wr, v.z, s.z));
-        s.w = fmaf(wi, v.z, fmaf(wr, v.w, s.w));
+        s.z = fmaf(-wi, vw, fmaf(wr, vz, s.z));
+        s.w = fmaf(wi, vz, fmaf(wr, vw, s.w));
     }
     // the sums themselves are kept in FP32 (no fused convert-on-FMA copy)
     asm volatile("" : "+v"(s.x), "+v"(s.y), "+v"(s.z), "+v"(s.w));
@@ -822,7 +823,7 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
     constexpr int N = 256, T = 128;
     // BL * N FP16 cells + the spare slot, then the band's staged voltages
     extern __shared__ uint2 band16[];
-    float4 *vst = reinterpret_cast<float4 *>(band16 + BL * N + 2);
+    mf_h4 *vst = reinterpret_cast<mf_h4 *>(band16 + BL * N + 2);
     // a workgroup takes MF_TS consecutive samples of its band: the band is
     // zeroed once (every sample rewrites the same cells, those with taps)
     const int64_t nts = (nt + MF_TS - 1) / MF_TS;
@@ -842,8 +843,9 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
     const uint4 *ent = entries + it.entry_off;
     const uint8_t *vc = volt + (int64_t)ch.c * P * A * VB;
     // the voltages of the elements that meet this band are decoded once per
-    // sample into LDS (the entries index this list); a lane's first two
-    // elements are read one sample ahead, the rest when staged
+    // sample into LDS as FP16 (exact for 4- and 8-bit integers; the entries
+    // index this list); a lane's first two elements are read one sample
+    // ahead, the rest when staged
     uint32_t ai[2] = {0u, 0u}, rx[2] = {0u, 0u}, ry[2] = {0u, 0u};
 #pragma unroll
     for (int j = 0; j < 2; ++j)
@@ -875,7 +877,7 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
             if (tid + j * T < it.n_ants) {
                 const int2 x = volt_dec(rx[j], VB);
                 const int2 y = P == 2 ? volt_dec(ry[j], VB) : make_int2(0, 0);
-                vst[tid + j * T] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
+                vst[tid + j * T] = mf_h4{(_Float16)x.x, (_Float16)x.y, (_Float16)y.x, (_Float16)y.y};
             }
         if (it.n_ants > 2 * T) {
             const uint8_t *vx = vc + (int64_t)t * vstride;
@@ -884,7 +886,7 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
                 const int2 x = volt_dec(vraw<VB>(vx, an), VB);
                 const int2 y = P == 2 ? volt_dec(vraw<VB>(vx, (uint32_t)A + an), VB)
                                       : make_int2(0, 0);
-                vst[i] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
+                vst[i] = mf_h4{(_Float16)x.x, (_Float16)x.y, (_Float16)y.x, (_Float16)y.y};
             }
         }
         __syncthreads();
@@ -903,8 +905,8 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
 #pragma unroll
             for (int j = 0; j < MF_UN; j += 2)
                 if (i0 + j < it.n_iter) {
-                    const float4 v0 = vst[eh[j].x & 0x7fffffffu];
-                    const float4 v1 = vst[eh[j + 1].x & 0x7fffffffu];
+                    const mf_h4 v0 = vst[eh[j].x & 0x7fffffffu];
+                    const mf_h4 v1 = vst[eh[j + 1].x & 0x7fffffffu];
                     mf_tap<P>(eh[j], v0, band16, s);
                     mf_tap<P>(eh[j + 1], v1, band16, s);
                 }
@@ -1369,7 +1371,7 @@ static epic_status ready_mf(int P) {
                                           : reinterpret_cast<const void *>(k_band_rows_mf<2, 1>))
                                : (vb == 2 ? reinterpret_cast<const void *>(k_band_rows_mf<1, 2>)
                                           : reinterpret_cast<const void *>(k_band_rows_mf<1, 1>));
-        st = lds_ready(k, kRowsMfLds + sizeof(float4) * 4096);
+        st = lds_ready(k, kRowsMfLds + sizeof(uint2) * 4096);
     }
     if (!st)
         st = lds_ready(P == 2 ? reinterpret_cast<const void *>(k_band_cols_mf<2>)
@@ -1393,7 +1395,7 @@ static epic_status launch_mf(epic_plan p, const BandSize &bs, int pass, const ui
         const BandItem *items = bp.d_items.as<BandItem>() + bs.item_off;
         const uint4 *ent = bp.d_entries.as<uint4>();
         const int32_t *ants = bp.d_ants.as<int32_t>();
-        const size_t lds = kRowsMfLds + sizeof(float4) * (size_t)bp.mf_max_ants;
+        const size_t lds = kRowsMfLds + sizeof(uint2) * (size_t)bp.mf_max_ants;
         if (bp.mf_max_ants > 4096)
             return fail(EPIC_ERR_UNSUPPORTED, "FP16 four-step: more than 4096 elements in a band");
         if (p->vb == 2)
