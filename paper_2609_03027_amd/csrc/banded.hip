@@ -783,7 +783,7 @@ __device__ __forceinline__ _Float16 h_hi(uint32_t v) {
 // workgroup runs MF_TS consecutive samples of its band; a lane list of at
 // most MF_UN entries is loaded once for all of them, and the next sample's
 // voltage codes are loaded while the current sample is gathered.
-constexpr int MF_TS = 8;   // samples per row-pass workgroup
+constexpr int MF_TS = 16;  // samples per row-pass workgroup
 constexpr int MF_UN = 16;  // gather entries a lane holds in registers
 
 // One gather tap: s += 2^-si conj(W) (-1)^(jx+jy) E for both feeds (FMA
