@@ -163,12 +163,12 @@ __device__ __forceinline__ void pass_b_products(Grid<P> g, int tid, float (*av)[
             g.zero(base + q * ROW);
             const float2 ex = v0[q];
             float *a = av[k * RB + q];
-            a[0] += ex.x * ex.x + ex.y * ex.y;
+            a[0] = fmaf(ex.x, ex.x, fmaf(ex.y, ex.y, a[0]));
             if (P == 2) {
                 const float2 ey = v1[q];
-                a[1] += ey.x * ey.x + ey.y * ey.y;
-                a[2] += ex.x * ey.x + ex.y * ey.y;
-                a[3] += ex.y * ey.x - ex.x * ey.y;
+                a[1] = fmaf(ey.x, ey.x, fmaf(ey.y, ey.y, a[1]));
+                a[2] = fmaf(ex.x, ey.x, fmaf(ex.y, ey.y, a[2]));
+                a[3] = fmaf(ex.y, ey.x, fmaf(-ex.x, ey.y, a[3]));
             }
         }
     }
@@ -193,10 +193,10 @@ __device__ __forceinline__ void jones_taps(const uint4 *r1, const uint4 *r2, con
     const float ar = __uint_as_float(e1.x), ai = __uint_as_float(e1.y);
     const float br = __uint_as_float(e1.z), bi = __uint_as_float(e1.w);
     const float cr = __uint_as_float(e2.x), ci = __uint_as_float(e2.y);
-    sx.x += ar * v.z - ai * v.w;
-    sx.y += ar * v.w + ai * v.z;
-    sy.x += br * v.x - bi * v.y + cr * v.z - ci * v.w;
-    sy.y += br * v.y + bi * v.x + cr * v.w + ci * v.z;
+    sx.x = fmaf(-ai, v.w, fmaf(ar, v.z, sx.x));
+    sx.y = fmaf(ai, v.z, fmaf(ar, v.w, sx.y));
+    sy.x = fmaf(-ci, v.w, fmaf(cr, v.z, fmaf(-bi, v.y, fmaf(br, v.x, sy.x))));
+    sy.y = fmaf(ci, v.z, fmaf(cr, v.w, fmaf(bi, v.x, fmaf(br, v.y, sy.y))));
 }
 
 // One sample's gather.  Each lane owns whole cells; it loads GB entries at
@@ -246,14 +246,14 @@ __device__ __forceinline__ void gather_cells(Grid<P> grid, const uint4 *ent, int
             if (k0 + k >= n_iter) break;            // uniform: n_iter is per item
             const float4 v = stage[e[k].x & 0xFFFFu];
             const float wr = __uint_as_float(e[k].z), wi = __uint_as_float(e[k].w);
-            sx.x += wr * v.x - wi * v.y;
-            sx.y += wr * v.y + wi * v.x;
+            sx.x = fmaf(-wi, v.y, fmaf(wr, v.x, sx.x));
+            sx.y = fmaf(wi, v.x, fmaf(wr, v.y, sx.y));
             if (JN) {
                 const int64_t r = (int64_t)(k0 + k) * 3 * T;
                 jones_taps(ent + r + T, ent + r + 2 * T, v, sx, sy);
             } else if (P == 2) {
-                sy.x += wr * v.z - wi * v.w;
-                sy.y += wr * v.w + wi * v.z;
+                sy.x = fmaf(-wi, v.w, fmaf(wr, v.z, sy.x));
+                sy.y = fmaf(wi, v.z, fmaf(wr, v.w, sy.y));
             }
             grid.store(e[k].y, sx, sy);
             const bool last = (e[k].x >> 31) != 0u;
@@ -737,10 +737,10 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
             for (int q = 0; q < 8; ++q) {
                 if (!oy) g.zero(base + q * ROW);
                 float *a = av[oy * 8 + q];
-                a[0] += vx[q].x * vx[q].x + vx[q].y * vx[q].y;
-                a[1] += vy[q].x * vy[q].x + vy[q].y * vy[q].y;
-                a[2] += vx[q].x * vy[q].x + vx[q].y * vy[q].y;
-                a[3] += vx[q].y * vy[q].x - vx[q].x * vy[q].y;
+                a[0] = fmaf(vx[q].x, vx[q].x, fmaf(vx[q].y, vx[q].y, a[0]));
+                a[1] = fmaf(vy[q].x, vy[q].x, fmaf(vy[q].y, vy[q].y, a[1]));
+                a[2] = fmaf(vx[q].x, vy[q].x, fmaf(vx[q].y, vy[q].y, a[2]));
+                a[3] = fmaf(vx[q].y, vy[q].x, fmaf(-vx[q].x, vy[q].y, a[3]));
             }
         }
         if (FR && (t + 1) % frame_len == 0) {
