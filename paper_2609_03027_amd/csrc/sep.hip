@@ -33,9 +33,17 @@ typedef _Float16 sh8 __attribute__((ext_vector_type(8)));
 typedef __bf16 sb8 __attribute__((ext_vector_type(8)));
 typedef float sf4 __attribute__((ext_vector_type(4)));
 
-constexpr int kT = 256;      // threads per workgroup (4 waves)
-constexpr int kW = 32;       // kx columns per workgroup (two 16-column MFMA blocks)
 constexpr int kAMax = 1024;  // elements staged per sample
+
+// Workgroup shape: NW waves and W kx columns.  A 128 grid takes half a
+// channel per workgroup with 8 waves (a sample's grid is formed twice per
+// channel, not four times); smaller grids take 32 columns with 4 waves.
+template <int DT, int N> struct SepShape {
+    static constexpr bool WIDE = N == 128;
+    static constexpr int NW = WIDE ? 8 : 4;
+    static constexpr int W = WIDE ? 64 : 32;
+    static constexpr int T = 64 * NW;
+};
 
 __device__ __forceinline__ uint16_t f16_bits(float x) {
     return __builtin_bit_cast(uint16_t, (_Float16)x);
@@ -77,6 +85,7 @@ struct SepArgs {
     int64_t vstride;
     int A, vb, C, n_time, tps, S;
     int64_t per_xcd, total;
+    int astage;             // elements the LDS stage holds (>= A)
     float h_scale;          // 2^-sb applied to H before rounding
     float out_scale;        // 2^(2 (sa + sb)) applied to the products
     float *acc;             // sums (when S == 1)
@@ -84,25 +93,34 @@ struct SepArgs {
     int64_t part_stride;
 };
 
-// One workgroup per (time slice, channel, 32-column kx tile); waves own the
-// step-1 rows (re/im, feed, u) and the step-2 rows (ky, re/im) in quarters.
-// HL = 1 (FP16) or 2 (BF16 hi + lo: products hi hi + hi lo + lo hi).
+// One workgroup per (time slice, channel, W-column kx tile).  Step 1: wave w
+// owns the 16-column block w % (W / 16) of the tile and every (NW / (W / 16))-th
+// row block (re/im, feed, u) from w / (W / 16); step 2: wave w owns the row
+// blocks (ky, re/im) w RB2W .. w RB2W + RB2W - 1 and every column (feed, kx)
+// of the tile.  HL = 1 (FP16) or 2 (BF16 hi + lo: products hi hi + hi lo +
+// lo hi).
 template <int DT, int N, int NA>
-__global__ __launch_bounds__(kT) void k_sep(const SepArgs a) {
+__global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
+    using SH = SepShape<DT, N>;
+    constexpr int T = SH::T, NW = SH::NW, W = SH::W;
     constexpr int HL = DT == EPIC_BF16X2_MFMA ? 2 : 1;
     constexpr int KS = 2 * NA / 32;          // k steps (K = 2 NA)
-    constexpr int NT = N / kW;               // kx tiles
-    constexpr int RB1W = NA / 16;            // step-1 row blocks per wave (4 NA rows / 16 / 4)
+    constexpr int NT = N / W;                // kx tiles
+    constexpr int NCB = W / 16;              // step-1 column blocks of a tile
+    constexpr int NRB1 = NA / 4;             // step-1 row blocks (4 NA rows)
+    constexpr int RSTEP = NW / NCB;          // waves sharing a column block
+    constexpr int RB1W = NRB1 / RSTEP;       // step-1 row blocks per wave
     constexpr int RB2 = N / 8;               // step-2 row blocks (2 N rows)
-    constexpr int RB2W = RB2 / 4;            // per wave
+    constexpr int RB2W = RB2 / NW;           // per wave
+    constexpr int NHX = W / 16;              // step-2 column blocks per feed
     constexpr int GP = NA + 8;               // grid row pitch (16-bit values)
     constexpr int GPLANE = NA * GP;          // one (feed, re/im) plane
     constexpr int KP = 2 * NA + 8;           // H column pitch
-    static_assert(RB2W >= 1 && RB1W >= 1, "grid sides");
+    static_assert(RB2W >= 1 && RB1W >= 1 && NW % NCB == 0, "grid sides");
     extern __shared__ float4 smem[];
-    float4 *stage = smem;                                            // [kAMax]
-    uint16_t *grid = reinterpret_cast<uint16_t *>(smem + kAMax);     // [HL][2][2][NA][GP]
-    uint16_t *hbuf = grid + HL * 4 * GPLANE;                         // [HL][2 kW][KP]
+    float4 *stage = smem;                                            // [astage]
+    uint16_t *grid = reinterpret_cast<uint16_t *>(smem + a.astage);  // [HL][2][2][NA][GP]
+    uint16_t *hbuf = grid + HL * 4 * GPLANE;                         // [HL][2 W][KP]
 
     const int64_t L = (int64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
     if (L >= a.total) return;
@@ -113,31 +131,32 @@ __global__ __launch_bounds__(kT) void k_sep(const SepArgs a) {
     const int tile = rem % NT;
     const int t_begin = slice * a.tps, t_stop = min(a.n_time, t_begin + a.tps);
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, col = lane & 15;
+    const int cb1 = wave % NCB, rw1 = wave / NCB;
 
-    // constants: step-1 B (this tile's Fa^T columns) and this wave's step-2 A rows
-    uint4 b1[HL][2][KS], a2[HL][RB2W][KS];
+    // constants: step-1 B (Fa^T columns of this wave's block) and this
+    // wave's step-2 A rows
+    uint4 b1[HL][KS], a2[HL][RB2W][KS];
 #pragma unroll
     for (int h = 0; h < HL; ++h) {
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-            for (int s = 0; s < KS; ++s)
-                b1[h][cb][s] = a.fx[((((int64_t)h * NT + tile) * 2 + cb) * KS + s) * 64 + lane];
+        for (int s = 0; s < KS; ++s)
+            b1[h][s] = a.fx[(((int64_t)h * (N / 16) + tile * NCB + cb1) * KS + s) * 64 + lane];
 #pragma unroll
         for (int r = 0; r < RB2W; ++r)
 #pragma unroll
             for (int s = 0; s < KS; ++s)
                 a2[h][r][s] = a.fy[(((int64_t)h * RB2 + wave * RB2W + r) * KS + s) * 64 + lane];
     }
-    for (int i = tid; i < HL * 4 * GPLANE; i += kT) grid[i] = 0;   // cells without taps stay 0
+    for (int i = tid; i < HL * 4 * GPLANE; i += T) grid[i] = 0;   // cells without taps stay 0
 
-    float sum[RB2W][2][2][4];
+    float sum[RB2W][NHX][2][4];
 #pragma unroll
     for (int r = 0; r < RB2W; ++r)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < NHX; ++h)
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -145,40 +164,30 @@ __global__ __launch_bounds__(kT) void k_sep(const SepArgs a) {
 
     const uint8_t *vc = a.volt + (int64_t)it.c * 2 * a.A * a.vb;
     const uint4 *ent = a.entries + it.entry_off + tid;
-    // this lane's first two elements' raw voltage bytes, loaded one sample
-    // ahead (elements beyond 2 kT are loaded when staged)
-    uint32_t rx[2] = {0u, 0u}, ry[2] = {0u, 0u};
-    if (t_begin < t_stop) {
+    // this lane's first element's raw voltage bytes, loaded one sample ahead
+    // (elements beyond T are loaded when staged)
+    uint32_t rx = 0u, ry = 0u;
+    if (t_begin < t_stop && tid < a.A) {
         const uint8_t *v0 = vc + (int64_t)t_begin * a.vstride;
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-            if (tid + k * kT < a.A) {
-                rx[k] = volt_raw(v0, tid + k * kT, a.vb);
-                ry[k] = volt_raw(v0, (int64_t)a.A + tid + k * kT, a.vb);
-            }
+        rx = volt_raw(v0, tid, a.vb);
+        ry = volt_raw(v0, (int64_t)a.A + tid, a.vb);
     }
     for (int t = t_begin; t < t_stop; ++t) {
         // stage this sample's voltages (both feeds) as float4
         const uint8_t *vt = vc + (int64_t)t * a.vstride;
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-            if (tid + k * kT < a.A) {
-                const int2 x = volt_dec(rx[k], a.vb), y = volt_dec(ry[k], a.vb);
-                stage[tid + k * kT] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
-            }
-        for (int e = tid + 2 * kT; e < a.A; e += kT) {
+        if (tid < a.A) {
+            const int2 x = volt_dec(rx, a.vb), y = volt_dec(ry, a.vb);
+            stage[tid] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
+        }
+        for (int e = tid + T; e < a.A; e += T) {
             const int2 x = volt_at(vt, e, a.vb), y = volt_at(vt, (int64_t)a.A + e, a.vb);
             stage[e] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
         }
         __syncthreads();
-        if (t + 1 < t_stop) {
+        if (t + 1 < t_stop && tid < a.A) {
             const uint8_t *vn = vt + a.vstride;
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-                if (tid + k * kT < a.A) {
-                    rx[k] = volt_raw(vn, tid + k * kT, a.vb);
-                    ry[k] = volt_raw(vn, (int64_t)a.A + tid + k * kT, a.vb);
-                }
+            rx = volt_raw(vn, tid, a.vb);
+            ry = volt_raw(vn, (int64_t)a.A + tid, a.vb);
         }
         // gather: each lane sums whole cells, conj(W) 2^-sa E, and writes each
         // once; entries are loaded eight at a time (indices clamped into the
@@ -191,17 +200,17 @@ __global__ __launch_bounds__(kT) void k_sep(const SepArgs a) {
                 uint4 eb[GB];
 #pragma unroll
                 for (int k = 0; k < GB; ++k)
-                    eb[k] = ent[(int64_t)min(i0 + k, it.n_iter - 1) * kT];
+                    eb[k] = ent[(int64_t)min(i0 + k, it.n_iter - 1) * T];
 #pragma unroll
                 for (int k = 0; k < GB; ++k) {
                     if (i0 + k >= it.n_iter) break;
                     const uint4 e = eb[k];
                     const float4 v = stage[e.x & 0x7FFFFFFFu];
                     const float wr = __uint_as_float(e.z), wi = __uint_as_float(e.w);
-                    sxr += wr * v.x - wi * v.y;
-                    sxi += wr * v.y + wi * v.x;
-                    syr += wr * v.z - wi * v.w;
-                    syi += wr * v.w + wi * v.z;
+                    sxr = fmaf(-wi, v.y, fmaf(wr, v.x, sxr));
+                    sxi = fmaf(wi, v.x, fmaf(wr, v.y, sxi));
+                    syr = fmaf(-wi, v.w, fmaf(wr, v.z, syr));
+                    syi = fmaf(wi, v.z, fmaf(wr, v.w, syi));
                     if (e.x >> 31) {
                         const int u = (int)e.y / NA, vv = (int)e.y % NA;
                         const int o = u * GP + vv;
@@ -222,10 +231,10 @@ __global__ __launch_bounds__(kT) void k_sep(const SepArgs a) {
             }
         }
         __syncthreads();
-        // step 1: rows (ri, p, u) of this wave, both 16-column blocks of the tile
+        // step 1: this wave's row blocks (ri, p, u) of its column block
 #pragma unroll
         for (int r = 0; r < RB1W; ++r) {
-            const int rb = wave * RB1W + r;            // 0 .. NA / 4 - 1
+            const int rb = rw1 + r * RSTEP;            // 0 .. NA / 4 - 1
             const int ublk = rb % (NA / 16);
             const int p = (rb / (NA / 16)) & 1;
             const int ri = rb / (NA / 8);
@@ -251,54 +260,53 @@ __global__ __launch_bounds__(kT) void k_sep(const SepArgs a) {
                     ga[h][s] = x;
                 }
             }
+            sf4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                sf4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    d = mma<DT>(ga[0][s], b1[0][cb][s], d);
-                    if (HL == 2) {
-                        d = mma<DT>(ga[0][s], b1[HL - 1][cb][s], d);
-                        d = mma<DT>(ga[HL - 1][s], b1[0][cb][s], d);
-                    }
+            for (int s = 0; s < KS; ++s) {
+                d = mma<DT>(ga[0][s], b1[0][s], d);
+                if (HL == 2) {
+                    d = mma<DT>(ga[0][s], b1[HL - 1][s], d);
+                    d = mma<DT>(ga[HL - 1][s], b1[0][s], d);
                 }
-                // rows 4 g + i: u = ublk 16 + 4 g + i of column kx = cb 16 + col
-                const int n2 = p * kW + cb * 16 + col;
-                const int k2 = ri * NA + ublk * 16 + 4 * g;
-                uint16_t hv[HL][4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float x = d[i] * a.h_scale;
-                    if (HL == 1) {
-                        hv[0][i] = f16_bits(x);
-                    } else {
-                        hv[0][i] = bf16_bits(x);
-                        hv[HL - 1][i] = bf16_bits(x - bf16_val(hv[0][i]));
-                    }
-                }
-#pragma unroll
-                for (int h = 0; h < HL; ++h)
-                    *reinterpret_cast<uint2 *>(hbuf + (h * 2 * kW + n2) * KP + k2) =
-                        make_uint2((uint32_t)hv[h][0] | (uint32_t)hv[h][1] << 16,
-                                   (uint32_t)hv[h][2] | (uint32_t)hv[h][3] << 16);
             }
+            // rows 4 g + i: u = ublk 16 + 4 g + i of column kx = cb1 16 + col
+            const int n2 = p * W + cb1 * 16 + col;
+            const int k2 = ri * NA + ublk * 16 + 4 * g;
+            uint16_t hv[HL][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float x = d[i] * a.h_scale;
+                if (HL == 1) {
+                    hv[0][i] = f16_bits(x);
+                } else {
+                    hv[0][i] = bf16_bits(x);
+                    hv[HL - 1][i] = bf16_bits(x - bf16_val(hv[0][i]));
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < HL; ++h)
+                *reinterpret_cast<uint2 *>(hbuf + (h * 2 * W + n2) * KP + k2) =
+                    make_uint2((uint32_t)hv[h][0] | (uint32_t)hv[h][1] << 16,
+                               (uint32_t)hv[h][2] | (uint32_t)hv[h][3] << 16);
+            // one row block's operands live at a time
+            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
         // step 2: rows (ky, re/im) of this wave; columns (feed, kx) of the tile;
-        // x and y blocks of one kx half give both feeds of the same pixels
+        // x and y blocks of one kx block give both feeds of the same pixels
 #pragma unroll
-        for (int hx = 0; hx < 2; ++hx) {
+        for (int hx = 0; hx < NHX; ++hx) {
             sf4 d[2][RB2W];
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                const int n2 = p * kW + hx * 16 + col;
+                const int n2 = p * W + hx * 16 + col;
                 uint4 bq[HL][KS];
 #pragma unroll
                 for (int s = 0; s < KS; ++s)
 #pragma unroll
                     for (int h = 0; h < HL; ++h)
                         bq[h][s] = *reinterpret_cast<const uint4 *>(
-                            hbuf + (h * 2 * kW + n2) * KP + 32 * s + 8 * g);
+                            hbuf + (h * 2 * W + n2) * KP + 32 * s + 8 * g);
 #pragma unroll
                 for (int r = 0; r < RB2W; ++r) {
                     sf4 x = {0.f, 0.f, 0.f, 0.f};
@@ -326,6 +334,8 @@ __global__ __launch_bounds__(kT) void k_sep(const SepArgs a) {
                     sum[r][hx][q][2] = fmaf(xr, yr, fmaf(xi, yi, sum[r][hx][q][2]));
                     sum[r][hx][q][3] = fmaf(xi, yr, fmaf(-xr, yi, sum[r][hx][q][3]));
                 }
+            // one column block's operands live at a time
+            __builtin_amdgcn_sched_barrier(0);
         }
         // the next sample's staging is ordered after step 2 by its barrier
     }
@@ -336,11 +346,11 @@ __global__ __launch_bounds__(kT) void k_sep(const SepArgs a) {
 #pragma unroll
     for (int r = 0; r < RB2W; ++r)
 #pragma unroll
-        for (int hx = 0; hx < 2; ++hx)
+        for (int hx = 0; hx < NHX; ++hx)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int ky = (wave * RB2W + r) * 8 + 2 * g + q;
-                const int kx = tile * kW + hx * 16 + col;
+                const int kx = tile * W + hx * 16 + col;
                 const int64_t pix = (int64_t)ky * N + kx;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -385,9 +395,28 @@ const void *pick_kernel(int dt, int N, int NA) {
     return nullptr;
 }
 
-size_t sep_lds(int hl, int NA) {
-    return sizeof(float4) * kAMax + sizeof(uint16_t) * (size_t)hl * 4 * NA * (NA + 8) +
-           sizeof(uint16_t) * (size_t)hl * 2 * kW * (2 * NA + 8);
+// Workgroup threads and tile width for a precision and grid side (the
+// values SepShape gives the kernel).
+struct SepDims {
+    int T, W;
+};
+SepDims sep_dims(int dt, int N) {
+    if (dt == EPIC_F16_MFMA) {
+        if (N == 128) return {SepShape<EPIC_F16_MFMA, 128>::T, SepShape<EPIC_F16_MFMA, 128>::W};
+        return {SepShape<EPIC_F16_MFMA, 64>::T, SepShape<EPIC_F16_MFMA, 64>::W};
+    }
+    if (N == 128) return {SepShape<EPIC_BF16X2_MFMA, 128>::T, SepShape<EPIC_BF16X2_MFMA, 128>::W};
+    return {SepShape<EPIC_BF16X2_MFMA, 64>::T, SepShape<EPIC_BF16X2_MFMA, 64>::W};
+}
+
+// staged elements: A rounded up to a multiple of 64
+int sep_astage(int A) { return (A + 63) / 64 * 64; }
+
+size_t sep_lds(int dt, int N, int NA, int A) {
+    const size_t hl = dt == EPIC_BF16X2_MFMA ? 2 : 1;
+    const size_t W = (size_t)sep_dims(dt, N).W;
+    return sizeof(float4) * (size_t)sep_astage(A) + sizeof(uint16_t) * hl * 4 * NA * (NA + 8) +
+           sizeof(uint16_t) * hl * 2 * W * (2 * NA + 8);
 }
 
 // 16-bit rounding of one value into the hi [, lo] fragment tables
@@ -435,7 +464,9 @@ epic_status sep_build(epic_plan p, const std::vector<int> &j0, const std::vector
     sp.Na = NA;
     sp.lo = lo;
     if (!pick_kernel(dt, N, NA)) return fail(EPIC_ERR_UNSUPPORTED, "separable DFT-GEMM shape");
-    if (sep_lds(HL, NA) > 160 * 1024) return fail(EPIC_ERR_UNSUPPORTED, "separable DFT-GEMM LDS");
+    if (sep_lds(dt, N, NA, A) > 160 * 1024)
+        return fail(EPIC_ERR_UNSUPPORTED, "separable DFT-GEMM LDS");
+    const SepDims dims = sep_dims(dt, N);
 
     // Worst-case bounds: a cell sums |W| |E|max over its taps; a row of H sums
     // its cells.  Powers of two keep both within 2^14 (the 16-bit formats'
@@ -488,7 +519,7 @@ epic_status sep_build(epic_plan p, const std::vector<int> &j0, const std::vector
                 }
         items[c].c = c;
         items[c].entry_off = (int64_t)all.size();
-        items[c].n_iter = lpt_pack(taps, kT, all);
+        items[c].n_iter = lpt_pack(taps, dims.T, all);
         items[c].img_off = p->ch[c].img_off;
     }
 
@@ -504,7 +535,7 @@ epic_status sep_build(epic_plan p, const std::vector<int> &j0, const std::vector
         re = std::cos(ang);
         im = std::sin(ang);
     };
-    const int KS = 2 * NA / 32, RB2 = N / 8, NT = N / kW;
+    const int KS = 2 * NA / 32, RB2 = N / 8;
     // step-2 A: row r = (ky, ri) = (r / 2, r % 2), k = (ri', u) = (k / NA, k % NA)
     std::vector<uint16_t> fyh((size_t)RB2 * KS * 64 * 8), fyl(fyh.size());
     for (int rb = 0; rb < RB2; ++rb)
@@ -518,19 +549,19 @@ epic_status sep_build(epic_plan p, const std::vector<int> &j0, const std::vector
                     const double v = (ri == 0) ? (rip == 0 ? fr : -fi) : (rip == 0 ? fi : fr);
                     put16(dt, fyh, fyl, (((size_t)rb * KS + st) * 64 + l) * 8 + j, v);
                 }
-    // step-1 B: column kx, k = (ri', v): Re / Im Fa[kx][v]
-    std::vector<uint16_t> fxh((size_t)NT * 2 * KS * 64 * 8), fxl(fxh.size());
-    for (int tl = 0; tl < NT; ++tl)
-        for (int cb = 0; cb < 2; ++cb)
-            for (int st = 0; st < KS; ++st)
-                for (int l = 0; l < 64; ++l)
-                    for (int j = 0; j < 8; ++j) {
-                        const int kx = tl * kW + cb * 16 + (l & 15), k = 32 * st + 8 * (l >> 4) + j;
-                        double fr, fi;
-                        fa(kx, k % NA, fr, fi);
-                        put16(dt, fxh, fxl, ((((size_t)tl * 2 + cb) * KS + st) * 64 + l) * 8 + j,
-                              k / NA == 0 ? fr : fi);
-                    }
+    // step-1 B: 16-column block cb, column kx = 16 cb + l % 16, k = (ri', v):
+    // Re / Im Fa[kx][v]
+    std::vector<uint16_t> fxh((size_t)(N / 16) * KS * 64 * 8), fxl(fxh.size());
+    for (int cb = 0; cb < N / 16; ++cb)
+        for (int st = 0; st < KS; ++st)
+            for (int l = 0; l < 64; ++l)
+                for (int j = 0; j < 8; ++j) {
+                    const int kx = cb * 16 + (l & 15), k = 32 * st + 8 * (l >> 4) + j;
+                    double fr, fi;
+                    fa(kx, k % NA, fr, fi);
+                    put16(dt, fxh, fxl, (((size_t)cb * KS + st) * 64 + l) * 8 + j,
+                          k / NA == 0 ? fr : fi);
+                }
     std::vector<uint16_t> fy, fx;
     fy.insert(fy.end(), fyh.begin(), fyh.end());
     fx.insert(fx.end(), fxh.begin(), fxh.end());
@@ -552,9 +583,13 @@ epic_status sep_build(epic_plan p, const std::vector<int> &j0, const std::vector
                                 hipMemcpyHostToDevice, s));
     EPIC_HIP(hipStreamSynchronize(s));
     sp.n_items = C;
-    // time slices: enough workgroups for two per CU, at most 64 slices
-    const int wgs = C * NT;
-    sp.t_slices = std::max(1, std::min(64, (512 + wgs - 1) / wgs));
+    // time slices: enough workgroups to fill every CU as many times as its
+    // LDS allows (at most two), at most 64 slices
+    const int wgs = C * (N / dims.W);
+    const int per_cu =
+        std::max<int>(1, std::min<int>(2, (160 * 1024) / (int)sep_lds(dt, N, NA, A)));
+    const int want = 256 * per_cu;
+    sp.t_slices = std::max(1, std::min(64, (want + wgs - 1) / wgs));
     sp.part_floats = sp.t_slices > 1 ? p->image_floats : 0;
     return EPIC_OK;
 }
@@ -566,7 +601,8 @@ epic_status sep_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int
     const int HL = dt == EPIC_BF16X2_MFMA ? 2 : 1;
     const void *kern = pick_kernel(dt, sp.N, sp.Na);
     if (!kern) return fail(EPIC_ERR_UNSUPPORTED, "separable DFT-GEMM shape");
-    const size_t lds = sep_lds(HL, sp.Na);
+    const size_t lds = sep_lds(dt, sp.N, sp.Na, p->A);
+    const SepDims dims = sep_dims(dt, sp.N);
     epic_status st = lds_ready(kern, lds);
     if (st) return st;
     SepArgs a{};
@@ -577,13 +613,14 @@ epic_status sep_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int
     a.volt = d_volt;
     a.vstride = p->vstride();
     a.A = p->A;
+    a.astage = sep_astage(p->A);
     a.vb = p->vb;
     a.C = p->C;
     a.n_time = n_time;
     const int S = std::max(1, std::min(sp.t_slices, n_time));
     a.tps = (n_time + S - 1) / S;
     a.S = (n_time + a.tps - 1) / a.tps;         // slices in use
-    const int NT = sp.N / kW;
+    const int NT = sp.N / dims.W;
     a.total = (int64_t)a.S * p->C * NT;
     a.per_xcd = (a.total + 7) / 8;
     if (8 * a.per_xcd > 0x7fffffff) return fail(EPIC_ERR_ARG, "separable DFT-GEMM: grid too large");
@@ -596,7 +633,8 @@ epic_status sep_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int
                     acc->d_work.bytes < sizeof(float) * (size_t)a.S * (size_t)p->image_floats))
         return fail(EPIC_ERR_ARG, "accumulator has no slice memory for the separable DFT-GEMM");
     void *args[] = {&a};
-    EPIC_HIP(hipLaunchKernel(kern, dim3((unsigned)(8 * a.per_xcd)), dim3(kT), args, lds, s));
+    EPIC_HIP(hipLaunchKernel(kern, dim3((unsigned)(8 * a.per_xcd)), dim3((unsigned)dims.T), args,
+                             lds, s));
     if (a.S > 1) {
         const int64_t n = p->image_floats;
         hipLaunchKernelGGL(k_sep_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
