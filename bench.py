@@ -375,7 +375,8 @@ def streaming_large(E, torch, n_streams, n_chan=64, n_blocks=60, ring=2, warm_bl
 def batched(E, torch, reps=5):
     """SKA-station-like uneven batch: 384 channels over 50-350 MHz with grid
     sides 32..192, 512 samples per integration, all in one graph launch.
-    Eager launches vs the graph, default vs autotuned sub-transform tiles."""
+    Eager launches vs the graph, default vs autotuned sub-transform tiles,
+    launch form and time slices."""
     import numpy as np
 
     import synth
@@ -405,14 +406,16 @@ def batched(E, torch, reps=5):
     flops, _ = algorithmic_flops(wl)        # FFT-equivalent + products + gridding
     t0 = time.perf_counter()
     sub, report = autotune.tune(pos, wl.chan_freq_hz, wl.grid_n, wl.n_pol,
-                                aperture_n=wl.aperture_n, use_cache=False)
+                                aperture_n=wl.aperture_n, n_time=wl.n_time, use_cache=False)
     res["autotune_s"] = time.perf_counter() - t0
     res["autotune_choice"] = {str(n): int(m) for n, m in
                               sorted(set(zip(wl.grid_n.tolist(), sub.tolist())))}
     res["autotune_ms"] = {str(k): v for k, v in report.items()}
     res["autotune_launch"] = report.get("launch", {}).get("choice")
+    res["autotune_slices"] = autotune.slices_of(report)
     for label, kw in (("default", {}),
-                      ("autotuned", {"sub_n": sub, "batch_queue": autotune.use_queue(report)}),
+                      ("autotuned", {"sub_n": sub, "batch_queue": autotune.use_queue(report),
+                                     "time_slices": autotune.slices_of(report)}),
                       ("queue", {"batch_queue": True})):
         plan = E.Plan.from_workload(wl, pos, **kw)
         acc = E.Accumulator(plan)

@@ -206,6 +206,15 @@ typedef struct {
                                     bytes per sample (EPIC_ERR_ARG): the [c][p][a] block of
                                     each sample is packed, samples may be spaced further
                                     apart (a ring with headers, a larger capture buffer) */
+    int32_t time_slices;         /* fused size groups of one class per item (paired groups
+                                    take none) and the work queue (EPIC_F32): split
+                                    each call's samples into this many time slices, each
+                                    summed into its own partial image set and reduced in
+                                    slice order (deterministic for a given value; other
+                                    values change the FP32 summation order only).  0 = the
+                                    library's choice (enough workgroups for about four
+                                    waves per SIMD); 1 .. 64, else EPIC_ERR_ARG.  The
+                                    autotuner's third knob */
 } epic_plan_desc;
 
 typedef struct epic_plan_s *epic_plan;  /* opaque; owns device tables */

@@ -70,6 +70,7 @@ class PlanDesc(C.Structure):
         ("fixed_grid_shift", C.c_int32),
         ("xform", C.c_int32),
         ("volt_stride_t", C.c_int64),
+        ("time_slices", C.c_int32),
     ]
 
 
@@ -159,10 +160,11 @@ class Plan:
                  kernel_k=3, kernel_sigma=0.5, kernel_table=None, precision=EPIC_F32,
                  sub_n=None, volt_bits=4, jones=False, twiddle_bits=8,
                  stage_shifts=FIXED_DEFAULT, grid_shift=FIXED_DEFAULT, xform=XFORM_AUTO,
-                 volt_stride=0, batch_queue=False, stream=None):
+                 volt_stride=0, batch_queue=False, time_slices=0, stream=None):
         """``grid_n`` None: the library picks each channel's side (see
         ``epic_plan_desc.grid_n``); ``volt_stride``: bytes between time
-        samples of the voltage input (0 = packed)."""
+        samples of the voltage input (0 = packed); ``time_slices``: time
+        slices of the fused size groups (0 = the library's choice)."""
         lib = load()
         self._pos = np.ascontiguousarray(pos, dtype=np.float64)
         self._freq = np.ascontiguousarray(freq_hz, dtype=np.float64)
@@ -199,6 +201,7 @@ class Plan:
         d.fixed_grid_shift = int(grid_shift)
         d.xform = int(xform)
         d.volt_stride_t = int(volt_stride)
+        d.time_slices = int(time_slices)
         self._sub = None if sub_n is None else np.ascontiguousarray(sub_n, dtype=np.int32)
         d.sub_n = None if self._sub is None else self._sub.ctypes.data_as(C.POINTER(C.c_int32))
         h = C.c_void_p()

@@ -16,8 +16,12 @@ second knob is the launch form: with the chosen tiles it times the plan as
 one launch per size group (classes paired where they can be, samples split
 into time slices where a group under-fills the device) and as one persistent
 work-queue launch over every item (``BATCH_QUEUE``), and keeps the faster
-(again only past 2 %).  Results are cached as JSON keyed by the batch shape (``EPIC_AUTOTUNE_CACHE``
-or ~/.cache/epic_mi355x/autotune.json).
+(again only past 2 %).  The third is the number of time slices per size
+group (``time_slices``: the library's own choice, or 1, 2, 4, 8, 16), timed
+with the chosen tiles and launch form: more slices fill the device with
+more workgroups but each adds a partial image set to reduce.  Results are
+cached as JSON keyed by the batch shape (``EPIC_AUTOTUNE_CACHE`` or
+~/.cache/epic_mi355x/autotune.json).
 """
 from __future__ import annotations
 
@@ -62,9 +66,13 @@ def _key(grid_n, pos, freq, n_pol, kernel_k, cell_lambda, aperture_n):
             f"-sizes{sizes}")
 
 
-def _time_batch(pos, freq, grid_n, n_pol, sub, volt, reps, plan_kw, queue=False):
+SLICE_CHOICES = (1, 2, 4, 8, 16)
+
+
+def _time_batch(pos, freq, grid_n, n_pol, sub, volt, reps, plan_kw, queue=False, slices=0):
     import torch
-    plan = L.Plan(pos, freq, grid_n, n_pol, sub_n=sub, batch_queue=queue, **plan_kw)
+    plan = L.Plan(pos, freq, grid_n, n_pol, sub_n=sub, batch_queue=queue, time_slices=slices,
+                  **plan_kw)
     acc = L.Accumulator(plan)
     g = L.Graph(plan, acc, volt)
     g.launch()
@@ -85,17 +93,22 @@ def tune(pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5, kernel_k
          kernel_sigma=0.5, n_time=64, reps=3, use_cache=True, verbose=False):
     """Sub-transform choice per channel (array aligned with ``grid_n``; 0 =
     the library default, 16/32/64 = fused tile side, SUB_BANDED = banded).
+    ``n_time`` is the number of samples per call the plan will be used with
+    (the best slice count depends on it).
 
     Returns ``(sub_n, report)``; report maps each grid side to the measured
-    milliseconds of one graph launch over all channels per choice tried, and
+    milliseconds of one graph launch over all channels per choice tried,
     ``report["launch"]`` holds the launch-form comparison, its ``"choice"``
-    being ``"queue"`` or ``"groups"`` (see ``use_queue``).
+    being ``"queue"`` or ``"groups"`` (see ``use_queue``), and
+    ``report["slices"]`` the time-slice comparison, its ``"choice"`` the
+    ``time_slices`` value to plan with (0 = the library's; see
+    ``slices_of``).
     """
     import torch
     freq_hz = np.asarray(freq_hz, dtype=np.float64)
     grid_n = np.asarray(grid_n, dtype=np.int32)
     path = _cache_path()
-    key = _key(grid_n, pos, freq_hz, n_pol, kernel_k, cell_lambda, aperture_n)
+    key = _key(grid_n, pos, freq_hz, n_pol, kernel_k, cell_lambda, aperture_n) + f"-T{n_time}"
     cache = {}
     if use_cache and os.path.exists(path):
         try:
@@ -103,10 +116,11 @@ def tune(pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5, kernel_k
         except (OSError, ValueError):
             cache = {}
     sizes = sorted(set(int(x) for x in grid_n))
-    if key in cache and "launch" in cache[key]:
+    if key in cache and "slices" in cache[key]:
         best = {int(k): int(v) for k, v in cache[key]["best"].items()}
         rep = {int(k): v for k, v in cache[key]["ms"].items()}
         rep["launch"] = cache[key]["launch"]
+        rep["slices"] = cache[key]["slices"]
         return np.array([best[int(n)] for n in grid_n], dtype=np.int32), rep
     plan_kw = dict(aperture_n=aperture_n, cell_lambda=cell_lambda, kernel_k=kernel_k,
                    kernel_sigma=kernel_sigma)
@@ -141,10 +155,26 @@ def tune(pos, freq_hz, grid_n, n_pol, *, aperture_n=0, cell_lambda=0.5, kernel_k
             print(f"autotune launch form: groups {base:.3f} ms, queue {q:.3f} ms", flush=True)
     launch["choice"] = "queue" if launch.get("queue", base) < 0.98 * base else "groups"
     report["launch"] = launch
+    # time slices with the chosen tiles and launch form
+    queue = launch["choice"] == "queue"
+    best_ms = min(base, launch.get("queue", base)) if queue else base
+    sl = {"0": best_ms}
+    best_s = 0
+    for k in SLICE_CHOICES:
+        ms = _time_batch(pos, freq_hz, grid_n, n_pol, sub_of(choice), volt, reps, plan_kw,
+                         queue=queue, slices=k)
+        sl[str(k)] = ms
+        if verbose:
+            print(f"autotune time slices {k}: {ms:.3f} ms (best {best_ms:.3f})", flush=True)
+        if ms < 0.98 * best_ms:
+            best_ms, best_s = ms, k
+    sl["choice"] = best_s
+    report["slices"] = sl
     if use_cache:
         cache[key] = {"best": {str(k): v for k, v in choice.items()},
-                      "ms": {str(k): v for k, v in report.items() if k != "launch"},
-                      "launch": launch}
+                      "ms": {str(k): v for k, v in report.items()
+                             if k not in ("launch", "slices")},
+                      "launch": launch, "slices": sl}
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             json.dump(cache, open(path, "w"), indent=1)
@@ -158,10 +188,17 @@ def use_queue(report) -> bool:
     return report.get("launch", {}).get("choice") == "queue"
 
 
+def slices_of(report) -> int:
+    """The tuned ``time_slices`` (0 = the library's choice)."""
+    return int(report.get("slices", {}).get("choice", 0))
+
+
 def tuned_plan(wl, pos, **kw):
     """A plan for a synth workload with autotuned sub-transform sides and
     launch form."""
+    kw.setdefault("n_time", wl.n_time)
     sub, report = tune(pos, wl.chan_freq_hz, wl.grid_n, wl.n_pol, aperture_n=wl.aperture_n,
                        cell_lambda=wl.cell_lambda, kernel_k=wl.kernel_k,
                        kernel_sigma=wl.kernel_sigma_cells, **kw)
-    return L.Plan.from_workload(wl, pos, sub_n=sub, batch_queue=use_queue(report))
+    return L.Plan.from_workload(wl, pos, sub_n=sub, batch_queue=use_queue(report),
+                                time_slices=slices_of(report))

@@ -130,6 +130,8 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
             return fail(EPIC_ERR_ARG, "volt_stride_t must be 0, or at least C * P * A * bytes "
                                       "per sample and a multiple of the bytes per sample");
     }
+    if (d->time_slices < 0 || d->time_slices > 64)
+        return fail(EPIC_ERR_ARG, "time_slices must be 0 (the library's choice) or 1 .. 64");
     if (d->precision < EPIC_F32 || d->precision > EPIC_FIXED16)
         return fail(EPIC_ERR_ARG, "unknown precision");
     if (d->precision == EPIC_FIXED16) {
@@ -209,6 +211,7 @@ epic_status epic_plan_create(const epic_plan_desc *d, void *hip_stream, epic_pla
     p->grid_n.assign(grid_n, grid_n + p->C);
     p->xform = d->xform;
     p->volt_stride = d->volt_stride_t;
+    p->time_slices = d->time_slices;
     if (d->sub_n) p->sub_n.assign(d->sub_n, d->sub_n + p->C);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     epic_status st = EPIC_OK;

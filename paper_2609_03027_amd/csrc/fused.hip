@@ -1058,6 +1058,7 @@ static epic_status slice_group(epic_plan p, FusedGroup *g, std::vector<FusedItem
             }
         }
     }
+    if (p->time_slices > 0) S = p->time_slices;   // the caller's (autotuned) choice
     g->slices = g->kind == 0 ? S : 1;
     std::vector<int64_t> off(p->C, -1);
     std::vector<GroupChan> chans;

@@ -284,6 +284,7 @@ struct epic_plan_s {
     int64_t work_bytes = 0;       // per-accumulator working memory the path needs
     int xform = 0;                // epic_xform, resolved at build (never AUTO after it)
     int64_t volt_stride = 0;      // bytes between time samples (0: packed)
+    int time_slices = 0;          // fused groups: slices per call (0: the library's choice)
     // bytes between time samples of the voltage input
     int64_t vstride() const { return volt_stride ? volt_stride : (int64_t)C * P * A * vb; }
     epic::SepPlan sep;            // separable DFT-GEMM tables (EPIC_XFORM_DFT_SEPARABLE)

@@ -243,6 +243,8 @@ def test_fp16_plans_take_one_path_for_all_channels():
     ({"volt_stride_t": 3}, 2, b"volt_stride_t"),               # below C P A = 4 bytes
     ({"volt_stride_t": 5, "flags": 1}, 2, b"volt_stride_t"),   # 8-bit: below 8 bytes
     ({"volt_stride_t": 9, "flags": 1}, 2, b"volt_stride_t"),   # 8-bit: odd stride
+    ({"time_slices": -1}, 2, b"time_slices"),
+    ({"time_slices": 65}, 2, b"time_slices"),
 ])
 def test_transform_form_and_stride_are_checked_before_device_work(over, status, msg):
     import paper_2609_03027_amd as E

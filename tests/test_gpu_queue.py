@@ -144,3 +144,30 @@ def test_full_band_equals_size_group_launches():
     for i, c in enumerate((0, 383)):
         emax, _ = image_errors(pq.channel_image(oq, c).numpy().astype(np.float64), ref[i])
         assert emax.max() <= 1e-4
+
+
+@pytest.mark.parametrize("queue", [False, True])
+@pytest.mark.parametrize("slices", [1, 3, 16])
+def test_time_slices_chosen_by_the_caller(queue, slices):
+    """The ``time_slices`` plan knob (the autotuner's third): any slice count
+    gives the oracle's images within the FP32 guard, and a plan gives the
+    same bits on every run."""
+    torch = _torch()
+    import paper_2609_03027_amd as E
+    wl, pos, volt = _ska(12, per=1)
+    _say(f"case slices: {slices} time slices, {'queue' if queue else 'size groups'}, "
+         "6 grid sides, 12 samples")
+    plan = E.Plan.from_workload(wl, pos, batch_queue=queue, time_slices=slices)
+    dv = torch.from_numpy(volt).cuda()
+    outs = []
+    for _ in range(2):
+        acc = E.Accumulator(plan)
+        E.accumulate(plan, acc, volt=dv)
+        outs.append(_images(E, torch, plan, acc).cpu())
+        acc.close()
+    assert torch.equal(outs[0], outs[1])
+    got = [plan.channel_image(outs[0], c).numpy().astype(np.float64) for c in range(wl.n_chan)]
+    ref = oracle_images(volt, pos, wl, range(wl.n_chan))
+    for c in range(wl.n_chan):
+        guard = fp32_guard(int(wl.grid_n[c]), wl.kernel_k, wl.n_time)
+        assert image_errors(got[c], ref[c])[0].max() <= guard
