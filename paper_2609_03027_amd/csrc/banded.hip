@@ -283,13 +283,13 @@ __global__ __launch_bounds__(BT) void k_band_rows(
                 const float2 cw = csr_w[e];
                 const int2 x = volt_at(vx, a, vb);
                 const float xr = (float)x.x, xi = (float)x.y;
-                s.x += cw.x * xr - cw.y * xi;
-                s.y += cw.x * xi + cw.y * xr;
+                s.x = fmaf(-cw.y, xi, fmaf(cw.x, xr, s.x));
+                s.y = fmaf(cw.y, xr, fmaf(cw.x, xi, s.y));
                 if (P == 2) {
                     const int2 y = volt_at(vx, A + a, vb);
                     const float yr = (float)y.x, yi = (float)y.y;
-                    s.z += cw.x * yr - cw.y * yi;
-                    s.w += cw.x * yi + cw.y * yr;
+                    s.z = fmaf(-cw.y, yi, fmaf(cw.x, yr, s.z));
+                    s.w = fmaf(cw.y, yr, fmaf(cw.x, yi, s.w));
                 }
             }
             if ((row + col) & 1) s = make_float4(-s.x, -s.y, -s.z, -s.w);
@@ -360,11 +360,11 @@ __global__ __launch_bounds__(BT) void k_band_cols(const BandChan *__restrict__ c
             if (k < npix) {
                 const int i = threadIdx.x + k * BT;
                 const float4 e = res[(i % BL) * LP + i / BL];
-                av[k][0] += e.x * e.x + e.y * e.y;
+                av[k][0] = fmaf(e.x, e.x, fmaf(e.y, e.y, av[k][0]));
                 if (P == 2) {
-                    av[k][1] += e.z * e.z + e.w * e.w;
-                    av[k][2] += e.x * e.z + e.y * e.w;
-                    av[k][3] += e.y * e.z - e.x * e.w;
+                    av[k][1] = fmaf(e.z, e.z, fmaf(e.w, e.w, av[k][1]));
+                    av[k][2] = fmaf(e.x, e.z, fmaf(e.y, e.w, av[k][2]));
+                    av[k][3] = fmaf(e.y, e.z, fmaf(-e.x, e.w, av[k][3]));
                 }
             }
         }
@@ -517,13 +517,13 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
             const float wi = __builtin_bit_cast(float, e[k].w);
             const int2 x = volt_dec(bx[k], VB);
             const float xr = (float)x.x, xi = (float)x.y;
-            s.x += wr * xr - wi * xi;
-            s.y += wr * xi + wi * xr;
+            s.x = fmaf(-wi, xi, fmaf(wr, xr, s.x));
+            s.y = fmaf(wi, xr, fmaf(wr, xi, s.y));
             if (P == 2) {
                 const int2 y = volt_dec(by[k], VB);
                 const float yr = (float)y.x, yi = (float)y.y;
-                s.z += wr * yr - wi * yi;
-                s.w += wr * yi + wi * yr;
+                s.z = fmaf(-wi, yi, fmaf(wr, yr, s.z));
+                s.w = fmaf(wi, yr, fmaf(wr, yi, s.w));
             }
             lds[e[k].y] = s;
             if (e[k].x & 0x80000000u) s = zero;
@@ -642,11 +642,11 @@ void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const float4 e = v[dpos<R>(q)];
-            av[q][0] += e.x * e.x + e.y * e.y;
+            av[q][0] = fmaf(e.x, e.x, fmaf(e.y, e.y, av[q][0]));
             if (P == 2) {
-                av[q][1] += e.z * e.z + e.w * e.w;
-                av[q][2] += e.x * e.z + e.y * e.w;
-                av[q][3] += e.y * e.z - e.x * e.w;
+                av[q][1] = fmaf(e.z, e.z, fmaf(e.w, e.w, av[q][1]));
+                av[q][2] = fmaf(e.x, e.z, fmaf(e.y, e.w, av[q][2]));
+                av[q][3] = fmaf(e.y, e.z, fmaf(-e.x, e.w, av[q][3]));
             }
         }
         __syncthreads();   // every read of the last pass before the next writes
