@@ -66,6 +66,7 @@ class BlockRecord:
     pass_gap: float = math.nan     # since the previous pass began
     call_s: float = math.nan       # host time inside the accumulate call
     readout_call_s: float = math.nan   # host time in read-out + copy calls after it
+    readout_parts: tuple = None        # executor's split of that time (seconds), if any
 
     @property
     def latency(self):
@@ -192,6 +193,8 @@ class Server:
                     st.images.append((st.samples_in_integration,
                                       self.ex.readout(st.handle)))
                     rec.readout_call_s = self.ex.now() - h0
+                    parts = getattr(self.ex, "readout_parts", None)
+                    rec.readout_parts = parts(st.handle) if parts else None
                     st.blocks_in_integration = 0
                     st.samples_in_integration = 0
             if st.next_block >= spec.n_blocks and not st.inflight:
@@ -230,15 +233,23 @@ class Server:
 
     def host_stats(self, records):
         """Where host time went: the longest scheduling pass and gap between
-        passes, and the longest accumulate and read-out calls."""
+        passes, the longest accumulate and read-out calls, and the slowest
+        read-out call's split when the executor gives one (for the device
+        executor: waiting on the previous copy, the read-out call, the event
+        and reset, the copy issue)."""
         def mx(v):
             v = [x for x in v if np.isfinite(x)]
             return float(max(v) * 1e3) if v else None
-        return {"max_pass_ms": self.max_pass_s * 1e3,
-                "max_pass_gap_ms": (self.max_gap_s * 1e3 if np.isfinite(self.max_gap_s)
-                                    else None),
-                "max_accumulate_call_ms": mx([r.call_s for r in records]),
-                "max_readout_call_ms": mx([r.readout_call_s for r in records])}
+        out = {"max_pass_ms": self.max_pass_s * 1e3,
+               "max_pass_gap_ms": (self.max_gap_s * 1e3 if np.isfinite(self.max_gap_s)
+                                   else None),
+               "max_accumulate_call_ms": mx([r.call_s for r in records]),
+               "max_readout_call_ms": mx([r.readout_call_s for r in records])}
+        ro = [r for r in records if np.isfinite(r.readout_call_s) and r.readout_parts]
+        if ro:
+            worst = max(ro, key=lambda r: r.readout_call_s)
+            out["slowest_readout_parts_ms"] = [round(x * 1e3, 3) for x in worst.readout_parts]
+        return out
 
 
 # ---------------------------------------------------------------- executors
@@ -311,16 +322,22 @@ class DeviceExecutor:
         self.ref.record()
         torch.cuda.synchronize()
         self.host0 = time.perf_counter()
+        self._pending = []       # streams whose latest image awaits its copy
 
     def now(self):
         return time.perf_counter() - self.host0
 
     def idle(self, dt):
+        self._poll_copies()
         t = time.perf_counter() + dt
         while time.perf_counter() < t:
             pass
 
     def sync(self):
+        for h in self._pending:
+            if h.get("pending") is not None:
+                self._issue_copy(h)
+        self._pending = []
         self.torch.cuda.synchronize()
 
     def plan_bytes(self, plan):
@@ -362,6 +379,9 @@ class DeviceExecutor:
                 "ring": self.rings[spec.name]}
 
     def close(self, h):
+        if h.get("pending") is not None:
+            self._issue_copy(h)
+        self._pending = [x for x in self._pending if x is not h]
         h["stream"].synchronize()
         h["copy"].synchronize()
         h["acc"].close()
@@ -384,9 +404,12 @@ class DeviceExecutor:
         return self.ref.elapsed_time(ev) / 1e3
 
     def readout(self, h):
-        """Read-out on the stream's queue; the copy to pinned host memory runs
-        on a side queue so the next block does not wait for it (valid after
-        ``sync``)."""
+        """Read-out on the stream's queue.  The copy to pinned host memory runs
+        on a side queue so the next block does not wait for it, and it is
+        issued only once the read-out has finished (``idle`` polls for that):
+        a copy issued with its input still pending held the host for up to
+        9 ms with four stations in flight.  The image is valid after
+        ``sync``."""
         import paper_2609_03027_amd as E
         torch = self.torch
         if h["n_out"] < len(h["host"]):
@@ -394,17 +417,48 @@ class DeviceExecutor:
         else:
             out = torch.empty(h["img"].shape, dtype=torch.float32, pin_memory=True)
         h["n_out"] += 1
-        s, cp = h["stream"], h["copy"]
+        s = h["stream"]
+        t0 = time.perf_counter()
+        if h.get("pending") is not None:
+            self._issue_copy(h)              # the previous image's copy, now
         if h["copied"] is not None:
             s.wait_event(h["copied"])        # the previous copy still reads img
         with torch.cuda.stream(s):
+            t1 = time.perf_counter()
             E.readout(h["spec"].plan, h["acc"], h["img"], E.REMOVE_AUTOS | E.NORMALISE, stream=s)
+            t2 = time.perf_counter()
             ready = torch.cuda.Event()
             ready.record(s)
             h["acc"].reset(stream=s)
-        cp.wait_event(ready)
-        with torch.cuda.stream(cp):
-            out.copy_(h["img"], non_blocking=True)
-            h["copied"] = torch.cuda.Event()
-            h["copied"].record(cp)
+            t3 = time.perf_counter()
+        h["pending"] = (ready, out)
+        self._pending.append(h)
+        t4 = time.perf_counter()
+        # host seconds in: issuing the previous image's copy and the wait on
+        # it, the read-out call, the event and reset, the bookkeeping
+        h["parts"] = (t1 - t0, t2 - t1, t3 - t2, t4 - t3)
         return out
+
+    def _issue_copy(self, h):
+        ready, out = h["pending"]
+        h["pending"] = None
+        cp = h["copy"]
+        cp.wait_event(ready)
+        with self.torch.cuda.stream(cp):
+            out.copy_(h["img"], non_blocking=True)
+            h["copied"] = self.torch.cuda.Event()
+            h["copied"].record(cp)
+
+    def _poll_copies(self):
+        keep = []
+        for h in self._pending:
+            if h.get("pending") is None:
+                continue
+            if h["pending"][0].query():
+                self._issue_copy(h)
+            else:
+                keep.append(h)
+        self._pending = keep
+
+    def readout_parts(self, h):
+        return h.get("parts")
