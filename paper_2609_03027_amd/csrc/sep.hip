@@ -172,6 +172,16 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
         rx = volt_raw(v0, tid, a.vb);
         ry = volt_raw(v0, (int64_t)a.A + tid, a.vb);
     }
+    // a lane list of at most GB entries is loaded once for all the samples
+    // (FP16 only: the BF16 hi + lo form has no registers to spare)
+    constexpr int GB = 8;
+    const bool held = HL == 1 && it.n_iter <= GB;
+    uint4 eh[HL == 1 ? GB : 1];
+    if (HL == 1) {
+#pragma unroll
+        for (int k = 0; k < GB; ++k)
+            eh[k] = held ? ent[(int64_t)min(k, it.n_iter - 1) * T] : make_uint4(0u, 0u, 0u, 0u);
+    }
     for (int t = t_begin; t < t_stop; ++t) {
         // stage this sample's voltages (both feeds) as float4
         const uint8_t *vt = vc + (int64_t)t * a.vstride;
@@ -194,13 +204,17 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
         // list, the surplus not applied) so a lane waits for one L2 round
         // trip per eight entries
         {
-            constexpr int GB = 8;
             float sxr = 0.f, sxi = 0.f, syr = 0.f, syi = 0.f;
             for (int i0 = 0; i0 < it.n_iter; i0 += GB) {
                 uint4 eb[GB];
+                if (held) {
 #pragma unroll
-                for (int k = 0; k < GB; ++k)
-                    eb[k] = ent[(int64_t)min(i0 + k, it.n_iter - 1) * T];
+                    for (int k = 0; k < GB; ++k) eb[k] = eh[k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < GB; ++k)
+                        eb[k] = ent[(int64_t)min(i0 + k, it.n_iter - 1) * T];
+                }
 #pragma unroll
                 for (int k = 0; k < GB; ++k) {
                     if (i0 + k >= it.n_iter) break;

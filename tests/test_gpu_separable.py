@@ -1,7 +1,8 @@
 """Separable DFT-GEMM (EPIC_XFORM_DFT_SEPARABLE: E = Fa G Fa^T with F pruned
 to the gridded region, FP16 or BF16 hi + lo operands on the matrix cores,
 FP32 accumulation) against the FP64 oracle at its precision's bound: the
-LWA-like 128^2 grid with its 64^2 region, whole 32^2 and 64^2 grids, 4- and
+LWA-like 128^2 grid with its 64^2 region, a 32^2 region of a 128^2 grid,
+whole 32^2 and 64^2 grids, 4- and
 8-bit voltages, several calls and time slices, graph replays, and the shapes
 it refuses."""
 import dataclasses
@@ -57,6 +58,19 @@ def test_lwa_region_of_a_zero_padded_grid(prec):
          "24 samples in 2 calls")
     got = _run(wl, pos, volt, prec, calls=2)
     _check(got, oracle_images(volt, pos, wl, range(3)), NAMES[prec], "lwa")
+
+
+@pytest.mark.parametrize("prec", [1, 3])
+def test_32_region_of_a_128_grid(prec):
+    """A 32^2 region in a 128^2 grid: the 128 workgroup shape (8 waves over
+    64-column tiles) with the short K = 64 operands."""
+    wl = dataclasses.replace(synth.workload("tiny2"), grid_n=np.array([128]), aperture_n=32)
+    pos = synth.antenna_layout(wl)
+    volt = synth.voltages(wl, pos)[:20]
+    wl = wl.with_time(20)
+    _say(f"case separable {NAMES[prec]}: 16 elements, 128^2 grid, 32^2 region, 20 samples")
+    got = _run(wl, pos, volt, prec, calls=2)
+    _check(got, oracle_images(volt, pos, wl, range(1)), NAMES[prec], "tiny2-128-32")
 
 
 @pytest.mark.parametrize("prec", [1, 3])
