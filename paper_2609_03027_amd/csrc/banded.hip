@@ -759,6 +759,8 @@ __device__ __forceinline__ void mf_line(const MfConst &k, mf_h4 xr, mf_h4 xi, mf
 
 // FP16 scratch cell: both feeds, (x re, x im), (y re, y im) as half pairs.
 typedef _Float16 mf_h2 __attribute__((ext_vector_type(2)));
+typedef uint32_t mf_u2 __attribute__((ext_vector_type(2)));
+typedef uint32_t mf_u4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint32_t h2bits(float a, float b) {
     mf_h2 h;
     h.x = (_Float16)a;
@@ -934,7 +936,9 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
             for (int i = 0; i < 4; ++i) {
                 const uint32_t hx = h2bits(er[i], ei[i]);
                 const uint32_t hy = P == 2 ? h2bits(fr2[i], fi2[i]) : 0u;
-                out[16 * (4 * g + i)] = make_uint2(hx, hy);
+                // streamed: the column pass reads it after the whole round
+                __builtin_nontemporal_store(mf_u2{hx, hy},
+                                            reinterpret_cast<mf_u2 *>(out + 16 * (4 * g + i)));
             }
         }
     }
@@ -982,9 +986,12 @@ __global__ __launch_bounds__(MF_CT, 4) void k_band_cols_mf(
             const int i = tid + r8 * T;
             const int row = i >> 3, cp = i & 7;
             pre[r8] = make_uint4(0u, 0u, 0u, 0u);
-            if (row >= ch.row_lo && row <= ch.row_hi)
-                pre[r8] = *reinterpret_cast<const uint4 *>(src + (int64_t)(row - ch.row_lo) * N +
-                                                           2 * cp);
+            if (row >= ch.row_lo && row <= ch.row_hi) {
+                // streamed: each strip is read once
+                const mf_u4 x = __builtin_nontemporal_load(reinterpret_cast<const mf_u4 *>(
+                    src + (int64_t)(row - ch.row_lo) * N + 2 * cp));
+                pre[r8] = make_uint4(x.x, x.y, x.z, x.w);
+            }
         }
     };
     if (slice < nt) load_strip(slice);
