@@ -67,6 +67,17 @@ __device__ __forceinline__ uint32_t vraw(const uint8_t *p, uint32_t idx) {
     return p[idx];
 }
 
+// Streamed scratch accesses: row transforms are written once and read once,
+// a whole round apart, so they bypass the caches' retention (non-temporal).
+typedef float band_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void nt_store(float4 *p, const float4 v) {
+    __builtin_nontemporal_store(band_f4{v.x, v.y, v.z, v.w}, reinterpret_cast<band_f4 *>(p));
+}
+__device__ __forceinline__ float4 nt_load(const void *p) {
+    const band_f4 x = __builtin_nontemporal_load(reinterpret_cast<const band_f4 *>(p));
+    return make_float4(x.x, x.y, x.z, x.w);
+}
+
 // One radix-R Stockham pass over BL lines (positive exponent).
 template <int R>
 __device__ __forceinline__ void stockham_pass(const float4 *src, float4 *dst, int N, int pitch,
@@ -542,7 +553,7 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
         float4 *out = scratch + (int64_t)t * scratch_t + ch.scratch_off +
                       (int64_t)(row - ch.row_lo) * N + j;
 #pragma unroll
-        for (int q = 0; q < R; ++q) out[q * L] = v[dpos<R>(q)];
+        for (int q = 0; q < R; ++q) nt_store(out + q * L, v[dpos<R>(q)]);
     }
 }
 
@@ -615,7 +626,7 @@ void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict
     if (PREF && t_first < t_end) {
 #pragma unroll
         for (int q = 0; q < R; ++q)
-            pre[q] = *reinterpret_cast<const float4 *>(base + t_first * tstride + off(q));
+            pre[q] = nt_load(base + t_first * tstride + off(q));
     }
     float av[R][NPROD];
 #pragma unroll
@@ -628,14 +639,14 @@ void k_band_cols_pw(const BandChan *__restrict__ chans, const float2 *__restrict
         if (!PREF) {
             const char *cur = base + (int64_t)t * tstride;
 #pragma unroll
-            for (int q = 0; q < R; ++q) pre[q] = *reinterpret_cast<const float4 *>(cur + off(q));
+            for (int q = 0; q < R; ++q) pre[q] = nt_load(cur + off(q));
         }
 #pragma unroll
         for (int q = 0; q < R; ++q) v[q] = ((live >> q) & 1u) ? pre[q] : zero;
         if (PREF && t + t_step < t_end) {
             const char *nx = base + (int64_t)(t + t_step) * tstride;
 #pragma unroll
-            for (int q = 0; q < R; ++q) pre[q] = *reinterpret_cast<const float4 *>(nx + off(q));
+            for (int q = 0; q < R; ++q) pre[q] = nt_load(nx + off(q));
         }
         dft<R>(v);
         pw_rest<R, NP>(v, line, j, twl);
