@@ -9,6 +9,17 @@
 
 namespace epic {
 
+// Grids and sky images are written once and read once, a whole pass apart
+// (gigabytes per call): streamed past the caches (non-temporal).
+typedef float st_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_store(float2 *p, const float2 v) {
+    __builtin_nontemporal_store(st_f2{v.x, v.y}, reinterpret_cast<st_f2 *>(p));
+}
+__device__ __forceinline__ float2 st_load(const float2 *p) {
+    const st_f2 x = __builtin_nontemporal_load(reinterpret_cast<const st_f2 *>(p));
+    return make_float2(x.x, x.y);
+}
+
 // Gather gridding: one thread per output cell, summing conj(W) E over the
 // cell's taps from the plan's CSR table.  Every cell is written.  With Jones
 // kernels (J = 4) output polarisation p sums conj(W^{p x}) E^x + conj(W^{p y})
@@ -85,8 +96,8 @@ __global__ void k_grid_csr_t(const uint8_t *__restrict__ volt, int64_t volt_t_st
                 for (int p = 0; p < P; ++p) {
                     const int2 x = volt_at(v + (int64_t)k * volt_t_stride, (int64_t)p * A + a, vb);
                     const float er = (float)x.x, ei = (float)x.y;
-                    s[k][p].x += w.x * er - w.y * ei;
-                    s[k][p].y += w.x * ei + w.y * er;
+                    s[k][p].x = fmaf(-w.y, ei, fmaf(w.x, er, s[k][p].x));
+                    s[k][p].y = fmaf(w.y, er, fmaf(w.x, ei, s[k][p].y));
                 }
             }
         }
@@ -96,8 +107,9 @@ __global__ void k_grid_csr_t(const uint8_t *__restrict__ volt, int64_t volt_t_st
         if (k < nt)
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                grid[(int64_t)(t0 + k) * grid_t_stride + grid_off[c] + (int64_t)p * N * N + cell] =
-                    s[k][p];
+                st_store(grid + (int64_t)(t0 + k) * grid_t_stride + grid_off[c] +
+                             (int64_t)p * N * N + cell,
+                         s[k][p]);
 }
 
 // --------------------------------------------------------------- FFT
@@ -416,7 +428,7 @@ __global__ __launch_bounds__(T) void k_fft2d_p2(const float2 *in, float2 *out,
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + k * T;
-            if (NN % T == 0 || i < NN) pre[k] = src[i];
+            if (NN % T == 0 || i < NN) pre[k] = st_load(src + i);
         }
     };
     int64_t img = blockIdx.x;
@@ -445,7 +457,7 @@ __global__ __launch_bounds__(T) void k_fft2d_p2(const float2 *in, float2 *out,
                 const int r = i / N, col = i % N;
                 float2 v = sbuf[r * pitch + col];
                 if ((r + col) & 1) v = make_float2(-v.x, -v.y);
-                dst[i] = v;
+                st_store(dst + i, v);
             }
         }
         __syncthreads();   // every read of this image before the next one's writes
@@ -465,13 +477,13 @@ __global__ void k_accum_sky(const float2 *__restrict__ sky, const int4 *__restri
     const float2 *s = sky + grid_off[c] + pix;
     float xx = 0.f, yy = 0.f, re = 0.f, im = 0.f;
     for (int t = 0; t < n_time; ++t) {
-        const float2 ex = s[(int64_t)t * grid_t_stride];
-        xx += ex.x * ex.x + ex.y * ex.y;
+        const float2 ex = st_load(s + (int64_t)t * grid_t_stride);
+        xx = fmaf(ex.x, ex.x, fmaf(ex.y, ex.y, xx));
         if (P == 2) {
-            const float2 ey = s[(int64_t)t * grid_t_stride + plane];
-            yy += ey.x * ey.x + ey.y * ey.y;
-            re += ex.x * ey.x + ex.y * ey.y;
-            im += ex.y * ey.x - ex.x * ey.y;
+            const float2 ey = st_load(s + (int64_t)t * grid_t_stride + plane);
+            yy = fmaf(ey.x, ey.x, fmaf(ey.y, ey.y, yy));
+            re = fmaf(ex.x, ey.x, fmaf(ex.y, ey.y, re));
+            im = fmaf(ex.y, ey.x, fmaf(-ex.x, ey.y, im));
         }
     }
     float *a = acc + img_off[c] + pix;
