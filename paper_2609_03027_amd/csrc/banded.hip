@@ -1493,9 +1493,9 @@ epic_status banded_acc_setup(epic_plan p, epic_acc acc) {
     return EPIC_OK;
 }
 
-// Rounds of t_chunk samples alternate between the two scratch halves: the
-// row pass of round k + 1 (queue 0) runs while the column pass of round k
-// (queue 1) reads the other half.  Events: 0 fork, 1 + b row pass into half b
+// Rounds of at most t_chunk samples (of equal length) alternate between the
+// two scratch halves: the row pass of round k + 1 (queue 0) runs while the
+// column pass of round k (queue 1) reads the other half.  Events: 0 fork, 1 + b row pass into half b
 // done, 3 + b column pass out of half b done, 5 the row queue's last pass
 // done.  banded_join makes the caller's stream wait on both queues' last
 // events: each queue that forked from the caller's stream is joined back
@@ -1558,9 +1558,14 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
     }
     const int64_t half = (int64_t)bp.elem_bytes * bp.scratch_t * bp.t_chunk;   // bytes
     epic_status st = EPIC_OK;
+    // the fewest rounds of at most `round` samples, of equal length as far as
+    // whole frames allow (a short last round would run its passes alone)
+    const int n_rounds = (n_time + round - 1) / round;
+    int step = (n_time + n_rounds - 1) / n_rounds;
+    if (fo.len) step = (step + fo.len - 1) / fo.len * fo.len;
     int k = 0;
-    for (int t0 = 0; t0 < n_time && !st; t0 += round, ++k) {
-        const int nt = std::min(round, n_time - t0);
+    for (int t0 = 0; t0 < n_time && !st; t0 += step, ++k) {
+        const int nt = std::min(step, n_time - t0);
         FrameOut fr = fo;
         if (fo.len) fr.out = fo.out + (int64_t)(t0 / fo.len) * fo.stride;
         const int b = k & 1;

@@ -790,27 +790,41 @@ __global__ __launch_bounds__(512) void k_fused_pair(const FusedItem *__restrict_
 
 // Per-element self-term sums S_a^{pq} = sum_t E_a^p conj(E_a^q), exact in
 // int32 (|E|^2 <= 128 per sample).  Grid: (elements, channels, time chunks).
-template <int P>
-__global__ void k_autos(const uint8_t *__restrict__ volt, int64_t volt_t_stride, int A,
-                        int n_time, int t_chunk, int vb, int32_t *__restrict__ autos) {
+// VB bytes per voltage sample; eight samples' bytes are loaded at once.
+template <int P, int VB>
+__global__ __launch_bounds__(256) void k_autos(const uint8_t *__restrict__ volt,
+                                               int64_t volt_t_stride, int A, int n_time,
+                                               int t_chunk, int32_t *__restrict__ autos) {
+    constexpr int U = 8;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (a >= A) return;
     const int t0 = blockIdx.z * t_chunk;
     const int t1 = min(n_time, t0 + t_chunk);
     int sxx = 0, syy = 0, sre = 0, sim = 0;
-    const uint8_t *v = volt + (int64_t)c * P * A * vb;
-    for (int t = t0; t < t1; ++t) {
-        const uint8_t *vt = v + (int64_t)t * volt_t_stride;
-        const int2 x = volt_at(vt, a, vb);
-        const int xr = x.x, xi = x.y;
-        sxx += xr * xr + xi * xi;
-        if (P == 2) {
-            const int2 y = volt_at(vt, A + a, vb);
-            const int yr = y.x, yi = y.y;
-            syy += yr * yr + yi * yi;
-            sre += xr * yr + xi * yi;
-            sim += xi * yr - xr * yi;
+    const uint8_t *v = volt + (int64_t)c * P * A * VB;
+    for (int tb = t0; tb < t1; tb += U) {
+        uint32_t rx[U], ry[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const uint8_t *vt = v + (int64_t)min(tb + k, t1 - 1) * volt_t_stride;
+            rx[k] = volt_raw(vt, a, VB);
+            ry[k] = P == 2 ? volt_raw(vt, (int64_t)A + a, VB) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            // samples past the chunk (clamped loads) count as zero
+            const bool in = tb + k < t1;
+            const int2 x = volt_dec(rx[k], VB);
+            const int xr = in ? x.x : 0, xi = in ? x.y : 0;
+            sxx += xr * xr + xi * xi;
+            if (P == 2) {
+                const int2 y = volt_dec(ry[k], VB);
+                const int yr = in ? y.x : 0, yi = in ? y.y : 0;
+                syy += yr * yr + yi * yi;
+                sre += xr * yr + xi * yi;
+                sim += xi * yr - xr * yi;
+            }
         }
     }
     constexpr int NPROD = P == 2 ? 4 : 1;
@@ -1475,12 +1489,15 @@ epic_status autos_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, i
     const int t_chunk = 64;
     dim3 grid((p->A + 255) / 256, p->C, (n_time + t_chunk - 1) / t_chunk);
     if (grid.z > 65535) return fail(EPIC_ERR_ARG, "n_time too large for one call");
-    if (p->P == 2)
-        hipLaunchKernelGGL(k_autos<2>, grid, dim3(256), 0, s, d_volt, vstride, p->A, n_time,
-                           t_chunk, p->vb, acc->d_autos.as<int32_t>());
-    else
-        hipLaunchKernelGGL(k_autos<1>, grid, dim3(256), 0, s, d_volt, vstride, p->A, n_time,
-                           t_chunk, p->vb, acc->d_autos.as<int32_t>());
+#define EPIC_AUTOS(PP, VV)                                                                 \
+    hipLaunchKernelGGL((k_autos<PP, VV>), grid, dim3(256), 0, s, d_volt, vstride, p->A, n_time, \
+                       t_chunk, acc->d_autos.as<int32_t>())
+    if (p->P == 2) {
+        if (p->vb == 2) EPIC_AUTOS(2, 2); else EPIC_AUTOS(2, 1);
+    } else {
+        if (p->vb == 2) EPIC_AUTOS(1, 2); else EPIC_AUTOS(1, 1);
+    }
+#undef EPIC_AUTOS
     EPIC_HIP(hipGetLastError());
     return EPIC_OK;
 }
