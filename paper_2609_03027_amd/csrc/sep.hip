@@ -69,6 +69,12 @@ __device__ __forceinline__ sf4 mma(uint4 a, uint4 b, sf4 c) {
                                                       __builtin_bit_cast(sb8, b), c, 0, 0, 0);
 }
 
+// A lane's gather entries held in registers (passed by value so that the
+// compiler keeps them in registers).
+template <int GB> struct EntryBatch {
+    uint4 e[GB];
+};
+
 struct SepItem {
     int32_t c;
     int32_t n_iter;     // gather iterations per lane
@@ -99,7 +105,7 @@ struct SepArgs {
 // blocks (ky, re/im) w RB2W .. w RB2W + RB2W - 1 and every column (feed, kx)
 // of the tile.  HL = 1 (FP16) or 2 (BF16 hi + lo: products hi hi + hi lo +
 // lo hi).
-template <int DT, int N, int NA>
+template <int DT, int N, int NA, bool PIPE>
 __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
     using SH = SepShape<DT, N>;
     constexpr int T = SH::T, NW = SH::NW, W = SH::W;
@@ -117,10 +123,13 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
     constexpr int GPLANE = NA * GP;          // one (feed, re/im) plane
     constexpr int KP = 2 * NA + 8;           // H column pitch
     static_assert(RB2W >= 1 && RB1W >= 1 && NW % NCB == 0, "grid sides");
+    // PIPE: two of each buffer, one sample's gather, another's step 1 and a
+    // third's step 2 between consecutive barriers
+    constexpr int NB = PIPE ? 2 : 1;
     extern __shared__ float4 smem[];
-    float4 *stage = smem;                                            // [astage]
-    uint16_t *grid = reinterpret_cast<uint16_t *>(smem + a.astage);  // [HL][2][2][NA][GP]
-    uint16_t *hbuf = grid + HL * 4 * GPLANE;                         // [HL][2 W][KP]
+    float4 *stage0 = smem;                                                  // [NB][astage]
+    uint16_t *grid0 = reinterpret_cast<uint16_t *>(smem + NB * a.astage);   // [NB][HL][2][2][NA][GP]
+    uint16_t *hbuf0 = grid0 + NB * HL * 4 * GPLANE;                         // [NB][HL][2 W][KP]
 
     const int64_t L = (int64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
     if (L >= a.total) return;
@@ -150,7 +159,7 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
             for (int s = 0; s < KS; ++s)
                 a2[h][r][s] = a.fy[(((int64_t)h * RB2 + wave * RB2W + r) * KS + s) * 64 + lane];
     }
-    for (int i = tid; i < HL * 4 * GPLANE; i += T) grid[i] = 0;   // cells without taps stay 0
+    for (int i = tid; i < NB * HL * 4 * GPLANE; i += T) grid0[i] = 0;   // cells without taps stay 0
 
     float sum[RB2W][NHX][2][4];
 #pragma unroll
@@ -176,14 +185,14 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
     // (FP16 only: the BF16 hi + lo form has no registers to spare)
     constexpr int GB = 8;
     const bool held = HL == 1 && it.n_iter <= GB;
-    uint4 eh[HL == 1 ? GB : 1];
-    if (HL == 1) {
+    EntryBatch<GB> eh{};
+    if (HL == 1 && held) {
 #pragma unroll
-        for (int k = 0; k < GB; ++k)
-            eh[k] = held ? ent[(int64_t)min(k, it.n_iter - 1) * T] : make_uint4(0u, 0u, 0u, 0u);
+        for (int k = 0; k < GB; ++k) eh.e[k] = ent[(int64_t)min(k, it.n_iter - 1) * T];
     }
-    for (int t = t_begin; t < t_stop; ++t) {
-        // stage this sample's voltages (both feeds) as float4
+    // phases of one sample: stage its voltages, gather its grid, step 1
+    // (grid -> H), step 2 (H -> E, products into the sums)
+    auto stage_t = [&](int t, float4 *stage) {
         const uint8_t *vt = vc + (int64_t)t * a.vstride;
         if (tid < a.A) {
             const int2 x = volt_dec(rx, a.vb), y = volt_dec(ry, a.vb);
@@ -193,23 +202,26 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
             const int2 x = volt_at(vt, e, a.vb), y = volt_at(vt, (int64_t)a.A + e, a.vb);
             stage[e] = make_float4((float)x.x, (float)x.y, (float)y.x, (float)y.y);
         }
-        __syncthreads();
-        if (t + 1 < t_stop && tid < a.A) {
-            const uint8_t *vn = vt + a.vstride;
+    };
+    auto fetch_t = [&](int t) {   // the raw bytes of sample t, into rx / ry
+        if (t < t_stop && tid < a.A) {
+            const uint8_t *vn = vc + (int64_t)t * a.vstride;
             rx = volt_raw(vn, tid, a.vb);
             ry = volt_raw(vn, (int64_t)a.A + tid, a.vb);
         }
-        // gather: each lane sums whole cells, conj(W) 2^-sa E, and writes each
-        // once; entries are loaded eight at a time (indices clamped into the
-        // list, the surplus not applied) so a lane waits for one L2 round
-        // trip per eight entries
+    };
+    // gather: each lane sums whole cells, conj(W) 2^-sa E, and writes each
+    // once; entries are loaded eight at a time (indices clamped into the
+    // list, the surplus not applied) so a lane waits for one L2 round trip
+    // per eight entries
+    auto gather_t = [&](const float4 *stage, uint16_t *grid, const EntryBatch<GB> hb) {
         {
             float sxr = 0.f, sxi = 0.f, syr = 0.f, syi = 0.f;
             for (int i0 = 0; i0 < it.n_iter; i0 += GB) {
                 uint4 eb[GB];
                 if (held) {
 #pragma unroll
-                    for (int k = 0; k < GB; ++k) eb[k] = eh[k];
+                    for (int k = 0; k < GB; ++k) eb[k] = hb.e[k];
                 } else {
 #pragma unroll
                     for (int k = 0; k < GB; ++k)
@@ -244,7 +256,8 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
                 }
             }
         }
-        __syncthreads();
+    };
+    auto step1_t = [&](const uint16_t *grid, uint16_t *hbuf) {
         // step 1: this wave's row blocks (ri, p, u) of its column block
 #pragma unroll
         for (int r = 0; r < RB1W; ++r) {
@@ -305,7 +318,8 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
             // one row block's operands live at a time
             __builtin_amdgcn_sched_barrier(0);
         }
-        __syncthreads();
+    };
+    auto step2_t = [&](const uint16_t *hbuf) {
         // step 2: rows (ky, re/im) of this wave; columns (feed, kx) of the tile;
         // x and y blocks of one kx block give both feeds of the same pixels
 #pragma unroll
@@ -351,7 +365,39 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
             // one column block's operands live at a time
             __builtin_amdgcn_sched_barrier(0);
         }
-        // the next sample's staging is ordered after step 2 by its barrier
+    };
+    if (!PIPE) {
+        for (int t = t_begin; t < t_stop; ++t) {
+            stage_t(t, stage0);
+            __syncthreads();
+            fetch_t(t + 1);
+            gather_t(stage0, grid0, eh);
+            __syncthreads();
+            step1_t(grid0, hbuf0);
+            __syncthreads();
+            step2_t(hbuf0);
+            // the next sample's staging is ordered after step 2 by its barrier
+        }
+    } else if (t_begin < t_stop) {
+        // iteration i: stage i + 1, gather i, step 1 of i - 1, step 2 of i - 2
+        // (sample j uses buffer (j - t_begin) & 1 of each kind; one barrier
+        // per iteration orders every write before the next iteration's read
+        // and every read before the write two iterations on)
+        stage_t(t_begin, stage0);
+        fetch_t(t_begin + 1);
+        __syncthreads();
+        for (int i = t_begin; i < t_stop + 2; ++i) {
+            const int b = (i - t_begin) & 1;
+            if (i + 1 < t_stop) {
+                stage_t(i + 1, stage0 + (b ^ 1) * a.astage);
+                fetch_t(i + 2);
+            }
+            if (i < t_stop) gather_t(stage0 + b * a.astage, grid0 + b * (HL * 4 * GPLANE), eh);
+            if (i - 1 >= t_begin && i - 1 < t_stop)
+                step1_t(grid0 + (b ^ 1) * (HL * 4 * GPLANE), hbuf0 + (b ^ 1) * (HL * 2 * W * KP));
+            if (i - 2 >= t_begin) step2_t(hbuf0 + b * (HL * 2 * W * KP));
+            __syncthreads();
+        }
     }
     if (t_begin >= t_stop) return;
     const int64_t plane = (int64_t)N * N;
@@ -387,24 +433,26 @@ __global__ void k_sep_reduce(const float *__restrict__ part, int64_t stride, int
     acc[i] = v;
 }
 
-template <int DT, int N, int NA>
+template <int DT, int N, int NA, bool PIPE>
 const void *sep_kernel() {
-    return reinterpret_cast<const void *>(k_sep<DT, N, NA>);
+    return reinterpret_cast<const void *>(k_sep<DT, N, NA, PIPE>);
 }
 
-const void *pick_kernel(int dt, int N, int NA) {
-#define EPIC_SEP(D, NN, AA) \
-    if (dt == D && N == NN && NA == AA) return sep_kernel<D, NN, AA>();
-    EPIC_SEP(EPIC_F16_MFMA, 32, 32)
-    EPIC_SEP(EPIC_F16_MFMA, 64, 32)
-    EPIC_SEP(EPIC_F16_MFMA, 64, 64)
-    EPIC_SEP(EPIC_F16_MFMA, 128, 32)
-    EPIC_SEP(EPIC_F16_MFMA, 128, 64)
-    EPIC_SEP(EPIC_BF16X2_MFMA, 32, 32)
-    EPIC_SEP(EPIC_BF16X2_MFMA, 64, 32)
-    EPIC_SEP(EPIC_BF16X2_MFMA, 64, 64)
-    EPIC_SEP(EPIC_BF16X2_MFMA, 128, 32)
-    EPIC_SEP(EPIC_BF16X2_MFMA, 128, 64)
+const void *pick_kernel(int dt, int N, int NA, bool pipe) {
+#define EPIC_SEP(D, NN, AA, PP) \
+    if (dt == D && N == NN && NA == AA && pipe == PP) return sep_kernel<D, NN, AA, PP>();
+    EPIC_SEP(EPIC_F16_MFMA, 32, 32, false)
+    EPIC_SEP(EPIC_F16_MFMA, 64, 32, false)
+    EPIC_SEP(EPIC_F16_MFMA, 64, 64, false)
+    EPIC_SEP(EPIC_F16_MFMA, 128, 32, false)
+    EPIC_SEP(EPIC_F16_MFMA, 128, 64, false)
+    EPIC_SEP(EPIC_F16_MFMA, 128, 32, true)
+    EPIC_SEP(EPIC_F16_MFMA, 128, 64, true)
+    EPIC_SEP(EPIC_BF16X2_MFMA, 32, 32, false)
+    EPIC_SEP(EPIC_BF16X2_MFMA, 64, 32, false)
+    EPIC_SEP(EPIC_BF16X2_MFMA, 64, 64, false)
+    EPIC_SEP(EPIC_BF16X2_MFMA, 128, 32, false)
+    EPIC_SEP(EPIC_BF16X2_MFMA, 128, 64, false)
 #undef EPIC_SEP
     return nullptr;
 }
@@ -426,11 +474,19 @@ SepDims sep_dims(int dt, int N) {
 // staged elements: A rounded up to a multiple of 64
 int sep_astage(int A) { return (A + 63) / 64 * 64; }
 
-size_t sep_lds(int dt, int N, int NA, int A) {
+size_t sep_lds(int dt, int N, int NA, int A, bool pipe) {
     const size_t hl = dt == EPIC_BF16X2_MFMA ? 2 : 1;
     const size_t W = (size_t)sep_dims(dt, N).W;
-    return sizeof(float4) * (size_t)sep_astage(A) + sizeof(uint16_t) * hl * 4 * NA * (NA + 8) +
-           sizeof(uint16_t) * hl * 2 * W * (2 * NA + 8);
+    return (pipe ? 2 : 1) *
+           (sizeof(float4) * (size_t)sep_astage(A) + sizeof(uint16_t) * hl * 4 * NA * (NA + 8) +
+            sizeof(uint16_t) * hl * 2 * W * (2 * NA + 8));
+}
+
+// The one-barrier pipeline (two of each buffer) for FP16 on 128 grids,
+// where a workgroup has its CU to itself anyway, when the doubled buffers
+// fit the LDS.
+bool sep_pipe(int dt, int N, int NA, int A) {
+    return dt == EPIC_F16_MFMA && N == 128 && sep_lds(dt, N, NA, A, true) <= 160 * 1024;
 }
 
 // 16-bit rounding of one value into the hi [, lo] fragment tables
@@ -477,8 +533,10 @@ epic_status sep_build(epic_plan p, const std::vector<int> &j0, const std::vector
     sp.N = N;
     sp.Na = NA;
     sp.lo = lo;
-    if (!pick_kernel(dt, N, NA)) return fail(EPIC_ERR_UNSUPPORTED, "separable DFT-GEMM shape");
-    if (sep_lds(dt, N, NA, A) > 160 * 1024)
+    const bool pipe = sep_pipe(dt, N, NA, A);
+    if (!pick_kernel(dt, N, NA, pipe))
+        return fail(EPIC_ERR_UNSUPPORTED, "separable DFT-GEMM shape");
+    if (sep_lds(dt, N, NA, A, pipe) > 160 * 1024)
         return fail(EPIC_ERR_UNSUPPORTED, "separable DFT-GEMM LDS");
     const SepDims dims = sep_dims(dt, N);
 
@@ -601,7 +659,7 @@ epic_status sep_build(epic_plan p, const std::vector<int> &j0, const std::vector
     // LDS allows (at most two), at most 64 slices
     const int wgs = C * (N / dims.W);
     const int per_cu =
-        std::max<int>(1, std::min<int>(2, (160 * 1024) / (int)sep_lds(dt, N, NA, A)));
+        std::max<int>(1, std::min<int>(2, (160 * 1024) / (int)sep_lds(dt, N, NA, A, pipe)));
     const int want = 256 * per_cu;
     sp.t_slices = std::max(1, std::min(64, (want + wgs - 1) / wgs));
     sp.part_floats = sp.t_slices > 1 ? p->image_floats : 0;
@@ -613,9 +671,10 @@ epic_status sep_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int
     const SepPlan &sp = p->sep;
     const int dt = p->precision;
     const int HL = dt == EPIC_BF16X2_MFMA ? 2 : 1;
-    const void *kern = pick_kernel(dt, sp.N, sp.Na);
+    const bool pipe = sep_pipe(dt, sp.N, sp.Na, p->A);
+    const void *kern = pick_kernel(dt, sp.N, sp.Na, pipe);
     if (!kern) return fail(EPIC_ERR_UNSUPPORTED, "separable DFT-GEMM shape");
-    const size_t lds = sep_lds(dt, sp.N, sp.Na, p->A);
+    const size_t lds = sep_lds(dt, sp.N, sp.Na, p->A, pipe);
     const SepDims dims = sep_dims(dt, sp.N);
     epic_status st = lds_ready(kern, lds);
     if (st) return st;
