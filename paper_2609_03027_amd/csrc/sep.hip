@@ -43,6 +43,9 @@ template <int DT, int N> struct SepShape {
     static constexpr int NW = WIDE ? 8 : 4;
     static constexpr int W = WIDE ? 64 : 32;
     static constexpr int T = 64 * NW;
+    // step-1 column blocks a wave takes (each grid fragment it loads then
+    // serves both): two in FP16; BF16 hi + lo has no registers to spare
+    static constexpr int CBW = DT == EPIC_F16_MFMA ? 2 : 1;
 };
 
 __device__ __forceinline__ uint16_t f16_bits(float x) {
@@ -100,8 +103,8 @@ struct SepArgs {
 };
 
 // One workgroup per (time slice, channel, W-column kx tile).  Step 1: wave w
-// owns the 16-column block w % (W / 16) of the tile and every (NW / (W / 16))-th
-// row block (re/im, feed, u) from w / (W / 16); step 2: wave w owns the row
+// owns CBW adjacent 16-column blocks of the tile (group w % NCG) and every
+// (NW / NCG)-th row block (re/im, feed, u) from w / NCG; step 2: wave w owns the row
 // blocks (ky, re/im) w RB2W .. w RB2W + RB2W - 1 and every column (feed, kx)
 // of the tile.  HL = 1 (FP16) or 2 (BF16 hi + lo: products hi hi + hi lo +
 // lo hi).
@@ -113,8 +116,10 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
     constexpr int KS = 2 * NA / 32;          // k steps (K = 2 NA)
     constexpr int NT = N / W;                // kx tiles
     constexpr int NCB = W / 16;              // step-1 column blocks of a tile
+    constexpr int CBW = SH::CBW;             // of which a wave takes CBW adjacent ones
+    constexpr int NCG = NCB / CBW;           // column-block groups
     constexpr int NRB1 = NA / 4;             // step-1 row blocks (4 NA rows)
-    constexpr int RSTEP = NW / NCB;          // waves sharing a column block
+    constexpr int RSTEP = NW / NCG;          // waves sharing a column-block group
     constexpr int RB1W = NRB1 / RSTEP;       // step-1 row blocks per wave
     constexpr int RB2 = N / 8;               // step-2 row blocks (2 N rows)
     constexpr int RB2W = RB2 / NW;           // per wave
@@ -122,7 +127,7 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
     constexpr int GP = NA + 8;               // grid row pitch (16-bit values)
     constexpr int GPLANE = NA * GP;          // one (feed, re/im) plane
     constexpr int KP = 2 * NA + 8;           // H column pitch
-    static_assert(RB2W >= 1 && RB1W >= 1 && NW % NCB == 0, "grid sides");
+    static_assert(RB2W >= 1 && RB1W >= 1 && NCB % CBW == 0 && NW % NCG == 0, "grid sides");
     // PIPE: two of each buffer, one sample's gather, another's step 1 and a
     // third's step 2 between consecutive barriers
     constexpr int NB = PIPE ? 2 : 1;
@@ -143,16 +148,19 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, col = lane & 15;
-    const int cb1 = wave % NCB, rw1 = wave / NCB;
+    const int cg1 = wave % NCG, rw1 = wave / NCG;
 
     // constants: step-1 B (Fa^T columns of this wave's block) and this
     // wave's step-2 A rows
-    uint4 b1[HL][KS], a2[HL][RB2W][KS];
+    uint4 b1[HL][CBW][KS], a2[HL][RB2W][KS];
 #pragma unroll
     for (int h = 0; h < HL; ++h) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
-            b1[h][s] = a.fx[(((int64_t)h * (N / 16) + tile * NCB + cb1) * KS + s) * 64 + lane];
+        for (int c = 0; c < CBW; ++c)
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+                b1[h][c][s] = a.fx[(((int64_t)h * (N / 16) + tile * NCB + cg1 * CBW + c) * KS + s) *
+                                       64 + lane];
 #pragma unroll
         for (int r = 0; r < RB2W; ++r)
 #pragma unroll
@@ -258,7 +266,7 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
         }
     };
     auto step1_t = [&](const uint16_t *grid, uint16_t *hbuf) {
-        // step 1: this wave's row blocks (ri, p, u) of its column block
+        // step 1: this wave's row blocks (ri, p, u) of its column blocks
 #pragma unroll
         for (int r = 0; r < RB1W; ++r) {
             const int rb = rw1 + r * RSTEP;            // 0 .. NA / 4 - 1
@@ -287,34 +295,37 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
                     ga[h][s] = x;
                 }
             }
-            sf4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                d = mma<DT>(ga[0][s], b1[0][s], d);
-                if (HL == 2) {
-                    d = mma<DT>(ga[0][s], b1[HL - 1][s], d);
-                    d = mma<DT>(ga[HL - 1][s], b1[0][s], d);
+            for (int c = 0; c < CBW; ++c) {
+                sf4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    d = mma<DT>(ga[0][s], b1[0][c][s], d);
+                    if (HL == 2) {
+                        d = mma<DT>(ga[0][s], b1[HL - 1][c][s], d);
+                        d = mma<DT>(ga[HL - 1][s], b1[0][c][s], d);
+                    }
                 }
-            }
-            // rows 4 g + i: u = ublk 16 + 4 g + i of column kx = cb1 16 + col
-            const int n2 = p * W + cb1 * 16 + col;
-            const int k2 = ri * NA + ublk * 16 + 4 * g;
-            uint16_t hv[HL][4];
+                // rows 4 g + i: u = ublk 16 + 4 g + i of column kx = cb 16 + col
+                const int n2 = p * W + (cg1 * CBW + c) * 16 + col;
+                const int k2 = ri * NA + ublk * 16 + 4 * g;
+                uint16_t hv[HL][4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float x = d[i] * a.h_scale;
-                if (HL == 1) {
-                    hv[0][i] = f16_bits(x);
-                } else {
-                    hv[0][i] = bf16_bits(x);
-                    hv[HL - 1][i] = bf16_bits(x - bf16_val(hv[0][i]));
+                for (int i = 0; i < 4; ++i) {
+                    const float x = d[i] * a.h_scale;
+                    if (HL == 1) {
+                        hv[0][i] = f16_bits(x);
+                    } else {
+                        hv[0][i] = bf16_bits(x);
+                        hv[HL - 1][i] = bf16_bits(x - bf16_val(hv[0][i]));
+                    }
                 }
-            }
 #pragma unroll
-            for (int h = 0; h < HL; ++h)
-                *reinterpret_cast<uint2 *>(hbuf + (h * 2 * W + n2) * KP + k2) =
-                    make_uint2((uint32_t)hv[h][0] | (uint32_t)hv[h][1] << 16,
-                               (uint32_t)hv[h][2] | (uint32_t)hv[h][3] << 16);
+                for (int h = 0; h < HL; ++h)
+                    *reinterpret_cast<uint2 *>(hbuf + (h * 2 * W + n2) * KP + k2) =
+                        make_uint2((uint32_t)hv[h][0] | (uint32_t)hv[h][1] << 16,
+                                   (uint32_t)hv[h][2] | (uint32_t)hv[h][3] << 16);
+            }
             // one row block's operands live at a time
             __builtin_amdgcn_sched_barrier(0);
         }
