@@ -46,6 +46,12 @@ template <int DT, int N> struct SepShape {
     // step-1 column blocks a wave takes (each grid fragment it loads then
     // serves both): two in FP16; BF16 hi + lo has no registers to spare
     static constexpr int CBW = DT == EPIC_F16_MFMA ? 2 : 1;
+    // step 2: the tile's column-block pairs (x, y) are split into HXG groups,
+    // a wave taking one group and RB2 HXG / NW row blocks (each H fragment
+    // it loads then serves more rows); FP16 on 128 grids uses two groups and
+    // gives up the register-held gather lists for the registers this takes
+    static constexpr int HXG = WIDE && DT == EPIC_F16_MFMA ? 2 : 1;
+    static constexpr bool HOLD = DT == EPIC_F16_MFMA && HXG == 1;
 };
 
 __device__ __forceinline__ uint16_t f16_bits(float x) {
@@ -104,9 +110,9 @@ struct SepArgs {
 
 // One workgroup per (time slice, channel, W-column kx tile).  Step 1: wave w
 // owns CBW adjacent 16-column blocks of the tile (group w % NCG) and every
-// (NW / NCG)-th row block (re/im, feed, u) from w / NCG; step 2: wave w owns the row
-// blocks (ky, re/im) w RB2W .. w RB2W + RB2W - 1 and every column (feed, kx)
-// of the tile.  HL = 1 (FP16) or 2 (BF16 hi + lo: products hi hi + hi lo +
+// (NW / NCG)-th row block (re/im, feed, u) from w / NCG; step 2: wave w owns
+// the row blocks (ky, re/im) (w / HXG) RB2W .. + RB2W - 1 and the columns
+// (feed, kx) of column-pair group w % HXG.  HL = 1 (FP16) or 2 (BF16 hi + lo: products hi hi + hi lo +
 // lo hi).
 template <int DT, int N, int NA, bool PIPE>
 __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
@@ -122,12 +128,14 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
     constexpr int RSTEP = NW / NCG;          // waves sharing a column-block group
     constexpr int RB1W = NRB1 / RSTEP;       // step-1 row blocks per wave
     constexpr int RB2 = N / 8;               // step-2 row blocks (2 N rows)
-    constexpr int RB2W = RB2 / NW;           // per wave
-    constexpr int NHX = W / 16;              // step-2 column blocks per feed
+    constexpr int HXG = SH::HXG;             // step-2 column-pair groups
+    constexpr int RB2W = RB2 * HXG / NW;     // step-2 row blocks per wave
+    constexpr int NHX = W / 16 / HXG;        // step-2 column blocks per feed and wave
     constexpr int GP = NA + 8;               // grid row pitch (16-bit values)
     constexpr int GPLANE = NA * GP;          // one (feed, re/im) plane
     constexpr int KP = 2 * NA + 8;           // H column pitch
-    static_assert(RB2W >= 1 && RB1W >= 1 && NCB % CBW == 0 && NW % NCG == 0, "grid sides");
+    static_assert(RB2W >= 1 && RB1W >= 1 && NCB % CBW == 0 && NW % NCG == 0 && NHX >= 1 &&
+                      NW % HXG == 0, "grid sides");
     // PIPE: two of each buffer, one sample's gather, another's step 1 and a
     // third's step 2 between consecutive barriers
     constexpr int NB = PIPE ? 2 : 1;
@@ -149,6 +157,7 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, col = lane & 15;
     const int cg1 = wave % NCG, rw1 = wave / NCG;
+    const int hg2 = wave % HXG, rg2 = wave / HXG;   // step-2 column group, row group
 
     // constants: step-1 B (Fa^T columns of this wave's block) and this
     // wave's step-2 A rows
@@ -165,7 +174,7 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
         for (int r = 0; r < RB2W; ++r)
 #pragma unroll
             for (int s = 0; s < KS; ++s)
-                a2[h][r][s] = a.fy[(((int64_t)h * RB2 + wave * RB2W + r) * KS + s) * 64 + lane];
+                a2[h][r][s] = a.fy[(((int64_t)h * RB2 + rg2 * RB2W + r) * KS + s) * 64 + lane];
     }
     for (int i = tid; i < NB * HL * 4 * GPLANE; i += T) grid0[i] = 0;   // cells without taps stay 0
 
@@ -192,9 +201,9 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
     // a lane list of at most GB entries is loaded once for all the samples
     // (FP16 only: the BF16 hi + lo form has no registers to spare)
     constexpr int GB = 8;
-    const bool held = HL == 1 && it.n_iter <= GB;
+    const bool held = SH::HOLD && it.n_iter <= GB;
     EntryBatch<GB> eh{};
-    if (HL == 1 && held) {
+    if (SH::HOLD && held) {
 #pragma unroll
         for (int k = 0; k < GB; ++k) eh.e[k] = ent[(int64_t)min(k, it.n_iter - 1) * T];
     }
@@ -338,7 +347,7 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
             sf4 d[2][RB2W];
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                const int n2 = p * W + hx * 16 + col;
+                const int n2 = p * W + (hg2 * NHX + hx) * 16 + col;
                 uint4 bq[HL][KS];
 #pragma unroll
                 for (int s = 0; s < KS; ++s)
@@ -420,8 +429,8 @@ __global__ __launch_bounds__((SepShape<DT, N>::T)) void k_sep(const SepArgs a) {
         for (int hx = 0; hx < NHX; ++hx)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const int ky = (wave * RB2W + r) * 8 + 2 * g + q;
-                const int kx = tile * W + hx * 16 + col;
+                const int ky = (rg2 * RB2W + r) * 8 + 2 * g + q;
+                const int kx = tile * W + (hg2 * NHX + hx) * 16 + col;
                 const int64_t pix = (int64_t)ky * N + kx;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
