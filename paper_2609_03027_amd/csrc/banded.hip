@@ -466,6 +466,27 @@ constexpr int cols_pitch() {
     return pad + ((want - pad % 16) % 16 + 16) % 16;
 }
 
+// One batch of UN gather entries of a row-pass lane (iterations past n_iter
+// re-read the last one and become no-op padding entries aimed at LDS slot
+// spare) and the voltage bytes they name.
+template <int UN, int P, int VB>
+__device__ __forceinline__ void pw_load(uint4 (&e)[UN], uint32_t (&bx)[UN], uint32_t (&by)[UN],
+                                        const uint4 *__restrict__ ent, int i0, int n_iter, int T,
+                                        int tid, const uint8_t *vx, int A, int spare) {
+#pragma unroll
+    for (int k = 0; k < UN; ++k)
+        e[k] = ent[(uint32_t)(min(i0 + k, n_iter - 1) * T + tid)];
+#pragma unroll
+    for (int k = 0; k < UN; ++k)
+        if (i0 + k >= n_iter) e[k] = make_uint4(0u, (uint32_t)spare, 0u, 0u);
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+        const uint32_t a = e[k].x & 0x7fffffffu;
+        bx[k] = vraw<VB>(vx, a);
+        by[k] = P == 2 ? vraw<VB>(vx, (uint32_t)A + a) : 0u;
+    }
+}
+
 // Pass 1.  One workgroup per (item, sample): thread (l, j) = (tid / L,
 // tid % L) owns line l of the band.  (A variant that looped each workgroup
 // over a slice of samples with its gather list in registers measured slower:
@@ -494,34 +515,31 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     const BandChan ch = chans[it.chan];
     const int tid = threadIdx.x;
     const int l = tid / L, j = tid % L;
-    for (int n = tid; n < N; n += T) twl[n] = tw[n];
+    // gather: each lane sums its own cells; every entry stores the running
+    // sum to its cell (the last entry of a cell leaves the full sum) and the
+    // last one restarts it, so the loop has no branches; padding entries
+    // point at the spare LDS slot after the band.  The first batch of
+    // entries and voltages is loaded before the barrier that publishes the
+    // zeroed band, so its two dependent loads overlap the fill and the
+    // barrier.
+    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * VB;
+    const uint4 *ent = entries + it.entry_off;
+    const int n_iter = it.n_iter;
+    constexpr int NTW = N / T;
+    static_assert(N % T == 0, "row pass: twiddles fill whole thread strides");
+    float2 twr[NTW];
+#pragma unroll
+    for (int k = 0; k < NTW; ++k) twr[k] = tw[tid + k * T];
+    uint4 e[UN];
+    uint32_t bx[UN], by[UN];
+    if (n_iter > 0) pw_load<UN, P, VB>(e, bx, by, ent, 0, n_iter, T, tid, vx, A, BL * N);
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int k = 0; k < BL * N / T; ++k) lds[tid + k * T] = zero;
     __syncthreads();
-    // gather: each lane sums its own cells; every entry stores the running
-    // sum to its cell (the last entry of a cell leaves the full sum) and the
-    // last one restarts it, so the loop has no branches; padding entries
-    // point at the spare LDS slot after the band
-    const uint8_t *vx = volt + (int64_t)t * vstride + (int64_t)ch.c * P * A * VB;
-    const uint4 *ent = entries + it.entry_off;
     float4 s = zero;
-    for (int i0 = 0; i0 < it.n_iter; i0 += UN) {
-        // iterations past n_iter re-read the last one and become no-ops
-        uint4 e[UN];
-#pragma unroll
-        for (int k = 0; k < UN; ++k)
-            e[k] = ent[(uint32_t)(min(i0 + k, it.n_iter - 1) * T + tid)];
-#pragma unroll
-        for (int k = 0; k < UN; ++k)
-            if (i0 + k >= it.n_iter) e[k] = make_uint4(0u, (uint32_t)(BL * N), 0u, 0u);
-        uint32_t bx[UN], by[UN];
-#pragma unroll
-        for (int k = 0; k < UN; ++k) {
-            const uint32_t a = e[k].x & 0x7fffffffu;
-            bx[k] = vraw<VB>(vx, a);
-            by[k] = P == 2 ? vraw<VB>(vx, (uint32_t)A + a) : 0u;
-        }
+    for (int i0 = 0; i0 < n_iter; i0 += UN) {
+        if (i0) pw_load<UN, P, VB>(e, bx, by, ent, i0, n_iter, T, tid, vx, A, BL * N);
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
             const float wr = __builtin_bit_cast(float, e[k].z);
@@ -540,6 +558,10 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
             if (e[k].x & 0x80000000u) s = zero;
         }
     }
+    // twiddles (first read after two more barriers) stored once every load
+    // has been waited for
+#pragma unroll
+    for (int k = 0; k < NTW; ++k) twl[tid + k * T] = twr[k];
     __syncthreads();
     // pass 0 from the gathered band (plain pitch N), then the rest in LDS
     float4 v[R];
