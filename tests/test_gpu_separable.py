@@ -1,8 +1,8 @@
 """Separable DFT-GEMM (EPIC_XFORM_DFT_SEPARABLE: E = Fa G Fa^T with F pruned
 to the gridded region, FP16 or BF16 hi + lo operands on the matrix cores,
 FP32 accumulation) against the FP64 oracle at its precision's bound: the
-LWA-like 128^2 grid with its 64^2 region, a 32^2 region of a 128^2 grid,
-whole 32^2 and 64^2 grids, 4- and
+LWA-like 128^2 grid with its 64^2 region (also with 1024 elements, the
+form's limit), a 32^2 region of a 128^2 grid, whole 32^2 and 64^2 grids, 4- and
 8-bit voltages, several calls and time slices, graph replays, and the shapes
 it refuses."""
 import dataclasses
@@ -71,6 +71,23 @@ def test_32_region_of_a_128_grid(prec):
     _say(f"case separable {NAMES[prec]}: 16 elements, 128^2 grid, 32^2 region, 20 samples")
     got = _run(wl, pos, volt, prec, calls=2)
     _check(got, oracle_images(volt, pos, wl, range(1)), NAMES[prec], "tiny2-128-32")
+
+
+@pytest.mark.parametrize("prec", [1, 3])
+def test_most_elements_on_a_128_grid(prec):
+    """1024 elements (the form's limit) in the LWA disc: the largest voltage
+    stage and the longest gather lists; in FP16 the doubled buffers of the
+    one-barrier pipeline no longer fit the LDS, so the single-buffer kernel
+    runs, and in BF16 hi + lo the LDS is 156 KB."""
+    full = dataclasses.replace(synth.workload("lwa"), n_ant=1024, seed=1091)
+    chans = [0, 127]
+    wl = full.subset(chans).with_time(8)
+    pos = synth.antenna_layout(full)
+    volt = synth.voltages(full.with_time(8), pos, chans=chans)
+    _say(f"case separable {NAMES[prec]}: 1024 elements, LWA channels {chans}, 128^2 grid, "
+         "8 samples")
+    got = _run(wl, pos, volt, prec, calls=2)
+    _check(got, oracle_images(volt, pos, wl, range(2)), NAMES[prec], "lwa-1024")
 
 
 @pytest.mark.parametrize("prec", [1, 3])
