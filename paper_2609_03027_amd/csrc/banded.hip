@@ -809,32 +809,29 @@ __device__ __forceinline__ _Float16 h_hi(uint32_t v) {
 
 // Pass 1, FP16 four-step.  Same items, gather and launch shape as
 // k_band_rows_pw<16, 2, P> (128 threads, 8-row bands), but the band is kept
-// in LDS as FP16 cells: each running FP32 cell sum (of weights that carry
-// 2^-si) is rounded at its store (the last store of a cell leaves
-// fl16(2^-si x the full sum), exactly the step-1 operand), which halves the
-// LDS per workgroup and doubles the workgroups a CU holds.  Wave w then
-// transforms rows w, w + 2, ... of the band and writes them to the scratch
-// as FP16 cells (uint2 per cell, cell index as in the FP32 scratch).  A
+// in LDS as FP16 cells: each cell's running sum (half pairs, of weights
+// that carry 2^-si) is stored at every tap (the last store of a cell leaves
+// the step-1 operand), which halves the LDS per workgroup and doubles the
+// workgroups a CU holds.  Wave w then transforms rows w, w + 2, ... of the
+// band and writes them to the scratch as FP16 cells (uint2 per cell, cell
+// index as in the FP32 scratch).  A
 // workgroup runs MF_TS consecutive samples of its band; a lane list of at
 // most MF_UN entries is loaded once for all of them, and the next sample's
 // voltage codes are loaded while the current sample is gathered.
 constexpr int MF_TS = 16;  // samples per row-pass workgroup
 constexpr int MF_UN = 16;  // gather entries a lane holds in registers
 
-// One gather tap: s += 2^-si conj(W) (-1)^(jx+jy) E for both feeds (FMA
-// chains; the plan folds the exact power of two 2^-si into the weights), v
-// being the tap's staged voltages; then the cell's running sum is stored
-// rounded to FP16, and a cell's last tap starts the next cell's sum at zero.
-// A padding entry (weights 0, cell = the spare slot after the band) changes
-// nothing.
 // One gather tap of the FP16 row pass: the cell's running sums (x and y
-// feeds, each a (re, im) half pair) take conj(W) E with two packed FP16
-// FMAs per feed, (wr, wr) (re, im) + (-wi, wi) (im, re); the entry carries
-// those two weight pairs.  Every tap stores the running sums to its cell and
-// the cell's last tap restarts them.  (Half-precision sums add a rounding
-// per tap to the one the FP16 cell takes anyway; in a model of the
-// streaming array's gridding the image error from the cells is ~3e-6 of the
-// peak either way, far below the transform's.)
+// feeds, each a (re, im) half pair) take 2^-si conj(W) (-1)^(jx+jy) E (the
+// plan folds the sign and the exact power of two into the weights) with two
+// packed FP16 FMAs per feed, (wr, wr) (re, im) + (-wi, wi) (im, re); the
+// entry carries those two weight pairs.  A padding entry (weights 0, cell =
+// the spare slot after the band) changes nothing.  Every tap stores the
+// running sums to its cell and the cell's last tap restarts them.
+// (Half-precision sums add a rounding per tap to the one the FP16 cell
+// takes anyway; in a model of the streaming array's gridding the image
+// error from the cells is ~3e-6 of the peak either way, far below the
+// transform's.)
 template <int P>
 __device__ __forceinline__ void mf_tap(const uint4 e, const mf_h4 hv, uint2 *band16,
                                        mf_h2 &sx, mf_h2 &sy) {
