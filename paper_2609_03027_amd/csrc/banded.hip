@@ -756,8 +756,8 @@ typedef _Float16 mf_h8 __attribute__((ext_vector_type(8)));
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 
 struct MfConst {
-    mf_h8 fre;           // (Fr, -Fi)[a][4g + j], j = 0..3
-    mf_h8 fim;           // (Fi, Fr)[a][4g + j]
+    mf_h8 fre;           // (Fr, -Fi)[a][4g + j], interleaved: Fr_0, -Fi_0, Fr_1, -Fi_1, ...
+    mf_h8 fim;           // (Fi, Fr)[a][4g + j], interleaved
     float2 tw[4];        // exp(+2 pi i a (4g + i) / 256) / 16
 };
 
@@ -770,24 +770,29 @@ __device__ __forceinline__ mf_f4 mfma32(mf_h8 a, mf_h8 b, mf_f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
-// One 256-point line transform of one feed: (xr, xi) = the lane's step-1 A
-// operand, x[16 (4g + j) + a]; returns X[a + 16 (4g + i)] in (er, ei).
-__device__ __forceinline__ void mf_line(const MfConst &k, mf_h4 xr, mf_h4 xi, mf_f4 &er,
-                                        mf_f4 &ei) {
+// One 256-point line transform of one feed.  x: the lane's step-1 A operand,
+// the half pairs (re, im) of x[16 (4g + j) + a] for j = 0..3 in order: the
+// MFMA's k index runs over (j, re/im), the constant fragments take the same
+// order, and any order of k common to both operands gives the same product.
+// Returns X[a + 16 (4g + i)] in (er, ei).
+__device__ __forceinline__ void mf_line(const MfConst &k, mf_h8 x, mf_f4 &er, mf_f4 &ei) {
     const mf_f4 z = {0.f, 0.f, 0.f, 0.f};
-    const mf_h8 x = __builtin_shufflevector(xr, xi, 0, 1, 2, 3, 4, 5, 6, 7);
     const mf_f4 dr = mfma32(x, k.fre, z);
     const mf_f4 di = mfma32(x, k.fim, z);
-    mf_h4 br, bi;
+    mf_h8 y;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float2 w = k.tw[i];
-        br[i] = (_Float16)(dr[i] * w.x - di[i] * w.y);
-        bi[i] = (_Float16)(dr[i] * w.y + di[i] * w.x);
+        y[2 * i] = (_Float16)(dr[i] * w.x - di[i] * w.y);
+        y[2 * i + 1] = (_Float16)(dr[i] * w.y + di[i] * w.x);
     }
-    const mf_h8 y = __builtin_shufflevector(br, bi, 0, 1, 2, 3, 4, 5, 6, 7);
     er = mfma32(k.fre, y, z);
     ei = mfma32(k.fim, y, z);
+}
+
+// Four half pairs of one feed as a step-1 operand.
+__device__ __forceinline__ mf_h8 mf_pairs(uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3) {
+    return __builtin_bit_cast(mf_h8, make_uint4(p0, p1, p2, p3));
 }
 
 // FP16 scratch cell: both feeds, (x re, x im), (y re, y im) as half pairs.
@@ -800,12 +805,18 @@ __device__ __forceinline__ uint32_t h2bits(float a, float b) {
     h.y = (_Float16)b;
     return __builtin_bit_cast(uint32_t, h);
 }
-__device__ __forceinline__ _Float16 h_lo(uint32_t v) {
-    return __builtin_bit_cast(_Float16, (uint16_t)(v & 0xffffu));
+
+// The FP16 row band in LDS: one plane of half pairs per feed, each row of a
+// plane stored with its columns transposed, column 16 n1 + n2 at 16 n2 + n1,
+// so that the four cells a lane takes into a line transform (n1 = 4g .. 4g +
+// 3 of n2 = a) are one aligned 16-byte read, a wave's reads of a row are one
+// contiguous kilobyte, and the pairs arrive in operand order.  Plane y
+// starts MF_YB words after plane x; slot BL * N of each plane is the spare
+// cell of padding entries.
+__host__ __device__ constexpr uint32_t mf_cell(uint32_t row, uint32_t col) {
+    return row * 256u + (col & 15u) * 16u + (col >> 4);
 }
-__device__ __forceinline__ _Float16 h_hi(uint32_t v) {
-    return __builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
-}
+constexpr int MF_YB = BL * 256 + 4;   // plane y, 16-byte aligned
 
 // Pass 1, FP16 four-step.  Same items, gather and launch shape as
 // k_band_rows_pw<16, 2, P> (128 threads, 8-row bands), but the band is kept
@@ -833,7 +844,7 @@ constexpr int MF_UN = 16;  // gather entries a lane holds in registers
 // error from the cells is ~3e-6 of the peak either way, far below the
 // transform's.)
 template <int P>
-__device__ __forceinline__ void mf_tap(const uint4 e, const mf_h4 hv, uint2 *band16,
+__device__ __forceinline__ void mf_tap(const uint4 e, const mf_h4 hv, uint32_t *band,
                                        mf_h2 &sx, mf_h2 &sy) {
     const mf_h2 w1 = __builtin_bit_cast(mf_h2, e.z), w2 = __builtin_bit_cast(mf_h2, e.w);
     const mf_h2 vx = {hv.x, hv.y}, vxs = {hv.y, hv.x};
@@ -842,7 +853,8 @@ __device__ __forceinline__ void mf_tap(const uint4 e, const mf_h4 hv, uint2 *ban
         const mf_h2 vy = {hv.z, hv.w}, vys = {hv.w, hv.z};
         sy = __builtin_elementwise_fma(w2, vys, __builtin_elementwise_fma(w1, vy, sy));
     }
-    band16[e.y] = make_uint2(__builtin_bit_cast(uint32_t, sx), __builtin_bit_cast(uint32_t, sy));
+    band[e.y] = __builtin_bit_cast(uint32_t, sx);
+    if (P == 2) band[MF_YB + e.y] = __builtin_bit_cast(uint32_t, sy);
     const bool last = (int)e.x < 0;
     const mf_h2 zero = {(_Float16)0.f, (_Float16)0.f};
     sx = last ? zero : sx;
@@ -856,9 +868,11 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
     const uint4 *__restrict__ entries, const int32_t *__restrict__ ants, int A,
     uint2 *__restrict__ scratch, int64_t scratch_t, const MfConst *__restrict__ mfc) {
     constexpr int N = 256, T = 128;
-    // BL * N FP16 cells + the spare slot, then the band's staged voltages
-    extern __shared__ uint2 band16[];
-    mf_h4 *vst = reinterpret_cast<mf_h4 *>(band16 + BL * N + 2);
+    // the two planes of BL * N FP16 cells (+ the spare slot), then the
+    // band's staged voltages
+    extern __shared__ uint4 mf_lds[];
+    uint32_t *band = reinterpret_cast<uint32_t *>(mf_lds);
+    mf_h4 *vst = reinterpret_cast<mf_h4 *>(band + 2 * MF_YB);
     // a workgroup takes MF_TS consecutive samples of its band: the band is
     // zeroed once (every sample rewrites the same cells, those with taps)
     const int64_t nts = (nt + MF_TS - 1) / MF_TS;
@@ -870,7 +884,7 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
     if (it.n_iter < 0) return;
     const BandChan ch = chans[it.chan];
     const int tid = threadIdx.x;
-    for (int i = tid; i <= BL * N; i += T) band16[i] = make_uint2(0u, 0u);
+    for (int i = tid; i < 2 * MF_YB; i += T) band[i] = 0u;
     const int lane = tid & 63, wv = tid >> 6;
     const int a = lane & 15, g = lane >> 4;
     const MfConst k = mf_consts(mfc, lane);
@@ -898,7 +912,7 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
     // a lane list of at most MF_UN entries is read once for all the samples;
     // list positions past its end hold padding entries
     const bool held = it.n_iter <= MF_UN;
-    const uint4 pad = make_uint4(0u, (uint32_t)(BL * N), 0u, 0u);
+    const uint4 pad = make_uint4(0u, (uint32_t)(BL * N), 0u, 0u);   // the spare cell
     uint4 eh[MF_UN];
 #pragma unroll
     for (int j = 0; j < MF_UN; ++j) {
@@ -942,8 +956,8 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
                 if (i0 + j < it.n_iter) {
                     const mf_h4 v0 = vst[eh[j].x & 0x7fffffffu];
                     const mf_h4 v1 = vst[eh[j + 1].x & 0x7fffffffu];
-                    mf_tap<P>(eh[j], v0, band16, sx, sy);
-                    mf_tap<P>(eh[j + 1], v1, band16, sx, sy);
+                    mf_tap<P>(eh[j], v0, band, sx, sy);
+                    mf_tap<P>(eh[j + 1], v1, band, sx, sy);
                 }
         }
         __syncthreads();
@@ -951,18 +965,11 @@ __global__ __launch_bounds__(128, 3) void k_band_rows_mf(
         for (int l = wv; l < BL; l += 2) {
             const int row = ch.row_lo + it.band * BL + l;
             if (row > ch.row_hi) break;
-            mf_h4 xr, xi, yr, yi;
-    #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint2 v = band16[l * N + 16 * (4 * g + j) + a];
-                xr[j] = h_lo(v.x);
-                xi[j] = h_hi(v.x);
-                yr[j] = h_lo(v.y);
-                yi[j] = h_hi(v.y);
-            }
+            const uint4 *cx = reinterpret_cast<const uint4 *>(band + mf_cell(l, 16 * 4 * g + a));
             mf_f4 er, ei, fr2, fi2;
-            mf_line(k, xr, xi, er, ei);
-            if (P == 2) mf_line(k, yr, yi, fr2, fi2);
+            mf_line(k, __builtin_bit_cast(mf_h8, cx[0]), er, ei);
+            if (P == 2)
+                mf_line(k, __builtin_bit_cast(mf_h8, cx[MF_YB / 4]), fr2, fi2);
             uint2 *out = scratch + (int64_t)t * scratch_t + ch.scratch_off +
                          (int64_t)(row - ch.row_lo) * N + a;
     #pragma unroll
@@ -1041,18 +1048,12 @@ __global__ __launch_bounds__(MF_CT, 4) void k_band_cols_mf(
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const int col = wv + NW * c;
-            mf_h4 xr, xi, yr, yi;
+            uint2 v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint2 v = tile[col * MF_LP + 16 * (4 * g + j) + a];
-                xr[j] = h_lo(v.x);
-                xi[j] = h_hi(v.x);
-                yr[j] = h_lo(v.y);
-                yi[j] = h_hi(v.y);
-            }
+            for (int j = 0; j < 4; ++j) v[j] = tile[col * MF_LP + 16 * (4 * g + j) + a];
             mf_f4 er, ei, fr2, fi2;
-            mf_line(k, xr, xi, er, ei);
-            if (P == 2) mf_line(k, yr, yi, fr2, fi2);
+            mf_line(k, mf_pairs(v[0].x, v[1].x, v[2].x, v[3].x), er, ei);
+            if (P == 2) mf_line(k, mf_pairs(v[0].y, v[1].y, v[2].y, v[3].y), fr2, fi2);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 av[c][i][0] = fmaf(er[i], er[i], fmaf(ei[i], ei[i], av[c][i][0]));
@@ -1255,10 +1256,12 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
         bp.mf_out = (float)std::ldexp(1.0, 16 + 2 * si);
         // the row pass sums each cell in FP16 as it stands: the gather
         // weights carry the exact scale 2^-si and become the half pairs
-        // (wr, wr) and (-wi, wi) (padding entries stay 0)
+        // (wr, wr) and (-wi, wi) (padding entries stay 0); cells take their
+        // place in the row band's transposed planes (the spare cell keeps its)
         for (uint4 &e : all) {
             const float wr = __builtin_bit_cast(float, e.z) * bp.mf_in;
             const float wi = __builtin_bit_cast(float, e.w) * bp.mf_in;
+            if (e.y < (uint32_t)(BL * 256)) e.y = mf_cell(e.y / 256u, e.y % 256u);
             e.z = pack_h2(wr, wr);
             e.w = pack_h2(-wi, wi);
         }
@@ -1269,10 +1272,10 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
             for (int j = 0; j < 4; ++j) {
                 const double f = 2.0 * M_PI * (double)((a * (4 * g + j)) & 15) / 16.0;
                 const _Float16 c = (_Float16)(float)std::cos(f), sn = (_Float16)(float)std::sin(f);
-                tab[lane].fre[j] = c;
-                tab[lane].fre[4 + j] = -sn;
-                tab[lane].fim[j] = sn;
-                tab[lane].fim[4 + j] = c;
+                tab[lane].fre[2 * j] = c;
+                tab[lane].fre[2 * j + 1] = -sn;
+                tab[lane].fim[2 * j] = sn;
+                tab[lane].fim[2 * j + 1] = c;
                 const double u = 2.0 * M_PI * (double)(a * (4 * g + j)) / 256.0;
                 tab[lane].tw[j] = make_float2((float)std::cos(u) * 0.0625f,
                                               (float)std::sin(u) * 0.0625f);
@@ -1410,7 +1413,7 @@ static epic_status launch_pw(epic_plan p, const BandSize &bs, int pass, const ui
     return EPIC_OK;
 }
 
-constexpr size_t kRowsMfLds = sizeof(uint2) * (BL * 256 + 2);   // + the staged voltages
+constexpr size_t kRowsMfLds = sizeof(uint32_t) * 2 * MF_YB;   // + the staged voltages
 constexpr size_t kColsMfLds = sizeof(uint2) * MF_BC * MF_LP;
 
 static epic_status ready_mf(int P) {
