@@ -1,6 +1,7 @@
 """FP16 four-step MFMA transform on 256 x 256 channels (precision
 EPIC_F16_MFMA, banded path): the 4096-element streaming array and a small
-array on a 256^2 grid, 4- and 8-bit voltages, several calls, against the
+array on a 256^2 grid, a dense 4096-element array (about 30 taps per
+cell), 4- and 8-bit voltages, several calls, against the
 FP64 oracle to the stated FP16 four-step bound."""
 import dataclasses
 import json
@@ -64,3 +65,21 @@ def test_fp16_fourstep_odd_element_count_and_single_feed(n_ant, n_pol):
     _say(f"case fp16 four-step: {n_ant} elements x {n_pol} feeds on 256^2, 12 samples in 2 calls")
     _check(_run(wl, pos, volt, precision=1, chunks=2), oracle_images(volt, pos, wl, [0]),
            f"fp16-4step-{n_ant}x{n_pol}", TOL["max"], TOL["rms"])
+
+
+def test_dense_array_fp16_fourstep_many_taps_per_cell():
+    # the streaming array's 4096 elements packed into a 60 m disc: about 30
+    # taps per gridded cell, so the half-pair cell sums of the row pass take
+    # many roundings, and bands hold far more elements and longer lane lists
+    # than on the 300 m disc
+    full = dataclasses.replace(synth.workload("stream"), disc_diameter_m=60.0,
+                               min_spacing_m=0.5, seed=1093)
+    chans = [0, 63]
+    _say("case fp16 four-step: 4096 elements in a 60 m disc, 256^2, channels 0 and 63, "
+         "4 samples")
+    wl = full.subset(chans).with_time(4)
+    pos = synth.antenna_layout(full)
+    volt = synth.voltages(full.with_time(4), pos, chans=chans)
+    got = _run(wl, pos, volt, precision=1)
+    _check(got, oracle_images(volt, pos, wl, range(2)), "fp16-4step-dense", TOL["max"],
+           TOL["rms"])
