@@ -1528,14 +1528,21 @@ epic_status banded_acc_setup(epic_plan p, epic_acc acc) {
 }
 
 // Rounds of at most t_chunk samples (of equal length) alternate between the
-// two scratch halves: the row pass of round k + 1 (queue 0) runs while the
-// column pass of round k (queue 1) reads the other half.  Events: 0 fork, 1 + b row pass into half b
-// done, 3 + b column pass out of half b done, 5 the row queue's last pass
-// done.  banded_join makes the caller's stream wait on both queues' last
-// events: each queue that forked from the caller's stream is joined back
-// into it directly.  A stream under graph capture gets both passes itself,
-// in order, with no events (epic_graph_create refuses banded captures of
-// more than two rounds).
+// two scratch halves.  Whole-integration calls run each round's row pass
+// and then its column pass on the caller's stream: in alternating runs the
+// streaming array's FP32 block took 6.44-6.48 ms so against 6.61-6.76 ms
+// with the next round's row pass overlapping the column pass on a second
+// queue (the two passes contend for the same CUs and HBM; the FP16 block
+// and the wide field were the same either way).  Frame-mode calls keep the
+// overlap (the wide field's frames 2.16-2.20 ms with it, 2.24-2.25 ms in
+// order): the row pass of round k + 1 (queue 0) runs while the column pass
+// of round k (queue 1) reads the other half.
+// Events: 0 fork, 1 + b row pass into half b done, 3 + b column pass out of
+// half b done, 5 the row queue's last pass done.  banded_join makes the
+// caller's stream wait on both queues' last events: each queue that forked
+// from the caller's stream is joined back into it directly.  A stream under
+// graph capture gets both passes itself, in order, with no events
+// (epic_graph_create refuses banded captures of more than two rounds).
 epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, int n_time,
                               hipStream_t s, bool dry, const FrameOut &fo) {
     const BandPlan &bp = p->band;
@@ -1581,7 +1588,7 @@ epic_status banded_accumulate(epic_plan p, epic_acc acc, const uint8_t *d_volt, 
     const BandChan *chans = bp.d_chans.as<BandChan>();
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     EPIC_HIP(hipStreamIsCapturing(s, &cap));
-    const bool split = cap == hipStreamCaptureStatusNone;
+    const bool split = cap == hipStreamCaptureStatusNone && fo.len > 0;
     acc->band_split = split;
     const hipStream_t q_rows = split ? acc->band_q[0] : s, q_cols = split ? acc->band_q[1] : s;
     hipEvent_t *ev = acc->band_ev;

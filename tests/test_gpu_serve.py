@@ -81,7 +81,7 @@ def test_budget_admits_streams_in_turn_on_device():
 
 def test_fp16_fourstep_stream_alone_equals_in_mix():
     """Streaming on the FP16 four-step banded path (256^2 grids): each stream's
-    accumulator forks its row and column passes onto its own two queues; a
+    row and column passes run on its own queue, overlapping other streams'; a
     stream's image is bit for bit the same alone and among three others."""
     torch = _torch()
     import dataclasses
