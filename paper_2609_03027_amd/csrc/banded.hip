@@ -444,9 +444,18 @@ template <int R, int NP>
 constexpr int rows_pitch() {
     return Pw<R, NP>::PAD + 2;
 }
+// Lines per row-pass band: 8, or 4 for N = 8^3, whose 512-point lines would
+// otherwise hold a workgroup's band in 74 KB of LDS and two workgroups per
+// CU; with 41 KB three share a CU (the wide field's frames 2.19 -> 2.07 ms,
+// whole images unchanged; with the twiddles in registers instead of LDS,
+// four workgroups per CU measured slower).
+__host__ __device__ constexpr int band_lines(int R, int NP) {
+    return (R == 8 && NP == 3) ? 4 : BL;
+}
+
 template <int R, int NP>
 constexpr int rows_threads() {
-    return BL * Pw<R, NP>::L;
+    return band_lines(R, NP) * Pw<R, NP>::L;
 }
 // Columns per pass-2 workgroup: 16 (256-byte row segments) unless that would
 // pass 256 threads.
@@ -498,10 +507,10 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     const uint4 *__restrict__ entries, int A, const float2 *__restrict__ tw,
     float4 *__restrict__ scratch, int64_t scratch_t) {
     constexpr int N = Pw<R, NP>::N, L = Pw<R, NP>::L, T = rows_threads<R, NP>();
-    constexpr int LP = rows_pitch<R, NP>();
+    constexpr int LP = rows_pitch<R, NP>(), BLR = band_lines(R, NP);
     constexpr int UN = T >= 256 ? 8 : 16;  // gather entries in flight per lane
     extern __shared__ float4 lds[];
-    float2 *twl = reinterpret_cast<float2 *>(lds + BL * LP);
+    float2 *twl = reinterpret_cast<float2 *>(lds + BLR * LP);
     // Items come in blocks of G (one channel's bands, padded with empty
     // items); the flat order is block, then sample, then item, so that the
     // workgroups an XCD runs back to back share a sample's voltages and keep
@@ -532,14 +541,14 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     for (int k = 0; k < NTW; ++k) twr[k] = tw[tid + k * T];
     uint4 e[UN];
     uint32_t bx[UN], by[UN];
-    if (n_iter > 0) pw_load<UN, P, VB>(e, bx, by, ent, 0, n_iter, T, tid, vx, A, BL * N);
+    if (n_iter > 0) pw_load<UN, P, VB>(e, bx, by, ent, 0, n_iter, T, tid, vx, A, BLR * N);
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int k = 0; k < BL * N / T; ++k) lds[tid + k * T] = zero;
+    for (int k = 0; k < BLR * N / T; ++k) lds[tid + k * T] = zero;
     __syncthreads();
     float4 s = zero;
     for (int i0 = 0; i0 < n_iter; i0 += UN) {
-        if (i0) pw_load<UN, P, VB>(e, bx, by, ent, i0, n_iter, T, tid, vx, A, BL * N);
+        if (i0) pw_load<UN, P, VB>(e, bx, by, ent, i0, n_iter, T, tid, vx, A, BLR * N);
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
             const float wr = __builtin_bit_cast(float, e[k].z);
@@ -570,7 +579,7 @@ __global__ __launch_bounds__((rows_threads<R, NP>())) void k_band_rows_pw(
     dft<R>(v);
     __syncthreads();
     pw_rest<R, NP>(v, lds + l * LP, j, twl);
-    const int row = ch.row_lo + it.band * BL + l;
+    const int row = ch.row_lo + it.band * BLR + l;
     if (row <= ch.row_hi) {
         float4 *out = scratch + (int64_t)t * scratch_t + ch.scratch_off +
                       (int64_t)(row - ch.row_lo) * N + j;
@@ -1096,18 +1105,18 @@ static int pw_radix(int N, int *np) {
 // ants), whose voltages the FP16 four-step row pass stages once per sample.
 static epic_status band_items(epic_plan p, const std::vector<int> &j0,
                               const std::vector<double> &w, const BandChan &b, int chan_index,
-                              int T, int G, std::vector<BandItem> &items,
+                              int bl, int T, int G, std::vector<BandItem> &items,
                               std::vector<uint4> &all, bool compact,
                               std::vector<int32_t> &ants) {
     const int A = p->A, K = p->K, N = b.N, c = b.c;
-    const int n_bands = (b.row_hi - b.row_lo + 1 + BL - 1) / BL;
+    const int n_bands = (b.row_hi - b.row_lo + 1 + bl - 1) / bl;
     std::vector<std::vector<GatherTap>> per(n_bands);
     for (int a = 0; a < A; ++a) {
         const int jx0 = j0[((size_t)c * A + a) * 2], jy0 = j0[((size_t)c * A + a) * 2 + 1];
         for (int dy = 0; dy < K; ++dy)
             for (int dx = 0; dx < K; ++dx) {
                 const int row = jy0 + dy, col = jx0 + dx;
-                const int band = (row - b.row_lo) / BL, r0 = b.row_lo + band * BL;
+                const int band = (row - b.row_lo) / bl, r0 = b.row_lo + band * bl;
                 const size_t wi = (((size_t)c * A + a) * K * K + dy * K + dx) * 2;
                 const double sg = ((row + col) & 1) ? -1.0 : 1.0;
                 GatherTap tp{};
@@ -1142,7 +1151,7 @@ static epic_status band_items(epic_plan p, const std::vector<int> &j0,
         // point at the spare LDS slot after the band
         for (size_t e = (size_t)it.entry_off; e < all.size(); ++e)
             if (all[e].x == 0u && all[e].y == 0u && all[e].z == 0u && all[e].w == 0u)
-                all[e].y = (uint32_t)(BL * N);
+                all[e].y = (uint32_t)(bl * N);
         items.push_back(it);
     }
     // pad the channel to whole blocks of G items with empty ones
@@ -1196,11 +1205,12 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
             span_lo[c] = lo;
             span_hi[c] = hi;
             min_span = std::min(min_span, hi - lo + 1);
-            max_bands = std::max(max_bands, (hi - lo + 1 + BL - 1) / BL);
+            const int bl = bs.R ? band_lines(bs.R, bs.NP) : BL;
+            max_bands = std::max(max_bands, (hi - lo + 1 + bl - 1) / bl);
         }
         if (bs.R) {
-            const int T = BL * (N / bs.R);
-            const double taps = (double)p->A * p->K * p->K * BL / std::max(1, min_span);
+            const int bl = band_lines(bs.R, bs.NP), T = bl * (N / bs.R);
+            const double taps = (double)p->A * p->K * p->K * bl / std::max(1, min_span);
             const double item_bytes = 16.0 * (taps + T);
             const int gmax = std::max(1, std::min(max_bands, (int)((512 << 10) / item_bytes)));
             const int nblk = (max_bands + gmax - 1) / gmax;
@@ -1220,7 +1230,8 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
             // items index the channels of their own size group
             if (bs.R)
                 band_items(p, j0, w, b, (int)(bp.host.size() - bs.chan_off),
-                           BL * (bs.N / bs.R), bs.G, items, all, compact, ants);
+                           band_lines(bs.R, bs.NP), band_lines(bs.R, bs.NP) * (bs.N / bs.R),
+                           bs.G, items, all, compact, ants);
             bp.host.push_back(b);
             bs.max_bands = std::max(bs.max_bands, (hi - lo + 1 + BL - 1) / BL);
             ++bs.n;
@@ -1352,7 +1363,8 @@ static const void *cols_pw_kernel(int P) {
 }
 template <int R, int NP>
 static size_t rows_pw_lds() {
-    return sizeof(float4) * BL * rows_pitch<R, NP>() + sizeof(float2) * Pw<R, NP>::N;
+    return sizeof(float4) * band_lines(R, NP) * rows_pitch<R, NP>() +
+           sizeof(float2) * Pw<R, NP>::N;
 }
 template <int R, int NP>
 static size_t cols_pw_lds() {
