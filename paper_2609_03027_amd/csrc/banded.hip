@@ -444,13 +444,15 @@ template <int R, int NP>
 constexpr int rows_pitch() {
     return Pw<R, NP>::PAD + 2;
 }
-// Lines per row-pass band: 8, or 4 for N = 8^3, whose 512-point lines would
+// Lines per FP32 row-pass band.  4 for N = 8^3, whose 512-point lines would
 // otherwise hold a workgroup's band in 74 KB of LDS and two workgroups per
 // CU; with 41 KB three share a CU (the wide field's frames 2.19 -> 2.07 ms,
 // whole images unchanged; with the twiddles in registers instead of LDS,
-// four workgroups per CU measured slower).
+// four workgroups per CU measured slower).  4 for N = 16^2 as well: one-wave
+// workgroups, eight per CU (the streaming array's block 6.51 -> 6.43 ms).
+// 8 for N = 8^2.  (The FP16 four-step row pass keeps BL-line bands.)
 __host__ __device__ constexpr int band_lines(int R, int NP) {
-    return (R == 8 && NP == 3) ? 4 : BL;
+    return ((R == 8 && NP == 3) || R == 16) ? 4 : BL;
 }
 
 template <int R, int NP>
@@ -1182,6 +1184,9 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
     std::vector<uint4> all;
     std::vector<int32_t> ants;
     const bool compact = p->precision == EPIC_F16_MFMA;
+    // the FP16 four-step row pass keeps BL-line bands; the FP32 row pass
+    // takes band_lines(R, NP)
+    const bool mf = p->precision == EPIC_F16_MFMA;
     int64_t off = 0;
     for (int N : sides) {
         BandSize bs;
@@ -1205,11 +1210,11 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
             span_lo[c] = lo;
             span_hi[c] = hi;
             min_span = std::min(min_span, hi - lo + 1);
-            const int bl = bs.R ? band_lines(bs.R, bs.NP) : BL;
+            const int bl = (bs.R && !mf) ? band_lines(bs.R, bs.NP) : BL;
             max_bands = std::max(max_bands, (hi - lo + 1 + bl - 1) / bl);
         }
         if (bs.R) {
-            const int bl = band_lines(bs.R, bs.NP), T = bl * (N / bs.R);
+            const int bl = mf ? BL : band_lines(bs.R, bs.NP), T = bl * (N / bs.R);
             const double taps = (double)p->A * p->K * p->K * bl / std::max(1, min_span);
             const double item_bytes = 16.0 * (taps + T);
             const int gmax = std::max(1, std::min(max_bands, (int)((512 << 10) / item_bytes)));
@@ -1230,7 +1235,8 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
             // items index the channels of their own size group
             if (bs.R)
                 band_items(p, j0, w, b, (int)(bp.host.size() - bs.chan_off),
-                           band_lines(bs.R, bs.NP), band_lines(bs.R, bs.NP) * (bs.N / bs.R),
+                           mf ? BL : band_lines(bs.R, bs.NP),
+                           (mf ? BL : band_lines(bs.R, bs.NP)) * (bs.N / bs.R),
                            bs.G, items, all, compact, ants);
             bp.host.push_back(b);
             bs.max_bands = std::max(bs.max_bands, (hi - lo + 1 + BL - 1) / BL);
