@@ -1102,8 +1102,8 @@ def main():
                 lw, lpos, lvolt, lchans, lgpu = out["large_stream"].pop("_err_gpu")
                 errs.update(oracle_errors(lw, lpos, lvolt, lchans, lgpu, remove_autos=False))
             out["errors"] = errs
-            # the benchmark spec's comparison: each form's per-integration time on
-            # the LWA workload beside its measured max error; the plain FP32
+            # accuracy against time: each form's per-integration time on the
+            # LWA workload beside its measured max error; the plain FP32
             # gridding + FFT form (staged, grids and sky through HBM) is timed
             # on its sample slice and scaled to the integration
             cmp = {}
