@@ -1,6 +1,6 @@
 """High-cadence frames on the GPU (Eq. 2 over frame_len consecutive samples,
 epic_accumulate_frames) against the FP64 oracle on the fused, paired-class
-and banded paths; a transient injected into one frame is found there; the
+and banded paths (64^2, 256^2 over three rounds, 512^2); a transient injected into one frame is found there; the
 frames add up to one accumulate over the same samples; bad requests are
 refused."""
 import numpy as np
@@ -65,6 +65,21 @@ def test_banded_frames_match_oracle():
     _say("case frames ska 64^2 banded, 3 frames of 4")
     _, got = _frames(wl, pos, volt, 4, sub_n=[-1])
     _check_frames(got, volt, pos, wl, 4, "frames-banded")
+
+
+@pytest.mark.parametrize("n,n_time", [(256, 520), (512, 24)])
+def test_banded_frames_on_256_and_512_grids(n, n_time):
+    # 256^2: the radix-16 row pass, three rounds of whole frames (176, 176,
+    # 168 samples) over the two scratch halves with the row pass of one
+    # round beside the column pass of the previous one; 512^2: the radix-8
+    # three-step kernels with time-sliced column passes per frame
+    import dataclasses
+    wl = dataclasses.replace(synth.workload("tiny2"), grid_n=np.array([n]), n_time=n_time)
+    pos = synth.antenna_layout(wl)
+    volt = synth.voltages(wl, pos)
+    _say(f"case frames tiny2 on {n}^2 banded, {n_time // 4} frames of 4")
+    _, got = _frames(wl, pos, volt, 4, sub_n=[-1])
+    _check_frames(got, volt, pos, wl, 4, f"frames-banded-{n}")
 
 
 def test_transient_detected_in_its_frame():
