@@ -355,10 +355,11 @@ __global__ __launch_bounds__(1024) void k_fft2d(const float2 *in, float2 *out,
 
 // The same transform for power-of-two sides N <= 128 with N a template
 // constant: the radix schedule (4, 4, ..., then 2 if needed) and every index
-// division become compile-time shifts and masks.  PF: the next image is
-// prefetched into registers during the transform (N < 128; at N = 128 the
-// 16 prefetch registers per thread would spill, so the image is loaded at
-// the start of its turn instead).
+// division become compile-time shifts and masks.  PFN of a thread's PER
+// elements of the next image are prefetched into registers during the
+// transform, the rest loaded at the start of its turn: all of them for
+// N < 128; a quarter at N = 128, where more spill (all 16 need 24 more
+// registers than the 128 a 1024-thread workgroup allows).
 template <int N, int T, int R, int NS>
 __device__ __forceinline__ void p2_pass(float2 *buf, bool along_x, const float2 *__restrict__ tw) {
     constexpr int pitch = N + 1, nb = N / R, total = N * nb;
@@ -405,7 +406,7 @@ __device__ __forceinline__ void p2_passes(float2 *buf, bool along_x, const float
     }
 }
 
-template <int N, int T, bool PF>
+template <int N, int T, int PFN>
 __global__ __launch_bounds__(T) void k_fft2d_p2(const float2 *in, float2 *out,
                                                    const int32_t *__restrict__ chans, int n_chans,
                                                    const int64_t *__restrict__ grid_off, int P,
@@ -422,19 +423,21 @@ __global__ __launch_bounds__(T) void k_fft2d_p2(const float2 *in, float2 *out,
         const int64_t t = img / ((int64_t)P * n_chans);
         return t * grid_t_stride + grid_off[chans[ci]] + (int64_t)p * NN;
     };
+    static_assert(PFN >= 0 && PFN <= PER, "prefetch count");
     float2 pre[PER];
-    auto load = [&](int64_t img) {
+    // elements k0 .. k1 - 1 of a thread's share of image img
+    auto load = [&](int64_t img, int k0, int k1) {
         const float2 *src = in + base_of(img);
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + k * T;
-            if (NN % T == 0 || i < NN) pre[k] = st_load(src + i);
+            if (k >= k0 && k < k1 && (NN % T == 0 || i < NN)) pre[k] = st_load(src + i);
         }
     };
     int64_t img = blockIdx.x;
-    if (PF && img < n_img) load(img);
+    if (PFN > 0 && img < n_img) load(img, 0, PFN);
     for (; img < n_img; img += gridDim.x) {
-        if (!PF) load(img);
+        if (PFN < PER) load(img, PFN, PER);
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + k * T;
@@ -446,7 +449,7 @@ __global__ __launch_bounds__(T) void k_fft2d_p2(const float2 *in, float2 *out,
             }
         }
         __syncthreads();
-        if (PF && img + gridDim.x < n_img) load(img + gridDim.x);
+        if (PFN > 0 && img + gridDim.x < n_img) load(img + gridDim.x, 0, PFN);
         p2_passes<N, T, 1>(sbuf, true, twl);
         p2_passes<N, T, 1>(sbuf, false, twl);
         float2 *dst = out + base_of(img);
@@ -584,10 +587,10 @@ epic_status staged_image(epic_plan p, const void *d_grid, int n_time, void *d_sk
             EPIC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
             const int64_t n_img = imgs_per_t * n_time;
             const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_img, n_cu));
-            const void *kp2 = N == 128  ? reinterpret_cast<const void *>(k_fft2d_p2<128, 1024, false>)
-                              : N == 64 ? reinterpret_cast<const void *>(k_fft2d_p2<64, 1024, true>)
-                              : N == 32 ? reinterpret_cast<const void *>(k_fft2d_p2<32, 1024, true>)
-                              : N == 16 ? reinterpret_cast<const void *>(k_fft2d_p2<16, 1024, true>)
+            const void *kp2 = N == 128  ? reinterpret_cast<const void *>(k_fft2d_p2<128, 1024, 4>)
+                              : N == 64 ? reinterpret_cast<const void *>(k_fft2d_p2<64, 1024, 4>)
+                              : N == 32 ? reinterpret_cast<const void *>(k_fft2d_p2<32, 1024, 1>)
+                              : N == 16 ? reinterpret_cast<const void *>(k_fft2d_p2<16, 1024, 1>)
                                         : nullptr;
             if (kp2) {
                 if ((st = lds_ready(kp2, lds2))) return st;
@@ -596,16 +599,16 @@ epic_status staged_image(epic_plan p, const void *d_grid, int n_time, void *d_sk
                 const int64_t *goff = p->d_grid_off.as<int64_t>();
                 const int64_t gts = p->grid_elems_per_t;
                 if (N == 128)
-                    hipLaunchKernelGGL((k_fft2d_p2<128, 1024, false>), dim3(blocks), dim3(1024), lds2, s,
+                    hipLaunchKernelGGL((k_fft2d_p2<128, 1024, 4>), dim3(blocks), dim3(1024), lds2, s,
                                        gi, go, chans, n_chans, goff, p->P, gts, n_img, twd);
                 else if (N == 64)
-                    hipLaunchKernelGGL((k_fft2d_p2<64, 1024, true>), dim3(blocks), dim3(1024), lds2, s,
+                    hipLaunchKernelGGL((k_fft2d_p2<64, 1024, 4>), dim3(blocks), dim3(1024), lds2, s,
                                        gi, go, chans, n_chans, goff, p->P, gts, n_img, twd);
                 else if (N == 32)
-                    hipLaunchKernelGGL((k_fft2d_p2<32, 1024, true>), dim3(blocks), dim3(1024), lds2, s,
+                    hipLaunchKernelGGL((k_fft2d_p2<32, 1024, 1>), dim3(blocks), dim3(1024), lds2, s,
                                        gi, go, chans, n_chans, goff, p->P, gts, n_img, twd);
                 else
-                    hipLaunchKernelGGL((k_fft2d_p2<16, 1024, true>), dim3(blocks), dim3(1024), lds2, s,
+                    hipLaunchKernelGGL((k_fft2d_p2<16, 1024, 1>), dim3(blocks), dim3(1024), lds2, s,
                                        gi, go, chans, n_chans, goff, p->P, gts, n_img, twd);
                 EPIC_HIP(hipGetLastError());
                 continue;
