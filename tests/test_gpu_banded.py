@@ -16,6 +16,13 @@ pytestmark = pytest.mark.gpu
 BANDED = -1
 
 
+@pytest.fixture(autouse=True)
+def _rounds_of_256_samples(monkeypatch):
+    """Rounds of at most 256 samples (the EPIC_BAND_ROUND cap, read at plan
+    creation), so that the sample counts below span the rounds they name."""
+    monkeypatch.setenv("EPIC_BAND_ROUND", "256")
+
+
 @pytest.mark.parametrize("name", ["tiny", "tiny2"])
 @pytest.mark.parametrize("chunks", [1, 3])
 def test_forced_banded_matches_oracle(name, chunks):

@@ -43,9 +43,11 @@ def test_small_array_256_grid_fp16_fourstep_in_calls(bits):
            TOL["max"], TOL["rms"])
 
 
-def test_fp16_fourstep_rounds_alternate_scratch_halves():
-    # 300 samples on a 256^2 grid: two rounds of the banded path (256 + 44
+def test_fp16_fourstep_rounds_alternate_scratch_halves(monkeypatch):
+    # 300 samples on a 256^2 grid in rounds of at most 256 (the
+    # EPIC_BAND_ROUND cap): two rounds of the banded path (150 + 150
     # samples), the second in the other half of the FP16 scratch
+    monkeypatch.setenv("EPIC_BAND_ROUND", "256")
     wl = dataclasses.replace(synth.workload("tiny2"), grid_n=np.array([256]), n_time=300)
     pos = synth.antenna_layout(wl)
     volt = synth.voltages(wl, pos)

@@ -68,12 +68,14 @@ def test_banded_frames_match_oracle():
 
 
 @pytest.mark.parametrize("n,n_time", [(256, 520), (512, 24)])
-def test_banded_frames_on_256_and_512_grids(n, n_time):
-    # 256^2: the radix-16 row pass, three rounds of whole frames (176, 176,
-    # 168 samples) over the two scratch halves with the row pass of one
-    # round beside the column pass of the previous one; 512^2: the radix-8
+def test_banded_frames_on_256_and_512_grids(n, n_time, monkeypatch):
+    # 256^2: the radix-16 row pass, with rounds of at most 256 samples (the
+    # EPIC_BAND_ROUND cap) three rounds of whole frames (176, 176, 168
+    # samples) over the two scratch halves with the row pass of one round
+    # beside the column pass of the previous one; 512^2: the radix-8
     # three-step kernels with time-sliced column passes per frame
     import dataclasses
+    monkeypatch.setenv("EPIC_BAND_ROUND", "256")
     wl = dataclasses.replace(synth.workload("tiny2"), grid_n=np.array([n]), n_time=n_time)
     pos = synth.antenna_layout(wl)
     volt = synth.voltages(wl, pos)
