@@ -448,7 +448,7 @@ constexpr int rows_pitch() {
 // otherwise hold a workgroup's band in 74 KB of LDS and two workgroups per
 // CU; with 41 KB three share a CU (the wide field's frames 2.19 -> 2.07 ms,
 // whole images unchanged; with the twiddles in registers instead of LDS,
-// four workgroups per CU measured slower).  4 for N = 16^2 as well: one-wave
+// four workgroups per CU measured slower, and so did 2-row bands).  4 for N = 16^2 as well: one-wave
 // workgroups, eight per CU (the streaming array's block 6.51 -> 6.43 ms).
 // 8 for N = 8^2.  (The FP16 four-step row pass keeps BL-line bands.)
 __host__ __device__ constexpr int band_lines(int R, int NP) {
