@@ -356,7 +356,8 @@ epic_status epic_readout_noalloc(epic_plan plan, const float *d_acc, const int32
  * The graph holds no memset nodes.  Capture happens on an internal stream;
  * hip_stream is only synchronised.  A graph must be destroyed before its plan
  * or accumulator.  Plans with banded channels capture at most two scratch
- * rounds (2 t_chunk samples, 512 for most plans): longer captures fail with
+ * rounds (2 t_chunk samples, t_chunk at most 512 and fewer where a round's row
+ * transforms would pass 8 GiB): longer captures fail with
  * EPIC_ERR_UNSUPPORTED before capture begins. */
 epic_status epic_graph_create(epic_plan plan, epic_acc acc, const uint8_t *d_volt,
                               int32_t n_time, void *hip_stream, epic_graph *out);

@@ -1303,7 +1303,7 @@ epic_status banded_build(epic_plan p, const std::vector<int> &j0, const std::vec
         EPIC_HIP(hipMemcpyAsync(bp.d_mf.p, tab.data(), sizeof(MfConst) * tab.size(),
                                 hipMemcpyHostToDevice, s));
     }
-    // samples per round: each of the two scratch halves near 1 GiB (cells
+    // samples per round: each of the two scratch halves at most 8 GiB (cells
     // are float4, or two FP16 pairs on the FP16 four-step path)
     bp.elem_bytes = p->precision == EPIC_F16_MFMA ? 8 : (int)sizeof(float4);
     const int64_t per_t = off * (int64_t)bp.elem_bytes;
